@@ -1,0 +1,23 @@
+"""Plain FP64 CPU oracle of GMRES-SDR -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import anything from this package.  The product (the HIP library and its
+Python binding) never calls it and shares no code with it.
+
+Contents
+--------
+``sketch``      the sparse-sign sketching operator S (Section 3, eq. (3.1)):
+                an explicit scipy matrix built from a published counter-based
+                generator (SplitMix64 output mixer).
+``gmres_sdr``   GMRES-SDR, one cycle per Algorithm 1 and the restart /
+                sequence logic of Sections 3.2-3.6, in float64 / complex128.
+"""
+
+from .sketch import sketch_operator, sketch_pattern, splitmix64_mix  # noqa: F401
+from .gmres_sdr import (  # noqa: F401
+    Recycle,
+    SolveResult,
+    sdr_cycle,
+    sdr_solve,
+    harmonic_ritz_update,
+)

@@ -1,0 +1,79 @@
+"""Planted mistakes in the oracle (on the CPU) must each fail some pin.
+
+Each mutant is the oracle's source with one plausible slip (a dropped term, a
+wrong index or sign, a missing conjugate, an inverted selection).  The pins of
+``test_oracle_pins`` are re-run against the mutant; at least one of them has to
+fail, which shows the pins constrain that part of the oracle.
+"""
+
+import os
+import sys
+import types
+
+import pytest
+
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "oracle", "gmres_sdr.py")
+
+MUTANTS = {
+    "window_one_short": ("range(max(j - t + 1, 1), j + 1)", "range(max(j - t + 2, 1), j + 1)"),
+    "no_conjugate": ("np.vdot(V[:, i - 1], w)", "np.dot(V[:, i - 1], w)"),
+    "sav_drops_subdiagonal": ("SAV[:, j - 1] = SV[:, : j + 1] @ H[: j + 1, j - 1]",
+                              "SAV[:, j - 1] = SV[:, :j] @ H[:j, j - 1]"),
+    "smallest_mu_selected": ('order = np.argsort(-mod, kind="stable")',
+                             'order = np.argsort(mod, kind="stable")'),
+    "residual_sign": ("rt = r0 - A @ xt", "rt = r0 + A @ xt"),
+    "su_from_saw": ("new = Recycle(Wb @ G, SB @ G, SAW @ G)",
+                    "new = Recycle(Wb @ G, SAW @ G, SAW @ G)"),
+    "m_without_conjugate": ("M = Uh.conj().T @ SB @ Vh", "M = Uh.T @ SB @ Vh"),
+    "safety_inverted": ("safety = res / sres", "safety = sres / res"),
+    "sketch_not_of_new_vector": ("SV[:, j] = S @ V[:, j]  # one sketch per iteration",
+                                 "SV[:, j] = S @ V[:, j - 1]"),
+}
+
+PINS = [
+    lambda: pins.test_truncated_arnoldi_relation_and_band(False),
+    lambda: pins.test_truncated_arnoldi_relation_and_band(True),
+    pins.test_inner_product_count_is_t_plus_one_per_step,
+    pins.test_sketch_of_Av_from_arnoldi_relation,
+    pins.test_sketched_residual_nonincreasing_within_cycle,
+    pins.test_identity_sketch_full_orthogonalisation_is_gmres_dr,
+    lambda: pins.test_exact_eigenspace_is_recovered_for_any_sketch(1),
+    pins.test_exact_eigenspace_complex,
+    pins.test_recycled_exact_solution_space_converges_in_one_step,
+    lambda: pins.test_solution_matches_dense_lu("cd"),
+    lambda: pins.test_solution_matches_dense_lu("helmholtz"),
+    pins.test_safety_factor_update_rule,
+]
+
+
+def _mutant_module(old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, old
+    src = src.replace(old, new).replace("from .sketch import", "from oracle.sketch import")
+    name = "oracle_mutant"
+    mod = types.ModuleType(name)
+    sys.modules[name] = mod  # dataclasses look their module up here
+    try:
+        exec(compile(src, name, "exec"), mod.__dict__)
+    finally:
+        del sys.modules[name]
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, monkeypatch):
+    mod = _mutant_module(*MUTANTS[name])
+    monkeypatch.setattr(pins, "sdr_solve", mod.sdr_solve)
+    monkeypatch.setattr(pins, "harmonic_ritz_update", mod.harmonic_ritz_update)
+    monkeypatch.setattr(pins, "Recycle", mod.Recycle)
+    caught = []
+    for pin in PINS:
+        try:
+            pin()
+        except Exception:  # an assertion or a numerical failure both count
+            caught.append(pin)
+            break
+    assert caught, f"mutant {name} passed every pin"
