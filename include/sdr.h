@@ -1,0 +1,207 @@
+/*
+ * sdr.h -- C interface of the GMRES-SDR library for MI355X (gfx950).
+ *
+ * GMRES-SDR (Burke, Guettel, Soodhalter, "GMRES with randomized sketching and
+ * deflated restarting", arXiv 2311.14206) solves A x = b for a sparse,
+ * nonsymmetric, real or complex A, and sequences A_i x_i = b_i, by restarted
+ * cycles of Algorithm 1: truncated Arnoldi (each new basis vector is
+ * orthogonalised against the t previous ones only, Section 3.2), a sparse-sign
+ * sketch S of every basis vector (Section 3, eq. (3.1)), the sketched least
+ * squares problem min_y ||S r0 - S A [U V] y|| (eq. (3.3), Section 3.3), the
+ * safety-factor residual control of Section 3.4, and the sketched
+ * harmonic-Ritz compression of [U V] into the next recycle space (Section 3.5,
+ * eq. (3.5)).  Sequences reuse U, SU, SAU (Section 3.6).
+ *
+ * Conventions
+ *  - Every vector / matrix pointer passed to a solve is a DEVICE pointer on the
+ *    current HIP device.  Complex data are interleaved (re, im) pairs.
+ *  - CSR: int32 row_ptr[n+1] (row_ptr[0] = 0, non-decreasing), int32
+ *    col_idx[nnz] in [0, n), values[nnz] of the stated dtype.
+ *  - The handle copies the matrix (it owns its copies); b, x, g, lambda and
+ *    output buffers are borrowed for the duration of a call only.
+ *  - Calls are ordered on the handle's stream (sdr_set_stream) and return after
+ *    the work has completed.  A handle must be used by one thread at a time.
+ *  - Return codes: 0 success, 1 not converged (x holds the last iterate),
+ *    negative values are errors; sdr_last_error() gives a message (thread
+ *    local).
+ */
+#ifndef SDR_H
+#define SDR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SDR_F64 = 0,   /* real float64 */
+  SDR_F32 = 1,   /* real float32 (only as a basis precision, see "precision") */
+  SDR_C128 = 2,  /* complex128 */
+  SDR_C64 = 3    /* complex64 (only as a basis precision) */
+} sdr_dtype;
+
+enum {
+  SDR_OK = 0,
+  SDR_NOT_CONVERGED = 1,
+  SDR_EINVAL = -1,      /* bad sizes or parameters, non-finite input */
+  SDR_EPATTERN = -2,    /* sdr_update_matrix: sparsity pattern differs */
+  SDR_EDEVICE = -3,     /* a HIP call failed */
+  SDR_EBREAKDOWN = -4,  /* no progress possible (breakdown at the first step) */
+  SDR_ENOMEM = -5       /* device allocation failed */
+};
+
+/* Sparse matrix in CSR form, device pointers.  dtype is SDR_F64 or SDR_C128. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const void* values;
+  sdr_dtype dtype;
+} sdr_csr;
+
+/* Counters and timings of the last solve (paper Section 5 counts MV and IP). */
+typedef struct {
+  int32_t cycles;          /* restart cycles run */
+  int32_t iters;           /* Arnoldi steps (accepted) */
+  int32_t matvecs;         /* products with A, incl. residual checks */
+  int32_t inner_products;  /* length-N inner products and norms */
+  int32_t sketches;        /* length-N vectors sketched */
+  int32_t res_checks;      /* true-residual evaluations (Section 3.4) */
+  int32_t status;          /* return code of the solve */
+  int32_t k_eff;           /* recycle dimension after the solve */
+  double relres;           /* ||b - A x|| / ||b|| at exit (FP64) */
+  double sres;             /* last sketched residual */
+  double safety;           /* safety factor at exit */
+  double seconds;          /* wall time of the solve */
+  double host_eig_seconds; /* host time in the harmonic-Ritz eigen-step */
+  double gpu_step_seconds; /* not used; 0 */
+} sdr_stats;
+
+/* Per-cycle decision record of the last solve. */
+typedef struct {
+  int32_t j_stop;     /* Arnoldi steps taken in the cycle */
+  int32_t n_checks;   /* true-residual checks in the cycle */
+  int32_t ell;        /* numerical rank used in the harmonic-Ritz step */
+  int32_t k_eff;      /* recycle dimension produced */
+  int32_t flags;      /* 1 converged, 2 Arnoldi breakdown, 4 rank loss */
+  int32_t pad;
+  double sres;        /* sketched residual at the stop */
+  double res;         /* true residual at the stop (absolute) */
+} sdr_cycle_record;
+
+typedef struct sdr_handle sdr_handle;
+
+/*
+ * Create a solver for the n x n matrix A (Algorithm 1 inputs m, t, k, s).
+ *   m      Arnoldi steps per cycle (>= 1); the search space is [U, V(:,1:j)].
+ *   k      recycle dimension (>= 0); real problems may keep k+1 so that a
+ *          complex-conjugate harmonic-Ritz pair is never split.
+ *   t      truncation window (1 <= t <= min(m, 4)).
+ *   s_dim  sketch rows; s_dim > m + k and s_dim % zeta == 0 (zeta = 8 by
+ *          default, option "zeta").
+ *   seed   64-bit seed of the sketching operator.
+ * The CSR arrays are copied.  Returns NULL on error (see sdr_last_error()).
+ */
+sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_t seed);
+
+/*
+ * Set an option (before the first solve for "precision" and "zeta").
+ *   "zeta"           nonzeros per sketch column (default 8)
+ *   "max_cycles"     restart limit (default 10000)
+ *   "safety0"        initial safety factor (default 1.4, Section 3.4)
+ *   "persist_safety" 1: keep safety across cycles (default 0: reset per cycle)
+ *   "precision"      0: basis in the matrix precision (FP64 / complex128);
+ *                    1: basis, SpMV and sketches in FP32 / complex64 with the
+ *                    least squares, eigen-step and residual in FP64 / c128
+ *   "variant"        0: exact sequences (recompute S A_i U), 1: inexact
+ *   "breakdown_rtol" Arnoldi breakdown threshold (default 1e-14; 1e-6 FP32)
+ *   "rank_rtol"      rank-loss threshold of the sketched LSQ (default 1e-12)
+ *   "lookahead"      Arnoldi steps queued ahead of the host (default 4)
+ * Returns 0 or SDR_EINVAL.
+ */
+int sdr_set_option(sdr_handle* h, const char* key, double value);
+
+/* Use this HIP stream (hipStream_t as void*); NULL selects the handle's own. */
+int sdr_set_stream(sdr_handle* h, void* hip_stream);
+
+/*
+ * Solve A x = b to ||b - A x|| <= tol * ||b||.  If A_or_null is not NULL it
+ * replaces the matrix first (as sdr_update_matrix).  x holds the initial guess
+ * on entry and the solution on exit.  The recycle space of the previous solve
+ * is reused (Section 3.6).  stats may be NULL.
+ * Returns 0, SDR_NOT_CONVERGED, or an error code.
+ */
+int sdr_solve(sdr_handle* h, const sdr_csr* A_or_null, const void* b, void* x, double tol,
+              sdr_stats* stats);
+
+/*
+ * Replace the matrix values (same n, nnz, row_ptr, col_idx) for the next solve
+ * of a sequence.  With the exact variant the next solve recomputes S A_i U
+ * (k extra products and sketches); the inexact variant keeps the stale one.
+ * Returns 0, SDR_EPATTERN, or an error code.
+ */
+int sdr_update_matrix(sdr_handle* h, const sdr_csr* A_i);
+
+/*
+ * Adjoint solve A^T lambda = g (A^H for complex) with its own recycle space,
+ * kept across calls.  tol is relative to ||g||.  Returns as sdr_solve.
+ */
+int sdr_solve_adjoint(sdr_handle* h, const void* g, void* lambda, double tol, sdr_stats* stats);
+
+/*
+ * For every stored entry e = (i, j): grad_vals[e] = -lambda[i] * x[j] (real)
+ * or -lambda[i] * conj(x[j]) (complex).  With A x = b and lambda solving the
+ * adjoint system A^T lambda = dL/dx (A^H lambda = dL/d conj(x) for complex
+ * data) this is the derivative of the loss L with respect to the stored
+ * entries of A (with respect to conj(A_ij) for complex data); dL/db = lambda.
+ * lambda, x: n device vectors, grad_vals: nnz device vector, matrix dtype.
+ */
+int sdr_grad_values(sdr_handle* h, const void* lambda, const void* x, void* grad_vals);
+
+/* Copy the per-cycle records of the last solve; returns the number written. */
+int sdr_get_trace(sdr_handle* h, sdr_cycle_record* out, int cap);
+
+/* Current recycle dimension, and a copy of U (n x k, ld = n), SU, SAU
+ * (s x k, ld = s) into device buffers (any may be NULL).  Real handles write
+ * float64; complex handles complex128. */
+int sdr_get_recycle(sdr_handle* h, void* U, void* SU, void* SAU, int* k_out);
+
+/* y = S X for ncols device columns X (ld = n) in the handle's FP64/c128
+ * type; Y is s x ncols (ld = s).  The operator Section 3 describes, drawn
+ * from the handle's seed. */
+int sdr_sketch(sdr_handle* h, const void* X, int ncols, void* Y);
+
+/* y = A x with the handle's matrix (FP64 / complex128 device vectors). */
+int sdr_spmv(sdr_handle* h, const void* x, void* y);
+
+/* Basis data of the last cycle for inspection: the first ncols normalised
+ * basis vectors V (n x ncols, FP64/c128 device), H ((m+1) x m host, column
+ * major), SV (s x ncols host).  Any pointer may be NULL. */
+int sdr_get_basis(sdr_handle* h, int ncols, void* V, void* H_host, void* SV_host);
+
+void sdr_destroy(sdr_handle* h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* sdr_last_error(void);
+
+/*
+ * Host-only helper used by the library's cycle end and exported for testing:
+ * the sketched harmonic-Ritz step (Section 3.5).  Given the triangular factor
+ * R (l0 x l0, column major, upper) of SAW = Q R and C = Q^H [SU, SV] (l0 x l0),
+ * computes G (l0 x k_eff, column major, ld = l0) whose columns span the
+ * invariant subspace of the k largest-modulus eigenvalues of the sketched
+ * pencil, with the truncated-SVD regularisation when R is numerically rank
+ * deficient.  is_complex selects complex128 data; for real data G is real and
+ * a conjugate pair is never split.  Returns k_eff (>= 0) and writes ell, or a
+ * negative error code.  G must hold l0 * (k+1) elements.
+ */
+int sdr_host_harmonic_ritz(int l0, const void* R, const void* C, int s, int k, int is_complex,
+                           void* G, int* ell);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDR_H */

@@ -1,0 +1,435 @@
+// Host small-dense linear algebra for the sketched harmonic-Ritz step
+// (Section 3.5): the ordered generalised Schur decomposition of the pencil
+// (M_ell, Sigma_ell) is computed as the ordered Schur decomposition of
+// Sigma_ell^{-1} M_ell, whose invariant subspace is the pencil's right
+// deflating subspace because Sigma_ell is diagonal and positive.  When the
+// triangular factor R of SAW = Q R is comfortably far from the truncation
+// threshold, the truncated SVD keeps every singular value and the matrix is
+// similar (by the unitary right singular vectors) to R^{-1} Q^H [SU, SV], the
+// minimum-norm solution of eq. (3.5); that matrix is used directly and the SVD
+// is skipped.
+#include "dense.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <numeric>
+
+namespace sdr {
+namespace dense {
+
+static inline double abs1(cd z) { return std::fabs(z.real()) + std::fabs(z.imag()); }
+
+// Rotation G = [[c, s], [-conj(s), c]] with G [x; y] = [r; 0], c real.
+static inline void givens(cd x, cd y, double& c, cd& s) {
+  const double ay = std::abs(y);
+  if (ay == 0.0) {
+    c = 1.0;
+    s = 0.0;
+    return;
+  }
+  const double ax = std::abs(x);
+  if (ax == 0.0) {
+    c = 0.0;
+    s = std::conj(y) / ay;
+    return;
+  }
+  const double r = std::hypot(ax, ay);
+  c = ax / r;
+  s = (x / ax) * std::conj(y) / r;
+}
+
+bool schur(Mat& T, Mat& Z) {
+  const int n = T.n;
+  Z = Mat(n, n);
+  for (int i = 0; i < n; ++i) Z(i, i) = 1.0;
+  if (n <= 1) return true;
+  // Householder reduction to upper Hessenberg form, T <- P T P, Z <- Z P.
+  std::vector<cd> v(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int len = n - k - 1;
+    double xn = 0.0;
+    for (int i = 0; i < len; ++i) xn += std::norm(T(k + 1 + i, k));
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const cd x0 = T(k + 1, k);
+    const double ax0 = std::abs(x0);
+    const cd alpha = -(ax0 > 0.0 ? x0 / ax0 : cd(1.0, 0.0)) * xn;
+    for (int i = 0; i < len; ++i) v[i] = T(k + 1 + i, k);
+    v[0] -= alpha;
+    double vn2 = 0.0;
+    for (int i = 0; i < len; ++i) vn2 += std::norm(v[i]);
+    if (vn2 == 0.0) continue;
+    const double f = 2.0 / vn2;
+    for (int j = k; j < n; ++j) {
+      cd s = 0.0;
+      for (int i = 0; i < len; ++i) s += std::conj(v[i]) * T(k + 1 + i, j);
+      s *= f;
+      for (int i = 0; i < len; ++i) T(k + 1 + i, j) -= v[i] * s;
+    }
+    for (int i = 0; i < n; ++i) {
+      cd s = 0.0;
+      for (int l = 0; l < len; ++l) s += T(i, k + 1 + l) * v[l];
+      s *= f;
+      for (int l = 0; l < len; ++l) T(i, k + 1 + l) -= s * std::conj(v[l]);
+    }
+    for (int i = 0; i < n; ++i) {
+      cd s = 0.0;
+      for (int l = 0; l < len; ++l) s += Z(i, k + 1 + l) * v[l];
+      s *= f;
+      for (int l = 0; l < len; ++l) Z(i, k + 1 + l) -= s * std::conj(v[l]);
+    }
+    T(k + 1, k) = alpha;
+    for (int i = 1; i < len; ++i) T(k + 1 + i, k) = 0.0;
+  }
+  // Single-shift QR iteration with Wilkinson shifts and deflation.
+  const double eps = std::numeric_limits<double>::epsilon();
+  double anorm = 0.0;
+  for (auto& z : T.a) anorm = std::max(anorm, abs1(z));
+  int hi = n - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    int l = hi;
+    for (; l > 0; --l) {
+      double sc = abs1(T(l - 1, l - 1)) + abs1(T(l, l));
+      if (sc == 0.0) sc = anorm;
+      if (abs1(T(l, l - 1)) <= eps * sc) break;
+    }
+    if (l > 0) T(l, l - 1) = 0.0;
+    if (l == hi) {
+      --hi;
+      iter = 0;
+      continue;
+    }
+    cd mu;
+    if (iter > 0 && iter % 10 == 0) {
+      mu = T(hi, hi) + cd(0.75 * abs1(T(hi, hi - 1)), 0.0);  // exceptional shift
+    } else {
+      const cd a = T(hi - 1, hi - 1), b = T(hi - 1, hi), c = T(hi, hi - 1), d = T(hi, hi);
+      const cd tr = 0.5 * (a + d);
+      const cd disc = std::sqrt(0.25 * (a - d) * (a - d) + b * c);
+      const cd m1 = tr + disc, m2 = tr - disc;
+      mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+    }
+    cd x = T(l, l) - mu, y = T(l + 1, l);
+    for (int k = l; k < hi; ++k) {
+      if (k > l) {
+        x = T(k, k - 1);
+        y = T(k + 1, k - 1);
+      }
+      double c;
+      cd s;
+      givens(x, y, c, s);
+      for (int j = std::max(l, k - 1); j < n; ++j) {
+        const cd t1 = T(k, j), t2 = T(k + 1, j);
+        T(k, j) = c * t1 + s * t2;
+        T(k + 1, j) = -std::conj(s) * t1 + c * t2;
+      }
+      const int rmax = std::min(k + 2, hi);
+      for (int i = 0; i <= rmax; ++i) {
+        const cd t1 = T(i, k), t2 = T(i, k + 1);
+        T(i, k) = c * t1 + std::conj(s) * t2;
+        T(i, k + 1) = -s * t1 + c * t2;
+      }
+      for (int i = 0; i < n; ++i) {
+        const cd t1 = Z(i, k), t2 = Z(i, k + 1);
+        Z(i, k) = c * t1 + std::conj(s) * t2;
+        Z(i, k + 1) = -s * t1 + c * t2;
+      }
+      if (k > l) T(k + 1, k - 1) = 0.0;
+    }
+    ++iter;
+    if (++total > 60 * n) return false;
+  }
+  for (int j = 0; j < n; ++j)
+    for (int i = j + 1; i < n; ++i) T(i, j) = 0.0;
+  return true;
+}
+
+// Exchange the diagonal entries i and i+1 of the upper triangular T by a
+// unitary 2 x 2 rotation whose first column is the eigenvector of the
+// trailing entry; update Z accordingly.
+static void swap_adjacent(Mat& T, Mat& Z, int i) {
+  const int n = T.n;
+  const cd a = T(i, i), b = T(i + 1, i + 1), c = T(i, i + 1);
+  const cd x0 = c, x1 = b - a;
+  const double nr = std::hypot(std::abs(x0), std::abs(x1));
+  if (nr == 0.0) return;
+  const cd z0 = x0 / nr, z1 = x1 / nr;
+  for (int r = 0; r <= i + 1; ++r) {
+    const cd t1 = T(r, i), t2 = T(r, i + 1);
+    T(r, i) = t1 * z0 + t2 * z1;
+    T(r, i + 1) = -t1 * std::conj(z1) + t2 * std::conj(z0);
+  }
+  for (int cc = i; cc < n; ++cc) {
+    const cd t1 = T(i, cc), t2 = T(i + 1, cc);
+    T(i, cc) = std::conj(z0) * t1 + std::conj(z1) * t2;
+    T(i + 1, cc) = -z1 * t1 + z0 * t2;
+  }
+  for (int r = 0; r < n; ++r) {
+    const cd t1 = Z(r, i), t2 = Z(r, i + 1);
+    Z(r, i) = t1 * z0 + t2 * z1;
+    Z(r, i + 1) = -t1 * std::conj(z1) + t2 * std::conj(z0);
+  }
+  T(i + 1, i) = 0.0;
+  T(i, i) = b;
+  T(i + 1, i + 1) = a;
+}
+
+int reorder(Mat& T, Mat& Z, std::vector<char> sel) {
+  const int n = T.n;
+  int ks = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!sel[i]) continue;
+    for (int p = i; p > ks; --p) swap_adjacent(T, Z, p - 1);
+    ++ks;
+  }
+  return ks;
+}
+
+void svd_jacobi(const Mat& A0, Mat& P, std::vector<double>& sig, Mat& W) {
+  const int n = A0.n;
+  Mat A = A0;
+  W = Mat(n, n);
+  for (int i = 0; i < n; ++i) W(i, i) = 1.0;
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n - 1; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        double al = 0.0, be = 0.0;
+        cd ga = 0.0;
+        for (int i = 0; i < n; ++i) {
+          al += std::norm(A(i, p));
+          be += std::norm(A(i, q));
+          ga += std::conj(A(i, p)) * A(i, q);
+        }
+        const double ag = std::abs(ga);
+        if (ag == 0.0 || ag <= eps * std::sqrt(al * be)) continue;
+        off = std::max(off, ag / std::sqrt(al * be));
+        const cd e = ga / ag;
+        const double zeta = (be - al) / (2.0 * ag);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+        // [a_p, a_q] <- [a_p, a_q] [[c, s e], [-s conj(e), c]]
+        for (int i = 0; i < n; ++i) {
+          const cd ap = A(i, p), aq = A(i, q);
+          A(i, p) = c * ap - s * std::conj(e) * aq;
+          A(i, q) = s * e * ap + c * aq;
+          const cd wp = W(i, p), wq = W(i, q);
+          W(i, p) = c * wp - s * std::conj(e) * wq;
+          W(i, q) = s * e * wp + c * wq;
+        }
+      }
+    }
+    if (off <= eps * n) break;
+  }
+  sig.assign(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += std::norm(A(i, j));
+    sig[j] = std::sqrt(s);
+  }
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return sig[a] > sig[b]; });
+  Mat Ps(n, n), Ws(n, n);
+  std::vector<double> ss(n);
+  for (int jj = 0; jj < n; ++jj) {
+    const int j = ord[jj];
+    ss[jj] = sig[j];
+    const double inv = sig[j] > 0.0 ? 1.0 / sig[j] : 0.0;
+    for (int i = 0; i < n; ++i) {
+      Ps(i, jj) = A(i, j) * inv;
+      Ws(i, jj) = W(i, j);
+    }
+  }
+  P = Ps;
+  W = Ws;
+  sig = ss;
+}
+
+// Real orthonormal basis of the span of the complex columns Zk, assumed closed
+// under conjugation: pivoted Gram-Schmidt (twice) on [Re Zk, Im Zk].
+static Mat real_basis(const Mat& Zk, int keff) {
+  const int n = Zk.n, m = Zk.m;
+  std::vector<std::vector<double>> cols;
+  for (int j = 0; j < m; ++j) {
+    std::vector<double> re(n), im(n);
+    for (int i = 0; i < n; ++i) {
+      re[i] = Zk(i, j).real();
+      im[i] = Zk(i, j).imag();
+    }
+    cols.push_back(re);
+    cols.push_back(im);
+  }
+  Mat out(n, keff);
+  std::vector<char> used(cols.size(), 0);
+  for (int k = 0; k < keff; ++k) {
+    int best = -1;
+    double bn = -1.0;
+    for (size_t c = 0; c < cols.size(); ++c) {
+      if (used[c]) continue;
+      double s = 0.0;
+      for (double v : cols[c]) s += v * v;
+      if (s > bn) {
+        bn = s;
+        best = (int)c;
+      }
+    }
+    if (best < 0 || bn <= 0.0) break;
+    used[best] = 1;
+    std::vector<double> q = cols[best];
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int p = 0; p < k; ++p) {
+        double d = 0.0;
+        for (int i = 0; i < n; ++i) d += out(i, p).real() * q[i];
+        for (int i = 0; i < n; ++i) q[i] -= d * out(i, p).real();
+      }
+    }
+    double qn = 0.0;
+    for (double v : q) qn += v * v;
+    qn = std::sqrt(qn);
+    for (int i = 0; i < n; ++i) out(i, k) = q[i] / qn;
+    for (size_t c = 0; c < cols.size(); ++c) {
+      if (used[c]) continue;
+      double d = 0.0;
+      for (int i = 0; i < n; ++i) d += out(i, k).real() * cols[c][i];
+      for (int i = 0; i < n; ++i) cols[c][i] -= d * out(i, k).real();
+    }
+  }
+  return out;
+}
+
+int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std::vector<cd>& G,
+                  int* ell_out) {
+  G.clear();
+  *ell_out = 0;
+  if (l0 <= 0 || k <= 0) return 0;
+  const double thr = std::max(s, l0) * std::ldexp(1.0, -52);
+  Mat Rm(l0, l0), Cm(l0, l0);
+  for (int j = 0; j < l0; ++j)
+    for (int i = 0; i < l0; ++i) {
+      Rm(i, j) = i <= j ? R[(size_t)j * l0 + i] : cd(0.0);
+      Cm(i, j) = C[(size_t)j * l0 + i];
+    }
+  // triangular inverse and the 1-norm condition number of R
+  Mat Ri(l0, l0);
+  bool singular = false;
+  for (int i = 0; i < l0; ++i)
+    if (std::abs(Rm(i, i)) == 0.0) singular = true;
+  double cond = std::numeric_limits<double>::infinity();
+  if (!singular) {
+    for (int j = 0; j < l0; ++j) {
+      Ri(j, j) = 1.0 / Rm(j, j);
+      for (int i = j - 1; i >= 0; --i) {
+        cd acc = 0.0;
+        for (int p = i + 1; p <= j; ++p) acc += Rm(i, p) * Ri(p, j);
+        Ri(i, j) = -acc / Rm(i, i);
+      }
+    }
+    double n1 = 0.0, n1i = 0.0;
+    for (int j = 0; j < l0; ++j) {
+      double a = 0.0, b = 0.0;
+      for (int i = 0; i < l0; ++i) {
+        a += std::abs(Rm(i, j));
+        b += std::abs(Ri(i, j));
+      }
+      n1 = std::max(n1, a);
+      n1i = std::max(n1i, b);
+    }
+    cond = n1 * n1i;
+  }
+  // cond_2(R) <= l0 * cond_1(R): below the threshold no singular value is cut.
+  const bool svd_path = !(std::isfinite(cond) && (double)l0 * cond * thr < 1e-2);
+  Mat Aeig;
+  Mat Wl;  // right singular vectors kept (svd path)
+  int ell = l0;
+  if (!svd_path) {
+    Aeig = Mat(l0, l0);
+    for (int j = 0; j < l0; ++j)
+      for (int i = 0; i < l0; ++i) {
+        cd acc = 0.0;
+        for (int p = i; p < l0; ++p) acc += Ri(i, p) * Cm(p, j);
+        Aeig(i, j) = acc;
+      }
+  } else {
+    Mat P, W;
+    std::vector<double> sig;
+    svd_jacobi(Rm, P, sig, W);
+    ell = 0;
+    if (sig[0] > 0.0)
+      for (int i = 0; i < l0; ++i)
+        if (sig[i] > sig[0] * thr) ++ell;
+    if (ell == 0) return 0;
+    Mat PC(ell, l0);  // P_ell^H C
+    for (int j = 0; j < l0; ++j)
+      for (int i = 0; i < ell; ++i) {
+        cd acc = 0.0;
+        for (int p = 0; p < l0; ++p) acc += std::conj(P(p, i)) * Cm(p, j);
+        PC(i, j) = acc;
+      }
+    Aeig = Mat(ell, ell);
+    for (int j = 0; j < ell; ++j)
+      for (int i = 0; i < ell; ++i) {
+        cd acc = 0.0;
+        for (int p = 0; p < l0; ++p) acc += PC(i, p) * W(p, j);
+        Aeig(i, j) = acc / sig[i];
+      }
+    Wl = Mat(l0, ell);
+    for (int j = 0; j < ell; ++j)
+      for (int i = 0; i < l0; ++i) Wl(i, j) = W(i, j);
+  }
+  *ell_out = ell;
+  Mat T = Aeig, Z;
+  if (!schur(T, Z)) return -1;
+  const int n = ell;
+  std::vector<cd> lam(n);
+  for (int i = 0; i < n; ++i) lam[i] = T(i, i);
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int a, int b) { return std::abs(lam[a]) > std::abs(lam[b]); });
+  const int kk = std::min(k, n);
+  std::vector<char> sel(n, 0);
+  for (int i = 0; i < kk; ++i) sel[ord[i]] = 1;
+  if (real) {
+    // never split a complex-conjugate pair
+    for (int i = 0; i < n; ++i) {
+      if (!sel[i]) continue;
+      const double al = std::abs(lam[i]);
+      if (std::fabs(lam[i].imag()) <= 1e-8 * al) continue;
+      int best = -1;
+      double bd = std::numeric_limits<double>::infinity();
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double d = std::abs(lam[j] - std::conj(lam[i]));
+        if (d < bd) {
+          bd = d;
+          best = j;
+        }
+      }
+      if (best >= 0 && bd <= 1e-6 * al && !sel[best]) sel[best] = 1;
+    }
+  }
+  const int keff = reorder(T, Z, sel);
+  Mat Zk(n, keff);
+  for (int j = 0; j < keff; ++j)
+    for (int i = 0; i < n; ++i) Zk(i, j) = Z(i, j);
+  Mat Y = real ? real_basis(Zk, keff) : Zk;
+  G.assign((size_t)l0 * keff, cd(0.0));
+  if (!svd_path) {
+    for (int j = 0; j < keff; ++j)
+      for (int i = 0; i < l0; ++i) G[(size_t)j * l0 + i] = Y(i, j);
+  } else {
+    for (int j = 0; j < keff; ++j)
+      for (int i = 0; i < l0; ++i) {
+        cd acc = 0.0;
+        for (int p = 0; p < n; ++p) acc += Wl(i, p) * Y(p, j);
+        G[(size_t)j * l0 + i] = real ? cd(acc.real(), 0.0) : acc;
+      }
+  }
+  return keff;
+}
+
+}  // namespace dense
+}  // namespace sdr

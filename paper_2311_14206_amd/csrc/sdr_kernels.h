@@ -1,0 +1,131 @@
+// Launch wrappers of the GMRES-SDR device kernels (gfx950).
+#pragma once
+
+#include "sdr_common.h"
+
+namespace sdr {
+
+constexpr int kBlock = 256;        // threads per block of the streaming kernels
+constexpr int kWaves = kBlock / 64;
+constexpr int kLsqBlock = 512;     // threads of the single-block least-squares kernels
+constexpr int kMaxWindow = 4;      // largest truncation window t
+constexpr int kRowsSpmv = 1024;    // rows per block, SpMV + window dots
+constexpr int kRowsUpdate = 2048;  // rows per block, update + norm + sketch
+
+template <class T> struct Window { const T* p[kMaxWindow]; };
+
+// Host-visible record of one Arnoldi step, written by the least-squares kernel.
+struct StepRec {
+  double sres;
+  double nu;
+  int32_t j;
+  int32_t flags;  // 1 halt, 2 breakdown, 4 rank loss
+  int32_t seq;    // written last: equals j once the record is complete
+  int32_t pad;
+};
+
+// Device control block of a cycle.
+struct Ctrl {
+  int32_t halt;     // != 0: step kernels return immediately
+  int32_t halt_j;
+  int32_t flags;
+  int32_t pad;
+  double thresh;    // tol_abs / safety
+};
+
+// Small dense state of the sketched least squares (FP64 / complex128).
+template <class A> struct LsqState {
+  A* Q;    int ldq;   // s x Lmax orthonormal factor of SAW
+  A* R;    int ldr;   // Lmax x Lmax upper triangular, column major
+  A* z;               // Q^H S r0
+  A* rho;             // S r0 - Q Q^H S r0 (projected sketched residual)
+  A* SB;   int ldsb;  // [SU, SV]       s x (khat + m + 1)
+  A* SAW;  int ldsaw; // [SAU, SAV]     s x (khat + m)
+  A* H;    int ldh;   // (m+1) x m Hessenberg (banded), column major
+  double* nu;         // norms of the stored basis vectors p_i
+  double* sres_hist;
+  Ctrl* ctrl;
+  StepRec* rec;       // host-mapped records, one per step
+};
+
+// w = A x, partial window products <p_q, w> and ||w||^2 per block.
+template <class T>
+void launch_spmv_dots(hipStream_t st, int n, const int* rp, const int* ci, const T* val, const T* x,
+                      T* w, Window<T> win, int tw, typename traits<T>::acc* part, int nb,
+                      const Ctrl* ctrl);
+
+// w <- w - sum_q (d_q / nu_{i0+q}^2) p_{i0+q}; partial ||w||^2 and S w per block.
+template <class T>
+void launch_update_sketch(hipStream_t st, int n, T* w, Window<T> win, int tw,
+                          const typename traits<T>::acc* red1, const double* nu, int i0,
+                          SketchSpec sk, typename traits<T>::acc* part, int nb, const Ctrl* ctrl);
+
+// out[c] = scale_c * sum_b part[c * nb + b] (fixed order); scale 1/sqrt(zeta) for c < nscaled.
+template <class A>
+void launch_reduce_cols(hipStream_t st, const A* part, int nb, int ncols, int nscaled,
+                        double scale, A* out, const Ctrl* ctrl);
+
+// One Arnoldi step's small work: H column, SV column, SAV column, QR append,
+// projected residual and the halt decision.
+template <class A>
+void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int t, int s,
+                     const A* red1, const A* red2, double brtol, double rank_rtol);
+
+// Initialise the QR of SAW with its first khat columns (SAU) and rho = S r0.
+template <class A>
+void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr,
+                     double rank_rtol);
+
+// y = R(0:n,0:n)^{-1} z(0:n); coefficients for [U, P]: y_i (U part), y_i / nu_i (P part).
+template <class A>
+void launch_backsolve(hipStream_t st, LsqState<A> S, int n, int khat, A* ycoef);
+
+// Batched sketch of cc columns of X (ld) plus column norms: partials
+// [(cc*s + cc) x nb], then reduced by launch_reduce_cols.
+template <class X>
+void launch_sketch_cols(hipStream_t st, int n, const X* x, int64_t ld, int cc, SketchSpec sk,
+                        typename traits<X>::acc* part, int nb);
+
+// xt = U yU + P yP (ku + jp columns), output in the accumulation type.
+template <class T>
+void launch_gemv_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
+                       int64_t ldp, int jp, const typename traits<T>::acc* y,
+                       typename traits<T>::acc* out);
+
+// rnew = r0 - A x (full precision values), partial ||rnew||^2 per block (nb = ceil(n/kRowsUpdate)).
+template <class A>
+void launch_spmv_residual(hipStream_t st, int n, const int* rp, const int* ci, const A* val,
+                          const A* x, const A* r0, A* rnew, A* part, int nb);
+
+// C = [U P] G (n x kc), G (ku + jp) x kc column major (ld = ku + jp).
+template <class T>
+void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
+                       int64_t ldp, int jp, const typename traits<T>::acc* G, int kc, T* C,
+                       int64_t ldc);
+
+// C (M x N) = op(A) B with op(A) = A^H (A stored K x M) or A (M x K); small sizes.
+template <class A>
+void launch_small_gemm(hipStream_t st, bool conjtrans, int M, int N, int K, const A* a, int lda,
+                       const A* b, int ldb, A* c, int ldc);
+
+template <class A> void launch_axpy(hipStream_t st, int n, A alpha, const A* x, A* y);
+// dst (T) = scale * src (acc type), rounding to T
+template <class T>
+void launch_cast_scale(hipStream_t st, int n, const typename traits<T>::acc* src, double scale,
+                       T* dst);
+// dst (T) = src (T) cast from full precision A values (matrix copy)
+template <class T>
+void launch_narrow_values(hipStream_t st, int64_t n, const typename traits<T>::acc* src, T* dst);
+template <class A>
+void launch_gather_conj(hipStream_t st, int64_t nnz, const A* src, const int* perm, A* dst);
+template <class A>
+void launch_grad_values(hipStream_t st, int n, const int* rp, const int* ci, const A* lam,
+                        const A* x, A* g);
+// widen T -> acc (for basis inspection)
+template <class T>
+void launch_widen_scale(hipStream_t st, int n, const T* src, double scale,
+                        typename traits<T>::acc* dst);
+
+void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh);
+
+}  // namespace sdr

@@ -1,0 +1,737 @@
+// GMRES-SDR device kernels for gfx950 (wave64, LDS-staged sketches).
+//
+// Per Arnoldi step (Algorithm 1, truncated Arnoldi with one sketch per step):
+//   k_spmv_dots      w = A p_j and the window products <p_i, w>, ||w||^2
+//   k_reduce_cols    fixed-order reduction of the per-block partials
+//   k_update_sketch  p_{j+1} = w - sum c_i p_i in place, ||p_{j+1}||^2 and S p_{j+1}
+//   k_reduce_cols    again, for the s + 1 partial columns
+//   k_lsq_step       H column, SV and SAV columns, QR append, sketched residual
+// Basis vectors are stored unnormalised (p_i = nu_i v_i); the norms nu_i are
+// folded into the coefficients, which saves a normalisation pass per step.
+
+#include "sdr_kernels.h"
+
+namespace sdr {
+
+// ------------------------------------------------------------ reductions --
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ cx<double> wave_sum(cx<double> v) { return {wave_sum(v.x), wave_sum(v.y)}; }
+
+// Sum of one value per thread over the block, same order on every call.
+// red must hold blockDim.x / 64 entries; result valid in every thread.
+template <class A>
+__device__ A block_sum(A v, A* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  A s = red[0];
+  for (int i = 1; i < nw; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
+__device__ __forceinline__ void lds_add(cx<double>* p, cx<double> v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+
+__device__ __forceinline__ double neg_if(double v, bool n) { return n ? -v : v; }
+__device__ __forceinline__ cx<double> neg_if(cx<double> v, bool n) { return n ? -v : v; }
+
+// Scatter one element's value into the zeta rows of S's column `col`.
+template <class A>
+__device__ __forceinline__ void sketch_scatter(A* acc, int64_t col, A v, const SketchSpec& sk) {
+  const uint64_t base = sk.seed + kGamma * ((uint64_t)col * (uint64_t)sk.words + 1ull);
+  for (int g = 0; g < sk.words; ++g) {
+    const uint64_t h = mix64(base + (uint64_t)g * kGamma);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = 4 * g + q;
+      if (b < sk.zeta) {
+        const uint32_t u = (uint32_t)(h >> (16 * q)) & 0xFFFFu;
+        const int row = b * sk.bsz + (int)(((u >> 1) * (uint32_t)sk.bsz) >> 15);
+        lds_add(&acc[row], neg_if(v, (u & 1u) != 0u));
+      }
+    }
+  }
+}
+
+// ------------------------------------------------- SpMV + window products --
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_spmv_dots(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
+    const T* __restrict__ x, T* __restrict__ w, Window<T> win, int tw,
+    typename traits<T>::acc* __restrict__ part, int nb, const Ctrl* __restrict__ ctrl) {
+  using A = typename traits<T>::acc;
+  if (ctrl->halt) return;
+  __shared__ A red[kWaves];
+  A d[kMaxWindow];
+#pragma unroll
+  for (int q = 0; q < kMaxWindow; ++q) d[q] = zero<A>();
+  double nw = 0.0;
+  const int r0 = blockIdx.x * kRowsSpmv;
+  const int r1 = min(n, r0 + kRowsSpmv);
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+    A acc = zero<A>();
+    const int e1 = rp[r + 1];
+    for (int e = rp[r]; e < e1; ++e) acc += widen(val[e]) * widen(x[ci[e]]);
+    const T wt = narrow<T>(acc);
+    w[r] = wt;
+    const A wa = widen(wt);
+    nw += abs2(wa);
+#pragma unroll
+    for (int q = 0; q < kMaxWindow; ++q)
+      if (q < tw) d[q] += conj(widen(win.p[q][r])) * wa;
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxWindow; ++q) {
+    if (q < tw) {
+      const A s = block_sum(d[q], red);
+      if (threadIdx.x == 0) part[(int64_t)q * nb + blockIdx.x] = s;
+    }
+  }
+  const double s = block_sum(nw, (double*)red);
+  if (threadIdx.x == 0) {
+    A v = zero<A>();
+    *(double*)&v = s;
+    part[(int64_t)tw * nb + blockIdx.x] = v;
+  }
+}
+
+template <class T>
+void launch_spmv_dots(hipStream_t st, int n, const int* rp, const int* ci, const T* val, const T* x,
+                      T* w, Window<T> win, int tw, typename traits<T>::acc* part, int nb,
+                      const Ctrl* ctrl) {
+  hipLaunchKernelGGL(k_spmv_dots<T>, dim3(nb), dim3(kBlock), 0, st, n, rp, ci, val, x, w, win, tw,
+                     part, nb, ctrl);
+}
+
+// ---------------------------------------- update + norm + sparse sketch ---
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_update_sketch(
+    int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ red1,
+    const double* __restrict__ nu, int i0, SketchSpec sk, typename traits<T>::acc* __restrict__ part,
+    int nb, const Ctrl* __restrict__ ctrl) {
+  using A = typename traits<T>::acc;
+  if (ctrl->halt) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  A* acc = reinterpret_cast<A*>(smem_raw);  // [kWaves][s], one copy per wave
+  __shared__ A red[kWaves];
+  const int s = sk.s;
+  for (int i = threadIdx.x; i < kWaves * s; i += kBlock) acc[i] = zero<A>();
+  A c[kMaxWindow];
+#pragma unroll
+  for (int q = 0; q < kMaxWindow; ++q) {
+    if (q < tw) {
+      const double nq = nu[i0 + q];
+      c[q] = scale(red1[q], 1.0 / (nq * nq));
+    } else {
+      c[q] = zero<A>();
+    }
+  }
+  __syncthreads();
+  A* mine = acc + (threadIdx.x >> 6) * s;
+  double nrm = 0.0;
+  const int r0 = blockIdx.x * kRowsUpdate;
+  const int r1 = min(n, r0 + kRowsUpdate);
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+    A v = widen(w[r]);
+#pragma unroll
+    for (int q = 0; q < kMaxWindow; ++q)
+      if (q < tw) v -= c[q] * widen(win.p[q][r]);
+    const T vt = narrow<T>(v);
+    w[r] = vt;
+    const A va = widen(vt);
+    nrm += abs2(va);
+    sketch_scatter(mine, r, va, sk);
+  }
+  __syncthreads();
+  for (int row = threadIdx.x; row < s; row += kBlock) {
+    A sum = acc[row];
+    for (int q = 1; q < kWaves; ++q) sum += acc[q * s + row];
+    part[(int64_t)row * nb + blockIdx.x] = sum;
+  }
+  const double ns = block_sum(nrm, (double*)red);
+  if (threadIdx.x == 0) {
+    A v = zero<A>();
+    *(double*)&v = ns;
+    part[(int64_t)s * nb + blockIdx.x] = v;
+  }
+}
+
+template <class T>
+void launch_update_sketch(hipStream_t st, int n, T* w, Window<T> win, int tw,
+                          const typename traits<T>::acc* red1, const double* nu, int i0,
+                          SketchSpec sk, typename traits<T>::acc* part, int nb, const Ctrl* ctrl) {
+  using A = typename traits<T>::acc;
+  const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
+  hipLaunchKernelGGL(k_update_sketch<T>, dim3(nb), dim3(kBlock), lds, st, n, w, win, tw, red1, nu,
+                     i0, sk, part, nb, ctrl);
+}
+
+// ------------------------------------------------ fixed-order reduction ---
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_reduce_cols(const A* __restrict__ part, int nb,
+                                                        int nscaled, double scl, A* __restrict__ out,
+                                                        const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->halt) return;
+  __shared__ A red[kWaves];
+  const int col = blockIdx.x;
+  A sum = zero<A>();
+  for (int i = threadIdx.x; i < nb; i += kBlock) sum += part[(int64_t)col * nb + i];
+  sum = block_sum(sum, red);
+  if (threadIdx.x == 0) out[col] = col < nscaled ? scale(sum, scl) : sum;
+}
+
+template <class A>
+void launch_reduce_cols(hipStream_t st, const A* part, int nb, int ncols, int nscaled,
+                        double scl, A* out, const Ctrl* ctrl) {
+  hipLaunchKernelGGL(k_reduce_cols<A>, dim3(ncols), dim3(kBlock), 0, st, part, nb, nscaled, scl, out,
+                     ctrl);
+}
+
+// ------------------------------------------------ sketched least squares ---
+// Append column a (in LDS, length s) to the QR factorisation Q R of SAW by
+// classical Gram-Schmidt with one reorthogonalisation (Section 3.3 allows
+// Householder or Gram-Schmidt with reorthogonalisation), then update the
+// projected residual rho and z = Q^H S r0.  Returns the sketched residual.
+template <class A>
+__device__ double qr_append(LsqState<A>& S, A* a, A* cbuf, A* red, int col, int s,
+                            double rank_rtol, bool* rank_loss) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+  double n0 = 0.0;
+  for (int r = tid; r < s; r += blockDim.x) n0 += abs2(a[r]);
+  n0 = sqrt(block_sum(n0, (double*)red));
+  for (int i = tid; i < col; i += blockDim.x) cbuf[i] = zero<A>();
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    // c = Q^H a  (one wave per column)
+    for (int i = wv; i < col; i += nwv) {
+      A d = zero<A>();
+      const A* qi = S.Q + (int64_t)i * S.ldq;
+      for (int r = lane; r < s; r += 64) d += conj(qi[r]) * a[r];
+      d = wave_sum(d);
+      if (lane == 0) cbuf[col + i] = d;  // pass result in the upper half
+    }
+    __syncthreads();
+    // a -= Q c
+    for (int r = tid; r < s; r += blockDim.x) {
+      A v = a[r];
+      for (int i = 0; i < col; ++i) v -= S.Q[(int64_t)i * S.ldq + r] * cbuf[col + i];
+      a[r] = v;
+    }
+    for (int i = tid; i < col; i += blockDim.x) cbuf[i] += cbuf[col + i];
+    __syncthreads();
+  }
+  double na = 0.0;
+  for (int r = tid; r < s; r += blockDim.x) na += abs2(a[r]);
+  na = sqrt(block_sum(na, (double*)red));
+  const bool loss = !(na > rank_rtol * n0);
+  *rank_loss = loss;
+  const double inv = na > 0.0 ? 1.0 / na : 0.0;
+  A* qc = S.Q + (int64_t)col * S.ldq;
+  for (int r = tid; r < s; r += blockDim.x) qc[r] = scale(a[r], inv);
+  for (int i = tid; i < col; i += blockDim.x) S.R[(int64_t)col * S.ldr + i] = cbuf[i];
+  if (tid == 0) {
+    A d = zero<A>();
+    *(double*)&d = na;
+    S.R[(int64_t)col * S.ldr + col] = d;
+  }
+  __syncthreads();
+  double sres;
+  if (!loss) {
+    A zc = zero<A>();
+    for (int r = tid; r < s; r += blockDim.x) zc += conj(qc[r]) * S.rho[r];
+    zc = block_sum(zc, red);
+    double rr = 0.0;
+    for (int r = tid; r < s; r += blockDim.x) {
+      const A v = S.rho[r] - qc[r] * zc;
+      S.rho[r] = v;
+      rr += abs2(v);
+    }
+    sres = sqrt(block_sum(rr, (double*)red));
+    if (tid == 0) S.z[col] = zc;
+  } else {
+    double rr = 0.0;
+    for (int r = tid; r < s; r += blockDim.x) rr += abs2(S.rho[r]);
+    sres = sqrt(block_sum(rr, (double*)red));
+    if (tid == 0) S.z[col] = zero<A>();
+  }
+  __syncthreads();
+  return sres;
+}
+
+template <class A>
+__global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, int khat, int m,
+                                                        int t, int s, const A* __restrict__ red1,
+                                                        const A* __restrict__ red2, double brtol,
+                                                        double rank_rtol) {
+  if (S.ctrl->halt) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  A* a = reinterpret_cast<A*>(smem_raw);  // s
+  A* cbuf = a + s;                        // 2 * Lmax
+  __shared__ A red[kLsqBlock / 64];
+  __shared__ A hcol[kMaxWindow + 1];
+  __shared__ int sh_break;
+  const int tid = threadIdx.x;
+  const int i0 = j - t > 0 ? j - t : 0;  // first window vector (0-based)
+  const int tw = j - i0;
+  if (tid == 0) {
+    const double nuj = sqrt(re(red2[s]));
+    const double nuprev = S.nu[j - 1];
+    const double nw = sqrt(re(red1[tw]));
+    const bool brk = !(nuj > brtol * nw);
+    sh_break = brk;
+    S.nu[j] = nuj;
+    for (int q = 0; q < tw; ++q) {
+      const A h = scale(red1[q], 1.0 / (S.nu[i0 + q] * nuprev));
+      hcol[q] = h;
+      S.H[(int64_t)(j - 1) * S.ldh + i0 + q] = h;
+    }
+    A hs = zero<A>();
+    *(double*)&hs = brk ? 0.0 : nuj / nuprev;
+    hcol[tw] = hs;
+    S.H[(int64_t)(j - 1) * S.ldh + j] = hs;
+  }
+  __syncthreads();
+  const bool brk = sh_break;
+  const double nuj = sqrt(re(red2[s]));
+  A* svj = S.SB + (int64_t)(khat + j) * S.ldsb;
+  for (int r = tid; r < s; r += blockDim.x) {
+    const A v = brk ? zero<A>() : scale(red2[r], 1.0 / nuj);
+    svj[r] = v;
+    A sum = zero<A>();
+    for (int q = 0; q < tw; ++q) sum += S.SB[(int64_t)(khat + i0 + q) * S.ldsb + r] * hcol[q];
+    sum += v * hcol[tw];
+    a[r] = sum;
+    S.SAW[(int64_t)(khat + j - 1) * S.ldsaw + r] = sum;
+  }
+  __syncthreads();
+  bool loss = false;
+  const double sres = qr_append(S, a, cbuf, red, khat + j - 1, s, rank_rtol, &loss);
+  if (tid == 0) {
+    int flags = 0;
+    if (brk) flags |= 2;
+    if (loss) flags |= 4;
+    const bool halt = sres < S.ctrl->thresh || j == m || brk || loss;
+    if (halt) flags |= 1;
+    S.sres_hist[j] = sres;
+    if (halt) {
+      S.ctrl->halt = 1;
+      S.ctrl->halt_j = j;
+      S.ctrl->flags = flags;
+    }
+    StepRec* rc = S.rec + j;
+    rc->sres = sres;
+    rc->nu = nuj;
+    rc->j = j;
+    rc->flags = flags;
+    __threadfence_system();
+    __atomic_store_n(&rc->seq, j, __ATOMIC_RELEASE);
+    __threadfence_system();
+  }
+}
+
+template <class A>
+void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int t, int s,
+                     const A* red1, const A* red2, double brtol, double rank_rtol) {
+  const int lmax = khat + m + 1;
+  const size_t lds = (size_t)(s + 2 * lmax) * sizeof(A);
+  hipLaunchKernelGGL(k_lsq_step<A>, dim3(1), dim3(kLsqBlock), lds, st, S, j, khat, m, t, s, red1,
+                     red2, brtol, rank_rtol);
+}
+
+template <class A>
+__global__ __launch_bounds__(kLsqBlock) void k_lsq_init(LsqState<A> S, int khat, int s,
+                                                        const A* __restrict__ Sr, double rank_rtol) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  A* a = reinterpret_cast<A*>(smem_raw);
+  A* cbuf = a + s;
+  __shared__ A red[kLsqBlock / 64];
+  for (int r = threadIdx.x; r < s; r += blockDim.x) S.rho[r] = Sr[r];
+  __syncthreads();
+  double sres = 0.0;
+  for (int c = 0; c < khat; ++c) {
+    for (int r = threadIdx.x; r < s; r += blockDim.x) a[r] = S.SAW[(int64_t)c * S.ldsaw + r];
+    __syncthreads();
+    bool loss = false;
+    sres = qr_append(S, a, cbuf, red, c, s, rank_rtol, &loss);
+  }
+  if (threadIdx.x == 0) S.sres_hist[0] = sres;
+}
+
+template <class A>
+void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr, double rank_rtol) {
+  const size_t lds = (size_t)(s + 2 * (khat + 1)) * sizeof(A);
+  hipLaunchKernelGGL(k_lsq_init<A>, dim3(1), dim3(kLsqBlock), lds, st, S, khat, s, Sr, rank_rtol);
+}
+
+// R y = z by columns (back substitution), then the basis coefficients.
+template <class A>
+__global__ __launch_bounds__(kLsqBlock) void k_backsolve(LsqState<A> S, int n, int khat,
+                                                         A* __restrict__ ycoef) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  A* y = reinterpret_cast<A*>(smem_raw);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = S.z[i];
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) {
+      const A rii = S.R[(int64_t)i * S.ldr + i];
+      const double d = abs2(rii);
+      if (d > 0.0) {
+        // y_i / r_ii = y_i * conj(r_ii) / |r_ii|^2
+        y[i] = scale(y[i] * conj(rii), 1.0 / d);
+      } else {
+        y[i] = zero<A>();
+      }
+    }
+    __syncthreads();
+    const A yi = y[i];
+    for (int k = threadIdx.x; k < i; k += blockDim.x) y[k] -= S.R[(int64_t)i * S.ldr + k] * yi;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    ycoef[i] = i < khat ? y[i] : scale(y[i], 1.0 / S.nu[i - khat]);
+}
+
+template <class A>
+void launch_backsolve(hipStream_t st, LsqState<A> S, int n, int khat, A* ycoef) {
+  hipLaunchKernelGGL(k_backsolve<A>, dim3(1), dim3(kLsqBlock), (size_t)n * sizeof(A), st, S, n,
+                     khat, ycoef);
+}
+
+// -------------------------------------------------------- batched sketch ---
+template <class X>
+__global__ __launch_bounds__(kBlock) void k_sketch_cols(int n, const X* __restrict__ x, int64_t ld,
+                                                        int cc, SketchSpec sk,
+                                                        typename traits<X>::acc* __restrict__ part,
+                                                        int nb) {
+  using A = typename traits<X>::acc;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  A* acc = reinterpret_cast<A*>(smem_raw);  // [kWaves][cc * s]
+  __shared__ A red[kWaves];
+  const int s = sk.s;
+  const int w = cc * s;
+  for (int i = threadIdx.x; i < kWaves * w; i += kBlock) acc[i] = zero<A>();
+  __syncthreads();
+  A* mine = acc + (threadIdx.x >> 6) * w;
+  double nrm[8];
+  for (int c = 0; c < 8; ++c) nrm[c] = 0.0;
+  const int r0 = blockIdx.x * kRowsUpdate;
+  const int r1 = min(n, r0 + kRowsUpdate);
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+    const uint64_t base = sk.seed + kGamma * ((uint64_t)r * (uint64_t)sk.words + 1ull);
+    for (int g = 0; g < sk.words; ++g) {
+      const uint64_t h = mix64(base + (uint64_t)g * kGamma);
+      for (int q = 0; q < 4; ++q) {
+        const int b = 4 * g + q;
+        if (b < sk.zeta) {
+          const uint32_t u = (uint32_t)(h >> (16 * q)) & 0xFFFFu;
+          const int row = b * sk.bsz + (int)(((u >> 1) * (uint32_t)sk.bsz) >> 15);
+          const bool ng = (u & 1u) != 0u;
+          for (int c = 0; c < cc; ++c) lds_add(&mine[c * s + row], neg_if(widen(x[r + c * ld]), ng));
+        }
+      }
+    }
+    for (int c = 0; c < cc; ++c) nrm[c] += abs2(widen(x[r + c * ld]));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < w; i += kBlock) {
+    A sum = acc[i];
+    for (int q = 1; q < kWaves; ++q) sum += acc[q * w + i];
+    part[(int64_t)i * nb + blockIdx.x] = sum;
+  }
+  for (int c = 0; c < cc; ++c) {
+    const double ns = block_sum(nrm[c], (double*)red);
+    if (threadIdx.x == 0) {
+      A v = zero<A>();
+      *(double*)&v = ns;
+      part[(int64_t)(w + c) * nb + blockIdx.x] = v;
+    }
+  }
+}
+
+template <class X>
+void launch_sketch_cols(hipStream_t st, int n, const X* x, int64_t ld, int cc, SketchSpec sk,
+                        typename traits<X>::acc* part, int nb) {
+  using A = typename traits<X>::acc;
+  const size_t lds = (size_t)kWaves * cc * sk.s * sizeof(A);
+  hipLaunchKernelGGL(k_sketch_cols<X>, dim3(nb), dim3(kBlock), lds, st, n, x, ld, cc, sk, part, nb);
+}
+
+// ------------------------------------------------- tall-skinny products ---
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gemv_basis(int n, const T* __restrict__ U, int64_t ldu,
+                                                       int ku, const T* __restrict__ P, int64_t ldp,
+                                                       int jp, const typename traits<T>::acc* __restrict__ y,
+                                                       typename traits<T>::acc* __restrict__ out) {
+  using A = typename traits<T>::acc;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  A* ys = reinterpret_cast<A*>(smem_raw);
+  for (int i = threadIdx.x; i < ku + jp; i += blockDim.x) ys[i] = y[i];
+  __syncthreads();
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    A acc = zero<A>();
+    for (int i = 0; i < ku; ++i) acc += widen(U[r + i * ldu]) * ys[i];
+    for (int i = 0; i < jp; ++i) acc += widen(P[r + i * ldp]) * ys[ku + i];
+    out[r] = acc;
+  }
+}
+
+template <class T>
+void launch_gemv_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
+                       int64_t ldp, int jp, const typename traits<T>::acc* y,
+                       typename traits<T>::acc* out) {
+  using A = typename traits<T>::acc;
+  const int nb = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_gemv_basis<T>, dim3(nb), dim3(kBlock), (size_t)(ku + jp) * sizeof(A), st, n,
+                     U, ldu, ku, P, ldp, jp, y, out);
+}
+
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_spmv_residual(int n, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci,
+                                                          const A* __restrict__ val,
+                                                          const A* __restrict__ x,
+                                                          const A* __restrict__ r0,
+                                                          A* __restrict__ rnew, A* __restrict__ part) {
+  __shared__ A red[kWaves];
+  double nrm = 0.0;
+  const int b0 = blockIdx.x * kRowsUpdate;
+  const int b1 = min(n, b0 + kRowsUpdate);
+  for (int r = b0 + (int)threadIdx.x; r < b1; r += kBlock) {
+    A acc = zero<A>();
+    const int e1 = rp[r + 1];
+    for (int e = rp[r]; e < e1; ++e) acc += val[e] * x[ci[e]];
+    const A v = r0[r] - acc;
+    rnew[r] = v;
+    nrm += abs2(v);
+  }
+  const double s = block_sum(nrm, (double*)red);
+  if (threadIdx.x == 0) {
+    A v = zero<A>();
+    *(double*)&v = s;
+    part[blockIdx.x] = v;
+  }
+}
+
+template <class A>
+void launch_spmv_residual(hipStream_t st, int n, const int* rp, const int* ci, const A* val,
+                          const A* x, const A* r0, A* rnew, A* part, int nb) {
+  hipLaunchKernelGGL(k_spmv_residual<A>, dim3(nb), dim3(kBlock), 0, st, n, rp, ci, val, x, r0, rnew,
+                     part);
+}
+
+// C = [U P] G with G staged in LDS; one row per thread, kc <= KM accumulators.
+template <class T, int KM>
+__global__ __launch_bounds__(kBlock) void k_gemm_basis(int n, const T* __restrict__ U, int64_t ldu,
+                                                       int ku, const T* __restrict__ P, int64_t ldp,
+                                                       int jp, const typename traits<T>::acc* __restrict__ G,
+                                                       int kc, T* __restrict__ C, int64_t ldc) {
+  using A = typename traits<T>::acc;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  A* gs = reinterpret_cast<A*>(smem_raw);  // (ku + jp) x KM, row major
+  const int l0 = ku + jp;
+  for (int i = threadIdx.x; i < l0 * KM; i += blockDim.x) {
+    const int row = i / KM, c = i % KM;
+    gs[i] = c < kc ? G[row + (int64_t)c * l0] : zero<A>();
+  }
+  __syncthreads();
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    A acc[KM];
+#pragma unroll
+    for (int c = 0; c < KM; ++c) acc[c] = zero<A>();
+    for (int i = 0; i < l0; ++i) {
+      const A v = i < ku ? widen(U[r + i * ldu]) : widen(P[r + (i - ku) * ldp]);
+#pragma unroll
+      for (int c = 0; c < KM; ++c) acc[c] += v * gs[i * KM + c];
+    }
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+      if (c < kc) C[r + c * ldc] = narrow<T>(acc[c]);
+  }
+}
+
+template <class T>
+void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
+                       int64_t ldp, int jp, const typename traits<T>::acc* G, int kc, T* C,
+                       int64_t ldc) {
+  using A = typename traits<T>::acc;
+  const int nb = (n + kBlock - 1) / kBlock;
+  const int l0 = ku + jp;
+  if (kc <= 8) {
+    hipLaunchKernelGGL((k_gemm_basis<T, 8>), dim3(nb), dim3(kBlock), (size_t)l0 * 8 * sizeof(A), st,
+                       n, U, ldu, ku, P, ldp, jp, G, kc, C, ldc);
+  } else if (kc <= 16) {
+    hipLaunchKernelGGL((k_gemm_basis<T, 16>), dim3(nb), dim3(kBlock), (size_t)l0 * 16 * sizeof(A),
+                       st, n, U, ldu, ku, P, ldp, jp, G, kc, C, ldc);
+  } else if (kc <= 24) {
+    hipLaunchKernelGGL((k_gemm_basis<T, 24>), dim3(nb), dim3(kBlock), (size_t)l0 * 24 * sizeof(A),
+                       st, n, U, ldu, ku, P, ldp, jp, G, kc, C, ldc);
+  } else {
+    hipLaunchKernelGGL((k_gemm_basis<T, 32>), dim3(nb), dim3(kBlock), (size_t)l0 * 32 * sizeof(A),
+                       st, n, U, ldu, ku, P, ldp, jp, G, kc, C, ldc);
+  }
+}
+
+template <class A>
+__global__ void k_small_gemm(bool ct, int M, int N, int K, const A* __restrict__ a, int lda,
+                             const A* __restrict__ b, int ldb, A* __restrict__ c, int ldc) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int i = idx % M, jc = idx / M;
+  A sum = zero<A>();
+  if (ct) {
+    for (int k = 0; k < K; ++k) sum += conj(a[(int64_t)i * lda + k]) * b[(int64_t)jc * ldb + k];
+  } else {
+    for (int k = 0; k < K; ++k) sum += a[(int64_t)k * lda + i] * b[(int64_t)jc * ldb + k];
+  }
+  c[(int64_t)jc * ldc + i] = sum;
+}
+
+template <class A>
+void launch_small_gemm(hipStream_t st, bool ct, int M, int N, int K, const A* a, int lda,
+                       const A* b, int ldb, A* c, int ldc) {
+  if (M * N == 0) return;
+  const int nb = (M * N + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_small_gemm<A>, dim3(nb), dim3(kBlock), 0, st, ct, M, N, K, a, lda, b, ldb, c,
+                     ldc);
+}
+
+// ------------------------------------------------------------ elementwise --
+template <class A>
+__global__ void k_axpy(int n, A alpha, const A* __restrict__ x, A* __restrict__ y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    y[i] += alpha * x[i];
+}
+template <class A> void launch_axpy(hipStream_t st, int n, A alpha, const A* x, A* y) {
+  hipLaunchKernelGGL(k_axpy<A>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, alpha, x, y);
+}
+
+template <class T>
+__global__ void k_cast_scale(int n, const typename traits<T>::acc* __restrict__ src, double s,
+                             T* __restrict__ dst) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    dst[i] = narrow<T>(scale(src[i], s));
+}
+template <class T>
+void launch_cast_scale(hipStream_t st, int n, const typename traits<T>::acc* src, double s, T* dst) {
+  hipLaunchKernelGGL(k_cast_scale<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, src,
+                     s, dst);
+}
+
+template <class T>
+__global__ void k_widen_scale(int n, const T* __restrict__ src, double s,
+                              typename traits<T>::acc* __restrict__ dst) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    dst[i] = scale(widen(src[i]), s);
+}
+template <class T>
+void launch_widen_scale(hipStream_t st, int n, const T* src, double s, typename traits<T>::acc* dst) {
+  hipLaunchKernelGGL(k_widen_scale<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, src,
+                     s, dst);
+}
+
+template <class T>
+__global__ void k_narrow_values(int64_t n, const typename traits<T>::acc* __restrict__ src,
+                                T* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = narrow<T>(src[i]);
+}
+template <class T>
+void launch_narrow_values(hipStream_t st, int64_t n, const typename traits<T>::acc* src, T* dst) {
+  const int nb = (int)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_narrow_values<T>, dim3(nb), dim3(kBlock), 0, st, n, src, dst);
+}
+
+template <class A>
+__global__ void k_gather_conj(int64_t nnz, const A* __restrict__ src, const int* __restrict__ perm,
+                              A* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nnz;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = conj(src[perm[i]]);
+}
+template <class A>
+void launch_gather_conj(hipStream_t st, int64_t nnz, const A* src, const int* perm, A* dst) {
+  const int nb = (int)((nnz + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_gather_conj<A>, dim3(nb), dim3(kBlock), 0, st, nnz, src, perm, dst);
+}
+
+template <class A>
+__global__ void k_grad_values(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const A* __restrict__ lam, const A* __restrict__ x, A* __restrict__ g) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const A l = lam[r];
+    const int e1 = rp[r + 1];
+    for (int e = rp[r]; e < e1; ++e) g[e] = -(l * conj(x[ci[e]]));
+  }
+}
+template <class A>
+void launch_grad_values(hipStream_t st, int n, const int* rp, const int* ci, const A* lam,
+                        const A* x, A* g) {
+  hipLaunchKernelGGL(k_grad_values<A>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, rp,
+                     ci, lam, x, g);
+}
+
+__global__ void k_set_ctrl(Ctrl* c, int halt, double thresh) {
+  if (threadIdx.x == 0) {
+    c->halt = halt;
+    c->halt_j = 0;
+    c->flags = 0;
+    c->thresh = thresh;
+  }
+}
+void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
+  hipLaunchKernelGGL(k_set_ctrl, dim3(1), dim3(64), 0, st, c, halt, thresh);
+}
+
+// ---------------------------------------------------- instantiations ---
+#define SDR_INST_BASIS(T)                                                                        \
+  template void launch_spmv_dots<T>(hipStream_t, int, const int*, const int*, const T*, const T*, \
+                                    T*, Window<T>, int, traits<T>::acc*, int, const Ctrl*);        \
+  template void launch_update_sketch<T>(hipStream_t, int, T*, Window<T>, int,                     \
+                                        const traits<T>::acc*, const double*, int, SketchSpec,    \
+                                        traits<T>::acc*, int, const Ctrl*);                       \
+  template void launch_sketch_cols<T>(hipStream_t, int, const T*, int64_t, int, SketchSpec,       \
+                                      traits<T>::acc*, int);                                      \
+  template void launch_gemv_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
+                                     int, const traits<T>::acc*, traits<T>::acc*);                \
+  template void launch_gemm_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
+                                     int, const traits<T>::acc*, int, T*, int64_t);               \
+  template void launch_cast_scale<T>(hipStream_t, int, const traits<T>::acc*, double, T*);        \
+  template void launch_widen_scale<T>(hipStream_t, int, const T*, double, traits<T>::acc*);       \
+  template void launch_narrow_values<T>(hipStream_t, int64_t, const traits<T>::acc*, T*);
+
+SDR_INST_BASIS(double)
+SDR_INST_BASIS(float)
+SDR_INST_BASIS(cx<double>)
+SDR_INST_BASIS(cx<float>)
+
+#define SDR_INST_ACC(A)                                                                         \
+  template void launch_reduce_cols<A>(hipStream_t, const A*, int, int, int, double, A*,        \
+                                      const Ctrl*);                                             \
+  template void launch_lsq_step<A>(hipStream_t, LsqState<A>, int, int, int, int, int, const A*, \
+                                   const A*, double, double);                                   \
+  template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double);       \
+  template void launch_backsolve<A>(hipStream_t, LsqState<A>, int, int, A*);                    \
+  template void launch_spmv_residual<A>(hipStream_t, int, const int*, const int*, const A*,     \
+                                        const A*, const A*, A*, A*, int);                      \
+  template void launch_small_gemm<A>(hipStream_t, bool, int, int, int, const A*, int, const A*, \
+                                     int, A*, int);                                             \
+  template void launch_axpy<A>(hipStream_t, int, A, const A*, A*);                              \
+  template void launch_gather_conj<A>(hipStream_t, int64_t, const A*, const int*, A*);          \
+  template void launch_grad_values<A>(hipStream_t, int, const int*, const int*, const A*,       \
+                                      const A*, A*);
+
+SDR_INST_ACC(double)
+SDR_INST_ACC(cx<double>)
+
+}  // namespace sdr

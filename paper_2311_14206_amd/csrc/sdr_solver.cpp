@@ -1,0 +1,1025 @@
+// GMRES-SDR host driver and C interface.
+//
+// One restart cycle follows Algorithm 1 for A x = r0 with the readings listed
+// in the library documentation: m Arnoldi steps on top of the recycle block
+// U, truncated orthogonalisation against the last t vectors, one sketch per
+// step, the sketched least squares updated by one QR column per step, the
+// safety-factor residual control of Section 3.4, and the sketched
+// harmonic-Ritz update of U, SU, SAU after every cycle (Section 3.5).  The
+// restart loop applies x += xt, r = r0 - A xt (Section 3.6 for sequences).
+//
+// The Arnoldi steps are queued on the stream ahead of the host; each step's
+// least-squares kernel writes its sketched residual to host-mapped memory and
+// raises a device halt flag when a true-residual check is due, which turns the
+// queued steps behind it into no-ops.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sdr.h"
+#include "dense.h"
+#include "sdr_kernels.h"
+
+using namespace sdr;
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const std::string& s) { g_err = s; }
+
+struct HipError {
+  int code;
+};
+
+#define HIPCHK(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      set_err(std::string("HIP error ") + hipGetErrorString(e_) + " at " #call);          \
+      throw HipError{SDR_EDEVICE};                                                         \
+    }                                                                                      \
+  } while (0)
+
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class P>
+P* dalloc(size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, count * sizeof(P));
+  if (e != hipSuccess) {
+    set_err(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    throw HipError{SDR_ENOMEM};
+  }
+  return static_cast<P*>(p);
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+struct Options {
+  int zeta = 8;
+  int max_cycles = 10000;
+  double safety0 = 1.4;
+  bool persist_safety = false;
+  int precision = 0;
+  int variant = 0;
+  double brtol = -1.0;  // < 0: default for the basis precision
+  double rank_rtol = 1e-12;
+  int lookahead = 4;
+};
+
+// Matrix view (device, full precision values).
+template <class A>
+struct MatView {
+  int n = 0;
+  int64_t nnz = 0;
+  const int* rp = nullptr;
+  const int* ci = nullptr;
+  const A* val = nullptr;
+};
+
+inline double to_double_re(double v) { return v; }
+inline double to_double_re(cx<double> v) { return v.x; }
+
+template <class A> A from_cd(std::complex<double> z);
+template <> double from_cd<double>(std::complex<double> z) { return z.real(); }
+template <> cx<double> from_cd<cx<double>>(std::complex<double> z) { return {z.real(), z.imag()}; }
+inline std::complex<double> to_cd(double v) { return {v, 0.0}; }
+inline std::complex<double> to_cd(cx<double> v) { return {v.x, v.y}; }
+
+struct SolverBase {
+  virtual ~SolverBase() {}
+  virtual int solve(const void* b, void* x, double tol, sdr_stats* st,
+                    std::vector<sdr_cycle_record>* trace) = 0;
+  virtual void matrix_changed() = 0;
+  virtual int get_recycle(void* U, void* SU, void* SAU, int* k) = 0;
+  virtual int get_basis(int ncols, void* V, void* H, void* SV) = 0;
+  virtual int sketch(const void* X, int ncols, void* Y) = 0;
+  virtual void set_stream(hipStream_t s) = 0;
+};
+
+template <class T>
+class Solver final : public SolverBase {
+ public:
+  using A = typename traits<T>::acc;
+  static constexpr bool kSame = sizeof(T) == sizeof(A);
+
+  Solver(MatView<A> mat, int m, int k, int t, int s, uint64_t seed, const Options& opt,
+         hipStream_t st)
+      : M_(mat), m_(m), k_(k), t_(t), s_(s), opt_(opt), stream_(st) {
+    n_ = mat.n;
+    sk_.seed = seed;
+    sk_.s = s;
+    sk_.zeta = opt.zeta;
+    sk_.bsz = s / opt.zeta;
+    sk_.words = (opt.zeta + 3) / 4;
+    brtol_ = opt.brtol >= 0.0 ? opt.brtol : (kSame ? 1e-14 : 1e-6);
+    nb1_ = (n_ + kRowsSpmv - 1) / kRowsSpmv;
+    nb2_ = (n_ + kRowsUpdate - 1) / kRowsUpdate;
+    kmax_ = k + 1;
+    lmax_ = kmax_ + m + 1;
+    const size_t N = (size_t)n_;
+    try {
+      if (!kSame) valB_ = dalloc<T>((size_t)mat.nnz);
+      P_ = dalloc<T>(N * (m + 1));
+      U_ = dalloc<T>(N * kmax_);
+      Unew_ = dalloc<T>(N * kmax_);
+      SU_ = dalloc<A>((size_t)s * kmax_);
+      SAU_ = dalloc<A>((size_t)s * kmax_);
+      Q_ = dalloc<A>((size_t)s * lmax_);
+      R_ = dalloc<A>((size_t)lmax_ * lmax_);
+      z_ = dalloc<A>(lmax_);
+      rho_ = dalloc<A>(s);
+      SB_ = dalloc<A>((size_t)s * (lmax_ + 1));
+      SAW_ = dalloc<A>((size_t)s * lmax_);
+      H_ = dalloc<A>((size_t)(m + 1) * m);
+      nu_ = dalloc<double>(m + 2);
+      sres_hist_ = dalloc<double>(m + 2);
+      ctrl_ = dalloc<Ctrl>(1);
+      ctrl_free_ = dalloc<Ctrl>(1);
+      part1_ = dalloc<A>((size_t)(kMaxWindow + 1) * nb1_);
+      part2_ = dalloc<A>((size_t)(8 * s + 8 + 1) * nb2_);
+      red1_ = dalloc<A>(kMaxWindow + 1);
+      red2_ = dalloc<A>(8 * s + 8 + 1);
+      red3_ = dalloc<A>(4);
+      Sr_ = dalloc<A>(s);
+      ycoef_ = dalloc<A>(lmax_);
+      xt_ = dalloc<A>(N);
+      r_ = dalloc<A>(N);
+      rnew_ = dalloc<A>(N);
+      G_ = dalloc<A>((size_t)lmax_ * kmax_);
+      Gs_ = dalloc<A>((size_t)lmax_ * kmax_);
+      C_ = dalloc<A>((size_t)lmax_ * lmax_);
+      HIPCHK(hipHostMalloc((void**)&rec_host_, sizeof(StepRec) * (m + 2),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+      HIPCHK(hipHostGetDevicePointer((void**)&rec_dev_, rec_host_, 0));
+      HIPCHK(hipMemsetAsync(ctrl_free_, 0, sizeof(Ctrl), stream_));
+      HIPCHK(hipMemsetAsync(nu_, 0, sizeof(double) * (m + 2), stream_));
+      HIPCHK(hipMemsetAsync(H_, 0, sizeof(A) * (m + 1) * m, stream_));
+      HIPCHK(hipStreamSynchronize(stream_));
+    } catch (...) {
+      release();
+      throw;
+    }
+    low_dirty_ = true;
+  }
+
+  ~Solver() override { release(); }
+
+  void set_stream(hipStream_t s) override { stream_ = s; }
+
+  void set_matrix(MatView<A> mat) { M_ = mat; }
+
+  void matrix_changed() override {
+    low_dirty_ = true;
+    if (opt_.variant == 0) sau_stale_ = true;
+  }
+
+  const T* basis_values() {
+    if (kSame) return reinterpret_cast<const T*>(M_.val);
+    if (low_dirty_) {
+      launch_narrow_values<T>(stream_, M_.nnz, M_.val, valB_);
+      LAUNCHCHK();
+      low_dirty_ = false;
+    }
+    return valB_;
+  }
+
+  // out[c] = S X(:, c) for c < nc (X with leading dimension n), norms^2 in nrm2.
+  template <class X>
+  void sketch_cols(const X* x, int nc, A* out, int ldo, double* nrm2) {
+    const int maxcc = std::max(1, std::min(8, (int)(48 * 1024 / (kWaves * s_ * sizeof(A)))));
+    for (int c0 = 0; c0 < nc; c0 += maxcc) {
+      const int cc = std::min(maxcc, nc - c0);
+      launch_sketch_cols<X>(stream_, n_, x + (size_t)c0 * n_, (int64_t)n_, cc, sk_, part2_, nb2_);
+      LAUNCHCHK();
+      launch_reduce_cols<A>(stream_, part2_, nb2_, cc * s_ + cc, cc * s_,
+                            1.0 / std::sqrt((double)sk_.zeta), red2_, nullptr);
+      LAUNCHCHK();
+      for (int c = 0; c < cc; ++c)
+        HIPCHK(hipMemcpyAsync(out + (size_t)(c0 + c) * ldo, red2_ + (size_t)c * s_, sizeof(A) * s_,
+                              hipMemcpyDeviceToDevice, stream_));
+      if (nrm2) {
+        std::vector<A> h(cc);
+        HIPCHK(hipMemcpyAsync(h.data(), red2_ + (size_t)cc * s_, sizeof(A) * cc,
+                              hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        for (int c = 0; c < cc; ++c) nrm2[c0 + c] = to_double_re(h[c]);
+      }
+    }
+  }
+
+  int sketch(const void* X, int ncols, void* Y) override {
+    sketch_cols<A>(static_cast<const A*>(X), ncols, static_cast<A*>(Y), s_, nullptr);
+    HIPCHK(hipStreamSynchronize(stream_));
+    return SDR_OK;
+  }
+
+  double residual(const A* x, const A* b, A* r) {
+    launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, part2_, nb2_);
+    LAUNCHCHK();
+    launch_reduce_cols<A>(stream_, part2_, nb2_, 1, 0, 1.0, red3_, nullptr);
+    LAUNCHCHK();
+    A h;
+    HIPCHK(hipMemcpyAsync(&h, red3_, sizeof(A), hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+    return std::sqrt(to_double_re(h));
+  }
+
+  LsqState<A> lsq() {
+    LsqState<A> S;
+    S.Q = Q_;
+    S.ldq = s_;
+    S.R = R_;
+    S.ldr = lmax_;
+    S.z = z_;
+    S.rho = rho_;
+    S.SB = SB_;
+    S.ldsb = s_;
+    S.SAW = SAW_;
+    S.ldsaw = s_;
+    S.H = H_;
+    S.ldh = m_ + 1;
+    S.nu = nu_;
+    S.sres_hist = sres_hist_;
+    S.ctrl = ctrl_;
+    S.rec = rec_dev_;
+    return S;
+  }
+
+  void enqueue_step(int j, const T* vals) {
+    const int i0 = std::max(j - t_, 0);
+    const int tw = j - i0;
+    Window<T> win{};
+    for (int q = 0; q < tw; ++q) win.p[q] = P_ + (size_t)(i0 + q) * n_;
+    T* w = P_ + (size_t)j * n_;
+    const T* x = P_ + (size_t)(j - 1) * n_;
+    launch_spmv_dots<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, part1_, nb1_, ctrl_);
+    launch_reduce_cols<A>(stream_, part1_, nb1_, tw + 1, 0, 1.0, red1_, ctrl_);
+    launch_update_sketch<T>(stream_, n_, w, win, tw, red1_, nu_, i0, sk_, part2_, nb2_, ctrl_);
+    launch_reduce_cols<A>(stream_, part2_, nb2_, s_ + 1, s_, 1.0 / std::sqrt((double)sk_.zeta),
+                          red2_, ctrl_);
+    launch_lsq_step<A>(stream_, lsq(), j, khat_, m_, t_, s_, red1_, red2_, brtol_, opt_.rank_rtol);
+    LAUNCHCHK();
+  }
+
+  // Wait for the record of step j; returns false if it never arrives.
+  bool wait_record(int j, StepRec& out) {
+    volatile StepRec* rc = rec_host_ + j;
+    long spins = 0;
+    for (;;) {
+      if (__atomic_load_n(&rec_host_[j].seq, __ATOMIC_ACQUIRE) == j) {
+        out.sres = rc->sres;
+        out.nu = rc->nu;
+        out.j = rc->j;
+        out.flags = rc->flags;
+        return true;
+      }
+      if (++spins % 4096 == 0) {
+        hipError_t q = hipStreamQuery(stream_);
+        if (q == hipSuccess) {
+          if (__atomic_load_n(&rec_host_[j].seq, __ATOMIC_ACQUIRE) == j) continue;
+          return false;
+        }
+        if (q != hipErrorNotReady) {
+          set_err(std::string("stream error: ") + hipGetErrorString(q));
+          throw HipError{SDR_EDEVICE};
+        }
+      }
+    }
+  }
+
+  double check(int j) {
+    const int nls = khat_ + j;
+    launch_backsolve<A>(stream_, lsq(), nls, khat_, ycoef_);
+    launch_gemv_basis<T>(stream_, n_, U_, n_, khat_, P_, n_, j, ycoef_, xt_);
+    LAUNCHCHK();
+    return residual(xt_, r_, rnew_);
+  }
+
+  int solve(const void* bv, void* xv, double tol, sdr_stats* st,
+            std::vector<sdr_cycle_record>* trace) override {
+    const A* b = static_cast<const A*>(bv);
+    A* x = static_cast<A*>(xv);
+    const double t0 = now();
+    double eig_time = 0.0;
+    trace->clear();
+    int matvecs = 0, ips = 0, sketches = 0, checks = 0, iters = 0, cycles = 0;
+    const T* vals = basis_values();
+    double nb2v = 0.0;
+    sketch_cols<A>(b, 1, Sr_, s_, &nb2v);  // ||b|| (the sketch is discarded)
+    const double nb = std::sqrt(nb2v);
+    if (!std::isfinite(nb)) {
+      set_err("non-finite right-hand side");
+      return SDR_EINVAL;
+    }
+    double rn = residual(x, b, r_);
+    matvecs++;
+    ips++;
+    if (!std::isfinite(rn)) {
+      set_err("non-finite initial residual");
+      return SDR_EINVAL;
+    }
+    if (nb == 0.0) {
+      HIPCHK(hipMemsetAsync(x, 0, sizeof(A) * n_, stream_));
+      HIPCHK(hipStreamSynchronize(stream_));
+      fill_stats(st, 0, 0, matvecs, ips, sketches, checks, SDR_OK, 0.0, 0.0, 1.4, now() - t0, 0.0);
+      return SDR_OK;
+    }
+    const double tol_abs = tol * nb;
+    if (sau_stale_ && khat_ > 0) {
+      // exact variant: S A_i U with the new matrix (k products and sketches)
+      for (int c = 0; c < khat_; ++c) {
+        Window<T> win{};
+        launch_spmv_dots<T>(stream_, n_, M_.rp, M_.ci, vals, U_ + (size_t)c * n_,
+                            Unew_ + (size_t)c * n_, win, 0, part1_, nb1_, ctrl_free_);
+        LAUNCHCHK();
+      }
+      sketch_cols<T>(Unew_, khat_, SAU_, s_, nullptr);
+      matvecs += khat_;
+      sketches += khat_;
+    }
+    sau_stale_ = false;
+    double safety = opt_.safety0;
+    bool converged = rn <= tol_abs;
+    double last_sres = 0.0;
+    int status = SDR_NOT_CONVERGED;
+    while (!converged && cycles < opt_.max_cycles) {
+      if (!opt_.persist_safety) safety = opt_.safety0;
+      sdr_cycle_record rec{};
+      khat_prev_ = khat_;
+      // --- cycle start: S r0, p_0 = r0, nu_0, SV(:,0), recycled columns ---
+      sketch_cols<A>(r_, 1, Sr_, s_, nullptr);
+      sketches++;
+      ips++;
+      launch_cast_scale<T>(stream_, n_, r_, 1.0, P_);
+      LAUNCHCHK();
+      double nu0sq = 0.0;
+      sketch_cols<T>(P_, 1, SB_ + (size_t)khat_ * s_, s_, &nu0sq);
+      const double nu0 = std::sqrt(nu0sq);
+      {
+        std::vector<A> sv(s_);
+        HIPCHK(hipMemcpyAsync(sv.data(), SB_ + (size_t)khat_ * s_, sizeof(A) * s_,
+                              hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        for (auto& v : sv) v = scale(v, 1.0 / nu0);
+        HIPCHK(hipMemcpyAsync(SB_ + (size_t)khat_ * s_, sv.data(), sizeof(A) * s_,
+                              hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(nu_, &nu0, sizeof(double), hipMemcpyHostToDevice, stream_));
+      }
+      if (khat_ > 0) {
+        HIPCHK(hipMemcpyAsync(SB_, SU_, sizeof(A) * s_ * khat_, hipMemcpyDeviceToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(SAW_, SAU_, sizeof(A) * s_ * khat_, hipMemcpyDeviceToDevice, stream_));
+      }
+      for (int j = 0; j <= m_ + 1; ++j) __atomic_store_n(&rec_host_[j].seq, -1, __ATOMIC_RELEASE);
+      launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
+      launch_lsq_init<A>(stream_, lsq(), khat_, s_, Sr_, opt_.rank_rtol);
+      LAUNCHCHK();
+      // --- truncated Arnoldi with sketched least squares ---
+      int enq = 0, done = 0, jstop = 0, flags_stop = 0;
+      double res = 0.0, sres = 0.0;
+      bool cyc_conv = false;
+      for (;;) {
+        while (enq < m_ && enq - done < opt_.lookahead) enqueue_step(++enq, vals);
+        StepRec rc;
+        if (!wait_record(done + 1, rc)) {
+          set_err("step record missing");
+          throw HipError{SDR_EDEVICE};
+        }
+        ++done;
+        const int tw = done - std::max(done - t_, 0);
+        matvecs++;
+        ips += tw + 1;
+        iters++;
+        if (!(rc.flags & 2)) sketches++;
+        sres = rc.sres;
+        if (rc.flags & 1) {
+          HIPCHK(hipStreamSynchronize(stream_));
+          res = check(done);
+          matvecs++;
+          ips++;
+          checks++;
+          rec.n_checks++;
+          if (!std::isfinite(res)) {
+            set_err("non-finite residual");
+            throw HipError{SDR_EDEVICE};
+          }
+          if (res < tol_abs) {
+            cyc_conv = true;
+            jstop = done;
+            break;
+          }
+          if (rc.flags & 6) {
+            jstop = done;
+            flags_stop = rc.flags & 6;
+            break;
+          }
+          if (sres > 0.0) safety = res / sres;
+          if (done == m_) {
+            jstop = done;
+            break;
+          }
+          launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
+          LAUNCHCHK();
+          enq = done;
+        }
+      }
+      cycles++;
+      last_sres = sres;
+      // x += xt, r = r0 - A xt
+      A one = from_cd<A>({1.0, 0.0});
+      launch_axpy<A>(stream_, n_, one, xt_, x);
+      LAUNCHCHK();
+      std::swap(r_, rnew_);
+      rn = res;
+      // --- sketched harmonic-Ritz update of U, SU, SAU (always) ---
+      const double te = now();
+      int ell = 0;
+      const int keff = update_recycle(jstop, &ell);
+      eig_time += now() - te;
+      rec.j_stop = jstop;
+      rec.ell = ell;
+      rec.k_eff = keff;
+      rec.flags = (cyc_conv ? 1 : 0) | flags_stop;
+      rec.sres = sres;
+      rec.res = res;
+      trace->push_back(rec);
+      converged = cyc_conv;
+      if (flags_stop && !cyc_conv && jstop == 1) break;
+    }
+    HIPCHK(hipStreamSynchronize(stream_));
+    status = converged ? SDR_OK : SDR_NOT_CONVERGED;
+    fill_stats(st, cycles, iters, matvecs, ips, sketches, checks, status, rn / nb, last_sres,
+               safety, now() - t0, eig_time);
+    return status;
+  }
+
+  // Returns k_eff; R, C = Q^H SB to the host, G back, then the products.
+  int update_recycle(int j, int* ell) {
+    const int l0 = khat_ + j;
+    *ell = 0;
+    if (k_ == 0 || l0 == 0) {
+      khat_ = 0;
+      return 0;
+    }
+    launch_small_gemm<A>(stream_, true, l0, l0, s_, Q_, s_, SB_, s_, C_, l0);
+    LAUNCHCHK();
+    std::vector<A> Rh((size_t)l0 * l0), Ch((size_t)l0 * l0);
+    std::vector<double> nuh(j + 1);
+    HIPCHK(hipMemcpy2DAsync(Rh.data(), sizeof(A) * l0, R_, sizeof(A) * lmax_, sizeof(A) * l0, l0,
+                            hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(Ch.data(), C_, sizeof(A) * l0 * l0, hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(nuh.data(), nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+    std::vector<std::complex<double>> Rc((size_t)l0 * l0), Cc((size_t)l0 * l0), G;
+    for (size_t i = 0; i < Rc.size(); ++i) {
+      Rc[i] = to_cd(Rh[i]);
+      Cc[i] = to_cd(Ch[i]);
+    }
+    const int keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s_, k_, !traits<T>::cpx, G, ell);
+    if (keff < 0) {
+      set_err("Schur iteration did not converge");
+      throw HipError{SDR_EDEVICE};
+    }
+    if (keff == 0) {
+      khat_ = 0;
+      return 0;
+    }
+    std::vector<A> Gh((size_t)l0 * keff), Gp((size_t)l0 * keff);
+    for (int c = 0; c < keff; ++c)
+      for (int i = 0; i < l0; ++i) {
+        const A g = from_cd<A>(G[(size_t)c * l0 + i]);
+        Gh[(size_t)c * l0 + i] = g;
+        Gp[(size_t)c * l0 + i] = i < khat_ ? g : scale(g, 1.0 / nuh[i - khat_]);
+      }
+    HIPCHK(hipMemcpyAsync(Gs_, Gh.data(), sizeof(A) * Gh.size(), hipMemcpyHostToDevice, stream_));
+    HIPCHK(hipMemcpyAsync(G_, Gp.data(), sizeof(A) * Gp.size(), hipMemcpyHostToDevice, stream_));
+    launch_gemm_basis<T>(stream_, n_, U_, n_, khat_, P_, n_, j, G_, keff, Unew_, n_);
+    // SU <- [SU SV] G, SAU <- [SAU SAV] G (the old SU/SAU sit in SB/SAW)
+    launch_small_gemm<A>(stream_, false, s_, keff, l0, SB_, s_, Gs_, l0, SU_, s_);
+    launch_small_gemm<A>(stream_, false, s_, keff, l0, SAW_, s_, Gs_, l0, SAU_, s_);
+    LAUNCHCHK();
+    std::swap(U_, Unew_);
+    khat_ = keff;
+    HIPCHK(hipStreamSynchronize(stream_));
+    return keff;
+  }
+
+  void fill_stats(sdr_stats* st, int cycles, int iters, int mv, int ip, int sk, int ch, int status,
+                  double relres, double sres, double safety, double secs, double eig) {
+    if (!st) return;
+    std::memset(st, 0, sizeof(*st));
+    st->cycles = cycles;
+    st->iters = iters;
+    st->matvecs = mv;
+    st->inner_products = ip;
+    st->sketches = sk;
+    st->res_checks = ch;
+    st->status = status;
+    st->k_eff = khat_;
+    st->relres = relres;
+    st->sres = sres;
+    st->safety = safety;
+    st->seconds = secs;
+    st->host_eig_seconds = eig;
+  }
+
+  int get_recycle(void* U, void* SU, void* SAU, int* k) override {
+    if (k) *k = khat_;
+    if (khat_ > 0) {
+      if (U) {
+        launch_widen_scale<T>(stream_, n_ * khat_, U_, 1.0, static_cast<A*>(U));
+        LAUNCHCHK();
+      }
+      if (SU)
+        HIPCHK(hipMemcpyAsync(SU, SU_, sizeof(A) * s_ * khat_, hipMemcpyDeviceToDevice, stream_));
+      if (SAU)
+        HIPCHK(hipMemcpyAsync(SAU, SAU_, sizeof(A) * s_ * khat_, hipMemcpyDeviceToDevice, stream_));
+    }
+    HIPCHK(hipStreamSynchronize(stream_));
+    return SDR_OK;
+  }
+
+  int get_basis(int ncols, void* V, void* Hh, void* SVh) override {
+    if (ncols < 0 || ncols > m_ + 1) {
+      set_err("ncols out of range");
+      return SDR_EINVAL;
+    }
+    std::vector<double> nuh(m_ + 2);
+    HIPCHK(hipMemcpyAsync(nuh.data(), nu_, sizeof(double) * (m_ + 2), hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+    if (V)
+      for (int c = 0; c < ncols; ++c) {
+        const double sc = nuh[c] > 0.0 ? 1.0 / nuh[c] : 0.0;
+        launch_widen_scale<T>(stream_, n_, P_ + (size_t)c * n_, sc, static_cast<A*>(V) + (size_t)c * n_);
+        LAUNCHCHK();
+      }
+    if (Hh)
+      HIPCHK(hipMemcpyAsync(Hh, H_, sizeof(A) * (m_ + 1) * m_, hipMemcpyDeviceToHost, stream_));
+    if (SVh && ncols > 0)
+      HIPCHK(hipMemcpyAsync(SVh, SB_ + (size_t)khat_prev_ * s_, sizeof(A) * s_ * ncols,
+                            hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+    return SDR_OK;
+  }
+
+ private:
+  void release() {
+    for (void* p : {(void*)valB_, (void*)P_, (void*)U_, (void*)Unew_, (void*)SU_, (void*)SAU_,
+                    (void*)Q_, (void*)R_, (void*)z_, (void*)rho_, (void*)SB_, (void*)SAW_, (void*)H_,
+                    (void*)nu_, (void*)sres_hist_, (void*)ctrl_, (void*)ctrl_free_, (void*)part1_,
+                    (void*)part2_, (void*)red1_, (void*)red2_, (void*)red3_, (void*)Sr_,
+                    (void*)ycoef_, (void*)xt_, (void*)r_, (void*)rnew_, (void*)G_, (void*)Gs_,
+                    (void*)C_})
+      dfree(p);
+    if (rec_host_) (void)hipHostFree(rec_host_);
+    rec_host_ = nullptr;
+  }
+
+  MatView<A> M_;
+  int n_ = 0, m_, k_, t_, s_;
+  Options opt_;
+  hipStream_t stream_;
+  SketchSpec sk_{};
+  double brtol_ = 1e-14;
+  int nb1_ = 0, nb2_ = 0, kmax_ = 0, lmax_ = 0;
+  int khat_ = 0, khat_prev_ = 0;
+  bool sau_stale_ = false, low_dirty_ = true;
+  T* valB_ = nullptr;
+  T *P_ = nullptr, *U_ = nullptr, *Unew_ = nullptr;
+  A *SU_ = nullptr, *SAU_ = nullptr, *Q_ = nullptr, *R_ = nullptr, *z_ = nullptr, *rho_ = nullptr;
+  A *SB_ = nullptr, *SAW_ = nullptr, *H_ = nullptr;
+  double *nu_ = nullptr, *sres_hist_ = nullptr;
+  Ctrl *ctrl_ = nullptr, *ctrl_free_ = nullptr;
+  A *part1_ = nullptr, *part2_ = nullptr, *red1_ = nullptr, *red2_ = nullptr, *red3_ = nullptr;
+  A *Sr_ = nullptr, *ycoef_ = nullptr, *xt_ = nullptr, *r_ = nullptr, *rnew_ = nullptr;
+  A *G_ = nullptr, *Gs_ = nullptr, *C_ = nullptr;
+  StepRec *rec_host_ = nullptr, *rec_dev_ = nullptr;
+};
+
+}  // namespace
+
+// ============================================================== C handle ===
+struct sdr_handle {
+  int n = 0;
+  int64_t nnz = 0;
+  int m = 0, k = 0, t = 0, s = 0;
+  uint64_t seed = 0;
+  bool cpx = false;
+  Options opt;
+  int* rp = nullptr;
+  int* ci = nullptr;
+  void* vals = nullptr;
+  // transpose (adjoint) pattern
+  int* rpT = nullptr;
+  int* ciT = nullptr;
+  int* perm = nullptr;
+  void* valsT = nullptr;
+  bool adj_ready = false;
+  uint64_t pattern_hash = 0;
+  hipStream_t own = nullptr;
+  hipStream_t stream = nullptr;
+  std::unique_ptr<SolverBase> fwd, adj;
+  std::vector<sdr_cycle_record> trace;
+  size_t elem() const { return cpx ? 16 : 8; }
+};
+
+namespace {
+
+uint64_t hash_pattern(const std::vector<int>& rp, const std::vector<int>& ci) {
+  uint64_t h = 1469598103934665603ull;
+  auto mixin = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  for (int v : rp) mixin((uint32_t)v);
+  for (int v : ci) mixin((uint32_t)v);
+  return h;
+}
+
+std::unique_ptr<SolverBase> make_solver(sdr_handle* h, bool adjoint) {
+  const int* rp = adjoint ? h->rpT : h->rp;
+  const int* ci = adjoint ? h->ciT : h->ci;
+  const void* v = adjoint ? h->valsT : h->vals;
+  if (!h->cpx) {
+    MatView<double> mv{h->n, h->nnz, rp, ci, static_cast<const double*>(v)};
+    if (h->opt.precision == 1)
+      return std::unique_ptr<SolverBase>(new Solver<float>(mv, h->m, h->k, h->t, h->s, h->seed, h->opt, h->stream));
+    return std::unique_ptr<SolverBase>(new Solver<double>(mv, h->m, h->k, h->t, h->s, h->seed, h->opt, h->stream));
+  }
+  MatView<cx<double>> mv{h->n, h->nnz, rp, ci, static_cast<const cx<double>*>(v)};
+  if (h->opt.precision == 1)
+    return std::unique_ptr<SolverBase>(new Solver<cx<float>>(mv, h->m, h->k, h->t, h->s, h->seed, h->opt, h->stream));
+  return std::unique_ptr<SolverBase>(new Solver<cx<double>>(mv, h->m, h->k, h->t, h->s, h->seed, h->opt, h->stream));
+}
+
+SolverBase* fwd(sdr_handle* h) {
+  if (h->s % h->opt.zeta != 0) {
+    set_err("s_dim must be a multiple of zeta");
+    throw HipError{SDR_EINVAL};
+  }
+  if (!h->fwd) h->fwd = make_solver(h, false);
+  return h->fwd.get();
+}
+
+int validate_csr(const sdr_csr* A, std::vector<int>* rp_out, std::vector<int>* ci_out) {
+  if (!A || A->n <= 0 || A->nnz < 0 || !A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values))) {
+    set_err("invalid CSR descriptor");
+    return SDR_EINVAL;
+  }
+  if (A->dtype != SDR_F64 && A->dtype != SDR_C128) {
+    set_err("matrix dtype must be SDR_F64 or SDR_C128");
+    return SDR_EINVAL;
+  }
+  if (A->n > (int64_t)0x7fffffff || A->nnz > (int64_t)0x7fffffff) {
+    set_err("n and nnz must fit in int32");
+    return SDR_EINVAL;
+  }
+  std::vector<int> rp(A->n + 1), ci(A->nnz);
+  HIPCHK(hipMemcpy(rp.data(), A->row_ptr, sizeof(int) * (A->n + 1), hipMemcpyDeviceToHost));
+  if (A->nnz) HIPCHK(hipMemcpy(ci.data(), A->col_idx, sizeof(int) * A->nnz, hipMemcpyDeviceToHost));
+  if (rp[0] != 0 || rp[A->n] != A->nnz) {
+    set_err("row_ptr must start at 0 and end at nnz");
+    return SDR_EINVAL;
+  }
+  for (int64_t i = 0; i < A->n; ++i)
+    if (rp[i + 1] < rp[i]) {
+      set_err("row_ptr must be non-decreasing");
+      return SDR_EINVAL;
+    }
+  for (int64_t e = 0; e < A->nnz; ++e)
+    if (ci[e] < 0 || ci[e] >= A->n) {
+      set_err("column index out of range");
+      return SDR_EINVAL;
+    }
+  if (rp_out) *rp_out = std::move(rp);
+  if (ci_out) *ci_out = std::move(ci);
+  return SDR_OK;
+}
+
+void build_adjoint(sdr_handle* h) {
+  if (h->adj_ready) return;
+  std::vector<int> rp(h->n + 1), ci(h->nnz);
+  HIPCHK(hipMemcpy(rp.data(), h->rp, sizeof(int) * (h->n + 1), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ci.data(), h->ci, sizeof(int) * h->nnz, hipMemcpyDeviceToHost));
+  std::vector<int> rpT(h->n + 1, 0), ciT(h->nnz), perm(h->nnz);
+  for (int64_t e = 0; e < h->nnz; ++e) rpT[ci[e] + 1]++;
+  for (int i = 0; i < h->n; ++i) rpT[i + 1] += rpT[i];
+  std::vector<int> fill(rpT.begin(), rpT.end() - 1);
+  for (int i = 0; i < h->n; ++i)
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      const int d = fill[ci[e]]++;
+      ciT[d] = i;
+      perm[d] = e;
+    }
+  h->rpT = dalloc<int>(h->n + 1);
+  h->ciT = dalloc<int>(h->nnz);
+  h->perm = dalloc<int>(h->nnz);
+  h->valsT = dalloc<unsigned char>(h->elem() * h->nnz);
+  HIPCHK(hipMemcpy(h->rpT, rpT.data(), sizeof(int) * (h->n + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->ciT, ciT.data(), sizeof(int) * h->nnz, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->perm, perm.data(), sizeof(int) * h->nnz, hipMemcpyHostToDevice));
+  h->adj_ready = true;
+}
+
+void refresh_adjoint_values(sdr_handle* h) {
+  if (!h->adj_ready) return;
+  if (h->cpx)
+    launch_gather_conj<cx<double>>(h->stream, h->nnz, static_cast<const cx<double>*>(h->vals), h->perm,
+                                   static_cast<cx<double>*>(h->valsT));
+  else
+    launch_gather_conj<double>(h->stream, h->nnz, static_cast<const double*>(h->vals), h->perm,
+                               static_cast<double*>(h->valsT));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sdr_last_error(void) { return g_err.c_str(); }
+
+sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_t seed) {
+  g_err.clear();
+  sdr_handle* h = nullptr;
+  try {
+    std::vector<int> rp, ci;
+    if (validate_csr(A, &rp, &ci) != SDR_OK) return nullptr;
+    if (m < 1 || k < 0 || t < 1 || t > m || t > kMaxWindow || s_dim <= m + k) {
+      set_err("invalid parameters: need m>=1, k>=0, 1<=t<=min(m,4), s_dim>m+k");
+      return nullptr;
+    }
+    h = new sdr_handle();
+    h->n = (int)A->n;
+    h->nnz = A->nnz;
+    h->m = m;
+    h->k = k;
+    h->t = t;
+    h->s = s_dim;
+    h->seed = seed;
+    h->cpx = A->dtype == SDR_C128;
+    h->pattern_hash = hash_pattern(rp, ci);
+    HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+    h->stream = h->own;
+    h->rp = dalloc<int>(h->n + 1);
+    h->ci = dalloc<int>(h->nnz);
+    h->vals = dalloc<unsigned char>(h->elem() * h->nnz);
+    HIPCHK(hipMemcpy(h->rp, A->row_ptr, sizeof(int) * (h->n + 1), hipMemcpyDeviceToDevice));
+    if (h->nnz) {
+      HIPCHK(hipMemcpy(h->ci, A->col_idx, sizeof(int) * h->nnz, hipMemcpyDeviceToDevice));
+      HIPCHK(hipMemcpy(h->vals, A->values, h->elem() * h->nnz, hipMemcpyDeviceToDevice));
+    }
+    return h;
+  } catch (HipError&) {
+    if (h) sdr_destroy(h);
+    return nullptr;
+  }
+}
+
+int sdr_set_option(sdr_handle* h, const char* key, double v) {
+  if (!h || !key) {
+    set_err("null handle or key");
+    return SDR_EINVAL;
+  }
+  const std::string k(key);
+  const bool built = (bool)h->fwd;
+  if (k == "zeta") {
+    const int z = (int)v;
+    if (built || z < 1 || z > 32) {
+      set_err("zeta must divide s_dim, be in [1,32] and be set before the first solve");
+      return SDR_EINVAL;
+    }
+    h->opt.zeta = z;
+  } else if (k == "max_cycles") {
+    if (v < 1) return set_err("max_cycles >= 1"), SDR_EINVAL;
+    h->opt.max_cycles = (int)v;
+  } else if (k == "safety0") {
+    if (!(v >= 1.0)) return set_err("safety0 >= 1"), SDR_EINVAL;
+    h->opt.safety0 = v;
+  } else if (k == "persist_safety") {
+    h->opt.persist_safety = v != 0.0;
+  } else if (k == "precision") {
+    if (built || (v != 0.0 && v != 1.0)) {
+      set_err("precision is 0 or 1 and must be set before the first solve");
+      return SDR_EINVAL;
+    }
+    h->opt.precision = (int)v;
+  } else if (k == "variant") {
+    if (built || (v != 0.0 && v != 1.0)) {
+      set_err("variant is 0 or 1 and must be set before the first solve");
+      return SDR_EINVAL;
+    }
+    h->opt.variant = (int)v;
+  } else if (k == "breakdown_rtol") {
+    if (built || !(v >= 0.0)) return set_err("breakdown_rtol >= 0, before the first solve"), SDR_EINVAL;
+    h->opt.brtol = v;
+  } else if (k == "rank_rtol") {
+    if (built || !(v >= 0.0)) return set_err("rank_rtol >= 0, before the first solve"), SDR_EINVAL;
+    h->opt.rank_rtol = v;
+  } else if (k == "lookahead") {
+    if (built || v < 1 || v > 64) return set_err("lookahead in [1,64], before the first solve"), SDR_EINVAL;
+    h->opt.lookahead = (int)v;
+  } else {
+    set_err("unknown option " + k);
+    return SDR_EINVAL;
+  }
+  return SDR_OK;
+}
+
+int sdr_set_stream(sdr_handle* h, void* s) {
+  if (!h) return set_err("null handle"), SDR_EINVAL;
+  h->stream = s ? static_cast<hipStream_t>(s) : h->own;
+  if (h->fwd) h->fwd->set_stream(h->stream);
+  if (h->adj) h->adj->set_stream(h->stream);
+  return SDR_OK;
+}
+
+int sdr_update_matrix(sdr_handle* h, const sdr_csr* A) {
+  if (!h) return set_err("null handle"), SDR_EINVAL;
+  try {
+    std::vector<int> rp, ci;
+    int rc = validate_csr(A, &rp, &ci);
+    if (rc != SDR_OK) return rc;
+    if (A->n != h->n || A->nnz != h->nnz || (A->dtype == SDR_C128) != h->cpx ||
+        hash_pattern(rp, ci) != h->pattern_hash) {
+      set_err("matrix pattern differs from the handle's");
+      return SDR_EPATTERN;
+    }
+    HIPCHK(hipMemcpyAsync(h->vals, A->values, h->elem() * h->nnz, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    refresh_adjoint_values(h);
+    if (h->fwd) h->fwd->matrix_changed();
+    if (h->adj) h->adj->matrix_changed();
+    return SDR_OK;
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_solve(sdr_handle* h, const sdr_csr* A, const void* b, void* x, double tol, sdr_stats* st) {
+  if (!h || !b || !x || !(tol > 0.0)) return set_err("null argument or tol <= 0"), SDR_EINVAL;
+  g_err.clear();
+  try {
+    if (A) {
+      int rc = sdr_update_matrix(h, A);
+      if (rc != SDR_OK) return rc;
+    }
+    return fwd(h)->solve(b, x, tol, st, &h->trace);
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_solve_adjoint(sdr_handle* h, const void* g, void* lam, double tol, sdr_stats* st) {
+  if (!h || !g || !lam || !(tol > 0.0)) return set_err("null argument or tol <= 0"), SDR_EINVAL;
+  g_err.clear();
+  try {
+    if (!h->adj_ready) {
+      build_adjoint(h);
+      refresh_adjoint_values(h);
+    }
+    if (h->s % h->opt.zeta != 0) return set_err("s_dim must be a multiple of zeta"), SDR_EINVAL;
+    if (!h->adj) h->adj = make_solver(h, true);
+    std::vector<sdr_cycle_record> tr;
+    return h->adj->solve(g, lam, tol, st, &tr);
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_grad_values(sdr_handle* h, const void* lam, const void* x, void* g) {
+  if (!h || !lam || !x || !g) return set_err("null argument"), SDR_EINVAL;
+  try {
+    if (h->cpx)
+      launch_grad_values<cx<double>>(h->stream, h->n, h->rp, h->ci, static_cast<const cx<double>*>(lam),
+                                     static_cast<const cx<double>*>(x), static_cast<cx<double>*>(g));
+    else
+      launch_grad_values<double>(h->stream, h->n, h->rp, h->ci, static_cast<const double*>(lam),
+                                 static_cast<const double*>(x), static_cast<double*>(g));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SDR_OK;
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_get_trace(sdr_handle* h, sdr_cycle_record* out, int cap) {
+  if (!h) return set_err("null handle"), SDR_EINVAL;
+  const int n = std::min<int>(cap, (int)h->trace.size());
+  if (out && n > 0) std::memcpy(out, h->trace.data(), sizeof(sdr_cycle_record) * n);
+  return (int)h->trace.size();
+}
+
+int sdr_get_recycle(sdr_handle* h, void* U, void* SU, void* SAU, int* k) {
+  if (!h) return set_err("null handle"), SDR_EINVAL;
+  try {
+    return fwd(h)->get_recycle(U, SU, SAU, k);
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_sketch(sdr_handle* h, const void* X, int ncols, void* Y) {
+  if (!h || !X || !Y || ncols < 0) return set_err("bad argument"), SDR_EINVAL;
+  try {
+    return fwd(h)->sketch(X, ncols, Y);
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_spmv(sdr_handle* h, const void* x, void* y) {
+  if (!h || !x || !y) return set_err("bad argument"), SDR_EINVAL;
+  try {
+    Ctrl* c = dalloc<Ctrl>(1);
+    HIPCHK(hipMemsetAsync(c, 0, sizeof(Ctrl), h->stream));
+    const int nb = (h->n + kRowsSpmv - 1) / kRowsSpmv;
+    if (h->cpx) {
+      auto* part = dalloc<cx<double>>((size_t)nb * (kMaxWindow + 1));
+      Window<cx<double>> win{};
+      launch_spmv_dots<cx<double>>(h->stream, h->n, h->rp, h->ci, static_cast<const cx<double>*>(h->vals),
+                                   static_cast<const cx<double>*>(x), static_cast<cx<double>*>(y), win, 0,
+                                   part, nb, c);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(h->stream));
+      dfree(part);
+    } else {
+      auto* part = dalloc<double>((size_t)nb * (kMaxWindow + 1));
+      Window<double> win{};
+      launch_spmv_dots<double>(h->stream, h->n, h->rp, h->ci, static_cast<const double*>(h->vals),
+                               static_cast<const double*>(x), static_cast<double*>(y), win, 0, part, nb, c);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(h->stream));
+      dfree(part);
+    }
+    dfree(c);
+    return SDR_OK;
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_get_basis(sdr_handle* h, int ncols, void* V, void* H, void* SV) {
+  if (!h) return set_err("null handle"), SDR_EINVAL;
+  try {
+    return fwd(h)->get_basis(ncols, V, H, SV);
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+void sdr_destroy(sdr_handle* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  h->fwd.reset();
+  h->adj.reset();
+  for (void* p : {(void*)h->rp, (void*)h->ci, h->vals, (void*)h->rpT, (void*)h->ciT, (void*)h->perm,
+                  h->valsT})
+    dfree(p);
+  if (h->own) (void)hipStreamDestroy(h->own);
+  delete h;
+}
+
+int sdr_host_harmonic_ritz(int l0, const void* R, const void* C, int s, int k, int is_complex,
+                           void* G, int* ell) {
+  if (l0 < 0 || k < 0 || (l0 > 0 && (!R || !C || !G)) || !ell) return set_err("bad argument"), SDR_EINVAL;
+  std::vector<std::complex<double>> Rc((size_t)l0 * l0), Cc((size_t)l0 * l0), Gv;
+  for (size_t i = 0; i < Rc.size(); ++i) {
+    if (is_complex) {
+      Rc[i] = static_cast<const std::complex<double>*>(R)[i];
+      Cc[i] = static_cast<const std::complex<double>*>(C)[i];
+    } else {
+      Rc[i] = static_cast<const double*>(R)[i];
+      Cc[i] = static_cast<const double*>(C)[i];
+    }
+  }
+  const int keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s, k, !is_complex, Gv, ell);
+  if (keff < 0) return set_err("Schur iteration did not converge"), SDR_EDEVICE;
+  for (size_t i = 0; i < Gv.size(); ++i) {
+    if (is_complex)
+      static_cast<std::complex<double>*>(G)[i] = Gv[i];
+    else
+      static_cast<double*>(G)[i] = Gv[i].real();
+  }
+  return keff;
+}
+
+}  // extern "C"
