@@ -1,0 +1,199 @@
+"""GMRES-SDR benchmark on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cd2d_1024]
+
+A step is one complete solve to a 1e-8 relative residual, from x0 = 0 and an
+empty recycle space, of the 2D upwind convection-diffusion operator on a
+1024 x 1024 grid (N = 1,048,576, nnz = 5,238,784, Peclet 50, b ~ N(0,1) seed 1)
+with m = 100, k = 20, t = 2, s = 240 (zeta = 8) in FP64.  Inputs are resident
+in HBM before the timed region.  Prints one JSON line:
+
+* value: median time to 1e-8 (s) over the K timed solves;
+* roofline: the SpMV + window-product kernel (the largest per-step kernel),
+  algorithmic bytes per launch / its mean duration from HIP events recorded
+  on the library's stream inside the timed region;
+* cpu_baseline: the FP64 oracle on the host cores, timed on one 100-step
+  cycle of the same solve and scaled to the solve's Arnoldi steps.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 rel. residual (s), solves/s on sequences; HBM GB/s of SpMV+sketch"
+HBM_PEAK_GBS = 8000.0
+
+
+def spmv_dots_bytes(N, nnz, tw, p=8, pv=8):
+    """Algorithmic HBM bytes of one SpMV + window-product launch (32-bit indices):
+    values and column indices, row pointers, the input vector once, the other
+    tw - 1 window vectors, and the output vector."""
+    return nnz * (pv + 4) + 4 * (N + 1) + p * N * (1 + (tw - 1) + 1)
+
+
+def update_sketch_bytes(N, tw, p=8):
+    """One update + norm + sketch launch: read w, read tw window vectors, write w."""
+    return p * N * (tw + 2)
+
+
+def cpu_baseline(A, b, p, gpu_iters):
+    import numpy as np
+    from oracle import sdr_solve
+    from oracle.sketch import sketch_operator
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        blas_threads = max([i.get("num_threads", 1) for i in info] or [1])
+    except Exception:  # pragma: no cover
+        blas_threads = 1
+    As = A.to_scipy()
+    S = sketch_operator(A.n, p["s"], p["zeta"], p["s_seed"])
+    t0 = time.perf_counter()
+    ro = sdr_solve(As, b, m=p["m"], k=p["k"], t=p["t"], s=p["s"], zeta=p["zeta"],
+                   seed=p["s_seed"], tol=p["tol"], max_cycles=1, S=S)
+    dt = time.perf_counter() - t0
+    per_step = dt / max(ro.iters, 1)
+    return {"value": per_step * gpu_iters, "unit": "s", "cores": int(blas_threads),
+            "kind": "oracle",
+            "sample": (f"one {ro.iters}-step cycle of the same solve on the host "
+                       f"({dt:.1f} s, {per_step * 1e3:.1f} ms per Arnoldi step incl. its "
+                       f"least squares and the cycle's checks/eigen-step), scaled to the "
+                       f"GPU solve's {gpu_iters} steps; SciPy sparse products single-threaded, "
+                       f"BLAS threads {blas_threads}, nproc {os.cpu_count()}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cd2d_1024")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="run one device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2311_14206_amd.sdr import SDRSolver
+    from workloads import workload
+
+    dev = "cuda:0"
+    A, b, p = workload(args.workload)
+    N, nnz = A.n, A.nnz
+    print(f"[bench] workload {args.workload}: N={N} nnz={nnz} m={p['m']} k={p['k']} "
+          f"t={p['t']} s={p['s']}", file=sys.stderr, flush=True)
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_idx).to(dev)
+    vals = torch.from_numpy(A.values).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    h = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
+                  zeta=p["zeta"], kernel_timing=1, precision=args.precision)
+    if args.copy_calib_mb:
+        src = torch.ones(args.copy_calib_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for w in range(args.warmup):
+        h.reset()
+        x, st = h.solve(bd, tol=p["tol"])
+        print(f"[bench] warmup {w}: {st['seconds']:.3f} s, iters {st['iters']}, "
+              f"cycles {st['cycles']}", file=sys.stderr, flush=True)
+    h.kernel_times()  # clear
+    torch.cuda.synchronize()
+    times, stats = [], []
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        h.reset()
+        t0 = time.perf_counter()
+        x, st = h.solve(bd, tol=p["tol"])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        stats.append(st)
+        print(f"[bench] step {i}: {times[-1]:.3f} s, iters {st['iters']}, cycles {st['cycles']}, "
+              f"relres {st['relres']:.2e}, host eig {st['host_eig_seconds']:.3f} s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all
+    kt = h.kernel_times()
+    st = stats[-1]
+    if not st["converged"]:
+        print("[bench] solve did not converge", file=sys.stderr)
+        sys.exit(1)
+    # true residual on the host, outside the timed region
+    xh = x.cpu().numpy()
+    relres_host = float(np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b))
+
+    hist = kt["window_hist"]
+    launches = kt["launches"]
+    pb = 8 if args.precision == 0 else 4
+    k1_bytes = sum(hist[tw] * spmv_dots_bytes(N, nnz, tw, p=pb, pv=pb) for tw in range(len(hist)))
+    k2_bytes = sum(hist[tw] * update_sketch_bytes(N, tw, p=pb) for tw in range(len(hist)))
+    k1_s = kt["spmv_dots_ms"] * 1e-3
+    k2_s = kt["update_sketch_ms"] * 1e-3
+    step_s = kt["step_ms"] * 1e-3
+    k1_gbs = k1_bytes / k1_s / 1e9 if k1_s > 0 else None
+    step_gbs = (k1_bytes + k2_bytes) / step_s / 1e9 if step_s > 0 else None
+    kernels_gbs = (k1_bytes + k2_bytes) / (k1_s + k2_s) / 1e9 if k1_s + k2_s > 0 else None
+    med = statistics.median(times)
+    line = {
+        "metric": METRIC,
+        "value": med,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_all / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f32-basis/f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{args.workload}: 2D upwind convection-diffusion "
+                                f"{p['n']}x{p['n']} (N={N}, nnz={nnz}), Peclet 50, "
+                                f"b~N(0,1) seed {p['b_seed']}"),
+                   "m": p["m"], "k": p["k"], "t": p["t"], "s": p["s"], "zeta": p["zeta"],
+                   "tol": p["tol"], "precision": "fp64" if args.precision == 0 else "mixed"},
+        "solves_per_s": 1.0 / med,
+        "solve": {"cycles": st["cycles"], "iters": st["iters"], "matvecs": st["matvecs"],
+                  "inner_products": st["inner_products"], "res_checks": st["res_checks"],
+                  "relres": st["relres"], "relres_host_check": relres_host,
+                  "host_eig_seconds": st["host_eig_seconds"]},
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_spmv_dots (CSR SpMV + truncation-window products)",
+                     "achieved": k1_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (k1_gbs / HBM_PEAK_GBS) if k1_gbs else None,
+                     "traffic": None,
+                     "avg_us": 1e6 * k1_s / max(launches, 1),
+                     "bytes_per_launch": k1_bytes / max(launches, 1)},
+        "arnoldi_step": {"spmv_orth_sketch_gbs_kernels": kernels_gbs,
+                         "spmv_orth_sketch_gbs_step": step_gbs,
+                         "update_sketch_avg_us": 1e6 * k2_s / max(launches, 1),
+                         "step_avg_us": 1e6 * step_s / max(launches, 1),
+                         "bytes_per_step": (k1_bytes + k2_bytes) / max(launches, 1),
+                         "launches": launches},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(A, b, p, st["iters"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

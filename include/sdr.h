@@ -181,6 +181,20 @@ int sdr_spmv(sdr_handle* h, const void* x, void* y);
  * major), SV (s x ncols host).  Any pointer may be NULL. */
 int sdr_get_basis(sdr_handle* h, int ncols, void* V, void* H_host, void* SV_host);
 
+/* Drop the recycle space (the next solve starts without U).  Returns 0. */
+int sdr_reset(sdr_handle* h);
+
+/*
+ * Per-step kernel timings gathered with HIP events on the handle's stream
+ * when the option "kernel_timing" is 1, accumulated since the last call and
+ * then cleared.  ms[0]: SpMV + window products kernel, ms[1]: update + norm +
+ * sketch kernel, ms[2]: whole Arnoldi step (both kernels, both reductions and
+ * the least-squares kernel).  counts[0..2]: launches timed; counts[3 + tw]:
+ * steps whose truncation window held tw vectors (tw <= 4).  cap is the
+ * length of both arrays (8 covers everything).
+ */
+int sdr_kernel_times(sdr_handle* h, double* ms, int64_t* counts, int cap);
+
 void sdr_destroy(sdr_handle* h);
 
 /* Message of the last error on this thread ("" if none). */

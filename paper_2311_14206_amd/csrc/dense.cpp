@@ -186,38 +186,52 @@ int reorder(Mat& T, Mat& Z, std::vector<char> sel) {
   return ks;
 }
 
-void svd_jacobi(const Mat& A0, Mat& P, std::vector<double>& sig, Mat& W) {
-  const int n = A0.n;
-  Mat A = A0;
-  W = Mat(n, n);
-  for (int i = 0; i < n; ++i) W(i, i) = 1.0;
+static inline double conj_(double v) { return v; }
+static inline cd conj_(cd v) { return std::conj(v); }
+static inline double norm_(double v) { return v * v; }
+static inline double norm_(cd v) { return std::norm(v); }
+static inline double phase_re(double g, double ag) { return g / ag; }
+static inline cd phase_re(cd g, double ag) { return g / ag; }
+
+// One-sided Jacobi (Hestenes) on the columns of a square matrix in scalar type
+// S (double for real data: a quarter of the complex work).  A = P diag(sig) W^H
+// with the singular values in decreasing order.
+template <class S>
+static void jacobi_core(int n, std::vector<S>& A, std::vector<S>& W, std::vector<double>& sig) {
+  W.assign((size_t)n * n, S(0.0));
+  for (int i = 0; i < n; ++i) W[(size_t)i * n + i] = S(1.0);
   const double eps = std::numeric_limits<double>::epsilon();
   for (int sweep = 0; sweep < 80; ++sweep) {
     double off = 0.0;
     for (int p = 0; p < n - 1; ++p) {
+      S* ap = &A[(size_t)p * n];
+      S* wp = &W[(size_t)p * n];
       for (int q = p + 1; q < n; ++q) {
+        S* aq = &A[(size_t)q * n];
+        S* wq = &W[(size_t)q * n];
         double al = 0.0, be = 0.0;
-        cd ga = 0.0;
+        S ga = S(0.0);
         for (int i = 0; i < n; ++i) {
-          al += std::norm(A(i, p));
-          be += std::norm(A(i, q));
-          ga += std::conj(A(i, p)) * A(i, q);
+          al += norm_(ap[i]);
+          be += norm_(aq[i]);
+          ga += conj_(ap[i]) * aq[i];
         }
         const double ag = std::abs(ga);
         if (ag == 0.0 || ag <= eps * std::sqrt(al * be)) continue;
         off = std::max(off, ag / std::sqrt(al * be));
-        const cd e = ga / ag;
+        const S e = phase_re(ga, ag);
         const double zeta = (be - al) / (2.0 * ag);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        const S se = sn * e, sec = sn * conj_(e);
         // [a_p, a_q] <- [a_p, a_q] [[c, s e], [-s conj(e), c]]
         for (int i = 0; i < n; ++i) {
-          const cd ap = A(i, p), aq = A(i, q);
-          A(i, p) = c * ap - s * std::conj(e) * aq;
-          A(i, q) = s * e * ap + c * aq;
-          const cd wp = W(i, p), wq = W(i, q);
-          W(i, p) = c * wp - s * std::conj(e) * wq;
-          W(i, q) = s * e * wp + c * wq;
+          const S x = ap[i], y = aq[i];
+          ap[i] = c * x - sec * y;
+          aq[i] = se * x + c * y;
+          const S u = wp[i], v = wq[i];
+          wp[i] = c * u - sec * v;
+          wq[i] = se * u + c * v;
         }
       }
     }
@@ -225,27 +239,47 @@ void svd_jacobi(const Mat& A0, Mat& P, std::vector<double>& sig, Mat& W) {
   }
   sig.assign(n, 0.0);
   for (int j = 0; j < n; ++j) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += std::norm(A(i, j));
-    sig[j] = std::sqrt(s);
+    double s2 = 0.0;
+    for (int i = 0; i < n; ++i) s2 += norm_(A[(size_t)j * n + i]);
+    sig[j] = std::sqrt(s2);
   }
+}
+
+void svd_jacobi(const Mat& A0, Mat& P, std::vector<double>& sig, Mat& W, bool real) {
+  const int n = A0.n;
+  std::vector<double> s0;
   std::vector<int> ord(n);
   std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return sig[a] > sig[b]; });
-  Mat Ps(n, n), Ws(n, n);
-  std::vector<double> ss(n);
-  for (int jj = 0; jj < n; ++jj) {
-    const int j = ord[jj];
-    ss[jj] = sig[j];
-    const double inv = sig[j] > 0.0 ? 1.0 / sig[j] : 0.0;
-    for (int i = 0; i < n; ++i) {
-      Ps(i, jj) = A(i, j) * inv;
-      Ws(i, jj) = W(i, j);
+  P = Mat(n, n);
+  W = Mat(n, n);
+  if (real) {
+    std::vector<double> A((size_t)n * n), Wr;
+    for (size_t i = 0; i < A.size(); ++i) A[i] = A0.a[i].real();
+    jacobi_core(n, A, Wr, s0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return s0[a] > s0[b]; });
+    for (int jj = 0; jj < n; ++jj) {
+      const int j = ord[jj];
+      const double inv = s0[j] > 0.0 ? 1.0 / s0[j] : 0.0;
+      for (int i = 0; i < n; ++i) {
+        P(i, jj) = A[(size_t)j * n + i] * inv;
+        W(i, jj) = Wr[(size_t)j * n + i];
+      }
+    }
+  } else {
+    std::vector<cd> A = A0.a, Wc;
+    jacobi_core(n, A, Wc, s0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return s0[a] > s0[b]; });
+    for (int jj = 0; jj < n; ++jj) {
+      const int j = ord[jj];
+      const double inv = s0[j] > 0.0 ? 1.0 / s0[j] : 0.0;
+      for (int i = 0; i < n; ++i) {
+        P(i, jj) = A[(size_t)j * n + i] * inv;
+        W(i, jj) = Wc[(size_t)j * n + i];
+      }
     }
   }
-  P = Ps;
-  W = Ws;
-  sig = ss;
+  sig.resize(n);
+  for (int jj = 0; jj < n; ++jj) sig[jj] = s0[ord[jj]];
 }
 
 // Real orthonormal basis of the span of the complex columns Zk, assumed closed
@@ -327,20 +361,17 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
         Ri(i, j) = -acc / Rm(i, i);
       }
     }
-    double n1 = 0.0, n1i = 0.0;
-    for (int j = 0; j < l0; ++j) {
-      double a = 0.0, b = 0.0;
-      for (int i = 0; i < l0; ++i) {
-        a += std::abs(Rm(i, j));
-        b += std::abs(Ri(i, j));
+    double f = 0.0, fi = 0.0;
+    for (int j = 0; j < l0; ++j)
+      for (int i = 0; i <= j; ++i) {
+        f += std::norm(Rm(i, j));
+        fi += std::norm(Ri(i, j));
       }
-      n1 = std::max(n1, a);
-      n1i = std::max(n1i, b);
-    }
-    cond = n1 * n1i;
+    cond = std::sqrt(f * fi);
   }
-  // cond_2(R) <= l0 * cond_1(R): below the threshold no singular value is cut.
-  const bool svd_path = !(std::isfinite(cond) && (double)l0 * cond * thr < 1e-2);
+  // sigma_min / sigma_1 >= 1 / (||R||_F ||R^{-1}||_F): below the threshold no
+  // singular value can be cut, and the truncated SVD would keep all of them.
+  const bool svd_path = !(std::isfinite(cond) && cond * thr < 0.5);
   Mat Aeig;
   Mat Wl;  // right singular vectors kept (svd path)
   int ell = l0;
@@ -355,7 +386,7 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
   } else {
     Mat P, W;
     std::vector<double> sig;
-    svd_jacobi(Rm, P, sig, W);
+    svd_jacobi(Rm, P, sig, W, real);
     ell = 0;
     if (sig[0] > 0.0)
       for (int i = 0; i < l0; ++i)

@@ -28,8 +28,8 @@ bool schur(Mat& T, Mat& Z);
 int reorder(Mat& T, Mat& Z, std::vector<char> sel);
 
 // One-sided Jacobi SVD of a square matrix: A = P diag(sig) W^H, singular
-// values in decreasing order.
-void svd_jacobi(const Mat& A, Mat& P, std::vector<double>& sig, Mat& W);
+// values in decreasing order; real arithmetic when real is set.
+void svd_jacobi(const Mat& A, Mat& P, std::vector<double>& sig, Mat& W, bool real);
 
 // Sketched harmonic-Ritz step (Section 3.5): see sdr_host_harmonic_ritz.
 // R: l0 x l0 upper triangular factor of SAW; C = Q^H [SU, SV].  Writes G

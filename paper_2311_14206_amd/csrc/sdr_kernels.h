@@ -54,11 +54,24 @@ void launch_spmv_dots(hipStream_t st, int n, const int* rp, const int* ci, const
                       T* w, Window<T> win, int tw, typename traits<T>::acc* part, int nb,
                       const Ctrl* ctrl);
 
+// Prologue: d_q from the SpMV partials (part1, nb1) and, if part2prev is given,
+// nu[jprev] = ||p_jprev|| from the previous step's partials (column s).  Then
 // w <- w - sum_q (d_q / nu_{i0+q}^2) p_{i0+q}; partial ||w||^2 and S w per block.
 template <class T>
 void launch_update_sketch(hipStream_t st, int n, T* w, Window<T> win, int tw,
-                          const typename traits<T>::acc* red1, const double* nu, int i0,
-                          SketchSpec sk, typename traits<T>::acc* part, int nb, const Ctrl* ctrl);
+                          const typename traits<T>::acc* part1, int nb1,
+                          const typename traits<T>::acc* part2prev, int nb2prev, double* nu, int i0,
+                          int jprev, SketchSpec sk, typename traits<T>::acc* part, int nb,
+                          const Ctrl* ctrl);
+
+// out = [reduced columns of pa (first nscaled scaled by scl), reduced columns of pb].
+template <class A>
+void launch_reduce2(hipStream_t st, const A* pa, int nba, int ca, int nscaled, double scl,
+                    const A* pb, int nbb, int cb, A* out, const Ctrl* ctrl);
+
+// nu[0] and SV(:, 0) from a reduced sketch of p_0 ([s values, ||p_0||^2]).
+template <class A>
+void launch_init_v0(hipStream_t st, const A* red, int s, A* svcol, double* nu);
 
 // out[c] = scale_c * sum_b part[c * nb + b] (fixed order); scale 1/sqrt(zeta) for c < nscaled.
 template <class A>
@@ -67,9 +80,10 @@ void launch_reduce_cols(hipStream_t st, const A* part, int nb, int ncols, int ns
 
 // One Arnoldi step's small work: H column, SV column, SAV column, QR append,
 // projected residual and the halt decision.
+// red: [S p_j (s), ||p_j||^2, window products (tw), ||A p_{j-1}||^2].
 template <class A>
 void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int t, int s,
-                     const A* red1, const A* red2, double brtol, double rank_rtol);
+                     const A* red, double brtol, double rank_rtol);
 
 // Initialise the QR of SAW with its first khat columns (SAU) and rho = S r0.
 template <class A>

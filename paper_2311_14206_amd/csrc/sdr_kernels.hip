@@ -1,11 +1,13 @@
 // GMRES-SDR device kernels for gfx950 (wave64, LDS-staged sketches).
 //
-// Per Arnoldi step (Algorithm 1, truncated Arnoldi with one sketch per step):
-//   k_spmv_dots      w = A p_j and the window products <p_i, w>, ||w||^2
-//   k_reduce_cols    fixed-order reduction of the per-block partials
-//   k_update_sketch  p_{j+1} = w - sum c_i p_i in place, ||p_{j+1}||^2 and S p_{j+1}
-//   k_reduce_cols    again, for the s + 1 partial columns
-//   k_lsq_step       H column, SV and SAV columns, QR append, sketched residual
+// Per Arnoldi step j (Algorithm 1, truncated Arnoldi with one sketch per step):
+//   stream A (the Arnoldi chain)
+//     k_spmv_dots      w = A p_{j-1}, partial window products <p_i, w> and ||w||^2
+//     k_update_sketch  reduces those partials and ||p_{j-1}||^2 in its prologue,
+//                      p_j = w - sum c_i p_i in place, partial ||p_j||^2 and S p_j
+//   stream B (the sketched least squares, behind an event)
+//     k_reduce2        fixed-order reduction of both partial sets
+//     k_lsq_step       H column, SV and SAV columns, QR append, sketched residual
 // Basis vectors are stored unnormalised (p_i = nu_i v_i); the norms nu_i are
 // folded into the coefficients, which saves a normalisation pass per step.
 
@@ -114,10 +116,21 @@ void launch_spmv_dots(hipStream_t st, int n, const int* rp, const int* ci, const
 }
 
 // ---------------------------------------- update + norm + sparse sketch ---
+// Column sum of a [ncols x nb] partial array in the order every reducer of
+// this library uses (thread-strided, then the fixed block tree), so that the
+// same partials always give the same bits.
+template <class A>
+__device__ __forceinline__ A col_sum(const A* __restrict__ part, int nb, int col, A* red) {
+  A sum = zero<A>();
+  for (int i = threadIdx.x; i < nb; i += kBlock) sum += part[(int64_t)col * nb + i];
+  return block_sum(sum, red);
+}
+
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_update_sketch(
-    int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ red1,
-    const double* __restrict__ nu, int i0, SketchSpec sk, typename traits<T>::acc* __restrict__ part,
+    int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ part1,
+    int nb1, const typename traits<T>::acc* __restrict__ part2prev, int nb2prev, double* __restrict__ nu,
+    int i0, int jprev, SketchSpec sk, typename traits<T>::acc* __restrict__ part,
     int nb, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
   if (ctrl->halt) return;
@@ -126,12 +139,20 @@ __global__ __launch_bounds__(kBlock) void k_update_sketch(
   __shared__ A red[kWaves];
   const int s = sk.s;
   for (int i = threadIdx.x; i < kWaves * s; i += kBlock) acc[i] = zero<A>();
+  // prologue: window products of this step and ||p_{j-1}||^2 of the previous one
+  double nprev = 0.0;
+  if (part2prev) {
+    const A v = col_sum(part2prev, nb2prev, s, red);
+    nprev = sqrt(re(v));
+    if (blockIdx.x == 0 && threadIdx.x == 0) nu[jprev] = nprev;
+  }
   A c[kMaxWindow];
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) {
     if (q < tw) {
-      const double nq = nu[i0 + q];
-      c[q] = scale(red1[q], 1.0 / (nq * nq));
+      const A d = col_sum(part1, nb1, q, red);
+      const double nq = (part2prev && i0 + q == jprev) ? nprev : nu[i0 + q];
+      c[q] = scale(d, 1.0 / (nq * nq));
     } else {
       c[q] = zero<A>();
     }
@@ -168,12 +189,14 @@ __global__ __launch_bounds__(kBlock) void k_update_sketch(
 
 template <class T>
 void launch_update_sketch(hipStream_t st, int n, T* w, Window<T> win, int tw,
-                          const typename traits<T>::acc* red1, const double* nu, int i0,
-                          SketchSpec sk, typename traits<T>::acc* part, int nb, const Ctrl* ctrl) {
+                          const typename traits<T>::acc* part1, int nb1,
+                          const typename traits<T>::acc* part2prev, int nb2prev, double* nu, int i0,
+                          int jprev, SketchSpec sk, typename traits<T>::acc* part, int nb,
+                          const Ctrl* ctrl) {
   using A = typename traits<T>::acc;
   const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
-  hipLaunchKernelGGL(k_update_sketch<T>, dim3(nb), dim3(kBlock), lds, st, n, w, win, tw, red1, nu,
-                     i0, sk, part, nb, ctrl);
+  hipLaunchKernelGGL(k_update_sketch<T>, dim3(nb), dim3(kBlock), lds, st, n, w, win, tw, part1, nb1,
+                     part2prev, nb2prev, nu, i0, jprev, sk, part, nb, ctrl);
 }
 
 // ------------------------------------------------ fixed-order reduction ---
@@ -184,9 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_cols(const A* __restrict__ pa
   if (ctrl && ctrl->halt) return;
   __shared__ A red[kWaves];
   const int col = blockIdx.x;
-  A sum = zero<A>();
-  for (int i = threadIdx.x; i < nb; i += kBlock) sum += part[(int64_t)col * nb + i];
-  sum = block_sum(sum, red);
+  const A sum = col_sum(part, nb, col, red);
   if (threadIdx.x == 0) out[col] = col < nscaled ? scale(sum, scl) : sum;
 }
 
@@ -197,36 +218,116 @@ void launch_reduce_cols(hipStream_t st, const A* part, int nb, int ncols, int ns
                      ctrl);
 }
 
+// out[c] for c < ca from partA (c < nscaled scaled by scl), then cb columns of partB.
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_reduce2(const A* __restrict__ pa, int nba, int ca,
+                                                    int nscaled, double scl, const A* __restrict__ pb,
+                                                    int nbb, A* __restrict__ out,
+                                                    const Ctrl* __restrict__ ctrl) {
+  if (ctrl->halt) return;
+  __shared__ A red[kWaves];
+  const int col = blockIdx.x;
+  const A sum = col < ca ? col_sum(pa, nba, col, red) : col_sum(pb, nbb, col - ca, red);
+  if (threadIdx.x == 0) out[col] = col < nscaled ? scale(sum, scl) : sum;
+}
+
+template <class A>
+void launch_reduce2(hipStream_t st, const A* pa, int nba, int ca, int nscaled, double scl,
+                    const A* pb, int nbb, int cb, A* out, const Ctrl* ctrl) {
+  hipLaunchKernelGGL(k_reduce2<A>, dim3(ca + cb), dim3(kBlock), 0, st, pa, nba, ca, nscaled, scl, pb,
+                     nbb, out, ctrl);
+}
+
+// Cycle start: nu_0 = ||p_0|| and SV(:, 0) = S p_0 / nu_0 from a reduced sketch [s values, norm^2].
+template <class A>
+__global__ void k_init_v0(const A* __restrict__ red, int s, A* __restrict__ svcol, double* __restrict__ nu) {
+  const double n0 = sqrt(re(red[s]));
+  const double inv = n0 > 0.0 ? 1.0 / n0 : 0.0;
+  for (int r = threadIdx.x; r < s; r += blockDim.x) svcol[r] = scale(red[r], inv);
+  if (threadIdx.x == 0) nu[0] = n0;
+}
+
+template <class A>
+void launch_init_v0(hipStream_t st, const A* red, int s, A* svcol, double* nu) {
+  hipLaunchKernelGGL(k_init_v0<A>, dim3(1), dim3(kBlock), 0, st, red, s, svcol, nu);
+}
+
 // ------------------------------------------------ sketched least squares ---
+constexpr int kLsqPrefetch = 16;  // staged elements per thread and chunk
+
+// LDS layout of the least-squares kernels: a (s), acc (s), c (2 Lmax), then
+// the staged chunk of Q (ch x s).  ch follows from the LDS budget.
+template <class A>
+__host__ __device__ inline int lsq_chunk(int s, int lmax) {
+  const int budget = 60 * 1024 / (int)sizeof(A) - 2 * s - 2 * lmax;
+  int ch = budget / s;
+  const int cap = kLsqPrefetch * kLsqBlock / s;
+  if (ch > cap) ch = cap;
+  return ch < 1 ? 1 : ch;
+}
+
 // Append column a (in LDS, length s) to the QR factorisation Q R of SAW by
 // classical Gram-Schmidt with one reorthogonalisation (Section 3.3 allows
 // Householder or Gram-Schmidt with reorthogonalisation), then update the
-// projected residual rho and z = Q^H S r0.  Returns the sketched residual.
+// projected residual rho and z = Q^H S r0.  Each Gram-Schmidt pass reads Q
+// once, chunk by chunk through LDS: the chunk's products with the pass input
+// and its contribution to the update use the same staged data, and the next
+// chunk's loads are issued before the current chunk is used.  Returns the
+// sketched residual.
 template <class A>
-__device__ double qr_append(LsqState<A>& S, A* a, A* cbuf, A* red, int col, int s,
-                            double rank_rtol, bool* rank_loss) {
+__device__ double qr_append(LsqState<A>& S, A* a, A* acc, A* cbuf, A* qs, int ch, A* red, int col,
+                            int s, double rank_rtol, bool* rank_loss) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+  const A* __restrict__ Q = S.Q;  // ld = s: columns are contiguous
   double n0 = 0.0;
   for (int r = tid; r < s; r += blockDim.x) n0 += abs2(a[r]);
   n0 = sqrt(block_sum(n0, (double*)red));
   for (int i = tid; i < col; i += blockDim.x) cbuf[i] = zero<A>();
-  __syncthreads();
+  const int nch = (col + ch - 1) / ch;
   for (int pass = 0; pass < 2; ++pass) {
-    // c = Q^H a  (one wave per column)
-    for (int i = wv; i < col; i += nwv) {
-      A d = zero<A>();
-      const A* qi = S.Q + (int64_t)i * S.ldq;
-      for (int r = lane; r < s; r += 64) d += conj(qi[r]) * a[r];
-      d = wave_sum(d);
-      if (lane == 0) cbuf[col + i] = d;  // pass result in the upper half
+    for (int r = tid; r < s; r += blockDim.x) acc[r] = a[r];
+    A pre[kLsqPrefetch];
+    if (nch > 0) {
+      const int tot = min(ch, col) * s;
+#pragma unroll
+      for (int u = 0; u < kLsqPrefetch; ++u) {
+        const int idx = tid + u * kLsqBlock;
+        pre[u] = idx < tot ? Q[idx] : zero<A>();
+      }
+    }
+    for (int q = 0; q < nch; ++q) {
+      const int c0 = q * ch, cw = min(ch, col - c0), tot = cw * s;
+      __syncthreads();  // previous chunk fully consumed
+#pragma unroll
+      for (int u = 0; u < kLsqPrefetch; ++u) {
+        const int idx = tid + u * kLsqBlock;
+        if (idx < tot) qs[idx] = pre[u];
+      }
+      if (q + 1 < nch) {
+        const int c1 = c0 + ch, tot1 = min(ch, col - c1) * s;
+        const A* __restrict__ Qn = Q + (int64_t)c1 * s;
+#pragma unroll
+        for (int u = 0; u < kLsqPrefetch; ++u) {
+          const int idx = tid + u * kLsqBlock;
+          pre[u] = idx < tot1 ? Qn[idx] : zero<A>();
+        }
+      }
+      __syncthreads();
+      for (int i = wv; i < cw; i += nwv) {
+        A d = zero<A>();
+        for (int r = lane; r < s; r += 64) d += conj(qs[i * s + r]) * a[r];
+        d = wave_sum(d);
+        if (lane == 0) cbuf[col + c0 + i] = d;  // pass result in the upper half
+      }
+      __syncthreads();
+      for (int r = tid; r < s; r += blockDim.x) {
+        A v = acc[r];
+        for (int i = 0; i < cw; ++i) v -= qs[i * s + r] * cbuf[col + c0 + i];
+        acc[r] = v;
+      }
     }
     __syncthreads();
-    // a -= Q c
-    for (int r = tid; r < s; r += blockDim.x) {
-      A v = a[r];
-      for (int i = 0; i < col; ++i) v -= S.Q[(int64_t)i * S.ldq + r] * cbuf[col + i];
-      a[r] = v;
-    }
+    for (int r = tid; r < s; r += blockDim.x) a[r] = acc[r];
     for (int i = tid; i < col; i += blockDim.x) cbuf[i] += cbuf[col + i];
     __syncthreads();
   }
@@ -237,7 +338,11 @@ __device__ double qr_append(LsqState<A>& S, A* a, A* cbuf, A* red, int col, int 
   *rank_loss = loss;
   const double inv = na > 0.0 ? 1.0 / na : 0.0;
   A* qc = S.Q + (int64_t)col * S.ldq;
-  for (int r = tid; r < s; r += blockDim.x) qc[r] = scale(a[r], inv);
+  for (int r = tid; r < s; r += blockDim.x) {
+    const A v = scale(a[r], inv);
+    qc[r] = v;
+    a[r] = v;  // keep the new q in LDS for the residual update
+  }
   for (int i = tid; i < col; i += blockDim.x) S.R[(int64_t)col * S.ldr + i] = cbuf[i];
   if (tid == 0) {
     A d = zero<A>();
@@ -248,11 +353,11 @@ __device__ double qr_append(LsqState<A>& S, A* a, A* cbuf, A* red, int col, int 
   double sres;
   if (!loss) {
     A zc = zero<A>();
-    for (int r = tid; r < s; r += blockDim.x) zc += conj(qc[r]) * S.rho[r];
+    for (int r = tid; r < s; r += blockDim.x) zc += conj(a[r]) * S.rho[r];
     zc = block_sum(zc, red);
     double rr = 0.0;
     for (int r = tid; r < s; r += blockDim.x) {
-      const A v = S.rho[r] - qc[r] * zc;
+      const A v = S.rho[r] - a[r] * zc;
       S.rho[r] = v;
       rr += abs2(v);
     }
@@ -270,28 +375,35 @@ __device__ double qr_append(LsqState<A>& S, A* a, A* cbuf, A* red, int col, int 
 
 template <class A>
 __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, int khat, int m,
-                                                        int t, int s, const A* __restrict__ red1,
-                                                        const A* __restrict__ red2, double brtol,
-                                                        double rank_rtol) {
+                                                        int t, int s, const A* __restrict__ red,
+                                                        double brtol, double rank_rtol) {
+  // red: [0, s) S p_j (scaled), [s] ||p_j||^2, [s+1, s+1+tw) window products,
+  //      [s+1+tw] ||A p_{j-1}||^2
   if (S.ctrl->halt) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lmax = khat + m + 1;
+  const int ch = lsq_chunk<A>(s, lmax);
   A* a = reinterpret_cast<A*>(smem_raw);  // s
-  A* cbuf = a + s;                        // 2 * Lmax
-  __shared__ A red[kLsqBlock / 64];
+  A* accb = a + s;                        // s
+  A* cbuf = accb + s;                     // 2 * Lmax
+  A* qs = cbuf + 2 * lmax;                // ch * s
+  __shared__ A red_s[kLsqBlock / 64];
   __shared__ A hcol[kMaxWindow + 1];
   __shared__ int sh_break;
   const int tid = threadIdx.x;
   const int i0 = j - t > 0 ? j - t : 0;  // first window vector (0-based)
   const int tw = j - i0;
+  const A* dots = red + s + 1;
+  const double nuj = sqrt(re(red[s]));
   if (tid == 0) {
-    const double nuj = sqrt(re(red2[s]));
     const double nuprev = S.nu[j - 1];
-    const double nw = sqrt(re(red1[tw]));
+    const double nw = sqrt(re(dots[tw]));
     const bool brk = !(nuj > brtol * nw);
     sh_break = brk;
+    // same reduction order as the update kernel's prologue: identical bits
     S.nu[j] = nuj;
     for (int q = 0; q < tw; ++q) {
-      const A h = scale(red1[q], 1.0 / (S.nu[i0 + q] * nuprev));
+      const A h = scale(dots[q], 1.0 / (S.nu[i0 + q] * nuprev));
       hcol[q] = h;
       S.H[(int64_t)(j - 1) * S.ldh + i0 + q] = h;
     }
@@ -302,10 +414,9 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, in
   }
   __syncthreads();
   const bool brk = sh_break;
-  const double nuj = sqrt(re(red2[s]));
   A* svj = S.SB + (int64_t)(khat + j) * S.ldsb;
   for (int r = tid; r < s; r += blockDim.x) {
-    const A v = brk ? zero<A>() : scale(red2[r], 1.0 / nuj);
+    const A v = brk ? zero<A>() : scale(red[r], 1.0 / nuj);
     svj[r] = v;
     A sum = zero<A>();
     for (int q = 0; q < tw; ++q) sum += S.SB[(int64_t)(khat + i0 + q) * S.ldsb + r] * hcol[q];
@@ -315,7 +426,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, in
   }
   __syncthreads();
   bool loss = false;
-  const double sres = qr_append(S, a, cbuf, red, khat + j - 1, s, rank_rtol, &loss);
+  const double sres = qr_append(S, a, accb, cbuf, qs, ch, red_s, khat + j - 1, s, rank_rtol, &loss);
   if (tid == 0) {
     int flags = 0;
     if (brk) flags |= 2;
@@ -341,19 +452,23 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, in
 
 template <class A>
 void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int t, int s,
-                     const A* red1, const A* red2, double brtol, double rank_rtol) {
+                     const A* red, double brtol, double rank_rtol) {
   const int lmax = khat + m + 1;
-  const size_t lds = (size_t)(s + 2 * lmax) * sizeof(A);
-  hipLaunchKernelGGL(k_lsq_step<A>, dim3(1), dim3(kLsqBlock), lds, st, S, j, khat, m, t, s, red1,
-                     red2, brtol, rank_rtol);
+  const size_t lds = (size_t)(2 * s + 2 * lmax + lsq_chunk<A>(s, lmax) * s) * sizeof(A);
+  hipLaunchKernelGGL(k_lsq_step<A>, dim3(1), dim3(kLsqBlock), lds, st, S, j, khat, m, t, s, red,
+                     brtol, rank_rtol);
 }
 
 template <class A>
 __global__ __launch_bounds__(kLsqBlock) void k_lsq_init(LsqState<A> S, int khat, int s,
                                                         const A* __restrict__ Sr, double rank_rtol) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lmax = khat + 1;
+  const int ch = lsq_chunk<A>(s, lmax);
   A* a = reinterpret_cast<A*>(smem_raw);
-  A* cbuf = a + s;
+  A* accb = a + s;
+  A* cbuf = accb + s;
+  A* qs = cbuf + 2 * lmax;
   __shared__ A red[kLsqBlock / 64];
   for (int r = threadIdx.x; r < s; r += blockDim.x) S.rho[r] = Sr[r];
   __syncthreads();
@@ -362,14 +477,15 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_init(LsqState<A> S, int khat,
     for (int r = threadIdx.x; r < s; r += blockDim.x) a[r] = S.SAW[(int64_t)c * S.ldsaw + r];
     __syncthreads();
     bool loss = false;
-    sres = qr_append(S, a, cbuf, red, c, s, rank_rtol, &loss);
+    sres = qr_append(S, a, accb, cbuf, qs, ch, red, c, s, rank_rtol, &loss);
   }
   if (threadIdx.x == 0) S.sres_hist[0] = sres;
 }
 
 template <class A>
 void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr, double rank_rtol) {
-  const size_t lds = (size_t)(s + 2 * (khat + 1)) * sizeof(A);
+  const int lmax = khat + 1;
+  const size_t lds = (size_t)(2 * s + 2 * lmax + lsq_chunk<A>(s, lmax) * s) * sizeof(A);
   hipLaunchKernelGGL(k_lsq_init<A>, dim3(1), dim3(kLsqBlock), lds, st, S, khat, s, Sr, rank_rtol);
 }
 
@@ -698,8 +814,9 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
   template void launch_spmv_dots<T>(hipStream_t, int, const int*, const int*, const T*, const T*, \
                                     T*, Window<T>, int, traits<T>::acc*, int, const Ctrl*);        \
   template void launch_update_sketch<T>(hipStream_t, int, T*, Window<T>, int,                     \
-                                        const traits<T>::acc*, const double*, int, SketchSpec,    \
-                                        traits<T>::acc*, int, const Ctrl*);                       \
+                                        const traits<T>::acc*, int, const traits<T>::acc*, int,   \
+                                        double*, int, int, SketchSpec, traits<T>::acc*, int,      \
+                                        const Ctrl*);                                             \
   template void launch_sketch_cols<T>(hipStream_t, int, const T*, int64_t, int, SketchSpec,       \
                                       traits<T>::acc*, int);                                      \
   template void launch_gemv_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
@@ -719,7 +836,10 @@ SDR_INST_BASIS(cx<float>)
   template void launch_reduce_cols<A>(hipStream_t, const A*, int, int, int, double, A*,        \
                                       const Ctrl*);                                             \
   template void launch_lsq_step<A>(hipStream_t, LsqState<A>, int, int, int, int, int, const A*, \
-                                   const A*, double, double);                                   \
+                                   double, double);                                             \
+  template void launch_reduce2<A>(hipStream_t, const A*, int, int, int, double, const A*, int,  \
+                                  int, A*, const Ctrl*);                                        \
+  template void launch_init_v0<A>(hipStream_t, const A*, int, A*, double*);                     \
   template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double);       \
   template void launch_backsolve<A>(hipStream_t, LsqState<A>, int, int, A*);                    \
   template void launch_spmv_residual<A>(hipStream_t, int, const int*, const int*, const A*,     \

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -82,6 +83,7 @@ struct Options {
   double brtol = -1.0;  // < 0: default for the basis precision
   double rank_rtol = 1e-12;
   int lookahead = 4;
+  bool kernel_timing = false;
 };
 
 // Matrix view (device, full precision values).
@@ -112,6 +114,8 @@ struct SolverBase {
   virtual int get_basis(int ncols, void* V, void* H, void* SV) = 0;
   virtual int sketch(const void* X, int ncols, void* Y) = 0;
   virtual void set_stream(hipStream_t s) = 0;
+  virtual void reset() = 0;
+  virtual int kernel_times(double* ms, int64_t* counts, int cap) = 0;
 };
 
 template <class T>
@@ -153,10 +157,18 @@ class Solver final : public SolverBase {
       sres_hist_ = dalloc<double>(m + 2);
       ctrl_ = dalloc<Ctrl>(1);
       ctrl_free_ = dalloc<Ctrl>(1);
-      part1_ = dalloc<A>((size_t)(kMaxWindow + 1) * nb1_);
-      part2_ = dalloc<A>((size_t)(8 * s + 8 + 1) * nb2_);
-      red1_ = dalloc<A>(kMaxWindow + 1);
+      nslot_ = opt.lookahead + 2;
+      slot1_ = (size_t)(kMaxWindow + 1) * nb1_;
+      slot2_ = (size_t)(s + 1) * nb2_;
+      slotr_ = (size_t)(s + 1 + kMaxWindow + 1);
+      part1_ = dalloc<A>(slot1_ * nslot_);
+      part2_ = dalloc<A>(slot2_ * nslot_);
+      redb_ = dalloc<A>(slotr_ * nslot_);
+      psk_ = dalloc<A>((size_t)(8 * s + 8 + 1) * nb2_);
       red2_ = dalloc<A>(8 * s + 8 + 1);
+      HIPCHK(hipStreamCreateWithFlags(&streamB_, hipStreamNonBlocking));
+      evs_.assign(nslot_ + 1, nullptr);
+      for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       red3_ = dalloc<A>(4);
       Sr_ = dalloc<A>(s);
       ycoef_ = dalloc<A>(lmax_);
@@ -166,12 +178,26 @@ class Solver final : public SolverBase {
       G_ = dalloc<A>((size_t)lmax_ * kmax_);
       Gs_ = dalloc<A>((size_t)lmax_ * kmax_);
       C_ = dalloc<A>((size_t)lmax_ * lmax_);
+      if (opt.kernel_timing) {
+        ev_.assign(m + 2, std::array<hipEvent_t, 3>{});
+        for (auto& a : ev_)
+          for (auto& e : a) HIPCHK(hipEventCreate(&e));
+      }
       HIPCHK(hipHostMalloc((void**)&rec_host_, sizeof(StepRec) * (m + 2),
                            hipHostMallocMapped | hipHostMallocCoherent));
       HIPCHK(hipHostGetDevicePointer((void**)&rec_dev_, rec_host_, 0));
+      HIPCHK(hipHostMalloc((void**)&hR_, sizeof(A) * (size_t)lmax_ * lmax_, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hC_, sizeof(A) * (size_t)lmax_ * lmax_, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hz_, sizeof(A) * (size_t)lmax_, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hy_, sizeof(A) * (size_t)lmax_, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hnu_, sizeof(double) * (size_t)(m + 2), hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hG_, sizeof(A) * (size_t)lmax_ * kmax_ * 2, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hscal_, sizeof(A) * 8, hipHostMallocDefault));
       HIPCHK(hipMemsetAsync(ctrl_free_, 0, sizeof(Ctrl), stream_));
       HIPCHK(hipMemsetAsync(nu_, 0, sizeof(double) * (m + 2), stream_));
       HIPCHK(hipMemsetAsync(H_, 0, sizeof(A) * (m + 1) * m, stream_));
+      HIPCHK(hipStreamSynchronize(stream_));
+      HIPCHK(hipMemsetAsync(redb_, 0, sizeof(A) * slotr_ * nslot_, stream_));
       HIPCHK(hipStreamSynchronize(stream_));
     } catch (...) {
       release();
@@ -207,20 +233,19 @@ class Solver final : public SolverBase {
     const int maxcc = std::max(1, std::min(8, (int)(48 * 1024 / (kWaves * s_ * sizeof(A)))));
     for (int c0 = 0; c0 < nc; c0 += maxcc) {
       const int cc = std::min(maxcc, nc - c0);
-      launch_sketch_cols<X>(stream_, n_, x + (size_t)c0 * n_, (int64_t)n_, cc, sk_, part2_, nb2_);
+      launch_sketch_cols<X>(stream_, n_, x + (size_t)c0 * n_, (int64_t)n_, cc, sk_, psk_, nb2_);
       LAUNCHCHK();
-      launch_reduce_cols<A>(stream_, part2_, nb2_, cc * s_ + cc, cc * s_,
+      launch_reduce_cols<A>(stream_, psk_, nb2_, cc * s_ + cc, cc * s_,
                             1.0 / std::sqrt((double)sk_.zeta), red2_, nullptr);
       LAUNCHCHK();
       for (int c = 0; c < cc; ++c)
         HIPCHK(hipMemcpyAsync(out + (size_t)(c0 + c) * ldo, red2_ + (size_t)c * s_, sizeof(A) * s_,
                               hipMemcpyDeviceToDevice, stream_));
       if (nrm2) {
-        std::vector<A> h(cc);
-        HIPCHK(hipMemcpyAsync(h.data(), red2_ + (size_t)cc * s_, sizeof(A) * cc,
+        HIPCHK(hipMemcpyAsync(hscal_, red2_ + (size_t)cc * s_, sizeof(A) * cc,
                               hipMemcpyDeviceToHost, stream_));
         HIPCHK(hipStreamSynchronize(stream_));
-        for (int c = 0; c < cc; ++c) nrm2[c0 + c] = to_double_re(h[c]);
+        for (int c = 0; c < cc; ++c) nrm2[c0 + c] = to_double_re(hscal_[c]);
       }
     }
   }
@@ -232,14 +257,13 @@ class Solver final : public SolverBase {
   }
 
   double residual(const A* x, const A* b, A* r) {
-    launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, part2_, nb2_);
+    launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, psk_, nb2_);
     LAUNCHCHK();
-    launch_reduce_cols<A>(stream_, part2_, nb2_, 1, 0, 1.0, red3_, nullptr);
+    launch_reduce_cols<A>(stream_, psk_, nb2_, 1, 0, 1.0, red3_, nullptr);
     LAUNCHCHK();
-    A h;
-    HIPCHK(hipMemcpyAsync(&h, red3_, sizeof(A), hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(hscal_, red3_, sizeof(A), hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipStreamSynchronize(stream_));
-    return std::sqrt(to_double_re(h));
+    return std::sqrt(to_double_re(hscal_[0]));
   }
 
   LsqState<A> lsq() {
@@ -266,17 +290,36 @@ class Solver final : public SolverBase {
   void enqueue_step(int j, const T* vals) {
     const int i0 = std::max(j - t_, 0);
     const int tw = j - i0;
+    const int sl = j % nslot_, slp = (j - 1) % nslot_;
     Window<T> win{};
     for (int q = 0; q < tw; ++q) win.p[q] = P_ + (size_t)(i0 + q) * n_;
     T* w = P_ + (size_t)j * n_;
     const T* x = P_ + (size_t)(j - 1) * n_;
-    launch_spmv_dots<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, part1_, nb1_, ctrl_);
-    launch_reduce_cols<A>(stream_, part1_, nb1_, tw + 1, 0, 1.0, red1_, ctrl_);
-    launch_update_sketch<T>(stream_, n_, w, win, tw, red1_, nu_, i0, sk_, part2_, nb2_, ctrl_);
-    launch_reduce_cols<A>(stream_, part2_, nb2_, s_ + 1, s_, 1.0 / std::sqrt((double)sk_.zeta),
-                          red2_, ctrl_);
-    launch_lsq_step<A>(stream_, lsq(), j, khat_, m_, t_, s_, red1_, red2_, brtol_, opt_.rank_rtol);
+    A* p1 = part1_ + slot1_ * sl;
+    A* p2 = part2_ + slot2_ * sl;
+    const A* p2prev = j >= 2 ? part2_ + slot2_ * slp : nullptr;
+    const bool tm = opt_.kernel_timing;
+    // stream A: the Arnoldi chain
+    if (tm) HIPCHK(hipEventRecord(ev_[j][0], stream_));
+    launch_spmv_dots<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, p1, nb1_, ctrl_);
+    if (tm) HIPCHK(hipEventRecord(ev_[j][1], stream_));
+    launch_update_sketch<T>(stream_, n_, w, win, tw, p1, nb1_, p2prev, nb2_, nu_, i0, j - 1, sk_, p2,
+                            nb2_, ctrl_);
+    if (tm) HIPCHK(hipEventRecord(ev_[j][2], stream_));
     LAUNCHCHK();
+    // stream B: the sketched least squares of step j
+    HIPCHK(hipEventRecord(evs_[sl], stream_));
+    HIPCHK(hipStreamWaitEvent(streamB_, evs_[sl], 0));
+    A* rd = redb_ + slotr_ * sl;
+    launch_reduce2<A>(streamB_, p2, nb2_, s_ + 1, s_, 1.0 / std::sqrt((double)sk_.zeta), p1, nb1_,
+                      tw + 1, rd, ctrl_);
+    launch_lsq_step<A>(streamB_, lsq(), j, khat_, m_, t_, s_, rd, brtol_, opt_.rank_rtol);
+    LAUNCHCHK();
+  }
+
+  void sync_both() {
+    HIPCHK(hipStreamSynchronize(stream_));
+    HIPCHK(hipStreamSynchronize(streamB_));
   }
 
   // Wait for the record of step j; returns false if it never arrives.
@@ -292,22 +335,47 @@ class Solver final : public SolverBase {
         return true;
       }
       if (++spins % 4096 == 0) {
-        hipError_t q = hipStreamQuery(stream_);
-        if (q == hipSuccess) {
+        const hipError_t qa = hipStreamQuery(stream_);
+        const hipError_t qb = hipStreamQuery(streamB_);
+        if (qa != hipSuccess && qa != hipErrorNotReady) {
+          set_err(std::string("stream error: ") + hipGetErrorString(qa));
+          throw HipError{SDR_EDEVICE};
+        }
+        if (qb != hipSuccess && qb != hipErrorNotReady) {
+          set_err(std::string("stream error: ") + hipGetErrorString(qb));
+          throw HipError{SDR_EDEVICE};
+        }
+        if (qa == hipSuccess && qb == hipSuccess) {
           if (__atomic_load_n(&rec_host_[j].seq, __ATOMIC_ACQUIRE) == j) continue;
           return false;
-        }
-        if (q != hipErrorNotReady) {
-          set_err(std::string("stream error: ") + hipGetErrorString(q));
-          throw HipError{SDR_EDEVICE};
         }
       }
     }
   }
 
-  double check(int j) {
+  // y = R^{-1} z for the leading (khat + j) block, on the host (a sequential
+  // back substitution is latency bound on one compute unit); coefficients of
+  // the stored basis [U, P]: y_i for U, y_i / nu_i for the unnormalised P.
+  void solve_coefficients(int j) {
     const int nls = khat_ + j;
-    launch_backsolve<A>(stream_, lsq(), nls, khat_, ycoef_);
+    HIPCHK(hipMemcpyAsync(hR_, R_, sizeof(A) * (size_t)lmax_ * nls, hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(hz_, z_, sizeof(A) * nls, hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(hnu_, nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+    std::vector<std::complex<double>> y(nls);
+    for (int i = 0; i < nls; ++i) y[i] = to_cd(hz_[i]);
+    for (int i = nls - 1; i >= 0; --i) {
+      const std::complex<double> rii = to_cd(hR_[(size_t)i * lmax_ + i]);
+      y[i] = std::abs(rii) > 0.0 ? y[i] / rii : std::complex<double>(0.0);
+      for (int k = 0; k < i; ++k) y[k] -= to_cd(hR_[(size_t)i * lmax_ + k]) * y[i];
+    }
+    for (int i = 0; i < nls; ++i)
+      hy_[i] = from_cd<A>(i < khat_ ? y[i] : y[i] / hnu_[i - khat_]);
+    HIPCHK(hipMemcpyAsync(ycoef_, hy_, sizeof(A) * nls, hipMemcpyHostToDevice, stream_));
+  }
+
+  double check(int j) {
+    solve_coefficients(j);
     launch_gemv_basis<T>(stream_, n_, U_, n_, khat_, P_, n_, j, ycoef_, xt_);
     LAUNCHCHK();
     return residual(xt_, r_, rnew_);
@@ -369,27 +437,21 @@ class Solver final : public SolverBase {
       sketches++;
       ips++;
       launch_cast_scale<T>(stream_, n_, r_, 1.0, P_);
+      launch_sketch_cols<T>(stream_, n_, P_, (int64_t)n_, 1, sk_, psk_, nb2_);
+      launch_reduce_cols<A>(stream_, psk_, nb2_, s_ + 1, s_, 1.0 / std::sqrt((double)sk_.zeta), red2_,
+                            nullptr);
+      launch_init_v0<A>(stream_, red2_, s_, SB_ + (size_t)khat_ * s_, nu_);
       LAUNCHCHK();
-      double nu0sq = 0.0;
-      sketch_cols<T>(P_, 1, SB_ + (size_t)khat_ * s_, s_, &nu0sq);
-      const double nu0 = std::sqrt(nu0sq);
-      {
-        std::vector<A> sv(s_);
-        HIPCHK(hipMemcpyAsync(sv.data(), SB_ + (size_t)khat_ * s_, sizeof(A) * s_,
-                              hipMemcpyDeviceToHost, stream_));
-        HIPCHK(hipStreamSynchronize(stream_));
-        for (auto& v : sv) v = scale(v, 1.0 / nu0);
-        HIPCHK(hipMemcpyAsync(SB_ + (size_t)khat_ * s_, sv.data(), sizeof(A) * s_,
-                              hipMemcpyHostToDevice, stream_));
-        HIPCHK(hipMemcpyAsync(nu_, &nu0, sizeof(double), hipMemcpyHostToDevice, stream_));
-      }
       if (khat_ > 0) {
         HIPCHK(hipMemcpyAsync(SB_, SU_, sizeof(A) * s_ * khat_, hipMemcpyDeviceToDevice, stream_));
         HIPCHK(hipMemcpyAsync(SAW_, SAU_, sizeof(A) * s_ * khat_, hipMemcpyDeviceToDevice, stream_));
       }
       for (int j = 0; j <= m_ + 1; ++j) __atomic_store_n(&rec_host_[j].seq, -1, __ATOMIC_RELEASE);
       launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
-      launch_lsq_init<A>(stream_, lsq(), khat_, s_, Sr_, opt_.rank_rtol);
+      LAUNCHCHK();
+      HIPCHK(hipEventRecord(evs_[nslot_], stream_));
+      HIPCHK(hipStreamWaitEvent(streamB_, evs_[nslot_], 0));
+      launch_lsq_init<A>(streamB_, lsq(), khat_, s_, Sr_, opt_.rank_rtol);
       LAUNCHCHK();
       // --- truncated Arnoldi with sketched least squares ---
       int enq = 0, done = 0, jstop = 0, flags_stop = 0;
@@ -410,7 +472,7 @@ class Solver final : public SolverBase {
         if (!(rc.flags & 2)) sketches++;
         sres = rc.sres;
         if (rc.flags & 1) {
-          HIPCHK(hipStreamSynchronize(stream_));
+          sync_both();
           res = check(done);
           matvecs++;
           ips++;
@@ -442,6 +504,22 @@ class Solver final : public SolverBase {
       }
       cycles++;
       last_sres = sres;
+      if (opt_.kernel_timing) {
+        sync_both();
+        for (int j = 1; j <= jstop; ++j) {
+          float a = 0.f, b2 = 0.f, c = 0.f;
+          HIPCHK(hipEventElapsedTime(&a, ev_[j][0], ev_[j][1]));
+          HIPCHK(hipEventElapsedTime(&b2, ev_[j][1], ev_[j][2]));
+          HIPCHK(hipEventElapsedTime(&c, ev_[j][0], ev_[j][2]));
+          kt_ms_[0] += a;
+          kt_ms_[1] += b2;
+          kt_ms_[2] += c;
+          kt_n_[0]++;
+          kt_n_[1]++;
+          kt_n_[2]++;
+          kt_bytes_tw_[std::min(j, t_)]++;
+        }
+      }
       // x += xt, r = r0 - A xt
       A one = from_cd<A>({1.0, 0.0});
       launch_axpy<A>(stream_, n_, one, xt_, x);
@@ -463,7 +541,7 @@ class Solver final : public SolverBase {
       converged = cyc_conv;
       if (flags_stop && !cyc_conv && jstop == 1) break;
     }
-    HIPCHK(hipStreamSynchronize(stream_));
+    sync_both();
     status = converged ? SDR_OK : SDR_NOT_CONVERGED;
     fill_stats(st, cycles, iters, matvecs, ips, sketches, checks, status, rn / nb, last_sres,
                safety, now() - t0, eig_time);
@@ -480,18 +558,16 @@ class Solver final : public SolverBase {
     }
     launch_small_gemm<A>(stream_, true, l0, l0, s_, Q_, s_, SB_, s_, C_, l0);
     LAUNCHCHK();
-    std::vector<A> Rh((size_t)l0 * l0), Ch((size_t)l0 * l0);
-    std::vector<double> nuh(j + 1);
-    HIPCHK(hipMemcpy2DAsync(Rh.data(), sizeof(A) * l0, R_, sizeof(A) * lmax_, sizeof(A) * l0, l0,
-                            hipMemcpyDeviceToHost, stream_));
-    HIPCHK(hipMemcpyAsync(Ch.data(), C_, sizeof(A) * l0 * l0, hipMemcpyDeviceToHost, stream_));
-    HIPCHK(hipMemcpyAsync(nuh.data(), nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(hR_, R_, sizeof(A) * (size_t)lmax_ * l0, hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(hC_, C_, sizeof(A) * (size_t)l0 * l0, hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(hnu_, nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipStreamSynchronize(stream_));
     std::vector<std::complex<double>> Rc((size_t)l0 * l0), Cc((size_t)l0 * l0), G;
-    for (size_t i = 0; i < Rc.size(); ++i) {
-      Rc[i] = to_cd(Rh[i]);
-      Cc[i] = to_cd(Ch[i]);
-    }
+    for (int c = 0; c < l0; ++c)
+      for (int i = 0; i < l0; ++i) {
+        Rc[(size_t)c * l0 + i] = i <= c ? to_cd(hR_[(size_t)c * lmax_ + i]) : std::complex<double>(0.0);
+        Cc[(size_t)c * l0 + i] = to_cd(hC_[(size_t)c * l0 + i]);
+      }
     const int keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s_, k_, !traits<T>::cpx, G, ell);
     if (keff < 0) {
       set_err("Schur iteration did not converge");
@@ -501,15 +577,16 @@ class Solver final : public SolverBase {
       khat_ = 0;
       return 0;
     }
-    std::vector<A> Gh((size_t)l0 * keff), Gp((size_t)l0 * keff);
+    A* Gh = hG_;
+    A* Gp = hG_ + (size_t)l0 * keff;
     for (int c = 0; c < keff; ++c)
       for (int i = 0; i < l0; ++i) {
         const A g = from_cd<A>(G[(size_t)c * l0 + i]);
         Gh[(size_t)c * l0 + i] = g;
-        Gp[(size_t)c * l0 + i] = i < khat_ ? g : scale(g, 1.0 / nuh[i - khat_]);
+        Gp[(size_t)c * l0 + i] = i < khat_ ? g : scale(g, 1.0 / hnu_[i - khat_]);
       }
-    HIPCHK(hipMemcpyAsync(Gs_, Gh.data(), sizeof(A) * Gh.size(), hipMemcpyHostToDevice, stream_));
-    HIPCHK(hipMemcpyAsync(G_, Gp.data(), sizeof(A) * Gp.size(), hipMemcpyHostToDevice, stream_));
+    HIPCHK(hipMemcpyAsync(Gs_, Gh, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
+    HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
     launch_gemm_basis<T>(stream_, n_, U_, n_, khat_, P_, n_, j, G_, keff, Unew_, n_);
     // SU <- [SU SV] G, SAU <- [SAU SAV] G (the old SU/SAU sit in SB/SAW)
     launch_small_gemm<A>(stream_, false, s_, keff, l0, SB_, s_, Gs_, l0, SU_, s_);
@@ -584,12 +661,26 @@ class Solver final : public SolverBase {
     for (void* p : {(void*)valB_, (void*)P_, (void*)U_, (void*)Unew_, (void*)SU_, (void*)SAU_,
                     (void*)Q_, (void*)R_, (void*)z_, (void*)rho_, (void*)SB_, (void*)SAW_, (void*)H_,
                     (void*)nu_, (void*)sres_hist_, (void*)ctrl_, (void*)ctrl_free_, (void*)part1_,
-                    (void*)part2_, (void*)red1_, (void*)red2_, (void*)red3_, (void*)Sr_,
+                    (void*)part2_, (void*)redb_, (void*)psk_, (void*)red2_, (void*)red3_, (void*)Sr_,
                     (void*)ycoef_, (void*)xt_, (void*)r_, (void*)rnew_, (void*)G_, (void*)Gs_,
                     (void*)C_})
       dfree(p);
     if (rec_host_) (void)hipHostFree(rec_host_);
     rec_host_ = nullptr;
+    for (void* p : {(void*)hR_, (void*)hC_, (void*)hz_, (void*)hy_, (void*)hnu_, (void*)hG_,
+                    (void*)hscal_})
+      if (p) (void)hipHostFree(p);
+    hR_ = hC_ = hz_ = hy_ = hG_ = hscal_ = nullptr;
+    hnu_ = nullptr;
+    for (auto& a : ev_)
+      for (auto& e : a)
+        if (e) (void)hipEventDestroy(e);
+    ev_.clear();
+    for (auto& e : evs_)
+      if (e) (void)hipEventDestroy(e);
+    evs_.clear();
+    if (streamB_) (void)hipStreamDestroy(streamB_);
+    streamB_ = nullptr;
   }
 
   MatView<A> M_;
@@ -607,10 +698,45 @@ class Solver final : public SolverBase {
   A *SB_ = nullptr, *SAW_ = nullptr, *H_ = nullptr;
   double *nu_ = nullptr, *sres_hist_ = nullptr;
   Ctrl *ctrl_ = nullptr, *ctrl_free_ = nullptr;
-  A *part1_ = nullptr, *part2_ = nullptr, *red1_ = nullptr, *red2_ = nullptr, *red3_ = nullptr;
+  A *part1_ = nullptr, *part2_ = nullptr, *redb_ = nullptr, *psk_ = nullptr, *red2_ = nullptr,
+    *red3_ = nullptr;
+  int nslot_ = 0;
+  size_t slot1_ = 0, slot2_ = 0, slotr_ = 0;
+  hipStream_t streamB_ = nullptr;
+  std::vector<hipEvent_t> evs_;
   A *Sr_ = nullptr, *ycoef_ = nullptr, *xt_ = nullptr, *r_ = nullptr, *rnew_ = nullptr;
   A *G_ = nullptr, *Gs_ = nullptr, *C_ = nullptr;
   StepRec *rec_host_ = nullptr, *rec_dev_ = nullptr;
+  // pinned host staging of the small dense data
+  A *hR_ = nullptr, *hC_ = nullptr, *hz_ = nullptr, *hy_ = nullptr, *hG_ = nullptr, *hscal_ = nullptr;
+  double* hnu_ = nullptr;
+  std::vector<std::array<hipEvent_t, 3>> ev_;
+  double kt_ms_[3] = {0, 0, 0};
+  int64_t kt_n_[3] = {0, 0, 0};
+  int64_t kt_bytes_tw_[kMaxWindow + 1] = {0, 0, 0, 0, 0};
+
+ public:
+  void reset() override {
+    khat_ = 0;
+    sau_stale_ = false;
+  }
+
+  // [0] spmv_dots ms, [1] update_sketch ms, [2] whole step ms (K1 start to LSQ end);
+  // counts[0..2] launches; counts[3 + tw] = launches with window size tw.
+  int kernel_times(double* ms, int64_t* counts, int cap) override {
+    for (int i = 0; i < 3 && i < cap; ++i) {
+      if (ms) ms[i] = kt_ms_[i];
+      if (counts) counts[i] = kt_n_[i];
+    }
+    for (int tw = 0; tw <= kMaxWindow; ++tw)
+      if (counts && 3 + tw < cap) counts[3 + tw] = kt_bytes_tw_[tw];
+    for (int i = 0; i < 3; ++i) {
+      kt_ms_[i] = 0;
+      kt_n_[i] = 0;
+    }
+    for (auto& v : kt_bytes_tw_) v = 0;
+    return SDR_OK;
+  }
 };
 
 }  // namespace
@@ -833,6 +959,9 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
   } else if (k == "rank_rtol") {
     if (built || !(v >= 0.0)) return set_err("rank_rtol >= 0, before the first solve"), SDR_EINVAL;
     h->opt.rank_rtol = v;
+  } else if (k == "kernel_timing") {
+    if (built) return set_err("kernel_timing must be set before the first solve"), SDR_EINVAL;
+    h->opt.kernel_timing = v != 0.0;
   } else if (k == "lookahead") {
     if (built || v < 1 || v > 64) return set_err("lookahead in [1,64], before the first solve"), SDR_EINVAL;
     h->opt.lookahead = (int)v;
@@ -981,6 +1110,22 @@ int sdr_get_basis(sdr_handle* h, int ncols, void* V, void* H, void* SV) {
   if (!h) return set_err("null handle"), SDR_EINVAL;
   try {
     return fwd(h)->get_basis(ncols, V, H, SV);
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_reset(sdr_handle* h) {
+  if (!h) return set_err("null handle"), SDR_EINVAL;
+  if (h->fwd) h->fwd->reset();
+  if (h->adj) h->adj->reset();
+  return SDR_OK;
+}
+
+int sdr_kernel_times(sdr_handle* h, double* ms, int64_t* counts, int cap) {
+  if (!h) return set_err("null handle"), SDR_EINVAL;
+  try {
+    return fwd(h)->kernel_times(ms, counts, cap);
   } catch (HipError& e) {
     return e.code;
   }

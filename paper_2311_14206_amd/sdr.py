@@ -61,6 +61,8 @@ EXPORTS = {
     "sdr_sketch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "sdr_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sdr_get_basis": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sdr_reset": (C.c_int, [C.c_void_p]),
+    "sdr_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
     "sdr_destroy": (None, [C.c_void_p]),
     "sdr_last_error": (C.c_char_p, []),
     "sdr_host_harmonic_ritz": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
@@ -201,6 +203,18 @@ class SDRSolver:
         _check(lib().sdr_grad_values(self.h, C.c_void_p(_ptr(lam)), C.c_void_p(_ptr(x)),
                                      C.c_void_p(_ptr(g))), "sdr_grad_values")
         return g
+
+    def reset(self):
+        """Drop the recycle space."""
+        _check(lib().sdr_reset(self.h), "sdr_reset")
+
+    def kernel_times(self):
+        """Event timings since the last call (needs the option kernel_timing=1)."""
+        ms = (C.c_double * 8)()
+        cnt = (C.c_int64 * 8)()
+        _check(lib().sdr_kernel_times(self.h, ms, cnt, 8), "sdr_kernel_times")
+        return {"spmv_dots_ms": ms[0], "update_sketch_ms": ms[1], "step_ms": ms[2],
+                "launches": cnt[0], "window_hist": [cnt[3 + i] for i in range(5)]}
 
     def trace(self):
         n = _check(lib().sdr_get_trace(self.h, None, 0), "sdr_get_trace")
