@@ -145,6 +145,227 @@ bool schur(Mat& T, Mat& Z) {
   return true;
 }
 
+// Real Schur form by Hessenberg reduction and Francis double-shift QR
+// (real arithmetic throughout): A = Z T Z^T with T quasi-upper triangular.
+// 2 x 2 diagonal blocks with real eigenvalues are split by a rotation, so every
+// remaining 2 x 2 block holds a complex-conjugate pair.  T, Z column major.
+static bool schur_real(int n, std::vector<double>& T, std::vector<double>& Z) {
+  auto t = [&](int i, int j) -> double& { return T[(size_t)j * n + i]; };
+  auto z = [&](int i, int j) -> double& { return Z[(size_t)j * n + i]; };
+  Z.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) z(i, i) = 1.0;
+  if (n <= 1) return true;
+  std::vector<double> v(n);
+  for (int k = 0; k + 2 < n; ++k) {  // Householder reduction to Hessenberg form
+    const int len = n - k - 1;
+    double xn = 0.0;
+    for (int i = 0; i < len; ++i) xn += t(k + 1 + i, k) * t(k + 1 + i, k);
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const double alpha = t(k + 1, k) > 0.0 ? -xn : xn;
+    for (int i = 0; i < len; ++i) v[i] = t(k + 1 + i, k);
+    v[0] -= alpha;
+    double vn2 = 0.0;
+    for (int i = 0; i < len; ++i) vn2 += v[i] * v[i];
+    if (vn2 == 0.0) continue;
+    const double f = 2.0 / vn2;
+    for (int j = k; j < n; ++j) {
+      double sm = 0.0;
+      for (int i = 0; i < len; ++i) sm += v[i] * t(k + 1 + i, j);
+      sm *= f;
+      for (int i = 0; i < len; ++i) t(k + 1 + i, j) -= v[i] * sm;
+    }
+    for (int i = 0; i < n; ++i) {
+      double sm = 0.0;
+      for (int l = 0; l < len; ++l) sm += t(i, k + 1 + l) * v[l];
+      sm *= f;
+      for (int l = 0; l < len; ++l) t(i, k + 1 + l) -= sm * v[l];
+    }
+    for (int i = 0; i < n; ++i) {
+      double sm = 0.0;
+      for (int l = 0; l < len; ++l) sm += z(i, k + 1 + l) * v[l];
+      sm *= f;
+      for (int l = 0; l < len; ++l) z(i, k + 1 + l) -= sm * v[l];
+    }
+    t(k + 1, k) = alpha;
+    for (int i = 1; i < len; ++i) t(k + 1 + i, k) = 0.0;
+  }
+  // reflector P = I - beta v v^T (len 2 or 3) applied to rows k.. (left) and
+  // columns k.. (right) of T, and to columns of Z
+  auto left = [&](int k, int len, const double* vv, double beta, int c0, int c1) {
+    for (int j = c0; j <= c1; ++j) {
+      double sm = 0.0;
+      for (int i = 0; i < len; ++i) sm += vv[i] * t(k + i, j);
+      sm *= beta;
+      for (int i = 0; i < len; ++i) t(k + i, j) -= sm * vv[i];
+    }
+  };
+  auto right = [&](std::vector<double>& M, int k, int len, const double* vv, double beta, int r1) {
+    for (int i = 0; i <= r1; ++i) {
+      double sm = 0.0;
+      for (int l = 0; l < len; ++l) sm += M[(size_t)(k + l) * n + i] * vv[l];
+      sm *= beta;
+      for (int l = 0; l < len; ++l) M[(size_t)(k + l) * n + i] -= sm * vv[l];
+    }
+  };
+  auto house = [](double* x, int len, double* vv, double& beta) {
+    double nr = 0.0;
+    for (int i = 0; i < len; ++i) nr += x[i] * x[i];
+    nr = std::sqrt(nr);
+    for (int i = 0; i < len; ++i) vv[i] = x[i];
+    if (nr == 0.0) {
+      beta = 0.0;
+      return;
+    }
+    const double alpha = x[0] > 0.0 ? -nr : nr;
+    vv[0] -= alpha;
+    double vn2 = 0.0;
+    for (int i = 0; i < len; ++i) vn2 += vv[i] * vv[i];
+    beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+  };
+  const double eps = std::numeric_limits<double>::epsilon();
+  double anorm = 0.0;
+  for (double x : T) anorm = std::max(anorm, std::fabs(x));
+  int p = n - 1, iter = 0, total = 0;
+  while (p > 0) {
+    int l = p;
+    for (; l > 0; --l) {
+      double sc = std::fabs(t(l - 1, l - 1)) + std::fabs(t(l, l));
+      if (sc == 0.0) sc = anorm;
+      if (std::fabs(t(l, l - 1)) <= eps * sc) break;
+    }
+    if (l > 0) t(l, l - 1) = 0.0;
+    if (l == p) {
+      --p;
+      iter = 0;
+      continue;
+    }
+    if (l == p - 1) {
+      // 2 x 2 block: split it if its eigenvalues are real
+      const int i = p - 1;
+      const double a = t(i, i), b = t(i, i + 1), c = t(i + 1, i), d = t(i + 1, i + 1);
+      const double hp = 0.5 * (a - d), disc = hp * hp + b * c;
+      if (disc >= 0.0) {
+        const double lam = 0.5 * (a + d) + (hp >= 0.0 ? 1.0 : -1.0) * std::sqrt(disc);
+        double v0, v1;
+        if (std::fabs(lam - d) + std::fabs(c) >= std::fabs(b) + std::fabs(lam - a)) {
+          v0 = lam - d;
+          v1 = c;
+        } else {
+          v0 = b;
+          v1 = lam - a;
+        }
+        const double nr = std::hypot(v0, v1);
+        if (nr > 0.0) {
+          const double cs = v0 / nr, sn = v1 / nr;  // G = [[cs, -sn], [sn, cs]]
+          for (int r = 0; r < n; ++r) {
+            const double x0 = t(r, i), x1 = t(r, i + 1);
+            t(r, i) = cs * x0 + sn * x1;
+            t(r, i + 1) = -sn * x0 + cs * x1;
+          }
+          for (int cc = 0; cc < n; ++cc) {
+            const double x0 = t(i, cc), x1 = t(i + 1, cc);
+            t(i, cc) = cs * x0 + sn * x1;
+            t(i + 1, cc) = -sn * x0 + cs * x1;
+          }
+          for (int r = 0; r < n; ++r) {
+            const double x0 = z(r, i), x1 = z(r, i + 1);
+            z(r, i) = cs * x0 + sn * x1;
+            z(r, i + 1) = -sn * x0 + cs * x1;
+          }
+          t(i + 1, i) = 0.0;
+        }
+      }
+      p -= 2;
+      iter = 0;
+      continue;
+    }
+    double tr, det;
+    if (iter > 0 && iter % 10 == 0) {  // exceptional shift
+      const double sc = std::fabs(t(p, p - 1)) + std::fabs(t(p - 1, p - 2));
+      tr = 1.5 * sc;
+      det = sc * sc;
+    } else {
+      tr = t(p - 1, p - 1) + t(p, p);
+      det = t(p - 1, p - 1) * t(p, p) - t(p - 1, p) * t(p, p - 1);
+    }
+    double x[3];
+    x[0] = t(l, l) * t(l, l) + t(l, l + 1) * t(l + 1, l) - tr * t(l, l) + det;
+    x[1] = t(l + 1, l) * (t(l, l) + t(l + 1, l + 1) - tr);
+    x[2] = t(l + 1, l) * t(l + 2, l + 1);
+    double vv[3], beta;
+    for (int k = l; k <= p - 2; ++k) {
+      house(x, 3, vv, beta);
+      const int r = std::max(l, k - 1);
+      left(k, 3, vv, beta, r, n - 1);
+      const int rr = std::min(k + 3, p);
+      right(T, k, 3, vv, beta, rr);
+      right(Z, k, 3, vv, beta, n - 1);
+      if (k > l) {
+        t(k + 1, k - 1) = 0.0;
+        t(k + 2, k - 1) = 0.0;
+      }
+      x[0] = t(k + 1, k);
+      x[1] = t(k + 2, k);
+      if (k < p - 2) x[2] = t(k + 3, k);
+    }
+    house(x, 2, vv, beta);
+    left(p - 1, 2, vv, beta, p - 2, n - 1);
+    right(T, p - 1, 2, vv, beta, p);
+    right(Z, p - 1, 2, vv, beta, n - 1);
+    t(p, p - 2) = 0.0;
+    ++iter;
+    if (++total > 60 * n) return false;
+  }
+  for (int j = 0; j < n; ++j)
+    for (int i = j + 2; i < n; ++i) t(i, j) = 0.0;
+  return true;
+}
+
+// Complex upper triangular form of a real Schur form: each 2 x 2 block (a
+// conjugate pair) is triangularised by a unitary rotation whose first column
+// is the block's eigenvector.  partner[i] is the other member of i's pair, or
+// -1 for a real eigenvalue.
+static void real_to_complex_schur(int n, const std::vector<double>& Tr, const std::vector<double>& Zr,
+                                  Mat& T, Mat& Z, std::vector<int>& partner) {
+  T = Mat(n, n);
+  Z = Mat(n, n);
+  for (size_t i = 0; i < Tr.size(); ++i) {
+    T.a[i] = Tr[i];
+    Z.a[i] = Zr[i];
+  }
+  partner.assign(n, -1);
+  for (int i = 0; i + 1 < n; ++i) {
+    if (T(i + 1, i) == cd(0.0)) continue;
+    const cd a = T(i, i), b = T(i, i + 1), c = T(i + 1, i), d = T(i + 1, i + 1);
+    const cd hp = 0.5 * (a - d);
+    const cd lam = 0.5 * (a + d) + std::sqrt(hp * hp + b * c);
+    cd v0 = b, v1 = lam - a;
+    const double nr = std::hypot(std::abs(v0), std::abs(v1));
+    v0 /= nr;
+    v1 /= nr;
+    for (int r = 0; r < n; ++r) {
+      const cd t1 = T(r, i), t2 = T(r, i + 1);
+      T(r, i) = t1 * v0 + t2 * v1;
+      T(r, i + 1) = -t1 * std::conj(v1) + t2 * std::conj(v0);
+    }
+    for (int cc = 0; cc < n; ++cc) {
+      const cd t1 = T(i, cc), t2 = T(i + 1, cc);
+      T(i, cc) = std::conj(v0) * t1 + std::conj(v1) * t2;
+      T(i + 1, cc) = -v1 * t1 + v0 * t2;
+    }
+    for (int r = 0; r < n; ++r) {
+      const cd t1 = Z(r, i), t2 = Z(r, i + 1);
+      Z(r, i) = t1 * v0 + t2 * v1;
+      Z(r, i + 1) = -t1 * std::conj(v1) + t2 * std::conj(v0);
+    }
+    T(i + 1, i) = 0.0;
+    partner[i] = i + 1;
+    partner[i + 1] = i;
+    ++i;
+  }
+}
+
 // Exchange the diagonal entries i and i+1 of the upper triangular T by a
 // unitary 2 x 2 rotation whose first column is the eigenvector of the
 // trailing entry; update Z accordingly.
@@ -245,6 +466,9 @@ static void jacobi_core(int n, std::vector<S>& A, std::vector<S>& W, std::vector
   }
 }
 
+// The rotations act on the columns of X = A^H: for the triangular factor of a
+// QR decomposition the one-sided method converges in far fewer sweeps on the
+// transpose.  X V = U diag(sig) gives A = V diag(sig) U^H, so P = V, W = U.
 void svd_jacobi(const Mat& A0, Mat& P, std::vector<double>& sig, Mat& W, bool real) {
   const int n = A0.n;
   std::vector<double> s0;
@@ -253,28 +477,31 @@ void svd_jacobi(const Mat& A0, Mat& P, std::vector<double>& sig, Mat& W, bool re
   P = Mat(n, n);
   W = Mat(n, n);
   if (real) {
-    std::vector<double> A((size_t)n * n), Wr;
-    for (size_t i = 0; i < A.size(); ++i) A[i] = A0.a[i].real();
-    jacobi_core(n, A, Wr, s0);
+    std::vector<double> X((size_t)n * n), V;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) X[(size_t)j * n + i] = A0(j, i).real();
+    jacobi_core(n, X, V, s0);
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return s0[a] > s0[b]; });
     for (int jj = 0; jj < n; ++jj) {
       const int j = ord[jj];
       const double inv = s0[j] > 0.0 ? 1.0 / s0[j] : 0.0;
       for (int i = 0; i < n; ++i) {
-        P(i, jj) = A[(size_t)j * n + i] * inv;
-        W(i, jj) = Wr[(size_t)j * n + i];
+        W(i, jj) = X[(size_t)j * n + i] * inv;
+        P(i, jj) = V[(size_t)j * n + i];
       }
     }
   } else {
-    std::vector<cd> A = A0.a, Wc;
-    jacobi_core(n, A, Wc, s0);
+    std::vector<cd> X((size_t)n * n), V;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) X[(size_t)j * n + i] = std::conj(A0(j, i));
+    jacobi_core(n, X, V, s0);
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return s0[a] > s0[b]; });
     for (int jj = 0; jj < n; ++jj) {
       const int j = ord[jj];
       const double inv = s0[j] > 0.0 ? 1.0 / s0[j] : 0.0;
       for (int i = 0; i < n; ++i) {
-        P(i, jj) = A[(size_t)j * n + i] * inv;
-        W(i, jj) = Wc[(size_t)j * n + i];
+        W(i, jj) = X[(size_t)j * n + i] * inv;
+        P(i, jj) = V[(size_t)j * n + i];
       }
     }
   }
@@ -411,9 +638,18 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
       for (int i = 0; i < l0; ++i) Wl(i, j) = W(i, j);
   }
   *ell_out = ell;
-  Mat T = Aeig, Z;
-  if (!schur(T, Z)) return -1;
   const int n = ell;
+  Mat T, Z;
+  std::vector<int> partner(n, -1);
+  if (real) {
+    std::vector<double> Tr((size_t)n * n), Zr;
+    for (size_t i = 0; i < Tr.size(); ++i) Tr[i] = Aeig.a[i].real();
+    if (!schur_real(n, Tr, Zr)) return -1;
+    real_to_complex_schur(n, Tr, Zr, T, Z, partner);
+  } else {
+    T = Aeig;
+    if (!schur(T, Z)) return -1;
+  }
   std::vector<cd> lam(n);
   for (int i = 0; i < n; ++i) lam[i] = T(i, i);
   std::vector<int> ord(n);
@@ -424,23 +660,9 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
   std::vector<char> sel(n, 0);
   for (int i = 0; i < kk; ++i) sel[ord[i]] = 1;
   if (real) {
-    // never split a complex-conjugate pair
-    for (int i = 0; i < n; ++i) {
-      if (!sel[i]) continue;
-      const double al = std::abs(lam[i]);
-      if (std::fabs(lam[i].imag()) <= 1e-8 * al) continue;
-      int best = -1;
-      double bd = std::numeric_limits<double>::infinity();
-      for (int j = 0; j < n; ++j) {
-        if (j == i) continue;
-        const double d = std::abs(lam[j] - std::conj(lam[i]));
-        if (d < bd) {
-          bd = d;
-          best = j;
-        }
-      }
-      if (best >= 0 && bd <= 1e-6 * al && !sel[best]) sel[best] = 1;
-    }
+    // never split a complex-conjugate pair (the two members of a 2 x 2 block)
+    for (int i = 0; i < n; ++i)
+      if (sel[i] && partner[i] >= 0) sel[partner[i]] = 1;
   }
   const int keff = reorder(T, Z, sel);
   Mat Zk(n, keff);
