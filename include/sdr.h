@@ -7,10 +7,10 @@
  * cycles of Algorithm 1: truncated Arnoldi (each new basis vector is
  * orthogonalised against the t previous ones only, Section 3.2), a sparse-sign
  * sketch S of every basis vector (Section 3, eq. (3.1)), the sketched least
- * squares problem min_y ||S r0 - S A [U V] y|| (eq. (3.3), Section 3.3), the
+ * squares problem min_y ||S r0 - S A [U V] y|| (eq. (3.2), Section 3.3), the
  * safety-factor residual control of Section 3.4, and the sketched
  * harmonic-Ritz compression of [U V] into the next recycle space (Section 3.5,
- * eq. (3.5)).  Sequences reuse U, SU, SAU (Section 3.6).
+ * eq. (3.6)).  Sequences reuse U, SU, SAU (Section 3.6).
  *
  * Conventions
  *  - Every vector / matrix pointer passed to a solve is a DEVICE pointer on the
@@ -61,7 +61,7 @@ typedef struct {
   sdr_dtype dtype;
 } sdr_csr;
 
-/* Counters and timings of the last solve (paper Section 5 counts MV and IP). */
+/* Counters and timings of the last solve (Section 6 counts MV and IP). */
 typedef struct {
   int32_t cycles;          /* restart cycles run */
   int32_t iters;           /* Arnoldi steps (accepted) */

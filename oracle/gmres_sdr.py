@@ -99,7 +99,7 @@ def _norm(v) -> float:
 
 
 def harmonic_ritz_update(W, SB, SAW, k: int, real: bool, s: int):
-    """Sketched harmonic-Ritz compression (Section 3.5, eq. (3.5)).
+    """Sketched harmonic-Ritz compression (Section 3.5, eq. (3.6)).
 
     W = [U, V(:,1:j)] (N x ell0), SB = its sketch, SAW = S A W.
     Returns (G, ell, k_eff) with G = Vhat_ell Z(:, 1:k_eff), so that the new

@@ -6,7 +6,7 @@
 // triangular factor R of SAW = Q R is comfortably far from the truncation
 // threshold, the truncated SVD keeps every singular value and the matrix is
 // similar (by the unitary right singular vectors) to R^{-1} Q^H [SU, SV], the
-// minimum-norm solution of eq. (3.5); that matrix is used directly and the SVD
+// minimum-norm solution of eq. (3.6); that matrix is used directly and the SVD
 // is skipped.
 #include "dense.h"
 

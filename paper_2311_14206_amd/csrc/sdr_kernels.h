@@ -48,11 +48,12 @@ template <class A> struct LsqState {
   StepRec* rec;       // host-mapped records, one per step
 };
 
-// w = A x, partial window products <p_q, w> and ||w||^2 per block.
+// w = A x, partial window products <p_q, w> and ||w||^2 per block.  With
+// events e0/e1 the dispatch records its own start and end (kernel timing).
 template <class T>
 void launch_spmv_dots(hipStream_t st, int n, const int* rp, const int* ci, const T* val, const T* x,
                       T* w, Window<T> win, int tw, typename traits<T>::acc* part, int nb,
-                      const Ctrl* ctrl);
+                      const Ctrl* ctrl, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Prologue: d_q from the SpMV partials (part1, nb1) and, if part2prev is given,
 // nu[jprev] = ||p_jprev|| from the previous step's partials (column s).  Then
@@ -62,7 +63,7 @@ void launch_update_sketch(hipStream_t st, int n, T* w, Window<T> win, int tw,
                           const typename traits<T>::acc* part1, int nb1,
                           const typename traits<T>::acc* part2prev, int nb2prev, double* nu, int i0,
                           int jprev, SketchSpec sk, typename traits<T>::acc* part, int nb,
-                          const Ctrl* ctrl);
+                          const Ctrl* ctrl, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // out = [reduced columns of pa (first nscaled scaled by scl), reduced columns of pb].
 template <class A>
@@ -88,7 +89,7 @@ void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int 
 // Initialise the QR of SAW with its first khat columns (SAU) and rho = S r0.
 template <class A>
 void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr,
-                     double rank_rtol);
+                     double rank_rtol, int m);
 
 // y = R(0:n,0:n)^{-1} z(0:n); coefficients for [U, P]: y_i (U part), y_i / nu_i (P part).
 template <class A>

@@ -11,6 +11,8 @@
 // Basis vectors are stored unnormalised (p_i = nu_i v_i); the norms nu_i are
 // folded into the coefficients, which saves a normalisation pass per step.
 
+#include <hip/hip_ext.h>
+
 #include "sdr_kernels.h"
 
 namespace sdr {
@@ -110,9 +112,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dots(
 template <class T>
 void launch_spmv_dots(hipStream_t st, int n, const int* rp, const int* ci, const T* val, const T* x,
                       T* w, Window<T> win, int tw, typename traits<T>::acc* part, int nb,
-                      const Ctrl* ctrl) {
-  hipLaunchKernelGGL(k_spmv_dots<T>, dim3(nb), dim3(kBlock), 0, st, n, rp, ci, val, x, w, win, tw,
-                     part, nb, ctrl);
+                      const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
+  if (e0)  // events recorded by the dispatch itself: the kernel's own duration
+    hipExtLaunchKernelGGL(k_spmv_dots<T>, dim3(nb), dim3(kBlock), 0, st, e0, e1, 0, n, rp, ci, val, x,
+                          w, win, tw, part, nb, ctrl);
+  else
+    hipLaunchKernelGGL(k_spmv_dots<T>, dim3(nb), dim3(kBlock), 0, st, n, rp, ci, val, x, w, win, tw,
+                       part, nb, ctrl);
 }
 
 // ---------------------------------------- update + norm + sparse sketch ---
@@ -192,11 +198,15 @@ void launch_update_sketch(hipStream_t st, int n, T* w, Window<T> win, int tw,
                           const typename traits<T>::acc* part1, int nb1,
                           const typename traits<T>::acc* part2prev, int nb2prev, double* nu, int i0,
                           int jprev, SketchSpec sk, typename traits<T>::acc* part, int nb,
-                          const Ctrl* ctrl) {
+                          const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
   using A = typename traits<T>::acc;
   const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
-  hipLaunchKernelGGL(k_update_sketch<T>, dim3(nb), dim3(kBlock), lds, st, n, w, win, tw, part1, nb1,
-                     part2prev, nb2prev, nu, i0, jprev, sk, part, nb, ctrl);
+  if (e0)
+    hipExtLaunchKernelGGL(k_update_sketch<T>, dim3(nb), dim3(kBlock), lds, st, e0, e1, 0, n, w, win,
+                          tw, part1, nb1, part2prev, nb2prev, nu, i0, jprev, sk, part, nb, ctrl);
+  else
+    hipLaunchKernelGGL(k_update_sketch<T>, dim3(nb), dim3(kBlock), lds, st, n, w, win, tw, part1, nb1,
+                       part2prev, nb2prev, nu, i0, jprev, sk, part, nb, ctrl);
 }
 
 // ------------------------------------------------ fixed-order reduction ---
@@ -373,6 +383,285 @@ __device__ double qr_append(LsqState<A>& S, A* a, A* acc, A* cbuf, A* qs, int ch
   return sres;
 }
 
+// ---- register-resident variant ------------------------------------------
+// Q (s x col, ld = s) is held in registers: lane l of wave w keeps rows
+// l + 64 rr (rr < RL) of columns w + 8 cc (cc < CW), so one burst of
+// coalesced loads brings the whole factor in.  Products with a column are a
+// per-lane sum plus a wave reduction (every lane ends with the value); the
+// update a - Q c is a per-lane sum reduced over the eight waves through LDS.
+// Every wave keeps a full copy of the working vector (its rows per lane).
+constexpr int kRegWaves = kLsqBlock / 64;
+
+template <class A, int RL, int CW>
+struct RegQ {
+  A q[RL][CW];
+};
+
+template <class A, int RL, int CW>
+__device__ __forceinline__ void regq_load(RegQ<A, RL, CW>& Q, const A* __restrict__ g, int s, int col) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int cc = 0; cc < CW; ++cc) {
+    const int i = wv + kRegWaves * cc;
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) {
+      const int r = lane + 64 * rr;
+      Q.q[rr][cc] = (i < col && r < s) ? g[(int64_t)i * s + r] : zero<A>();
+    }
+  }
+}
+
+// a (registers, rows lane + 64 rr) is orthogonalised against the col columns
+// in Q (twice); returns ||a|| after and writes the R column (c1 + c2) for
+// i < col into R, and the new unit column into Q's registers and into g.
+template <class A, int RL, int CW>
+__device__ double regq_append(RegQ<A, RL, CW>& Q, A (&a)[RL], A* __restrict__ g, A* __restrict__ Rcol,
+                              A* lds_red /* kRegWaves * 64 * RL */, int s, int col, double rank_rtol,
+                              bool* loss) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double n0 = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < RL; ++rr) n0 += abs2(a[rr]);
+  n0 = sqrt(wave_sum(n0));
+  A ctot[CW];
+#pragma unroll
+  for (int cc = 0; cc < CW; ++cc) ctot[cc] = zero<A>();
+  for (int pass = 0; pass < 2; ++pass) {
+    A c[CW];
+#pragma unroll
+    for (int cc = 0; cc < CW; ++cc) {
+      A d = zero<A>();
+#pragma unroll
+      for (int rr = 0; rr < RL; ++rr) d += conj(Q.q[rr][cc]) * a[rr];
+      c[cc] = wave_sum(d);
+      ctot[cc] += c[cc];
+    }
+    // partial update over this wave's columns, reduced over the waves
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) {
+      A u = zero<A>();
+#pragma unroll
+      for (int cc = 0; cc < CW; ++cc) u += Q.q[rr][cc] * c[cc];
+      lds_red[(wv * RL + rr) * 64 + lane] = u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) {
+      A u = lds_red[(0 * RL + rr) * 64 + lane];
+      for (int w = 1; w < kRegWaves; ++w) u += lds_red[(w * RL + rr) * 64 + lane];
+      a[rr] -= u;
+    }
+    __syncthreads();
+  }
+  // R column: entries of this wave's columns (lane 0 writes)
+  if (lane == 0) {
+#pragma unroll
+    for (int cc = 0; cc < CW; ++cc) {
+      const int i = wv + kRegWaves * cc;
+      if (i < col) Rcol[i] = ctot[cc];
+    }
+  }
+  double na = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < RL; ++rr) na += abs2(a[rr]);
+  na = sqrt(wave_sum(na));
+  *loss = !(na > rank_rtol * n0);
+  const double inv = na > 0.0 ? 1.0 / na : 0.0;
+#pragma unroll
+  for (int rr = 0; rr < RL; ++rr) a[rr] = scale(a[rr], inv);
+  // the new column joins Q: global memory (wave 0) and the owner wave's registers
+  if (wv == 0) {
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) {
+      const int r = lane + 64 * rr;
+      if (r < s) g[(int64_t)col * s + r] = a[rr];
+    }
+  }
+  if (wv == col % kRegWaves) {
+    const int cc = col / kRegWaves;
+#pragma unroll
+    for (int k = 0; k < CW; ++k)
+      if (k == cc)
+#pragma unroll
+        for (int rr = 0; rr < RL; ++rr) Q.q[rr][k] = (lane + 64 * rr < s) ? a[rr] : zero<A>();
+  }
+  return na;
+}
+
+// projected residual update with the new unit column q (registers of every
+// wave); wave 0 owns rho.  Returns the sketched residual (all threads).
+template <class A, int RL>
+__device__ double regq_residual(const A (&q)[RL], A* __restrict__ rho, A* __restrict__ zc_out,
+                                bool skip, int s, double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (wv == 0) {
+    A rv[RL];
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) {
+      const int r = lane + 64 * rr;
+      rv[rr] = r < s ? rho[r] : zero<A>();
+    }
+    A zc = zero<A>();
+    if (!skip) {
+#pragma unroll
+      for (int rr = 0; rr < RL; ++rr) zc += conj(q[rr]) * rv[rr];
+      zc = wave_sum(zc);
+#pragma unroll
+      for (int rr = 0; rr < RL; ++rr) {
+        rv[rr] -= q[rr] * zc;
+        const int r = lane + 64 * rr;
+        if (r < s) rho[r] = rv[rr];
+      }
+    }
+    double rr2 = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) rr2 += abs2(rv[rr]);
+    rr2 = wave_sum(rr2);
+    if (lane == 0) {
+      *zc_out = zc;
+      *sh = sqrt(rr2);
+    }
+  }
+  __syncthreads();
+  return *sh;
+}
+
+template <class A, int RL, int CW>
+__global__ __launch_bounds__(kLsqBlock) void k_lsq_step_reg(LsqState<A> S, int j, int khat, int m,
+                                                            int t, int s, const A* __restrict__ red,
+                                                            double brtol, double rank_rtol) {
+  if (S.ctrl->halt) return;
+  __shared__ A lds_red[kRegWaves * 64 * RL];
+  __shared__ A hcol[kMaxWindow + 1];
+  __shared__ int sh_break;
+  __shared__ double sh_res;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i0 = j - t > 0 ? j - t : 0;
+  const int tw = j - i0;
+  const int col = khat + j - 1;
+  RegQ<A, RL, CW> Q;
+  regq_load(Q, S.Q, s, col);  // issued first: in flight during the small work below
+  const A* dots = red + s + 1;
+  const double nuj = sqrt(re(red[s]));
+  if (tid == 0) {
+    const double nuprev = S.nu[j - 1];
+    const double nw = sqrt(re(dots[tw]));
+    const bool brk = !(nuj > brtol * nw);
+    sh_break = brk;
+    S.nu[j] = nuj;  // same reduction order as the update kernel's prologue
+    for (int q = 0; q < tw; ++q) {
+      const A h = scale(dots[q], 1.0 / (S.nu[i0 + q] * nuprev));
+      hcol[q] = h;
+      S.H[(int64_t)(j - 1) * S.ldh + i0 + q] = h;
+    }
+    A hs = zero<A>();
+    *(double*)&hs = brk ? 0.0 : nuj / nuprev;
+    hcol[tw] = hs;
+    S.H[(int64_t)(j - 1) * S.ldh + j] = hs;
+  }
+  __syncthreads();
+  const bool brk = sh_break;
+  // SV(:, j) and SAV(:, j-1) = SV(:, window + j) H(:, j-1), rows of this lane
+  A a[RL];
+  A* svj = S.SB + (int64_t)(khat + j) * S.ldsb;
+  A* sawc = S.SAW + (int64_t)(khat + j - 1) * S.ldsaw;
+#pragma unroll
+  for (int rr = 0; rr < RL; ++rr) {
+    const int r = lane + 64 * rr;
+    A sum = zero<A>();
+    if (r < s) {
+      const A v = brk ? zero<A>() : scale(red[r], 1.0 / nuj);
+      for (int q = 0; q < tw; ++q) sum += S.SB[(int64_t)(khat + i0 + q) * S.ldsb + r] * hcol[q];
+      sum += v * hcol[tw];
+      if (tid < 64) {
+        svj[r] = v;
+        sawc[r] = sum;
+      }
+    }
+    a[rr] = sum;
+  }
+  bool loss = false;
+  const double na =
+      regq_append<A, RL, CW>(Q, a, S.Q, S.R + (int64_t)col * S.ldr, lds_red, s, col, rank_rtol, &loss);
+  if (tid == 0) {
+    A d = zero<A>();
+    *(double*)&d = na;
+    S.R[(int64_t)col * S.ldr + col] = d;
+  }
+  const double sres = regq_residual<A, RL>(a, S.rho, S.z + col, loss, s, &sh_res);
+  if (tid == 0) {
+    int flags = 0;
+    if (brk) flags |= 2;
+    if (loss) flags |= 4;
+    const bool halt = sres < S.ctrl->thresh || j == m || brk || loss;
+    if (halt) flags |= 1;
+    S.sres_hist[j] = sres;
+    if (halt) {
+      S.ctrl->halt = 1;
+      S.ctrl->halt_j = j;
+      S.ctrl->flags = flags;
+    }
+    StepRec* rc = S.rec + j;
+    rc->sres = sres;
+    rc->nu = nuj;
+    rc->j = j;
+    rc->flags = flags;
+    __threadfence_system();
+    __atomic_store_n(&rc->seq, j, __ATOMIC_RELEASE);
+    __threadfence_system();
+  }
+}
+
+template <class A, int RL, int CW>
+__global__ __launch_bounds__(kLsqBlock) void k_lsq_init_reg(LsqState<A> S, int khat, int s,
+                                                            const A* __restrict__ Sr, double rank_rtol) {
+  __shared__ A lds_red[kRegWaves * 64 * RL];
+  __shared__ double sh_res;
+  const int lane = threadIdx.x & 63;
+  RegQ<A, RL, CW> Q;
+#pragma unroll
+  for (int cc = 0; cc < CW; ++cc)
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) Q.q[rr][cc] = zero<A>();
+  for (int r = threadIdx.x; r < s; r += blockDim.x) S.rho[r] = Sr[r];
+  __syncthreads();
+  double sres = 0.0;
+  for (int c = 0; c < khat; ++c) {
+    A a[RL];
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) {
+      const int r = lane + 64 * rr;
+      a[rr] = r < s ? S.SAW[(int64_t)c * S.ldsaw + r] : zero<A>();
+    }
+    bool loss = false;
+    const double na =
+        regq_append<A, RL, CW>(Q, a, S.Q, S.R + (int64_t)c * S.ldr, lds_red, s, c, rank_rtol, &loss);
+    if (threadIdx.x == 0) {
+      A d = zero<A>();
+      *(double*)&d = na;
+      S.R[(int64_t)c * S.ldr + c] = d;
+    }
+    sres = regq_residual<A, RL>(a, S.rho, S.z + c, loss, s, &sh_res);
+  }
+  if (threadIdx.x == 0) S.sres_hist[0] = sres;
+}
+
+// register shapes: rows per lane RL and columns per wave CW
+template <class A>
+static bool lsq_reg_shape(int s, int lmax, int* rl, int* cw) {
+  const int need_rl = (s + 63) / 64;
+  const int need_cw = (lmax + kRegWaves - 1) / kRegWaves;
+  if (sizeof(A) == 8) {
+    if (need_rl <= 2 && need_cw <= 8) { *rl = 2; *cw = 8; return true; }
+    if (need_rl <= 2 && need_cw <= 16) { *rl = 2; *cw = 16; return true; }
+    if (need_rl <= 4 && need_cw <= 16) { *rl = 4; *cw = 16; return true; }
+  } else {
+    if (need_rl <= 2 && need_cw <= 8) { *rl = 2; *cw = 8; return true; }
+    if (need_rl <= 4 && need_cw <= 8) { *rl = 4; *cw = 8; return true; }
+  }
+  return false;
+}
+
 template <class A>
 __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, int khat, int m,
                                                         int t, int s, const A* __restrict__ red,
@@ -450,9 +739,22 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, in
   }
 }
 
+#define SDR_LSQ_REG_CASE(RL, CW, KER, ...)                                                  \
+  if (rl == RL && cw == CW) {                                                               \
+    hipLaunchKernelGGL((KER<A, RL, CW>), dim3(1), dim3(kLsqBlock), 0, st, __VA_ARGS__);     \
+    return;                                                                                 \
+  }
+
 template <class A>
 void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int t, int s,
                      const A* red, double brtol, double rank_rtol) {
+  int rl = 0, cw = 0;
+  if (lsq_reg_shape<A>(s, khat + m + 1, &rl, &cw)) {
+    SDR_LSQ_REG_CASE(2, 8, k_lsq_step_reg, S, j, khat, m, t, s, red, brtol, rank_rtol)
+    SDR_LSQ_REG_CASE(2, 16, k_lsq_step_reg, S, j, khat, m, t, s, red, brtol, rank_rtol)
+    SDR_LSQ_REG_CASE(4, 16, k_lsq_step_reg, S, j, khat, m, t, s, red, brtol, rank_rtol)
+    SDR_LSQ_REG_CASE(4, 8, k_lsq_step_reg, S, j, khat, m, t, s, red, brtol, rank_rtol)
+  }
   const int lmax = khat + m + 1;
   const size_t lds = (size_t)(2 * s + 2 * lmax + lsq_chunk<A>(s, lmax) * s) * sizeof(A);
   hipLaunchKernelGGL(k_lsq_step<A>, dim3(1), dim3(kLsqBlock), lds, st, S, j, khat, m, t, s, red,
@@ -483,7 +785,16 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_init(LsqState<A> S, int khat,
 }
 
 template <class A>
-void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr, double rank_rtol) {
+void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr, double rank_rtol,
+                     int m) {
+  int rl = 0, cw = 0;
+  // the same register shape as the step kernel of this cycle
+  if (lsq_reg_shape<A>(s, khat + m + 1, &rl, &cw)) {
+    SDR_LSQ_REG_CASE(2, 8, k_lsq_init_reg, S, khat, s, Sr, rank_rtol)
+    SDR_LSQ_REG_CASE(2, 16, k_lsq_init_reg, S, khat, s, Sr, rank_rtol)
+    SDR_LSQ_REG_CASE(4, 16, k_lsq_init_reg, S, khat, s, Sr, rank_rtol)
+    SDR_LSQ_REG_CASE(4, 8, k_lsq_init_reg, S, khat, s, Sr, rank_rtol)
+  }
   const int lmax = khat + 1;
   const size_t lds = (size_t)(2 * s + 2 * lmax + lsq_chunk<A>(s, lmax) * s) * sizeof(A);
   hipLaunchKernelGGL(k_lsq_init<A>, dim3(1), dim3(kLsqBlock), lds, st, S, khat, s, Sr, rank_rtol);
@@ -812,11 +1123,12 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
 // ---------------------------------------------------- instantiations ---
 #define SDR_INST_BASIS(T)                                                                        \
   template void launch_spmv_dots<T>(hipStream_t, int, const int*, const int*, const T*, const T*, \
-                                    T*, Window<T>, int, traits<T>::acc*, int, const Ctrl*);        \
+                                    T*, Window<T>, int, traits<T>::acc*, int, const Ctrl*,         \
+                                    hipEvent_t, hipEvent_t);                                       \
   template void launch_update_sketch<T>(hipStream_t, int, T*, Window<T>, int,                     \
                                         const traits<T>::acc*, int, const traits<T>::acc*, int,   \
                                         double*, int, int, SketchSpec, traits<T>::acc*, int,      \
-                                        const Ctrl*);                                             \
+                                        const Ctrl*, hipEvent_t, hipEvent_t);                     \
   template void launch_sketch_cols<T>(hipStream_t, int, const T*, int64_t, int, SketchSpec,       \
                                       traits<T>::acc*, int);                                      \
   template void launch_gemv_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
@@ -840,7 +1152,7 @@ SDR_INST_BASIS(cx<float>)
   template void launch_reduce2<A>(hipStream_t, const A*, int, int, int, double, const A*, int,  \
                                   int, A*, const Ctrl*);                                        \
   template void launch_init_v0<A>(hipStream_t, const A*, int, A*, double*);                     \
-  template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double);       \
+  template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double, int);  \
   template void launch_backsolve<A>(hipStream_t, LsqState<A>, int, int, A*);                    \
   template void launch_spmv_residual<A>(hipStream_t, int, const int*, const int*, const A*,     \
                                         const A*, const A*, A*, A*, int);                      \

@@ -141,7 +141,9 @@ class Solver final : public SolverBase {
     const size_t N = (size_t)n_;
     try {
       if (!kSame) valB_ = dalloc<T>((size_t)mat.nnz);
-      P_ = dalloc<T>(N * (m + 1));
+      Pbuf_[0] = dalloc<T>(N * (m + 1));
+      Pbuf_[1] = dalloc<T>(N * (m + 1));
+      P_ = Pbuf_[0];
       U_ = dalloc<T>(N * kmax_);
       Unew_ = dalloc<T>(N * kmax_);
       SU_ = dalloc<A>((size_t)s * kmax_);
@@ -150,14 +152,18 @@ class Solver final : public SolverBase {
       R_ = dalloc<A>((size_t)lmax_ * lmax_);
       z_ = dalloc<A>(lmax_);
       rho_ = dalloc<A>(s);
-      SB_ = dalloc<A>((size_t)s * (lmax_ + 1));
-      SAW_ = dalloc<A>((size_t)s * lmax_);
+      for (int b = 0; b < 2; ++b) {
+        SBbuf_[b] = dalloc<A>((size_t)s * (lmax_ + 1));
+        SAWbuf_[b] = dalloc<A>((size_t)s * lmax_);
+      }
+      SB_ = SBbuf_[0];
+      SAW_ = SAWbuf_[0];
       H_ = dalloc<A>((size_t)(m + 1) * m);
       nu_ = dalloc<double>(m + 2);
       sres_hist_ = dalloc<double>(m + 2);
       ctrl_ = dalloc<Ctrl>(1);
       ctrl_free_ = dalloc<Ctrl>(1);
-      nslot_ = opt.lookahead + 2;
+      nslot_ = m + 2;  // one partial slot per step: the least squares may lag a whole cycle
       slot1_ = (size_t)(kMaxWindow + 1) * nb1_;
       slot2_ = (size_t)(s + 1) * nb2_;
       slotr_ = (size_t)(s + 1 + kMaxWindow + 1);
@@ -167,6 +173,7 @@ class Solver final : public SolverBase {
       psk_ = dalloc<A>((size_t)(8 * s + 8 + 1) * nb2_);
       red2_ = dalloc<A>(8 * s + 8 + 1);
       HIPCHK(hipStreamCreateWithFlags(&streamB_, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&ev_copy_, hipEventDisableTiming));
       evs_.assign(nslot_ + 1, nullptr);
       for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       red3_ = dalloc<A>(4);
@@ -179,7 +186,7 @@ class Solver final : public SolverBase {
       Gs_ = dalloc<A>((size_t)lmax_ * kmax_);
       C_ = dalloc<A>((size_t)lmax_ * lmax_);
       if (opt.kernel_timing) {
-        ev_.assign(m + 2, std::array<hipEvent_t, 3>{});
+        ev_.assign(m + 2, std::array<hipEvent_t, 4>{});
         for (auto& a : ev_)
           for (auto& e : a) HIPCHK(hipEventCreate(&e));
       }
@@ -274,9 +281,10 @@ class Solver final : public SolverBase {
     S.ldr = lmax_;
     S.z = z_;
     S.rho = rho_;
-    S.SB = SB_;
+    // recycled columns right-aligned before column kmax: SV(:, i) sits at kmax + i
+    S.SB = SB_ + (size_t)(kmax_ - khat_) * s_;
     S.ldsb = s_;
-    S.SAW = SAW_;
+    S.SAW = SAW_ + (size_t)(kmax_ - khat_) * s_;
     S.ldsaw = s_;
     S.H = H_;
     S.ldh = m_ + 1;
@@ -287,7 +295,9 @@ class Solver final : public SolverBase {
     return S;
   }
 
-  void enqueue_step(int j, const T* vals) {
+  // Arnoldi part of step j on stream A (SpMV + window products, update + norm
+  // + sketch), then an event for the least-squares part.
+  void enqueue_step_a(int j, const T* vals) {
     const int i0 = std::max(j - t_, 0);
     const int tw = j - i0;
     const int sl = j % nslot_, slp = (j - 1) % nslot_;
@@ -299,20 +309,23 @@ class Solver final : public SolverBase {
     A* p2 = part2_ + slot2_ * sl;
     const A* p2prev = j >= 2 ? part2_ + slot2_ * slp : nullptr;
     const bool tm = opt_.kernel_timing;
-    // stream A: the Arnoldi chain
-    if (tm) HIPCHK(hipEventRecord(ev_[j][0], stream_));
-    launch_spmv_dots<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, p1, nb1_, ctrl_);
-    if (tm) HIPCHK(hipEventRecord(ev_[j][1], stream_));
+    launch_spmv_dots<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, p1, nb1_, ctrl_,
+                        tm ? ev_[j][0] : nullptr, tm ? ev_[j][1] : nullptr);
     launch_update_sketch<T>(stream_, n_, w, win, tw, p1, nb1_, p2prev, nb2_, nu_, i0, j - 1, sk_, p2,
-                            nb2_, ctrl_);
-    if (tm) HIPCHK(hipEventRecord(ev_[j][2], stream_));
+                            nb2_, ctrl_, tm ? ev_[j][2] : nullptr, tm ? ev_[j][3] : nullptr);
     LAUNCHCHK();
-    // stream B: the sketched least squares of step j
     HIPCHK(hipEventRecord(evs_[sl], stream_));
+  }
+
+  // Least-squares part of step j on stream B, behind step j's event.
+  void enqueue_step_b(int j) {
+    const int i0 = std::max(j - t_, 0);
+    const int tw = j - i0;
+    const int sl = j % nslot_;
     HIPCHK(hipStreamWaitEvent(streamB_, evs_[sl], 0));
     A* rd = redb_ + slotr_ * sl;
-    launch_reduce2<A>(streamB_, p2, nb2_, s_ + 1, s_, 1.0 / std::sqrt((double)sk_.zeta), p1, nb1_,
-                      tw + 1, rd, ctrl_);
+    launch_reduce2<A>(streamB_, part2_ + slot2_ * sl, nb2_, s_ + 1, s_,
+                      1.0 / std::sqrt((double)sk_.zeta), part1_ + slot1_ * sl, nb1_, tw + 1, rd, ctrl_);
     launch_lsq_step<A>(streamB_, lsq(), j, khat_, m_, t_, s_, rd, brtol_, opt_.rank_rtol);
     LAUNCHCHK();
   }
@@ -428,11 +441,14 @@ class Solver final : public SolverBase {
     bool converged = rn <= tol_abs;
     double last_sres = 0.0;
     int status = SDR_NOT_CONVERGED;
+    pend_.active = false;
     while (!converged && cycles < opt_.max_cycles) {
       if (!opt_.persist_safety) safety = opt_.safety0;
       sdr_cycle_record rec{};
-      khat_prev_ = khat_;
-      // --- cycle start: S r0, p_0 = r0, nu_0, SV(:,0), recycled columns ---
+      // --- cycle start on stream A: S r0, p_0 = r0, nu_0, SV(:, 0) ---
+      P_ = Pbuf_[cur_];
+      SB_ = SBbuf_[cur_];
+      SAW_ = SAWbuf_[cur_];
       sketch_cols<A>(r_, 1, Sr_, s_, nullptr);
       sketches++;
       ips++;
@@ -440,25 +456,47 @@ class Solver final : public SolverBase {
       launch_sketch_cols<T>(stream_, n_, P_, (int64_t)n_, 1, sk_, psk_, nb2_);
       launch_reduce_cols<A>(stream_, psk_, nb2_, s_ + 1, s_, 1.0 / std::sqrt((double)sk_.zeta), red2_,
                             nullptr);
-      launch_init_v0<A>(stream_, red2_, s_, SB_ + (size_t)khat_ * s_, nu_);
-      LAUNCHCHK();
-      if (khat_ > 0) {
-        HIPCHK(hipMemcpyAsync(SB_, SU_, sizeof(A) * s_ * khat_, hipMemcpyDeviceToDevice, stream_));
-        HIPCHK(hipMemcpyAsync(SAW_, SAU_, sizeof(A) * s_ * khat_, hipMemcpyDeviceToDevice, stream_));
-      }
+      launch_init_v0<A>(stream_, red2_, s_, SB_ + (size_t)kmax_ * s_, nu_);
+      last_sv_ = SB_ + (size_t)kmax_ * s_;
       for (int j = 0; j <= m_ + 1; ++j) __atomic_store_n(&rec_host_[j].seq, -1, __ATOMIC_RELEASE);
       launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
       LAUNCHCHK();
+      int enqA = 0, enqB = 0;
+      // stream B starts after the cycle-start work (S r0, SV(:, 0))
       HIPCHK(hipEventRecord(evs_[nslot_], stream_));
       HIPCHK(hipStreamWaitEvent(streamB_, evs_[nslot_], 0));
-      launch_lsq_init<A>(streamB_, lsq(), khat_, s_, Sr_, opt_.rank_rtol);
+      if (pend_.active) {
+        // The Arnoldi basis of this cycle does not depend on the recycle space
+        // (V spans K_m(A, r0)): queue its steps now and run the previous
+        // cycle's eigen-step on the host meanwhile.
+        for (int j = 1; j <= m_; ++j) enqueue_step_a(j, vals);
+        enqA = m_;
+        const double te = now();
+        finish_recycle(trace);
+        eig_time += now() - te;
+      }
+      if (khat_ > 0) {
+        HIPCHK(hipMemcpyAsync(SB_ + (size_t)(kmax_ - khat_) * s_, SU_, sizeof(A) * s_ * khat_,
+                              hipMemcpyDeviceToDevice, streamB_));
+        HIPCHK(hipMemcpyAsync(SAW_ + (size_t)(kmax_ - khat_) * s_, SAU_, sizeof(A) * s_ * khat_,
+                              hipMemcpyDeviceToDevice, streamB_));
+      }
+      launch_lsq_init<A>(streamB_, lsq(), khat_, s_, Sr_, opt_.rank_rtol, m_);
       LAUNCHCHK();
       // --- truncated Arnoldi with sketched least squares ---
-      int enq = 0, done = 0, jstop = 0, flags_stop = 0;
+      int done = 0, jstop = 0, flags_stop = 0;
       double res = 0.0, sres = 0.0;
       bool cyc_conv = false;
       for (;;) {
-        while (enq < m_ && enq - done < opt_.lookahead) enqueue_step(++enq, vals);
+        const int upto = std::min(m_, done + opt_.lookahead);
+        while (enqB < upto) {
+          const int j = ++enqB;
+          if (j > enqA) {
+            enqueue_step_a(j, vals);
+            enqA = j;
+          }
+          enqueue_step_b(j);
+        }
         StepRec rc;
         if (!wait_record(done + 1, rc)) {
           set_err("step record missing");
@@ -497,9 +535,10 @@ class Solver final : public SolverBase {
             jstop = done;
             break;
           }
+          // resume: the steps after `done` may have been skipped by the halt
           launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
           LAUNCHCHK();
-          enq = done;
+          enqA = enqB = done;
         }
       }
       cycles++;
@@ -509,8 +548,8 @@ class Solver final : public SolverBase {
         for (int j = 1; j <= jstop; ++j) {
           float a = 0.f, b2 = 0.f, c = 0.f;
           HIPCHK(hipEventElapsedTime(&a, ev_[j][0], ev_[j][1]));
-          HIPCHK(hipEventElapsedTime(&b2, ev_[j][1], ev_[j][2]));
-          HIPCHK(hipEventElapsedTime(&c, ev_[j][0], ev_[j][2]));
+          HIPCHK(hipEventElapsedTime(&b2, ev_[j][2], ev_[j][3]));
+          HIPCHK(hipEventElapsedTime(&c, ev_[j][0], ev_[j][3]));
           kt_ms_[0] += a;
           kt_ms_[1] += b2;
           kt_ms_[2] += c;
@@ -526,20 +565,22 @@ class Solver final : public SolverBase {
       LAUNCHCHK();
       std::swap(r_, rnew_);
       rn = res;
-      // --- sketched harmonic-Ritz update of U, SU, SAU (always) ---
-      const double te = now();
-      int ell = 0;
-      const int keff = update_recycle(jstop, &ell);
-      eig_time += now() - te;
       rec.j_stop = jstop;
-      rec.ell = ell;
-      rec.k_eff = keff;
       rec.flags = (cyc_conv ? 1 : 0) | flags_stop;
       rec.sres = sres;
       rec.res = res;
       trace->push_back(rec);
       converged = cyc_conv;
-      if (flags_stop && !cyc_conv && jstop == 1) break;
+      // --- sketched harmonic-Ritz update of U, SU, SAU (always) ---
+      begin_recycle(jstop, (int)trace->size() - 1);
+      cur_ ^= 1;
+      const bool more = !converged && cycles < opt_.max_cycles && !(flags_stop && jstop == 1);
+      if (!more) {
+        const double te = now();
+        finish_recycle(trace);
+        eig_time += now() - te;
+        break;
+      }
     }
     sync_both();
     status = converged ? SDR_OK : SDR_NOT_CONVERGED;
@@ -548,54 +589,74 @@ class Solver final : public SolverBase {
     return status;
   }
 
-  // Returns k_eff; R, C = Q^H SB to the host, G back, then the products.
-  int update_recycle(int j, int* ell) {
-    const int l0 = khat_ + j;
-    *ell = 0;
-    if (k_ == 0 || l0 == 0) {
-      khat_ = 0;
-      return 0;
-    }
-    launch_small_gemm<A>(stream_, true, l0, l0, s_, Q_, s_, SB_, s_, C_, l0);
+  // End of a cycle: C = Q^H [SU, SV] on the device and the small factors to
+  // pinned host memory; the eigen-step itself runs in finish_recycle.
+  void begin_recycle(int j, int trace_idx) {
+    pend_ = Pending{};
+    pend_.active = true;
+    pend_.j = j;
+    pend_.khat = khat_;
+    pend_.l0 = khat_ + j;
+    pend_.trace_idx = trace_idx;
+    pend_.P = P_;
+    pend_.SB = SB_ + (size_t)(kmax_ - khat_) * s_;
+    pend_.SAW = SAW_ + (size_t)(kmax_ - khat_) * s_;
+    const int l0 = pend_.l0;
+    if (k_ == 0 || l0 == 0) return;
+    launch_small_gemm<A>(stream_, true, l0, l0, s_, Q_, s_, pend_.SB, s_, C_, l0);
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(hR_, R_, sizeof(A) * (size_t)lmax_ * l0, hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipMemcpyAsync(hC_, C_, sizeof(A) * (size_t)l0 * l0, hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipMemcpyAsync(hnu_, nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream_));
-    HIPCHK(hipStreamSynchronize(stream_));
-    std::vector<std::complex<double>> Rc((size_t)l0 * l0), Cc((size_t)l0 * l0), G;
-    for (int c = 0; c < l0; ++c)
-      for (int i = 0; i < l0; ++i) {
-        Rc[(size_t)c * l0 + i] = i <= c ? to_cd(hR_[(size_t)c * lmax_ + i]) : std::complex<double>(0.0);
-        Cc[(size_t)c * l0 + i] = to_cd(hC_[(size_t)c * l0 + i]);
+    HIPCHK(hipEventRecord(ev_copy_, stream_));
+  }
+
+  // Host eigen-step of the pending cycle, then U = [U P] G (stream A) and
+  // SU = [SU SV] G, SAU = [SAU SAV] G.  Updates khat_ and the trace record.
+  void finish_recycle(std::vector<sdr_cycle_record>* trace) {
+    if (!pend_.active) return;
+    pend_.active = false;
+    const int l0 = pend_.l0, khat = pend_.khat;
+    int ell = 0, keff = 0;
+    if (k_ > 0 && l0 > 0) {
+      HIPCHK(hipEventSynchronize(ev_copy_));
+      std::vector<std::complex<double>> Rc((size_t)l0 * l0), Cc((size_t)l0 * l0), G;
+      for (int c = 0; c < l0; ++c)
+        for (int i = 0; i < l0; ++i) {
+          Rc[(size_t)c * l0 + i] =
+              i <= c ? to_cd(hR_[(size_t)c * lmax_ + i]) : std::complex<double>(0.0);
+          Cc[(size_t)c * l0 + i] = to_cd(hC_[(size_t)c * l0 + i]);
+        }
+      keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s_, k_, !traits<T>::cpx, G, &ell);
+      if (keff < 0) {
+        set_err("Schur iteration did not converge");
+        throw HipError{SDR_EDEVICE};
       }
-    const int keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s_, k_, !traits<T>::cpx, G, ell);
-    if (keff < 0) {
-      set_err("Schur iteration did not converge");
-      throw HipError{SDR_EDEVICE};
-    }
-    if (keff == 0) {
-      khat_ = 0;
-      return 0;
-    }
-    A* Gh = hG_;
-    A* Gp = hG_ + (size_t)l0 * keff;
-    for (int c = 0; c < keff; ++c)
-      for (int i = 0; i < l0; ++i) {
-        const A g = from_cd<A>(G[(size_t)c * l0 + i]);
-        Gh[(size_t)c * l0 + i] = g;
-        Gp[(size_t)c * l0 + i] = i < khat_ ? g : scale(g, 1.0 / hnu_[i - khat_]);
+      if (keff > 0) {
+        A* Gh = hG_;
+        A* Gp = hG_ + (size_t)l0 * keff;
+        for (int c = 0; c < keff; ++c)
+          for (int i = 0; i < l0; ++i) {
+            const A g = from_cd<A>(G[(size_t)c * l0 + i]);
+            Gh[(size_t)c * l0 + i] = g;
+            Gp[(size_t)c * l0 + i] = i < khat ? g : scale(g, 1.0 / hnu_[i - khat]);
+          }
+        // small products on stream B (they feed this cycle's least squares),
+        // the N x keff product on stream A (it feeds the first residual check)
+        HIPCHK(hipMemcpyAsync(Gs_, Gh, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, streamB_));
+        launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SB, s_, Gs_, l0, SU_, s_);
+        launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SAW, s_, Gs_, l0, SAU_, s_);
+        HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
+        launch_gemm_basis<T>(stream_, n_, U_, n_, khat, pend_.P, n_, pend_.j, G_, keff, Unew_, n_);
+        LAUNCHCHK();
+        std::swap(U_, Unew_);
       }
-    HIPCHK(hipMemcpyAsync(Gs_, Gh, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
-    HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
-    launch_gemm_basis<T>(stream_, n_, U_, n_, khat_, P_, n_, j, G_, keff, Unew_, n_);
-    // SU <- [SU SV] G, SAU <- [SAU SAV] G (the old SU/SAU sit in SB/SAW)
-    launch_small_gemm<A>(stream_, false, s_, keff, l0, SB_, s_, Gs_, l0, SU_, s_);
-    launch_small_gemm<A>(stream_, false, s_, keff, l0, SAW_, s_, Gs_, l0, SAU_, s_);
-    LAUNCHCHK();
-    std::swap(U_, Unew_);
+    }
     khat_ = keff;
-    HIPCHK(hipStreamSynchronize(stream_));
-    return keff;
+    if (trace && pend_.trace_idx >= 0 && pend_.trace_idx < (int)trace->size()) {
+      (*trace)[pend_.trace_idx].ell = ell;
+      (*trace)[pend_.trace_idx].k_eff = keff;
+    }
   }
 
   void fill_stats(sdr_stats* st, int cycles, int iters, int mv, int ip, int sk, int ch, int status,
@@ -644,22 +705,23 @@ class Solver final : public SolverBase {
     if (V)
       for (int c = 0; c < ncols; ++c) {
         const double sc = nuh[c] > 0.0 ? 1.0 / nuh[c] : 0.0;
-        launch_widen_scale<T>(stream_, n_, P_ + (size_t)c * n_, sc, static_cast<A*>(V) + (size_t)c * n_);
+        launch_widen_scale<T>(stream_, n_, Pbuf_[cur_ ^ 1] + (size_t)c * n_, sc,
+                              static_cast<A*>(V) + (size_t)c * n_);
         LAUNCHCHK();
       }
     if (Hh)
       HIPCHK(hipMemcpyAsync(Hh, H_, sizeof(A) * (m_ + 1) * m_, hipMemcpyDeviceToHost, stream_));
-    if (SVh && ncols > 0)
-      HIPCHK(hipMemcpyAsync(SVh, SB_ + (size_t)khat_prev_ * s_, sizeof(A) * s_ * ncols,
-                            hipMemcpyDeviceToHost, stream_));
+    if (SVh && ncols > 0 && last_sv_)
+      HIPCHK(hipMemcpyAsync(SVh, last_sv_, sizeof(A) * s_ * ncols, hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipStreamSynchronize(stream_));
     return SDR_OK;
   }
 
  private:
   void release() {
-    for (void* p : {(void*)valB_, (void*)P_, (void*)U_, (void*)Unew_, (void*)SU_, (void*)SAU_,
-                    (void*)Q_, (void*)R_, (void*)z_, (void*)rho_, (void*)SB_, (void*)SAW_, (void*)H_,
+    for (void* p : {(void*)valB_, (void*)Pbuf_[0], (void*)Pbuf_[1], (void*)U_, (void*)Unew_, (void*)SU_,
+                    (void*)SAU_, (void*)Q_, (void*)R_, (void*)z_, (void*)rho_, (void*)SBbuf_[0],
+                    (void*)SBbuf_[1], (void*)SAWbuf_[0], (void*)SAWbuf_[1], (void*)H_,
                     (void*)nu_, (void*)sres_hist_, (void*)ctrl_, (void*)ctrl_free_, (void*)part1_,
                     (void*)part2_, (void*)redb_, (void*)psk_, (void*)red2_, (void*)red3_, (void*)Sr_,
                     (void*)ycoef_, (void*)xt_, (void*)r_, (void*)rnew_, (void*)G_, (void*)Gs_,
@@ -679,6 +741,8 @@ class Solver final : public SolverBase {
     for (auto& e : evs_)
       if (e) (void)hipEventDestroy(e);
     evs_.clear();
+    if (ev_copy_) (void)hipEventDestroy(ev_copy_);
+    ev_copy_ = nullptr;
     if (streamB_) (void)hipStreamDestroy(streamB_);
     streamB_ = nullptr;
   }
@@ -694,6 +758,20 @@ class Solver final : public SolverBase {
   bool sau_stale_ = false, low_dirty_ = true;
   T* valB_ = nullptr;
   T *P_ = nullptr, *U_ = nullptr, *Unew_ = nullptr;
+  T* Pbuf_[2] = {nullptr, nullptr};
+  A* SBbuf_[2] = {nullptr, nullptr};
+  A* SAWbuf_[2] = {nullptr, nullptr};
+  int cur_ = 0;  // which of the double buffers the running cycle uses
+  // a finished cycle whose recycle update waits for the host eigen-step
+  struct Pending {
+    bool active = false;
+    int j = 0, l0 = 0, khat = 0, trace_idx = -1;
+    T* P = nullptr;
+    A* SB = nullptr;   // shifted so that column 0 is the first recycled column
+    A* SAW = nullptr;
+  } pend_;
+  hipEvent_t ev_copy_ = nullptr;
+  A* last_sv_ = nullptr;  // SV(:, 0) of the last cycle (basis inspection)
   A *SU_ = nullptr, *SAU_ = nullptr, *Q_ = nullptr, *R_ = nullptr, *z_ = nullptr, *rho_ = nullptr;
   A *SB_ = nullptr, *SAW_ = nullptr, *H_ = nullptr;
   double *nu_ = nullptr, *sres_hist_ = nullptr;
@@ -710,7 +788,7 @@ class Solver final : public SolverBase {
   // pinned host staging of the small dense data
   A *hR_ = nullptr, *hC_ = nullptr, *hz_ = nullptr, *hy_ = nullptr, *hG_ = nullptr, *hscal_ = nullptr;
   double* hnu_ = nullptr;
-  std::vector<std::array<hipEvent_t, 3>> ev_;
+  std::vector<std::array<hipEvent_t, 4>> ev_;
   double kt_ms_[3] = {0, 0, 0};
   int64_t kt_n_[3] = {0, 0, 0};
   int64_t kt_bytes_tw_[kMaxWindow + 1] = {0, 0, 0, 0, 0};

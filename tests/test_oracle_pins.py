@@ -79,7 +79,7 @@ def test_truncated_arnoldi_relation_and_band(cplx):
 def test_inner_product_count_is_t_plus_one_per_step():
     """Each truncated Arnoldi step costs min(j, t) window products and one
     norm: about t+1 inner products per matrix-vector product, the ratio seen in
-    the paper's tables for t = 2 (Section 5)."""
+    the tables of Section 6 for t = 2."""
     A = _small_cd(16)
     b = randn(A.shape[0], 2)
     for t in (1, 2, 3):
@@ -107,7 +107,7 @@ def test_sketch_of_Av_from_arnoldi_relation():
 
 
 def test_sketched_residual_nonincreasing_within_cycle():
-    """sres is minimised over nested spaces span([U, V(:,1:j)]) (eq. (3.3))."""
+    """sres is minimised over nested spaces span([U, V(:,1:j)]) (eq. (3.2))."""
     A = _small_cd(16)
     b = randn(A.shape[0], 3)
     res = sdr_solve(A, b, m=40, k=8, t=2, s=112, tol=1e-12, max_cycles=4)
@@ -278,7 +278,7 @@ def test_solution_matches_dense_lu(kind):
 
 def test_residual_chain_with_exact_epsilon():
     """||r|| <= ||r~|| <= ||S r~||/sqrt(1-eps) <= ||S r||/sqrt(1-eps)
-    <= sqrt((1+eps)/(1-eps)) ||r|| (eq. (3.4)) with eps the exact distortion
+    <= sqrt((1+eps)/(1-eps)) ||r|| (eq. (3.5)) with eps the exact distortion
     of S on span([r0, A W])."""
     A = _small_cd(16)
     N = A.shape[0]

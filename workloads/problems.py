@@ -12,7 +12,7 @@ fastest, every entry scaled by h^2):
 * ``helmholtz2d``  -Laplace(u) - kappa^2 (1 + 0.5i) u: diagonal
   4 - (kappa h)^2 (1+0.5i), neighbours -1 (complex128).
 * ``cd2d_central`` the convection-diffusion family of the paper's last
-  experiment (Section 5.3): (L (x) I + I (x) L) + alpha (D (x) I + I (x) D) with
+  experiment (Section 6.3): (L (x) I + I (x) L) + alpha (D (x) I + I (x) D) with
   L = (n+1)^2 tridiag(1,-2,1) and D = (n+1)/2 tridiag(-1,0,1).
 * ``theta_weighted`` scales every stored entry of a base matrix by theta_e.
 
@@ -122,7 +122,7 @@ def helmholtz2d(n: int, kappa: float = 20.0, damping: float = 0.5) -> CSR:
 
 
 def cd2d_central(n: int, alpha: float) -> CSR:
-    """Paper Section 5.3 operator (central differences, unscaled)."""
+    """Section 6.3 operator (central differences, unscaled)."""
     s2 = float(n + 1) ** 2
     s1 = (n + 1) / 2.0
     # L (x) I + I (x) L contributes s2*(-4) on the diagonal and s2 off-diagonal.
