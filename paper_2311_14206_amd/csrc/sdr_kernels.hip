@@ -8,8 +8,10 @@
 //   stream B (the sketched least squares, behind an event)
 //     k_reduce2        fixed-order reduction of both partial sets
 //     k_lsq_step       H column, SV and SAV columns, QR append, sketched residual
-// Basis vectors are stored unnormalised (p_i = nu_i v_i); the norms nu_i are
-// folded into the coefficients, which saves a normalisation pass per step.
+// Basis vectors are stored unnormalised: p_j is the orthogonalised vector
+// before its division by H(j+1, j), so nu_j = ||p_j|| = H(j+1, j) stays of the
+// order of ||A|| in every precision; the norms are folded into the
+// coefficients, which saves a normalisation pass per step.
 
 #include <hip/hip_ext.h>
 
@@ -163,6 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_update_sketch(
       c[q] = zero<A>();
     }
   }
+  // w' = (w - sum c_q p_q) / nu_{j-1}: the orthogonalised A v_{j-1}
+  const double inv_prev = 1.0 / (part2prev ? nprev : nu[jprev]);
   __syncthreads();
   A* mine = acc + (threadIdx.x >> 6) * s;
   double nrm = 0.0;
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_update_sketch(
 #pragma unroll
     for (int q = 0; q < kMaxWindow; ++q)
       if (q < tw) v -= c[q] * widen(win.p[q][r]);
-    const T vt = narrow<T>(v);
+    const T vt = narrow<T>(scale(v, inv_prev));
     w[r] = vt;
     const A va = widen(vt);
     nrm += abs2(va);
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step_reg(LsqState<A> S, int j
   if (tid == 0) {
     const double nuprev = S.nu[j - 1];
     const double nw = sqrt(re(dots[tw]));
-    const bool brk = !(nuj > brtol * nw);
+    const bool brk = !(nuj > brtol * nw / nuprev);  // H(j,j-1) vs ||A v_{j-1}||
     sh_break = brk;
     S.nu[j] = nuj;  // same reduction order as the update kernel's prologue
     for (int q = 0; q < tw; ++q) {
@@ -555,7 +559,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step_reg(LsqState<A> S, int j
       S.H[(int64_t)(j - 1) * S.ldh + i0 + q] = h;
     }
     A hs = zero<A>();
-    *(double*)&hs = brk ? 0.0 : nuj / nuprev;
+    *(double*)&hs = brk ? 0.0 : nuj;
     hcol[tw] = hs;
     S.H[(int64_t)(j - 1) * S.ldh + j] = hs;
   }
@@ -687,7 +691,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, in
   if (tid == 0) {
     const double nuprev = S.nu[j - 1];
     const double nw = sqrt(re(dots[tw]));
-    const bool brk = !(nuj > brtol * nw);
+    const bool brk = !(nuj > brtol * nw / nuprev);  // H(j,j-1) vs ||A v_{j-1}||
     sh_break = brk;
     // same reduction order as the update kernel's prologue: identical bits
     S.nu[j] = nuj;
@@ -697,7 +701,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, in
       S.H[(int64_t)(j - 1) * S.ldh + i0 + q] = h;
     }
     A hs = zero<A>();
-    *(double*)&hs = brk ? 0.0 : nuj / nuprev;
+    *(double*)&hs = brk ? 0.0 : nuj;
     hcol[tw] = hs;
     S.H[(int64_t)(j - 1) * S.ldh + j] = hs;
   }
@@ -993,18 +997,26 @@ void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, c
   using A = typename traits<T>::acc;
   const int nb = (n + kBlock - 1) / kBlock;
   const int l0 = ku + jp;
-  if (kc <= 8) {
-    hipLaunchKernelGGL((k_gemm_basis<T, 8>), dim3(nb), dim3(kBlock), (size_t)l0 * 8 * sizeof(A), st,
-                       n, U, ldu, ku, P, ldp, jp, G, kc, C, ldc);
-  } else if (kc <= 16) {
-    hipLaunchKernelGGL((k_gemm_basis<T, 16>), dim3(nb), dim3(kBlock), (size_t)l0 * 16 * sizeof(A),
-                       st, n, U, ldu, ku, P, ldp, jp, G, kc, C, ldc);
-  } else if (kc <= 24) {
-    hipLaunchKernelGGL((k_gemm_basis<T, 24>), dim3(nb), dim3(kBlock), (size_t)l0 * 24 * sizeof(A),
-                       st, n, U, ldu, ku, P, ldp, jp, G, kc, C, ldc);
-  } else {
-    hipLaunchKernelGGL((k_gemm_basis<T, 32>), dim3(nb), dim3(kBlock), (size_t)l0 * 32 * sizeof(A),
-                       st, n, U, ldu, ku, P, ldp, jp, G, kc, C, ldc);
+  // output columns in chunks whose staged G fits in 48 KB of LDS
+  int km = 32;
+  while (km > 8 && (size_t)l0 * km * sizeof(A) > 48 * 1024) km /= 2;
+  for (int c0 = 0; c0 < kc; c0 += km) {
+    const int cc = kc - c0 < km ? kc - c0 : km;
+    const A* Gc = G + (int64_t)c0 * l0;
+    T* Cc = C + (int64_t)c0 * ldc;
+    if (cc <= 8) {
+      hipLaunchKernelGGL((k_gemm_basis<T, 8>), dim3(nb), dim3(kBlock), (size_t)l0 * 8 * sizeof(A), st,
+                         n, U, ldu, ku, P, ldp, jp, Gc, cc, Cc, ldc);
+    } else if (cc <= 16) {
+      hipLaunchKernelGGL((k_gemm_basis<T, 16>), dim3(nb), dim3(kBlock), (size_t)l0 * 16 * sizeof(A),
+                         st, n, U, ldu, ku, P, ldp, jp, Gc, cc, Cc, ldc);
+    } else if (cc <= 24) {
+      hipLaunchKernelGGL((k_gemm_basis<T, 24>), dim3(nb), dim3(kBlock), (size_t)l0 * 24 * sizeof(A),
+                         st, n, U, ldu, ku, P, ldp, jp, Gc, cc, Cc, ldc);
+    } else {
+      hipLaunchKernelGGL((k_gemm_basis<T, 32>), dim3(nb), dim3(kBlock), (size_t)l0 * 32 * sizeof(A),
+                         st, n, U, ldu, ku, P, ldp, jp, Gc, cc, Cc, ldc);
+    }
   }
 }
 

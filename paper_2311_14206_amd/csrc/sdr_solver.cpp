@@ -452,7 +452,7 @@ class Solver final : public SolverBase {
       sketch_cols<A>(r_, 1, Sr_, s_, nullptr);
       sketches++;
       ips++;
-      launch_cast_scale<T>(stream_, n_, r_, 1.0, P_);
+      launch_cast_scale<T>(stream_, n_, r_, rn > 0.0 ? 1.0 / rn : 1.0, P_);  // p_0 = r0 / ||r0||
       launch_sketch_cols<T>(stream_, n_, P_, (int64_t)n_, 1, sk_, psk_, nb2_);
       launch_reduce_cols<A>(stream_, psk_, nb2_, s_ + 1, s_, 1.0 / std::sqrt((double)sk_.zeta), red2_,
                             nullptr);

@@ -1,0 +1,181 @@
+"""Full-size workloads on the GPU.
+
+At these sizes the oracle runs one cycle in seconds, so each workload checks
+its first cycle against the oracle (the same decisions, the same residual to
+1e-8 relative, the same x to 1e-8) and checks the complete solves through
+properties that hold at any size: the FP64 residual recomputed on the host
+meets the tolerance, and for the differentiated solve the loss and gradient
+match a sparse direct solve and a central difference.  Timings are printed for
+the record.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from oracle import sdr_solve
+from workloads import workload, sequence_system, edge_weighted, randn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _solver(A, p, **opt):
+    from paper_2311_14206_amd.sdr import SDRSolver
+    print(f"[gpu] SDRSolver n={A.n} nnz={A.nnz} m={p['m']} k={p['k']} t={p['t']} s={p['s']} {opt}",
+          flush=True)
+    return SDRSolver(_dev(A.row_ptr), _dev(A.col_idx), _dev(A.values), m=p["m"], k=p["k"],
+                     t=p["t"], s=p["s"], seed=p["s_seed"], zeta=p["zeta"], **opt)
+
+
+def _relres(A, b, x):
+    return float(np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b))
+
+
+def _first_cycle_parity(A, b, p):
+    h = _solver(A, p, max_cycles=1)
+    x, st = h.solve(_dev(b), tol=p["tol"])
+    ref = sdr_solve(A.to_scipy(), b, m=p["m"], k=p["k"], t=p["t"], s=p["s"], zeta=p["zeta"],
+                    seed=p["s_seed"], tol=p["tol"], max_cycles=1)
+    tr = h.trace()
+    print("first cycle gpu", tr[0], "oracle", ref.trace[0].j_stop, ref.trace[0].res, flush=True)
+    assert tr[0]["j_stop"] == ref.trace[0].j_stop
+    assert tr[0]["n_checks"] == len(ref.trace[0].checks)
+    assert tr[0]["k_eff"] == ref.trace[0].k_eff
+    assert abs(tr[0]["res"] - ref.trace[0].res) <= 1e-8 * ref.trace[0].res
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(xg - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+    h.close()
+
+
+def test_cd3d_128_sequence_fp64_and_fp32_basis():
+    """20 slowly changing 3D systems A_i = A + diag(d_i), fresh b_i, recycle
+    space carried (exact variant); FP64 and FP32-basis runs."""
+    A0, _, p = workload("cd3d_128_seq")
+    A1, b1 = sequence_system(A0, p, 1)
+    _first_cycle_parity(A1, b1, p)
+    for precision in (0, 1):
+        h = _solver(A0, p, precision=precision)
+        t_total, iters = 0.0, []
+        for i in range(1, p["n_systems"] + 1):
+            Ai, bi = sequence_system(A0, p, i)
+            h.update_matrix(_dev(Ai.values))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = h.solve(_dev(bi), tol=p["tol"])
+            torch.cuda.synchronize()
+            t_total += time.perf_counter() - t0
+            iters.append(st["iters"])
+            assert st["converged"] and st["relres"] <= p["tol"], (i, st)
+        assert _relres(Ai, bi, x.cpu().numpy()) <= p["tol"]
+        print(f"cd3d_128 sequence precision={precision}: {p['n_systems'] / t_total:.3f} solves/s, "
+              f"iters per system {iters}", flush=True)
+        h.close()
+
+
+def test_helmholtz_1024_complex128_and_complex64_basis():
+    A, b, p = workload("helmholtz_1024")
+    _first_cycle_parity(A, b, p)
+    for precision in (0, 1):
+        h = _solver(A, p, precision=precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = h.solve(_dev(b), tol=p["tol"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert st["converged"], st
+        rr = _relres(A, b, x.cpu().numpy())
+        print(f"helmholtz_1024 precision={precision}: {dt:.3f} s, iters {st['iters']}, cycles "
+              f"{st['cycles']}, relres {rr:.2e}", flush=True)
+        assert rr <= p["tol"]
+        h.close()
+
+
+def test_cd2d_512_differentiated_solve():
+    """Loss ||x(theta) - x_t||^2 with theta-weighted grid edges: 50 gradient steps
+    (forward and adjoint GMRES-SDR, adjoint recycle space carried), then the
+    loss and gradient at the final theta against a sparse direct solve, and a
+    central difference along the gradient."""
+    from paper_2311_14206_amd.autograd import sdr_solve as solve_ad
+    A, b, p = workload("cd2d_512_theta")
+    A0, theta0 = p["A0"], p["theta"]
+    xt = randn(A.n, p["xt_seed"])
+    h = _solver(A, p)
+    rows = np.repeat(np.arange(A0.n), np.diff(A0.row_ptr))
+    on = rows == A0.col_idx
+    a0 = _dev(A0.values)
+    offm = _dev((~on).astype(np.float64))
+    rows_t = _dev(rows.astype(np.int64))
+    diag_pos = _dev(np.nonzero(on)[0].astype(np.int64))
+
+    def values_of(theta):
+        """The edge-weighted entries (workloads.edge_weighted) as a torch function of theta."""
+        off = theta * a0 * offm
+        shift = torch.zeros(A0.n, dtype=a0.dtype, device=a0.device).index_add(
+            0, rows_t, (a0 - theta * a0) * offm)
+        return off + (a0 * (1 - offm)) + torch.zeros_like(a0).index_add(0, diag_pos, shift)
+
+    np.testing.assert_allclose(values_of(_dev(theta0)).cpu().numpy(), A.values, rtol=1e-14, atol=1e-14)
+    th = _dev(theta0).requires_grad_(True)
+    bb, xtd = _dev(b), _dev(xt)
+    losses, adj = [], []
+    eta = None
+    t0 = time.perf_counter()
+    for step in range(p["gd_steps"]):
+        x = solve_ad(values_of(th), bb, h, 1e-10)
+        loss = torch.sum((x - xtd) ** 2)
+        loss.backward()
+        adj.append(h.last_adjoint_stats["iters"])
+        with torch.no_grad():
+            if eta is None:
+                eta = 1e-3 / float(th.grad.abs().max())
+            th -= eta * th.grad
+        th.grad = None
+        losses.append(float(loss))
+    dt = time.perf_counter() - t0
+    print(f"cd2d_512 differentiated: {dt / p['gd_steps']:.3f} s per gradient step, loss "
+          f"{losses[0]:.6e} -> {losses[-1]:.6e}, adjoint iters {adj[0]} ... {adj[-1]}", flush=True)
+    assert losses[-1] < losses[0]
+    # At the final theta: the loss and the gradient against a sparse direct
+    # solve (SuperLU factors of A(theta), solves with A and A^T), entry by
+    # entry on a sample and in norm, then the directional derivative along the
+    # reference gradient against central differences of GPU solves.
+    import scipy.sparse.linalg as spl
+    th_np = th.detach().cpu().numpy()
+    thr = _dev(th_np).requires_grad_(True)
+    x = solve_ad(values_of(thr), bb, h, 1e-12)
+    loss = torch.sum((x - xtd) ** 2)
+    loss.backward()
+    g = thr.grad.detach().cpu().numpy()
+    lu = spl.splu(edge_weighted(A0, th_np).to_scipy().tocsc())
+    xr = lu.solve(b)
+    lam = lu.solve(2.0 * (xr - xt), trans="T")
+    # d vals_e / d theta_e = a0_e at an edge (i, j) and -a0_e at the diagonal of row i
+    gr = np.where(on, 0.0, A0.values * (-lam[rows] * xr[A0.col_idx] + lam[rows] * xr[rows]))
+    Lr = float(np.sum((xr - xt) ** 2))
+    gerr = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    print(f"final theta: loss {float(loss):.9e} (direct {Lr:.9e}), gradient rel. error {gerr:.2e}",
+          flush=True)
+    assert abs(float(loss) - Lr) <= 1e-8 * Lr
+    assert gerr <= 1e-6
+    idx = np.random.default_rng(p["fd_seed"]).choice(np.nonzero(~on)[0], 16, replace=False)
+    assert np.all(np.abs(g[idx] - gr[idx]) <= 1e-6 * np.abs(gr).max()), (g[idx], gr[idx])
+    u = gr / np.linalg.norm(gr)
+
+    def loss_at(tv):
+        with torch.no_grad():
+            xx = solve_ad(values_of(_dev(tv)), bb, h, 1e-12)
+            return float(torch.sum((xx - xtd) ** 2))
+
+    eps = 1e-2
+    fd = (loss_at(th_np + eps * u) - loss_at(th_np - eps * u)) / (2 * eps)
+    print(f"directional derivative: fd {fd:.9e}, autograd {float(g @ u):.9e}", flush=True)
+    assert abs(fd - float(g @ u)) <= 1e-5 * abs(float(g @ u))
+    h.close()

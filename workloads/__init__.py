@@ -12,9 +12,11 @@ from .problems import (  # noqa: F401
     cd2d_central,
     helmholtz2d,
     theta_weighted,
+    edge_weighted,
     shifted_diagonal,
     randn,
     crandn,
     workload,
+    sequence_system,
     WORKLOADS,
 )

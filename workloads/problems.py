@@ -15,6 +15,9 @@ fastest, every entry scaled by h^2):
   experiment (Section 6.3): (L (x) I + I (x) L) + alpha (D (x) I + I (x) D) with
   L = (n+1)^2 tridiag(1,-2,1) and D = (n+1)/2 tridiag(-1,0,1).
 * ``theta_weighted`` scales every stored entry of a base matrix by theta_e.
+* ``edge_weighted``  weights the grid edges (off-diagonal entries) by theta_e
+  and sets each diagonal so that the row keeps the base matrix's row sum: a
+  weighted upwind operator that stays a nonsingular M-matrix.
 
 These are problem inputs only: nothing here belongs to the solver.
 """
@@ -140,6 +143,27 @@ def theta_weighted(base: CSR, theta: np.ndarray) -> CSR:
     return base.with_values(theta * base.values)
 
 
+def _diag_positions(base: CSR):
+    rows = np.repeat(np.arange(base.n), np.diff(base.row_ptr))
+    return rows, rows == base.col_idx
+
+
+def edge_weighted(base: CSR, theta: np.ndarray) -> CSR:
+    """Off-diagonal entries theta_e * a_e; diagonal a_ii + sum_j (1 - theta_ij) a_ij.
+
+    theta has one entry per stored entry; the diagonal ones are unused.
+    """
+    theta = np.asarray(theta, dtype=np.float64)
+    rows, on = _diag_positions(base)
+    off = ~on
+    vals = base.values.copy()
+    vals[off] = theta[off] * base.values[off]
+    shift = np.zeros(base.n, dtype=base.values.dtype)
+    np.add.at(shift, rows[off], (1.0 - theta[off]) * base.values[off])
+    vals[on] = base.values[on] + shift[rows[on]]
+    return base.with_values(vals)
+
+
 def shifted_diagonal(base: CSR, d: np.ndarray) -> CSR:
     """base + diag(d) on the same pattern (every row holds its diagonal)."""
     rows = np.repeat(np.arange(base.n), np.diff(base.row_ptr))
@@ -183,7 +207,7 @@ WORKLOADS = {
     # theta-weighted convection-diffusion 512^2 for the differentiated solve.
     "cd2d_512_theta": dict(kind="cd2d_upwind", n=512, m=100, k=20, t=2, s=240, zeta=8,
                            tol=1e-8, theta_seed=7, xt_seed=8, b_seed=9, fd_seed=10,
-                           gd_steps=50),
+                           gd_steps=50, s_seed=42),
 }
 
 
@@ -199,7 +223,7 @@ def workload(name: str, n: int | None = None):
             theta = 1.0 + 0.1 * randn(A.nnz, p["theta_seed"])
             p["theta"] = theta
             p["A0"] = A
-            A = theta_weighted(A, theta)
+            A = edge_weighted(A, theta)
         b = randn(A.n, p.get("b_seed", p.get("b_seed0", 1)))
     elif kind == "cd3d_upwind":
         A = cd3d_upwind(p["n"])
