@@ -100,7 +100,8 @@ typedef struct sdr_handle sdr_handle;
  *          complex-conjugate harmonic-Ritz pair is never split.
  *   t      truncation window (1 <= t <= min(m, 4)).
  *   s_dim  sketch rows; s_dim > m + k and s_dim % zeta == 0 (zeta = 8 by
- *          default, option "zeta").
+ *          default, option "zeta"); at most 2048 for real and 1024 for
+ *          complex matrices (per-wave sketch accumulators in LDS).
  *   seed   64-bit seed of the sketching operator.
  * The CSR arrays are copied.  Returns NULL on error (see sdr_last_error()).
  */
@@ -118,7 +119,11 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *   "variant"        0: exact sequences (recompute S A_i U), 1: inexact
  *   "breakdown_rtol" Arnoldi breakdown threshold (default 1e-14; 1e-6 FP32)
  *   "rank_rtol"      rank-loss threshold of the sketched LSQ (default 1e-12)
- *   "lookahead"      Arnoldi steps queued ahead of the host (default 4)
+ *   "lookahead"      Arnoldi steps whose least squares is queued ahead of the
+ *                    host's residual control (default 16)
+ *   "lsq_chunk"      Arnoldi steps per least-squares launch (default 8)
+ *   "kernel_timing"  n > 0: HIP events around the SpMV and update kernels of
+ *                    every n-th Arnoldi step (sdr_kernel_times); default 0
  * Returns 0 or SDR_EINVAL.
  */
 int sdr_set_option(sdr_handle* h, const char* key, double value);
@@ -186,10 +191,11 @@ int sdr_reset(sdr_handle* h);
 
 /*
  * Per-step kernel timings gathered with HIP events on the handle's stream
- * when the option "kernel_timing" is 1, accumulated since the last call and
- * then cleared.  ms[0]: SpMV + window products kernel, ms[1]: update + norm +
- * sketch kernel, ms[2]: whole Arnoldi step (both kernels, both reductions and
- * the least-squares kernel).  counts[0..2]: launches timed; counts[3 + tw]:
+ * when the option "kernel_timing" is n > 0 (every n-th step), accumulated since the last call and
+ * then cleared.  ms[0]: SpMV + window products + sketch kernel, ms[1]:
+ * orthogonalisation update kernel, ms[2]: both kernels of the step, from the
+ * start of the first to the end of the second (the least squares runs on a
+ * second stream).  counts[0..2]: launches timed; counts[3 + tw]:
  * steps whose truncation window held tw vectors (tw <= 4).  cap is the
  * length of both arrays (8 covers everything).
  */

@@ -34,7 +34,7 @@ def build(verbose: bool = True) -> str:
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        extra = ["-march=x86-64-v3"] if src == "dense.cpp" else []  # host-only code: AVX2/FMA
+        extra = ["-march=x86-64-v3", "-fcx-limited-range"] if src == "dense.cpp" else []  # host-only code: AVX2/FMA, inline complex products
         cmd = [hipcc, *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

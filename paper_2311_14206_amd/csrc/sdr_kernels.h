@@ -9,8 +9,11 @@ constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kWaves = kBlock / 64;
 constexpr int kLsqBlock = 512;     // threads of the single-block least-squares kernels
 constexpr int kMaxWindow = 4;      // largest truncation window t
-constexpr int kRowsSpmv = 1024;    // rows per block, SpMV + window dots
-constexpr int kRowsUpdate = 2048;  // rows per block, update + norm + sketch
+constexpr int kRowsSpmv = 1024;    // rows per block, SpMV + window products + sketch
+constexpr int kRowsUpdate = 2048;  // rows per block of the other streaming kernels
+constexpr int kUpdateRows = 4;     // rows per thread of the orthogonalisation update
+constexpr int kWaveTileNnz = 512;  // largest staged chunk (entries of 64 rows) per wave of the SpMV
+constexpr int kSpmvLds = 64 * 1024;  // LDS budget of the SpMV kernel: sketch bins + staged chunks
 
 template <class T> struct Window { const T* p[kMaxWindow]; };
 
@@ -48,22 +51,25 @@ template <class A> struct LsqState {
   StepRec* rec;       // host-mapped records, one per step
 };
 
-// w = A x, partial window products <p_q, w> and ||w||^2 per block.  With
-// events e0/e1 the dispatch records its own start and end (kernel timing).
+// w = A x (if spmv) with per-block partial sums in part (nb blocks of
+// kRowsSpmv rows), columns: S x (sk.s of them, unscaled sparse-sign sums) and
+// ||x||^2 when sk.s > 0, then <p_q, w> for the tw window vectors and ||w||^2.
+// With sk.s = 0 only the window products and ||w||^2 are written; with spmv
+// false only the sketch and ||x||^2 (w, win unused).  With events e0/e1 the
+// dispatch records its own start and end (kernel timing).
 template <class T>
-void launch_spmv_dots(hipStream_t st, int n, const int* rp, const int* ci, const T* val, const T* x,
-                      T* w, Window<T> win, int tw, typename traits<T>::acc* part, int nb,
-                      const Ctrl* ctrl, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_spmv_sketch(hipStream_t st, int n, const int* rp, const int* ci, const T* val, const T* x,
+                        T* w, Window<T> win, int tw, SketchSpec sk, bool spmv,
+                        typename traits<T>::acc* part, int nb, const Ctrl* ctrl,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
-// Prologue: d_q from the SpMV partials (part1, nb1) and, if part2prev is given,
-// nu[jprev] = ||p_jprev|| from the previous step's partials (column s).  Then
-// w <- w - sum_q (d_q / nu_{i0+q}^2) p_{i0+q}; partial ||w||^2 and S w per block.
+// Prologue: nu[jprev] = ||p_jprev|| and d_q from this step's SpMV partials
+// (part, nb1 blocks, sketch length s: columns s, s+1 .. s+tw).  Then
+// w <- (w - sum_q (d_q / nu_{i0+q}^2) p_{i0+q}) / nu[jprev] in place.
 template <class T>
-void launch_update_sketch(hipStream_t st, int n, T* w, Window<T> win, int tw,
-                          const typename traits<T>::acc* part1, int nb1,
-                          const typename traits<T>::acc* part2prev, int nb2prev, double* nu, int i0,
-                          int jprev, SketchSpec sk, typename traits<T>::acc* part, int nb,
-                          const Ctrl* ctrl, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_update(hipStream_t st, int n, T* w, Window<T> win, int tw,
+                   const typename traits<T>::acc* part, int nb1, int s, double* nu, int i0, int jprev,
+                   const Ctrl* ctrl, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // out = [reduced columns of pa (first nscaled scaled by scl), reduced columns of pb].
 template <class A>
@@ -81,10 +87,26 @@ void launch_reduce_cols(hipStream_t st, const A* part, int nb, int ncols, int ns
 
 // One Arnoldi step's small work: H column, SV column, SAV column, QR append,
 // projected residual and the halt decision.
-// red: [S p_j (s), ||p_j||^2, window products (tw), ||A p_{j-1}||^2].
+// red: [S p_j (s), ||p_j||^2, window products (tw), ||A p_{j-1}||^2]; the
+// first two come from step j+1's SpMV partials, the others from step j's.
 template <class A>
 void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int t, int s,
                      const A* red, double brtol, double rank_rtol);
+
+// Steps j0 .. j1 of the least squares, step j reading its reduced inputs at
+// redb + slotr * (j % nslot) (layout of launch_lsq_step's red).  One launch
+// with the QR factor held on chip where the register shape allows, else one
+// launch per step.  Stops after a step that raises the halt flag.
+template <class A>
+void launch_lsq_steps(hipStream_t st, LsqState<A> S, int j0, int j1, int khat, int m, int t, int s,
+                      const A* redb, int64_t slotr, int nslot, double brtol, double rank_rtol);
+
+// The reduced inputs of steps j0 .. j1 into their slots of redb (slot
+// j % nslot): [S p_j scaled by scl, ||p_j||^2] from the SpMV partial slot of
+// step j+1, then [<p_q, w> (tw), ||w||^2] from the slot of step j.
+template <class A>
+void launch_reduce_steps(hipStream_t st, const A* part1, int64_t slot1, int nb1, int s, int j0, int j1,
+                         int t, int nslot, double scl, A* redb, int64_t slotr, const Ctrl* ctrl);
 
 // Initialise the QR of SAW with its first khat columns (SAU) and rho = S r0.
 template <class A>

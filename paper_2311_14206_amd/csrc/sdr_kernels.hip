@@ -2,16 +2,20 @@
 //
 // Per Arnoldi step j (Algorithm 1, truncated Arnoldi with one sketch per step):
 //   stream A (the Arnoldi chain)
-//     k_spmv_dots      w = A p_{j-1}, partial window products <p_i, w> and ||w||^2
-//     k_update_sketch  reduces those partials and ||p_{j-1}||^2 in its prologue,
-//                      p_j = w - sum c_i p_i in place, partial ||p_j||^2 and S p_j
-//   stream B (the sketched least squares, behind an event)
-//     k_reduce2        fixed-order reduction of both partial sets
-//     k_lsq_step       H column, SV and SAV columns, QR append, sketched residual
-// Basis vectors are stored unnormalised: p_j is the orthogonalised vector
-// before its division by H(j+1, j), so nu_j = ||p_j|| = H(j+1, j) stays of the
-// order of ||A|| in every precision; the norms are folded into the
-// coefficients, which saves a normalisation pass per step.
+//     k_spmv_sketch  w = A p_{j-1}, partial window products <p_i, w>, ||w||^2,
+//                    and the sketch S p_{j-1} with ||p_{j-1}||^2: the SpMV reads
+//                    p_{j-1} anyway, so the one sketch per step costs no
+//                    extra pass over HBM
+//     k_update       reduces the window products and ||p_{j-1}||^2 in its
+//                    prologue, then p_j = (w - sum c_i p_i) / nu_{j-1} in place
+//   stream B (the sketched least squares, behind the event of step j+1's SpMV)
+//     k_reduce2      fixed-order reduction of S p_j, ||p_j||^2 (step j+1) and
+//                    the window products of step j
+//     k_lsq_step     H column, SV and SAV columns, QR append, sketched residual
+// Stored basis vectors are p_j = H(j+1, j) v_j: the orthogonalised A v_{j-1},
+// so nu_j = ||p_j|| = H(j+1, j) stays of the order of ||A|| in every
+// precision; the norms are folded into the coefficients, which saves a
+// normalisation pass per step.
 
 #include <hip/hip_ext.h>
 
@@ -20,12 +24,81 @@
 namespace sdr {
 
 // ------------------------------------------------------------ reductions --
+// Lane exchange within rows of 16 lanes by DPP (a VALU modifier, no LDS
+// round trip): CTRL 0xB1 / 0x4E swap neighbours / pairs inside each quad,
+// 0x124 / 0x128 rotate each row by 4 / 8 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active); the same value in every
+// lane and the same bits on every call.  Row sums by DPP, then the four rows.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x124>(v);
+  v += dpp_mov<0x128>(v);
+  return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
 }
 __device__ __forceinline__ cx<double> wave_sum(cx<double> v) { return {wave_sum(v.x), wave_sum(v.y)}; }
+
+// Sums over the 64 lanes of NC per-lane values d[c] (NC = 8, 16 or 32); every
+// lane gets every sum, the same bits on every call.  Quads first (DPP), then
+// the 16 quad sums of each value are transposed through this wave's LDS
+// scratch (16 x (NC + 1) doubles, odd pitch: no bank conflicts), each of
+// G = 64 / NC consecutive lanes adds 16 / G of them, a DPP step combines the
+// G lanes and readlane broadcasts.  One pass for all NC values instead of NC
+// separate reductions.
+template <int NC>
+__device__ __forceinline__ void wave_sums(double (&d)[NC], double* scr) {
+  static_assert(NC == 8 || NC == 16 || NC == 32, "NC");
+  constexpr int P = NC + 1, G = 64 / NC, PER = 16 / G;
+  const int lane = threadIdx.x & 63, quad = lane >> 2, sub = lane & 3;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    d[c] += dpp_mov<0xB1>(d[c]);
+    d[c] += dpp_mov<0x4E>(d[c]);
+  }
+  // lane (quad, sub) stores values c = sub, sub + 4, ... of its quad
+#pragma unroll
+  for (int c = 0; c < NC; c += 4) {
+    double v = d[c];
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+      if (sub == k) v = d[c + k];
+    scr[quad * P + c + sub] = v;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int col = lane / G, part = lane % G;
+  double t = scr[(part * PER) * P + col];
+#pragma unroll
+  for (int i = 1; i < PER; ++i) t += scr[(part * PER + i) * P + col];
+  if (G >= 2) t += dpp_mov<0xB1>(t);
+  if (G >= 4) t += dpp_mov<0x4E>(t);
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    d[c] = G == 8 ? read_lane(t, G * c) + read_lane(t, G * c + 4) : read_lane(t, G * c);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void split_re(double v, double* o) { o[0] = v; }
+__device__ __forceinline__ void split_re(cx<double> v, double* o) { o[0] = v.x; o[1] = v.y; }
+__device__ __forceinline__ void join_re(double& v, const double* o) { v = o[0]; }
+__device__ __forceinline__ void join_re(cx<double>& v, const double* o) { v = cx<double>{o[0], o[1]}; }
+template <class A> struct ncomp { static constexpr int v = 1; };
+template <> struct ncomp<cx<double>> { static constexpr int v = 2; };
 
 // Sum of one value per thread over the block, same order on every call.
 // red must hold blockDim.x / 64 entries; result valid in every thread.
@@ -53,77 +126,29 @@ __device__ __forceinline__ cx<double> neg_if(cx<double> v, bool n) { return n ? 
 
 // Scatter one element's value into the zeta rows of S's column `col`.
 template <class A>
+__device__ __forceinline__ void sketch_word(A* acc, uint64_t h, int g, A v, const SketchSpec& sk) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = 4 * g + q;
+    if (b < sk.zeta) {
+      const uint32_t u = (uint32_t)(h >> (16 * q)) & 0xFFFFu;
+      const int row = b * sk.bsz + (int)(((u >> 1) * (uint32_t)sk.bsz) >> 15);
+      lds_add(&acc[row], neg_if(v, (u & 1u) != 0u));
+    }
+  }
+}
+
+template <class A>
 __device__ __forceinline__ void sketch_scatter(A* acc, int64_t col, A v, const SketchSpec& sk) {
   const uint64_t base = sk.seed + kGamma * ((uint64_t)col * (uint64_t)sk.words + 1ull);
-  for (int g = 0; g < sk.words; ++g) {
-    const uint64_t h = mix64(base + (uint64_t)g * kGamma);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b = 4 * g + q;
-      if (b < sk.zeta) {
-        const uint32_t u = (uint32_t)(h >> (16 * q)) & 0xFFFFu;
-        const int row = b * sk.bsz + (int)(((u >> 1) * (uint32_t)sk.bsz) >> 15);
-        lds_add(&acc[row], neg_if(v, (u & 1u) != 0u));
-      }
-    }
+  if (sk.words <= 2) {  // zeta <= 8: both words unrolled
+    sketch_word(acc, mix64(base), 0, v, sk);
+    if (sk.words == 2) sketch_word(acc, mix64(base + kGamma), 1, v, sk);
+  } else {
+    for (int g = 0; g < sk.words; ++g) sketch_word(acc, mix64(base + (uint64_t)g * kGamma), g, v, sk);
   }
 }
 
-// ------------------------------------------------- SpMV + window products --
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_spmv_dots(
-    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
-    const T* __restrict__ x, T* __restrict__ w, Window<T> win, int tw,
-    typename traits<T>::acc* __restrict__ part, int nb, const Ctrl* __restrict__ ctrl) {
-  using A = typename traits<T>::acc;
-  if (ctrl->halt) return;
-  __shared__ A red[kWaves];
-  A d[kMaxWindow];
-#pragma unroll
-  for (int q = 0; q < kMaxWindow; ++q) d[q] = zero<A>();
-  double nw = 0.0;
-  const int r0 = blockIdx.x * kRowsSpmv;
-  const int r1 = min(n, r0 + kRowsSpmv);
-  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
-    A acc = zero<A>();
-    const int e1 = rp[r + 1];
-    for (int e = rp[r]; e < e1; ++e) acc += widen(val[e]) * widen(x[ci[e]]);
-    const T wt = narrow<T>(acc);
-    w[r] = wt;
-    const A wa = widen(wt);
-    nw += abs2(wa);
-#pragma unroll
-    for (int q = 0; q < kMaxWindow; ++q)
-      if (q < tw) d[q] += conj(widen(win.p[q][r])) * wa;
-  }
-#pragma unroll
-  for (int q = 0; q < kMaxWindow; ++q) {
-    if (q < tw) {
-      const A s = block_sum(d[q], red);
-      if (threadIdx.x == 0) part[(int64_t)q * nb + blockIdx.x] = s;
-    }
-  }
-  const double s = block_sum(nw, (double*)red);
-  if (threadIdx.x == 0) {
-    A v = zero<A>();
-    *(double*)&v = s;
-    part[(int64_t)tw * nb + blockIdx.x] = v;
-  }
-}
-
-template <class T>
-void launch_spmv_dots(hipStream_t st, int n, const int* rp, const int* ci, const T* val, const T* x,
-                      T* w, Window<T> win, int tw, typename traits<T>::acc* part, int nb,
-                      const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
-  if (e0)  // events recorded by the dispatch itself: the kernel's own duration
-    hipExtLaunchKernelGGL(k_spmv_dots<T>, dim3(nb), dim3(kBlock), 0, st, e0, e1, 0, n, rp, ci, val, x,
-                          w, win, tw, part, nb, ctrl);
-  else
-    hipLaunchKernelGGL(k_spmv_dots<T>, dim3(nb), dim3(kBlock), 0, st, n, rp, ci, val, x, w, win, tw,
-                       part, nb, ctrl);
-}
-
-// ---------------------------------------- update + norm + sparse sketch ---
 // Column sum of a [ncols x nb] partial array in the order every reducer of
 // this library uses (thread-strided, then the fixed block tree), so that the
 // same partials always give the same bits.
@@ -134,83 +159,210 @@ __device__ __forceinline__ A col_sum(const A* __restrict__ part, int nb, int col
   return block_sum(sum, red);
 }
 
+__device__ __forceinline__ void put_re(double* p, double v) { *p = v; }
+__device__ __forceinline__ void put_re(cx<double>* p, double v) { *p = cx<double>{v, 0.0}; }
+
+// --------------------------------- SpMV + window products + input sketch --
+// Each wave works on its own chunks of 64 rows, with no block barrier inside
+// the row loop: a chunk whose entries fit the wave's staging buffer is read
+// coalesced (lane e forms val[e] * x[ci[e]] into LDS, then lane r sums its row
+// there); a longer chunk is read row by row.  The input vector x = p_{j-1} is
+// read once more, coalesced, for its sketch and norm, and serves as the
+// newest window vector.  (A grid-wide "last block" reduction would need a
+// device-scope fence per block, which writes back the L2 of the block's XCD:
+// the update kernel reduces the few scalars it needs instead.)
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_update_sketch(
-    int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ part1,
-    int nb1, const typename traits<T>::acc* __restrict__ part2prev, int nb2prev, double* __restrict__ nu,
-    int i0, int jprev, SketchSpec sk, typename traits<T>::acc* __restrict__ part,
-    int nb, const Ctrl* __restrict__ ctrl) {
+__global__ __launch_bounds__(kBlock) void k_spmv_sketch(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
+    const T* __restrict__ x, T* __restrict__ w, Window<T> win, int tw, SketchSpec sk, int wave_cap,
+    int do_spmv, typename traits<T>::acc* __restrict__ part, int nb, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
   if (ctrl->halt) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  A* acc = reinterpret_cast<A*>(smem_raw);  // [kWaves][s], one copy per wave
+  const int s = sk.s;  // 0: no sketch
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  A* bins = reinterpret_cast<A*>(smem_raw) + wv * s;                   // this wave's sketch [s]
+  A* prod = reinterpret_cast<A*>(smem_raw) + kWaves * s + wv * wave_cap;  // this wave's staging
   __shared__ A red[kWaves];
-  const int s = sk.s;
-  for (int i = threadIdx.x; i < kWaves * s; i += kBlock) acc[i] = zero<A>();
-  // prologue: window products of this step and ||p_{j-1}||^2 of the previous one
-  double nprev = 0.0;
-  if (part2prev) {
-    const A v = col_sum(part2prev, nb2prev, s, red);
-    nprev = sqrt(re(v));
-    if (blockIdx.x == 0 && threadIdx.x == 0) nu[jprev] = nprev;
+  for (int i = lane; i < s; i += 64) bins[i] = zero<A>();
+  A d[kMaxWindow];
+#pragma unroll
+  for (int q = 0; q < kMaxWindow; ++q) d[q] = zero<A>();
+  double nw = 0.0, nx = 0.0;
+  const int r0 = blockIdx.x * kRowsSpmv;
+  const int r1 = min(n, r0 + kRowsSpmv);
+  for (int t0 = r0 + 64 * wv; t0 < r1; t0 += kBlock) {
+    const int t1 = min(r1, t0 + 64);
+    const int r = t0 + lane;
+    const bool in = r < t1;
+    // loads that do not depend on the row's entries go first
+    A xa = zero<A>();
+    A pw[kMaxWindow];
+    int ra = 0, rb = 0;
+    if (in) {
+      xa = widen(x[r]);
+      if (do_spmv) {
+        ra = rp[r];
+        rb = rp[r + 1];
+#pragma unroll
+        for (int q = 0; q < kMaxWindow; ++q)
+          pw[q] = (q < tw && !(q + 1 == tw && win.p[q] == x)) ? widen(win.p[q][r]) : xa;
+      }
+    }
+    A acc = zero<A>();
+    if (do_spmv) {
+      const int e0 = rp[t0], e1 = rp[t1];  // the same in every lane of the wave
+      if (e1 - e0 <= wave_cap) {
+        // all of the chunk's entries in flight at once, then their x gathers
+        int cc[kWaveTileNnz / 64];
+        A vv[kWaveTileNnz / 64];
+#pragma unroll
+        for (int u = 0; u < kWaveTileNnz / 64; ++u) {
+          const int e = e0 + lane + 64 * u;
+          if (e < e1) {
+            cc[u] = ci[e];
+            vv[u] = widen(val[e]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kWaveTileNnz / 64; ++u) {
+          const int e = e0 + lane + 64 * u;
+          if (e < e1) vv[u] = vv[u] * widen(x[cc[u]]);
+        }
+#pragma unroll
+        for (int u = 0; u < kWaveTileNnz / 64; ++u) {
+          const int e = e0 + lane + 64 * u;
+          if (e < e1) prod[e - e0] = vv[u];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (in)
+          for (int e = ra - e0; e < rb - e0; ++e) acc += prod[e];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else if (in) {
+        for (int e = ra; e < rb; ++e) acc += widen(val[e]) * widen(x[ci[e]]);
+      }
+    }
+    if (in) {
+      if (s > 0) {
+        nx += abs2(xa);
+        sketch_scatter(bins, r, xa, sk);
+      }
+      if (do_spmv) {
+        const T wt = narrow<T>(acc);
+        w[r] = wt;
+        const A wa = widen(wt);
+        nw += abs2(wa);
+#pragma unroll
+        for (int q = 0; q < kMaxWindow; ++q)
+          if (q < tw) d[q] += conj(pw[q]) * wa;
+      }
+    }
   }
+  __syncthreads();
+  int c0 = 0;
+  if (s > 0) {
+    A* all = reinterpret_cast<A*>(smem_raw);
+    for (int row = threadIdx.x; row < s; row += kBlock) {
+      A sum = all[row];
+      for (int q = 1; q < kWaves; ++q) sum += all[q * s + row];
+      part[(int64_t)row * nb + blockIdx.x] = sum;
+    }
+    const double sx = block_sum(nx, (double*)red);
+    if (threadIdx.x == 0) put_re(part + (int64_t)s * nb + blockIdx.x, sx);
+    c0 = s + 1;
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxWindow; ++q) {
+    if (q < tw) {
+      const A v = block_sum(d[q], red);
+      if (threadIdx.x == 0) part[(int64_t)(c0 + q) * nb + blockIdx.x] = v;
+    }
+  }
+  const double sw = block_sum(nw, (double*)red);
+  if (threadIdx.x == 0) put_re(part + (int64_t)(c0 + tw) * nb + blockIdx.x, sw);
+}
+
+template <class T>
+static int spmv_wave_cap(int s) {
+  using A = typename traits<T>::acc;
+  const int budget = ((int)(kSpmvLds / sizeof(A)) - kWaves * s) / kWaves;
+  // the staging loop is unrolled for kWaveTileNnz entries: the cap is that or nothing
+  return budget < kWaveTileNnz ? 0 : kWaveTileNnz;
+}
+
+template <class T>
+void launch_spmv_sketch(hipStream_t st, int n, const int* rp, const int* ci, const T* val, const T* x,
+                        T* w, Window<T> win, int tw, SketchSpec sk, bool spmv,
+                        typename traits<T>::acc* part, int nb, const Ctrl* ctrl, hipEvent_t e0,
+                        hipEvent_t e1) {
+  using A = typename traits<T>::acc;
+  const int cap = spmv ? spmv_wave_cap<T>(sk.s) : 0;
+  const size_t lds = ((size_t)kWaves * sk.s + (size_t)kWaves * cap) * sizeof(A);
+  const int dsp = spmv ? 1 : 0;
+  if (e0)  // events recorded by the dispatch itself: the kernel's own duration
+    hipExtLaunchKernelGGL(k_spmv_sketch<T>, dim3(nb), dim3(kBlock), lds, st, e0, e1, 0, n, rp, ci, val,
+                          x, w, win, tw, sk, cap, dsp, part, nb, ctrl);
+  else
+    hipLaunchKernelGGL(k_spmv_sketch<T>, dim3(nb), dim3(kBlock), lds, st, n, rp, ci, val, x, w, win,
+                       tw, sk, cap, dsp, part, nb, ctrl);
+}
+
+// ------------------------------------------- truncated orthogonalisation ---
+// Prologue: nu_{j-1} = ||p_{j-1}|| and the window products from the SpMV
+// partials of this step (columns s, s+1 .. s+tw), in the order every reducer
+// uses.  Then p_j = (w - sum c_q p_q) / nu_{j-1} in place with
+// c_q = <p_q, w> / nu_q^2: a pure stream over w and the window vectors, each
+// thread with kUpdateRows independent rows in flight.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_update(
+    int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ part,
+    int nb1, int s, double* __restrict__ nu, int i0, int jprev, const Ctrl* __restrict__ ctrl) {
+  using A = typename traits<T>::acc;
+  if (ctrl->halt) return;
+  __shared__ A red[kWaves];
+  const double nprev = sqrt(re(col_sum(part, nb1, s, red)));
+  if (blockIdx.x == 0 && threadIdx.x == 0) nu[jprev] = nprev;
   A c[kMaxWindow];
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) {
     if (q < tw) {
-      const A d = col_sum(part1, nb1, q, red);
-      const double nq = (part2prev && i0 + q == jprev) ? nprev : nu[i0 + q];
-      c[q] = scale(d, 1.0 / (nq * nq));
+      const A dq = col_sum(part, nb1, s + 1 + q, red);
+      const double nq = i0 + q == jprev ? nprev : nu[i0 + q];
+      c[q] = scale(dq, 1.0 / (nq * nq));
     } else {
       c[q] = zero<A>();
     }
   }
-  // w' = (w - sum c_q p_q) / nu_{j-1}: the orthogonalised A v_{j-1}
-  const double inv_prev = 1.0 / (part2prev ? nprev : nu[jprev]);
-  __syncthreads();
-  A* mine = acc + (threadIdx.x >> 6) * s;
-  double nrm = 0.0;
-  const int r0 = blockIdx.x * kRowsUpdate;
-  const int r1 = min(n, r0 + kRowsUpdate);
-  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
-    A v = widen(w[r]);
+  const double inv = 1.0 / nprev;
+  const int base = blockIdx.x * (kBlock * kUpdateRows) + (int)threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < kMaxWindow; ++q)
-      if (q < tw) v -= c[q] * widen(win.p[q][r]);
-    const T vt = narrow<T>(scale(v, inv_prev));
-    w[r] = vt;
-    const A va = widen(vt);
-    nrm += abs2(va);
-    sketch_scatter(mine, r, va, sk);
-  }
-  __syncthreads();
-  for (int row = threadIdx.x; row < s; row += kBlock) {
-    A sum = acc[row];
-    for (int q = 1; q < kWaves; ++q) sum += acc[q * s + row];
-    part[(int64_t)row * nb + blockIdx.x] = sum;
-  }
-  const double ns = block_sum(nrm, (double*)red);
-  if (threadIdx.x == 0) {
-    A v = zero<A>();
-    *(double*)&v = ns;
-    part[(int64_t)s * nb + blockIdx.x] = v;
+  for (int u = 0; u < kUpdateRows; ++u) {
+    const int r = base + u * kBlock;
+    if (r < n) {
+      A v = widen(w[r]);
+#pragma unroll
+      for (int q = 0; q < kMaxWindow; ++q)
+        if (q < tw) v -= c[q] * widen(win.p[q][r]);
+      w[r] = narrow<T>(scale(v, inv));
+    }
   }
 }
 
 template <class T>
-void launch_update_sketch(hipStream_t st, int n, T* w, Window<T> win, int tw,
-                          const typename traits<T>::acc* part1, int nb1,
-                          const typename traits<T>::acc* part2prev, int nb2prev, double* nu, int i0,
-                          int jprev, SketchSpec sk, typename traits<T>::acc* part, int nb,
-                          const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
-  using A = typename traits<T>::acc;
-  const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
+void launch_update(hipStream_t st, int n, T* w, Window<T> win, int tw,
+                   const typename traits<T>::acc* part, int nb1, int s, double* nu, int i0, int jprev,
+                   const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
+  const int nb = (n + kBlock * kUpdateRows - 1) / (kBlock * kUpdateRows);
   if (e0)
-    hipExtLaunchKernelGGL(k_update_sketch<T>, dim3(nb), dim3(kBlock), lds, st, e0, e1, 0, n, w, win,
-                          tw, part1, nb1, part2prev, nb2prev, nu, i0, jprev, sk, part, nb, ctrl);
+    hipExtLaunchKernelGGL(k_update<T>, dim3(nb), dim3(kBlock), 0, st, e0, e1, 0, n, w, win, tw, part,
+                          nb1, s, nu, i0, jprev, ctrl);
   else
-    hipLaunchKernelGGL(k_update_sketch<T>, dim3(nb), dim3(kBlock), lds, st, n, w, win, tw, part1, nb1,
-                       part2prev, nb2prev, nu, i0, jprev, sk, part, nb, ctrl);
+    hipLaunchKernelGGL(k_update<T>, dim3(nb), dim3(kBlock), 0, st, n, w, win, tw, part, nb1, s, nu, i0,
+                       jprev, ctrl);
 }
 
 // ------------------------------------------------ fixed-order reduction ---
@@ -250,6 +402,34 @@ void launch_reduce2(hipStream_t st, const A* pa, int nba, int ca, int nscaled, d
                     const A* pb, int nbb, int cb, A* out, const Ctrl* ctrl) {
   hipLaunchKernelGGL(k_reduce2<A>, dim3(ca + cb), dim3(kBlock), 0, st, pa, nba, ca, nscaled, scl, pb,
                      nbb, out, ctrl);
+}
+
+// Reduced inputs of the least squares of steps j0 .. j0 + gridDim.y - 1, each
+// into its slot of redb: [S p_j (s, scaled), ||p_j||^2] from the SpMV
+// partials of step j+1, then the window products and ||w||^2 of step j.
+// One block per (column, step), the same fixed order as k_reduce2.
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_reduce_steps(const A* __restrict__ part1, int64_t slot1,
+                                                         int nb1, int s, int j0, int t, int nslot,
+                                                         double scl, A* __restrict__ redb,
+                                                         int64_t slotr, const Ctrl* __restrict__ ctrl) {
+  if (ctrl->halt) return;
+  __shared__ A red[kWaves];
+  const int j = j0 + (int)blockIdx.y;
+  const int tw = j - (j - t > 0 ? j - t : 0);
+  const int col = blockIdx.x;
+  if (col >= s + 1 + tw + 1) return;
+  const A* pa = part1 + slot1 * ((j + 1) % nslot);
+  const A* pb = part1 + slot1 * (j % nslot) + (int64_t)(s + 1) * nb1;
+  const A sum = col < s + 1 ? col_sum(pa, nb1, col, red) : col_sum(pb, nb1, col - (s + 1), red);
+  if (threadIdx.x == 0) redb[slotr * (j % nslot) + col] = col < s ? scale(sum, scl) : sum;
+}
+
+template <class A>
+void launch_reduce_steps(hipStream_t st, const A* part1, int64_t slot1, int nb1, int s, int j0, int j1,
+                         int t, int nslot, double scl, A* redb, int64_t slotr, const Ctrl* ctrl) {
+  hipLaunchKernelGGL(k_reduce_steps<A>, dim3(s + 1 + kMaxWindow + 1, j1 - j0 + 1), dim3(kBlock), 0, st,
+                     part1, slot1, nb1, s, j0, t, nslot, scl, redb, slotr, ctrl);
 }
 
 // Cycle start: nu_0 = ||p_0|| and SV(:, 0) = S p_0 / nu_0 from a reduced sketch [s values, norm^2].
@@ -420,24 +600,35 @@ __device__ __forceinline__ void regq_load(RegQ<A, RL, CW>& Q, const A* __restric
 // i < col into R, and the new unit column into Q's registers and into g.
 template <class A, int RL, int CW>
 __device__ double regq_append(RegQ<A, RL, CW>& Q, A (&a)[RL], A* __restrict__ g, A* __restrict__ Rcol,
-                              A* lds_red /* kRegWaves * 64 * RL */, int s, int col, double rank_rtol,
-                              bool* loss) {
+                              A* lds_red /* kRegWaves * 64 * RL */, double* scr /* per wave */, int s,
+                              int col, double rank_rtol, bool* loss) {
+  constexpr int NC = CW * ncomp<A>::v;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double n0 = 0.0;
 #pragma unroll
   for (int rr = 0; rr < RL; ++rr) n0 += abs2(a[rr]);
   n0 = sqrt(wave_sum(n0));
+  // this wave holds columns wv + kRegWaves * cc; those at or beyond col are
+  // zero (a wave with none skips the reduction; per-column branches would
+  // break the interleaving of the reductions and cost more than they save)
+  const int nact = col > wv ? (col - wv + kRegWaves - 1) / kRegWaves : 0;
   A ctot[CW];
 #pragma unroll
   for (int cc = 0; cc < CW; ++cc) ctot[cc] = zero<A>();
   for (int pass = 0; pass < 2; ++pass) {
-    A c[CW];
+    double dd[NC];
 #pragma unroll
     for (int cc = 0; cc < CW; ++cc) {
       A d = zero<A>();
 #pragma unroll
-      for (int rr = 0; rr < RL; ++rr) d += conj(Q.q[rr][cc]) * a[rr];
-      c[cc] = wave_sum(d);
+        for (int rr = 0; rr < RL; ++rr) d += conj(Q.q[rr][cc]) * a[rr];
+      split_re(d, dd + cc * ncomp<A>::v);
+    }
+    if (nact > 0) wave_sums<NC>(dd, scr);
+    A c[CW];
+#pragma unroll
+    for (int cc = 0; cc < CW; ++cc) {
+      join_re(c[cc], dd + cc * ncomp<A>::v);
       ctot[cc] += c[cc];
     }
     // partial update over this wave's columns, reduced over the waves
@@ -445,7 +636,8 @@ __device__ double regq_append(RegQ<A, RL, CW>& Q, A (&a)[RL], A* __restrict__ g,
     for (int rr = 0; rr < RL; ++rr) {
       A u = zero<A>();
 #pragma unroll
-      for (int cc = 0; cc < CW; ++cc) u += Q.q[rr][cc] * c[cc];
+      for (int cc = 0; cc < CW; ++cc)
+        u += Q.q[rr][cc] * c[cc];
       lds_red[(wv * RL + rr) * 64 + lane] = u;
     }
     __syncthreads();
@@ -536,6 +728,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step_reg(LsqState<A> S, int j
                                                             double brtol, double rank_rtol) {
   if (S.ctrl->halt) return;
   __shared__ A lds_red[kRegWaves * 64 * RL];
+  __shared__ double scr_all[kRegWaves * 16 * (CW * ncomp<A>::v + 1)];
   __shared__ A hcol[kMaxWindow + 1];
   __shared__ int sh_break;
   __shared__ double sh_res;
@@ -586,7 +779,8 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step_reg(LsqState<A> S, int j
   }
   bool loss = false;
   const double na =
-      regq_append<A, RL, CW>(Q, a, S.Q, S.R + (int64_t)col * S.ldr, lds_red, s, col, rank_rtol, &loss);
+      regq_append<A, RL, CW>(Q, a, S.Q, S.R + (int64_t)col * S.ldr, lds_red,
+                             scr_all + (tid >> 6) * 16 * (CW * ncomp<A>::v + 1), s, col, rank_rtol, &loss);
   if (tid == 0) {
     A d = zero<A>();
     *(double*)&d = na;
@@ -616,10 +810,152 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step_reg(LsqState<A> S, int j
   }
 }
 
+// Steps j0 .. j1 of the least squares in one launch: Q stays in registers,
+// the projected residual rho in wave 0's registers and the SV columns of the
+// truncation window in an LDS ring, so a step costs its QR append and little
+// else.  The same arithmetic as k_lsq_step_reg, step after step; the launch
+// stops after a step that raises the halt flag.  Step records are stored
+// with seq last (a workgroup release orders the stores); one system-scope
+// fence at the end publishes them all.
+template <class A, int RL, int CW>
+__global__ __launch_bounds__(kLsqBlock) void k_lsq_steps_reg(LsqState<A> S, int j0, int j1, int khat,
+                                                             int m, int t, int s,
+                                                             const A* __restrict__ redb, int64_t slotr,
+                                                             int nslot, double brtol, double rank_rtol) {
+  if (S.ctrl->halt) return;
+  constexpr int SP = 64 * RL;  // ring pitch (>= s)
+  __shared__ A lds_red[kRegWaves * 64 * RL];
+  __shared__ double scr_all[kRegWaves * 16 * (CW * ncomp<A>::v + 1)];
+  __shared__ A ring[kMaxWindow * SP];  // SV(:, k) at slot k % kMaxWindow
+  __shared__ A hcol[kMaxWindow + 1];
+  __shared__ int sh_break, sh_halt;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  RegQ<A, RL, CW> Q;
+  regq_load(Q, S.Q, s, khat + j0 - 1);
+  {
+    const int i0 = j0 - t > 0 ? j0 - t : 0;
+    for (int k = i0; k < j0; ++k)
+      for (int r = tid; r < s; r += blockDim.x)
+        ring[(k % kMaxWindow) * SP + r] = S.SB[(int64_t)(khat + k) * S.ldsb + r];
+  }
+  A rho[RL];
+#pragma unroll
+  for (int rr = 0; rr < RL; ++rr) {
+    const int r = lane + 64 * rr;
+    rho[rr] = (wv == 0 && r < s) ? S.rho[r] : zero<A>();
+  }
+  double* scr = scr_all + wv * 16 * (CW * ncomp<A>::v + 1);
+  __syncthreads();
+  for (int j = j0; j <= j1; ++j) {
+    const A* red = redb + slotr * (j % nslot);
+    const int i0 = j - t > 0 ? j - t : 0;
+    const int tw = j - i0;
+    const int col = khat + j - 1;
+    const A* dots = red + s + 1;
+    const double nuj = sqrt(re(red[s]));
+    if (tid == 0) {
+      const double nuprev = S.nu[j - 1];
+      const double nw = sqrt(re(dots[tw]));
+      const bool brk = !(nuj > brtol * nw / nuprev);  // H(j,j-1) vs ||A v_{j-1}||
+      sh_break = brk;
+      S.nu[j] = nuj;
+      for (int q = 0; q < tw; ++q) {
+        const A h = scale(dots[q], 1.0 / (S.nu[i0 + q] * nuprev));
+        hcol[q] = h;
+        S.H[(int64_t)(j - 1) * S.ldh + i0 + q] = h;
+      }
+      A hs = zero<A>();
+      *(double*)&hs = brk ? 0.0 : nuj;
+      hcol[tw] = hs;
+      S.H[(int64_t)(j - 1) * S.ldh + j] = hs;
+    }
+    __syncthreads();
+    const bool brk = sh_break;
+    A a[RL], v[RL];
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) {
+      const int r = lane + 64 * rr;
+      A sum = zero<A>();
+      v[rr] = zero<A>();
+      if (r < s) {
+        v[rr] = brk ? zero<A>() : scale(red[r], 1.0 / nuj);
+        for (int q = 0; q < tw; ++q) sum += ring[((i0 + q) % kMaxWindow) * SP + r] * hcol[q];
+        sum += v[rr] * hcol[tw];
+        if (wv == 0) {
+          S.SB[(int64_t)(khat + j) * S.ldsb + r] = v[rr];
+          S.SAW[(int64_t)(khat + j - 1) * S.ldsaw + r] = sum;
+        }
+      }
+      a[rr] = sum;
+    }
+    bool loss = false;
+    const double na = regq_append<A, RL, CW>(Q, a, S.Q, S.R + (int64_t)col * S.ldr, lds_red, scr, s, col,
+                                             rank_rtol, &loss);
+    // the window ring takes SV(:, j) (slot of SV(:, j - kMaxWindow), no longer needed)
+    if (wv == 0) {
+#pragma unroll
+      for (int rr = 0; rr < RL; ++rr) {
+        const int r = lane + 64 * rr;
+        if (r < s) ring[(j % kMaxWindow) * SP + r] = v[rr];
+      }
+    }
+    if (wv == 0) {
+      A zc = zero<A>();
+      if (!loss) {
+#pragma unroll
+        for (int rr = 0; rr < RL; ++rr) zc += conj(a[rr]) * rho[rr];
+        zc = wave_sum(zc);
+#pragma unroll
+        for (int rr = 0; rr < RL; ++rr) rho[rr] -= a[rr] * zc;
+      }
+      double rr2 = 0.0;
+#pragma unroll
+      for (int rr = 0; rr < RL; ++rr) rr2 += abs2(rho[rr]);
+      const double sres = sqrt(wave_sum(rr2));
+      if (lane == 0) {
+        A d = zero<A>();
+        *(double*)&d = na;
+        S.R[(int64_t)col * S.ldr + col] = d;
+        S.z[col] = zc;
+        int flags = 0;
+        if (brk) flags |= 2;
+        if (loss) flags |= 4;
+        const bool halt = sres < S.ctrl->thresh || j == m || brk || loss;
+        if (halt) flags |= 1;
+        S.sres_hist[j] = sres;
+        if (halt) {
+          S.ctrl->halt = 1;
+          S.ctrl->halt_j = j;
+          S.ctrl->flags = flags;
+        }
+        sh_halt = halt;
+        StepRec* rc = S.rec + j;
+        rc->sres = sres;
+        rc->nu = nuj;
+        rc->j = j;
+        rc->flags = flags;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        rc->seq = j;
+      }
+    }
+    __syncthreads();
+    if (sh_halt) break;
+  }
+  if (wv == 0) {
+#pragma unroll
+    for (int rr = 0; rr < RL; ++rr) {
+      const int r = lane + 64 * rr;
+      if (r < s) S.rho[r] = rho[rr];
+    }
+  }
+  if (tid == 0) __threadfence_system();
+}
+
 template <class A, int RL, int CW>
 __global__ __launch_bounds__(kLsqBlock) void k_lsq_init_reg(LsqState<A> S, int khat, int s,
                                                             const A* __restrict__ Sr, double rank_rtol) {
   __shared__ A lds_red[kRegWaves * 64 * RL];
+  __shared__ double scr_all[kRegWaves * 16 * (CW * ncomp<A>::v + 1)];
   __shared__ double sh_res;
   const int lane = threadIdx.x & 63;
   RegQ<A, RL, CW> Q;
@@ -639,7 +975,9 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_init_reg(LsqState<A> S, int k
     }
     bool loss = false;
     const double na =
-        regq_append<A, RL, CW>(Q, a, S.Q, S.R + (int64_t)c * S.ldr, lds_red, s, c, rank_rtol, &loss);
+        regq_append<A, RL, CW>(Q, a, S.Q, S.R + (int64_t)c * S.ldr, lds_red,
+                               scr_all + (threadIdx.x >> 6) * 16 * (CW * ncomp<A>::v + 1), s, c,
+                               rank_rtol, &loss);
     if (threadIdx.x == 0) {
       A d = zero<A>();
       *(double*)&d = na;
@@ -743,10 +1081,14 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, in
   }
 }
 
+// register shapes instantiated per type: (2,8), (2,16), (4,16), (4,8) for
+// real data, (2,8), (4,8) for complex (wider ones spill)
 #define SDR_LSQ_REG_CASE(RL, CW, KER, ...)                                                  \
-  if (rl == RL && cw == CW) {                                                               \
-    hipLaunchKernelGGL((KER<A, RL, CW>), dim3(1), dim3(kLsqBlock), 0, st, __VA_ARGS__);     \
-    return;                                                                                 \
+  if constexpr (sizeof(A) == 8 || CW == 8) {                                                \
+    if (rl == RL && cw == CW) {                                                             \
+      hipLaunchKernelGGL((KER<A, RL, CW>), dim3(1), dim3(kLsqBlock), 0, st, __VA_ARGS__);   \
+      return;                                                                               \
+    }                                                                                       \
   }
 
 template <class A>
@@ -763,6 +1105,37 @@ void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int 
   const size_t lds = (size_t)(2 * s + 2 * lmax + lsq_chunk<A>(s, lmax) * s) * sizeof(A);
   hipLaunchKernelGGL(k_lsq_step<A>, dim3(1), dim3(kLsqBlock), lds, st, S, j, khat, m, t, s, red,
                      brtol, rank_rtol);
+}
+
+// LDS of the batched kernel: update partials, reduction scratch, window ring
+template <class A>
+static constexpr size_t lsq_steps_lds(int rl, int cw) {
+  return (size_t)kRegWaves * 64 * rl * sizeof(A) +
+         (size_t)kRegWaves * 16 * (cw * (sizeof(A) / 8) + 1) * 8 + (size_t)kMaxWindow * 64 * rl * sizeof(A);
+}
+
+#define SDR_LSQ_STEPS_CASE(RL, CW)                                                            \
+  if constexpr (lsq_steps_lds<A>(RL, CW) <= 64 * 1024 && (sizeof(A) == 8 || CW == 8)) {        \
+    if (rl == RL && cw == CW) {                                                               \
+      hipLaunchKernelGGL((k_lsq_steps_reg<A, RL, CW>), dim3(1), dim3(kLsqBlock), 0, st, S, j0, \
+                         j1, khat, m, t, s, redb, slotr, nslot, brtol, rank_rtol);             \
+      return;                                                                                 \
+    }                                                                                         \
+  }
+
+template <class A>
+void launch_lsq_steps(hipStream_t st, LsqState<A> S, int j0, int j1, int khat, int m, int t, int s,
+                      const A* redb, int64_t slotr, int nslot, double brtol, double rank_rtol) {
+  int rl = 0, cw = 0;
+  if (lsq_reg_shape<A>(s, khat + m + 1, &rl, &cw)) {
+    SDR_LSQ_STEPS_CASE(2, 8)
+    SDR_LSQ_STEPS_CASE(2, 16)
+    SDR_LSQ_STEPS_CASE(4, 16)
+    SDR_LSQ_STEPS_CASE(4, 8)
+  }
+  // shapes without a batched kernel: one launch per step
+  for (int j = j0; j <= j1; ++j)
+    launch_lsq_step<A>(st, S, j, khat, m, t, s, redb + slotr * (j % nslot), brtol, rank_rtol);
 }
 
 template <class A>
@@ -1134,13 +1507,11 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
 
 // ---------------------------------------------------- instantiations ---
 #define SDR_INST_BASIS(T)                                                                        \
-  template void launch_spmv_dots<T>(hipStream_t, int, const int*, const int*, const T*, const T*, \
-                                    T*, Window<T>, int, traits<T>::acc*, int, const Ctrl*,         \
-                                    hipEvent_t, hipEvent_t);                                       \
-  template void launch_update_sketch<T>(hipStream_t, int, T*, Window<T>, int,                     \
-                                        const traits<T>::acc*, int, const traits<T>::acc*, int,   \
-                                        double*, int, int, SketchSpec, traits<T>::acc*, int,      \
-                                        const Ctrl*, hipEvent_t, hipEvent_t);                     \
+  template void launch_spmv_sketch<T>(hipStream_t, int, const int*, const int*, const T*,          \
+                                      const T*, T*, Window<T>, int, SketchSpec, bool,             \
+                                      traits<T>::acc*, int, const Ctrl*, hipEvent_t, hipEvent_t); \
+  template void launch_update<T>(hipStream_t, int, T*, Window<T>, int, const traits<T>::acc*, int, \
+                                 int, double*, int, int, const Ctrl*, hipEvent_t, hipEvent_t);    \
   template void launch_sketch_cols<T>(hipStream_t, int, const T*, int64_t, int, SketchSpec,       \
                                       traits<T>::acc*, int);                                      \
   template void launch_gemv_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
@@ -1165,6 +1536,10 @@ SDR_INST_BASIS(cx<float>)
                                   int, A*, const Ctrl*);                                        \
   template void launch_init_v0<A>(hipStream_t, const A*, int, A*, double*);                     \
   template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double, int);  \
+  template void launch_lsq_steps<A>(hipStream_t, LsqState<A>, int, int, int, int, int, int,      \
+                                    const A*, int64_t, int, double, double);                     \
+  template void launch_reduce_steps<A>(hipStream_t, const A*, int64_t, int, int, int, int, int,  \
+                                       int, double, A*, int64_t, const Ctrl*);                  \
   template void launch_backsolve<A>(hipStream_t, LsqState<A>, int, int, A*);                    \
   template void launch_spmv_residual<A>(hipStream_t, int, const int*, const int*, const A*,     \
                                         const A*, const A*, A*, A*, int);                      \

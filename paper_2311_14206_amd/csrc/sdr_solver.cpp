@@ -22,6 +22,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <future>
 #include <memory>
 #include <string>
 #include <vector>
@@ -82,8 +83,9 @@ struct Options {
   int variant = 0;
   double brtol = -1.0;  // < 0: default for the basis precision
   double rank_rtol = 1e-12;
-  int lookahead = 4;
-  bool kernel_timing = false;
+  int lookahead = 16;     // Arnoldi steps whose least squares is queued ahead of the host
+  int lsq_chunk = 8;      // steps per least-squares launch
+  int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
 };
 
 // Matrix view (device, full precision values).
@@ -164,12 +166,12 @@ class Solver final : public SolverBase {
       ctrl_ = dalloc<Ctrl>(1);
       ctrl_free_ = dalloc<Ctrl>(1);
       nslot_ = m + 2;  // one partial slot per step: the least squares may lag a whole cycle
-      slot1_ = (size_t)(kMaxWindow + 1) * nb1_;
-      slot2_ = (size_t)(s + 1) * nb2_;
+      // SpMV partial columns per step: S p_{j-1} (s), ||p_{j-1}||^2, window products, ||w||^2
+      slot1_ = (size_t)(s + 1 + kMaxWindow + 1) * nb1_;
       slotr_ = (size_t)(s + 1 + kMaxWindow + 1);
       part1_ = dalloc<A>(slot1_ * nslot_);
-      part2_ = dalloc<A>(slot2_ * nslot_);
       redb_ = dalloc<A>(slotr_ * nslot_);
+      red0_ = dalloc<A>(s + 1);
       psk_ = dalloc<A>((size_t)(8 * s + 8 + 1) * nb2_);
       red2_ = dalloc<A>(8 * s + 8 + 1);
       HIPCHK(hipStreamCreateWithFlags(&streamB_, hipStreamNonBlocking));
@@ -295,38 +297,55 @@ class Solver final : public SolverBase {
     return S;
   }
 
-  // Arnoldi part of step j on stream A (SpMV + window products, update + norm
-  // + sketch), then an event for the least-squares part.
-  void enqueue_step_a(int j, const T* vals) {
+  // Arnoldi part of step j on stream A: the SpMV of p_{j-1} with its window
+  // products and its sketch, an event for the least squares of step j-1,
+  // then the update to p_j.  Step m+1 is the sketch of p_m alone.
+  // With ev, an event after the SpMV for the least squares on stream B.
+  void enqueue_step_a(int j, const T* vals, bool ev) {
+    const int sl = j % nslot_;
+    A* p1 = part1_ + slot1_ * sl;
+    const T* x = P_ + (size_t)(j - 1) * n_;
+    if (j > m_) {
+      Window<T> none{};
+      launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, x, nullptr, none, 0, sk_, false, p1, nb1_,
+                            ctrl_);
+      LAUNCHCHK();
+      HIPCHK(hipEventRecord(evs_[sl], stream_));
+      return;
+    }
     const int i0 = std::max(j - t_, 0);
     const int tw = j - i0;
-    const int sl = j % nslot_, slp = (j - 1) % nslot_;
     Window<T> win{};
     for (int q = 0; q < tw; ++q) win.p[q] = P_ + (size_t)(i0 + q) * n_;
     T* w = P_ + (size_t)j * n_;
-    const T* x = P_ + (size_t)(j - 1) * n_;
-    A* p1 = part1_ + slot1_ * sl;
-    A* p2 = part2_ + slot2_ * sl;
-    const A* p2prev = j >= 2 ? part2_ + slot2_ * slp : nullptr;
-    const bool tm = opt_.kernel_timing;
-    launch_spmv_dots<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, p1, nb1_, ctrl_,
-                        tm ? ev_[j][0] : nullptr, tm ? ev_[j][1] : nullptr);
-    launch_update_sketch<T>(stream_, n_, w, win, tw, p1, nb1_, p2prev, nb2_, nu_, i0, j - 1, sk_, p2,
-                            nb2_, ctrl_, tm ? ev_[j][2] : nullptr, tm ? ev_[j][3] : nullptr);
+    const bool tm = timed(j);
+    launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
+                          tm ? ev_[j][0] : nullptr, tm ? ev_[j][1] : nullptr);
     LAUNCHCHK();
-    HIPCHK(hipEventRecord(evs_[sl], stream_));
+    if (ev) HIPCHK(hipEventRecord(evs_[sl], stream_));
+    launch_update<T>(stream_, n_, w, win, tw, p1, nb1_, s_, nu_, i0, j - 1, ctrl_,
+                     tm ? ev_[j][2] : nullptr, tm ? ev_[j][3] : nullptr);
+    LAUNCHCHK();
   }
 
-  // Least-squares part of step j on stream B, behind step j's event.
-  void enqueue_step_b(int j) {
-    const int i0 = std::max(j - t_, 0);
-    const int tw = j - i0;
-    const int sl = j % nslot_;
-    HIPCHK(hipStreamWaitEvent(streamB_, evs_[sl], 0));
-    A* rd = redb_ + slotr_ * sl;
-    launch_reduce2<A>(streamB_, part2_ + slot2_ * sl, nb2_, s_ + 1, s_,
-                      1.0 / std::sqrt((double)sk_.zeta), part1_ + slot1_ * sl, nb1_, tw + 1, rd, ctrl_);
-    launch_lsq_step<A>(streamB_, lsq(), j, khat_, m_, t_, s_, rd, brtol_, opt_.rank_rtol);
+  bool timed(int j) const { return opt_.kernel_timing > 0 && j % opt_.kernel_timing == 0; }
+
+  // The least squares of steps j0 .. j1 runs behind the SpMV of step j1 + 1;
+  // chunks start at base, base + chunk, ... so that only their last SpMV
+  // records an event.
+  bool needs_event(int j, int base) const {
+    return j == m_ + 1 || (j > base && (j - base) % opt_.lsq_chunk == 0);
+  }
+
+  // Least squares of steps j0 .. j1 on stream B, behind the SpMV of step
+  // j1 + 1 (which sketches p_{j1}); the window products of step j come from
+  // step j's SpMV.
+  void enqueue_chunk(int j0, int j1) {
+    HIPCHK(hipStreamWaitEvent(streamB_, evs_[(j1 + 1) % nslot_], 0));
+    launch_reduce_steps<A>(streamB_, part1_, (int64_t)slot1_, nb1_, s_, j0, j1, t_, nslot_,
+                           1.0 / std::sqrt((double)sk_.zeta), redb_, (int64_t)slotr_, ctrl_);
+    launch_lsq_steps<A>(streamB_, lsq(), j0, j1, khat_, m_, t_, s_, redb_, (int64_t)slotr_, nslot_,
+                        brtol_, opt_.rank_rtol);
     LAUNCHCHK();
   }
 
@@ -428,8 +447,9 @@ class Solver final : public SolverBase {
       // exact variant: S A_i U with the new matrix (k products and sketches)
       for (int c = 0; c < khat_; ++c) {
         Window<T> win{};
-        launch_spmv_dots<T>(stream_, n_, M_.rp, M_.ci, vals, U_ + (size_t)c * n_,
-                            Unew_ + (size_t)c * n_, win, 0, part1_, nb1_, ctrl_free_);
+        launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, U_ + (size_t)c * n_,
+                              Unew_ + (size_t)c * n_, win, 0, SketchSpec{}, true, part1_, nb1_,
+                              ctrl_free_);
         LAUNCHCHK();
       }
       sketch_cols<T>(Unew_, khat_, SAU_, s_, nullptr);
@@ -453,27 +473,41 @@ class Solver final : public SolverBase {
       sketches++;
       ips++;
       launch_cast_scale<T>(stream_, n_, r_, rn > 0.0 ? 1.0 / rn : 1.0, P_);  // p_0 = r0 / ||r0||
-      launch_sketch_cols<T>(stream_, n_, P_, (int64_t)n_, 1, sk_, psk_, nb2_);
-      launch_reduce_cols<A>(stream_, psk_, nb2_, s_ + 1, s_, 1.0 / std::sqrt((double)sk_.zeta), red2_,
-                            nullptr);
-      launch_init_v0<A>(stream_, red2_, s_, SB_ + (size_t)kmax_ * s_, nu_);
       last_sv_ = SB_ + (size_t)kmax_ * s_;
       for (int j = 0; j <= m_ + 1; ++j) __atomic_store_n(&rec_host_[j].seq, -1, __ATOMIC_RELEASE);
       launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
       LAUNCHCHK();
-      int enqA = 0, enqB = 0;
-      // stream B starts after the cycle-start work (S r0, SV(:, 0))
-      HIPCHK(hipEventRecord(evs_[nslot_], stream_));
-      HIPCHK(hipStreamWaitEvent(streamB_, evs_[nslot_], 0));
+      // step 1's SpMV sketches p_0; stream B starts behind it with SV(:, 0) and nu_0
+      enqueue_step_a(1, vals, true);
+      int enqA = 1, enqB = 0, base = 1;
+      HIPCHK(hipStreamWaitEvent(streamB_, evs_[1 % nslot_], 0));
+      launch_reduce_cols<A>(streamB_, part1_ + slot1_ * (1 % nslot_), nb1_, s_ + 1, s_,
+                            1.0 / std::sqrt((double)sk_.zeta), red0_, nullptr);
+      launch_init_v0<A>(streamB_, red0_, s_, SB_ + (size_t)kmax_ * s_, nu_);
+      LAUNCHCHK();
       if (pend_.active) {
         // The Arnoldi basis of this cycle does not depend on the recycle space
-        // (V spans K_m(A, r0)): queue its steps now and run the previous
-        // cycle's eigen-step on the host meanwhile.
-        for (int j = 1; j <= m_; ++j) enqueue_step_a(j, vals);
-        enqA = m_;
-        const double te = now();
-        finish_recycle(trace);
-        eig_time += now() - te;
+        // (V spans K_m(A, r0)): the previous cycle's eigen-step runs on a
+        // worker thread while this one queues the cycle's steps.
+        auto eig = std::async(std::launch::async, [this] {
+          try {
+            return eig_compute();
+          } catch (HipError& e) {
+            EigResult f;
+            f.code = e.code;
+            f.err = g_err;
+            return f;
+          }
+        });
+        for (int j = 2; j <= m_ + 1; ++j) enqueue_step_a(j, vals, needs_event(j, base));
+        enqA = m_ + 1;
+        EigResult er = eig.get();
+        if (er.code) {
+          set_err(er.err);
+          throw HipError{er.code};
+        }
+        eig_time += er.seconds;
+        finish_recycle_enqueue(er, trace);
       }
       if (khat_ > 0) {
         HIPCHK(hipMemcpyAsync(SB_ + (size_t)(kmax_ - khat_) * s_, SU_, sizeof(A) * s_ * khat_,
@@ -488,14 +522,15 @@ class Solver final : public SolverBase {
       double res = 0.0, sres = 0.0;
       bool cyc_conv = false;
       for (;;) {
-        const int upto = std::min(m_, done + opt_.lookahead);
+        const int upto = std::min(m_, done + std::max(opt_.lookahead, 1));
         while (enqB < upto) {
-          const int j = ++enqB;
-          if (j > enqA) {
-            enqueue_step_a(j, vals);
-            enqA = j;
+          const int j0 = enqB + 1, j1 = std::min(j0 + opt_.lsq_chunk - 1, m_);
+          while (enqA < j1 + 1) {  // step j+1 sketches p_j
+            ++enqA;
+            enqueue_step_a(enqA, vals, needs_event(enqA, base));
           }
-          enqueue_step_b(j);
+          enqueue_chunk(j0, j1);
+          enqB = j1;
         }
         StepRec rc;
         if (!wait_record(done + 1, rc)) {
@@ -539,6 +574,7 @@ class Solver final : public SolverBase {
           launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
           LAUNCHCHK();
           enqA = enqB = done;
+          base = done + 1;
         }
       }
       cycles++;
@@ -546,6 +582,7 @@ class Solver final : public SolverBase {
       if (opt_.kernel_timing) {
         sync_both();
         for (int j = 1; j <= jstop; ++j) {
+          if (!timed(j)) continue;
           float a = 0.f, b2 = 0.f, c = 0.f;
           HIPCHK(hipEventElapsedTime(&a, ev_[j][0], ev_[j][1]));
           HIPCHK(hipEventElapsedTime(&b2, ev_[j][2], ev_[j][3]));
@@ -576,9 +613,9 @@ class Solver final : public SolverBase {
       cur_ ^= 1;
       const bool more = !converged && cycles < opt_.max_cycles && !(flags_stop && jstop == 1);
       if (!more) {
-        const double te = now();
-        finish_recycle(trace);
-        eig_time += now() - te;
+        EigResult er = eig_compute();
+        eig_time += er.seconds;
+        finish_recycle_enqueue(er, trace);
         break;
       }
     }
@@ -611,52 +648,71 @@ class Solver final : public SolverBase {
     HIPCHK(hipEventRecord(ev_copy_, stream_));
   }
 
-  // Host eigen-step of the pending cycle, then U = [U P] G (stream A) and
-  // SU = [SU SV] G, SAU = [SAU SAV] G.  Updates khat_ and the trace record.
-  void finish_recycle(std::vector<sdr_cycle_record>* trace) {
+  // Host eigen-step of the pending cycle (no device work: it may run on a
+  // worker thread while the next cycle is queued).
+  struct EigResult {
+    int keff = 0, ell = 0;
+    double seconds = 0.0;
+    std::vector<std::complex<double>> G;
+    int code = 0;     // error raised on the worker thread
+    std::string err;  // and its message (error strings are per thread)
+  };
+  EigResult eig_compute() {
+    EigResult r;
+    const int l0 = pend_.l0;
+    if (!pend_.active || k_ == 0 || l0 == 0) return r;
+    const double t0 = now();
+    HIPCHK(hipEventSynchronize(ev_copy_));
+    std::vector<std::complex<double>> Rc((size_t)l0 * l0), Cc((size_t)l0 * l0);
+    for (int c = 0; c < l0; ++c)
+      for (int i = 0; i < l0; ++i) {
+        Rc[(size_t)c * l0 + i] = i <= c ? to_cd(hR_[(size_t)c * lmax_ + i]) : std::complex<double>(0.0);
+        Cc[(size_t)c * l0 + i] = to_cd(hC_[(size_t)c * l0 + i]);
+      }
+    r.keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s_, k_, !traits<T>::cpx, r.G, &r.ell);
+    if (r.keff < 0) {
+      set_err("Schur iteration did not converge");
+      throw HipError{SDR_EDEVICE};
+    }
+    r.seconds = now() - t0;
+    return r;
+  }
+
+  // U = [U P] G (stream A) and SU = [SU SV] G, SAU = [SAU SAV] G (stream B)
+  // from the eigen-step's result; updates khat_ and the trace record.
+  void finish_recycle_enqueue(const EigResult& r, std::vector<sdr_cycle_record>* trace) {
     if (!pend_.active) return;
     pend_.active = false;
-    const int l0 = pend_.l0, khat = pend_.khat;
-    int ell = 0, keff = 0;
-    if (k_ > 0 && l0 > 0) {
-      HIPCHK(hipEventSynchronize(ev_copy_));
-      std::vector<std::complex<double>> Rc((size_t)l0 * l0), Cc((size_t)l0 * l0), G;
-      for (int c = 0; c < l0; ++c)
+    const int l0 = pend_.l0, khat = pend_.khat, keff = r.keff;
+    if (keff > 0) {
+      A* Gh = hG_;
+      A* Gp = hG_ + (size_t)l0 * keff;
+      for (int c = 0; c < keff; ++c)
         for (int i = 0; i < l0; ++i) {
-          Rc[(size_t)c * l0 + i] =
-              i <= c ? to_cd(hR_[(size_t)c * lmax_ + i]) : std::complex<double>(0.0);
-          Cc[(size_t)c * l0 + i] = to_cd(hC_[(size_t)c * l0 + i]);
+          const A g = from_cd<A>(r.G[(size_t)c * l0 + i]);
+          Gh[(size_t)c * l0 + i] = g;
+          Gp[(size_t)c * l0 + i] = i < khat ? g : scale(g, 1.0 / hnu_[i - khat]);
         }
-      keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s_, k_, !traits<T>::cpx, G, &ell);
-      if (keff < 0) {
-        set_err("Schur iteration did not converge");
-        throw HipError{SDR_EDEVICE};
-      }
-      if (keff > 0) {
-        A* Gh = hG_;
-        A* Gp = hG_ + (size_t)l0 * keff;
-        for (int c = 0; c < keff; ++c)
-          for (int i = 0; i < l0; ++i) {
-            const A g = from_cd<A>(G[(size_t)c * l0 + i]);
-            Gh[(size_t)c * l0 + i] = g;
-            Gp[(size_t)c * l0 + i] = i < khat ? g : scale(g, 1.0 / hnu_[i - khat]);
-          }
-        // small products on stream B (they feed this cycle's least squares),
-        // the N x keff product on stream A (it feeds the first residual check)
-        HIPCHK(hipMemcpyAsync(Gs_, Gh, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, streamB_));
-        launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SB, s_, Gs_, l0, SU_, s_);
-        launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SAW, s_, Gs_, l0, SAU_, s_);
-        HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
-        launch_gemm_basis<T>(stream_, n_, U_, n_, khat, pend_.P, n_, pend_.j, G_, keff, Unew_, n_);
-        LAUNCHCHK();
-        std::swap(U_, Unew_);
-      }
+      // small products on stream B (they feed this cycle's least squares),
+      // the N x keff product on stream A (it feeds the first residual check)
+      HIPCHK(hipMemcpyAsync(Gs_, Gh, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, streamB_));
+      launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SB, s_, Gs_, l0, SU_, s_);
+      launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SAW, s_, Gs_, l0, SAU_, s_);
+      HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
+      launch_gemm_basis<T>(stream_, n_, U_, n_, khat, pend_.P, n_, pend_.j, G_, keff, Unew_, n_);
+      LAUNCHCHK();
+      std::swap(U_, Unew_);
     }
     khat_ = keff;
     if (trace && pend_.trace_idx >= 0 && pend_.trace_idx < (int)trace->size()) {
-      (*trace)[pend_.trace_idx].ell = ell;
+      (*trace)[pend_.trace_idx].ell = r.ell;
       (*trace)[pend_.trace_idx].k_eff = keff;
     }
+  }
+
+  void finish_recycle(std::vector<sdr_cycle_record>* trace) {
+    if (!pend_.active) return;
+    finish_recycle_enqueue(eig_compute(), trace);
   }
 
   void fill_stats(sdr_stats* st, int cycles, int iters, int mv, int ip, int sk, int ch, int status,
@@ -720,10 +776,11 @@ class Solver final : public SolverBase {
  private:
   void release() {
     for (void* p : {(void*)valB_, (void*)Pbuf_[0], (void*)Pbuf_[1], (void*)U_, (void*)Unew_, (void*)SU_,
+                    (void*)red0_,
                     (void*)SAU_, (void*)Q_, (void*)R_, (void*)z_, (void*)rho_, (void*)SBbuf_[0],
                     (void*)SBbuf_[1], (void*)SAWbuf_[0], (void*)SAWbuf_[1], (void*)H_,
                     (void*)nu_, (void*)sres_hist_, (void*)ctrl_, (void*)ctrl_free_, (void*)part1_,
-                    (void*)part2_, (void*)redb_, (void*)psk_, (void*)red2_, (void*)red3_, (void*)Sr_,
+                    (void*)redb_, (void*)psk_, (void*)red2_, (void*)red3_, (void*)Sr_,
                     (void*)ycoef_, (void*)xt_, (void*)r_, (void*)rnew_, (void*)G_, (void*)Gs_,
                     (void*)C_})
       dfree(p);
@@ -776,10 +833,10 @@ class Solver final : public SolverBase {
   A *SB_ = nullptr, *SAW_ = nullptr, *H_ = nullptr;
   double *nu_ = nullptr, *sres_hist_ = nullptr;
   Ctrl *ctrl_ = nullptr, *ctrl_free_ = nullptr;
-  A *part1_ = nullptr, *part2_ = nullptr, *redb_ = nullptr, *psk_ = nullptr, *red2_ = nullptr,
-    *red3_ = nullptr;
+  A *part1_ = nullptr, *redb_ = nullptr, *psk_ = nullptr, *red2_ = nullptr, *red3_ = nullptr,
+    *red0_ = nullptr;
   int nslot_ = 0;
-  size_t slot1_ = 0, slot2_ = 0, slotr_ = 0;
+  size_t slot1_ = 0, slotr_ = 0;
   hipStream_t streamB_ = nullptr;
   std::vector<hipEvent_t> evs_;
   A *Sr_ = nullptr, *ycoef_ = nullptr, *xt_ = nullptr, *r_ = nullptr, *rnew_ = nullptr;
@@ -799,7 +856,7 @@ class Solver final : public SolverBase {
     sau_stale_ = false;
   }
 
-  // [0] spmv_dots ms, [1] update_sketch ms, [2] whole step ms (K1 start to LSQ end);
+  // [0] SpMV + sketch ms, [1] update ms, [2] both kernels of a step (SpMV start to update end);
   // counts[0..2] launches; counts[3 + tw] = launches with window size tw.
   int kernel_times(double* ms, int64_t* counts, int cap) override {
     for (int i = 0; i < 3 && i < cap; ++i) {
@@ -970,6 +1027,14 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
       set_err("invalid parameters: need m>=1, k>=0, 1<=t<=min(m,4), s_dim>m+k");
       return nullptr;
     }
+    {
+      // one LDS accumulator copy of the sketch per wave of the streaming kernels
+      const size_t esz = A->dtype == SDR_C128 ? 16 : 8;
+      if ((size_t)kWaves * (size_t)s_dim * esz > (size_t)kSpmvLds) {
+        set_err("s_dim too large: need s_dim <= " + std::to_string(kSpmvLds / (kWaves * esz)));
+        return nullptr;
+      }
+    }
     h = new sdr_handle();
     h->n = (int)A->n;
     h->nnz = A->nnz;
@@ -1038,11 +1103,14 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
     if (built || !(v >= 0.0)) return set_err("rank_rtol >= 0, before the first solve"), SDR_EINVAL;
     h->opt.rank_rtol = v;
   } else if (k == "kernel_timing") {
-    if (built) return set_err("kernel_timing must be set before the first solve"), SDR_EINVAL;
-    h->opt.kernel_timing = v != 0.0;
+    if (built || !(v >= 0.0 && v <= 1e6)) return set_err("kernel_timing in [0,1e6], before the first solve"), SDR_EINVAL;
+    h->opt.kernel_timing = (int)v;
   } else if (k == "lookahead") {
-    if (built || v < 1 || v > 64) return set_err("lookahead in [1,64], before the first solve"), SDR_EINVAL;
+    if (built || v < 1 || v > 1024) return set_err("lookahead in [1,1024], before the first solve"), SDR_EINVAL;
     h->opt.lookahead = (int)v;
+  } else if (k == "lsq_chunk") {
+    if (built || v < 1 || v > 64) return set_err("lsq_chunk in [1,64], before the first solve"), SDR_EINVAL;
+    h->opt.lsq_chunk = (int)v;
   } else {
     set_err("unknown option " + k);
     return SDR_EINVAL;
@@ -1162,17 +1230,19 @@ int sdr_spmv(sdr_handle* h, const void* x, void* y) {
     if (h->cpx) {
       auto* part = dalloc<cx<double>>((size_t)nb * (kMaxWindow + 1));
       Window<cx<double>> win{};
-      launch_spmv_dots<cx<double>>(h->stream, h->n, h->rp, h->ci, static_cast<const cx<double>*>(h->vals),
-                                   static_cast<const cx<double>*>(x), static_cast<cx<double>*>(y), win, 0,
-                                   part, nb, c);
+      launch_spmv_sketch<cx<double>>(h->stream, h->n, h->rp, h->ci,
+                                     static_cast<const cx<double>*>(h->vals),
+                                     static_cast<const cx<double>*>(x), static_cast<cx<double>*>(y), win,
+                                     0, SketchSpec{}, true, part, nb, c);
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(h->stream));
       dfree(part);
     } else {
       auto* part = dalloc<double>((size_t)nb * (kMaxWindow + 1));
       Window<double> win{};
-      launch_spmv_dots<double>(h->stream, h->n, h->rp, h->ci, static_cast<const double*>(h->vals),
-                               static_cast<const double*>(x), static_cast<double*>(y), win, 0, part, nb, c);
+      launch_spmv_sketch<double>(h->stream, h->n, h->rp, h->ci, static_cast<const double*>(h->vals),
+                                 static_cast<const double*>(x), static_cast<double*>(y), win, 0,
+                                 SketchSpec{}, true, part, nb, c);
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(h->stream));
       dfree(part);

@@ -209,11 +209,12 @@ class SDRSolver:
         _check(lib().sdr_reset(self.h), "sdr_reset")
 
     def kernel_times(self):
-        """Event timings since the last call (needs the option kernel_timing=1)."""
+        """Event timings since the last call (needs the option kernel_timing=n: every
+        n-th Arnoldi step's SpMV and update kernels are timed)."""
         ms = (C.c_double * 8)()
         cnt = (C.c_int64 * 8)()
         _check(lib().sdr_kernel_times(self.h, ms, cnt, 8), "sdr_kernel_times")
-        return {"spmv_dots_ms": ms[0], "update_sketch_ms": ms[1], "step_ms": ms[2],
+        return {"spmv_sketch_ms": ms[0], "update_ms": ms[1], "step_ms": ms[2],
                 "launches": cnt[0], "window_hist": [cnt[3 + i] for i in range(5)]}
 
     def trace(self):
