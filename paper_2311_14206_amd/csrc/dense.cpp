@@ -45,7 +45,7 @@ bool schur(Mat& T, Mat& Z) {
   for (int i = 0; i < n; ++i) Z(i, i) = 1.0;
   if (n <= 1) return true;
   // Householder reduction to upper Hessenberg form, T <- P T P, Z <- Z P.
-  std::vector<cd> v(n);
+  std::vector<cd> v(n), wrk(n);
   for (int k = 0; k + 2 < n; ++k) {
     const int len = n - k - 1;
     double xn = 0.0;
@@ -67,17 +67,21 @@ bool schur(Mat& T, Mat& Z) {
       s *= f;
       for (int i = 0; i < len; ++i) T(k + 1 + i, j) -= v[i] * s;
     }
-    for (int i = 0; i < n; ++i) {
-      cd s = 0.0;
-      for (int l = 0; l < len; ++l) s += T(i, k + 1 + l) * v[l];
-      s *= f;
-      for (int l = 0; l < len; ++l) T(i, k + 1 + l) -= s * std::conj(v[l]);
-    }
-    for (int i = 0; i < n; ++i) {
-      cd s = 0.0;
-      for (int l = 0; l < len; ++l) s += Z(i, k + 1 + l) * v[l];
-      s *= f;
-      for (int l = 0; l < len; ++l) Z(i, k + 1 + l) -= s * std::conj(v[l]);
+    // right: M(:, k+1:) -= f (M(:, k+1:) v) v^H, column by column
+    for (Mat* Mp : {&T, &Z}) {
+      cd* M = Mp->a.data();
+      std::fill(wrk.begin(), wrk.end(), cd(0.0));
+      for (int l = 0; l < len; ++l) {
+        const cd* col = M + (size_t)(k + 1 + l) * n;
+        const cd vl = v[l];
+        for (int i = 0; i < n; ++i) wrk[i] += col[i] * vl;
+      }
+      for (int i = 0; i < n; ++i) wrk[i] *= f;
+      for (int l = 0; l < len; ++l) {
+        cd* col = M + (size_t)(k + 1 + l) * n;
+        const cd cv = std::conj(v[l]);
+        for (int i = 0; i < n; ++i) col[i] -= wrk[i] * cv;
+      }
     }
     T(k + 1, k) = alpha;
     for (int i = 1; i < len; ++i) T(k + 1 + i, k) = 0.0;
@@ -155,7 +159,7 @@ static bool schur_real(int n, std::vector<double>& T, std::vector<double>& Z) {
   Z.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) z(i, i) = 1.0;
   if (n <= 1) return true;
-  std::vector<double> v(n);
+  std::vector<double> v(n), wrk(n);
   for (int k = 0; k + 2 < n; ++k) {  // Householder reduction to Hessenberg form
     const int len = n - k - 1;
     double xn = 0.0;
@@ -175,17 +179,21 @@ static bool schur_real(int n, std::vector<double>& T, std::vector<double>& Z) {
       sm *= f;
       for (int i = 0; i < len; ++i) t(k + 1 + i, j) -= v[i] * sm;
     }
-    for (int i = 0; i < n; ++i) {
-      double sm = 0.0;
-      for (int l = 0; l < len; ++l) sm += t(i, k + 1 + l) * v[l];
-      sm *= f;
-      for (int l = 0; l < len; ++l) t(i, k + 1 + l) -= sm * v[l];
-    }
-    for (int i = 0; i < n; ++i) {
-      double sm = 0.0;
-      for (int l = 0; l < len; ++l) sm += z(i, k + 1 + l) * v[l];
-      sm *= f;
-      for (int l = 0; l < len; ++l) z(i, k + 1 + l) -= sm * v[l];
+    // right: M(:, k+1:) -= f (M(:, k+1:) v) v^T, column by column
+    for (std::vector<double>* Mp : {&T, &Z}) {
+      double* M = Mp->data();
+      std::fill(wrk.begin(), wrk.end(), 0.0);
+      for (int l = 0; l < len; ++l) {
+        const double* col = M + (size_t)(k + 1 + l) * n;
+        const double vl = v[l];
+        for (int i = 0; i < n; ++i) wrk[i] += col[i] * vl;
+      }
+      for (int i = 0; i < n; ++i) wrk[i] *= f;
+      for (int l = 0; l < len; ++l) {
+        double* col = M + (size_t)(k + 1 + l) * n;
+        const double vl = v[l];
+        for (int i = 0; i < n; ++i) col[i] -= wrk[i] * vl;
+      }
     }
     t(k + 1, k) = alpha;
     for (int i = 1; i < len; ++i) t(k + 1 + i, k) = 0.0;
@@ -193,19 +201,41 @@ static bool schur_real(int n, std::vector<double>& T, std::vector<double>& Z) {
   // reflector P = I - beta v v^T (len 2 or 3) applied to rows k.. (left) and
   // columns k.. (right) of T, and to columns of Z
   auto left = [&](int k, int len, const double* vv, double beta, int c0, int c1) {
-    for (int j = c0; j <= c1; ++j) {
-      double sm = 0.0;
-      for (int i = 0; i < len; ++i) sm += vv[i] * t(k + i, j);
-      sm *= beta;
-      for (int i = 0; i < len; ++i) t(k + i, j) -= sm * vv[i];
+    if (len == 3) {
+      for (int j = c0; j <= c1; ++j) {
+        double* c = &t(k, j);
+        const double sm = (vv[0] * c[0] + vv[1] * c[1] + vv[2] * c[2]) * beta;
+        c[0] -= sm * vv[0];
+        c[1] -= sm * vv[1];
+        c[2] -= sm * vv[2];
+      }
+    } else {
+      for (int j = c0; j <= c1; ++j) {
+        double* c = &t(k, j);
+        const double sm = (vv[0] * c[0] + vv[1] * c[1]) * beta;
+        c[0] -= sm * vv[0];
+        c[1] -= sm * vv[1];
+      }
     }
   };
+  // columns k .. k+len-1 of M, rows 0 .. r1 (contiguous down each column)
   auto right = [&](std::vector<double>& M, int k, int len, const double* vv, double beta, int r1) {
-    for (int i = 0; i <= r1; ++i) {
-      double sm = 0.0;
-      for (int l = 0; l < len; ++l) sm += M[(size_t)(k + l) * n + i] * vv[l];
-      sm *= beta;
-      for (int l = 0; l < len; ++l) M[(size_t)(k + l) * n + i] -= sm * vv[l];
+    double* m0 = M.data() + (size_t)k * n;
+    double* m1 = m0 + n;
+    if (len == 3) {
+      double* m2 = m1 + n;
+      for (int i = 0; i <= r1; ++i) {
+        const double sm = (m0[i] * vv[0] + m1[i] * vv[1] + m2[i] * vv[2]) * beta;
+        m0[i] -= sm * vv[0];
+        m1[i] -= sm * vv[1];
+        m2[i] -= sm * vv[2];
+      }
+    } else {
+      for (int i = 0; i <= r1; ++i) {
+        const double sm = (m0[i] * vv[0] + m1[i] * vv[1]) * beta;
+        m0[i] -= sm * vv[0];
+        m1[i] -= sm * vv[1];
+      }
     }
   };
   auto house = [](double* x, int len, double* vv, double& beta) {
@@ -561,6 +591,40 @@ static Mat real_basis(const Mat& Zk, int keff) {
   return out;
 }
 
+// Ri = R^{-1} (R upper triangular, n x n, column major, nonsingular) by
+// columns, X = Ri C, and the bound ||R||_F ||R^{-1}||_F returned.  Loops run
+// down contiguous columns.
+template <class S>
+static double tri_inverse_product(int n, const S* R, S* Ri, const S* C, std::vector<S>& X) {
+  for (int j = 0; j < n; ++j) {
+    S* col = Ri + (size_t)j * n;
+    col[j] = S(1.0) / R[(size_t)j * n + j];
+    // column j of R^{-1}: back substitution R x = e_j, x(j) known
+    for (int p = j; p >= 1; --p) {
+      const S xp = col[p];
+      const S* rp = R + (size_t)p * n;  // column p of R: rows 0 .. p-1 above the diagonal
+      for (int i = 0; i < p; ++i) col[i] -= rp[i] * xp;
+      col[p - 1] /= R[(size_t)(p - 1) * n + (p - 1)];
+    }
+  }
+  double f = 0.0, fi = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i <= j; ++i) {
+      f += norm_(R[(size_t)j * n + i]);
+      fi += norm_(Ri[(size_t)j * n + i]);
+    }
+  X.assign((size_t)n * n, S(0.0));
+  for (int j = 0; j < n; ++j) {
+    S* xj = X.data() + (size_t)j * n;
+    for (int p = 0; p < n; ++p) {
+      const S cpj = C[(size_t)j * n + p];
+      const S* rip = Ri + (size_t)p * n;  // column p of R^{-1}: rows 0 .. p
+      for (int i = 0; i <= p; ++i) xj[i] += rip[i] * cpj;
+    }
+  }
+  return std::sqrt(f * fi);
+}
+
 int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std::vector<cd>& G,
                   int* ell_out) {
   G.clear();
@@ -573,43 +637,36 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
       Rm(i, j) = i <= j ? R[(size_t)j * l0 + i] : cd(0.0);
       Cm(i, j) = C[(size_t)j * l0 + i];
     }
-  // triangular inverse and the 1-norm condition number of R
-  Mat Ri(l0, l0);
+  // triangular inverse of R, the Frobenius condition bound, and R^{-1} C (real
+  // arithmetic for real data)
   bool singular = false;
   for (int i = 0; i < l0; ++i)
     if (std::abs(Rm(i, i)) == 0.0) singular = true;
   double cond = std::numeric_limits<double>::infinity();
+  Mat RiC;  // R^{-1} C when R is nonsingular
   if (!singular) {
-    for (int j = 0; j < l0; ++j) {
-      Ri(j, j) = 1.0 / Rm(j, j);
-      for (int i = j - 1; i >= 0; --i) {
-        cd acc = 0.0;
-        for (int p = i + 1; p <= j; ++p) acc += Rm(i, p) * Ri(p, j);
-        Ri(i, j) = -acc / Rm(i, i);
+    if (real) {
+      std::vector<double> r((size_t)l0 * l0), ri((size_t)l0 * l0, 0.0), c((size_t)l0 * l0), x;
+      for (size_t i = 0; i < r.size(); ++i) {
+        r[i] = Rm.a[i].real();
+        c[i] = Cm.a[i].real();
       }
+      cond = tri_inverse_product(l0, r.data(), ri.data(), c.data(), x);
+      RiC = Mat(l0, l0);
+      for (size_t i = 0; i < x.size(); ++i) RiC.a[i] = x[i];
+    } else {
+      std::vector<cd> ri((size_t)l0 * l0, cd(0.0)), x;
+      cond = tri_inverse_product(l0, Rm.a.data(), ri.data(), Cm.a.data(), x);
+      RiC = Mat(l0, l0);
+      RiC.a = x;
     }
-    double f = 0.0, fi = 0.0;
-    for (int j = 0; j < l0; ++j)
-      for (int i = 0; i <= j; ++i) {
-        f += std::norm(Rm(i, j));
-        fi += std::norm(Ri(i, j));
-      }
-    cond = std::sqrt(f * fi);
   }
-  // sigma_min / sigma_1 >= 1 / (||R||_F ||R^{-1}||_F): below the threshold no
-  // singular value can be cut, and the truncated SVD would keep all of them.
   const bool svd_path = !(std::isfinite(cond) && cond * thr < 0.5);
   Mat Aeig;
   Mat Wl;  // right singular vectors kept (svd path)
   int ell = l0;
   if (!svd_path) {
-    Aeig = Mat(l0, l0);
-    for (int j = 0; j < l0; ++j)
-      for (int i = 0; i < l0; ++i) {
-        cd acc = 0.0;
-        for (int p = i; p < l0; ++p) acc += Ri(i, p) * Cm(p, j);
-        Aeig(i, j) = acc;
-      }
+    Aeig = RiC;
   } else {
     Mat P, W;
     std::vector<double> sig;

@@ -200,6 +200,8 @@ class Solver final : public SolverBase {
       HIPCHK(hipHostMalloc((void**)&hz_, sizeof(A) * (size_t)lmax_, hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hy_, sizeof(A) * (size_t)lmax_, hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hnu_, sizeof(double) * (size_t)(m + 2), hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hRc_, sizeof(A) * (size_t)lmax_ * lmax_, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hnuc_, sizeof(double) * (size_t)(m + 2), hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hG_, sizeof(A) * (size_t)lmax_ * kmax_ * 2, hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hscal_, sizeof(A) * 8, hipHostMallocDefault));
       HIPCHK(hipMemsetAsync(ctrl_free_, 0, sizeof(Ctrl), stream_));
@@ -390,19 +392,20 @@ class Solver final : public SolverBase {
   // the stored basis [U, P]: y_i for U, y_i / nu_i for the unnormalised P.
   void solve_coefficients(int j) {
     const int nls = khat_ + j;
-    HIPCHK(hipMemcpyAsync(hR_, R_, sizeof(A) * (size_t)lmax_ * nls, hipMemcpyDeviceToHost, stream_));
+    // (own staging: the eigen-step's copies of R and nu may be in use on a worker thread)
+    HIPCHK(hipMemcpyAsync(hRc_, R_, sizeof(A) * (size_t)lmax_ * nls, hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipMemcpyAsync(hz_, z_, sizeof(A) * nls, hipMemcpyDeviceToHost, stream_));
-    HIPCHK(hipMemcpyAsync(hnu_, nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(hnuc_, nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipStreamSynchronize(stream_));
     std::vector<std::complex<double>> y(nls);
     for (int i = 0; i < nls; ++i) y[i] = to_cd(hz_[i]);
     for (int i = nls - 1; i >= 0; --i) {
-      const std::complex<double> rii = to_cd(hR_[(size_t)i * lmax_ + i]);
+      const std::complex<double> rii = to_cd(hRc_[(size_t)i * lmax_ + i]);
       y[i] = std::abs(rii) > 0.0 ? y[i] / rii : std::complex<double>(0.0);
-      for (int k = 0; k < i; ++k) y[k] -= to_cd(hR_[(size_t)i * lmax_ + k]) * y[i];
+      for (int k = 0; k < i; ++k) y[k] -= to_cd(hRc_[(size_t)i * lmax_ + k]) * y[i];
     }
     for (int i = 0; i < nls; ++i)
-      hy_[i] = from_cd<A>(i < khat_ ? y[i] : y[i] / hnu_[i - khat_]);
+      hy_[i] = from_cd<A>(i < khat_ ? y[i] : y[i] / hnuc_[i - khat_]);
     HIPCHK(hipMemcpyAsync(ycoef_, hy_, sizeof(A) * nls, hipMemcpyHostToDevice, stream_));
   }
 
@@ -461,6 +464,8 @@ class Solver final : public SolverBase {
     bool converged = rn <= tol_abs;
     double last_sres = 0.0;
     int status = SDR_NOT_CONVERGED;
+    if (eig_fut_.valid()) eig_fut_.wait();  // left over from a solve that failed
+    eig_fut_ = std::future<EigResult>();
     pend_.active = false;
     while (!converged && cycles < opt_.max_cycles) {
       if (!opt_.persist_safety) safety = opt_.safety0;
@@ -489,23 +494,9 @@ class Solver final : public SolverBase {
         // The Arnoldi basis of this cycle does not depend on the recycle space
         // (V spans K_m(A, r0)): the previous cycle's eigen-step runs on a
         // worker thread while this one queues the cycle's steps.
-        auto eig = std::async(std::launch::async, [this] {
-          try {
-            return eig_compute();
-          } catch (HipError& e) {
-            EigResult f;
-            f.code = e.code;
-            f.err = g_err;
-            return f;
-          }
-        });
         for (int j = 2; j <= m_ + 1; ++j) enqueue_step_a(j, vals, needs_event(j, base));
         enqA = m_ + 1;
-        EigResult er = eig.get();
-        if (er.code) {
-          set_err(er.err);
-          throw HipError{er.code};
-        }
+        EigResult er = take_eig();
         eig_time += er.seconds;
         finish_recycle_enqueue(er, trace);
       }
@@ -519,6 +510,7 @@ class Solver final : public SolverBase {
       LAUNCHCHK();
       // --- truncated Arnoldi with sketched least squares ---
       int done = 0, jstop = 0, flags_stop = 0;
+      bool early = false;
       double res = 0.0, sres = 0.0;
       bool cyc_conv = false;
       for (;;) {
@@ -546,6 +538,12 @@ class Solver final : public SolverBase {
         sres = rc.sres;
         if (rc.flags & 1) {
           sync_both();
+          if (done == m_) {
+            // the cycle ends here whatever the check says: its eigen-step
+            // starts now and runs beside the check
+            begin_recycle(done, (int)trace->size(), streamB_);
+            early = true;
+          }
           res = check(done);
           matvecs++;
           ips++;
@@ -609,11 +607,11 @@ class Solver final : public SolverBase {
       trace->push_back(rec);
       converged = cyc_conv;
       // --- sketched harmonic-Ritz update of U, SU, SAU (always) ---
-      begin_recycle(jstop, (int)trace->size() - 1);
+      if (!early) begin_recycle(jstop, (int)trace->size() - 1, stream_);
       cur_ ^= 1;
       const bool more = !converged && cycles < opt_.max_cycles && !(flags_stop && jstop == 1);
       if (!more) {
-        EigResult er = eig_compute();
+        EigResult er = take_eig();
         eig_time += er.seconds;
         finish_recycle_enqueue(er, trace);
         break;
@@ -626,9 +624,19 @@ class Solver final : public SolverBase {
     return status;
   }
 
-  // End of a cycle: C = Q^H [SU, SV] on the device and the small factors to
-  // pinned host memory; the eigen-step itself runs in finish_recycle.
-  void begin_recycle(int j, int trace_idx) {
+  // Result of the host eigen-step of a finished cycle.
+  struct EigResult {
+    int keff = 0, ell = 0;
+    double seconds = 0.0;
+    std::vector<std::complex<double>> G;
+    int code = 0;     // error raised on the worker thread
+    std::string err;  // and its message (error strings are per thread)
+  };
+
+  // End of a cycle: C = Q^H [SU, SV] on the device (stream st) and the small
+  // factors to pinned host memory, then the eigen-step starts on a worker
+  // thread; take_eig() collects it.
+  void begin_recycle(int j, int trace_idx, hipStream_t st) {
     pend_ = Pending{};
     pend_.active = true;
     pend_.j = j;
@@ -640,23 +648,37 @@ class Solver final : public SolverBase {
     pend_.SAW = SAW_ + (size_t)(kmax_ - khat_) * s_;
     const int l0 = pend_.l0;
     if (k_ == 0 || l0 == 0) return;
-    launch_small_gemm<A>(stream_, true, l0, l0, s_, Q_, s_, pend_.SB, s_, C_, l0);
+    launch_small_gemm<A>(st, true, l0, l0, s_, Q_, s_, pend_.SB, s_, C_, l0);
     LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(hR_, R_, sizeof(A) * (size_t)lmax_ * l0, hipMemcpyDeviceToHost, stream_));
-    HIPCHK(hipMemcpyAsync(hC_, C_, sizeof(A) * (size_t)l0 * l0, hipMemcpyDeviceToHost, stream_));
-    HIPCHK(hipMemcpyAsync(hnu_, nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream_));
-    HIPCHK(hipEventRecord(ev_copy_, stream_));
+    HIPCHK(hipMemcpyAsync(hR_, R_, sizeof(A) * (size_t)lmax_ * l0, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hC_, C_, sizeof(A) * (size_t)l0 * l0, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hnu_, nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(ev_copy_, st));
+    eig_fut_ = std::async(std::launch::async, [this] {
+      try {
+        return eig_compute();
+      } catch (HipError& e) {
+        EigResult f;
+        f.code = e.code;
+        f.err = g_err;
+        return f;
+      }
+    });
+  }
+
+  // The pending eigen-step's result (an empty one if none was started).
+  EigResult take_eig() {
+    if (!eig_fut_.valid()) return EigResult{};
+    EigResult er = eig_fut_.get();
+    if (er.code) {
+      set_err(er.err);
+      throw HipError{er.code};
+    }
+    return er;
   }
 
   // Host eigen-step of the pending cycle (no device work: it may run on a
   // worker thread while the next cycle is queued).
-  struct EigResult {
-    int keff = 0, ell = 0;
-    double seconds = 0.0;
-    std::vector<std::complex<double>> G;
-    int code = 0;     // error raised on the worker thread
-    std::string err;  // and its message (error strings are per thread)
-  };
   EigResult eig_compute() {
     EigResult r;
     const int l0 = pend_.l0;
@@ -708,11 +730,6 @@ class Solver final : public SolverBase {
       (*trace)[pend_.trace_idx].ell = r.ell;
       (*trace)[pend_.trace_idx].k_eff = keff;
     }
-  }
-
-  void finish_recycle(std::vector<sdr_cycle_record>* trace) {
-    if (!pend_.active) return;
-    finish_recycle_enqueue(eig_compute(), trace);
   }
 
   void fill_stats(sdr_stats* st, int cycles, int iters, int mv, int ip, int sk, int ch, int status,
@@ -775,6 +792,7 @@ class Solver final : public SolverBase {
 
  private:
   void release() {
+    if (eig_fut_.valid()) eig_fut_.wait();
     for (void* p : {(void*)valB_, (void*)Pbuf_[0], (void*)Pbuf_[1], (void*)U_, (void*)Unew_, (void*)SU_,
                     (void*)red0_,
                     (void*)SAU_, (void*)Q_, (void*)R_, (void*)z_, (void*)rho_, (void*)SBbuf_[0],
@@ -787,10 +805,11 @@ class Solver final : public SolverBase {
     if (rec_host_) (void)hipHostFree(rec_host_);
     rec_host_ = nullptr;
     for (void* p : {(void*)hR_, (void*)hC_, (void*)hz_, (void*)hy_, (void*)hnu_, (void*)hG_,
+                    (void*)hRc_, (void*)hnuc_,
                     (void*)hscal_})
       if (p) (void)hipHostFree(p);
-    hR_ = hC_ = hz_ = hy_ = hG_ = hscal_ = nullptr;
-    hnu_ = nullptr;
+    hR_ = hC_ = hz_ = hy_ = hG_ = hscal_ = hRc_ = nullptr;
+    hnu_ = hnuc_ = nullptr;
     for (auto& a : ev_)
       for (auto& e : a)
         if (e) (void)hipEventDestroy(e);
@@ -843,8 +862,10 @@ class Solver final : public SolverBase {
   A *G_ = nullptr, *Gs_ = nullptr, *C_ = nullptr;
   StepRec *rec_host_ = nullptr, *rec_dev_ = nullptr;
   // pinned host staging of the small dense data
-  A *hR_ = nullptr, *hC_ = nullptr, *hz_ = nullptr, *hy_ = nullptr, *hG_ = nullptr, *hscal_ = nullptr;
-  double* hnu_ = nullptr;
+  A *hR_ = nullptr, *hC_ = nullptr, *hz_ = nullptr, *hy_ = nullptr, *hG_ = nullptr, *hscal_ = nullptr,
+    *hRc_ = nullptr;
+  double *hnu_ = nullptr, *hnuc_ = nullptr;
+  std::future<EigResult> eig_fut_;  // the pending cycle's eigen-step on a worker thread
   std::vector<std::array<hipEvent_t, 4>> ev_;
   double kt_ms_[3] = {0, 0, 0};
   int64_t kt_n_[3] = {0, 0, 0};
