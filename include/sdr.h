@@ -119,9 +119,10 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *   "variant"        0: exact sequences (recompute S A_i U), 1: inexact
  *   "breakdown_rtol" Arnoldi breakdown threshold (default 1e-14; 1e-6 FP32)
  *   "rank_rtol"      rank-loss threshold of the sketched LSQ (default 1e-12)
- *   "lookahead"      Arnoldi steps whose least squares is queued ahead of the
- *                    host's residual control (default 16)
  *   "lsq_chunk"      Arnoldi steps per least-squares launch (default 8)
+ *   "dia"            1 (default): a pattern whose entries lie on at most 16
+ *                    diagonals (padding at most nnz/4) is stored by diagonals
+ *                    for the basis SpMV; 0: always CSR
  *   "kernel_timing"  n > 0: HIP events around the SpMV and update kernels of
  *                    every n-th Arnoldi step (sdr_kernel_times); default 0
  * Returns 0 or SDR_EINVAL.
@@ -200,6 +201,14 @@ int sdr_reset(sdr_handle* h);
  * length of both arrays (8 covers everything).
  */
 int sdr_kernel_times(sdr_handle* h, double* ms, int64_t* counts, int cap);
+
+/*
+ * Storage of the matrix in the basis SpMV: returns the number of diagonals
+ * when the pattern is stored by diagonals (option "dia") and writes their
+ * offsets (column - row, ascending) to offsets[0 .. min(that, cap) - 1];
+ * returns 0 for CSR.  Negative: error code.
+ */
+int sdr_spmv_layout(sdr_handle* h, int* offsets, int cap);
 
 void sdr_destroy(sdr_handle* h);
 

@@ -14,16 +14,37 @@ constexpr int kRowsUpdate = 2048;  // rows per block of the other streaming kern
 constexpr int kUpdateRows = 4;     // rows per thread of the orthogonalisation update
 constexpr int kWaveTileNnz = 512;  // largest staged chunk (entries of 64 rows) per wave of the SpMV
 constexpr int kSpmvLds = 64 * 1024;  // LDS budget of the SpMV kernel: sketch bins + staged chunks
+constexpr int kMaxDiag = 16;       // most diagonals of the stencil (diagonal-storage) SpMV
 
 template <class T> struct Window { const T* p[kMaxWindow]; };
 
-// Host-visible record of one Arnoldi step, written by the least-squares kernel.
+// A matrix whose nonzeros lie on ndiag diagonals (offsets off[d] = column -
+// row), stored diagonal by diagonal: val[d * n + r] = A(r, r + off[d]), zero
+// where r + off[d] falls outside the matrix or the entry is not stored.
+template <class T> struct DiaView {
+  int ndiag;
+  int off[kMaxDiag];
+  const T* val;
+};
+
+// Record of one Arnoldi step, written by the least-squares kernels with
+// plain stores (host-mapped memory; read by the host after the streams are
+// synchronised).
 struct StepRec {
   double sres;
   double nu;
   int32_t j;
   int32_t flags;  // 1 halt, 2 breakdown, 4 rank loss
-  int32_t seq;    // written last: equals j once the record is complete
+  int32_t pad[2];
+};
+
+// Written once by the step that raises the halt flag: its fields, a
+// system-scope fence, then seq (the host resets seq to -1 and waits for it).
+struct HaltRec {
+  double sres;
+  int32_t j;
+  int32_t flags;
+  int32_t seq;
   int32_t pad;
 };
 
@@ -49,6 +70,7 @@ template <class A> struct LsqState {
   double* sres_hist;
   Ctrl* ctrl;
   StepRec* rec;       // host-mapped records, one per step
+  HaltRec* halt;      // host-mapped record of the halting step
 };
 
 // w = A x (if spmv) with per-block partial sums in part (nb blocks of
@@ -62,6 +84,19 @@ void launch_spmv_sketch(hipStream_t st, int n, const int* rp, const int* ci, con
                         T* w, Window<T> win, int tw, SketchSpec sk, bool spmv,
                         typename traits<T>::acc* part, int nb, const Ctrl* ctrl,
                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
+// The same kernel for a matrix in diagonal storage: w = A x with x read at
+// the shifted row r + off[d] (coalesced for every diagonal), no index arrays.
+template <class T>
+void launch_spmv_dia_sketch(hipStream_t st, int n, DiaView<T> A, const T* x, T* w, Window<T> win, int tw,
+                            SketchSpec sk, bool spmv, typename traits<T>::acc* part, int nb,
+                            const Ctrl* ctrl, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
+// dst[map[e]] = src[e] rounded to T (CSR values into diagonal storage; the
+// other positions of dst keep their zeros).
+template <class T>
+void launch_pack_dia(hipStream_t st, int64_t nnz, const typename traits<T>::acc* src, const int* map,
+                     T* dst);
 
 // Prologue: nu[jprev] = ||p_jprev|| and d_q from this step's SpMV partials
 // (part, nb1 blocks, sketch length s: columns s, s+1 .. s+tw).  Then

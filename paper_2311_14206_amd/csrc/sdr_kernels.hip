@@ -19,6 +19,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "sdr_kernels.h"
 
 namespace sdr {
@@ -157,6 +159,38 @@ __device__ __forceinline__ A col_sum(const A* __restrict__ part, int nb, int col
   A sum = zero<A>();
   for (int i = threadIdx.x; i < nb; i += kBlock) sum += part[(int64_t)col * nb + i];
   return block_sum(sum, red);
+}
+
+// Columns c0 .. c0 + nc - 1 (nc <= NMAX) of a partial array at once, each in
+// exactly col_sum's order (so the same bits), with the loads of all columns
+// in flight together and one barrier round for all of them.
+template <class A, int NMAX>
+__device__ __forceinline__ void col_sums(const A* __restrict__ part, int nb, int c0, int nc, A (&out)[NMAX],
+                                         A* red /* NMAX * kWaves */) {
+  A sum[NMAX];
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) sum[c] = zero<A>();
+  for (int i = threadIdx.x; i < nb; i += kBlock) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c)
+      if (c < nc) sum[c] += part[(int64_t)(c0 + c) * nb + i];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) sum[c] = wave_sum(sum[c]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) red[c * kWaves + wv] = sum[c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) {
+    A t = red[c * kWaves];
+    for (int i = 1; i < kWaves; ++i) t += red[c * kWaves + i];
+    out[c] = t;
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ void put_re(double* p, double v) { *p = v; }
@@ -311,6 +345,103 @@ void launch_spmv_sketch(hipStream_t st, int n, const int* rp, const int* ci, con
                        tw, sk, cap, dsp, part, nb, ctrl);
 }
 
+// ------------------------------ diagonal-storage SpMV + products + sketch --
+// Thread-per-row over kRowsSpmv rows per block: every load is coalesced (the
+// ndiag value streams and x shifted by each offset), with nothing staged.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
+    int n, DiaView<T> M, const T* __restrict__ x, T* __restrict__ w, Window<T> win, int tw, SketchSpec sk,
+    int do_spmv, typename traits<T>::acc* __restrict__ part, int nb, const Ctrl* __restrict__ ctrl) {
+  using A = typename traits<T>::acc;
+  if (ctrl->halt) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int s = sk.s;  // 0: no sketch
+  A* bins = reinterpret_cast<A*>(smem_raw) + (threadIdx.x >> 6) * s;
+  __shared__ A red[kWaves];
+  for (int i = threadIdx.x & 63; i < s; i += 64) bins[i] = zero<A>();
+  A d[kMaxWindow];
+#pragma unroll
+  for (int q = 0; q < kMaxWindow; ++q) d[q] = zero<A>();
+  double nw = 0.0, nx = 0.0;
+  const int r0 = blockIdx.x * kRowsSpmv;
+  const int r1 = min(n, r0 + kRowsSpmv);
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+    const A xa = widen(x[r]);
+    if (s > 0) {
+      nx += abs2(xa);
+      sketch_scatter(bins, r, xa, sk);
+    }
+    if (do_spmv) {
+      A acc = zero<A>();
+#pragma unroll
+      for (int k = 0; k < kMaxDiag; ++k) {
+        if (k < M.ndiag) {
+          const int c = r + M.off[k];
+          const T v = M.val[(int64_t)k * n + r];
+          if (c >= 0 && c < n) acc += widen(v) * widen(x[c]);
+        }
+      }
+      const T wt = narrow<T>(acc);
+      w[r] = wt;
+      const A wa = widen(wt);
+      nw += abs2(wa);
+#pragma unroll
+      for (int q = 0; q < kMaxWindow; ++q)
+        if (q < tw) d[q] += conj(q + 1 == tw && win.p[q] == x ? xa : widen(win.p[q][r])) * wa;
+    }
+  }
+  __syncthreads();
+  int c0 = 0;
+  if (s > 0) {
+    A* all = reinterpret_cast<A*>(smem_raw);
+    for (int row = threadIdx.x; row < s; row += kBlock) {
+      A sum = all[row];
+      for (int q = 1; q < kWaves; ++q) sum += all[q * s + row];
+      part[(int64_t)row * nb + blockIdx.x] = sum;
+    }
+    const double sx = block_sum(nx, (double*)red);
+    if (threadIdx.x == 0) put_re(part + (int64_t)s * nb + blockIdx.x, sx);
+    c0 = s + 1;
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxWindow; ++q) {
+    if (q < tw) {
+      const A v = block_sum(d[q], red);
+      if (threadIdx.x == 0) part[(int64_t)(c0 + q) * nb + blockIdx.x] = v;
+    }
+  }
+  const double sw = block_sum(nw, (double*)red);
+  if (threadIdx.x == 0) put_re(part + (int64_t)(c0 + tw) * nb + blockIdx.x, sw);
+}
+
+template <class T>
+void launch_spmv_dia_sketch(hipStream_t st, int n, DiaView<T> M, const T* x, T* w, Window<T> win, int tw,
+                            SketchSpec sk, bool spmv, typename traits<T>::acc* part, int nb,
+                            const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
+  using A = typename traits<T>::acc;
+  const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
+  const int dsp = spmv ? 1 : 0;
+  if (e0)
+    hipExtLaunchKernelGGL(k_spmv_dia_sketch<T>, dim3(nb), dim3(kBlock), lds, st, e0, e1, 0, n, M, x, w, win,
+                          tw, sk, dsp, part, nb, ctrl);
+  else
+    hipLaunchKernelGGL(k_spmv_dia_sketch<T>, dim3(nb), dim3(kBlock), lds, st, n, M, x, w, win, tw, sk, dsp,
+                       part, nb, ctrl);
+}
+
+template <class T>
+__global__ void k_pack_dia(int64_t nnz, const typename traits<T>::acc* __restrict__ src,
+                           const int* __restrict__ map, T* __restrict__ dst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+    dst[map[e]] = narrow<T>(src[e]);
+}
+
+template <class T>
+void launch_pack_dia(hipStream_t st, int64_t nnz, const typename traits<T>::acc* src, const int* map, T* dst) {
+  const int nb = (int)std::min<int64_t>((nnz + kBlock - 1) / kBlock, 65536);
+  hipLaunchKernelGGL(k_pack_dia<T>, dim3(nb > 0 ? nb : 1), dim3(kBlock), 0, st, nnz, src, map, dst);
+}
+
 // ------------------------------------------- truncated orthogonalisation ---
 // Prologue: nu_{j-1} = ||p_{j-1}|| and the window products from the SpMV
 // partials of this step (columns s, s+1 .. s+tw), in the order every reducer
@@ -323,16 +454,17 @@ __global__ __launch_bounds__(kBlock) void k_update(
     int nb1, int s, double* __restrict__ nu, int i0, int jprev, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
   if (ctrl->halt) return;
-  __shared__ A red[kWaves];
-  const double nprev = sqrt(re(col_sum(part, nb1, s, red)));
+  __shared__ A red[(kMaxWindow + 1) * kWaves];
+  A sums[kMaxWindow + 1];
+  col_sums<A, kMaxWindow + 1>(part, nb1, s, tw + 1, sums, red);
+  const double nprev = sqrt(re(sums[0]));
   if (blockIdx.x == 0 && threadIdx.x == 0) nu[jprev] = nprev;
   A c[kMaxWindow];
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) {
     if (q < tw) {
-      const A dq = col_sum(part, nb1, s + 1 + q, red);
       const double nq = i0 + q == jprev ? nprev : nu[i0 + q];
-      c[q] = scale(dq, 1.0 / (nq * nq));
+      c[q] = scale(sums[1 + q], 1.0 / (nq * nq));
     } else {
       c[q] = zero<A>();
     }
@@ -447,6 +579,27 @@ void launch_init_v0(hipStream_t st, const A* red, int s, A* svcol, double* nu) {
 }
 
 // ------------------------------------------------ sketched least squares ---
+// Step record (plain stores; the host reads them after synchronising) and,
+// for the step that halts, the halt record published behind a system-scope
+// fence: one fence per halt, none per step.
+template <class A>
+__device__ __forceinline__ void put_record(const LsqState<A>& S, int j, double sres, double nu, int flags,
+                                           bool halt) {
+  StepRec* rc = S.rec + j;
+  rc->sres = sres;
+  rc->nu = nu;
+  rc->j = j;
+  rc->flags = flags;
+  if (halt) {
+    HaltRec* h = S.halt;
+    h->sres = sres;
+    h->j = j;
+    h->flags = flags;
+    __threadfence_system();
+    __hip_atomic_store(&h->seq, j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 constexpr int kLsqPrefetch = 16;  // staged elements per thread and chunk
 
 // LDS layout of the least-squares kernels: a (s), acc (s), c (2 Lmax), then
@@ -799,14 +952,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step_reg(LsqState<A> S, int j
       S.ctrl->halt_j = j;
       S.ctrl->flags = flags;
     }
-    StepRec* rc = S.rec + j;
-    rc->sres = sres;
-    rc->nu = nuj;
-    rc->j = j;
-    rc->flags = flags;
-    __threadfence_system();
-    __atomic_store_n(&rc->seq, j, __ATOMIC_RELEASE);
-    __threadfence_system();
+    put_record(S, j, sres, nuj, flags, halt);
   }
 }
 
@@ -814,9 +960,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step_reg(LsqState<A> S, int j
 // the projected residual rho in wave 0's registers and the SV columns of the
 // truncation window in an LDS ring, so a step costs its QR append and little
 // else.  The same arithmetic as k_lsq_step_reg, step after step; the launch
-// stops after a step that raises the halt flag.  Step records are stored
-// with seq last (a workgroup release orders the stores); one system-scope
-// fence at the end publishes them all.
+// stops after a step that raises the halt flag.
 template <class A, int RL, int CW>
 __global__ __launch_bounds__(kLsqBlock) void k_lsq_steps_reg(LsqState<A> S, int j0, int j1, int khat,
                                                              int m, int t, int s,
@@ -929,13 +1073,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_steps_reg(LsqState<A> S, int 
           S.ctrl->flags = flags;
         }
         sh_halt = halt;
-        StepRec* rc = S.rec + j;
-        rc->sres = sres;
-        rc->nu = nuj;
-        rc->j = j;
-        rc->flags = flags;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        rc->seq = j;
+        put_record(S, j, sres, nuj, flags, halt);
       }
     }
     __syncthreads();
@@ -948,7 +1086,6 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_steps_reg(LsqState<A> S, int 
       if (r < s) S.rho[r] = rho[rr];
     }
   }
-  if (tid == 0) __threadfence_system();
 }
 
 template <class A, int RL, int CW>
@@ -1070,14 +1207,7 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, in
       S.ctrl->halt_j = j;
       S.ctrl->flags = flags;
     }
-    StepRec* rc = S.rec + j;
-    rc->sres = sres;
-    rc->nu = nuj;
-    rc->j = j;
-    rc->flags = flags;
-    __threadfence_system();
-    __atomic_store_n(&rc->seq, j, __ATOMIC_RELEASE);
-    __threadfence_system();
+    put_record(S, j, sres, nuj, flags, halt);
   }
 }
 
@@ -1510,6 +1640,10 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
   template void launch_spmv_sketch<T>(hipStream_t, int, const int*, const int*, const T*,          \
                                       const T*, T*, Window<T>, int, SketchSpec, bool,             \
                                       traits<T>::acc*, int, const Ctrl*, hipEvent_t, hipEvent_t); \
+  template void launch_spmv_dia_sketch<T>(hipStream_t, int, DiaView<T>, const T*, T*, Window<T>,  \
+                                          int, SketchSpec, bool, traits<T>::acc*, int,           \
+                                          const Ctrl*, hipEvent_t, hipEvent_t);                  \
+  template void launch_pack_dia<T>(hipStream_t, int64_t, const traits<T>::acc*, const int*, T*);   \
   template void launch_update<T>(hipStream_t, int, T*, Window<T>, int, const traits<T>::acc*, int, \
                                  int, double*, int, int, const Ctrl*, hipEvent_t, hipEvent_t);    \
   template void launch_sketch_cols<T>(hipStream_t, int, const T*, int64_t, int, SketchSpec,       \

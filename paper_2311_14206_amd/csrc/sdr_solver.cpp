@@ -83,10 +83,43 @@ struct Options {
   int variant = 0;
   double brtol = -1.0;  // < 0: default for the basis precision
   double rank_rtol = 1e-12;
-  int lookahead = 16;     // Arnoldi steps whose least squares is queued ahead of the host
   int lsq_chunk = 8;      // steps per least-squares launch
   int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
+  int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
 };
+
+// Diagonal layout of a CSR pattern: the distinct offsets column - row (at
+// most kMaxDiag, sorted) and, per stored entry, its position d * n + row in
+// diagonal storage.  Refused (false) for more offsets, for diagonals padded
+// beyond a quarter of nnz, for repeated entries or an index range past int32.
+bool dia_layout(int n, const std::vector<int>& rp, const std::vector<int>& ci, std::vector<int>* offs,
+                std::vector<int>* map) {
+  const int64_t nnz = (int64_t)ci.size();
+  std::vector<int> o;
+  for (int r = 0; r < n; ++r)
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      const int off = ci[e] - r;
+      if (std::find(o.begin(), o.end(), off) == o.end()) {
+        if ((int)o.size() == kMaxDiag) return false;
+        o.push_back(off);
+      }
+    }
+  if (o.empty() || (int64_t)o.size() * n > nnz + nnz / 4 || (int64_t)o.size() * n >= ((int64_t)1 << 31))
+    return false;
+  std::sort(o.begin(), o.end());
+  std::vector<char> seen((size_t)o.size() * n, 0);
+  map->assign((size_t)nnz, 0);
+  for (int r = 0; r < n; ++r)
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      const int d = (int)(std::lower_bound(o.begin(), o.end(), ci[e] - r) - o.begin());
+      const int64_t pos = (int64_t)d * n + r;
+      if (seen[pos]) return false;
+      seen[pos] = 1;
+      (*map)[e] = (int)pos;
+    }
+  *offs = o;
+  return true;
+}
 
 // Matrix view (device, full precision values).
 template <class A>
@@ -118,6 +151,7 @@ struct SolverBase {
   virtual void set_stream(hipStream_t s) = 0;
   virtual void reset() = 0;
   virtual int kernel_times(double* ms, int64_t* counts, int cap) = 0;
+  virtual int spmv_layout(int* offsets, int cap) = 0;
 };
 
 template <class T>
@@ -142,7 +176,6 @@ class Solver final : public SolverBase {
     lmax_ = kmax_ + m + 1;
     const size_t N = (size_t)n_;
     try {
-      if (!kSame) valB_ = dalloc<T>((size_t)mat.nnz);
       Pbuf_[0] = dalloc<T>(N * (m + 1));
       Pbuf_[1] = dalloc<T>(N * (m + 1));
       P_ = Pbuf_[0];
@@ -195,6 +228,8 @@ class Solver final : public SolverBase {
       HIPCHK(hipHostMalloc((void**)&rec_host_, sizeof(StepRec) * (m + 2),
                            hipHostMallocMapped | hipHostMallocCoherent));
       HIPCHK(hipHostGetDevicePointer((void**)&rec_dev_, rec_host_, 0));
+      HIPCHK(hipHostMalloc((void**)&halt_host_, sizeof(HaltRec), hipHostMallocMapped | hipHostMallocCoherent));
+      HIPCHK(hipHostGetDevicePointer((void**)&halt_dev_, halt_host_, 0));
       HIPCHK(hipHostMalloc((void**)&hR_, sizeof(A) * (size_t)lmax_ * lmax_, hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hC_, sizeof(A) * (size_t)lmax_ * lmax_, hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hz_, sizeof(A) * (size_t)lmax_, hipHostMallocDefault));
@@ -210,6 +245,21 @@ class Solver final : public SolverBase {
       HIPCHK(hipStreamSynchronize(stream_));
       HIPCHK(hipMemsetAsync(redb_, 0, sizeof(A) * slotr_ * nslot_, stream_));
       HIPCHK(hipStreamSynchronize(stream_));
+      if (opt.dia) {
+        std::vector<int> rp(n_ + 1), ci((size_t)mat.nnz), offs, map;
+        HIPCHK(hipMemcpy(rp.data(), mat.rp, sizeof(int) * (n_ + 1), hipMemcpyDeviceToHost));
+        if (mat.nnz) HIPCHK(hipMemcpy(ci.data(), mat.ci, sizeof(int) * mat.nnz, hipMemcpyDeviceToHost));
+        if (mat.nnz && dia_layout(n_, rp, ci, &offs, &map)) {
+          dia_.ndiag = (int)offs.size();
+          for (int d = 0; d < dia_.ndiag; ++d) dia_.off[d] = offs[d];
+          dia_map_ = dalloc<int>(map.size());
+          diaval_ = dalloc<T>((size_t)dia_.ndiag * n_);
+          HIPCHK(hipMemcpy(dia_map_, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
+          HIPCHK(hipMemset(diaval_, 0, sizeof(T) * (size_t)dia_.ndiag * n_));
+          dia_.val = diaval_;
+        }
+      }
+      if (!kSame && !dia()) valB_ = dalloc<T>((size_t)mat.nnz);  // CSR values in the basis precision
     } catch (...) {
       release();
       throw;
@@ -228,7 +278,19 @@ class Solver final : public SolverBase {
     if (opt_.variant == 0) sau_stale_ = true;
   }
 
+  bool dia() const { return dia_.ndiag > 0; }
+
+  // Matrix values for the basis SpMV: diagonal storage (packed on change) or
+  // CSR values in the basis precision.
   const T* basis_values() {
+    if (dia()) {
+      if (low_dirty_) {
+        launch_pack_dia<T>(stream_, M_.nnz, M_.val, dia_map_, diaval_);
+        LAUNCHCHK();
+        low_dirty_ = false;
+      }
+      return diaval_;
+    }
     if (kSame) return reinterpret_cast<const T*>(M_.val);
     if (low_dirty_) {
       launch_narrow_values<T>(stream_, M_.nnz, M_.val, valB_);
@@ -296,6 +358,7 @@ class Solver final : public SolverBase {
     S.sres_hist = sres_hist_;
     S.ctrl = ctrl_;
     S.rec = rec_dev_;
+    S.halt = halt_dev_;
     return S;
   }
 
@@ -321,8 +384,12 @@ class Solver final : public SolverBase {
     for (int q = 0; q < tw; ++q) win.p[q] = P_ + (size_t)(i0 + q) * n_;
     T* w = P_ + (size_t)j * n_;
     const bool tm = timed(j);
-    launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
-                          tm ? ev_[j][0] : nullptr, tm ? ev_[j][1] : nullptr);
+    if (dia())
+      launch_spmv_dia_sketch<T>(stream_, n_, dia_, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
+                                tm ? ev_[j][0] : nullptr, tm ? ev_[j][1] : nullptr);
+    else
+      launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
+                            tm ? ev_[j][0] : nullptr, tm ? ev_[j][1] : nullptr);
     LAUNCHCHK();
     if (ev) HIPCHK(hipEventRecord(evs_[sl], stream_));
     launch_update<T>(stream_, n_, w, win, tw, p1, nb1_, s_, nu_, i0, j - 1, ctrl_,
@@ -356,16 +423,15 @@ class Solver final : public SolverBase {
     HIPCHK(hipStreamSynchronize(streamB_));
   }
 
-  // Wait for the record of step j; returns false if it never arrives.
-  bool wait_record(int j, StepRec& out) {
-    volatile StepRec* rc = rec_host_ + j;
+  // Wait for the halt record; returns false if the streams drain without one.
+  bool wait_halt(HaltRec& out) {
     long spins = 0;
     for (;;) {
-      if (__atomic_load_n(&rec_host_[j].seq, __ATOMIC_ACQUIRE) == j) {
-        out.sres = rc->sres;
-        out.nu = rc->nu;
-        out.j = rc->j;
-        out.flags = rc->flags;
+      if (__atomic_load_n(&halt_host_->seq, __ATOMIC_ACQUIRE) >= 0) {
+        volatile HaltRec* h = halt_host_;
+        out.sres = h->sres;
+        out.j = h->j;
+        out.flags = h->flags;
         return true;
       }
       if (++spins % 4096 == 0) {
@@ -380,11 +446,22 @@ class Solver final : public SolverBase {
           throw HipError{SDR_EDEVICE};
         }
         if (qa == hipSuccess && qb == hipSuccess) {
-          if (__atomic_load_n(&rec_host_[j].seq, __ATOMIC_ACQUIRE) == j) continue;
+          if (__atomic_load_n(&halt_host_->seq, __ATOMIC_ACQUIRE) >= 0) continue;
           return false;
         }
       }
     }
+  }
+
+  // Queue the rest of the cycle from step j0: the Arnoldi steps (with
+  // events at chunk ends) and the least-squares chunks behind them.
+  void enqueue_from(int j0, int& enqA, const T* vals) {
+    const int base = j0;
+    while (enqA < m_ + 1) {
+      ++enqA;
+      enqueue_step_a(enqA, vals, needs_event(enqA, base));
+    }
+    for (int c0 = j0; c0 <= m_; c0 += opt_.lsq_chunk) enqueue_chunk(c0, std::min(c0 + opt_.lsq_chunk - 1, m_));
   }
 
   // y = R^{-1} z for the leading (khat + j) block, on the host (a sequential
@@ -450,9 +527,13 @@ class Solver final : public SolverBase {
       // exact variant: S A_i U with the new matrix (k products and sketches)
       for (int c = 0; c < khat_; ++c) {
         Window<T> win{};
-        launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, U_ + (size_t)c * n_,
-                              Unew_ + (size_t)c * n_, win, 0, SketchSpec{}, true, part1_, nb1_,
-                              ctrl_free_);
+        if (dia())
+          launch_spmv_dia_sketch<T>(stream_, n_, dia_, U_ + (size_t)c * n_, Unew_ + (size_t)c * n_, win, 0,
+                                    SketchSpec{}, true, part1_, nb1_, ctrl_free_);
+        else
+          launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, U_ + (size_t)c * n_,
+                                Unew_ + (size_t)c * n_, win, 0, SketchSpec{}, true, part1_, nb1_,
+                                ctrl_free_);
         LAUNCHCHK();
       }
       sketch_cols<T>(Unew_, khat_, SAU_, s_, nullptr);
@@ -479,12 +560,12 @@ class Solver final : public SolverBase {
       ips++;
       launch_cast_scale<T>(stream_, n_, r_, rn > 0.0 ? 1.0 / rn : 1.0, P_);  // p_0 = r0 / ||r0||
       last_sv_ = SB_ + (size_t)kmax_ * s_;
-      for (int j = 0; j <= m_ + 1; ++j) __atomic_store_n(&rec_host_[j].seq, -1, __ATOMIC_RELEASE);
+      __atomic_store_n(&halt_host_->seq, -1, __ATOMIC_RELEASE);
       launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
       LAUNCHCHK();
       // step 1's SpMV sketches p_0; stream B starts behind it with SV(:, 0) and nu_0
       enqueue_step_a(1, vals, true);
-      int enqA = 1, enqB = 0, base = 1;
+      int enqA = 1;
       HIPCHK(hipStreamWaitEvent(streamB_, evs_[1 % nslot_], 0));
       launch_reduce_cols<A>(streamB_, part1_ + slot1_ * (1 % nslot_), nb1_, s_ + 1, s_,
                             1.0 / std::sqrt((double)sk_.zeta), red0_, nullptr);
@@ -494,7 +575,7 @@ class Solver final : public SolverBase {
         // The Arnoldi basis of this cycle does not depend on the recycle space
         // (V spans K_m(A, r0)): the previous cycle's eigen-step runs on a
         // worker thread while this one queues the cycle's steps.
-        for (int j = 2; j <= m_ + 1; ++j) enqueue_step_a(j, vals, needs_event(j, base));
+        for (int j = 2; j <= m_ + 1; ++j) enqueue_step_a(j, vals, needs_event(j, 1));
         enqA = m_ + 1;
         EigResult er = take_eig();
         eig_time += er.seconds;
@@ -513,31 +594,26 @@ class Solver final : public SolverBase {
       bool early = false;
       double res = 0.0, sres = 0.0;
       bool cyc_conv = false;
+      enqueue_from(1, enqA, vals);
       for (;;) {
-        const int upto = std::min(m_, done + std::max(opt_.lookahead, 1));
-        while (enqB < upto) {
-          const int j0 = enqB + 1, j1 = std::min(j0 + opt_.lsq_chunk - 1, m_);
-          while (enqA < j1 + 1) {  // step j+1 sketches p_j
-            ++enqA;
-            enqueue_step_a(enqA, vals, needs_event(enqA, base));
-          }
-          enqueue_chunk(j0, j1);
-          enqB = j1;
-        }
-        StepRec rc;
-        if (!wait_record(done + 1, rc)) {
-          set_err("step record missing");
+        HaltRec hr;
+        if (!wait_halt(hr)) {
+          set_err("halt record missing");
           throw HipError{SDR_EDEVICE};
         }
-        ++done;
-        const int tw = done - std::max(done - t_, 0);
-        matvecs++;
-        ips += tw + 1;
-        iters++;
-        if (!(rc.flags & 2)) sketches++;
+        sync_both();  // every step record up to hr.j is complete
+        StepRec rc{};
+        while (done < hr.j) {
+          ++done;
+          rc = rec_host_[done];
+          const int tw = done - std::max(done - t_, 0);
+          matvecs++;
+          ips += tw + 1;
+          iters++;
+          if (!(rc.flags & 2)) sketches++;
+        }
         sres = rc.sres;
-        if (rc.flags & 1) {
-          sync_both();
+        {
           if (done == m_) {
             // the cycle ends here whatever the check says: its eigen-step
             // starts now and runs beside the check
@@ -571,8 +647,9 @@ class Solver final : public SolverBase {
           // resume: the steps after `done` may have been skipped by the halt
           launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
           LAUNCHCHK();
-          enqA = enqB = done;
-          base = done + 1;
+          __atomic_store_n(&halt_host_->seq, -1, __ATOMIC_RELEASE);
+          enqA = done;
+          enqueue_from(done + 1, enqA, vals);
         }
       }
       cycles++;
@@ -793,7 +870,8 @@ class Solver final : public SolverBase {
  private:
   void release() {
     if (eig_fut_.valid()) eig_fut_.wait();
-    for (void* p : {(void*)valB_, (void*)Pbuf_[0], (void*)Pbuf_[1], (void*)U_, (void*)Unew_, (void*)SU_,
+    for (void* p : {(void*)valB_, (void*)dia_map_, (void*)diaval_, (void*)Pbuf_[0], (void*)Pbuf_[1],
+                    (void*)U_, (void*)Unew_, (void*)SU_,
                     (void*)red0_,
                     (void*)SAU_, (void*)Q_, (void*)R_, (void*)z_, (void*)rho_, (void*)SBbuf_[0],
                     (void*)SBbuf_[1], (void*)SAWbuf_[0], (void*)SAWbuf_[1], (void*)H_,
@@ -804,6 +882,8 @@ class Solver final : public SolverBase {
       dfree(p);
     if (rec_host_) (void)hipHostFree(rec_host_);
     rec_host_ = nullptr;
+    if (halt_host_) (void)hipHostFree(halt_host_);
+    halt_host_ = nullptr;
     for (void* p : {(void*)hR_, (void*)hC_, (void*)hz_, (void*)hy_, (void*)hnu_, (void*)hG_,
                     (void*)hRc_, (void*)hnuc_,
                     (void*)hscal_})
@@ -833,6 +913,9 @@ class Solver final : public SolverBase {
   int khat_ = 0, khat_prev_ = 0;
   bool sau_stale_ = false, low_dirty_ = true;
   T* valB_ = nullptr;
+  DiaView<T> dia_{};      // diagonal storage of the basis-precision matrix (ndiag 0: CSR)
+  int* dia_map_ = nullptr;
+  T* diaval_ = nullptr;
   T *P_ = nullptr, *U_ = nullptr, *Unew_ = nullptr;
   T* Pbuf_[2] = {nullptr, nullptr};
   A* SBbuf_[2] = {nullptr, nullptr};
@@ -861,6 +944,7 @@ class Solver final : public SolverBase {
   A *Sr_ = nullptr, *ycoef_ = nullptr, *xt_ = nullptr, *r_ = nullptr, *rnew_ = nullptr;
   A *G_ = nullptr, *Gs_ = nullptr, *C_ = nullptr;
   StepRec *rec_host_ = nullptr, *rec_dev_ = nullptr;
+  HaltRec *halt_host_ = nullptr, *halt_dev_ = nullptr;
   // pinned host staging of the small dense data
   A *hR_ = nullptr, *hC_ = nullptr, *hz_ = nullptr, *hy_ = nullptr, *hG_ = nullptr, *hscal_ = nullptr,
     *hRc_ = nullptr;
@@ -875,6 +959,12 @@ class Solver final : public SolverBase {
   void reset() override {
     khat_ = 0;
     sau_stale_ = false;
+  }
+
+  int spmv_layout(int* offsets, int cap) override {
+    for (int d = 0; d < dia_.ndiag && d < cap; ++d)
+      if (offsets) offsets[d] = dia_.off[d];
+    return dia_.ndiag;
   }
 
   // [0] SpMV + sketch ms, [1] update ms, [2] both kernels of a step (SpMV start to update end);
@@ -1126,9 +1216,9 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
   } else if (k == "kernel_timing") {
     if (built || !(v >= 0.0 && v <= 1e6)) return set_err("kernel_timing in [0,1e6], before the first solve"), SDR_EINVAL;
     h->opt.kernel_timing = (int)v;
-  } else if (k == "lookahead") {
-    if (built || v < 1 || v > 1024) return set_err("lookahead in [1,1024], before the first solve"), SDR_EINVAL;
-    h->opt.lookahead = (int)v;
+  } else if (k == "dia") {
+    if (built || (v != 0.0 && v != 1.0)) return set_err("dia is 0 or 1, before the first solve"), SDR_EINVAL;
+    h->opt.dia = (int)v;
   } else if (k == "lsq_chunk") {
     if (built || v < 1 || v > 64) return set_err("lsq_chunk in [1,64], before the first solve"), SDR_EINVAL;
     h->opt.lsq_chunk = (int)v;
@@ -1295,6 +1385,15 @@ int sdr_kernel_times(sdr_handle* h, double* ms, int64_t* counts, int cap) {
   if (!h) return set_err("null handle"), SDR_EINVAL;
   try {
     return fwd(h)->kernel_times(ms, counts, cap);
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_spmv_layout(sdr_handle* h, int* offsets, int cap) {
+  if (!h) return set_err("null handle"), SDR_EINVAL;
+  try {
+    return fwd(h)->spmv_layout(offsets, cap);
   } catch (HipError& e) {
     return e.code;
   }

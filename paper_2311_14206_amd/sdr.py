@@ -63,6 +63,7 @@ EXPORTS = {
     "sdr_get_basis": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sdr_reset": (C.c_int, [C.c_void_p]),
     "sdr_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
+    "sdr_spmv_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int]),
     "sdr_destroy": (None, [C.c_void_p]),
     "sdr_last_error": (C.c_char_p, []),
     "sdr_host_harmonic_ritz": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
@@ -216,6 +217,12 @@ class SDRSolver:
         _check(lib().sdr_kernel_times(self.h, ms, cnt, 8), "sdr_kernel_times")
         return {"spmv_sketch_ms": ms[0], "update_ms": ms[1], "step_ms": ms[2],
                 "launches": cnt[0], "window_hist": [cnt[3 + i] for i in range(5)]}
+
+    def spmv_layout(self):
+        """Diagonal offsets of the basis SpMV's storage ([] for CSR)."""
+        off = (C.c_int * 16)()
+        nd = _check(lib().sdr_spmv_layout(self.h, off, 16), "sdr_spmv_layout")
+        return [off[i] for i in range(nd)]
 
     def trace(self):
         n = _check(lib().sdr_get_trace(self.h, None, 0), "sdr_get_trace")

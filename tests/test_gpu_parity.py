@@ -71,12 +71,14 @@ def test_sketch_operator_bit_identical(N, s, zeta):
     assert np.linalg.norm(Y - ref) <= 1e-14 * np.linalg.norm(ref)
 
 
-def test_first_arnoldi_steps_match_oracle():
-    """Truncated Arnoldi basis, H and SV of the first steps (per kernel, FP64)."""
+@pytest.mark.parametrize("dia", [1, 0])
+def test_first_arnoldi_steps_match_oracle(dia):
+    """Truncated Arnoldi basis, H and SV of the first steps (per kernel, FP64),
+    with the stencil stored by diagonals (dia=1) and as CSR (dia=0)."""
     A = cd2d_upwind(50)
     b = randn(A.n, 1)
     m = 6
-    h = _solver(A, m=m, k=3, t=2, s=64, max_cycles=1)
+    h = _solver(A, m=m, k=3, t=2, s=64, max_cycles=1, dia=dia)
     h.solve(_dev(b), tol=1e-15)
     V, H, SV = h.basis(m + 1)
     keep = []
@@ -114,7 +116,8 @@ def _assert_trace_and_x(xg, st, tr, ref, tol_x=1e-8, strict=True, A=None, b=None
     div = None
     for i, (cg, co) in enumerate(zip(tr, ref.trace)):
         same = (cg["j_stop"] == co.j_stop and cg["n_checks"] == len(co.checks)
-                and cg["k_eff"] == co.k_eff)
+                and cg["k_eff"] == co.k_eff
+                and bool(cg["flags"] & 2) == co.breakdown and bool(cg["flags"] & 4) == co.rank_loss)
         if not same:
             div = i
             break
@@ -137,10 +140,12 @@ def _assert_trace_and_x(xg, st, tr, ref, tol_x=1e-8, strict=True, A=None, b=None
     assert np.linalg.norm(xg - ref.x) <= tol_x * np.linalg.norm(ref.x)
 
 
-def test_solve_cd2d_64_matches_oracle():
-    """The 64x64 convection-diffusion solve (m=50, k=10, t=2, s=120, tol 1e-8)."""
+@pytest.mark.parametrize("dia", [1, 0])
+def test_solve_cd2d_64_matches_oracle(dia):
+    """The 64x64 convection-diffusion solve (m=50, k=10, t=2, s=120, tol 1e-8),
+    SpMV on diagonal storage (dia=1) and on CSR (dia=0)."""
     A, b, p = workload("cd2d_64")
-    h, xg, st, tr, ref = _compare_solve(A, b, p, p["tol"])
+    h, xg, st, tr, ref = _compare_solve(A, b, p, p["tol"], extra=dict(dia=dia))
     _assert_trace_and_x(xg, st, tr, ref)
     r = b - A.to_scipy() @ xg
     assert np.linalg.norm(r) <= p["tol"] * np.linalg.norm(b)
@@ -153,6 +158,37 @@ def test_solve_ragged_sizes_match_oracle(n, m, k, t, s):
     h, xg, st, tr, ref = _compare_solve(A, b, dict(m=m, k=k, t=t, s=s), 1e-9)
     # t = 1 with 40 steps: cond(SAW) reaches ~1e13 in the second cycle
     _assert_trace_and_x(xg, st, tr, ref, strict=(t > 1), A=A, b=b, tol=1e-9)
+
+
+def _general_sparse(n, seed):
+    """A nonsymmetric matrix with no stencil structure: random columns, a few
+    rows far longer than the rest (more entries per 64-row chunk than the SpMV
+    stages), shifted by 3 I (spectrum in a disc about 3 of radius ~2.5: a
+    well-conditioned sketched least squares over several cycles)."""
+    g = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(n):
+        k = 300 if 100 <= i < 104 else 6
+        c = g.choice(n, size=k, replace=False)
+        rows.extend([i] * k)
+        cols.extend(c.tolist())
+    vals = g.standard_normal(len(rows))
+    M = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    M.sum_duplicates()
+    return CSR.from_scipy(M + 3.0 * sp.identity(n))
+
+
+def test_solve_general_sparse_pattern_matches_oracle():
+    """A pattern with no diagonal structure takes the CSR SpMV (coalesced
+    staging, and the row-by-row path for chunks with long rows)."""
+    A = _general_sparse(3000, 17)
+    b = randn(A.n, 5)
+    h, xg, st, tr, ref = _compare_solve(A, b, dict(m=30, k=6, t=2, s=80), 1e-9)
+    assert len(ref.trace) > 2  # several cycles with a recycle space
+    _assert_trace_and_x(xg, st, tr, ref)
+    y = _host(h.spmv(_dev(b)))
+    ref_y = A.to_scipy() @ b
+    assert np.linalg.norm(y - ref_y) <= 1e-14 * np.linalg.norm(ref_y)
 
 
 def test_solve_complex_helmholtz_matches_oracle():
