@@ -11,7 +11,7 @@ constexpr int kLsqBlock = 512;     // threads of the single-block least-squares 
 constexpr int kMaxWindow = 4;      // largest truncation window t
 constexpr int kRowsSpmv = 1024;    // rows per block, SpMV + window products + sketch
 constexpr int kRowsUpdate = 2048;  // rows per block of the other streaming kernels
-constexpr int kUpdateRows = 4;     // rows per thread of the orthogonalisation update
+constexpr int kUpdateRows = 4;     // rows per thread of the update (tiles of kRowsSpmv rows, as the SpMV)
 constexpr int kWaveTileNnz = 512;  // largest staged chunk (entries of 64 rows) per wave of the SpMV
 constexpr int kSpmvLds = 64 * 1024;  // LDS budget of the SpMV kernel: sketch bins + staged chunks
 constexpr int kMaxDiag = 16;       // most diagonals of the stencil (diagonal-storage) SpMV

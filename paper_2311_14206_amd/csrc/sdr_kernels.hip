@@ -154,10 +154,20 @@ __device__ __forceinline__ void sketch_scatter(A* acc, int64_t col, A v, const S
 // Column sum of a [ncols x nb] partial array in the order every reducer of
 // this library uses (thread-strided, then the fixed block tree), so that the
 // same partials always give the same bits.
+// Loads go out four at a time (indices clamped into range, so none sits
+// behind a branch) and are added in index order.
 template <class A>
 __device__ __forceinline__ A col_sum(const A* __restrict__ part, int nb, int col, A* red) {
+  const A* p = part + (int64_t)col * nb;
   A sum = zero<A>();
-  for (int i = threadIdx.x; i < nb; i += kBlock) sum += part[(int64_t)col * nb + i];
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 4 * kBlock) {
+    A v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = p[min(i0 + u * kBlock, nb - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * kBlock < nb) sum += v[u];
+  }
   return block_sum(sum, red);
 }
 
@@ -170,10 +180,22 @@ __device__ __forceinline__ void col_sums(const A* __restrict__ part, int nb, int
   A sum[NMAX];
 #pragma unroll
   for (int c = 0; c < NMAX; ++c) sum[c] = zero<A>();
-  for (int i = threadIdx.x; i < nb; i += kBlock) {
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 4 * kBlock) {
+    A v[4][NMAX];  // columns past nc re-read column nc - 1 and are not added
 #pragma unroll
-    for (int c = 0; c < NMAX; ++c)
-      if (c < nc) sum[c] += part[(int64_t)(c0 + c) * nb + i];
+    for (int u = 0; u < 4; ++u) {
+      const int i = min(i0 + u * kBlock, nb - 1);
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) v[u][c] = part[(int64_t)(c0 + min(c, nc - 1)) * nb + i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + u * kBlock < nb) {
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c)
+          if (c < nc) sum[c] += v[u][c];
+      }
+    }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -195,6 +217,19 @@ __device__ __forceinline__ void col_sums(const A* __restrict__ part, int nb, int
 
 __device__ __forceinline__ void put_re(double* p, double v) { *p = v; }
 __device__ __forceinline__ void put_re(cx<double>* p, double v) { *p = cx<double>{v, 0.0}; }
+
+// Row tile of a block in the streaming kernels.  Workgroups are dispatched
+// to the 8 XCDs round robin, each XCD with its own L2: tile t of nb goes to
+// the block that lands on XCD t / ceil-share, so an XCD works on a contiguous
+// range of tiles.  An SpMV's halo rows then sit in the same L2, and the
+// update kernel, tiled the same way, finds the vectors the SpMV just wrote
+// there.  A bijection of [0, nb) for any nb.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int q = nb / kXcd, r = nb % kXcd;
+  const int x = b % kXcd, k = b / kXcd;
+  return x * q + (x < r ? x : r) + k;
+}
 
 // --------------------------------- SpMV + window products + input sketch --
 // Each wave works on its own chunks of 64 rows, with no block barrier inside
@@ -223,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sketch(
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) d[q] = zero<A>();
   double nw = 0.0, nx = 0.0;
-  const int r0 = blockIdx.x * kRowsSpmv;
+  const int tile = xcd_tile(blockIdx.x, nb);  // partial sums are stored by tile
+  const int r0 = tile * kRowsSpmv;
   const int r1 = min(n, r0 + kRowsSpmv);
   for (int t0 = r0 + 64 * wv; t0 < r1; t0 += kBlock) {
     const int t1 = min(r1, t0 + 64);
@@ -303,21 +339,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sketch(
     for (int row = threadIdx.x; row < s; row += kBlock) {
       A sum = all[row];
       for (int q = 1; q < kWaves; ++q) sum += all[q * s + row];
-      part[(int64_t)row * nb + blockIdx.x] = sum;
+      part[(int64_t)row * nb + tile] = sum;
     }
     const double sx = block_sum(nx, (double*)red);
-    if (threadIdx.x == 0) put_re(part + (int64_t)s * nb + blockIdx.x, sx);
+    if (threadIdx.x == 0) put_re(part + (int64_t)s * nb + tile, sx);
     c0 = s + 1;
   }
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) {
     if (q < tw) {
       const A v = block_sum(d[q], red);
-      if (threadIdx.x == 0) part[(int64_t)(c0 + q) * nb + blockIdx.x] = v;
+      if (threadIdx.x == 0) part[(int64_t)(c0 + q) * nb + tile] = v;
     }
   }
   const double sw = block_sum(nw, (double*)red);
-  if (threadIdx.x == 0) put_re(part + (int64_t)(c0 + tw) * nb + blockIdx.x, sw);
+  if (threadIdx.x == 0) put_re(part + (int64_t)(c0 + tw) * nb + tile, sw);
 }
 
 template <class T>
@@ -346,13 +382,19 @@ void launch_spmv_sketch(hipStream_t st, int n, const int* rp, const int* ci, con
 }
 
 // ------------------------------ diagonal-storage SpMV + products + sketch --
-// Thread-per-row over kRowsSpmv rows per block: every load is coalesced (the
-// ndiag value streams and x shifted by each offset), with nothing staged.
-template <class T>
+// Thread per row over kRowsSpmv rows per block.  Every load is coalesced (the
+// value streams, x shifted by each offset, the window vectors) and none sits
+// behind a branch: column indices are clamped into [0, n) and the terms that
+// fall outside the matrix are dropped by a select, so all loads of a row are
+// in flight together before the sketch's LDS atomics and the arithmetic.
+// ND > 0 fixes the number of diagonals at compile time (the common stencils);
+// ND == 0 reads it from M.
+template <class T, int ND>
 __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
     int n, DiaView<T> M, const T* __restrict__ x, T* __restrict__ w, Window<T> win, int tw, SketchSpec sk,
     int do_spmv, typename traits<T>::acc* __restrict__ part, int nb, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
+  constexpr int KD = ND > 0 ? ND : kMaxDiag;
   if (ctrl->halt) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = sk.s;  // 0: no sketch
@@ -363,22 +405,45 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) d[q] = zero<A>();
   double nw = 0.0, nx = 0.0;
-  const int r0 = blockIdx.x * kRowsSpmv;
+  const int tile = xcd_tile(blockIdx.x, nb);  // partial sums are stored by tile
+  const int r0 = tile * kRowsSpmv;
   const int r1 = min(n, r0 + kRowsSpmv);
-  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
-    const A xa = widen(x[r]);
-    if (s > 0) {
+  if (!do_spmv) {
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+      const A xa = widen(x[r]);
       nx += abs2(xa);
       sketch_scatter(bins, r, xa, sk);
     }
-    if (do_spmv) {
+  } else {
+    const int nd = ND > 0 ? ND : M.ndiag;
+    // In an Arnoldi step the newest window vector is x itself: its value is
+    // already in a register.
+    const int tl = (tw > 0 && win.p[tw - 1] == x) ? tw - 1 : tw;
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+      const T xt = x[r];
+      T vv[KD], xc[KD], pw[kMaxWindow];
+#pragma unroll
+      for (int q = 0; q < kMaxWindow; ++q)
+        if (q < tl) pw[q] = win.p[q][r];
+#pragma unroll
+      for (int k = 0; k < KD; ++k) {
+        if (ND > 0 || k < nd) {
+          vv[k] = M.val[(int64_t)k * n + r];
+          xc[k] = x[min(max(r + M.off[k], 0), n - 1)];
+        }
+      }
+      const A xa = widen(xt);
+      if (s > 0) {
+        nx += abs2(xa);
+        sketch_scatter(bins, r, xa, sk);
+      }
       A acc = zero<A>();
 #pragma unroll
-      for (int k = 0; k < kMaxDiag; ++k) {
-        if (k < M.ndiag) {
+      for (int k = 0; k < KD; ++k) {
+        if (ND > 0 || k < nd) {
           const int c = r + M.off[k];
-          const T v = M.val[(int64_t)k * n + r];
-          if (c >= 0 && c < n) acc += widen(v) * widen(x[c]);
+          const A t = widen(vv[k]) * widen(xc[k]);
+          acc += (c >= 0 && c < n) ? t : zero<A>();
         }
       }
       const T wt = narrow<T>(acc);
@@ -387,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
       nw += abs2(wa);
 #pragma unroll
       for (int q = 0; q < kMaxWindow; ++q)
-        if (q < tw) d[q] += conj(q + 1 == tw && win.p[q] == x ? xa : widen(win.p[q][r])) * wa;
+        if (q < tw) d[q] += conj(q < tl ? widen(pw[q]) : xa) * wa;
     }
   }
   __syncthreads();
@@ -397,21 +462,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
     for (int row = threadIdx.x; row < s; row += kBlock) {
       A sum = all[row];
       for (int q = 1; q < kWaves; ++q) sum += all[q * s + row];
-      part[(int64_t)row * nb + blockIdx.x] = sum;
+      part[(int64_t)row * nb + tile] = sum;
     }
     const double sx = block_sum(nx, (double*)red);
-    if (threadIdx.x == 0) put_re(part + (int64_t)s * nb + blockIdx.x, sx);
+    if (threadIdx.x == 0) put_re(part + (int64_t)s * nb + tile, sx);
     c0 = s + 1;
   }
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) {
     if (q < tw) {
       const A v = block_sum(d[q], red);
-      if (threadIdx.x == 0) part[(int64_t)(c0 + q) * nb + blockIdx.x] = v;
+      if (threadIdx.x == 0) part[(int64_t)(c0 + q) * nb + tile] = v;
     }
   }
   const double sw = block_sum(nw, (double*)red);
-  if (threadIdx.x == 0) put_re(part + (int64_t)(c0 + tw) * nb + blockIdx.x, sw);
+  if (threadIdx.x == 0) put_re(part + (int64_t)(c0 + tw) * nb + tile, sw);
 }
 
 template <class T>
@@ -421,12 +486,19 @@ void launch_spmv_dia_sketch(hipStream_t st, int n, DiaView<T> M, const T* x, T* 
   using A = typename traits<T>::acc;
   const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
   const int dsp = spmv ? 1 : 0;
+  void (*kern)(int, DiaView<T>, const T*, T*, Window<T>, int, SketchSpec, int, A*, int, const Ctrl*);
+  switch (M.ndiag) {
+    case 3: kern = k_spmv_dia_sketch<T, 3>; break;
+    case 5: kern = k_spmv_dia_sketch<T, 5>; break;
+    case 7: kern = k_spmv_dia_sketch<T, 7>; break;
+    case 9: kern = k_spmv_dia_sketch<T, 9>; break;
+    default: kern = k_spmv_dia_sketch<T, 0>; break;
+  }
   if (e0)
-    hipExtLaunchKernelGGL(k_spmv_dia_sketch<T>, dim3(nb), dim3(kBlock), lds, st, e0, e1, 0, n, M, x, w, win,
-                          tw, sk, dsp, part, nb, ctrl);
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), lds, st, e0, e1, 0, n, M, x, w, win, tw, sk, dsp,
+                          part, nb, ctrl);
   else
-    hipLaunchKernelGGL(k_spmv_dia_sketch<T>, dim3(nb), dim3(kBlock), lds, st, n, M, x, w, win, tw, sk, dsp,
-                       part, nb, ctrl);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), lds, st, n, M, x, w, win, tw, sk, dsp, part, nb, ctrl);
 }
 
 template <class T>
@@ -455,6 +527,18 @@ __global__ __launch_bounds__(kBlock) void k_update(
   using A = typename traits<T>::acc;
   if (ctrl->halt) return;
   __shared__ A red[(kMaxWindow + 1) * kWaves];
+  // The stream's loads go out first (clamped rows, unused past n) and are in
+  // flight while the block reduces the partials.
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * (kBlock * kUpdateRows) + (int)threadIdx.x;
+  T wv[kUpdateRows], pv[kUpdateRows][kMaxWindow];
+#pragma unroll
+  for (int u = 0; u < kUpdateRows; ++u) {
+    const int r = min(base + u * kBlock, n - 1);
+    wv[u] = w[r];
+#pragma unroll
+    for (int q = 0; q < kMaxWindow; ++q)
+      if (q < tw) pv[u][q] = win.p[q][r];
+  }
   A sums[kMaxWindow + 1];
   col_sums<A, kMaxWindow + 1>(part, nb1, s, tw + 1, sums, red);
   const double nprev = sqrt(re(sums[0]));
@@ -470,15 +554,14 @@ __global__ __launch_bounds__(kBlock) void k_update(
     }
   }
   const double inv = 1.0 / nprev;
-  const int base = blockIdx.x * (kBlock * kUpdateRows) + (int)threadIdx.x;
 #pragma unroll
   for (int u = 0; u < kUpdateRows; ++u) {
     const int r = base + u * kBlock;
     if (r < n) {
-      A v = widen(w[r]);
+      A v = widen(wv[u]);
 #pragma unroll
       for (int q = 0; q < kMaxWindow; ++q)
-        if (q < tw) v -= c[q] * widen(win.p[q][r]);
+        if (q < tw) v -= c[q] * widen(pv[u][q]);
       w[r] = narrow<T>(scale(v, inv));
     }
   }
