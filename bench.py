@@ -13,13 +13,27 @@ in HBM before the timed region.  Prints one JSON line:
   algorithmic bytes per launch / its mean duration from HIP events recorded
   by the dispatches themselves on the library's stream inside the timed
   region, on every 16th Arnoldi step (--timing-every);
+* roofline.traffic: HBM bytes per launch of that kernel from rocprofv3
+  FETCH_SIZE and WRITE_SIZE counters, scaled by what the same counters read
+  for a device copy of known size, taken from the committed summary
+  profiles/<kernel>_<workload>_hbm_traffic.md; null when the kernel sources
+  differ from the ones the counters were taken on (a digest of the sources is
+  stored with the figures);
 * cpu_baseline: the FP64 oracle on the host cores, timed on one 100-step
   cycle of the same solve and scaled to the solve's Arnoldi steps.
+
+    python bench.py --summarize-pmc FETCH.csv WRITE.csv --copy-calib-mb 256
+
+writes that summary (markdown) from the counter CSVs of two rocprofv3 runs of
+this script with --copy-calib-mb (one --pmc FETCH_SIZE, one --pmc WRITE_SIZE).
 """
 
 from __future__ import annotations
 
 import argparse
+import collections
+import csv
+import hashlib
 import json
 import os
 import statistics
@@ -51,6 +65,117 @@ def spmv_dia_sketch_bytes(N, ndiag, tw, p=8, pv=8):
 def update_bytes(N, tw, p=8):
     """One orthogonalisation update launch: read w, read tw window vectors, write w."""
     return p * N * (tw + 2)
+
+
+KERNEL_SOURCES = ("paper_2311_14206_amd/csrc/sdr_kernels.hip",
+                  "paper_2311_14206_amd/csrc/sdr_kernels.h",
+                  "paper_2311_14206_amd/csrc/sdr_common.h")
+
+
+def _strip_comments(src):
+    """C/C++ source without comments and whitespace runs (string literals kept)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c == '"':
+            j = i + 1
+            while j < n and src[j] != '"':
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def kernel_source_digest():
+    """Digest of the device sources, comments and layout ignored: HBM counters
+    are valid for this digest only."""
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(_strip_comments(f.read()).encode())
+    return h.hexdigest()[:16]
+
+
+def traffic_summary_path(kernel_base, workload_name):
+    return os.path.join(ROOT, "profiles", f"{kernel_base}_{workload_name}_hbm_traffic.md")
+
+
+def read_traffic(path, kernel_key):
+    """Calibrated HBM bytes per launch of kernel_key from a committed summary,
+    or None if there is none or it was taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    digest, value = None, None
+    with open(path) as f:
+        for ln in f:
+            ln = ln.strip()
+            if ln.startswith("source_digest:"):
+                digest = ln.split(":", 1)[1].strip()
+            elif ln.startswith("traffic[") and ln.split("]", 1)[0][len("traffic["):] == kernel_key:
+                value = float(ln.split("=", 1)[1])
+    if digest != kernel_source_digest():
+        return None
+    return value
+
+
+def _pmc_rows(path):
+    out = collections.defaultdict(list)
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("sdr::", "").strip()
+            out[name].append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(fetch_csv, write_csv, calib_mb, workload_name):
+    """Markdown summary of two counter runs: per-kernel mean FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by the factor that maps the
+    calibration copy's reading to its true size."""
+    fetch, write = _pmc_rows(fetch_csv), _pmc_rows(write_csv)
+    calib = calib_mb * (1 << 20)
+    f_kib = max(fetch.get("__amd_rocclr_copyBuffer", [0.0]))
+    w_kib = max(write.get("__amd_rocclr_copyBuffer", [0.0]))
+    if f_kib <= 0 or w_kib <= 0:
+        raise SystemExit("no calibration copy in the counter runs (run them with --copy-calib-mb)")
+    ff, fw = calib / (1024.0 * f_kib), calib / (1024.0 * w_kib)
+    R = "$GRAFT_REPO_ROOT"
+    run = (f"timeout -s KILL 240 rocprofv3 --pmc {{c}} --output-format csv -d {R}/gpurun_out/pmc_{{d}} "
+           f"-o run -- python3 {R}/bench.py --workload {workload_name} --steps 1 --warmup 0 "
+           f"--no-cpu-baseline --copy-calib-mb {calib_mb}")
+    lines = [f"# HBM traffic per dispatch, {workload_name} solve (rocprofv3 counters)", "",
+             "Commands (from /tmp with TMPDIR=/tmp; R is the repository root):", "",
+             "    " + run.format(c="FETCH_SIZE", d="fetch"),
+             "    " + run.format(c="WRITE_SIZE", d="write"),
+             f"    python3 {R}/bench.py --summarize-pmc {R}/gpurun_out/pmc_fetch/run_counter_collection.csv "
+             f"{R}/gpurun_out/pmc_write/run_counter_collection.csv --copy-calib-mb {calib_mb} "
+             f"--workload {workload_name}", "",
+             f"Calibration: one device copy of {calib_mb} MiB ({calib} bytes read and written) reads "
+             f"FETCH_SIZE {f_kib:.1f} KiB and WRITE_SIZE {w_kib:.1f} KiB, so bytes = "
+             f"{ff:.4f} x 1024 x FETCH_SIZE and {fw:.4f} x 1024 x WRITE_SIZE.", "",
+             "| kernel | dispatches | FETCH_SIZE KiB (mean) | WRITE_SIZE KiB (mean) | read MB | written MB | total MB |",
+             "|---|---|---|---|---|---|---|"]
+    keys = sorted(set(fetch) & set(write), key=lambda k: -statistics.mean(fetch[k]) * len(fetch[k]))
+    machine = []
+    for k in keys:
+        if k.startswith("__amd") or k.startswith("at::"):
+            continue
+        fk, wk = statistics.mean(fetch[k]), statistics.mean(write[k])
+        rb, wb = ff * 1024.0 * fk, fw * 1024.0 * wk
+        lines.append(f"| {k} | {len(fetch[k])} | {fk:.1f} | {wk:.1f} | {rb / 1e6:.2f} | {wb / 1e6:.2f} | "
+                     f"{(rb + wb) / 1e6:.2f} |")
+        machine.append(f"traffic[{k}] = {rb + wb:.0f}")
+    lines += ["", "Per-launch HBM bytes (read + written), as bench.py reads them:", "",
+              f"source_digest: {kernel_source_digest()}"] + machine
+    return "\n".join(lines) + "\n"
 
 
 def cpu_baseline(A, b, p, gpu_iters):
@@ -92,7 +217,13 @@ def main():
                          "events (events between kernels cost launch gaps; 1 times all)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary of two rocprofv3 counter runs and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        sys.stdout.write(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
+                                       args.copy_calib_mb or 256, args.workload))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the solver runs on a single MI355X)", file=sys.stderr)
@@ -155,12 +286,15 @@ def main():
     launches = kt["launches"]
     pb = 8 if args.precision == 0 else 4
     layout = h.spmv_layout()
+    tname = "double" if args.precision == 0 else "float"
     if layout:
+        k1_key = f"k_spmv_dia_sketch<{tname}, {len(layout) if len(layout) in (3, 5, 7, 9) else 0}>"
         k1_bytes = sum(hist[tw] * spmv_dia_sketch_bytes(N, len(layout), tw, p=pb, pv=pb)
                        for tw in range(len(hist)))
         k1_name = (f"k_spmv_dia_sketch (stencil SpMV on {len(layout)} diagonals {layout} + "
                    "truncation-window products + sparse-sign sketch of the input basis vector)")
     else:
+        k1_key = f"k_spmv_sketch<{tname}>"
         k1_bytes = sum(hist[tw] * spmv_sketch_bytes(N, nnz, tw, p=pb, pv=pb) for tw in range(len(hist)))
         k1_name = ("k_spmv_sketch (CSR SpMV + truncation-window products + sparse-sign sketch "
                    "of the input basis vector)")
@@ -199,9 +333,11 @@ def main():
                      "kernel": k1_name,
                      "achieved": k1_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (k1_gbs / HBM_PEAK_GBS) if k1_gbs else None,
-                     "traffic": None,
+                     "traffic": read_traffic(traffic_summary_path(k1_key.split("<")[0], args.workload),
+                                             k1_key),
                      "avg_us": 1e6 * k1_s / max(launches, 1),
-                     "bytes_per_launch": k1_bytes / max(launches, 1)},
+                     "bytes_per_launch": k1_bytes / max(launches, 1),
+                     "kernel_source_digest": kernel_source_digest()},
         "arnoldi_step": {"spmv_orth_sketch_gbs_kernels": kernels_gbs,
                          "spmv_orth_sketch_gbs_step": step_gbs,
                          "update_avg_us": 1e6 * k2_s / max(launches, 1),

@@ -2,16 +2,19 @@
 //
 // Per Arnoldi step j (Algorithm 1, truncated Arnoldi with one sketch per step):
 //   stream A (the Arnoldi chain)
-//     k_spmv_sketch  w = A p_{j-1}, partial window products <p_i, w>, ||w||^2,
+//     k_spmv_dia_sketch / k_spmv_sketch (matrix by diagonals / CSR)
+//                    w = A p_{j-1}, partial window products <p_i, w>, ||w||^2,
 //                    and the sketch S p_{j-1} with ||p_{j-1}||^2: the SpMV reads
 //                    p_{j-1} anyway, so the one sketch per step costs no
 //                    extra pass over HBM
 //     k_update       reduces the window products and ||p_{j-1}||^2 in its
 //                    prologue, then p_j = (w - sum c_i p_i) / nu_{j-1} in place
-//   stream B (the sketched least squares, behind the event of step j+1's SpMV)
-//     k_reduce2      fixed-order reduction of S p_j, ||p_j||^2 (step j+1) and
-//                    the window products of step j
-//     k_lsq_step     H column, SV and SAV columns, QR append, sketched residual
+//   stream B (the sketched least squares, a chunk of steps per launch, behind
+//   the event of the SpMV that completes the chunk's last sketch)
+//     k_reduce_steps fixed-order reduction of the chunk's partial slots
+//     k_lsq_steps_reg H column, SV and SAV columns, QR append, sketched
+//                    residual, step record and halt, step after step with
+//                    the Q factor held in registers
 // Stored basis vectors are p_j = H(j+1, j) v_j: the orthogonalised A v_{j-1},
 // so nu_j = ||p_j|| = H(j+1, j) stays of the order of ||A|| in every
 // precision; the norms are folded into the coefficients, which saves a
