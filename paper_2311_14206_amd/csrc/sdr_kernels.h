@@ -11,7 +11,7 @@ constexpr int kLsqBlock = 512;     // threads of the single-block least-squares 
 constexpr int kMaxWindow = 4;      // largest truncation window t
 constexpr int kRowsSpmv = 1024;    // rows per block, SpMV + window products + sketch
 constexpr int kRowsUpdate = 2048;  // rows per block of the other streaming kernels
-constexpr int kUpdateRows = 4;     // rows per thread of the update (tiles of kRowsSpmv rows, as the SpMV)
+constexpr int kUpdateRows = 8;     // rows per thread of the update: a tile is two SpMV tiles, on the same XCD
 constexpr int kWaveTileNnz = 512;  // largest staged chunk (entries of 64 rows) per wave of the SpMV
 constexpr int kSpmvLds = 64 * 1024;  // LDS budget of the SpMV kernel: sketch bins + staged chunks
 constexpr int kMaxDiag = 16;       // most diagonals of the stencil (diagonal-storage) SpMV
@@ -170,10 +170,12 @@ void launch_spmv_residual(hipStream_t st, int n, const int* rp, const int* ci, c
                           const A* x, const A* r0, A* rnew, A* part, int nb);
 
 // C = [U P] G (n x kc), G (ku + jp) x kc column major (ld = ku + jp).
+// max_blocks > 0 caps the grid (the kernel strides over the rows), which
+// leaves compute units to kernels running beside it on other streams.
 template <class T>
 void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
                        int64_t ldp, int jp, const typename traits<T>::acc* G, int kc, T* C,
-                       int64_t ldc);
+                       int64_t ldc, int max_blocks);
 
 // C (M x N) = op(A) B with op(A) = A^H (A stored K x M) or A (M x K); small sizes.
 template <class A>

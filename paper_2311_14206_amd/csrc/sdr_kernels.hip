@@ -1568,8 +1568,26 @@ __global__ __launch_bounds__(kBlock) void k_gemm_basis(int n, const T* __restric
     A acc[KM];
 #pragma unroll
     for (int c = 0; c < KM; ++c) acc[c] = zero<A>();
-    for (int i = 0; i < l0; ++i) {
-      const A v = i < ku ? widen(U[r + i * ldu]) : widen(P[r + (i - ku) * ldp]);
+    // four input columns per round, their loads issued together (the column
+    // pointer is chosen without a branch); accumulation in column order
+    int i = 0;
+    for (; i + 4 <= l0; i += 4) {
+      A v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ii = i + u;
+        const T* src = ii < ku ? U + ii * ldu : P + (int64_t)(ii - ku) * ldp;
+        v[u] = widen(src[r]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int c = 0; c < KM; ++c) acc[c] += v[u] * gs[(i + u) * KM + c];
+      }
+    }
+    for (; i < l0; ++i) {
+      const T* src = i < ku ? U + i * ldu : P + (int64_t)(i - ku) * ldp;
+      const A v = widen(src[r]);
 #pragma unroll
       for (int c = 0; c < KM; ++c) acc[c] += v * gs[i * KM + c];
     }
@@ -1582,9 +1600,10 @@ __global__ __launch_bounds__(kBlock) void k_gemm_basis(int n, const T* __restric
 template <class T>
 void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
                        int64_t ldp, int jp, const typename traits<T>::acc* G, int kc, T* C,
-                       int64_t ldc) {
+                       int64_t ldc, int max_blocks) {
   using A = typename traits<T>::acc;
-  const int nb = (n + kBlock - 1) / kBlock;
+  int nb = (n + kBlock - 1) / kBlock;
+  if (max_blocks > 0 && nb > max_blocks) nb = max_blocks;  // grid-stride over the rows
   const int l0 = ku + jp;
   // output columns in chunks whose staged G fits in 48 KB of LDS
   int km = 32;
@@ -1737,7 +1756,7 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
   template void launch_gemv_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
                                      int, const traits<T>::acc*, traits<T>::acc*);                \
   template void launch_gemm_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
-                                     int, const traits<T>::acc*, int, T*, int64_t);               \
+                                     int, const traits<T>::acc*, int, T*, int64_t, int);          \
   template void launch_cast_scale<T>(hipStream_t, int, const traits<T>::acc*, double, T*);        \
   template void launch_widen_scale<T>(hipStream_t, int, const T*, double, traits<T>::acc*);       \
   template void launch_narrow_values<T>(hipStream_t, int64_t, const traits<T>::acc*, T*);

@@ -86,6 +86,7 @@ struct Options {
   int lsq_chunk = 8;      // steps per least-squares launch
   int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
   int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
+  int gemm_blocks = 512;  // grid of the recycle-space product (0: one row per thread)
 };
 
 // Diagonal layout of a CSR pattern: the distinct offsets column - row (at
@@ -208,7 +209,9 @@ class Solver final : public SolverBase {
       psk_ = dalloc<A>((size_t)(8 * s + 8 + 1) * nb2_);
       red2_ = dalloc<A>(8 * s + 8 + 1);
       HIPCHK(hipStreamCreateWithFlags(&streamB_, hipStreamNonBlocking));
+      HIPCHK(hipStreamCreateWithFlags(&streamC_, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&ev_copy_, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ev_gemm_, hipEventDisableTiming));
       evs_.assign(nslot_ + 1, nullptr);
       for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       red3_ = dalloc<A>(4);
@@ -792,14 +795,19 @@ class Solver final : public SolverBase {
           Gh[(size_t)c * l0 + i] = g;
           Gp[(size_t)c * l0 + i] = i < khat ? g : scale(g, 1.0 / hnu_[i - khat]);
         }
-      // small products on stream B (they feed this cycle's least squares),
-      // the N x keff product on stream A (it feeds the first residual check)
+      // small products on stream B (they feed this cycle's least squares);
+      // the N x keff product on stream C, beside the Arnoldi steps already
+      // queued on stream A, which waits for it before anything reads U (the
+      // first residual check)
       HIPCHK(hipMemcpyAsync(Gs_, Gh, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, streamB_));
       launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SB, s_, Gs_, l0, SU_, s_);
       launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SAW, s_, Gs_, l0, SAU_, s_);
-      HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
-      launch_gemm_basis<T>(stream_, n_, U_, n_, khat, pend_.P, n_, pend_.j, G_, keff, Unew_, n_);
+      HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, streamC_));
+      launch_gemm_basis<T>(streamC_, n_, U_, n_, khat, pend_.P, n_, pend_.j, G_, keff, Unew_, n_,
+                           opt_.gemm_blocks);
       LAUNCHCHK();
+      HIPCHK(hipEventRecord(ev_gemm_, streamC_));
+      HIPCHK(hipStreamWaitEvent(stream_, ev_gemm_, 0));
       std::swap(U_, Unew_);
     }
     khat_ = keff;
@@ -899,8 +907,12 @@ class Solver final : public SolverBase {
     evs_.clear();
     if (ev_copy_) (void)hipEventDestroy(ev_copy_);
     ev_copy_ = nullptr;
+    if (ev_gemm_) (void)hipEventDestroy(ev_gemm_);
+    ev_gemm_ = nullptr;
     if (streamB_) (void)hipStreamDestroy(streamB_);
     streamB_ = nullptr;
+    if (streamC_) (void)hipStreamDestroy(streamC_);
+    streamC_ = nullptr;
   }
 
   MatView<A> M_;
@@ -940,6 +952,8 @@ class Solver final : public SolverBase {
   int nslot_ = 0;
   size_t slot1_ = 0, slotr_ = 0;
   hipStream_t streamB_ = nullptr;
+  hipStream_t streamC_ = nullptr;  // the recycle-space product U_new = [U P] G
+  hipEvent_t ev_gemm_ = nullptr;
   std::vector<hipEvent_t> evs_;
   A *Sr_ = nullptr, *ycoef_ = nullptr, *xt_ = nullptr, *r_ = nullptr, *rnew_ = nullptr;
   A *G_ = nullptr, *Gs_ = nullptr, *C_ = nullptr;
@@ -1222,6 +1236,10 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
   } else if (k == "lsq_chunk") {
     if (built || v < 1 || v > 64) return set_err("lsq_chunk in [1,64], before the first solve"), SDR_EINVAL;
     h->opt.lsq_chunk = (int)v;
+  } else if (k == "gemm_blocks") {
+    if (built || v < 0 || v > 65536 || v != (double)(int)v)
+      return set_err("gemm_blocks is an integer in [0,65536], before the first solve"), SDR_EINVAL;
+    h->opt.gemm_blocks = (int)v;
   } else {
     set_err("unknown option " + k);
     return SDR_EINVAL;
