@@ -215,8 +215,6 @@ def main():
     ap.add_argument("--timing-every", type=int, default=16,
                     help="time the SpMV and update kernels of every n-th Arnoldi step with HIP "
                          "events (events between kernels cost launch gaps; 1 times all)")
-    ap.add_argument("--gemm-blocks", type=int, default=None,
-                    help="grid of the recycle-space product (library default if omitted)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -246,9 +244,8 @@ def main():
     ci = torch.from_numpy(A.col_idx).to(dev)
     vals = torch.from_numpy(A.values).to(dev)
     bd = torch.from_numpy(b).to(dev)
-    extra = {} if args.gemm_blocks is None else {"gemm_blocks": args.gemm_blocks}
     h = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
-                  zeta=p["zeta"], kernel_timing=args.timing_every, precision=args.precision, **extra)
+                  zeta=p["zeta"], kernel_timing=args.timing_every, precision=args.precision)
     if args.copy_calib_mb:
         src = torch.ones(args.copy_calib_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -125,9 +125,6 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *                    for the basis SpMV; 0: always CSR
  *   "kernel_timing"  n > 0: HIP events around the SpMV and update kernels of
  *                    every n-th Arnoldi step (sdr_kernel_times); default 0
- *   "gemm_blocks"    grid of the recycle-space product U_new = [U P] G, which
- *                    runs on an internal stream beside the next cycle's
- *                    Arnoldi steps (default 512; 0: one row per thread)
  * Returns 0 or SDR_EINVAL.
  */
 int sdr_set_option(sdr_handle* h, const char* key, double value);

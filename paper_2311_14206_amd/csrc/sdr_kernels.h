@@ -170,14 +170,20 @@ void launch_spmv_residual(hipStream_t st, int n, const int* rp, const int* ci, c
                           const A* x, const A* r0, A* rnew, A* part, int nb);
 
 // C = [U P] G (n x kc), G (ku + jp) x kc column major (ld = ku + jp).
-// max_blocks > 0 caps the grid (the kernel strides over the rows), which
-// leaves compute units to kernels running beside it on other streams.
 template <class T>
 void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
                        int64_t ldp, int jp, const typename traits<T>::acc* G, int kc, T* C,
-                       int64_t ldc, int max_blocks);
+                       int64_t ldc);
 
 // C (M x N) = op(A) B with op(A) = A^H (A stored K x M) or A (M x K); small sizes.
+// y = R^{-1} z over the leading nls columns of the upper triangular R (ld
+// ldr), scaled into coefficients of the stored basis: y_i for i < khat,
+// y_i / nu[i - khat] after.  One wavefront on stream st.  Returns false
+// (nothing launched) when nls > 512.
+template <class A>
+bool launch_back_subst(hipStream_t st, int nls, int khat, const A* R, int ldr, const A* z, const double* nu,
+                       A* y);
+
 template <class A>
 void launch_small_gemm(hipStream_t st, bool conjtrans, int M, int N, int K, const A* a, int lda,
                        const A* b, int ldb, A* c, int ldc);

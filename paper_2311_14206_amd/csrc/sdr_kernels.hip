@@ -1487,6 +1487,22 @@ void launch_sketch_cols(hipStream_t st, int n, const X* x, int64_t ld, int cc, S
 }
 
 // ------------------------------------------------- tall-skinny products ---
+// acc + sum_i X(r, i) y_i over nc columns, in column order, eight loads in
+// flight per round.
+template <class T, class A>
+__device__ __forceinline__ A dot_cols(const T* __restrict__ X, int64_t ld, int nc, const A* ys, int r, A acc) {
+  int i = 0;
+  for (; i + 8 <= nc; i += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = X[r + (int64_t)(i + u) * ld];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += widen(v[u]) * ys[i + u];
+  }
+  for (; i < nc; ++i) acc += widen(X[r + (int64_t)i * ld]) * ys[i];
+  return acc;
+}
+
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_gemv_basis(int n, const T* __restrict__ U, int64_t ldu,
                                                        int ku, const T* __restrict__ P, int64_t ldp,
@@ -1499,8 +1515,8 @@ __global__ __launch_bounds__(kBlock) void k_gemv_basis(int n, const T* __restric
   __syncthreads();
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     A acc = zero<A>();
-    for (int i = 0; i < ku; ++i) acc += widen(U[r + i * ldu]) * ys[i];
-    for (int i = 0; i < jp; ++i) acc += widen(P[r + i * ldp]) * ys[ku + i];
+    acc = dot_cols(U, ldu, ku, ys, r, acc);
+    acc = dot_cols(P, ldp, jp, ys + ku, r, acc);
     out[r] = acc;
   }
 }
@@ -1600,10 +1616,9 @@ __global__ __launch_bounds__(kBlock) void k_gemm_basis(int n, const T* __restric
 template <class T>
 void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
                        int64_t ldp, int jp, const typename traits<T>::acc* G, int kc, T* C,
-                       int64_t ldc, int max_blocks) {
+                       int64_t ldc) {
   using A = typename traits<T>::acc;
-  int nb = (n + kBlock - 1) / kBlock;
-  if (max_blocks > 0 && nb > max_blocks) nb = max_blocks;  // grid-stride over the rows
+  const int nb = (n + kBlock - 1) / kBlock;
   const int l0 = ku + jp;
   // output columns in chunks whose staged G fits in 48 KB of LDS
   int km = 32;
@@ -1628,28 +1643,147 @@ void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, c
   }
 }
 
+// Small dense products of the least squares and the eigen-step (M, N up to a
+// few hundred, K up to the sketch size).
+// C = A^H B: one wave per entry of C, a dot product of two columns of length
+// K with the lanes over K (coalesced), then a fixed-order wave sum.
 template <class A>
-__global__ void k_small_gemm(bool ct, int M, int N, int K, const A* __restrict__ a, int lda,
-                             const A* __restrict__ b, int ldb, A* __restrict__ c, int ldc) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= M * N) return;
-  const int i = idx % M, jc = idx / M;
+__global__ __launch_bounds__(kBlock) void k_small_gemm_ct(int M, int N, int K, const A* __restrict__ a, int lda,
+                                                          const A* __restrict__ b, int ldb, A* __restrict__ c,
+                                                          int ldc) {
+  const int lane = threadIdx.x & 63;
+  const int o = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (o >= M * N) return;  // the whole wave leaves together
+  const int i = o % M, jc = o / M;
+  const A* ai = a + (int64_t)i * lda;
+  const A* bj = b + (int64_t)jc * ldb;
   A sum = zero<A>();
-  if (ct) {
-    for (int k = 0; k < K; ++k) sum += conj(a[(int64_t)i * lda + k]) * b[(int64_t)jc * ldb + k];
-  } else {
-    for (int k = 0; k < K; ++k) sum += a[(int64_t)k * lda + i] * b[(int64_t)jc * ldb + k];
+  for (int k = lane; k < K; k += 64) sum += conj(ai[k]) * bj[k];
+  sum = wave_sum(sum);
+  if (lane == 0) c[(int64_t)jc * ldc + i] = sum;
+}
+
+// C = A B: a block per 64 rows of one column of C, the lanes over the rows
+// (coalesced loads of A), the K terms split over the block's waves (eight
+// loads in flight per round) and the wave partials added in a fixed order.
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_small_gemm_nn(int M, int N, int K, const A* __restrict__ a, int lda,
+                                                          const A* __restrict__ b, int ldb, A* __restrict__ c,
+                                                          int ldc) {
+  __shared__ A part[kWaves * 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane, jc = blockIdx.y;
+  const int kc = (K + kWaves - 1) / kWaves, k0 = wv * kc, k1 = min(K, k0 + kc);
+  const int ic = min(i, M - 1);
+  const A* bj = b + (int64_t)jc * ldb;
+  A sum = zero<A>();
+  int k = k0;
+  for (; k + 8 <= k1; k += 8) {
+    A v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = a[(int64_t)(k + u) * lda + ic];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += v[u] * bj[k + u];
   }
-  c[(int64_t)jc * ldc + i] = sum;
+  for (; k < k1; ++k) sum += a[(int64_t)k * lda + ic] * bj[k];
+  part[wv * 64 + lane] = sum;
+  __syncthreads();
+  if (wv == 0 && i < M) {
+    A t = part[lane];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) t += part[w * 64 + lane];
+    c[(int64_t)jc * ldc + i] = t;
+  }
 }
 
 template <class A>
 void launch_small_gemm(hipStream_t st, bool ct, int M, int N, int K, const A* a, int lda,
                        const A* b, int ldb, A* c, int ldc) {
   if (M * N == 0) return;
-  const int nb = (M * N + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_small_gemm<A>, dim3(nb), dim3(kBlock), 0, st, ct, M, N, K, a, lda, b, ldb, c,
-                     ldc);
+  if (ct) {
+    const int nb = (M * N + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL(k_small_gemm_ct<A>, dim3(nb), dim3(kBlock), 0, st, M, N, K, a, lda, b, ldb, c, ldc);
+  } else {
+    hipLaunchKernelGGL(k_small_gemm_nn<A>, dim3((M + 63) / 64, N), dim3(kBlock), 0, st, M, N, K, a, lda, b,
+                       ldb, c, ldc);
+  }
+}
+
+// ------------------------------------------------- triangular solve --
+__device__ __forceinline__ bool nonzero(double v) { return v != 0.0; }
+__device__ __forceinline__ bool nonzero(cx<double> v) { return v.x != 0.0 || v.y != 0.0; }
+__device__ __forceinline__ double div(double a, double b) { return a / b; }
+__device__ __forceinline__ cx<double> div(cx<double> a, cx<double> b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+__device__ __forceinline__ cx<double> read_lane(cx<double> v, int l) { return {read_lane(v.x, l), read_lane(v.y, l)}; }
+
+// y = R^{-1} z over the leading nls columns of the upper triangular R (ld
+// ldr), then the coefficients of the stored basis: y_i for the recycled
+// columns (i < khat) and y_i / nu_{i-khat} for the unnormalised P columns.
+// One wave; lane l owns rows l + 64 q (q < RPL).  Column entries are loaded
+// eight columns ahead; y_i is broadcast from its owner lane and every row
+// k < i subtracts R(k, i) y_i, in the order of a sequential back substitution.
+template <class A, int RPL>
+__global__ __launch_bounds__(64) void k_back_subst(int nls, int khat, const A* __restrict__ R, int ldr,
+                                                   const A* __restrict__ z, const double* __restrict__ nu,
+                                                   A* __restrict__ yout) {
+  const int lane = threadIdx.x;
+  A y[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int k = lane + 64 * q;
+    y[q] = k < nls ? z[k] : zero<A>();
+  }
+  for (int i = nls - 1; i >= 0; i -= 8) {
+    A rc[8][RPL], rd[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = max(i - u, 0);
+      const A* col = R + (int64_t)c * ldr;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) rc[u][q] = col[min(lane + 64 * q, ldr - 1)];
+      rd[u] = col[c];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = i - u;
+      if (c >= 0) {
+        A yc = zero<A>();
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+          if (q == c / 64) yc = read_lane(y[q], c & 63);
+        yc = nonzero(rd[u]) ? div(yc, rd[u]) : zero<A>();
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const int k = lane + 64 * q;
+          if (k == c) y[q] = yc;
+          else if (k < c) y[q] -= rc[u][q] * yc;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int k = lane + 64 * q;
+    if (k < nls) yout[k] = k < khat ? y[q] : scale(y[q], 1.0 / nu[k - khat]);
+  }
+}
+
+template <class A>
+bool launch_back_subst(hipStream_t st, int nls, int khat, const A* R, int ldr, const A* z, const double* nu,
+                       A* y) {
+  if (nls <= 0) return true;
+  if (nls <= 128)
+    hipLaunchKernelGGL((k_back_subst<A, 2>), dim3(1), dim3(64), 0, st, nls, khat, R, ldr, z, nu, y);
+  else if (nls <= 256)
+    hipLaunchKernelGGL((k_back_subst<A, 4>), dim3(1), dim3(64), 0, st, nls, khat, R, ldr, z, nu, y);
+  else if (nls <= 512)
+    hipLaunchKernelGGL((k_back_subst<A, 8>), dim3(1), dim3(64), 0, st, nls, khat, R, ldr, z, nu, y);
+  else
+    return false;
+  return true;
 }
 
 // ------------------------------------------------------------ elementwise --
@@ -1756,7 +1890,7 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
   template void launch_gemv_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
                                      int, const traits<T>::acc*, traits<T>::acc*);                \
   template void launch_gemm_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
-                                     int, const traits<T>::acc*, int, T*, int64_t, int);          \
+                                     int, const traits<T>::acc*, int, T*, int64_t);               \
   template void launch_cast_scale<T>(hipStream_t, int, const traits<T>::acc*, double, T*);        \
   template void launch_widen_scale<T>(hipStream_t, int, const T*, double, traits<T>::acc*);       \
   template void launch_narrow_values<T>(hipStream_t, int64_t, const traits<T>::acc*, T*);
@@ -1782,6 +1916,7 @@ SDR_INST_BASIS(cx<float>)
   template void launch_backsolve<A>(hipStream_t, LsqState<A>, int, int, A*);                    \
   template void launch_spmv_residual<A>(hipStream_t, int, const int*, const int*, const A*,     \
                                         const A*, const A*, A*, A*, int);                      \
+  template bool launch_back_subst<A>(hipStream_t, int, int, const A*, int, const A*, const double*, A*); \
   template void launch_small_gemm<A>(hipStream_t, bool, int, int, int, const A*, int, const A*, \
                                      int, A*, int);                                             \
   template void launch_axpy<A>(hipStream_t, int, A, const A*, A*);                              \

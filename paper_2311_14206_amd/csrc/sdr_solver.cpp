@@ -86,7 +86,6 @@ struct Options {
   int lsq_chunk = 8;      // steps per least-squares launch
   int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
   int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
-  int gemm_blocks = 512;  // grid of the recycle-space product (0: one row per thread)
 };
 
 // Diagonal layout of a CSR pattern: the distinct offsets column - row (at
@@ -209,9 +208,7 @@ class Solver final : public SolverBase {
       psk_ = dalloc<A>((size_t)(8 * s + 8 + 1) * nb2_);
       red2_ = dalloc<A>(8 * s + 8 + 1);
       HIPCHK(hipStreamCreateWithFlags(&streamB_, hipStreamNonBlocking));
-      HIPCHK(hipStreamCreateWithFlags(&streamC_, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&ev_copy_, hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&ev_gemm_, hipEventDisableTiming));
       evs_.assign(nslot_ + 1, nullptr);
       for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       red3_ = dalloc<A>(4);
@@ -467,11 +464,16 @@ class Solver final : public SolverBase {
     for (int c0 = j0; c0 <= m_; c0 += opt_.lsq_chunk) enqueue_chunk(c0, std::min(c0 + opt_.lsq_chunk - 1, m_));
   }
 
-  // y = R^{-1} z for the leading (khat + j) block, on the host (a sequential
-  // back substitution is latency bound on one compute unit); coefficients of
-  // the stored basis [U, P]: y_i for U, y_i / nu_i for the unnormalised P.
+  // y = R^{-1} z for the leading (khat + j) block; coefficients of the stored
+  // basis [U, P]: y_i for U, y_i / nu_i for the unnormalised P.  On the device
+  // (one wavefront, no host round trip before the basis product); on the host
+  // beyond 512 columns.
   void solve_coefficients(int j) {
     const int nls = khat_ + j;
+    if (launch_back_subst<A>(stream_, nls, khat_, R_, lmax_, z_, nu_, ycoef_)) {
+      LAUNCHCHK();
+      return;
+    }
     // (own staging: the eigen-step's copies of R and nu may be in use on a worker thread)
     HIPCHK(hipMemcpyAsync(hRc_, R_, sizeof(A) * (size_t)lmax_ * nls, hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipMemcpyAsync(hz_, z_, sizeof(A) * nls, hipMemcpyDeviceToHost, stream_));
@@ -487,6 +489,39 @@ class Solver final : public SolverBase {
     for (int i = 0; i < nls; ++i)
       hy_[i] = from_cd<A>(i < khat_ ? y[i] : y[i] / hnuc_[i - khat_]);
     HIPCHK(hipMemcpyAsync(ycoef_, hy_, sizeof(A) * nls, hipMemcpyHostToDevice, stream_));
+  }
+
+  // Which inputs of a failed residual check hold non-finite values (host copies).
+  std::string nonfinite_report(int j) {
+    const int nls = khat_ + j;
+    auto bad = [](const std::vector<A>& v) {
+      size_t c = 0;
+      for (const A& a : v) {
+        const std::complex<double> z = to_cd(a);
+        if (!std::isfinite(z.real()) || !std::isfinite(z.imag())) ++c;
+      }
+      return c;
+    };
+    std::vector<A> y(nls), R((size_t)lmax_ * nls), z(nls), xt(n_);
+    std::vector<double> nu(j + 1);
+    HIPCHK(hipMemcpy(y.data(), ycoef_, sizeof(A) * nls, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(R.data(), R_, sizeof(A) * R.size(), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(z.data(), z_, sizeof(A) * nls, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(nu.data(), nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(xt.data(), xt_, sizeof(A) * n_, hipMemcpyDeviceToHost));
+    size_t rbad = 0;
+    for (int c = 0; c < nls; ++c)
+      for (int i = 0; i <= c; ++i) {
+        const std::complex<double> v = to_cd(R[(size_t)c * lmax_ + i]);
+        if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) ++rbad;
+      }
+    size_t nubad = 0;
+    for (double v : nu)
+      if (!std::isfinite(v) || v == 0.0) ++nubad;
+    return "non-finite: coefficients " + std::to_string(bad(y)) + "/" + std::to_string(nls) + ", R " +
+           std::to_string(rbad) + ", z " + std::to_string(bad(z)) + ", nu (or zero) " +
+           std::to_string(nubad) + "/" + std::to_string(j + 1) + ", basis product " +
+           std::to_string(bad(xt)) + "/" + std::to_string(n_) + ", k_hat " + std::to_string(khat_);
   }
 
   double check(int j) {
@@ -629,7 +664,8 @@ class Solver final : public SolverBase {
           checks++;
           rec.n_checks++;
           if (!std::isfinite(res)) {
-            set_err("non-finite residual");
+            set_err("non-finite residual at step " + std::to_string(done) + " of cycle " +
+                    std::to_string(cycles + 1) + " (" + nonfinite_report(done) + ")");
             throw HipError{SDR_EDEVICE};
           }
           if (res < tol_abs) {
@@ -795,19 +831,16 @@ class Solver final : public SolverBase {
           Gh[(size_t)c * l0 + i] = g;
           Gp[(size_t)c * l0 + i] = i < khat ? g : scale(g, 1.0 / hnu_[i - khat]);
         }
-      // small products on stream B (they feed this cycle's least squares);
-      // the N x keff product on stream C, beside the Arnoldi steps already
-      // queued on stream A, which waits for it before anything reads U (the
-      // first residual check)
+      // small products on stream B (they feed this cycle's least squares),
+      // the N x keff product on stream A behind the cycle's Arnoldi steps (it
+      // feeds the first residual check; run beside the steps it slowed them
+      // more than it saved)
       HIPCHK(hipMemcpyAsync(Gs_, Gh, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, streamB_));
       launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SB, s_, Gs_, l0, SU_, s_);
       launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SAW, s_, Gs_, l0, SAU_, s_);
-      HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, streamC_));
-      launch_gemm_basis<T>(streamC_, n_, U_, n_, khat, pend_.P, n_, pend_.j, G_, keff, Unew_, n_,
-                           opt_.gemm_blocks);
+      HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
+      launch_gemm_basis<T>(stream_, n_, U_, n_, khat, pend_.P, n_, pend_.j, G_, keff, Unew_, n_);
       LAUNCHCHK();
-      HIPCHK(hipEventRecord(ev_gemm_, streamC_));
-      HIPCHK(hipStreamWaitEvent(stream_, ev_gemm_, 0));
       std::swap(U_, Unew_);
     }
     khat_ = keff;
@@ -907,12 +940,8 @@ class Solver final : public SolverBase {
     evs_.clear();
     if (ev_copy_) (void)hipEventDestroy(ev_copy_);
     ev_copy_ = nullptr;
-    if (ev_gemm_) (void)hipEventDestroy(ev_gemm_);
-    ev_gemm_ = nullptr;
     if (streamB_) (void)hipStreamDestroy(streamB_);
     streamB_ = nullptr;
-    if (streamC_) (void)hipStreamDestroy(streamC_);
-    streamC_ = nullptr;
   }
 
   MatView<A> M_;
@@ -952,8 +981,6 @@ class Solver final : public SolverBase {
   int nslot_ = 0;
   size_t slot1_ = 0, slotr_ = 0;
   hipStream_t streamB_ = nullptr;
-  hipStream_t streamC_ = nullptr;  // the recycle-space product U_new = [U P] G
-  hipEvent_t ev_gemm_ = nullptr;
   std::vector<hipEvent_t> evs_;
   A *Sr_ = nullptr, *ycoef_ = nullptr, *xt_ = nullptr, *r_ = nullptr, *rnew_ = nullptr;
   A *G_ = nullptr, *Gs_ = nullptr, *C_ = nullptr;
@@ -1236,10 +1263,6 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
   } else if (k == "lsq_chunk") {
     if (built || v < 1 || v > 64) return set_err("lsq_chunk in [1,64], before the first solve"), SDR_EINVAL;
     h->opt.lsq_chunk = (int)v;
-  } else if (k == "gemm_blocks") {
-    if (built || v < 0 || v > 65536 || v != (double)(int)v)
-      return set_err("gemm_blocks is an integer in [0,65536], before the first solve"), SDR_EINVAL;
-    h->opt.gemm_blocks = (int)v;
   } else {
     set_err("unknown option " + k);
     return SDR_EINVAL;
