@@ -129,7 +129,15 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  */
 int sdr_set_option(sdr_handle* h, const char* key, double value);
 
-/* Use this HIP stream (hipStream_t as void*); NULL selects the handle's own. */
+/*
+ * Run the handle's calls on this HIP stream (hipStream_t as void*).  NULL
+ * means the device's null stream: the handle then runs on a non-blocking
+ * stream of its own that waits, at each call, for the work queued on the
+ * null stream before the call.  Either way inputs written by earlier work on
+ * the given stream are read in order.  Until this is called the handle uses
+ * its own stream without that wait: inputs must then be complete on the
+ * device before a call.
+ */
 int sdr_set_stream(sdr_handle* h, void* hip_stream);
 
 /*

@@ -193,6 +193,11 @@ template <class A> void launch_axpy(hipStream_t st, int n, A alpha, const A* x, 
 template <class T>
 void launch_cast_scale(hipStream_t st, int n, const typename traits<T>::acc* src, double scale,
                        T* dst);
+// The same with scale = 1 / sqrt(Re nrm2[0]) read on the device (1 if that
+// is not positive): the norm of a reduction still on the device.
+template <class T>
+void launch_cast_rscale(hipStream_t st, int n, const typename traits<T>::acc* src,
+                        const typename traits<T>::acc* nrm2, T* dst);
 // dst (T) = src (T) cast from full precision A values (matrix copy)
 template <class T>
 void launch_narrow_values(hipStream_t st, int64_t n, const typename traits<T>::acc* src, T* dst);

@@ -528,10 +528,11 @@ __global__ __launch_bounds__(kBlock) void k_update(
     int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ part,
     int nb1, int s, double* __restrict__ nu, int i0, int jprev, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
-  if (ctrl->halt) return;
+  const int halted = ctrl->halt;  // tested once the loads below are out
   __shared__ A red[(kMaxWindow + 1) * kWaves];
-  // The stream's loads go out first (clamped rows, unused past n) and are in
-  // flight while the block reduces the partials.
+  // The stream's loads go out first (clamped rows, unused past n), with the
+  // norms of the older window vectors, and are in flight while the block
+  // reduces the partials: no dependent global load follows the reduction.
   const int base = xcd_tile(blockIdx.x, gridDim.x) * (kBlock * kUpdateRows) + (int)threadIdx.x;
   T wv[kUpdateRows], pv[kUpdateRows][kMaxWindow];
 #pragma unroll
@@ -542,6 +543,10 @@ __global__ __launch_bounds__(kBlock) void k_update(
     for (int q = 0; q < kMaxWindow; ++q)
       if (q < tw) pv[u][q] = win.p[q][r];
   }
+  double nqv[kMaxWindow];
+#pragma unroll
+  for (int q = 0; q < kMaxWindow; ++q) nqv[q] = (q < tw && i0 + q != jprev) ? nu[i0 + q] : 1.0;
+  if (halted) return;
   A sums[kMaxWindow + 1];
   col_sums<A, kMaxWindow + 1>(part, nb1, s, tw + 1, sums, red);
   const double nprev = sqrt(re(sums[0]));
@@ -550,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) {
     if (q < tw) {
-      const double nq = i0 + q == jprev ? nprev : nu[i0 + q];
+      const double nq = i0 + q == jprev ? nprev : nqv[q];
       c[q] = scale(sums[1 + q], 1.0 / (nq * nq));
     } else {
       c[q] = zero<A>();
@@ -1809,6 +1814,21 @@ void launch_cast_scale(hipStream_t st, int n, const typename traits<T>::acc* src
 }
 
 template <class T>
+__global__ void k_cast_rscale(int n, const typename traits<T>::acc* __restrict__ src,
+                              const typename traits<T>::acc* __restrict__ nrm2, T* __restrict__ dst) {
+  const double q = re(nrm2[0]);
+  const double sc = q > 0.0 ? 1.0 / sqrt(q) : 1.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    dst[i] = narrow<T>(scale(src[i], sc));
+}
+template <class T>
+void launch_cast_rscale(hipStream_t st, int n, const typename traits<T>::acc* src,
+                        const typename traits<T>::acc* nrm2, T* dst) {
+  hipLaunchKernelGGL(k_cast_rscale<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, src, nrm2,
+                     dst);
+}
+
+template <class T>
 __global__ void k_widen_scale(int n, const T* __restrict__ src, double s,
                               typename traits<T>::acc* __restrict__ dst) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -1892,6 +1912,7 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
   template void launch_gemm_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
                                      int, const traits<T>::acc*, int, T*, int64_t);               \
   template void launch_cast_scale<T>(hipStream_t, int, const traits<T>::acc*, double, T*);        \
+  template void launch_cast_rscale<T>(hipStream_t, int, const traits<T>::acc*, const traits<T>::acc*, T*); \
   template void launch_widen_scale<T>(hipStream_t, int, const T*, double, traits<T>::acc*);       \
   template void launch_narrow_values<T>(hipStream_t, int64_t, const traits<T>::acc*, T*);
 

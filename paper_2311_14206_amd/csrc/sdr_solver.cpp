@@ -22,7 +22,10 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
 #include <future>
+#include <mutex>
+#include <thread>
 #include <memory>
 #include <string>
 #include <vector>
@@ -209,6 +212,7 @@ class Solver final : public SolverBase {
       red2_ = dalloc<A>(8 * s + 8 + 1);
       HIPCHK(hipStreamCreateWithFlags(&streamB_, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&ev_copy_, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ev_res_, hipEventDisableTiming));
       evs_.assign(nslot_ + 1, nullptr);
       for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       red3_ = dalloc<A>(4);
@@ -221,9 +225,11 @@ class Solver final : public SolverBase {
       Gs_ = dalloc<A>((size_t)lmax_ * kmax_);
       C_ = dalloc<A>((size_t)lmax_ * lmax_);
       if (opt.kernel_timing) {
-        ev_.assign(m + 2, std::array<hipEvent_t, 4>{});
-        for (auto& a : ev_)
-          for (auto& e : a) HIPCHK(hipEventCreate(&e));
+        for (auto& evp : ev_) {
+          evp.assign(m + 2, std::array<hipEvent_t, 4>{});
+          for (auto& a : evp)
+            for (auto& e : a) HIPCHK(hipEventCreate(&e));
+        }
       }
       HIPCHK(hipHostMalloc((void**)&rec_host_, sizeof(StepRec) * (m + 2),
                            hipHostMallocMapped | hipHostMallocCoherent));
@@ -255,7 +261,12 @@ class Solver final : public SolverBase {
           dia_map_ = dalloc<int>(map.size());
           diaval_ = dalloc<T>((size_t)dia_.ndiag * n_);
           HIPCHK(hipMemcpy(dia_map_, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
-          HIPCHK(hipMemset(diaval_, 0, sizeof(T) * (size_t)dia_.ndiag * n_));
+          // Null-stream copies need not have reached the device when they
+          // return, and the solver's kernels run on non-blocking streams:
+          // finish the copy, then zero the padding on the solver's stream.
+          HIPCHK(hipStreamSynchronize(nullptr));
+          HIPCHK(hipMemsetAsync(diaval_, 0, sizeof(T) * (size_t)dia_.ndiag * n_, stream_));
+          HIPCHK(hipStreamSynchronize(stream_));
           dia_.val = diaval_;
         }
       }
@@ -329,14 +340,23 @@ class Solver final : public SolverBase {
     return SDR_OK;
   }
 
-  double residual(const A* x, const A* b, A* r) {
+  // r = b - A x and ||r||^2 to the host, queued on stream A; finish_residual()
+  // waits for it.
+  void enqueue_residual(const A* x, const A* b, A* r) {
     launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, psk_, nb2_);
     LAUNCHCHK();
     launch_reduce_cols<A>(stream_, psk_, nb2_, 1, 0, 1.0, red3_, nullptr);
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(hscal_, red3_, sizeof(A), hipMemcpyDeviceToHost, stream_));
-    HIPCHK(hipStreamSynchronize(stream_));
+    HIPCHK(hipEventRecord(ev_res_, stream_));
+  }
+  double finish_residual() {
+    HIPCHK(hipEventSynchronize(ev_res_));  // (not the stream: later work may be queued)
     return std::sqrt(to_double_re(hscal_[0]));
+  }
+  double residual(const A* x, const A* b, A* r) {
+    enqueue_residual(x, b, r);
+    return finish_residual();
   }
 
   LsqState<A> lsq() {
@@ -384,20 +404,44 @@ class Solver final : public SolverBase {
     for (int q = 0; q < tw; ++q) win.p[q] = P_ + (size_t)(i0 + q) * n_;
     T* w = P_ + (size_t)j * n_;
     const bool tm = timed(j);
+    hipEvent_t* te = tm ? ev_[evp_][j].data() : nullptr;
     if (dia())
       launch_spmv_dia_sketch<T>(stream_, n_, dia_, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
-                                tm ? ev_[j][0] : nullptr, tm ? ev_[j][1] : nullptr);
+                                tm ? te[0] : nullptr, tm ? te[1] : nullptr);
     else
       launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
-                            tm ? ev_[j][0] : nullptr, tm ? ev_[j][1] : nullptr);
+                            tm ? te[0] : nullptr, tm ? te[1] : nullptr);
     LAUNCHCHK();
     if (ev) HIPCHK(hipEventRecord(evs_[sl], stream_));
     launch_update<T>(stream_, n_, w, win, tw, p1, nb1_, s_, nu_, i0, j - 1, ctrl_,
-                     tm ? ev_[j][2] : nullptr, tm ? ev_[j][3] : nullptr);
+                     tm ? te[2] : nullptr, tm ? te[3] : nullptr);
     LAUNCHCHK();
   }
 
   bool timed(int j) const { return opt_.kernel_timing > 0 && j % opt_.kernel_timing == 0; }
+
+  // Kernel times of a finished cycle, read while the GPU runs the next one
+  // (the events alternate between two sets by cycle, so a set is read
+  // before it is recorded again).
+  void drain_timing() {
+    if (ev_pend_j_ <= 0) return;
+    auto& evs = ev_[ev_pend_p_];
+    for (int j = 1; j <= ev_pend_j_; ++j) {
+      if (!timed(j)) continue;
+      float a = 0.f, b2 = 0.f, c = 0.f;
+      HIPCHK(hipEventElapsedTime(&a, evs[j][0], evs[j][1]));
+      HIPCHK(hipEventElapsedTime(&b2, evs[j][2], evs[j][3]));
+      HIPCHK(hipEventElapsedTime(&c, evs[j][0], evs[j][3]));
+      kt_ms_[0] += a;
+      kt_ms_[1] += b2;
+      kt_ms_[2] += c;
+      kt_n_[0]++;
+      kt_n_[1]++;
+      kt_n_[2]++;
+      kt_bytes_tw_[std::min(j, t_)]++;
+    }
+    ev_pend_j_ = 0;
+  }
 
   // The least squares of steps j0 .. j1 runs behind the SpMV of step j1 + 1;
   // chunks start at base, base + chunk, ... so that only their last SpMV
@@ -524,11 +568,13 @@ class Solver final : public SolverBase {
            std::to_string(bad(xt)) + "/" + std::to_string(n_) + ", k_hat " + std::to_string(khat_);
   }
 
-  double check(int j) {
+  // Residual check after step j: x~ = [U P] y and r_new = r0 - A x~, queued on
+  // stream A (finish_residual() returns ||r_new||).
+  void enqueue_check(int j) {
     solve_coefficients(j);
     launch_gemv_basis<T>(stream_, n_, U_, n_, khat_, P_, n_, j, ycoef_, xt_);
     LAUNCHCHK();
-    return residual(xt_, r_, rnew_);
+    enqueue_residual(xt_, r_, rnew_);
   }
 
   int solve(const void* bv, void* xv, double tol, sdr_stats* st,
@@ -538,6 +584,7 @@ class Solver final : public SolverBase {
     const double t0 = now();
     double eig_time = 0.0;
     trace->clear();
+    ev_pend_j_ = 0;  // (times of a solve that ended in an error are dropped)
     int matvecs = 0, ips = 0, sketches = 0, checks = 0, iters = 0, cycles = 0;
     const T* vals = basis_values();
     double nb2v = 0.0;
@@ -583,32 +630,18 @@ class Solver final : public SolverBase {
     bool converged = rn <= tol_abs;
     double last_sres = 0.0;
     int status = SDR_NOT_CONVERGED;
-    if (eig_fut_.valid()) eig_fut_.wait();  // left over from a solve that failed
-    eig_fut_ = std::future<EigResult>();
+    (void)wait_eig();  // left over from a solve that failed
     pend_.active = false;
+    bool started = false;  // this cycle's start already queued (at the end of the previous one)
     while (!converged && cycles < opt_.max_cycles) {
       if (!opt_.persist_safety) safety = opt_.safety0;
       sdr_cycle_record rec{};
-      // --- cycle start on stream A: S r0, p_0 = r0, nu_0, SV(:, 0) ---
-      P_ = Pbuf_[cur_];
-      SB_ = SBbuf_[cur_];
-      SAW_ = SAWbuf_[cur_];
-      sketch_cols<A>(r_, 1, Sr_, s_, nullptr);
+      if (!started) start_cycle(r_, rn, tol_abs / safety, vals);
+      started = false;
+      const int cyc_par = cycle_par_;
       sketches++;
       ips++;
-      launch_cast_scale<T>(stream_, n_, r_, rn > 0.0 ? 1.0 / rn : 1.0, P_);  // p_0 = r0 / ||r0||
-      last_sv_ = SB_ + (size_t)kmax_ * s_;
-      __atomic_store_n(&halt_host_->seq, -1, __ATOMIC_RELEASE);
-      launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
-      LAUNCHCHK();
-      // step 1's SpMV sketches p_0; stream B starts behind it with SV(:, 0) and nu_0
-      enqueue_step_a(1, vals, true);
       int enqA = 1;
-      HIPCHK(hipStreamWaitEvent(streamB_, evs_[1 % nslot_], 0));
-      launch_reduce_cols<A>(streamB_, part1_ + slot1_ * (1 % nslot_), nb1_, s_ + 1, s_,
-                            1.0 / std::sqrt((double)sk_.zeta), red0_, nullptr);
-      launch_init_v0<A>(streamB_, red0_, s_, SB_ + (size_t)kmax_ * s_, nu_);
-      LAUNCHCHK();
       if (pend_.active) {
         // The Arnoldi basis of this cycle does not depend on the recycle space
         // (V spans K_m(A, r0)): the previous cycle's eigen-step runs on a
@@ -633,11 +666,18 @@ class Solver final : public SolverBase {
       double res = 0.0, sres = 0.0;
       bool cyc_conv = false;
       enqueue_from(1, enqA, vals);
+      drain_timing();  // the previous cycle's kernel times, while this one runs
       for (;;) {
         HaltRec hr;
         if (!wait_halt(hr)) {
           set_err("halt record missing");
           throw HipError{SDR_EDEVICE};
+        }
+        if (hr.j == m_) {
+          // the cycle ends here whatever the check says: its eigen-step
+          // starts at once (stream B orders it after the least squares)
+          begin_recycle(hr.j, (int)trace->size(), streamB_);
+          early = true;
         }
         sync_both();  // every step record up to hr.j is complete
         StepRec rc{};
@@ -652,13 +692,21 @@ class Solver final : public SolverBase {
         }
         sres = rc.sres;
         {
+          enqueue_check(done);
           if (done == m_) {
-            // the cycle ends here whatever the check says: its eigen-step
-            // starts now and runs beside the check
-            begin_recycle(done, (int)trace->size(), streamB_);
-            early = true;
+            // Unless this check converges the next cycle starts from the new
+            // residual: x += x~ and that start are queued now, ahead of the
+            // host's reading of the residual (wasted work if it converges).
+            if (!(rc.flags & 6) && !opt_.persist_safety && cycles + 1 < opt_.max_cycles) {
+              launch_axpy<A>(stream_, n_, from_cd<A>({1.0, 0.0}), xt_, x);
+              LAUNCHCHK();
+              cur_ ^= 1;
+              start_cycle(rnew_, -1.0, tol_abs / opt_.safety0, vals);
+              cur_ ^= 1;
+              started = true;
+            }
           }
-          res = check(done);
+          res = finish_residual();
           matvecs++;
           ips++;
           checks++;
@@ -694,26 +742,14 @@ class Solver final : public SolverBase {
       cycles++;
       last_sres = sres;
       if (opt_.kernel_timing) {
-        sync_both();
-        for (int j = 1; j <= jstop; ++j) {
-          if (!timed(j)) continue;
-          float a = 0.f, b2 = 0.f, c = 0.f;
-          HIPCHK(hipEventElapsedTime(&a, ev_[j][0], ev_[j][1]));
-          HIPCHK(hipEventElapsedTime(&b2, ev_[j][2], ev_[j][3]));
-          HIPCHK(hipEventElapsedTime(&c, ev_[j][0], ev_[j][3]));
-          kt_ms_[0] += a;
-          kt_ms_[1] += b2;
-          kt_ms_[2] += c;
-          kt_n_[0]++;
-          kt_n_[1]++;
-          kt_n_[2]++;
-          kt_bytes_tw_[std::min(j, t_)]++;
-        }
+        ev_pend_j_ = jstop;  // read during the next cycle (drain_timing)
+        ev_pend_p_ = cyc_par;
       }
       // x += xt, r = r0 - A xt
-      A one = from_cd<A>({1.0, 0.0});
-      launch_axpy<A>(stream_, n_, one, xt_, x);
-      LAUNCHCHK();
+      if (!started) {
+        launch_axpy<A>(stream_, n_, from_cd<A>({1.0, 0.0}), xt_, x);
+        LAUNCHCHK();
+      }
       std::swap(r_, rnew_);
       rn = res;
       rec.j_stop = jstop;
@@ -734,10 +770,38 @@ class Solver final : public SolverBase {
       }
     }
     sync_both();
+    drain_timing();
     status = converged ? SDR_OK : SDR_NOT_CONVERGED;
     fill_stats(st, cycles, iters, matvecs, ips, sketches, checks, status, rn / nb, last_sres,
                safety, now() - t0, eig_time);
     return status;
+  }
+
+  // Cycle start on stream A: S r0, p_0 = r0 / ||r0|| into the P buffer of
+  // cur_, the control block and step 1, whose SpMV sketches p_0; stream B
+  // follows with SV(:, 0) and nu_0.  ||r0|| comes from the host (rn >= 0) or
+  // stays on the device (rn < 0: red3_ holds ||r0||^2 from the last check).
+  void start_cycle(const A* r0, double rn, double thresh, const T* vals) {
+    evp_ ^= 1;
+    cycle_par_ = evp_;
+    P_ = Pbuf_[cur_];
+    SB_ = SBbuf_[cur_];
+    SAW_ = SAWbuf_[cur_];
+    sketch_cols<A>(r0, 1, Sr_, s_, nullptr);
+    if (rn >= 0.0)
+      launch_cast_scale<T>(stream_, n_, r0, rn > 0.0 ? 1.0 / rn : 1.0, P_);
+    else
+      launch_cast_rscale<T>(stream_, n_, r0, red3_, P_);
+    last_sv_ = SB_ + (size_t)kmax_ * s_;
+    __atomic_store_n(&halt_host_->seq, -1, __ATOMIC_RELEASE);
+    launch_set_ctrl(stream_, ctrl_, 0, thresh);
+    LAUNCHCHK();
+    enqueue_step_a(1, vals, true);
+    HIPCHK(hipStreamWaitEvent(streamB_, evs_[1 % nslot_], 0));
+    launch_reduce_cols<A>(streamB_, part1_ + slot1_ * (1 % nslot_), nb1_, s_ + 1, s_,
+                          1.0 / std::sqrt((double)sk_.zeta), red0_, nullptr);
+    launch_init_v0<A>(streamB_, red0_, s_, SB_ + (size_t)kmax_ * s_, nu_);
+    LAUNCHCHK();
   }
 
   // Result of the host eigen-step of a finished cycle.
@@ -770,22 +834,52 @@ class Solver final : public SolverBase {
     HIPCHK(hipMemcpyAsync(hC_, C_, sizeof(A) * (size_t)l0 * l0, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(hnu_, nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
     HIPCHK(hipEventRecord(ev_copy_, st));
-    eig_fut_ = std::async(std::launch::async, [this] {
+    // hand the eigen-step to the worker thread (started once, kept)
+    if (!eig_thr_.joinable()) eig_thr_ = std::thread([this] { eig_loop(); });
+    {
+      std::lock_guard<std::mutex> lk(eig_mu_);
+      eig_job_ = true;
+      eig_done_ = false;
+    }
+    eig_pending_ = true;
+    eig_cv_.notify_all();
+  }
+
+  // Worker thread: one eigen-step per hand-over, until release().
+  void eig_loop() {
+    std::unique_lock<std::mutex> lk(eig_mu_);
+    for (;;) {
+      eig_cv_.wait(lk, [this] { return eig_job_ || eig_quit_; });
+      if (eig_quit_) return;
+      eig_job_ = false;
+      lk.unlock();
+      EigResult r;
       try {
-        return eig_compute();
+        r = eig_compute();
       } catch (HipError& e) {
-        EigResult f;
-        f.code = e.code;
-        f.err = g_err;
-        return f;
+        r = EigResult{};
+        r.code = e.code;
+        r.err = g_err;  // (error strings are per thread)
       }
-    });
+      lk.lock();
+      eig_res_ = std::move(r);
+      eig_done_ = true;
+      eig_cv_.notify_all();
+    }
+  }
+
+  // Wait for the pending eigen-step, if any, and return its result.
+  EigResult wait_eig() {
+    if (!eig_pending_) return EigResult{};
+    std::unique_lock<std::mutex> lk(eig_mu_);
+    eig_cv_.wait(lk, [this] { return eig_done_; });
+    eig_pending_ = false;
+    return std::move(eig_res_);
   }
 
   // The pending eigen-step's result (an empty one if none was started).
   EigResult take_eig() {
-    if (!eig_fut_.valid()) return EigResult{};
-    EigResult er = eig_fut_.get();
+    EigResult er = wait_eig();
     if (er.code) {
       set_err(er.err);
       throw HipError{er.code};
@@ -910,7 +1004,15 @@ class Solver final : public SolverBase {
 
  private:
   void release() {
-    if (eig_fut_.valid()) eig_fut_.wait();
+    (void)wait_eig();
+    if (eig_thr_.joinable()) {
+      {
+        std::lock_guard<std::mutex> lk(eig_mu_);
+        eig_quit_ = true;
+      }
+      eig_cv_.notify_all();
+      eig_thr_.join();
+    }
     for (void* p : {(void*)valB_, (void*)dia_map_, (void*)diaval_, (void*)Pbuf_[0], (void*)Pbuf_[1],
                     (void*)U_, (void*)Unew_, (void*)SU_,
                     (void*)red0_,
@@ -931,15 +1033,19 @@ class Solver final : public SolverBase {
       if (p) (void)hipHostFree(p);
     hR_ = hC_ = hz_ = hy_ = hG_ = hscal_ = hRc_ = nullptr;
     hnu_ = hnuc_ = nullptr;
-    for (auto& a : ev_)
-      for (auto& e : a)
-        if (e) (void)hipEventDestroy(e);
-    ev_.clear();
+    for (auto& evp : ev_) {
+      for (auto& a : evp)
+        for (auto& e : a)
+          if (e) (void)hipEventDestroy(e);
+      evp.clear();
+    }
     for (auto& e : evs_)
       if (e) (void)hipEventDestroy(e);
     evs_.clear();
     if (ev_copy_) (void)hipEventDestroy(ev_copy_);
     ev_copy_ = nullptr;
+    if (ev_res_) (void)hipEventDestroy(ev_res_);
+    ev_res_ = nullptr;
     if (streamB_) (void)hipStreamDestroy(streamB_);
     streamB_ = nullptr;
   }
@@ -971,6 +1077,7 @@ class Solver final : public SolverBase {
     A* SAW = nullptr;
   } pend_;
   hipEvent_t ev_copy_ = nullptr;
+  hipEvent_t ev_res_ = nullptr;   // after the residual norm's copy to the host
   A* last_sv_ = nullptr;  // SV(:, 0) of the last cycle (basis inspection)
   A *SU_ = nullptr, *SAU_ = nullptr, *Q_ = nullptr, *R_ = nullptr, *z_ = nullptr, *rho_ = nullptr;
   A *SB_ = nullptr, *SAW_ = nullptr, *H_ = nullptr;
@@ -990,8 +1097,14 @@ class Solver final : public SolverBase {
   A *hR_ = nullptr, *hC_ = nullptr, *hz_ = nullptr, *hy_ = nullptr, *hG_ = nullptr, *hscal_ = nullptr,
     *hRc_ = nullptr;
   double *hnu_ = nullptr, *hnuc_ = nullptr;
-  std::future<EigResult> eig_fut_;  // the pending cycle's eigen-step on a worker thread
-  std::vector<std::array<hipEvent_t, 4>> ev_;
+  // the pending cycle's eigen-step on a worker thread
+  std::thread eig_thr_;
+  std::mutex eig_mu_;
+  std::condition_variable eig_cv_;
+  bool eig_job_ = false, eig_done_ = false, eig_quit_ = false, eig_pending_ = false;
+  EigResult eig_res_;
+  std::vector<std::array<hipEvent_t, 4>> ev_[2];  // kernel timing events, by cycle parity
+  int evp_ = 0, ev_pend_p_ = 0, ev_pend_j_ = 0, cycle_par_ = 0;
   double kt_ms_[3] = {0, 0, 0};
   int64_t kt_n_[3] = {0, 0, 0};
   int64_t kt_bytes_tw_[kMaxWindow + 1] = {0, 0, 0, 0, 0};
@@ -1048,6 +1161,8 @@ struct sdr_handle {
   uint64_t pattern_hash = 0;
   hipStream_t own = nullptr;
   hipStream_t stream = nullptr;
+  bool follow_null = false;   // run on own, ordered after the null stream's earlier work
+  hipEvent_t ev_in = nullptr;
   std::unique_ptr<SolverBase> fwd, adj;
   std::vector<sdr_cycle_record> trace;
   size_t elem() const { return cpx ? 16 : 8; }
@@ -1148,6 +1263,7 @@ void build_adjoint(sdr_handle* h) {
   HIPCHK(hipMemcpy(h->rpT, rpT.data(), sizeof(int) * (h->n + 1), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(h->ciT, ciT.data(), sizeof(int) * h->nnz, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(h->perm, perm.data(), sizeof(int) * h->nnz, hipMemcpyHostToDevice));
+  HIPCHK(hipStreamSynchronize(nullptr));  // (the adjoint's kernels run on a non-blocking stream)
   h->adj_ready = true;
 }
 
@@ -1198,6 +1314,7 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
     h->cpx = A->dtype == SDR_C128;
     h->pattern_hash = hash_pattern(rp, ci);
     HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
     h->stream = h->own;
     h->rp = dalloc<int>(h->n + 1);
     h->ci = dalloc<int>(h->nnz);
@@ -1207,6 +1324,9 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
       HIPCHK(hipMemcpy(h->ci, A->col_idx, sizeof(int) * h->nnz, hipMemcpyDeviceToDevice));
       HIPCHK(hipMemcpy(h->vals, A->values, h->elem() * h->nnz, hipMemcpyDeviceToDevice));
     }
+    // device-to-device copies may return before they finish, and the handle's
+    // kernels run on non-blocking streams: complete them here
+    HIPCHK(hipStreamSynchronize(nullptr));
     return h;
   } catch (HipError&) {
     if (h) sdr_destroy(h);
@@ -1272,11 +1392,24 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
 
 int sdr_set_stream(sdr_handle* h, void* s) {
   if (!h) return set_err("null handle"), SDR_EINVAL;
+  // NULL: the handle's own (non-blocking) stream, made to wait at each call
+  // for the work queued on the null stream before it (running the solver on
+  // the legacy null stream itself costs launch time)
+  h->follow_null = s == nullptr;
   h->stream = s ? static_cast<hipStream_t>(s) : h->own;
   if (h->fwd) h->fwd->set_stream(h->stream);
   if (h->adj) h->adj->set_stream(h->stream);
   return SDR_OK;
 }
+
+namespace {
+// Order the call's work after the caller's null-stream work (see sdr_set_stream).
+void order_after_caller(sdr_handle* h) {
+  if (!h->follow_null) return;
+  HIPCHK(hipEventRecord(h->ev_in, nullptr));
+  HIPCHK(hipStreamWaitEvent(h->own, h->ev_in, 0));
+}
+}  // namespace
 
 int sdr_update_matrix(sdr_handle* h, const sdr_csr* A) {
   if (!h) return set_err("null handle"), SDR_EINVAL;
@@ -1289,6 +1422,7 @@ int sdr_update_matrix(sdr_handle* h, const sdr_csr* A) {
       set_err("matrix pattern differs from the handle's");
       return SDR_EPATTERN;
     }
+    order_after_caller(h);
     HIPCHK(hipMemcpyAsync(h->vals, A->values, h->elem() * h->nnz, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     refresh_adjoint_values(h);
@@ -1308,6 +1442,7 @@ int sdr_solve(sdr_handle* h, const sdr_csr* A, const void* b, void* x, double to
       int rc = sdr_update_matrix(h, A);
       if (rc != SDR_OK) return rc;
     }
+    order_after_caller(h);
     return fwd(h)->solve(b, x, tol, st, &h->trace);
   } catch (HipError& e) {
     return e.code;
@@ -1325,6 +1460,7 @@ int sdr_solve_adjoint(sdr_handle* h, const void* g, void* lam, double tol, sdr_s
     if (h->s % h->opt.zeta != 0) return set_err("s_dim must be a multiple of zeta"), SDR_EINVAL;
     if (!h->adj) h->adj = make_solver(h, true);
     std::vector<sdr_cycle_record> tr;
+    order_after_caller(h);
     return h->adj->solve(g, lam, tol, st, &tr);
   } catch (HipError& e) {
     return e.code;
@@ -1334,6 +1470,7 @@ int sdr_solve_adjoint(sdr_handle* h, const void* g, void* lam, double tol, sdr_s
 int sdr_grad_values(sdr_handle* h, const void* lam, const void* x, void* g) {
   if (!h || !lam || !x || !g) return set_err("null argument"), SDR_EINVAL;
   try {
+    order_after_caller(h);
     if (h->cpx)
       launch_grad_values<cx<double>>(h->stream, h->n, h->rp, h->ci, static_cast<const cx<double>*>(lam),
                                      static_cast<const cx<double>*>(x), static_cast<cx<double>*>(g));
@@ -1358,6 +1495,7 @@ int sdr_get_trace(sdr_handle* h, sdr_cycle_record* out, int cap) {
 int sdr_get_recycle(sdr_handle* h, void* U, void* SU, void* SAU, int* k) {
   if (!h) return set_err("null handle"), SDR_EINVAL;
   try {
+    order_after_caller(h);
     return fwd(h)->get_recycle(U, SU, SAU, k);
   } catch (HipError& e) {
     return e.code;
@@ -1367,6 +1505,7 @@ int sdr_get_recycle(sdr_handle* h, void* U, void* SU, void* SAU, int* k) {
 int sdr_sketch(sdr_handle* h, const void* X, int ncols, void* Y) {
   if (!h || !X || !Y || ncols < 0) return set_err("bad argument"), SDR_EINVAL;
   try {
+    order_after_caller(h);
     return fwd(h)->sketch(X, ncols, Y);
   } catch (HipError& e) {
     return e.code;
@@ -1376,6 +1515,7 @@ int sdr_sketch(sdr_handle* h, const void* X, int ncols, void* Y) {
 int sdr_spmv(sdr_handle* h, const void* x, void* y) {
   if (!h || !x || !y) return set_err("bad argument"), SDR_EINVAL;
   try {
+    order_after_caller(h);
     Ctrl* c = dalloc<Ctrl>(1);
     HIPCHK(hipMemsetAsync(c, 0, sizeof(Ctrl), h->stream));
     const int nb = (h->n + kRowsSpmv - 1) / kRowsSpmv;
@@ -1409,6 +1549,7 @@ int sdr_spmv(sdr_handle* h, const void* x, void* y) {
 int sdr_get_basis(sdr_handle* h, int ncols, void* V, void* H, void* SV) {
   if (!h) return set_err("null handle"), SDR_EINVAL;
   try {
+    order_after_caller(h);
     return fwd(h)->get_basis(ncols, V, H, SV);
   } catch (HipError& e) {
     return e.code;
@@ -1449,6 +1590,7 @@ void sdr_destroy(sdr_handle* h) {
                   h->valsT})
     dfree(p);
   if (h->own) (void)hipStreamDestroy(h->own);
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   delete h;
 }
 
