@@ -679,7 +679,11 @@ class Solver final : public SolverBase {
           begin_recycle(hr.j, (int)trace->size(), streamB_);
           early = true;
         }
-        sync_both();  // every step record up to hr.j is complete
+        // Every step record up to hr.j is complete (the halt record is
+        // published after them), and stream B's queued chunks must have seen
+        // the halt before a resume clears it; stream A needs no wait: the
+        // check's kernels queue behind its remaining work.
+        HIPCHK(hipStreamSynchronize(streamB_));
         StepRec rc{};
         while (done < hr.j) {
           ++done;
