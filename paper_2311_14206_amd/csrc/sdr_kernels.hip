@@ -398,7 +398,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
     int do_spmv, typename traits<T>::acc* __restrict__ part, int nb, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
   constexpr int KD = ND > 0 ? ND : kMaxDiag;
-  if (ctrl->halt) return;
+  // The halt flag is tested once the first row's loads are out, so its
+  // latency overlaps theirs (a halted launch still reads one row per thread).
+  const int halted = ctrl->halt;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = sk.s;  // 0: no sketch
   A* bins = reinterpret_cast<A*>(smem_raw) + (threadIdx.x >> 6) * s;
@@ -414,6 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
   if (!do_spmv) {
     for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
       const A xa = widen(x[r]);
+      if (halted) return;
       nx += abs2(xa);
       sketch_scatter(bins, r, xa, sk);
     }
@@ -435,6 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
           xc[k] = x[min(max(r + M.off[k], 0), n - 1)];
         }
       }
+      if (halted) return;
       const A xa = widen(xt);
       if (s > 0) {
         nx += abs2(xa);
@@ -458,6 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
         if (q < tw) d[q] += conj(q < tl ? widen(pw[q]) : xa) * wa;
     }
   }
+  if (halted) return;
   __syncthreads();
   int c0 = 0;
   if (s > 0) {
@@ -523,37 +528,37 @@ void launch_pack_dia(hipStream_t st, int64_t nnz, const typename traits<T>::acc*
 // uses.  Then p_j = (w - sum c_q p_q) / nu_{j-1} in place with
 // c_q = <p_q, w> / nu_q^2: a pure stream over w and the window vectors, each
 // thread with kUpdateRows independent rows in flight.
-template <class T>
+template <class T, int TWM>  // TWM: bound on the window length tw
 __global__ __launch_bounds__(kBlock) void k_update(
     int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ part,
     int nb1, int s, double* __restrict__ nu, int i0, int jprev, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
   const int halted = ctrl->halt;  // tested once the loads below are out
-  __shared__ A red[(kMaxWindow + 1) * kWaves];
+  __shared__ A red[(TWM + 1) * kWaves];
   // The stream's loads go out first (clamped rows, unused past n), with the
   // norms of the older window vectors, and are in flight while the block
   // reduces the partials: no dependent global load follows the reduction.
   const int base = xcd_tile(blockIdx.x, gridDim.x) * (kBlock * kUpdateRows) + (int)threadIdx.x;
-  T wv[kUpdateRows], pv[kUpdateRows][kMaxWindow];
+  T wv[kUpdateRows], pv[kUpdateRows][TWM];
 #pragma unroll
   for (int u = 0; u < kUpdateRows; ++u) {
     const int r = min(base + u * kBlock, n - 1);
     wv[u] = w[r];
 #pragma unroll
-    for (int q = 0; q < kMaxWindow; ++q)
+    for (int q = 0; q < TWM; ++q)
       if (q < tw) pv[u][q] = win.p[q][r];
   }
-  double nqv[kMaxWindow];
+  double nqv[TWM];
 #pragma unroll
-  for (int q = 0; q < kMaxWindow; ++q) nqv[q] = (q < tw && i0 + q != jprev) ? nu[i0 + q] : 1.0;
+  for (int q = 0; q < TWM; ++q) nqv[q] = (q < tw && i0 + q != jprev) ? nu[i0 + q] : 1.0;
   if (halted) return;
-  A sums[kMaxWindow + 1];
-  col_sums<A, kMaxWindow + 1>(part, nb1, s, tw + 1, sums, red);
+  A sums[TWM + 1];
+  col_sums<A, TWM + 1>(part, nb1, s, tw + 1, sums, red);
   const double nprev = sqrt(re(sums[0]));
   if (blockIdx.x == 0 && threadIdx.x == 0) nu[jprev] = nprev;
-  A c[kMaxWindow];
+  A c[TWM];
 #pragma unroll
-  for (int q = 0; q < kMaxWindow; ++q) {
+  for (int q = 0; q < TWM; ++q) {
     if (q < tw) {
       const double nq = i0 + q == jprev ? nprev : nqv[q];
       c[q] = scale(sums[1 + q], 1.0 / (nq * nq));
@@ -568,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
     if (r < n) {
       A v = widen(wv[u]);
 #pragma unroll
-      for (int q = 0; q < kMaxWindow; ++q)
+      for (int q = 0; q < TWM; ++q)
         if (q < tw) v -= c[q] * widen(pv[u][q]);
       w[r] = narrow<T>(scale(v, inv));
     }
@@ -580,12 +585,14 @@ void launch_update(hipStream_t st, int n, T* w, Window<T> win, int tw,
                    const typename traits<T>::acc* part, int nb1, int s, double* nu, int i0, int jprev,
                    const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
   const int nb = (n + kBlock * kUpdateRows - 1) / (kBlock * kUpdateRows);
+  void (*kern)(int, T*, Window<T>, int, const typename traits<T>::acc*, int, int, double*, int, int,
+               const Ctrl*) = tw <= 1 ? k_update<T, 1> : tw <= 2 ? k_update<T, 2> : k_update<T, kMaxWindow>;
   if (e0)
-    hipExtLaunchKernelGGL(k_update<T>, dim3(nb), dim3(kBlock), 0, st, e0, e1, 0, n, w, win, tw, part,
-                          nb1, s, nu, i0, jprev, ctrl);
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, e0, e1, 0, n, w, win, tw, part, nb1, s, nu,
+                          i0, jprev, ctrl);
   else
-    hipLaunchKernelGGL(k_update<T>, dim3(nb), dim3(kBlock), 0, st, n, w, win, tw, part, nb1, s, nu, i0,
-                       jprev, ctrl);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, n, w, win, tw, part, nb1, s, nu, i0, jprev,
+                       ctrl);
 }
 
 // ------------------------------------------------ fixed-order reduction ---
