@@ -34,7 +34,8 @@ def build(verbose: bool = True) -> str:
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        extra = ["-march=x86-64-v3", "-fcx-limited-range"] if src == "dense.cpp" else []  # host-only code: AVX2/FMA, inline complex products
+        # host-only code: AVX2/FMA, inline complex products, vectorised dot products
+        extra = ["-march=x86-64-v3", "-fcx-limited-range", "-fopenmp-simd"] if src == "dense.cpp" else []
         cmd = [hipcc, *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

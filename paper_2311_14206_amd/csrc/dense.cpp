@@ -149,6 +149,121 @@ bool schur(Mat& T, Mat& Z) {
   return true;
 }
 
+// M(r0 : r0+len, c0 : c1] -= f v (v^T M(r0 : r0+len, c0 : c1]), four columns a
+// pass (one sweep of v per four dot products and per four updates).
+static void reflect_left(double* __restrict__ M, int n, int r0, int len, const double* __restrict__ v,
+                         double f, int c0, int c1) {
+  int j = c0;
+  for (; j + 4 <= c1; j += 4) {
+    double* __restrict__ a0 = M + (size_t)j * n + r0;
+    double* __restrict__ a1 = a0 + n;
+    double* __restrict__ a2 = a1 + n;
+    double* __restrict__ a3 = a2 + n;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma omp simd reduction(+ : s0, s1, s2, s3)
+    for (int i = 0; i < len; ++i) {
+      s0 += v[i] * a0[i];
+      s1 += v[i] * a1[i];
+      s2 += v[i] * a2[i];
+      s3 += v[i] * a3[i];
+    }
+    s0 *= f;
+    s1 *= f;
+    s2 *= f;
+    s3 *= f;
+    for (int i = 0; i < len; ++i) {
+      a0[i] -= v[i] * s0;
+      a1[i] -= v[i] * s1;
+      a2[i] -= v[i] * s2;
+      a3[i] -= v[i] * s3;
+    }
+  }
+  for (; j < c1; ++j) {
+    double* __restrict__ a0 = M + (size_t)j * n + r0;
+    double s0 = 0.0;
+#pragma omp simd reduction(+ : s0)
+    for (int i = 0; i < len; ++i) s0 += v[i] * a0[i];
+    s0 *= f;
+    for (int i = 0; i < len; ++i) a0[i] -= v[i] * s0;
+  }
+}
+
+// M(0 : n, c0 : c0+len) -= f (M(0 : n, c0 : c0+len) v) v^T, four columns a pass.
+static void reflect_right(double* __restrict__ M, int n, int c0, int len, const double* __restrict__ v,
+                          double f, double* __restrict__ w) {
+  for (int i = 0; i < n; ++i) w[i] = 0.0;
+  int l = 0;
+  for (; l + 4 <= len; l += 4) {
+    const double* __restrict__ a0 = M + (size_t)(c0 + l) * n;
+    const double* __restrict__ a1 = a0 + n;
+    const double* __restrict__ a2 = a1 + n;
+    const double* __restrict__ a3 = a2 + n;
+    const double v0 = v[l], v1 = v[l + 1], v2 = v[l + 2], v3 = v[l + 3];
+    for (int i = 0; i < n; ++i) w[i] += a0[i] * v0 + a1[i] * v1 + a2[i] * v2 + a3[i] * v3;
+  }
+  for (; l < len; ++l) {
+    const double* __restrict__ a0 = M + (size_t)(c0 + l) * n;
+    const double v0 = v[l];
+    for (int i = 0; i < n; ++i) w[i] += a0[i] * v0;
+  }
+  for (int i = 0; i < n; ++i) w[i] *= f;
+  l = 0;
+  for (; l + 4 <= len; l += 4) {
+    double* __restrict__ a0 = M + (size_t)(c0 + l) * n;
+    double* __restrict__ a1 = a0 + n;
+    double* __restrict__ a2 = a1 + n;
+    double* __restrict__ a3 = a2 + n;
+    const double v0 = v[l], v1 = v[l + 1], v2 = v[l + 2], v3 = v[l + 3];
+    for (int i = 0; i < n; ++i) {
+      const double wi = w[i];
+      a0[i] -= wi * v0;
+      a1[i] -= wi * v1;
+      a2[i] -= wi * v2;
+      a3[i] -= wi * v3;
+    }
+  }
+  for (; l < len; ++l) {
+    double* __restrict__ a0 = M + (size_t)(c0 + l) * n;
+    const double v0 = v[l];
+    for (int i = 0; i < n; ++i) a0[i] -= w[i] * v0;
+  }
+}
+
+// Householder reduction of T (n x n, column major) to upper Hessenberg form,
+// T <- Z^T T Z with Z = P_0 P_1 ... P_{n-3}; Z is accumulated afterwards from
+// the last reflector back (each P_k then acts on a trailing block only).
+static void hessenberg(int n, std::vector<double>& T, std::vector<double>& Z) {
+  auto t = [&](int i, int j) -> double& { return T[(size_t)j * n + i]; };
+  std::vector<double> Vr((size_t)n * n, 0.0), F(n, 0.0), w(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int len = n - k - 1;
+    double xn = 0.0;
+    for (int i = 0; i < len; ++i) xn += t(k + 1 + i, k) * t(k + 1 + i, k);
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const double alpha = t(k + 1, k) > 0.0 ? -xn : xn;
+    double* v = Vr.data() + (size_t)k * n;
+    for (int i = 0; i < len; ++i) v[i] = t(k + 1 + i, k);
+    v[0] -= alpha;
+    double vn2 = 0.0;
+    for (int i = 0; i < len; ++i) vn2 += v[i] * v[i];
+    if (vn2 == 0.0) continue;
+    const double f = 2.0 / vn2;
+    F[k] = f;
+    reflect_left(T.data(), n, k + 1, len, v, f, k + 1, n);
+    reflect_right(T.data(), n, k + 1, len, v, f, w.data());
+    t(k + 1, k) = alpha;
+    for (int i = 1; i < len; ++i) t(k + 1 + i, k) = 0.0;
+  }
+  Z.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+  for (int k = n - 3; k >= 0; --k) {
+    if (F[k] == 0.0) continue;
+    // Z(k+1:, k+1:) <- P_k Z(k+1:, k+1:): columns left of k+1 are untouched
+    reflect_left(Z.data(), n, k + 1, n - k - 1, Vr.data() + (size_t)k * n, F[k], k + 1, n);
+  }
+}
+
 // Real Schur form by Hessenberg reduction and Francis double-shift QR
 // (real arithmetic throughout): A = Z T Z^T with T quasi-upper triangular.
 // 2 x 2 diagonal blocks with real eigenvalues are split by a rotation, so every
@@ -156,48 +271,11 @@ bool schur(Mat& T, Mat& Z) {
 static bool schur_real(int n, std::vector<double>& T, std::vector<double>& Z) {
   auto t = [&](int i, int j) -> double& { return T[(size_t)j * n + i]; };
   auto z = [&](int i, int j) -> double& { return Z[(size_t)j * n + i]; };
-  Z.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) z(i, i) = 1.0;
-  if (n <= 1) return true;
-  std::vector<double> v(n), wrk(n);
-  for (int k = 0; k + 2 < n; ++k) {  // Householder reduction to Hessenberg form
-    const int len = n - k - 1;
-    double xn = 0.0;
-    for (int i = 0; i < len; ++i) xn += t(k + 1 + i, k) * t(k + 1 + i, k);
-    xn = std::sqrt(xn);
-    if (xn == 0.0) continue;
-    const double alpha = t(k + 1, k) > 0.0 ? -xn : xn;
-    for (int i = 0; i < len; ++i) v[i] = t(k + 1 + i, k);
-    v[0] -= alpha;
-    double vn2 = 0.0;
-    for (int i = 0; i < len; ++i) vn2 += v[i] * v[i];
-    if (vn2 == 0.0) continue;
-    const double f = 2.0 / vn2;
-    for (int j = k; j < n; ++j) {
-      double sm = 0.0;
-      for (int i = 0; i < len; ++i) sm += v[i] * t(k + 1 + i, j);
-      sm *= f;
-      for (int i = 0; i < len; ++i) t(k + 1 + i, j) -= v[i] * sm;
-    }
-    // right: M(:, k+1:) -= f (M(:, k+1:) v) v^T, column by column
-    for (std::vector<double>* Mp : {&T, &Z}) {
-      double* M = Mp->data();
-      std::fill(wrk.begin(), wrk.end(), 0.0);
-      for (int l = 0; l < len; ++l) {
-        const double* col = M + (size_t)(k + 1 + l) * n;
-        const double vl = v[l];
-        for (int i = 0; i < n; ++i) wrk[i] += col[i] * vl;
-      }
-      for (int i = 0; i < n; ++i) wrk[i] *= f;
-      for (int l = 0; l < len; ++l) {
-        double* col = M + (size_t)(k + 1 + l) * n;
-        const double vl = v[l];
-        for (int i = 0; i < n; ++i) col[i] -= wrk[i] * vl;
-      }
-    }
-    t(k + 1, k) = alpha;
-    for (int i = 1; i < len; ++i) t(k + 1 + i, k) = 0.0;
+  if (n <= 1) {
+    Z.assign((size_t)n * n, 1.0);
+    return true;
   }
+  hessenberg(n, T, Z);
   // reflector P = I - beta v v^T (len 2 or 3) applied to rows k.. (left) and
   // columns k.. (right) of T, and to columns of Z
   auto left = [&](int k, int len, const double* vv, double beta, int c0, int c1) {
@@ -592,19 +670,42 @@ static Mat real_basis(const Mat& Zk, int keff) {
 }
 
 // Ri = R^{-1} (R upper triangular, n x n, column major, nonsingular) by
-// columns, X = Ri C, and the bound ||R||_F ||R^{-1}||_F returned.  Loops run
-// down contiguous columns.
+// back substitution, X = Ri C, and the bound ||R||_F ||R^{-1}||_F returned.
+// Both run four columns a pass down contiguous columns (one load of a column
+// of R or R^{-1} serves four updates).
 template <class S>
 static double tri_inverse_product(int n, const S* R, S* Ri, const S* C, std::vector<S>& X) {
-  for (int j = 0; j < n; ++j) {
-    S* col = Ri + (size_t)j * n;
-    col[j] = S(1.0) / R[(size_t)j * n + j];
-    // column j of R^{-1}: back substitution R x = e_j, x(j) known
-    for (int p = j; p >= 1; --p) {
-      const S xp = col[p];
-      const S* rp = R + (size_t)p * n;  // column p of R: rows 0 .. p-1 above the diagonal
-      for (int i = 0; i < p; ++i) col[i] -= rp[i] * xp;
-      col[p - 1] /= R[(size_t)(p - 1) * n + (p - 1)];
+  // Ri zero on entry; column jc = j0 + c is R^{-1} e_jc, its rows above jc
+  // found from the bottom: at step p row p is final, rows 0 .. p-1 take its
+  // contribution and row p-1 is then divided by its diagonal entry
+  for (int j0 = 0; j0 < n; j0 += 4) {
+    const int jb = std::min(4, n - j0);
+    S* col[4];
+    for (int c = 0; c < 4; ++c) col[c] = Ri + (size_t)(j0 + std::min(c, jb - 1)) * n;
+    for (int c = 0; c < jb; ++c) col[c][j0 + c] = S(1.0) / R[(size_t)(j0 + c) * n + j0 + c];
+    for (int p = j0 + jb - 1; p >= 1; --p) {
+      const S* __restrict__ rp = R + (size_t)p * n;
+      S xp[4];
+      for (int c = 0; c < 4; ++c) xp[c] = c < jb && p <= j0 + c ? col[c][p] : S(0.0);
+      S* __restrict__ c0 = col[0];
+      S* __restrict__ c1 = col[1];
+      S* __restrict__ c2 = col[2];
+      S* __restrict__ c3 = col[3];
+      if (jb == 4) {
+        for (int i = 0; i < p; ++i) {
+          const S r = rp[i];
+          c0[i] -= r * xp[0];
+          c1[i] -= r * xp[1];
+          c2[i] -= r * xp[2];
+          c3[i] -= r * xp[3];
+        }
+      } else {
+        for (int c = 0; c < jb; ++c)
+          for (int i = 0; i < p; ++i) col[c][i] -= rp[i] * xp[c];
+      }
+      const S d = R[(size_t)(p - 1) * n + (p - 1)];
+      for (int c = 0; c < jb; ++c)
+        if (p <= j0 + c) col[c][p - 1] /= d;
     }
   }
   double f = 0.0, fi = 0.0;
@@ -614,11 +715,30 @@ static double tri_inverse_product(int n, const S* R, S* Ri, const S* C, std::vec
       fi += norm_(Ri[(size_t)j * n + i]);
     }
   X.assign((size_t)n * n, S(0.0));
-  for (int j = 0; j < n; ++j) {
+  int j = 0;
+  for (; j + 4 <= n; j += 4) {
+    S* __restrict__ x0 = X.data() + (size_t)j * n;
+    S* __restrict__ x1 = x0 + n;
+    S* __restrict__ x2 = x1 + n;
+    S* __restrict__ x3 = x2 + n;
+    for (int p = 0; p < n; ++p) {
+      const S a0 = C[(size_t)j * n + p], a1 = C[(size_t)(j + 1) * n + p];
+      const S a2 = C[(size_t)(j + 2) * n + p], a3 = C[(size_t)(j + 3) * n + p];
+      const S* __restrict__ rip = Ri + (size_t)p * n;  // column p of R^{-1}: rows 0 .. p
+      for (int i = 0; i <= p; ++i) {
+        const S r = rip[i];
+        x0[i] += r * a0;
+        x1[i] += r * a1;
+        x2[i] += r * a2;
+        x3[i] += r * a3;
+      }
+    }
+  }
+  for (; j < n; ++j) {
     S* xj = X.data() + (size_t)j * n;
     for (int p = 0; p < n; ++p) {
       const S cpj = C[(size_t)j * n + p];
-      const S* rip = Ri + (size_t)p * n;  // column p of R^{-1}: rows 0 .. p
+      const S* rip = Ri + (size_t)p * n;
       for (int i = 0; i <= p; ++i) xj[i] += rip[i] * cpj;
     }
   }
@@ -696,36 +816,65 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
   }
   *ell_out = ell;
   const int n = ell;
-  Mat T, Z;
+  // moduli of the eigenvalues; in the real Schur form a 2 x 2 block holds a
+  // conjugate pair whose common modulus is the square root of its determinant
+  std::vector<double> mod(n);
   std::vector<int> partner(n, -1);
+  std::vector<double> Tr, Zr;
+  Mat T, Z;
   if (real) {
-    std::vector<double> Tr((size_t)n * n), Zr;
+    Tr.resize((size_t)n * n);
     for (size_t i = 0; i < Tr.size(); ++i) Tr[i] = Aeig.a[i].real();
     if (!schur_real(n, Tr, Zr)) return -1;
-    real_to_complex_schur(n, Tr, Zr, T, Z, partner);
+    auto tr = [&](int i, int j) { return Tr[(size_t)j * n + i]; };
+    for (int i = 0; i < n; ++i) {
+      if (i + 1 < n && tr(i + 1, i) != 0.0) {
+        const double det = tr(i, i) * tr(i + 1, i + 1) - tr(i, i + 1) * tr(i + 1, i);
+        mod[i] = mod[i + 1] = std::sqrt(std::fabs(det));
+        partner[i] = i + 1;
+        partner[i + 1] = i;
+        ++i;
+      } else {
+        mod[i] = std::fabs(tr(i, i));
+      }
+    }
   } else {
     T = Aeig;
     if (!schur(T, Z)) return -1;
+    for (int i = 0; i < n; ++i) mod[i] = std::abs(T(i, i));
   }
-  std::vector<cd> lam(n);
-  for (int i = 0; i < n; ++i) lam[i] = T(i, i);
   std::vector<int> ord(n);
   std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(),
-                   [&](int a, int b) { return std::abs(lam[a]) > std::abs(lam[b]); });
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return mod[a] > mod[b]; });
   const int kk = std::min(k, n);
   std::vector<char> sel(n, 0);
   for (int i = 0; i < kk; ++i) sel[ord[i]] = 1;
-  if (real) {
-    // never split a complex-conjugate pair (the two members of a 2 x 2 block)
-    for (int i = 0; i < n; ++i)
-      if (sel[i] && partner[i] >= 0) sel[partner[i]] = 1;
+  // never split a complex-conjugate pair (the two members of a 2 x 2 block)
+  for (int i = 0; i < n; ++i)
+    if (sel[i] && partner[i] >= 0) sel[partner[i]] = 1;
+  int keff = 0;
+  while (keff < n && sel[keff]) ++keff;
+  bool leading = true;  // the selection already leads the Schur form
+  for (int i = keff; i < n; ++i)
+    if (sel[i]) leading = false;
+  Mat Y;
+  if (real && leading) {
+    // the leading real Schur vectors are an orthonormal real basis of the
+    // selected invariant subspace: no reordering, no complex form needed
+    Y = Mat(n, keff);
+    for (int j = 0; j < keff; ++j)
+      for (int i = 0; i < n; ++i) Y(i, j) = Zr[(size_t)j * n + i];
+  } else {
+    if (real) {
+      std::vector<int> pc;
+      real_to_complex_schur(n, Tr, Zr, T, Z, pc);
+    }
+    keff = reorder(T, Z, sel);
+    Mat Zk(n, keff);
+    for (int j = 0; j < keff; ++j)
+      for (int i = 0; i < n; ++i) Zk(i, j) = Z(i, j);
+    Y = real ? real_basis(Zk, keff) : Zk;
   }
-  const int keff = reorder(T, Z, sel);
-  Mat Zk(n, keff);
-  for (int j = 0; j < keff; ++j)
-    for (int i = 0; i < n; ++i) Zk(i, j) = Z(i, j);
-  Mat Y = real ? real_basis(Zk, keff) : Zk;
   G.assign((size_t)l0 * keff, cd(0.0));
   if (!svd_path) {
     for (int j = 0; j < keff; ++j)

@@ -72,6 +72,22 @@ def test_host_harmonic_ritz_matches_oracle(cplx, seed):
 
 
 @pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("seed", [3, 4])
+def test_host_harmonic_ritz_matches_oracle_full_size(cplx, seed):
+    """The cycle's size of the timed workload: ell0 = k + m = 120, s = 240."""
+    from oracle import harmonic_ritz_update
+    from paper_2311_14206_amd.sdr import host_harmonic_ritz
+    s, l0, k = 240, 120, 20
+    SAW, SB = _case(seed, s, l0, cplx)
+    Q, R = np.linalg.qr(SAW)
+    G, ell, keff = host_harmonic_ritz(R, Q.conj().T @ SB, s, k, cplx)
+    Go, ello, keffo = harmonic_ritz_update(np.eye(l0), SB, SAW, k, not cplx, s)
+    assert keff == keffo and ell == ello
+    assert _angle(G, Go) < 1e-8
+    assert np.linalg.norm(G.conj().T @ G - np.eye(keff)) < 1e-12
+
+
+@pytest.mark.parametrize("cplx", [False, True])
 def test_host_harmonic_ritz_truncated_svd_path(cplx):
     """A numerically dependent column of SAW: the truncated SVD drops it."""
     from oracle import harmonic_ritz_update
