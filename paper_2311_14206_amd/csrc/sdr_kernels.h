@@ -169,7 +169,17 @@ template <class A>
 void launch_spmv_residual(hipStream_t st, int n, const int* rp, const int* ci, const A* val,
                           const A* x, const A* r0, A* rnew, A* part, int nb);
 
-// C = [U P] G (n x kc), G (ku + jp) x kc column major (ld = ku + jp).
+// rnew = r0 - A x with A in diagonal storage (values in the accumulation
+// type), partials as launch_spmv_residual.
+template <class A>
+void launch_spmv_dia_residual(hipStream_t st, int n, DiaView<A> M, const A* x, const A* r0, A* rnew, A* part,
+                              int nb);
+
+// Row width of G for launch_gemm_basis: kc rounded up to a multiple of 8.
+int gemm_basis_width(int kc);
+
+// C = [U P] G (n x kc), G (ku + jp) x kc stored row major with
+// gemm_basis_width(kc) entries a row, zero beyond column kc.
 template <class T>
 void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
                        int64_t ldp, int jp, const typename traits<T>::acc* G, int kc, T* C,

@@ -1570,6 +1570,63 @@ __global__ __launch_bounds__(kBlock) void k_spmv_residual(int n, const int* __re
   }
 }
 
+// rnew = r0 - A x over the diagonal storage (values in the accumulation
+// type), partial ||rnew||^2 per block exactly as k_spmv_residual.
+template <class A, int ND>
+__global__ __launch_bounds__(kBlock) void k_spmv_dia_residual(int n, DiaView<A> M, const A* __restrict__ x,
+                                                              const A* __restrict__ r0,
+                                                              A* __restrict__ rnew, A* __restrict__ part) {
+  constexpr int KD = ND > 0 ? ND : kMaxDiag;
+  __shared__ A red[kWaves];
+  const int nd = ND > 0 ? ND : M.ndiag;
+  double nrm = 0.0;
+  const int b0 = blockIdx.x * kRowsUpdate;
+  const int b1 = min(n, b0 + kRowsUpdate);
+  for (int r = b0 + (int)threadIdx.x; r < b1; r += kBlock) {
+    A vv[KD], xc[KD];
+#pragma unroll
+    for (int k = 0; k < KD; ++k) {
+      if (ND > 0 || k < nd) {
+        vv[k] = M.val[(int64_t)k * n + r];
+        xc[k] = x[min(max(r + M.off[k], 0), n - 1)];
+      }
+    }
+    const A rr = r0[r];
+    A acc = zero<A>();
+#pragma unroll
+    for (int k = 0; k < KD; ++k) {
+      if (ND > 0 || k < nd) {
+        const int c = r + M.off[k];
+        const A t = vv[k] * xc[k];
+        acc += (c >= 0 && c < n) ? t : zero<A>();
+      }
+    }
+    const A v = rr - acc;
+    rnew[r] = v;
+    nrm += abs2(v);
+  }
+  const double sum = block_sum(nrm, (double*)red);
+  if (threadIdx.x == 0) {
+    A v = zero<A>();
+    *(double*)&v = sum;
+    part[blockIdx.x] = v;
+  }
+}
+
+template <class A>
+void launch_spmv_dia_residual(hipStream_t st, int n, DiaView<A> M, const A* x, const A* r0, A* rnew, A* part,
+                              int nb) {
+  void (*kern)(int, DiaView<A>, const A*, const A*, A*, A*);
+  switch (M.ndiag) {
+    case 3: kern = k_spmv_dia_residual<A, 3>; break;
+    case 5: kern = k_spmv_dia_residual<A, 5>; break;
+    case 7: kern = k_spmv_dia_residual<A, 7>; break;
+    case 9: kern = k_spmv_dia_residual<A, 9>; break;
+    default: kern = k_spmv_dia_residual<A, 0>; break;
+  }
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, n, M, x, r0, rnew, part);
+}
+
 template <class A>
 void launch_spmv_residual(hipStream_t st, int n, const int* rp, const int* ci, const A* val,
                           const A* x, const A* r0, A* rnew, A* part, int nb) {
@@ -1577,47 +1634,47 @@ void launch_spmv_residual(hipStream_t st, int n, const int* rp, const int* ci, c
                      part);
 }
 
-// C = [U P] G with G staged in LDS; one row per thread, kc <= KM accumulators.
+// C = [U P] G, one row per thread with KM accumulators.  G is row major (row
+// stride ldg, zero beyond column kc): its entries are the same for every
+// lane, so they are read with scalar loads straight into the multiply-adds'
+// scalar operands (a row of G in a few wide loads, no LDS traffic).
 template <class T, int KM>
 __global__ __launch_bounds__(kBlock) void k_gemm_basis(int n, const T* __restrict__ U, int64_t ldu,
                                                        int ku, const T* __restrict__ P, int64_t ldp,
                                                        int jp, const typename traits<T>::acc* __restrict__ G,
-                                                       int kc, T* __restrict__ C, int64_t ldc) {
+                                                       int ldg, int kc, T* __restrict__ C, int64_t ldc) {
   using A = typename traits<T>::acc;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  A* gs = reinterpret_cast<A*>(smem_raw);  // (ku + jp) x KM, row major
   const int l0 = ku + jp;
-  for (int i = threadIdx.x; i < l0 * KM; i += blockDim.x) {
-    const int row = i / KM, c = i % KM;
-    gs[i] = c < kc ? G[row + (int64_t)c * l0] : zero<A>();
-  }
-  __syncthreads();
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     A acc[KM];
 #pragma unroll
     for (int c = 0; c < KM; ++c) acc[c] = zero<A>();
-    // four input columns per round, their loads issued together (the column
-    // pointer is chosen without a branch); accumulation in column order
+    // two input columns per round, their loads issued together (the column
+    // pointer is chosen without a branch); accumulation in column order.
+    // Wider rounds hold more rows of G in scalar registers than fit and ran
+    // slower.
     int i = 0;
-    for (; i + 4 <= l0; i += 4) {
-      A v[4];
+    for (; i + 2 <= l0; i += 2) {
+      A v[2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 2; ++u) {
         const int ii = i + u;
         const T* src = ii < ku ? U + ii * ldu : P + (int64_t)(ii - ku) * ldp;
         v[u] = widen(src[r]);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 2; ++u) {
+        const A* g = G + (int64_t)(i + u) * ldg;
 #pragma unroll
-        for (int c = 0; c < KM; ++c) acc[c] += v[u] * gs[(i + u) * KM + c];
+        for (int c = 0; c < KM; ++c) acc[c] += v[u] * g[c];
       }
     }
     for (; i < l0; ++i) {
       const T* src = i < ku ? U + i * ldu : P + (int64_t)(i - ku) * ldp;
       const A v = widen(src[r]);
+      const A* g = G + (int64_t)i * ldg;
 #pragma unroll
-      for (int c = 0; c < KM; ++c) acc[c] += v * gs[i * KM + c];
+      for (int c = 0; c < KM; ++c) acc[c] += v * g[c];
     }
 #pragma unroll
     for (int c = 0; c < KM; ++c)
@@ -1625,33 +1682,33 @@ __global__ __launch_bounds__(kBlock) void k_gemm_basis(int n, const T* __restric
   }
 }
 
+int gemm_basis_width(int kc) { return kc <= 8 ? 8 : (kc + 7) / 8 * 8; }
+
 template <class T>
 void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, const T* P,
                        int64_t ldp, int jp, const typename traits<T>::acc* G, int kc, T* C,
                        int64_t ldc) {
-  using A = typename traits<T>::acc;
   const int nb = (n + kBlock - 1) / kBlock;
-  const int l0 = ku + jp;
-  // output columns in chunks whose staged G fits in 48 KB of LDS
-  int km = 32;
-  while (km > 8 && (size_t)l0 * km * sizeof(A) > 48 * 1024) km /= 2;
-  for (int c0 = 0; c0 < kc; c0 += km) {
+  const int ldg = gemm_basis_width(kc);
+  // output columns in launches of at most 32 (the padded row width covers
+  // the last one)
+  for (int c0 = 0; c0 < kc; c0 += 32) {
+    const int km = gemm_basis_width(kc - c0 < 32 ? kc - c0 : 32);
     const int cc = kc - c0 < km ? kc - c0 : km;
-    const A* Gc = G + (int64_t)c0 * l0;
+    const auto* Gc = G + c0;
     T* Cc = C + (int64_t)c0 * ldc;
-    if (cc <= 8) {
-      hipLaunchKernelGGL((k_gemm_basis<T, 8>), dim3(nb), dim3(kBlock), (size_t)l0 * 8 * sizeof(A), st,
-                         n, U, ldu, ku, P, ldp, jp, Gc, cc, Cc, ldc);
-    } else if (cc <= 16) {
-      hipLaunchKernelGGL((k_gemm_basis<T, 16>), dim3(nb), dim3(kBlock), (size_t)l0 * 16 * sizeof(A),
-                         st, n, U, ldu, ku, P, ldp, jp, Gc, cc, Cc, ldc);
-    } else if (cc <= 24) {
-      hipLaunchKernelGGL((k_gemm_basis<T, 24>), dim3(nb), dim3(kBlock), (size_t)l0 * 24 * sizeof(A),
-                         st, n, U, ldu, ku, P, ldp, jp, Gc, cc, Cc, ldc);
-    } else {
-      hipLaunchKernelGGL((k_gemm_basis<T, 32>), dim3(nb), dim3(kBlock), (size_t)l0 * 32 * sizeof(A),
-                         st, n, U, ldu, ku, P, ldp, jp, Gc, cc, Cc, ldc);
-    }
+    if (km == 8)
+      hipLaunchKernelGGL((k_gemm_basis<T, 8>), dim3(nb), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp, jp,
+                         Gc, ldg, cc, Cc, ldc);
+    else if (km == 16)
+      hipLaunchKernelGGL((k_gemm_basis<T, 16>), dim3(nb), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp,
+                         jp, Gc, ldg, cc, Cc, ldc);
+    else if (km == 24)
+      hipLaunchKernelGGL((k_gemm_basis<T, 24>), dim3(nb), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp,
+                         jp, Gc, ldg, cc, Cc, ldc);
+    else
+      hipLaunchKernelGGL((k_gemm_basis<T, 32>), dim3(nb), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp,
+                         jp, Gc, ldg, cc, Cc, ldc);
   }
 }
 
@@ -1942,6 +1999,8 @@ SDR_INST_BASIS(cx<float>)
   template void launch_reduce_steps<A>(hipStream_t, const A*, int64_t, int, int, int, int, int,  \
                                        int, double, A*, int64_t, const Ctrl*);                  \
   template void launch_backsolve<A>(hipStream_t, LsqState<A>, int, int, A*);                    \
+  template void launch_spmv_dia_residual<A>(hipStream_t, int, DiaView<A>, const A*, const A*, A*, A*, \
+                                            int);                                                   \
   template void launch_spmv_residual<A>(hipStream_t, int, const int*, const int*, const A*,     \
                                         const A*, const A*, A*, A*, int);                      \
   template bool launch_back_subst<A>(hipStream_t, int, int, const A*, int, const A*, const double*, A*); \

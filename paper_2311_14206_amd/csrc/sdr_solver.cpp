@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstring>
 #include <condition_variable>
+#include <type_traits>
 #include <future>
 #include <mutex>
 #include <thread>
@@ -221,7 +222,7 @@ class Solver final : public SolverBase {
       xt_ = dalloc<A>(N);
       r_ = dalloc<A>(N);
       rnew_ = dalloc<A>(N);
-      G_ = dalloc<A>((size_t)lmax_ * kmax_);
+      G_ = dalloc<A>((size_t)lmax_ * gemm_basis_width(kmax_));
       Gs_ = dalloc<A>((size_t)lmax_ * kmax_);
       C_ = dalloc<A>((size_t)lmax_ * lmax_);
       if (opt.kernel_timing) {
@@ -243,7 +244,8 @@ class Solver final : public SolverBase {
       HIPCHK(hipHostMalloc((void**)&hnu_, sizeof(double) * (size_t)(m + 2), hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hRc_, sizeof(A) * (size_t)lmax_ * lmax_, hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hnuc_, sizeof(double) * (size_t)(m + 2), hipHostMallocDefault));
-      HIPCHK(hipHostMalloc((void**)&hG_, sizeof(A) * (size_t)lmax_ * kmax_ * 2, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hG_, sizeof(A) * (size_t)lmax_ * (2 * kmax_ + gemm_basis_width(kmax_)),
+                           hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hscal_, sizeof(A) * 8, hipHostMallocDefault));
       HIPCHK(hipMemsetAsync(ctrl_free_, 0, sizeof(Ctrl), stream_));
       HIPCHK(hipMemsetAsync(nu_, 0, sizeof(double) * (m + 2), stream_));
@@ -343,7 +345,17 @@ class Solver final : public SolverBase {
   // r = b - A x and ||r||^2 to the host, queued on stream A; finish_residual()
   // waits for it.
   void enqueue_residual(const A* x, const A* b, A* r) {
-    launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, psk_, nb2_);
+    if constexpr (std::is_same<T, A>::value) {
+      // the diagonal storage holds the matrix in full precision: same sums
+      if (dia()) {
+        (void)basis_values();  // (packed if the values changed)
+        launch_spmv_dia_residual<A>(stream_, n_, dia_, x, b, r, psk_, nb2_);
+      } else {
+        launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, psk_, nb2_);
+      }
+    } else {
+      launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, psk_, nb2_);
+    }
     LAUNCHCHK();
     launch_reduce_cols<A>(stream_, psk_, nb2_, 1, 0, 1.0, red3_, nullptr);
     LAUNCHCHK();
@@ -936,7 +948,12 @@ class Solver final : public SolverBase {
       HIPCHK(hipMemcpyAsync(Gs_, Gh, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, streamB_));
       launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SB, s_, Gs_, l0, SU_, s_);
       launch_small_gemm<A>(streamB_, false, s_, keff, l0, pend_.SAW, s_, Gs_, l0, SAU_, s_);
-      HIPCHK(hipMemcpyAsync(G_, Gp, sizeof(A) * (size_t)l0 * keff, hipMemcpyHostToDevice, stream_));
+      // the basis product takes G row major, rows padded with zeros
+      const int gw = gemm_basis_width(keff);
+      A* Gr = Gp + (size_t)l0 * keff;
+      for (int i = 0; i < l0; ++i)
+        for (int c = 0; c < gw; ++c) Gr[(size_t)i * gw + c] = c < keff ? Gp[(size_t)c * l0 + i] : A{};
+      HIPCHK(hipMemcpyAsync(G_, Gr, sizeof(A) * (size_t)l0 * gw, hipMemcpyHostToDevice, stream_));
       launch_gemm_basis<T>(stream_, n_, U_, n_, khat, pend_.P, n_, pend_.j, G_, keff, Unew_, n_);
       LAUNCHCHK();
       std::swap(U_, Unew_);
