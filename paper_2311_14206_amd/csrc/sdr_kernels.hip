@@ -177,7 +177,7 @@ __device__ __forceinline__ A col_sum(const A* __restrict__ part, int nb, int col
 // Columns c0 .. c0 + nc - 1 (nc <= NMAX) of a partial array at once, each in
 // exactly col_sum's order (so the same bits), with the loads of all columns
 // in flight together and one barrier round for all of them.
-template <class A, int NMAX>
+template <class A, int NMAX, bool FRESH = false>
 __device__ __forceinline__ void col_sums(const A* __restrict__ part, int nb, int c0, int nc, A (&out)[NMAX],
                                          A* red /* NMAX * kWaves */) {
   A sum[NMAX];
@@ -203,7 +203,9 @@ __device__ __forceinline__ void col_sums(const A* __restrict__ part, int nb, int
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < NMAX; ++c) sum[c] = wave_sum(sum[c]);
-  __syncthreads();
+  // (FRESH: red is used once in the kernel, so the barriers that order it
+  // against earlier and later uses are not needed)
+  if (!FRESH) __syncthreads();
   if (lane == 0) {
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) red[c * kWaves + wv] = sum[c];
@@ -215,11 +217,52 @@ __device__ __forceinline__ void col_sums(const A* __restrict__ part, int nb, int
     for (int i = 1; i < kWaves; ++i) t += red[c * kWaves + i];
     out[c] = t;
   }
-  __syncthreads();
+  if (!FRESH) __syncthreads();
 }
 
 __device__ __forceinline__ void put_re(double* p, double v) { *p = v; }
 __device__ __forceinline__ void put_re(cx<double>* p, double v) { *p = cx<double>{v, 0.0}; }
+
+// End of the SpMV kernels: the sketch bins (summed over the waves; bins_all
+// holds kWaves wave-major rows of s bins), ||x||^2 (when sketching), the
+// window products and ||w||^2 into the tile's partial slots.  The values are
+// summed per wave first, then one barrier (which also completes the bins)
+// and a fixed-order sum over the waves: the same operations in the same
+// order as one block_sum per value, with one barrier instead of three each.
+template <class A>
+__device__ __forceinline__ void store_step_partials(A* __restrict__ part, int nb, int tile, int s, int tw,
+                                                    const A* bins_all, double nx, const A (&d)[kMaxWindow],
+                                                    double nw, A (*wsum)[kMaxWindow + 2]) {
+  constexpr int NV = kMaxWindow + 2;
+  {
+    A v[NV];
+    v[0] = zero<A>();
+    put_re(&v[0], s > 0 ? wave_sum(nx) : 0.0);
+#pragma unroll
+    for (int q = 0; q < kMaxWindow; ++q) v[1 + q] = q < tw ? wave_sum(d[q]) : zero<A>();
+    v[NV - 1] = zero<A>();
+    put_re(&v[NV - 1], wave_sum(nw));
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) wsum[threadIdx.x >> 6][i] = v[i];
+  }
+  __syncthreads();
+  for (int row = threadIdx.x; row < s; row += kBlock) {
+    A sum = bins_all[row];
+    for (int q = 1; q < kWaves; ++q) sum += bins_all[q * s + row];
+    part[(int64_t)row * nb + tile] = sum;
+  }
+  // thread i < tw + 2 writes value i: ||x||^2 (when sketching) at row s, the
+  // window products at s + 1 + q, ||w||^2 at s + 1 + tw (without the sketch
+  // the rows start at 0 with the products)
+  const int i = threadIdx.x;
+  if (i >= (s > 0 ? 0 : 1) && i < tw + 2) {
+    const int src = i <= tw ? i : NV - 1;
+    A sum = wsum[0][src];
+    for (int q = 1; q < kWaves; ++q) sum += wsum[q][src];
+    part[(int64_t)(s > 0 ? s + i : i - 1) * nb + tile] = sum;
+  }
+}
 
 // Row tile of a block in the streaming kernels.  Workgroups are dispatched
 // to the 8 XCDs round robin, each XCD with its own L2: tile t of nb goes to
@@ -255,7 +298,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sketch(
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   A* bins = reinterpret_cast<A*>(smem_raw) + wv * s;                   // this wave's sketch [s]
   A* prod = reinterpret_cast<A*>(smem_raw) + kWaves * s + wv * wave_cap;  // this wave's staging
-  __shared__ A red[kWaves];
   for (int i = lane; i < s; i += 64) bins[i] = zero<A>();
   A d[kMaxWindow];
 #pragma unroll
@@ -335,28 +377,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sketch(
       }
     }
   }
-  __syncthreads();
-  int c0 = 0;
-  if (s > 0) {
-    A* all = reinterpret_cast<A*>(smem_raw);
-    for (int row = threadIdx.x; row < s; row += kBlock) {
-      A sum = all[row];
-      for (int q = 1; q < kWaves; ++q) sum += all[q * s + row];
-      part[(int64_t)row * nb + tile] = sum;
-    }
-    const double sx = block_sum(nx, (double*)red);
-    if (threadIdx.x == 0) put_re(part + (int64_t)s * nb + tile, sx);
-    c0 = s + 1;
-  }
-#pragma unroll
-  for (int q = 0; q < kMaxWindow; ++q) {
-    if (q < tw) {
-      const A v = block_sum(d[q], red);
-      if (threadIdx.x == 0) part[(int64_t)(c0 + q) * nb + tile] = v;
-    }
-  }
-  const double sw = block_sum(nw, (double*)red);
-  if (threadIdx.x == 0) put_re(part + (int64_t)(c0 + tw) * nb + tile, sw);
+  __shared__ A wsum[kWaves][kMaxWindow + 2];
+  store_step_partials(part, nb, tile, s, tw, reinterpret_cast<const A*>(smem_raw), nx, d, nw, wsum);
 }
 
 template <class T>
@@ -404,7 +426,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = sk.s;  // 0: no sketch
   A* bins = reinterpret_cast<A*>(smem_raw) + (threadIdx.x >> 6) * s;
-  __shared__ A red[kWaves];
   for (int i = threadIdx.x & 63; i < s; i += 64) bins[i] = zero<A>();
   A d[kMaxWindow];
 #pragma unroll
@@ -463,28 +484,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
     }
   }
   if (halted) return;
-  __syncthreads();
-  int c0 = 0;
-  if (s > 0) {
-    A* all = reinterpret_cast<A*>(smem_raw);
-    for (int row = threadIdx.x; row < s; row += kBlock) {
-      A sum = all[row];
-      for (int q = 1; q < kWaves; ++q) sum += all[q * s + row];
-      part[(int64_t)row * nb + tile] = sum;
-    }
-    const double sx = block_sum(nx, (double*)red);
-    if (threadIdx.x == 0) put_re(part + (int64_t)s * nb + tile, sx);
-    c0 = s + 1;
-  }
-#pragma unroll
-  for (int q = 0; q < kMaxWindow; ++q) {
-    if (q < tw) {
-      const A v = block_sum(d[q], red);
-      if (threadIdx.x == 0) part[(int64_t)(c0 + q) * nb + tile] = v;
-    }
-  }
-  const double sw = block_sum(nw, (double*)red);
-  if (threadIdx.x == 0) put_re(part + (int64_t)(c0 + tw) * nb + tile, sw);
+  __shared__ A wsum[kWaves][kMaxWindow + 2];
+  store_step_partials(part, nb, tile, s, tw, reinterpret_cast<const A*>(smem_raw), nx, d, nw, wsum);
 }
 
 template <class T>
@@ -553,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
   for (int q = 0; q < TWM; ++q) nqv[q] = (q < tw && i0 + q != jprev) ? nu[i0 + q] : 1.0;
   if (halted) return;
   A sums[TWM + 1];
-  col_sums<A, TWM + 1>(part, nb1, s, tw + 1, sums, red);
+  col_sums<A, TWM + 1, true>(part, nb1, s, tw + 1, sums, red);
   const double nprev = sqrt(re(sums[0]));
   if (blockIdx.x == 0 && threadIdx.x == 0) nu[jprev] = nprev;
   A c[TWM];
