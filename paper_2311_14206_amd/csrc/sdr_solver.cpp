@@ -214,6 +214,7 @@ class Solver final : public SolverBase {
       HIPCHK(hipStreamCreateWithFlags(&streamB_, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&ev_copy_, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&ev_res_, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ev_bs_, hipEventDisableTiming));
       evs_.assign(nslot_ + 1, nullptr);
       for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       red3_ = dalloc<A>(4);
@@ -526,8 +527,13 @@ class Solver final : public SolverBase {
   // beyond 512 columns.
   void solve_coefficients(int j) {
     const int nls = khat_ + j;
-    if (launch_back_subst<A>(stream_, nls, khat_, R_, lmax_, z_, nu_, ycoef_)) {
+    // On stream B, where R and z were formed (the host has seen that stream
+    // finish the steps up to j): it runs beside stream A's remaining work,
+    // such as the recycled-basis product, and the check's product waits for it.
+    if (launch_back_subst<A>(streamB_, nls, khat_, R_, lmax_, z_, nu_, ycoef_)) {
       LAUNCHCHK();
+      HIPCHK(hipEventRecord(ev_bs_, streamB_));
+      HIPCHK(hipStreamWaitEvent(stream_, ev_bs_, 0));
       return;
     }
     // (own staging: the eigen-step's copies of R and nu may be in use on a worker thread)
@@ -1067,6 +1073,8 @@ class Solver final : public SolverBase {
     ev_copy_ = nullptr;
     if (ev_res_) (void)hipEventDestroy(ev_res_);
     ev_res_ = nullptr;
+    if (ev_bs_) (void)hipEventDestroy(ev_bs_);
+    ev_bs_ = nullptr;
     if (streamB_) (void)hipStreamDestroy(streamB_);
     streamB_ = nullptr;
   }
@@ -1099,6 +1107,7 @@ class Solver final : public SolverBase {
   } pend_;
   hipEvent_t ev_copy_ = nullptr;
   hipEvent_t ev_res_ = nullptr;   // after the residual norm's copy to the host
+  hipEvent_t ev_bs_ = nullptr;    // after the check's back substitution (stream B)
   A* last_sv_ = nullptr;  // SV(:, 0) of the last cycle (basis inspection)
   A *SU_ = nullptr, *SAU_ = nullptr, *Q_ = nullptr, *R_ = nullptr, *z_ = nullptr, *rho_ = nullptr;
   A *SB_ = nullptr, *SAW_ = nullptr, *H_ = nullptr;
