@@ -216,7 +216,10 @@ class Solver final : public SolverBase {
       HIPCHK(hipEventCreateWithFlags(&ev_res_, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&ev_bs_, hipEventDisableTiming));
       evs_.assign(nslot_ + 1, nullptr);
-      for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      // Step events order stream B's least squares after stream A's SpMV
+      // launches on the same device: a device-scope release suffices, and
+      // the default system-scope fence (an L2 writeback each time) is skipped.
+      for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence));
       red3_ = dalloc<A>(4);
       Sr_ = dalloc<A>(s);
       ycoef_ = dalloc<A>(lmax_);
@@ -229,8 +232,9 @@ class Solver final : public SolverBase {
       if (opt.kernel_timing) {
         for (auto& evp : ev_) {
           evp.assign(m + 2, std::array<hipEvent_t, 4>{});
+          // (timing only: no system-scope fence at each record)
           for (auto& a : evp)
-            for (auto& e : a) HIPCHK(hipEventCreate(&e));
+            for (auto& e : a) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         }
       }
       HIPCHK(hipHostMalloc((void**)&rec_host_, sizeof(StepRec) * (m + 2),
