@@ -151,7 +151,10 @@ def test_solve_cd2d_64_matches_oracle(dia):
     assert np.linalg.norm(r) <= p["tol"] * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("n,m,k,t,s", [(50, 30, 6, 2, 80), (37, 25, 5, 3, 64), (23, 40, 8, 1, 104)])
+# (40, 30, 36, 2, 160): k_eff above 32 takes the recycled-basis product in two
+# column launches
+@pytest.mark.parametrize("n,m,k,t,s", [(50, 30, 6, 2, 80), (37, 25, 5, 3, 64), (23, 40, 8, 1, 104),
+                                       (40, 30, 36, 2, 160)])
 def test_solve_ragged_sizes_match_oracle(n, m, k, t, s):
     A = cd2d_upwind(n)
     b = randn(A.n, n)
