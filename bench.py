@@ -12,7 +12,8 @@ in HBM before the timed region.  Prints one JSON line:
 * roofline: the SpMV + window-product + sketch kernel (the largest per-step kernel),
   algorithmic bytes per launch / its mean duration from HIP events recorded
   by the dispatches themselves on the library's stream inside the timed
-  region, on every 16th Arnoldi step (--timing-every);
+  region, on every 64th Arnoldi step (--timing-every; each timed step costs
+  its event records, so sampling is kept sparse);
 * roofline.traffic: HBM bytes per launch of that kernel from rocprofv3
   FETCH_SIZE and WRITE_SIZE counters, scaled by what the same counters read
   for a device copy of known size, taken from the committed summary
@@ -212,7 +213,7 @@ def main():
     ap.add_argument("--workload", default="cd2d_1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, default=0)
-    ap.add_argument("--timing-every", type=int, default=16,
+    ap.add_argument("--timing-every", type=int, default=64,
                     help="time the SpMV and update kernels of every n-th Arnoldi step with HIP "
                          "events (events between kernels cost launch gaps; 1 times all)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
