@@ -164,16 +164,18 @@ void launch_gemv_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, c
                        int64_t ldp, int jp, const typename traits<T>::acc* y,
                        typename traits<T>::acc* out);
 
-// rnew = r0 - A x (full precision values), partial ||rnew||^2 per block (nb = ceil(n/kRowsUpdate)).
+// rnew = r0 - A x (full precision values), nb = ceil(n/kRowsUpdate) blocks.
+// Partials per block: with sk.s > 0 the sketch of rnew in rows 0 .. s-1 and
+// ||rnew||^2 in row s (k_sketch_cols' layout for one column, the same sums
+// in the same order); with sk.s = 0 ||rnew||^2 in row 0.
 template <class A>
 void launch_spmv_residual(hipStream_t st, int n, const int* rp, const int* ci, const A* val,
-                          const A* x, const A* r0, A* rnew, A* part, int nb);
+                          const A* x, const A* r0, A* rnew, A* part, int nb, SketchSpec sk);
 
-// rnew = r0 - A x with A in diagonal storage (values in the accumulation
-// type), partials as launch_spmv_residual.
+// The same with A in diagonal storage (values in the accumulation type).
 template <class A>
 void launch_spmv_dia_residual(hipStream_t st, int n, DiaView<A> M, const A* x, const A* r0, A* rnew, A* part,
-                              int nb);
+                              int nb, SketchSpec sk);
 
 // Row width of G for launch_gemm_basis: kc rounded up to a multiple of 8.
 int gemm_basis_width(int kc);

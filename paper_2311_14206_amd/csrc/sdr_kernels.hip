@@ -1544,14 +1544,43 @@ void launch_gemv_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, c
                      U, ldu, ku, P, ldp, jp, y, out);
 }
 
+// End of a residual kernel: with the sketch (sk.s > 0), the per-wave bins
+// summed over the waves into partial rows 0 .. s-1 and ||rnew||^2 into row
+// s, the layout and order of k_sketch_cols for one column; without it,
+// ||rnew||^2 into row 0.
+template <class A>
+__device__ __forceinline__ void store_residual_partials(A* __restrict__ part, int s, double nrm,
+                                                        const A* bins_all, A* red) {
+  const double sum = block_sum(nrm, (double*)red);  // (its barriers also complete the bins)
+  for (int i = threadIdx.x; i < s; i += kBlock) {
+    A t = bins_all[i];
+    for (int q = 1; q < kWaves; ++q) t += bins_all[q * s + i];
+    part[(int64_t)i * gridDim.x + blockIdx.x] = t;
+  }
+  if (threadIdx.x == 0) {
+    A v = zero<A>();
+    *(double*)&v = sum;
+    part[(int64_t)s * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// rnew = r0 - A x over CSR (full-precision values), partial ||rnew||^2 per
+// block; with sk.s > 0 also the partial sketch of rnew, so that the next
+// cycle's S r0 needs no pass of its own.
 template <class A>
 __global__ __launch_bounds__(kBlock) void k_spmv_residual(int n, const int* __restrict__ rp,
                                                           const int* __restrict__ ci,
                                                           const A* __restrict__ val,
                                                           const A* __restrict__ x,
                                                           const A* __restrict__ r0,
-                                                          A* __restrict__ rnew, A* __restrict__ part) {
+                                                          A* __restrict__ rnew, A* __restrict__ part,
+                                                          SketchSpec sk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ A red[kWaves];
+  const int s = sk.s;
+  A* bins_all = reinterpret_cast<A*>(smem_raw);
+  A* bins = bins_all + (threadIdx.x >> 6) * s;
+  for (int i = threadIdx.x & 63; i < s; i += 64) bins[i] = zero<A>();
   double nrm = 0.0;
   const int b0 = blockIdx.x * kRowsUpdate;
   const int b1 = min(n, b0 + kRowsUpdate);
@@ -1561,24 +1590,26 @@ __global__ __launch_bounds__(kBlock) void k_spmv_residual(int n, const int* __re
     for (int e = rp[r]; e < e1; ++e) acc += val[e] * x[ci[e]];
     const A v = r0[r] - acc;
     rnew[r] = v;
+    if (s > 0) sketch_scatter(bins, r, v, sk);
     nrm += abs2(v);
   }
-  const double s = block_sum(nrm, (double*)red);
-  if (threadIdx.x == 0) {
-    A v = zero<A>();
-    *(double*)&v = s;
-    part[blockIdx.x] = v;
-  }
+  store_residual_partials(part, s, nrm, bins_all, red);
 }
 
 // rnew = r0 - A x over the diagonal storage (values in the accumulation
-// type), partial ||rnew||^2 per block exactly as k_spmv_residual.
+// type); partials as k_spmv_residual.
 template <class A, int ND>
 __global__ __launch_bounds__(kBlock) void k_spmv_dia_residual(int n, DiaView<A> M, const A* __restrict__ x,
                                                               const A* __restrict__ r0,
-                                                              A* __restrict__ rnew, A* __restrict__ part) {
+                                                              A* __restrict__ rnew, A* __restrict__ part,
+                                                              SketchSpec sk) {
   constexpr int KD = ND > 0 ? ND : kMaxDiag;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ A red[kWaves];
+  const int s = sk.s;
+  A* bins_all = reinterpret_cast<A*>(smem_raw);
+  A* bins = bins_all + (threadIdx.x >> 6) * s;
+  for (int i = threadIdx.x & 63; i < s; i += 64) bins[i] = zero<A>();
   const int nd = ND > 0 ? ND : M.ndiag;
   double nrm = 0.0;
   const int b0 = blockIdx.x * kRowsUpdate;
@@ -1604,20 +1635,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_residual(int n, DiaView<A> 
     }
     const A v = rr - acc;
     rnew[r] = v;
+    if (s > 0) sketch_scatter(bins, r, v, sk);
     nrm += abs2(v);
   }
-  const double sum = block_sum(nrm, (double*)red);
-  if (threadIdx.x == 0) {
-    A v = zero<A>();
-    *(double*)&v = sum;
-    part[blockIdx.x] = v;
-  }
+  store_residual_partials(part, s, nrm, bins_all, red);
 }
 
 template <class A>
 void launch_spmv_dia_residual(hipStream_t st, int n, DiaView<A> M, const A* x, const A* r0, A* rnew, A* part,
-                              int nb) {
-  void (*kern)(int, DiaView<A>, const A*, const A*, A*, A*);
+                              int nb, SketchSpec sk) {
+  void (*kern)(int, DiaView<A>, const A*, const A*, A*, A*, SketchSpec);
   switch (M.ndiag) {
     case 3: kern = k_spmv_dia_residual<A, 3>; break;
     case 5: kern = k_spmv_dia_residual<A, 5>; break;
@@ -1625,14 +1652,16 @@ void launch_spmv_dia_residual(hipStream_t st, int n, DiaView<A> M, const A* x, c
     case 9: kern = k_spmv_dia_residual<A, 9>; break;
     default: kern = k_spmv_dia_residual<A, 0>; break;
   }
-  hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, n, M, x, r0, rnew, part);
+  const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), lds, st, n, M, x, r0, rnew, part, sk);
 }
 
 template <class A>
 void launch_spmv_residual(hipStream_t st, int n, const int* rp, const int* ci, const A* val,
-                          const A* x, const A* r0, A* rnew, A* part, int nb) {
-  hipLaunchKernelGGL(k_spmv_residual<A>, dim3(nb), dim3(kBlock), 0, st, n, rp, ci, val, x, r0, rnew,
-                     part);
+                          const A* x, const A* r0, A* rnew, A* part, int nb, SketchSpec sk) {
+  const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
+  hipLaunchKernelGGL(k_spmv_residual<A>, dim3(nb), dim3(kBlock), lds, st, n, rp, ci, val, x, r0, rnew,
+                     part, sk);
 }
 
 // C = [U P] G, one row per thread with KM accumulators.  G is row major (row
@@ -2001,9 +2030,9 @@ SDR_INST_BASIS(cx<float>)
                                        int, double, A*, int64_t, const Ctrl*);                  \
   template void launch_backsolve<A>(hipStream_t, LsqState<A>, int, int, A*);                    \
   template void launch_spmv_dia_residual<A>(hipStream_t, int, DiaView<A>, const A*, const A*, A*, A*, \
-                                            int);                                                   \
+                                            int, SketchSpec);                                       \
   template void launch_spmv_residual<A>(hipStream_t, int, const int*, const int*, const A*,     \
-                                        const A*, const A*, A*, A*, int);                      \
+                                        const A*, const A*, A*, A*, int, SketchSpec);          \
   template bool launch_back_subst<A>(hipStream_t, int, int, const A*, int, const A*, const double*, A*); \
   template void launch_small_gemm<A>(hipStream_t, bool, int, int, int, const A*, int, const A*, \
                                      int, A*, int);                                             \

@@ -321,6 +321,7 @@ class Solver final : public SolverBase {
   // out[c] = S X(:, c) for c < nc (X with leading dimension n), norms^2 in nrm2.
   template <class X>
   void sketch_cols(const X* x, int nc, A* out, int ldo, double* nrm2) {
+    sr_of_ = nullptr;  // (the partials below replace a residual's sketch)
     const int maxcc = std::max(1, std::min(8, (int)(48 * 1024 / (kWaves * s_ * sizeof(A)))));
     for (int c0 = 0; c0 < nc; c0 += maxcc) {
       const int cc = std::min(maxcc, nc - c0);
@@ -350,19 +351,26 @@ class Solver final : public SolverBase {
   // r = b - A x and ||r||^2 to the host, queued on stream A; finish_residual()
   // waits for it.
   void enqueue_residual(const A* x, const A* b, A* r) {
+    // The residual kernel also sketches r (when its bins fit), so that a
+    // cycle starting from r reduces these partials instead of sketching r
+    // in a pass of its own.
+    const bool fuse = (size_t)kWaves * s_ * sizeof(A) <= 48 * 1024;
+    SketchSpec skr = sk_;
+    if (!fuse) skr.s = 0;
     if constexpr (std::is_same<T, A>::value) {
       // the diagonal storage holds the matrix in full precision: same sums
       if (dia()) {
         (void)basis_values();  // (packed if the values changed)
-        launch_spmv_dia_residual<A>(stream_, n_, dia_, x, b, r, psk_, nb2_);
+        launch_spmv_dia_residual<A>(stream_, n_, dia_, x, b, r, psk_, nb2_, skr);
       } else {
-        launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, psk_, nb2_);
+        launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, psk_, nb2_, skr);
       }
     } else {
-      launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, psk_, nb2_);
+      launch_spmv_residual<A>(stream_, n_, M_.rp, M_.ci, M_.val, x, b, r, psk_, nb2_, skr);
     }
     LAUNCHCHK();
-    launch_reduce_cols<A>(stream_, psk_, nb2_, 1, 0, 1.0, red3_, nullptr);
+    sr_of_ = fuse ? r : nullptr;
+    launch_reduce_cols<A>(stream_, psk_ + (size_t)skr.s * nb2_, nb2_, 1, 0, 1.0, red3_, nullptr);
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(hscal_, red3_, sizeof(A), hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipEventRecord(ev_res_, stream_));
@@ -813,7 +821,12 @@ class Solver final : public SolverBase {
     P_ = Pbuf_[cur_];
     SB_ = SBbuf_[cur_];
     SAW_ = SAWbuf_[cur_];
-    sketch_cols<A>(r0, 1, Sr_, s_, nullptr);
+    if (sr_of_ == r0) {  // sketched by the residual kernel that formed r0
+      launch_reduce_cols<A>(stream_, psk_, nb2_, s_, s_, 1.0 / std::sqrt((double)sk_.zeta), Sr_, nullptr);
+      LAUNCHCHK();
+    } else {
+      sketch_cols<A>(r0, 1, Sr_, s_, nullptr);
+    }
     if (rn >= 0.0)
       launch_cast_scale<T>(stream_, n_, r0, rn > 0.0 ? 1.0 / rn : 1.0, P_);
     else
@@ -1117,6 +1130,7 @@ class Solver final : public SolverBase {
   A *SB_ = nullptr, *SAW_ = nullptr, *H_ = nullptr;
   double *nu_ = nullptr, *sres_hist_ = nullptr;
   Ctrl *ctrl_ = nullptr, *ctrl_free_ = nullptr;
+  const A* sr_of_ = nullptr;  // the vector whose sketch partials psk_ holds (rows 0 .. s-1)
   A *part1_ = nullptr, *redb_ = nullptr, *psk_ = nullptr, *red2_ = nullptr, *red3_ = nullptr,
     *red0_ = nullptr;
   int nslot_ = 0;
