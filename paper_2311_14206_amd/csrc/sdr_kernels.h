@@ -116,9 +116,10 @@ template <class A>
 void launch_init_v0(hipStream_t st, const A* red, int s, A* svcol, double* nu);
 
 // out[c] = scale_c * sum_b part[c * nb + b] (fixed order); scale 1/sqrt(zeta) for c < nscaled.
+// With mirror (host-mapped coherent memory) the sums are also stored there.
 template <class A>
 void launch_reduce_cols(hipStream_t st, const A* part, int nb, int ncols, int nscaled,
-                        double scale, A* out, const Ctrl* ctrl);
+                        double scale, A* out, const Ctrl* ctrl, A* mirror = nullptr);
 
 // One Arnoldi step's small work: H column, SV column, SAV column, QR append,
 // projected residual and the halt decision.
@@ -201,15 +202,17 @@ void launch_small_gemm(hipStream_t st, bool conjtrans, int M, int N, int K, cons
                        const A* b, int ldb, A* c, int ldc);
 
 template <class A> void launch_axpy(hipStream_t st, int n, A alpha, const A* x, A* y);
-// dst (T) = scale * src (acc type), rounding to T
+// dst (T) = scale * src (acc type), rounding to T; with ctrl, the control
+// block is also reset for a new cycle (not halted, threshold thresh).
 template <class T>
 void launch_cast_scale(hipStream_t st, int n, const typename traits<T>::acc* src, double scale,
-                       T* dst);
+                       T* dst, Ctrl* ctrl = nullptr, double thresh = 0.0);
 // The same with scale = 1 / sqrt(Re nrm2[0]) read on the device (1 if that
 // is not positive): the norm of a reduction still on the device.
 template <class T>
 void launch_cast_rscale(hipStream_t st, int n, const typename traits<T>::acc* src,
-                        const typename traits<T>::acc* nrm2, T* dst);
+                        const typename traits<T>::acc* nrm2, T* dst, Ctrl* ctrl = nullptr,
+                        double thresh = 0.0);
 // dst (T) = src (T) cast from full precision A values (matrix copy)
 template <class T>
 void launch_narrow_values(hipStream_t st, int64_t n, const typename traits<T>::acc* src, T* dst);

@@ -600,19 +600,23 @@ void launch_update(hipStream_t st, int n, T* w, Window<T> win, int tw,
 template <class A>
 __global__ __launch_bounds__(kBlock) void k_reduce_cols(const A* __restrict__ part, int nb,
                                                         int nscaled, double scl, A* __restrict__ out,
-                                                        const Ctrl* __restrict__ ctrl) {
+                                                        const Ctrl* __restrict__ ctrl, A* mirror) {
   if (ctrl && ctrl->halt) return;
   __shared__ A red[kWaves];
   const int col = blockIdx.x;
   const A sum = col_sum(part, nb, col, red);
-  if (threadIdx.x == 0) out[col] = col < nscaled ? scale(sum, scl) : sum;
+  if (threadIdx.x == 0) {
+    const A v = col < nscaled ? scale(sum, scl) : sum;
+    out[col] = v;
+    if (mirror) mirror[col] = v;
+  }
 }
 
 template <class A>
 void launch_reduce_cols(hipStream_t st, const A* part, int nb, int ncols, int nscaled,
-                        double scl, A* out, const Ctrl* ctrl) {
+                        double scl, A* out, const Ctrl* ctrl, A* mirror) {
   hipLaunchKernelGGL(k_reduce_cols<A>, dim3(ncols), dim3(kBlock), 0, st, part, nb, nscaled, scl, out,
-                     ctrl);
+                     ctrl, mirror);
 }
 
 // out[c] for c < ca from partA (c < nscaled scaled by scl), then cb columns of partB.
@@ -1895,21 +1899,34 @@ template <class A> void launch_axpy(hipStream_t st, int n, A alpha, const A* x, 
   hipLaunchKernelGGL(k_axpy<A>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, alpha, x, y);
 }
 
+// A cycle's control block, cleared by the launch that forms its first basis
+// vector (one launch fewer at each cycle start).
+__device__ __forceinline__ void set_ctrl_fields(Ctrl* c, double thresh) {
+  c->halt = 0;
+  c->halt_j = 0;
+  c->flags = 0;
+  c->thresh = thresh;
+}
+
 template <class T>
 __global__ void k_cast_scale(int n, const typename traits<T>::acc* __restrict__ src, double s,
-                             T* __restrict__ dst) {
+                             T* __restrict__ dst, Ctrl* ctrl, double thresh) {
+  if (ctrl && blockIdx.x == 0 && threadIdx.x == 0) set_ctrl_fields(ctrl, thresh);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     dst[i] = narrow<T>(scale(src[i], s));
 }
 template <class T>
-void launch_cast_scale(hipStream_t st, int n, const typename traits<T>::acc* src, double s, T* dst) {
+void launch_cast_scale(hipStream_t st, int n, const typename traits<T>::acc* src, double s, T* dst,
+                       Ctrl* ctrl, double thresh) {
   hipLaunchKernelGGL(k_cast_scale<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, src,
-                     s, dst);
+                     s, dst, ctrl, thresh);
 }
 
 template <class T>
 __global__ void k_cast_rscale(int n, const typename traits<T>::acc* __restrict__ src,
-                              const typename traits<T>::acc* __restrict__ nrm2, T* __restrict__ dst) {
+                              const typename traits<T>::acc* __restrict__ nrm2, T* __restrict__ dst,
+                              Ctrl* ctrl, double thresh) {
+  if (ctrl && blockIdx.x == 0 && threadIdx.x == 0) set_ctrl_fields(ctrl, thresh);
   const double q = re(nrm2[0]);
   const double sc = q > 0.0 ? 1.0 / sqrt(q) : 1.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -1917,9 +1934,9 @@ __global__ void k_cast_rscale(int n, const typename traits<T>::acc* __restrict__
 }
 template <class T>
 void launch_cast_rscale(hipStream_t st, int n, const typename traits<T>::acc* src,
-                        const typename traits<T>::acc* nrm2, T* dst) {
+                        const typename traits<T>::acc* nrm2, T* dst, Ctrl* ctrl, double thresh) {
   hipLaunchKernelGGL(k_cast_rscale<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, src, nrm2,
-                     dst);
+                     dst, ctrl, thresh);
 }
 
 template <class T>
@@ -2005,8 +2022,9 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
                                      int, const traits<T>::acc*, traits<T>::acc*);                \
   template void launch_gemm_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
                                      int, const traits<T>::acc*, int, T*, int64_t);               \
-  template void launch_cast_scale<T>(hipStream_t, int, const traits<T>::acc*, double, T*);        \
-  template void launch_cast_rscale<T>(hipStream_t, int, const traits<T>::acc*, const traits<T>::acc*, T*); \
+  template void launch_cast_scale<T>(hipStream_t, int, const traits<T>::acc*, double, T*, Ctrl*, double); \
+  template void launch_cast_rscale<T>(hipStream_t, int, const traits<T>::acc*, const traits<T>::acc*, T*, \
+                                       Ctrl*, double);                                             \
   template void launch_widen_scale<T>(hipStream_t, int, const T*, double, traits<T>::acc*);       \
   template void launch_narrow_values<T>(hipStream_t, int64_t, const traits<T>::acc*, T*);
 
@@ -2017,7 +2035,7 @@ SDR_INST_BASIS(cx<float>)
 
 #define SDR_INST_ACC(A)                                                                         \
   template void launch_reduce_cols<A>(hipStream_t, const A*, int, int, int, double, A*,        \
-                                      const Ctrl*);                                             \
+                                      const Ctrl*, A*);                                         \
   template void launch_lsq_step<A>(hipStream_t, LsqState<A>, int, int, int, int, int, const A*, \
                                    double, double);                                             \
   template void launch_reduce2<A>(hipStream_t, const A*, int, int, int, double, const A*, int,  \

@@ -252,6 +252,8 @@ class Solver final : public SolverBase {
       HIPCHK(hipHostMalloc((void**)&hG_, sizeof(A) * (size_t)lmax_ * (2 * kmax_ + gemm_basis_width(kmax_)),
                            hipHostMallocDefault));
       HIPCHK(hipHostMalloc((void**)&hscal_, sizeof(A) * 8, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&hres_, sizeof(A) * 2, hipHostMallocMapped | hipHostMallocCoherent));
+      HIPCHK(hipHostGetDevicePointer((void**)&hres_dev_, hres_, 0));
       HIPCHK(hipMemsetAsync(ctrl_free_, 0, sizeof(Ctrl), stream_));
       HIPCHK(hipMemsetAsync(nu_, 0, sizeof(double) * (m + 2), stream_));
       HIPCHK(hipMemsetAsync(H_, 0, sizeof(A) * (m + 1) * m, stream_));
@@ -370,14 +372,15 @@ class Solver final : public SolverBase {
     }
     LAUNCHCHK();
     sr_of_ = fuse ? r : nullptr;
-    launch_reduce_cols<A>(stream_, psk_ + (size_t)skr.s * nb2_, nb2_, 1, 0, 1.0, red3_, nullptr);
+    // ||r||^2 to red3_ (the next cycle's start scales by it on the device)
+    // and straight into host-mapped memory for the host
+    launch_reduce_cols<A>(stream_, psk_ + (size_t)skr.s * nb2_, nb2_, 1, 0, 1.0, red3_, nullptr, hres_dev_);
     LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(hscal_, red3_, sizeof(A), hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipEventRecord(ev_res_, stream_));
   }
   double finish_residual() {
     HIPCHK(hipEventSynchronize(ev_res_));  // (not the stream: later work may be queued)
-    return std::sqrt(to_double_re(hscal_[0]));
+    return std::sqrt(to_double_re(hres_[0]));
   }
   double residual(const A* x, const A* b, A* r) {
     enqueue_residual(x, b, r);
@@ -827,13 +830,13 @@ class Solver final : public SolverBase {
     } else {
       sketch_cols<A>(r0, 1, Sr_, s_, nullptr);
     }
+    // p_0, and the control block reset for the cycle (same launch)
     if (rn >= 0.0)
-      launch_cast_scale<T>(stream_, n_, r0, rn > 0.0 ? 1.0 / rn : 1.0, P_);
+      launch_cast_scale<T>(stream_, n_, r0, rn > 0.0 ? 1.0 / rn : 1.0, P_, ctrl_, thresh);
     else
-      launch_cast_rscale<T>(stream_, n_, r0, red3_, P_);
+      launch_cast_rscale<T>(stream_, n_, r0, red3_, P_, ctrl_, thresh);
     last_sv_ = SB_ + (size_t)kmax_ * s_;
     __atomic_store_n(&halt_host_->seq, -1, __ATOMIC_RELEASE);
-    launch_set_ctrl(stream_, ctrl_, 0, thresh);
     LAUNCHCHK();
     enqueue_step_a(1, vals, true);
     HIPCHK(hipStreamWaitEvent(streamB_, evs_[1 % nslot_], 0));
@@ -1073,9 +1076,10 @@ class Solver final : public SolverBase {
     halt_host_ = nullptr;
     for (void* p : {(void*)hR_, (void*)hC_, (void*)hz_, (void*)hy_, (void*)hnu_, (void*)hG_,
                     (void*)hRc_, (void*)hnuc_,
-                    (void*)hscal_})
+                    (void*)hscal_, (void*)hres_})
       if (p) (void)hipHostFree(p);
-    hR_ = hC_ = hz_ = hy_ = hG_ = hscal_ = hRc_ = nullptr;
+    hR_ = hC_ = hz_ = hy_ = hG_ = hscal_ = hRc_ = hres_ = nullptr;
+    hres_dev_ = nullptr;
     hnu_ = hnuc_ = nullptr;
     for (auto& evp : ev_) {
       for (auto& a : evp)
@@ -1142,6 +1146,8 @@ class Solver final : public SolverBase {
   StepRec *rec_host_ = nullptr, *rec_dev_ = nullptr;
   HaltRec *halt_host_ = nullptr, *halt_dev_ = nullptr;
   // pinned host staging of the small dense data
+  A* hres_ = nullptr;      // host-mapped coherent: the last residual's ||r||^2
+  A* hres_dev_ = nullptr;  // its device address
   A *hR_ = nullptr, *hC_ = nullptr, *hz_ = nullptr, *hy_ = nullptr, *hG_ = nullptr, *hscal_ = nullptr,
     *hRc_ = nullptr;
   double *hnu_ = nullptr, *hnuc_ = nullptr;
