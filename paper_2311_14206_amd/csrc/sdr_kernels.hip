@@ -1737,6 +1737,9 @@ void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, c
     else if (km == 16)
       hipLaunchKernelGGL((k_gemm_basis<T, 16>), dim3(nb), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp,
                          jp, Gc, ldg, cc, Cc, ldc);
+    else if (km == 24 && cc <= 20)  // (k = 20: no multiply-adds on padding columns)
+      hipLaunchKernelGGL((k_gemm_basis<T, 20>), dim3(nb), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp,
+                         jp, Gc, ldg, cc, Cc, ldc);
     else if (km == 24)
       hipLaunchKernelGGL((k_gemm_basis<T, 24>), dim3(nb), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp,
                          jp, Gc, ldg, cc, Cc, ldc);
