@@ -174,52 +174,6 @@ __device__ __forceinline__ A col_sum(const A* __restrict__ part, int nb, int col
   return block_sum(sum, red);
 }
 
-// Columns c0 .. c0 + nc - 1 (nc <= NMAX) of a partial array at once, each in
-// exactly col_sum's order (so the same bits), with the loads of all columns
-// in flight together and one barrier round for all of them.
-template <class A, int NMAX, bool FRESH = false>
-__device__ __forceinline__ void col_sums(const A* __restrict__ part, int nb, int c0, int nc, A (&out)[NMAX],
-                                         A* red /* NMAX * kWaves */) {
-  A sum[NMAX];
-#pragma unroll
-  for (int c = 0; c < NMAX; ++c) sum[c] = zero<A>();
-  for (int i0 = threadIdx.x; i0 < nb; i0 += 4 * kBlock) {
-    A v[4][NMAX];  // columns past nc re-read column nc - 1 and are not added
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = min(i0 + u * kBlock, nb - 1);
-#pragma unroll
-      for (int c = 0; c < NMAX; ++c) v[u][c] = part[(int64_t)(c0 + min(c, nc - 1)) * nb + i];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (i0 + u * kBlock < nb) {
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c)
-          if (c < nc) sum[c] += v[u][c];
-      }
-    }
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < NMAX; ++c) sum[c] = wave_sum(sum[c]);
-  // (FRESH: red is used once in the kernel, so the barriers that order it
-  // against earlier and later uses are not needed)
-  if (!FRESH) __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) red[c * kWaves + wv] = sum[c];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < NMAX; ++c) {
-    A t = red[c * kWaves];
-    for (int i = 1; i < kWaves; ++i) t += red[c * kWaves + i];
-    out[c] = t;
-  }
-  if (!FRESH) __syncthreads();
-}
-
 __device__ __forceinline__ void put_re(double* p, double v) { *p = v; }
 __device__ __forceinline__ void put_re(cx<double>* p, double v) { *p = cx<double>{v, 0.0}; }
 
@@ -534,11 +488,21 @@ __global__ __launch_bounds__(kBlock) void k_update(
     int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ part,
     int nb1, int s, double* __restrict__ nu, int i0, int jprev, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
+  constexpr int NC = TWM + 1;
   const int halted = ctrl->halt;  // tested once the loads below are out
-  __shared__ A red[(TWM + 1) * kWaves];
-  // The stream's loads go out first (clamped rows, unused past n), with the
-  // norms of the older window vectors, and are in flight while the block
-  // reduces the partials: no dependent global load follows the reduction.
+  __shared__ A red[NC * kWaves];
+  // This step's partial sums (columns s .. s + tw, L2-resident) are loaded
+  // first: their values return ahead of the stream loads issued after them,
+  // so the block's reduction runs while the stream is still in flight.
+  const A* pp = part + (int64_t)s * nb1;
+  const int nc = tw + 1;
+  A pv0[4][NC];  // columns past nc re-read column nc - 1 and are not added
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = min((int)threadIdx.x + u * kBlock, nb1 - 1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) pv0[u][c] = pp[(int64_t)min(c, nc - 1) * nb1 + i];
+  }
   const int base = xcd_tile(blockIdx.x, gridDim.x) * (kBlock * kUpdateRows) + (int)threadIdx.x;
   T wv[kUpdateRows], pv[kUpdateRows][TWM];
 #pragma unroll
@@ -553,8 +517,47 @@ __global__ __launch_bounds__(kBlock) void k_update(
 #pragma unroll
   for (int q = 0; q < TWM; ++q) nqv[q] = (q < tw && i0 + q != jprev) ? nu[i0 + q] : 1.0;
   if (halted) return;
-  A sums[TWM + 1];
-  col_sums<A, TWM + 1, true>(part, nb1, s, tw + 1, sums, red);
+  // column sums in the order of col_sum: thread-strided rounds of four,
+  // then the waves in order
+  A sums[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) sums[c] = zero<A>();
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if ((int)threadIdx.x + u * kBlock < nb1)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c < nc) sums[c] += pv0[u][c];
+  for (int j0 = (int)threadIdx.x + 4 * kBlock; j0 < nb1; j0 += 4 * kBlock) {
+    A v[4][NC];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = min(j0 + u * kBlock, nb1 - 1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[u][c] = pp[(int64_t)min(c, nc - 1) * nb1 + i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j0 + u * kBlock < nb1)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (c < nc) sums[c] += v[u][c];
+  }
+  {
+    const int lane = threadIdx.x & 63, wv_ = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sums[c] = wave_sum(sums[c]);
+    if (lane == 0)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) red[c * kWaves + wv_] = sums[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      A t = red[c * kWaves];
+      for (int i = 1; i < kWaves; ++i) t += red[c * kWaves + i];
+      sums[c] = t;
+    }
+  }
   const double nprev = sqrt(re(sums[0]));
   if (blockIdx.x == 0 && threadIdx.x == 0) nu[jprev] = nprev;
   A c[TWM];
