@@ -431,7 +431,7 @@ class Solver final : public SolverBase {
     Window<T> win{};
     for (int q = 0; q < tw; ++q) win.p[q] = P_ + (size_t)(i0 + q) * n_;
     T* w = P_ + (size_t)j * n_;
-    const bool tm = timed(j);
+    const bool tm = timed(j, evp_);
     hipEvent_t* te = tm ? ev_[evp_][j].data() : nullptr;
     if (dia())
       launch_spmv_dia_sketch<T>(stream_, n_, dia_, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
@@ -446,7 +446,12 @@ class Solver final : public SolverBase {
     LAUNCHCHK();
   }
 
-  bool timed(int j) const { return opt_.kernel_timing > 0 && j % opt_.kernel_timing == 0; }
+  // Step j of a cycle of parity par is timed when (j + offset) is a multiple
+  // of kernel_timing; the offset moves by 13 each cycle, so the samples
+  // cover every step position rather than always the same one.
+  bool timed(int j, int par) const {
+    return opt_.kernel_timing > 0 && (j + ev_ofs_[par]) % opt_.kernel_timing == 0;
+  }
 
   // Kernel times of a finished cycle, read while the GPU runs the next one
   // (the events alternate between two sets by cycle, so a set is read
@@ -455,7 +460,7 @@ class Solver final : public SolverBase {
     if (ev_pend_j_ <= 0) return;
     auto& evs = ev_[ev_pend_p_];
     for (int j = 1; j <= ev_pend_j_; ++j) {
-      if (!timed(j)) continue;
+      if (!timed(j, ev_pend_p_)) continue;
       float a = 0.f, b2 = 0.f, c = 0.f;
       HIPCHK(hipEventElapsedTime(&a, evs[j][0], evs[j][1]));
       HIPCHK(hipEventElapsedTime(&b2, evs[j][2], evs[j][3]));
@@ -821,6 +826,10 @@ class Solver final : public SolverBase {
   void start_cycle(const A* r0, double rn, double thresh, const T* vals) {
     evp_ ^= 1;
     cycle_par_ = evp_;
+    if (opt_.kernel_timing > 0) {
+      ev_ofs_[evp_] = ev_ofs_next_;
+      ev_ofs_next_ = (ev_ofs_next_ + 13) % opt_.kernel_timing;
+    }
     P_ = Pbuf_[cur_];
     SB_ = SBbuf_[cur_];
     SAW_ = SAWbuf_[cur_];
@@ -1159,6 +1168,7 @@ class Solver final : public SolverBase {
   EigResult eig_res_;
   std::vector<std::array<hipEvent_t, 4>> ev_[2];  // kernel timing events, by cycle parity
   int evp_ = 0, ev_pend_p_ = 0, ev_pend_j_ = 0, cycle_par_ = 0;
+  int ev_ofs_[2] = {0, 0}, ev_ofs_next_ = 0;  // timed-step offsets by cycle parity
   double kt_ms_[3] = {0, 0, 0};
   int64_t kt_n_[3] = {0, 0, 0};
   int64_t kt_bytes_tw_[kMaxWindow + 1] = {0, 0, 0, 0, 0};
