@@ -819,10 +819,12 @@ class Solver final : public SolverBase {
     return status;
   }
 
-  // Cycle start on stream A: S r0, p_0 = r0 / ||r0|| into the P buffer of
-  // cur_, the control block and step 1, whose SpMV sketches p_0; stream B
-  // follows with SV(:, 0) and nu_0.  ||r0|| comes from the host (rn >= 0) or
-  // stays on the device (rn < 0: red3_ holds ||r0||^2 from the last check).
+  // Cycle start on stream A: S r0 (from the partials of the residual kernel
+  // that formed r0, when it did), p_0 = r0 / ||r0|| into the P buffer of cur_
+  // with the control block reset in the same launch, and step 1, whose SpMV
+  // sketches p_0; stream B follows with SV(:, 0) and nu_0.  ||r0|| comes from
+  // the host (rn >= 0) or stays on the device (rn < 0: red3_ holds ||r0||^2
+  // from the last check).
   void start_cycle(const A* r0, double rn, double thresh, const T* vals) {
     evp_ ^= 1;
     cycle_par_ = evp_;
@@ -1136,7 +1138,7 @@ class Solver final : public SolverBase {
     A* SAW = nullptr;
   } pend_;
   hipEvent_t ev_copy_ = nullptr;
-  hipEvent_t ev_res_ = nullptr;   // after the residual norm's copy to the host
+  hipEvent_t ev_res_ = nullptr;   // after the residual norm's reduction into host-mapped memory
   hipEvent_t ev_bs_ = nullptr;    // after the check's back substitution (stream B)
   A* last_sv_ = nullptr;  // SV(:, 0) of the last cycle (basis inspection)
   A *SU_ = nullptr, *SAU_ = nullptr, *Q_ = nullptr, *R_ = nullptr, *z_ = nullptr, *rho_ = nullptr;
