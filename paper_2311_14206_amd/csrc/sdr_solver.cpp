@@ -419,9 +419,14 @@ class Solver final : public SolverBase {
     A* p1 = part1_ + slot1_ * sl;
     const T* x = P_ + (size_t)(j - 1) * n_;
     if (j > m_) {
+      // sketch of p_m only (the diagonal-storage kernel's sketch pass needs far
+      // less LDS than the CSR kernel's staging, so more of its blocks run at once)
       Window<T> none{};
-      launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, x, nullptr, none, 0, sk_, false, p1, nb1_,
-                            ctrl_);
+      if (dia())
+        launch_spmv_dia_sketch<T>(stream_, n_, dia_, x, nullptr, none, 0, sk_, false, p1, nb1_, ctrl_);
+      else
+        launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, x, nullptr, none, 0, sk_, false, p1, nb1_,
+                              ctrl_);
       LAUNCHCHK();
       HIPCHK(hipEventRecord(evs_[sl], stream_));
       return;
