@@ -124,7 +124,8 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *                    diagonals (padding at most nnz/4) is stored by diagonals
  *                    for the basis SpMV; 0: always CSR
  *   "kernel_timing"  n > 0: HIP events around the SpMV and update kernels of
- *                    every n-th Arnoldi step (sdr_kernel_times); default 0
+ *                    one Arnoldi step in n, at positions that move by 13 from
+ *                    cycle to cycle (sdr_kernel_times); default 0
  * Returns 0 or SDR_EINVAL.
  */
 int sdr_set_option(sdr_handle* h, const char* key, double value);
@@ -200,7 +201,7 @@ int sdr_reset(sdr_handle* h);
 
 /*
  * Per-step kernel timings gathered with HIP events on the handle's stream
- * when the option "kernel_timing" is n > 0 (every n-th step), accumulated since the last call and
+ * when the option "kernel_timing" is n > 0 (one step in n), accumulated since the last call and
  * then cleared.  ms[0]: SpMV + window products + sketch kernel, ms[1]:
  * orthogonalisation update kernel, ms[2]: both kernels of the step, from the
  * start of the first to the end of the second (the least squares runs on a
