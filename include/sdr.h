@@ -123,6 +123,20 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *   "dia"            1 (default): a pattern whose entries lie on at most 16
  *                    diagonals (padding at most nnz/4) is stored by diagonals
  *                    for the basis SpMV; 0: always CSR
+ *   "precond"        1: right Jacobi preconditioning of the forward solve
+ *                    (Section 6 solves its Stokes systems preconditioned; a
+ *                    diagonal right preconditioner is the cheapest such
+ *                    case): A x = b is solved as (A D^-1) u = b, x = D^-1 u,
+ *                    D = diag(A).  D^-1 is folded into the stored values
+ *                    (A D^-1 on the same pattern, refreshed by
+ *                    sdr_update_matrix), so an Arnoldi step costs the same.
+ *                    Every diagonal entry must be stored and nonzero, else
+ *                    the solve or update returns SDR_EINVAL.  Residuals,
+ *                    tolerances and stats refer to A x = b (the same vector
+ *                    b - A D^-1 u); the recycle space, basis and sketches
+ *                    (sdr_get_recycle, sdr_get_basis) belong to A D^-1.
+ *                    sdr_spmv and the adjoint solve use A unpreconditioned.
+ *                    Default 0, set before the first solve.
  *   "kernel_timing"  n > 0: HIP events around the SpMV and update kernels of
  *                    one Arnoldi step in n, at positions that move by 13 from
  *                    cycle to cycle (sdr_kernel_times); default 0

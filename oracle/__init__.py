@@ -10,7 +10,8 @@ Contents
                 an explicit scipy matrix built from a published counter-based
                 generator (SplitMix64 output mixer).
 ``gmres_sdr``   GMRES-SDR, one cycle per Algorithm 1 and the restart /
-                sequence logic of Sections 3.2-3.6, in float64 / complex128.
+                sequence logic of Sections 3.2-3.6, in float64 / complex128,
+                and its right Jacobi preconditioned form.
 """
 
 from .sketch import sketch_operator, sketch_pattern, splitmix64_mix  # noqa: F401
@@ -19,5 +20,6 @@ from .gmres_sdr import (  # noqa: F401
     SolveResult,
     sdr_cycle,
     sdr_solve,
+    sdr_solve_right_jacobi,
     harmonic_ritz_update,
 )

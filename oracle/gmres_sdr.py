@@ -32,6 +32,10 @@ GPU library takes the same ones):
 * Sequences (Section 3.6): with the same A the recycle triple is passed on;
   after a change of A the exact variant recomputes SAU = S (A U) (k extra
   products and sketches), the inexact variant keeps the stale SAU.
+* Right preconditioning (Section 6 solves preconditioned systems; the
+  Jacobi case): A x = b is solved as (A D^-1) u = b with D = diag(A) and
+  x = D^-1 u, so the residual b - (A D^-1) u is that of A x = b and the
+  recycle triple belongs to A D^-1.  ``sdr_solve_right_jacobi``.
 """
 
 from __future__ import annotations
@@ -333,4 +337,27 @@ def sdr_solve(A, b, *, x0=None, m: int, k: int, t: int, s: int, zeta: int = 8,
     out.sketches = cnt.get("sketches", 0)
     out.res_checks = cnt.get("res_checks", 0)
     out.recycle = recycle
+    return out
+
+
+def sdr_solve_right_jacobi(A, b, *, x0=None, **kw) -> SolveResult:
+    """GMRES-SDR on the right Jacobi preconditioned system (A D^-1) u = b.
+
+    D = diag(A) (every diagonal entry must be nonzero); the initial guess is
+    u0 = D x0 and the returned ``x`` is D^-1 u.  Keyword arguments as for
+    ``sdr_solve``, with ``recycle`` / ``new_matrix`` referring to A D^-1.
+    """
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix(A)
+    d = A.diagonal()
+    if np.any(d == 0):
+        raise ValueError("Jacobi preconditioning needs a nonzero diagonal")
+    dinv = 1.0 / d
+    # A D^-1 on A's own pattern and entry order: stored entry (i, j) times 1/d_j
+    Ahat = A.copy()
+    Ahat.data = A.data * dinv[A.indices]
+    u0 = None if x0 is None else d * np.asarray(x0)
+    out = sdr_solve(Ahat, b, x0=u0, **kw)
+    out.x = out.x / d
     return out

@@ -202,6 +202,15 @@ void launch_small_gemm(hipStream_t st, bool conjtrans, int M, int N, int K, cons
                        const A* b, int ldb, A* c, int ldc);
 
 template <class A> void launch_axpy(hipStream_t st, int n, A alpha, const A* x, A* y);
+// Right Jacobi preconditioning A D^-1, D = diag(A): d[r] = A(r, r) (zero if
+// row r stores no diagonal entry, which sets *flag to 1) and
+// scaled[e] = val[e] * (1 / d[col[e]]).
+template <class A>
+void launch_jacobi(hipStream_t st, int n, int64_t nnz, const int* rp, const int* ci, const A* val, A* d,
+                   A* scaled, int* flag);
+// x <- x * d (divide false) or x * (1 / d) (divide true), elementwise.
+template <class A>
+void launch_scale_by_diag(hipStream_t st, int n, const A* d, A* x, bool divide);
 // dst (T) = scale * src (acc type), rounding to T; with ctrl, the control
 // block is also reset for a new cycle (not halted, threshold thresh).
 template <class T>

@@ -2011,6 +2011,57 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
   hipLaunchKernelGGL(k_set_ctrl, dim3(1), dim3(64), 0, st, c, halt, thresh);
 }
 
+// ------------------------------------------- right Jacobi preconditioning ---
+// A D^-1 with D = diag(A): d from each row's stored diagonal entry (zero if
+// the row stores none, which sets *flag), the column-scaled values
+// a_ij * (1 / d_j), and x <- x * d or x * (1 / d) for the change of variable
+// x = D^-1 u.
+__device__ __forceinline__ double recip(double d) { return 1.0 / d; }
+__device__ __forceinline__ cx<double> recip(cx<double> d) { return scale(conj(d), 1.0 / abs2(d)); }
+
+template <class A>
+__global__ void k_jacobi_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const A* __restrict__ val, A* __restrict__ d, int* __restrict__ flag) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    A v = zero<A>();
+    const int e1 = rp[r + 1];
+    for (int e = rp[r]; e < e1; ++e)
+      if (ci[e] == r) v = val[e];
+    d[r] = v;
+    if (abs2(v) == 0.0) flag[0] = 1;
+  }
+}
+
+template <class A>
+__global__ void k_scale_cols(int64_t nnz, const int* __restrict__ ci, const A* __restrict__ val,
+                             const A* __restrict__ d, A* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = val[e] * recip(d[ci[e]]);
+}
+
+template <class A>
+void launch_jacobi(hipStream_t st, int n, int64_t nnz, const int* rp, const int* ci, const A* val, A* d,
+                   A* scaled, int* flag) {
+  hipLaunchKernelGGL(k_jacobi_diag<A>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, rp, ci, val, d,
+                     flag);
+  if (nnz > 0) {
+    const int64_t nb = std::min<int64_t>((nnz + kBlock - 1) / kBlock, 1 << 20);
+    hipLaunchKernelGGL(k_scale_cols<A>, dim3((unsigned)nb), dim3(kBlock), 0, st, nnz, ci, val, d, scaled);
+  }
+}
+
+template <class A>
+__global__ void k_scale_by_diag(int n, const A* __restrict__ d, A* __restrict__ x, int divide) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    x[i] = x[i] * (divide ? recip(d[i]) : d[i]);
+}
+
+template <class A>
+void launch_scale_by_diag(hipStream_t st, int n, const A* d, A* x, bool divide) {
+  hipLaunchKernelGGL(k_scale_by_diag<A>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, d, x,
+                     divide ? 1 : 0);
+}
+
 // ---------------------------------------------------- instantiations ---
 #define SDR_INST_BASIS(T)                                                                        \
   template void launch_spmv_sketch<T>(hipStream_t, int, const int*, const int*, const T*,          \
@@ -2061,6 +2112,9 @@ SDR_INST_BASIS(cx<float>)
   template void launch_small_gemm<A>(hipStream_t, bool, int, int, int, const A*, int, const A*, \
                                      int, A*, int);                                             \
   template void launch_axpy<A>(hipStream_t, int, A, const A*, A*);                              \
+  template void launch_jacobi<A>(hipStream_t, int, int64_t, const int*, const int*, const A*, A*, A*, \
+                                 int*);                                                         \
+  template void launch_scale_by_diag<A>(hipStream_t, int, const A*, A*, bool);                 \
   template void launch_gather_conj<A>(hipStream_t, int64_t, const A*, const int*, A*);          \
   template void launch_grad_values<A>(hipStream_t, int, const int*, const int*, const A*,       \
                                       const A*, A*);

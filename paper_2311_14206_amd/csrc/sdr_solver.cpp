@@ -90,6 +90,7 @@ struct Options {
   int lsq_chunk = 8;      // steps per least-squares launch
   int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
   int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
+  int precond = 0;        // 0: none; 1: right Jacobi, the forward solve runs on A D^-1
 };
 
 // Diagonal layout of a CSR pattern: the distinct offsets column - row (at
@@ -1228,6 +1229,11 @@ struct sdr_handle {
   int* ciT = nullptr;
   int* perm = nullptr;
   void* valsT = nullptr;
+  // right Jacobi preconditioning (option "precond"): d = diag(A) and the
+  // values of A D^-1 on the same pattern, which the forward solver runs on
+  void* d_pc = nullptr;
+  void* vals_pc = nullptr;
+  int* pc_flag = nullptr;
   bool adj_ready = false;
   uint64_t pattern_hash = 0;
   hipStream_t own = nullptr;
@@ -1255,7 +1261,7 @@ uint64_t hash_pattern(const std::vector<int>& rp, const std::vector<int>& ci) {
 std::unique_ptr<SolverBase> make_solver(sdr_handle* h, bool adjoint) {
   const int* rp = adjoint ? h->rpT : h->rp;
   const int* ci = adjoint ? h->ciT : h->ci;
-  const void* v = adjoint ? h->valsT : h->vals;
+  const void* v = adjoint ? h->valsT : h->opt.precond ? h->vals_pc : h->vals;
   if (!h->cpx) {
     MatView<double> mv{h->n, h->nnz, rp, ci, static_cast<const double*>(v)};
     if (h->opt.precision == 1)
@@ -1268,12 +1274,54 @@ std::unique_ptr<SolverBase> make_solver(sdr_handle* h, bool adjoint) {
   return std::unique_ptr<SolverBase>(new Solver<cx<double>>(mv, h->m, h->k, h->t, h->s, h->seed, h->opt, h->stream));
 }
 
+// Right Jacobi preconditioning, A x = b as (A D^-1) u = b with x = D^-1 u and
+// D = diag(A): refresh d and the values of A D^-1 from the handle's matrix.
+// Throws SDR_EINVAL if a diagonal entry is zero or not stored.
+void refresh_precond(sdr_handle* h) {
+  if (h->opt.precond == 0) return;
+  if (!h->vals_pc) {
+    h->d_pc = dalloc<unsigned char>(h->elem() * h->n);
+    h->vals_pc = dalloc<unsigned char>(h->elem() * std::max<int64_t>(h->nnz, 1));
+    h->pc_flag = dalloc<int>(1);
+  }
+  HIPCHK(hipMemsetAsync(h->pc_flag, 0, sizeof(int), h->stream));
+  if (h->cpx)
+    launch_jacobi<cx<double>>(h->stream, h->n, h->nnz, h->rp, h->ci, static_cast<const cx<double>*>(h->vals),
+                              static_cast<cx<double>*>(h->d_pc), static_cast<cx<double>*>(h->vals_pc),
+                              h->pc_flag);
+  else
+    launch_jacobi<double>(h->stream, h->n, h->nnz, h->rp, h->ci, static_cast<const double*>(h->vals),
+                          static_cast<double*>(h->d_pc), static_cast<double*>(h->vals_pc), h->pc_flag);
+  HIPCHK(hipGetLastError());
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, h->pc_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (flag) {
+    set_err("Jacobi preconditioning needs every diagonal entry of A stored and nonzero");
+    throw HipError{SDR_EINVAL};
+  }
+}
+
+// x <- D x (to_u) or D^-1 x: the change of variable of right Jacobi preconditioning.
+void precond_scale(sdr_handle* h, void* x, bool to_u) {
+  if (h->cpx)
+    launch_scale_by_diag<cx<double>>(h->stream, h->n, static_cast<const cx<double>*>(h->d_pc),
+                                     static_cast<cx<double>*>(x), !to_u);
+  else
+    launch_scale_by_diag<double>(h->stream, h->n, static_cast<const double*>(h->d_pc), static_cast<double*>(x),
+                                 !to_u);
+  HIPCHK(hipGetLastError());
+}
+
 SolverBase* fwd(sdr_handle* h) {
   if (h->s % h->opt.zeta != 0) {
     set_err("s_dim must be a multiple of zeta");
     throw HipError{SDR_EINVAL};
   }
-  if (!h->fwd) h->fwd = make_solver(h, false);
+  if (!h->fwd) {
+    refresh_precond(h);
+    h->fwd = make_solver(h, false);
+  }
   return h->fwd.get();
 }
 
@@ -1451,6 +1499,9 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
   } else if (k == "dia") {
     if (built || (v != 0.0 && v != 1.0)) return set_err("dia is 0 or 1, before the first solve"), SDR_EINVAL;
     h->opt.dia = (int)v;
+  } else if (k == "precond") {
+    if (built || (v != 0.0 && v != 1.0)) return set_err("precond is 0 or 1, before the first solve"), SDR_EINVAL;
+    h->opt.precond = (int)v;
   } else if (k == "lsq_chunk") {
     if (built || v < 1 || v > 64) return set_err("lsq_chunk in [1,64], before the first solve"), SDR_EINVAL;
     h->opt.lsq_chunk = (int)v;
@@ -1497,6 +1548,7 @@ int sdr_update_matrix(sdr_handle* h, const sdr_csr* A) {
     HIPCHK(hipMemcpyAsync(h->vals, A->values, h->elem() * h->nnz, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     refresh_adjoint_values(h);
+    if (h->fwd) refresh_precond(h);
     if (h->fwd) h->fwd->matrix_changed();
     if (h->adj) h->adj->matrix_changed();
     return SDR_OK;
@@ -1514,7 +1566,13 @@ int sdr_solve(sdr_handle* h, const sdr_csr* A, const void* b, void* x, double to
       if (rc != SDR_OK) return rc;
     }
     order_after_caller(h);
-    return fwd(h)->solve(b, x, tol, st, &h->trace);
+    SolverBase* f = fwd(h);
+    if (h->opt.precond == 0) return f->solve(b, x, tol, st, &h->trace);
+    precond_scale(h, x, true);  // the initial guess u0 = D x0
+    const int rc = f->solve(b, x, tol, st, &h->trace);
+    precond_scale(h, x, false);  // x = D^-1 u
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return rc;
   } catch (HipError& e) {
     return e.code;
   }
@@ -1658,7 +1716,7 @@ void sdr_destroy(sdr_handle* h) {
   h->fwd.reset();
   h->adj.reset();
   for (void* p : {(void*)h->rp, (void*)h->ci, h->vals, (void*)h->rpT, (void*)h->ciT, (void*)h->perm,
-                  h->valsT})
+                  h->valsT, h->d_pc, h->vals_pc, (void*)h->pc_flag})
     dfree(p);
   if (h->own) (void)hipStreamDestroy(h->own);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);

@@ -13,6 +13,7 @@ still ends with a sketched residual below the residual it started from.
 """
 import json
 import os
+import time
 
 import numpy as np
 import pytest
@@ -44,7 +45,12 @@ def _run(variant):
         if i > 0:
             h.update_matrix(_dev(cd2d_central(P["n"], alpha).values))
         print(f"[gpu] {variant} system {i} alpha {alpha}", flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         x, st = h.solve(b, tol=P["tol"])
+        torch.cuda.synchronize()
+        print(f"  solve {1e3 * (time.perf_counter() - t0):.1f} ms, cycles {st['cycles']}, "
+              f"matvecs {st['matvecs']}, inner products {st['inner_products']}", flush=True)
         out.append((st, h.trace()))
     return out
 

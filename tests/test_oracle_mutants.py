@@ -77,3 +77,32 @@ def test_mutant_is_caught(name, monkeypatch):
             caught.append(pin)
             break
     assert caught, f"mutant {name} passed every pin"
+
+
+# Planted mistakes in the right Jacobi preconditioned solve, against its pins.
+PRECOND_MUTANTS = {
+    "left_scaling": ("Ahat.data = A.data * dinv[A.indices]",
+                     "Ahat.data = A.data * dinv[np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))]"),
+    "d_not_inverted": ("Ahat.data = A.data * dinv[A.indices]", "Ahat.data = A.data * d[A.indices]"),
+    "x_not_back_transformed": ("out.x = out.x / d", "out.x = out.x"),
+    "x0_not_transformed": ("u0 = None if x0 is None else d * np.asarray(x0)",
+                           "u0 = None if x0 is None else np.asarray(x0)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PRECOND_MUTANTS))
+def test_precond_mutant_is_caught(name, monkeypatch):
+    import test_oracle_precond as ppins
+    mod = _mutant_module(*PRECOND_MUTANTS[name])
+    monkeypatch.setattr(ppins, "sdr_solve_right_jacobi", mod.sdr_solve_right_jacobi)
+    caught = False
+    for pin in (lambda: ppins.test_power_of_two_columns_reduce_to_the_unscaled_solve(False),
+                ppins.test_diagonal_matrix_is_one_step,
+                ppins.test_badly_scaled_columns_converge_as_the_balanced_system,
+                ppins.test_exact_initial_guess_and_zero_diagonal):
+        try:
+            pin()
+        except Exception:
+            caught = True
+            break
+    assert caught, f"mutant {name} passed every pin"

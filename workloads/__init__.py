@@ -14,6 +14,8 @@ from .problems import (  # noqa: F401
     theta_weighted,
     edge_weighted,
     shifted_diagonal,
+    column_scaled,
+    log_uniform,
     randn,
     crandn,
     workload,

@@ -15,6 +15,8 @@ fastest, every entry scaled by h^2):
   experiment (Section 6.3): (L (x) I + I (x) L) + alpha (D (x) I + I (x) D) with
   L = (n+1)^2 tridiag(1,-2,1) and D = (n+1)/2 tridiag(-1,0,1).
 * ``theta_weighted`` scales every stored entry of a base matrix by theta_e.
+* ``column_scaled`` multiplies column j of a base matrix by c_j (a badly
+  scaled unknown per column; ``log_uniform`` draws such scales).
 * ``edge_weighted``  weights the grid edges (off-diagonal entries) by theta_e
   and sets each diagonal so that the row keeps the base matrix's row sum: a
   weighted upwind operator that stays a nonsingular M-matrix.
@@ -172,6 +174,21 @@ def shifted_diagonal(base: CSR, d: np.ndarray) -> CSR:
     vals = base.values.copy()
     vals[diag_pos] += d
     return base.with_values(vals)
+
+
+def column_scaled(base: CSR, c: np.ndarray) -> CSR:
+    """base diag(c): every stored entry (i, j) multiplied by c_j."""
+    c = np.asarray(c)
+    assert c.shape == (base.n,)
+    return base.with_values(base.values * c[base.col_idx])
+
+
+def log_uniform(n: int, lo: float, hi: float, seed: int, pow2: bool = False) -> np.ndarray:
+    """n values 10^U(lo, hi) (PCG64); with pow2, the nearest powers of two."""
+    e = np.random.default_rng(seed).uniform(lo, hi, n)
+    if pow2:
+        return np.exp2(np.round(e * np.log2(10.0)))
+    return 10.0 ** e
 
 
 def randn(n: int, seed: int) -> np.ndarray:
