@@ -9,9 +9,10 @@ constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kWaves = kBlock / 64;
 constexpr int kLsqBlock = 512;     // threads of the single-block least-squares kernels
 constexpr int kMaxWindow = 4;      // largest truncation window t
-constexpr int kRowsSpmv = 1024;    // rows per block, SpMV + window products + sketch
+constexpr int kRowsSpmv = 768;     // rows per block, SpMV + window products + sketch (3 per thread)
 constexpr int kRowsUpdate = 2048;  // rows per block of the other streaming kernels
-constexpr int kUpdateRows = 8;     // rows per thread of the update: a tile is two SpMV tiles, on the same XCD
+constexpr int kUpdateRows = 8;     // rows per thread of the update (a tile of 2048 rows)
+constexpr int kPartRounds = 6;     // SpMV partials per thread the update loads up front (1536 tiles)
 constexpr int kWaveTileNnz = 512;  // largest staged chunk (entries of 64 rows) per wave of the SpMV
 constexpr int kSpmvLds = 64 * 1024;  // LDS budget of the SpMV kernel: sketch bins + staged chunks
 constexpr int kMaxDiag = 16;       // most diagonals of the stencil (diagonal-storage) SpMV

@@ -496,9 +496,9 @@ __global__ __launch_bounds__(kBlock) void k_update(
   // so the block's reduction runs while the stream is still in flight.
   const A* pp = part + (int64_t)s * nb1;
   const int nc = tw + 1;
-  A pv0[4][NC];  // columns past nc re-read column nc - 1 and are not added
+  A pv0[kPartRounds][NC];  // columns past nc re-read column nc - 1 and are not added
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < kPartRounds; ++u) {
     const int i = min((int)threadIdx.x + u * kBlock, nb1 - 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) pv0[u][c] = pp[(int64_t)min(c, nc - 1) * nb1 + i];
@@ -517,18 +517,19 @@ __global__ __launch_bounds__(kBlock) void k_update(
 #pragma unroll
   for (int q = 0; q < TWM; ++q) nqv[q] = (q < tw && i0 + q != jprev) ? nu[i0 + q] : 1.0;
   if (halted) return;
-  // column sums in the order of col_sum: thread-strided rounds of four,
-  // then the waves in order
+  // column sums in the order of col_sum: each thread adds partials
+  // threadIdx.x, + kBlock, + 2 kBlock, ... in increasing order, then the
+  // waves in order (the grouping of the loads into rounds does not change it)
   A sums[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) sums[c] = zero<A>();
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < kPartRounds; ++u)
     if ((int)threadIdx.x + u * kBlock < nb1)
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         if (c < nc) sums[c] += pv0[u][c];
-  for (int j0 = (int)threadIdx.x + 4 * kBlock; j0 < nb1; j0 += 4 * kBlock) {
+  for (int j0 = (int)threadIdx.x + kPartRounds * kBlock; j0 < nb1; j0 += 4 * kBlock) {
     A v[4][NC];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
