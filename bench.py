@@ -289,7 +289,9 @@ def main():
     layout = h.spmv_layout()
     tname = "double" if args.precision == 0 else "float"
     if layout:
-        k1_key = f"k_spmv_dia_sketch<{tname}, {len(layout) if len(layout) in (3, 5, 7, 9) else 0}>"
+        # instantiation: <type, diagonals (0: any), window bound (2 for t <= 2, else 4)>
+        k1_key = (f"k_spmv_dia_sketch<{tname}, {len(layout) if len(layout) in (3, 5, 7, 9) else 0}, "
+                  f"{2 if p['t'] <= 2 else 4}>")
         k1_bytes = sum(hist[tw] * spmv_dia_sketch_bytes(N, len(layout), tw, p=pb, pv=pb)
                        for tw in range(len(hist)))
         k1_name = (f"k_spmv_dia_sketch (stencil SpMV on {len(layout)} diagonals {layout} + "

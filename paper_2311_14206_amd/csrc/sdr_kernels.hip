@@ -367,8 +367,9 @@ void launch_spmv_sketch(hipStream_t st, int n, const int* rp, const int* ci, con
 // fall outside the matrix are dropped by a select, so all loads of a row are
 // in flight together before the sketch's LDS atomics and the arithmetic.
 // ND > 0 fixes the number of diagonals at compile time (the common stencils);
-// ND == 0 reads it from M.
-template <class T, int ND>
+// ND == 0 reads it from M.  TWM bounds the window length (2, or kMaxWindow for
+// longer windows), so a short window's accumulators take no registers.
+template <class T, int ND, int TWM>
 __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
     int n, DiaView<T> M, const T* __restrict__ x, T* __restrict__ w, Window<T> win, int tw, SketchSpec sk,
     int do_spmv, typename traits<T>::acc* __restrict__ part, int nb, const Ctrl* __restrict__ ctrl) {
@@ -402,9 +403,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
     const int tl = (tw > 0 && win.p[tw - 1] == x) ? tw - 1 : tw;
     for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
       const T xt = x[r];
-      T vv[KD], xc[KD], pw[kMaxWindow];
+      T vv[KD], xc[KD], pw[TWM];
 #pragma unroll
-      for (int q = 0; q < kMaxWindow; ++q)
+      for (int q = 0; q < TWM; ++q)
         if (q < tl) pw[q] = win.p[q][r];
 #pragma unroll
       for (int k = 0; k < KD; ++k) {
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
       const A wa = widen(wt);
       nw += abs2(wa);
 #pragma unroll
-      for (int q = 0; q < kMaxWindow; ++q)
+      for (int q = 0; q < TWM; ++q)
         if (q < tw) d[q] += conj(q < tl ? widen(pw[q]) : xa) * wa;
     }
   }
@@ -450,12 +451,22 @@ void launch_spmv_dia_sketch(hipStream_t st, int n, DiaView<T> M, const T* x, T* 
   const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
   const int dsp = spmv ? 1 : 0;
   void (*kern)(int, DiaView<T>, const T*, T*, Window<T>, int, SketchSpec, int, A*, int, const Ctrl*);
-  switch (M.ndiag) {
-    case 3: kern = k_spmv_dia_sketch<T, 3>; break;
-    case 5: kern = k_spmv_dia_sketch<T, 5>; break;
-    case 7: kern = k_spmv_dia_sketch<T, 7>; break;
-    case 9: kern = k_spmv_dia_sketch<T, 9>; break;
-    default: kern = k_spmv_dia_sketch<T, 0>; break;
+  if (tw <= 2) {
+    switch (M.ndiag) {
+      case 3: kern = k_spmv_dia_sketch<T, 3, 2>; break;
+      case 5: kern = k_spmv_dia_sketch<T, 5, 2>; break;
+      case 7: kern = k_spmv_dia_sketch<T, 7, 2>; break;
+      case 9: kern = k_spmv_dia_sketch<T, 9, 2>; break;
+      default: kern = k_spmv_dia_sketch<T, 0, 2>; break;
+    }
+  } else {
+    switch (M.ndiag) {
+      case 3: kern = k_spmv_dia_sketch<T, 3, kMaxWindow>; break;
+      case 5: kern = k_spmv_dia_sketch<T, 5, kMaxWindow>; break;
+      case 7: kern = k_spmv_dia_sketch<T, 7, kMaxWindow>; break;
+      case 9: kern = k_spmv_dia_sketch<T, 9, kMaxWindow>; break;
+      default: kern = k_spmv_dia_sketch<T, 0, kMaxWindow>; break;
+    }
   }
   if (e0)
     hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), lds, st, e0, e1, 0, n, M, x, w, win, tw, sk, dsp,
