@@ -86,3 +86,20 @@ def test_jacobi_zero_or_missing_diagonal_is_an_error():
     assert st["converged"]
     with pytest.raises(SDRError, match="diagonal"):
         h.update_matrix(gp._dev(zero))
+
+
+def test_jacobi_with_fp32_basis_reaches_fp64_tolerance():
+    """precision=1: A D^-1 narrowed to FP32 for the basis, residuals on the FP64 values."""
+    K = cd2d_upwind(47)
+    A = column_scaled(K, log_uniform(K.n, -3.0, 3.0, seed=11))
+    b = randn(K.n, 12)
+    h = gp._solver(A, precond=1, precision=1, **KW)
+    x, st = h.solve(gp._dev(b), tol=1e-8)
+    xg = gp._host(x)
+    assert st["converged"]
+    assert np.linalg.norm(b - A.to_scipy() @ xg) <= 1e-8 * np.linalg.norm(b)
+    ref = sdr_solve_right_jacobi(A.to_scipy(), b, tol=1e-8, **KW)
+    err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    print(f"jacobi + FP32 basis: {st['iters']} steps (oracle {ref.iters}), "
+          f"rel. error vs FP64 oracle {err:.2e}", flush=True)
+    assert err < 1e-5
