@@ -131,7 +131,8 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *                    (A D^-1 on the same pattern, refreshed by
  *                    sdr_update_matrix), so an Arnoldi step costs the same.
  *                    Every diagonal entry must be stored and nonzero, else
- *                    the solve or update returns SDR_EINVAL.  Residuals,
+ *                    the solve or update returns SDR_EINVAL (and, after a
+ *                    rejected update, every solve until a valid matrix).  Residuals,
  *                    tolerances and stats refer to A x = b (the same vector
  *                    b - A D^-1 u); the recycle space, basis and sketches
  *                    (sdr_get_recycle, sdr_get_basis) belong to A D^-1.

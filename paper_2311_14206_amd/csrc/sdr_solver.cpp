@@ -1234,6 +1234,7 @@ struct sdr_handle {
   void* d_pc = nullptr;
   void* vals_pc = nullptr;
   int* pc_flag = nullptr;
+  bool pc_bad = false;  // the last matrix had a zero diagonal entry: vals_pc is stale
   bool adj_ready = false;
   uint64_t pattern_hash = 0;
   hipStream_t own = nullptr;
@@ -1296,6 +1297,7 @@ void refresh_precond(sdr_handle* h) {
   int flag = 0;
   HIPCHK(hipMemcpyAsync(&flag, h->pc_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  h->pc_bad = flag != 0;
   if (flag) {
     set_err("Jacobi preconditioning needs every diagonal entry of A stored and nonzero");
     throw HipError{SDR_EINVAL};
@@ -1568,6 +1570,10 @@ int sdr_solve(sdr_handle* h, const sdr_csr* A, const void* b, void* x, double to
     order_after_caller(h);
     SolverBase* f = fwd(h);
     if (h->opt.precond == 0) return f->solve(b, x, tol, st, &h->trace);
+    if (h->pc_bad) {
+      set_err("Jacobi preconditioning needs every diagonal entry of A stored and nonzero");
+      return SDR_EINVAL;
+    }
     precond_scale(h, x, true);  // the initial guess u0 = D x0
     const int rc = f->solve(b, x, tol, st, &h->trace);
     precond_scale(h, x, false);  // x = D^-1 u

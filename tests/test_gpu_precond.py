@@ -86,6 +86,12 @@ def test_jacobi_zero_or_missing_diagonal_is_an_error():
     assert st["converged"]
     with pytest.raises(SDRError, match="diagonal"):
         h.update_matrix(gp._dev(zero))
+    # the rejected matrix is not solved with the previous one's A D^-1
+    with pytest.raises(SDRError, match="diagonal"):
+        h.solve(b, tol=1e-8)
+    h.update_matrix(gp._dev(K.values))
+    x, st = h.solve(b, tol=1e-8)
+    assert st["converged"]
 
 
 def test_jacobi_with_fp32_basis_reaches_fp64_tolerance():
