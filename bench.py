@@ -27,6 +27,12 @@ in HBM before the timed region.  Prints one JSON line:
 
 writes that summary (markdown) from the counter CSVs of two rocprofv3 runs of
 this script with --copy-calib-mb (one --pmc FETCH_SIZE, one --pmc WRITE_SIZE).
+
+    python bench.py --summarize-kstats STATS.csv TRACE.csv BENCH.json
+
+writes the kernel-statistics summary of a rocprofv3 --kernel-trace --stats run
+of this script, next to the kernel duration the bench's own events measured
+(BENCH.json: this script's output line from the same machine).
 """
 
 from __future__ import annotations
@@ -179,6 +185,62 @@ def summarize_pmc(fetch_csv, write_csv, calib_mb, workload_name):
     return "\n".join(lines) + "\n"
 
 
+def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name):
+    """Markdown summary of a rocprofv3 kernel-trace run: per-kernel calls and
+    durations, the step kernel's per-launch distribution, whether any of its
+    launches overlapped a kernel of the least-squares stream, and the bench's
+    own event timing of the same kernel."""
+    import numpy as np
+
+    def short(n):
+        return n.split("(")[0].replace("void ", "").replace("sdr::", "")
+
+    with open(stats_csv) as f:
+        rows = list(csv.DictReader(f))
+    with open(trace_csv) as f:
+        trace = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(r["Kernel_Name"]))
+                 for r in csv.DictReader(f)]
+    with open(bench_json) as f:
+        bj = json.loads(f.read().strip().splitlines()[-1])
+    from workloads import WORKLOADS
+    p = WORKLOADS[workload_name]
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    steps = [r for r in rows if short(r["Name"]).startswith(("k_spmv_dia_sketch<", "k_spmv_sketch<"))]
+    k1 = max(steps, key=lambda r: float(r["TotalDurationNs"]))
+    k1n = short(k1["Name"])
+    d1 = sorted((s_, e) for s_, e, n in trace if n == k1n)
+    dur = np.array([(e - s_) / 1e3 for s_, e in d1])
+    side = sorted((s_, e) for s_, e, n in trace if n.startswith(("k_lsq_", "k_reduce_steps")))
+    overlap = sum(1 for s_, e in d1 if any(a < e and b > s_ for a, b in side))
+    R = "$GRAFT_REPO_ROOT"
+    sv = bj["solve"]
+    lines = [f"# rocprofv3 kernel statistics: GMRES-SDR solve, {workload_name} ({bj['dtype']})", "",
+             f"Workload {bj['config']['workload']}; m = {p['m']}, k = {p['k']}, t = {p['t']}, "
+             f"s = {p['s']}, zeta = {p['zeta']}, tol {p['tol']:g}; one solve from x0 = 0 with an empty "
+             f"recycle space ({sv['iters']} Arnoldi steps, {sv['cycles']} cycles).", "",
+             "Commands (from /tmp with TMPDIR=/tmp; R is the repository root):", "",
+             f"    timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d "
+             f"{R}/gpurun_out/ktrace -o run -- python3 {R}/bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+             f"    python3 {R}/bench.py --summarize-kstats {R}/gpurun_out/ktrace/run_kernel_stats.csv "
+             f"{R}/gpurun_out/ktrace/run_kernel_trace.csv BENCH.json --workload {workload_name}", "",
+             "(BENCH.json: the output line of `python3 bench.py` run just before, on the same box.)", "",
+             f"Kernel source digest (bench.py kernel_source_digest, comments ignored): {kernel_source_digest()}.",
+             "",
+             f"The step kernel {k1n} averages {float(k1['AverageNs']) / 1e3:.2f} us over {len(dur)} launches "
+             f"here (median {np.median(dur):.2f} us, 5th and 95th percentiles "
+             f"{np.percentile(dur, 5):.2f} and {np.percentile(dur, 95):.2f} us). "
+             f"{overlap} of its launches overlapped a least-squares kernel of the second stream. "
+             f"The bench's own HIP events (recorded by the dispatches themselves on sampled steps, "
+             f"created without a system-scope fence) read {bj['roofline']['avg_us']:.2f} us over "
+             f"{bj['arnoldi_step']['launches']} launches in the bench run.", "",
+             "| Calls | Avg (us) | Total (ms) | % | Kernel |", "|---:|---:|---:|---:|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"| {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{100 * float(r['TotalDurationNs']) / total:.2f} | `{short(r['Name'])}` |")
+    return "\n".join(lines) + "\n"
+
+
 def cpu_baseline(A, b, p, gpu_iters):
     import numpy as np
     from oracle import sdr_solve
@@ -220,7 +282,12 @@ def main():
                     help="run one device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary of two rocprofv3 counter runs and exit")
+    ap.add_argument("--summarize-kstats", nargs=3, metavar=("STATS_CSV", "TRACE_CSV", "BENCH_JSON"),
+                    help="write the kernel-statistics summary of a rocprofv3 kernel-trace run and exit")
     args = ap.parse_args()
+    if args.summarize_kstats:
+        sys.stdout.write(summarize_kstats(*args.summarize_kstats, args.workload))
+        return
     if args.summarize_pmc:
         sys.stdout.write(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
                                        args.copy_calib_mb or 256, args.workload))
