@@ -143,6 +143,13 @@ def _pmc_rows(path):
     return out
 
 
+def _rel_dir(path):
+    """The directory of a profiler output file, as $R/... when under the repository."""
+    d = os.path.dirname(os.path.abspath(path))
+    rel = os.path.relpath(d, ROOT)
+    return d if rel.startswith("..") else f"$R/{rel}"
+
+
 def summarize_pmc(fetch_csv, write_csv, calib_mb, workload_name):
     """Markdown summary of two counter runs: per-kernel mean FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by the factor that maps the
@@ -154,16 +161,16 @@ def summarize_pmc(fetch_csv, write_csv, calib_mb, workload_name):
     if f_kib <= 0 or w_kib <= 0:
         raise SystemExit("no calibration copy in the counter runs (run them with --copy-calib-mb)")
     ff, fw = calib / (1024.0 * f_kib), calib / (1024.0 * w_kib)
-    R = "$GRAFT_REPO_ROOT"
-    run = (f"timeout -s KILL 240 rocprofv3 --pmc {{c}} --output-format csv -d {R}/gpurun_out/pmc_{{d}} "
+    R = "$R"
+    run = (f"timeout -s KILL 240 rocprofv3 --pmc {{c}} --output-format csv -d {{d}} "
            f"-o run -- python3 {R}/bench.py --workload {workload_name} --steps 1 --warmup 0 "
            f"--no-cpu-baseline --copy-calib-mb {calib_mb}")
     lines = [f"# HBM traffic per dispatch, {workload_name} solve (rocprofv3 counters)", "",
              "Commands (from /tmp with TMPDIR=/tmp; R is the repository root):", "",
-             "    " + run.format(c="FETCH_SIZE", d="fetch"),
-             "    " + run.format(c="WRITE_SIZE", d="write"),
-             f"    python3 {R}/bench.py --summarize-pmc {R}/gpurun_out/pmc_fetch/run_counter_collection.csv "
-             f"{R}/gpurun_out/pmc_write/run_counter_collection.csv --copy-calib-mb {calib_mb} "
+             "    " + run.format(c="FETCH_SIZE", d=_rel_dir(fetch_csv)),
+             "    " + run.format(c="WRITE_SIZE", d=_rel_dir(write_csv)),
+             f"    python3 {R}/bench.py --summarize-pmc {_rel_dir(fetch_csv)}/{os.path.basename(fetch_csv)} "
+             f"{_rel_dir(write_csv)}/{os.path.basename(write_csv)} --copy-calib-mb {calib_mb} "
              f"--workload {workload_name}", "",
              f"Calibration: one device copy of {calib_mb} MiB ({calib} bytes read and written) reads "
              f"FETCH_SIZE {f_kib:.1f} KiB and WRITE_SIZE {w_kib:.1f} KiB, so bytes = "
@@ -212,7 +219,8 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name):
     dur = np.array([(e - s_) / 1e3 for s_, e in d1])
     side = sorted((s_, e) for s_, e, n in trace if n.startswith(("k_lsq_", "k_reduce_steps")))
     overlap = sum(1 for s_, e in d1 if any(a < e and b > s_ for a, b in side))
-    R = "$GRAFT_REPO_ROOT"
+    R = "$R"
+    kd = _rel_dir(stats_csv)
     sv = bj["solve"]
     lines = [f"# rocprofv3 kernel statistics: GMRES-SDR solve, {workload_name} ({bj['dtype']})", "",
              f"Workload {bj['config']['workload']}; m = {p['m']}, k = {p['k']}, t = {p['t']}, "
@@ -220,9 +228,9 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name):
              f"recycle space ({sv['iters']} Arnoldi steps, {sv['cycles']} cycles).", "",
              "Commands (from /tmp with TMPDIR=/tmp; R is the repository root):", "",
              f"    timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d "
-             f"{R}/gpurun_out/ktrace -o run -- python3 {R}/bench.py --steps 1 --warmup 0 --no-cpu-baseline",
-             f"    python3 {R}/bench.py --summarize-kstats {R}/gpurun_out/ktrace/run_kernel_stats.csv "
-             f"{R}/gpurun_out/ktrace/run_kernel_trace.csv BENCH.json --workload {workload_name}", "",
+             f"{kd} -o run -- python3 {R}/bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+             f"    python3 {R}/bench.py --summarize-kstats {kd}/{os.path.basename(stats_csv)} "
+             f"{_rel_dir(trace_csv)}/{os.path.basename(trace_csv)} BENCH.json --workload {workload_name}", "",
              "(BENCH.json: the output line of `python3 bench.py` run just before, on the same box.)", "",
              f"Kernel source digest (bench.py kernel_source_digest, comments ignored): {kernel_source_digest()}.",
              "",
