@@ -109,3 +109,23 @@ def test_jacobi_with_fp32_basis_reaches_fp64_tolerance():
     print(f"jacobi + FP32 basis: {st['iters']} steps (oracle {ref.iters}), "
           f"rel. error vs FP64 oracle {err:.2e}", flush=True)
     assert err < 1e-5
+
+
+def test_spmv_and_adjoint_of_a_preconditioned_handle_use_a():
+    """precond applies to the forward solve only: sdr_spmv gives A x and the
+    adjoint solve solves A^T lambda = g."""
+    K = cd2d_upwind(30)
+    A = column_scaled(K, log_uniform(K.n, -1.0, 1.0, seed=19))
+    h = gp._solver(A, precond=1, **KW)
+    x0 = randn(K.n, 20)
+    y = gp._host(h.spmv(gp._dev(x0)))
+    ref = A.to_scipy() @ x0
+    assert np.linalg.norm(y - ref) <= 1e-14 * np.linalg.norm(ref)
+    b = randn(K.n, 21)
+    x, st = h.solve(gp._dev(b), tol=1e-9)
+    assert st["converged"]
+    g = randn(K.n, 22)
+    lam, sa = h.solve_adjoint(gp._dev(g), tol=1e-9)
+    assert sa["converged"]
+    r = g - A.to_scipy().T @ gp._host(lam)
+    assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(g)
