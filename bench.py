@@ -364,9 +364,14 @@ def main():
     layout = h.spmv_layout()
     tname = "double" if args.precision == 0 else "float"
     if layout:
-        # instantiation: <type, diagonals (0: any), window bound (2 for t <= 2, else 4)>
-        k1_key = (f"k_spmv_dia_sketch<{tname}, {len(layout) if len(layout) in (3, 5, 7, 9) else 0}, "
-                  f"{2 if p['t'] <= 2 else 4}>")
+        # instantiation: <type, diagonals (0: any), window bound (2 for t <= 2, else 4),
+        # threads (512 while 8 waves of FP64 sketch bins fit 64 KiB of LDS; else the
+        # generic 256-thread one)
+        if 8 * (p["s"] + 6) * 8 <= 64 * 1024:
+            k1_key = (f"k_spmv_dia_sketch<{tname}, {len(layout) if len(layout) in (3, 5, 7, 9) else 0}, "
+                      f"{2 if p['t'] <= 2 else 4}, 512>")
+        else:
+            k1_key = f"k_spmv_dia_sketch<{tname}, 0, 4, 256>"
         k1_bytes = sum(hist[tw] * spmv_dia_sketch_bytes(N, len(layout), tw, p=pb, pv=pb)
                        for tw in range(len(hist)))
         k1_name = (f"k_spmv_dia_sketch (stencil SpMV on {len(layout)} diagonals {layout} + "

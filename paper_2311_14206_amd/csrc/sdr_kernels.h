@@ -9,7 +9,9 @@ constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kWaves = kBlock / 64;
 constexpr int kLsqBlock = 512;     // threads of the single-block least-squares kernels
 constexpr int kMaxWindow = 4;      // largest truncation window t
-constexpr int kRowsSpmv = 768;     // rows per block, SpMV + window products + sketch (3 per thread)
+constexpr int kRowsSpmv = 1536;    // rows per tile, SpMV + window products + sketch
+constexpr int kSpmvThreads = 512;  // threads of the diagonal-storage SpMV (3 rows each); 256 when
+                                   // 8 waves of sketch bins exceed kSpmvLds
 constexpr int kRowsUpdate = 2048;  // rows per block of the other streaming kernels
 constexpr int kUpdateRows = 8;     // rows per thread of the update (a tile of 2048 rows)
 constexpr int kPartRounds = 6;     // SpMV partials per thread the update loads up front (1536 tiles)

@@ -183,7 +183,7 @@ __device__ __forceinline__ void put_re(cx<double>* p, double v) { *p = cx<double
 // summed per wave first, then one barrier (which also completes the bins)
 // and a fixed-order sum over the waves: the same operations in the same
 // order as one block_sum per value, with one barrier instead of three each.
-template <class A>
+template <class A, int NW = kWaves, int NT = kBlock>  // NW waves, NT threads per block
 __device__ __forceinline__ void store_step_partials(A* __restrict__ part, int nb, int tile, int s, int tw,
                                                     const A* bins_all, double nx, const A (&d)[kMaxWindow],
                                                     double nw, A (*wsum)[kMaxWindow + 2]) {
@@ -201,9 +201,9 @@ __device__ __forceinline__ void store_step_partials(A* __restrict__ part, int nb
       for (int i = 0; i < NV; ++i) wsum[threadIdx.x >> 6][i] = v[i];
   }
   __syncthreads();
-  for (int row = threadIdx.x; row < s; row += kBlock) {
+  for (int row = threadIdx.x; row < s; row += NT) {
     A sum = bins_all[row];
-    for (int q = 1; q < kWaves; ++q) sum += bins_all[q * s + row];
+    for (int q = 1; q < NW; ++q) sum += bins_all[q * s + row];
     part[(int64_t)row * nb + tile] = sum;
   }
   // thread i < tw + 2 writes value i: ||x||^2 (when sketching) at row s, the
@@ -213,7 +213,7 @@ __device__ __forceinline__ void store_step_partials(A* __restrict__ part, int nb
   if (i >= (s > 0 ? 0 : 1) && i < tw + 2) {
     const int src = i <= tw ? i : NV - 1;
     A sum = wsum[0][src];
-    for (int q = 1; q < kWaves; ++q) sum += wsum[q][src];
+    for (int q = 1; q < NW; ++q) sum += wsum[q][src];
     part[(int64_t)(s > 0 ? s + i : i - 1) * nb + tile] = sum;
   }
 }
@@ -368,9 +368,11 @@ void launch_spmv_sketch(hipStream_t st, int n, const int* rp, const int* ci, con
 // in flight together before the sketch's LDS atomics and the arithmetic.
 // ND > 0 fixes the number of diagonals at compile time (the common stencils);
 // ND == 0 reads it from M.  TWM bounds the window length (2, or kMaxWindow for
-// longer windows), so a short window's accumulators take no registers.
-template <class T, int ND, int TWM>
-__global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
+// longer windows), so a short window's accumulators take no registers.  NT
+// threads per block (512: 8 waves, 3 rows each over a 1536-row tile; 256 when
+// 8 waves of sketch bins do not fit the LDS budget).
+template <class T, int ND, int TWM, int NT>
+__global__ __launch_bounds__(NT) void k_spmv_dia_sketch(
     int n, DiaView<T> M, const T* __restrict__ x, T* __restrict__ w, Window<T> win, int tw, SketchSpec sk,
     int do_spmv, typename traits<T>::acc* __restrict__ part, int nb, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
   const int r0 = tile * kRowsSpmv;
   const int r1 = min(n, r0 + kRowsSpmv);
   if (!do_spmv) {
-    for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += NT) {
       const A xa = widen(x[r]);
       if (halted) return;
       nx += abs2(xa);
@@ -401,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
     // In an Arnoldi step the newest window vector is x itself: its value is
     // already in a register.
     const int tl = (tw > 0 && win.p[tw - 1] == x) ? tw - 1 : tw;
-    for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += NT) {
       const T xt = x[r];
       T vv[KD], xc[KD], pw[TWM];
 #pragma unroll
@@ -439,8 +441,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_sketch(
     }
   }
   if (halted) return;
-  __shared__ A wsum[kWaves][kMaxWindow + 2];
-  store_step_partials(part, nb, tile, s, tw, reinterpret_cast<const A*>(smem_raw), nx, d, nw, wsum);
+  __shared__ A wsum[NT / 64][kMaxWindow + 2];
+  store_step_partials<A, NT / 64, NT>(part, nb, tile, s, tw, reinterpret_cast<const A*>(smem_raw), nx, d, nw, wsum);
 }
 
 template <class T>
@@ -448,31 +450,38 @@ void launch_spmv_dia_sketch(hipStream_t st, int n, DiaView<T> M, const T* x, T* 
                             SketchSpec sk, bool spmv, typename traits<T>::acc* part, int nb,
                             const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
   using A = typename traits<T>::acc;
-  const size_t lds = (size_t)kWaves * sk.s * sizeof(A);
+  // 8 waves per block when their sketch bins fit the LDS budget, else 4 (the
+  // generic instantiation); sdr_create keeps 4 waves' bins within it
+  const bool wide =
+      (size_t)(kSpmvThreads / 64) * (sk.s + kMaxWindow + 2) * sizeof(A) <= (size_t)kSpmvLds;  // bins + wsum
+  const int nt = wide ? kSpmvThreads : kBlock;
+  const size_t lds = (size_t)(nt / 64) * sk.s * sizeof(A);
   const int dsp = spmv ? 1 : 0;
   void (*kern)(int, DiaView<T>, const T*, T*, Window<T>, int, SketchSpec, int, A*, int, const Ctrl*);
-  if (tw <= 2) {
+  if (!wide) {
+    kern = k_spmv_dia_sketch<T, 0, kMaxWindow, kBlock>;
+  } else if (tw <= 2) {
     switch (M.ndiag) {
-      case 3: kern = k_spmv_dia_sketch<T, 3, 2>; break;
-      case 5: kern = k_spmv_dia_sketch<T, 5, 2>; break;
-      case 7: kern = k_spmv_dia_sketch<T, 7, 2>; break;
-      case 9: kern = k_spmv_dia_sketch<T, 9, 2>; break;
-      default: kern = k_spmv_dia_sketch<T, 0, 2>; break;
+      case 3: kern = k_spmv_dia_sketch<T, 3, 2, kSpmvThreads>; break;
+      case 5: kern = k_spmv_dia_sketch<T, 5, 2, kSpmvThreads>; break;
+      case 7: kern = k_spmv_dia_sketch<T, 7, 2, kSpmvThreads>; break;
+      case 9: kern = k_spmv_dia_sketch<T, 9, 2, kSpmvThreads>; break;
+      default: kern = k_spmv_dia_sketch<T, 0, 2, kSpmvThreads>; break;
     }
   } else {
     switch (M.ndiag) {
-      case 3: kern = k_spmv_dia_sketch<T, 3, kMaxWindow>; break;
-      case 5: kern = k_spmv_dia_sketch<T, 5, kMaxWindow>; break;
-      case 7: kern = k_spmv_dia_sketch<T, 7, kMaxWindow>; break;
-      case 9: kern = k_spmv_dia_sketch<T, 9, kMaxWindow>; break;
-      default: kern = k_spmv_dia_sketch<T, 0, kMaxWindow>; break;
+      case 3: kern = k_spmv_dia_sketch<T, 3, kMaxWindow, kSpmvThreads>; break;
+      case 5: kern = k_spmv_dia_sketch<T, 5, kMaxWindow, kSpmvThreads>; break;
+      case 7: kern = k_spmv_dia_sketch<T, 7, kMaxWindow, kSpmvThreads>; break;
+      case 9: kern = k_spmv_dia_sketch<T, 9, kMaxWindow, kSpmvThreads>; break;
+      default: kern = k_spmv_dia_sketch<T, 0, kMaxWindow, kSpmvThreads>; break;
     }
   }
   if (e0)
-    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), lds, st, e0, e1, 0, n, M, x, w, win, tw, sk, dsp,
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(nt), lds, st, e0, e1, 0, n, M, x, w, win, tw, sk, dsp,
                           part, nb, ctrl);
   else
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), lds, st, n, M, x, w, win, tw, sk, dsp, part, nb, ctrl);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(nt), lds, st, n, M, x, w, win, tw, sk, dsp, part, nb, ctrl);
 }
 
 template <class T>

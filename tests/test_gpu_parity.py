@@ -287,3 +287,14 @@ def test_large_cd2d_1024_first_cycle_and_residual():
     assert abs(tr[0]["res"] - ref.trace[0].res) <= 1e-8 * ref.trace[0].res
     x1 = _host(x1)
     assert np.linalg.norm(x1 - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("cplx,s", [(False, 1040), (True, 520)])
+def test_large_sketch_takes_four_wave_spmv_blocks(cplx, s):
+    """A sketch whose per-wave bins exceed the LDS budget at 8 waves runs the
+    diagonal-storage SpMV in 4-wave blocks over the same tiles."""
+    A = helmholtz2d(30, kappa=8.0) if cplx else cd2d_upwind(40)
+    b = crandn(A.n, 23) if cplx else randn(A.n, 23)
+    h, xg, st, tr, ref = _compare_solve(A, b, dict(m=20, k=4, t=2, s=s), 1e-9)
+    assert len(h.spmv_layout()) == 5
+    _assert_trace_and_x(xg, st, tr, ref, b=b)
