@@ -9,9 +9,12 @@ Contents
 ``sketch``      the sparse-sign sketching operator S (Section 3, eq. (3.1)):
                 an explicit scipy matrix built from a published counter-based
                 generator (SplitMix64 output mixer).
-``gmres_sdr``   GMRES-SDR, one cycle per Algorithm 1 and the restart /
-                sequence logic of Sections 3.2-3.6, in float64 / complex128,
-                and its right Jacobi preconditioned form.
+``gmres_sdr``   GMRES-SDR written from Section 3: truncated Arnoldi,
+                sketches, sketched least squares, residual control and the
+                harmonic-Ritz compression as separate parts, composed into a
+                restart cycle, with the restart and sequence logic of
+                Section 3.6, in float64 / complex128, and its right Jacobi
+                preconditioned form.
 """
 
 from .sketch import sketch_operator, sketch_pattern, splitmix64_mix  # noqa: F401

@@ -1,9 +1,13 @@
 """GMRES-SDR oracle in float64 / complex128 -- test infrastructure only.
 
-Follows the paper's Algorithm 1 (one cycle of GMRES-SDR for A x = r0) step by
-step, in the paper's order and notation, plus the restart loop and the
-sequence variants of Section 3.6.  Every dense small-matrix step uses a plain
-NumPy/SciPy routine (lstsq, svd, ordqz); nothing is blocked, fused or
+One restart cycle of GMRES-SDR for A x = r0 is written from Section 3 as
+separate parts: the truncated Arnoldi process (Section 3.2), the sketches of
+the basis and of A times the basis (Section 3, eq. (3.1)), the sketched
+least-squares problem (eq. (3.2), Section 3.3), the residual control
+(Section 3.4) and the sketched harmonic-Ritz compression (Section 3.5, eq.
+(3.6)); ``sdr_cycle`` composes them, ``sdr_solve`` adds the restart loop and
+the sequence variants of Section 3.6.  Every dense small-matrix step uses a
+plain NumPy/SciPy routine (lstsq, svd, ordqz); nothing is blocked, fused or
 reordered.  Where the paper is silent the following readings are taken (the
 GPU library takes the same ones):
 
@@ -146,10 +150,99 @@ def harmonic_ritz_update(W, SB, SAW, k: int, real: bool, s: int):
     return G, ell, k_eff
 
 
+def _window(j: int, t: int) -> range:
+    """1-based indices of the basis vectors that the j-th new direction is
+    orthogonalised against: the t most recent ones, v_{j-t+1} .. v_j
+    (Section 3.2; fewer at the start of a cycle)."""
+    return range(max(j - t + 1, 1), j + 1)
+
+
+def arnoldi_extend(A, V, H, j: int, t: int, breakdown_rtol: float, bump) -> bool:
+    """Truncated Arnoldi (Section 3.2): append v_{j+1} to V.
+
+    w = A v_j loses its components along the window vectors one after the
+    other (modified Gram-Schmidt in increasing index, coefficients H(i, j) =
+    v_i^* w, conjugate-linear in v_i); H(j+1, j) = ||w|| and v_{j+1} =
+    w / H(j+1, j), so that A V_j = V_{j+1} H_j with H banded.  Returns True on
+    breakdown, H(j+1, j) <= breakdown_rtol * ||A v_j||, in which case no
+    v_{j+1} is formed and H(j+1, j) = 0.
+    """
+    w = A @ V[:, j - 1]
+    bump("matvecs")
+    norm_Av = _norm(w)
+    for i in _window(j, t):
+        hij = np.vdot(V[:, i - 1], w)
+        bump("inner_products")
+        H[i - 1, j - 1] = hij
+        w = w - V[:, i - 1] * hij
+    hn = _norm(w)
+    bump("inner_products")
+    if not (hn > breakdown_rtol * norm_Av):
+        H[j, j - 1] = 0.0
+        return True
+    H[j, j - 1] = hn
+    V[:, j] = w / hn
+    return False
+
+
+def sketch_extend(S, V, H, SV, SAV, j: int, breakdown: bool, bump) -> None:
+    """Sketches of step j (Section 3): the new basis vector is sketched once,
+    SV(:, j+1) = S v_{j+1}, and S A v_j needs no sketch of its own, since the
+    Arnoldi relation gives A v_j = V_{j+1} H(:, j), hence
+    S A v_j = SV(:, 1:j+1) H(1:j+1, j) (only the band is nonzero)."""
+    nc = j if breakdown else j + 1
+    if not breakdown:
+        SV[:, j] = S @ V[:, j]
+        bump("sketches")
+    SAV[:, j - 1] = SV[:, :nc] @ H[:nc, j - 1]
+
+
+def sketched_least_squares(SAW, Sr):
+    """Sketched minimal residual (eq. (3.2)): the minimum-norm y minimising
+    ||S r0 - SAW y||, and that minimum, the sketched residual norm."""
+    y, *_ = np.linalg.lstsq(SAW, Sr, rcond=None)
+    return y, _norm(Sr - SAW @ y)
+
+
+def newest_column_dependent(SAW, rank_rtol: float) -> bool:
+    """True if the last column of SAW lies within rank_rtol (relative) of the
+    span of the others: the sketched basis of the search space lost rank."""
+    a = SAW[:, -1]
+    na = _norm(a)
+    if SAW.shape[1] == 1 or na == 0:
+        return not (na > 0)
+    c, *_ = np.linalg.lstsq(SAW[:, :-1], a, rcond=None)
+    return not (_norm(a - SAW[:, :-1] @ c) / na > rank_rtol)
+
+
+class SafetyControl:
+    """Residual control of Section 3.4: the true residual is evaluated once
+    the sketched one falls below tol / safety; a failed evaluation raises
+    safety to the observed ratio ||r|| / ||S r||."""
+
+    def __init__(self, safety: float):
+        self.safety = safety
+
+    def due(self, sres: float, tol_abs: float) -> bool:
+        return sres < tol_abs / self.safety
+
+    def failed(self, sres: float, res: float) -> None:
+        if sres > 0:
+            self.safety = res / sres
+
+
 def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
               safety: float, *, breakdown_rtol=1e-14, rank_rtol=1e-12,
               counters=None, keep=None):
-    """One cycle of Algorithm 1 for A x = r0.
+    """One restart cycle of GMRES-SDR for the correction equation A x = r0.
+
+    The search space is [U, V_j]: the recycle block and the truncated Arnoldi
+    basis of K_j(A, r0), grown one vector at a time (arnoldi_extend).  After
+    each step the sketched least-squares problem over it is solved
+    (sketched_least_squares); the residual control of Section 3.4 decides
+    when the true residual is evaluated, and the cycle stops on convergence,
+    at j = m, at an Arnoldi breakdown or when the sketched basis loses rank.
+    Finally the recycle triple is compressed by harmonic_ritz_update.
 
     Returns (xt, rt, res, new_recycle, record, safety).  If ``keep`` is a
     dict it receives the cycle's V, H, SV, SAV, y and G for inspection.
@@ -164,8 +257,7 @@ def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
         cnt[key] = cnt.get(key, 0) + v
 
     U, SU, SAU = rec.U, rec.SU, rec.SAU
-    khat = U.shape[1]
-    # sketch of the initial residual; basis and sketched basis (Alg. 1)
+    # the cycle starts from v_1 = r0 / ||r0|| and its sketch S r0 / ||r0||
     Sr = S @ r0
     bump("sketches")
     beta = _norm(r0)
@@ -176,6 +268,7 @@ def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
     SV = np.zeros((s, m + 1), dtype=dt)
     SV[:, 0] = Sr / beta
     SAV = np.zeros((s, m), dtype=dt)
+    control = SafetyControl(safety)
 
     rec_out = CycleRecord(0, np.inf, np.inf, False, False, False, 0, 0)
     xt = None
@@ -183,72 +276,38 @@ def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
     res = np.inf
     j_stop = m
     for j in range(1, m + 1):
-        # --- truncated Arnoldi (MGS against the t most recent vectors) ---
-        w = A @ V[:, j - 1]
-        bump("matvecs")
-        norm_Av = _norm(w)
-        for i in range(max(j - t + 1, 1), j + 1):
-            H[i - 1, j - 1] = np.vdot(V[:, i - 1], w)
-            bump("inner_products")
-            w = w - V[:, i - 1] * H[i - 1, j - 1]
-        hn = _norm(w)
-        bump("inner_products")
-        breakdown = not (hn > breakdown_rtol * norm_Av)
-        if not breakdown:
-            H[j, j - 1] = hn
-            V[:, j] = w / hn
-            SV[:, j] = S @ V[:, j]  # one sketch per iteration
-            bump("sketches")
-            # sketch of A v_j from the Arnoldi relation, no extra sketch
-            SAV[:, j - 1] = SV[:, : j + 1] @ H[: j + 1, j - 1]
-        else:
-            H[j, j - 1] = 0.0
-            SAV[:, j - 1] = SV[:, :j] @ H[:j, j - 1]
+        breakdown = arnoldi_extend(A, V, H, j, t, breakdown_rtol, bump)
+        sketch_extend(S, V, H, SV, SAV, j, breakdown, bump)
         bump("iters")
         SAW = np.concatenate([SAU, SAV[:, :j]], axis=1)
-        # --- sketched least squares (minimum-norm solution) ---
-        y, *_ = np.linalg.lstsq(SAW, Sr, rcond=None)
-        sres = _norm(Sr - SAW @ y)
+        y, sres = sketched_least_squares(SAW, Sr)
         rec_out.sres_hist.append(sres)
-        # rank test of the appended column against the previous ones
-        a = SAW[:, -1]
-        Pm = SAW[:, :-1]
-        na = _norm(a)
-        if Pm.shape[1] > 0 and na > 0:
-            c, *_ = np.linalg.lstsq(Pm, a, rcond=None)
-            dist = _norm(a - Pm @ c) / na
-        else:
-            dist = 1.0 if na > 0 else 0.0
-        rank_loss = not (dist > rank_rtol)
-        # --- residual control (Section 3.4) ---
-        if sres < tol_abs / safety or j == m or breakdown or rank_loss:
-            Wb = np.concatenate([U, V[:, :j]], axis=1)
-            xt = Wb @ y
-            rt = r0 - A @ xt
-            bump("matvecs")
-            res = _norm(rt)
-            bump("inner_products")
-            bump("res_checks")
-            rec_out.checks.append(Check(j, sres, res, safety))
-            if res < tol_abs:
-                rec_out.converged = True
-                j_stop = j
-                break
-            if breakdown or rank_loss:
-                j_stop = j
-                break
-            if sres > 0:
-                safety = res / sres
-            if j == m:
-                j_stop = j
-                break
+        rank_loss = newest_column_dependent(SAW, rank_rtol)
+        if not (control.due(sres, tol_abs) or j == m or breakdown or rank_loss):
+            continue
+        # true residual of the iterate from the search space
+        xt = np.concatenate([U, V[:, :j]], axis=1) @ y
+        rt = r0 - A @ xt
+        bump("matvecs")
+        res = _norm(rt)
+        bump("inner_products")
+        bump("res_checks")
+        rec_out.checks.append(Check(j, sres, res, control.safety))
+        j_stop = j
+        if res < tol_abs:
+            rec_out.converged = True
+            break
+        if breakdown or rank_loss:
+            break
+        control.failed(sres, res)
     rec_out.j_stop = j_stop
     rec_out.sres = rec_out.sres_hist[-1]
     rec_out.res = res
     rec_out.breakdown = bool(breakdown)
     rec_out.rank_loss = bool(rank_loss)
 
-    # --- harmonic-Ritz update of the recycle space (always) ---
+    # compression of the search space into the next recycle triple, also
+    # after convergence (a sequence reuses it)
     j = j_stop
     SAW = np.concatenate([SAU, SAV[:, :j]], axis=1)
     SB = np.concatenate([SU, SV[:, :j]], axis=1)
@@ -260,7 +319,7 @@ def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
         keep.update(V=V[:, : j + 1], H=H[: j + 1, :j], SV=SV[:, : j + 1],
                     SAV=SAV[:, :j], y=y, G=G, Sr=Sr, j=j, xt=xt,
                     U_in=U, SU_in=SU, SAU_in=SAU)
-    return xt, rt, res, new, rec_out, safety
+    return xt, rt, res, new, rec_out, control.safety
 
 
 def sdr_solve(A, b, *, x0=None, m: int, k: int, t: int, s: int, zeta: int = 8,

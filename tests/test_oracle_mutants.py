@@ -20,8 +20,7 @@ SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 MUTANTS = {
     "window_one_short": ("range(max(j - t + 1, 1), j + 1)", "range(max(j - t + 2, 1), j + 1)"),
     "no_conjugate": ("np.vdot(V[:, i - 1], w)", "np.dot(V[:, i - 1], w)"),
-    "sav_drops_subdiagonal": ("SAV[:, j - 1] = SV[:, : j + 1] @ H[: j + 1, j - 1]",
-                              "SAV[:, j - 1] = SV[:, :j] @ H[:j, j - 1]"),
+    "sav_drops_subdiagonal": ("nc = j if breakdown else j + 1", "nc = j"),
     "smallest_mu_selected": ('order = np.argsort(-mod, kind="stable")',
                              'order = np.argsort(mod, kind="stable")'),
     "residual_sign": ("rt = r0 - A @ xt", "rt = r0 + A @ xt"),
@@ -29,8 +28,7 @@ MUTANTS = {
                     "new = Recycle(Wb @ G, SAW @ G, SAW @ G)"),
     "m_without_conjugate": ("M = Uh.conj().T @ SB @ Vh", "M = Uh.T @ SB @ Vh"),
     "safety_inverted": ("safety = res / sres", "safety = sres / res"),
-    "sketch_not_of_new_vector": ("SV[:, j] = S @ V[:, j]  # one sketch per iteration",
-                                 "SV[:, j] = S @ V[:, j - 1]"),
+    "sketch_not_of_new_vector": ("SV[:, j] = S @ V[:, j]\n", "SV[:, j] = S @ V[:, j - 1]\n"),
 }
 
 PINS = [

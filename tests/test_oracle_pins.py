@@ -92,7 +92,8 @@ def test_inner_product_count_is_t_plus_one_per_step():
 
 def test_sketch_of_Av_from_arnoldi_relation():
     """SAV(:, j) = SV(:, 1:j+1) H(1:j+1, j) equals the explicit sketch S (A v_j)
-    (Algorithm 1, one sketch per iteration)."""
+    (Section 3: each basis vector is sketched once, and S A v_j follows from
+    the Arnoldi relation)."""
     A = _small_cd(14)
     N = A.shape[0]
     b = randn(N, 2)
