@@ -21,19 +21,25 @@ import torch
 class SDRSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, values, b, solver, tol=1e-10, adj_tol=None):
-        solver.update_matrix(values.detach())
+        vals = values.detach().contiguous()
+        solver.update_matrix(vals)
         x, st = solver.solve(b.detach().contiguous(), tol=tol)
         if not st["converged"]:
             raise RuntimeError(f"forward GMRES-SDR solve did not converge: {st}")
         ctx.solver = solver
+        ctx.generation = solver.generation
         ctx.adj_tol = tol if adj_tol is None else adj_tol
         ctx.forward_stats = st
-        ctx.save_for_backward(x)
+        ctx.save_for_backward(x, vals)
         return x
 
     @staticmethod
     def backward(ctx, gx):
-        (x,) = ctx.saved_tensors
+        x, vals = ctx.saved_tensors
+        if ctx.solver.generation != ctx.generation:
+            # the shared solver was given another matrix since this node's
+            # forward (a second forward before backward): restore this one's
+            ctx.solver.update_matrix(vals)
         lam, st = ctx.solver.solve_adjoint(gx.contiguous(), tol=ctx.adj_tol)
         if not st["converged"]:
             raise RuntimeError(f"adjoint GMRES-SDR solve did not converge: {st}")

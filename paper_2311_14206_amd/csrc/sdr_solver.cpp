@@ -1549,10 +1549,13 @@ int sdr_update_matrix(sdr_handle* h, const sdr_csr* A) {
     order_after_caller(h);
     HIPCHK(hipMemcpyAsync(h->vals, A->values, h->elem() * h->nnz, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    refresh_adjoint_values(h);
-    if (h->fwd) refresh_precond(h);
+    // Both solvers learn of the new values before the preconditioner is
+    // refreshed: a rejected preconditioner (zero diagonal) throws, and the
+    // adjoint solve, which uses A itself, must still see the new matrix.
     if (h->fwd) h->fwd->matrix_changed();
     if (h->adj) h->adj->matrix_changed();
+    refresh_adjoint_values(h);
+    if (h->fwd) refresh_precond(h);
     return SDR_OK;
   } catch (HipError& e) {
     return e.code;

@@ -141,6 +141,7 @@ class SDRSolver:
             raise SDRError("sdr_create: " + lib().sdr_last_error().decode())
         self.h = C.c_void_p(h)
         self.m, self.k, self.t, self.s = m, k, t, s
+        self.generation = 0  # counts update_matrix calls (autograd checks it)
         for key, v in options.items():
             _check(lib().sdr_set_option(self.h, key.encode(), float(v)), f"option {key}")
 
@@ -184,6 +185,7 @@ class SDRSolver:
         _check(lib().sdr_update_matrix(self.h, C.byref(_csr(self.row_ptr, self.col_idx, values))),
                "sdr_update_matrix")
         self.values = values
+        self.generation += 1
 
     def solve_adjoint(self, g, tol=1e-8):
         self._vec(g)

@@ -113,3 +113,25 @@ def test_gradient_descent_recycles_adjoint_space():
         losses.append(float(loss))
     print("losses", losses, "adjoint iters", adj_iters)
     assert all(b < a for a, b in zip(losses[:-1], losses[1:]))
+
+
+def test_two_forwards_before_backward_use_their_own_matrices():
+    """Two losses built on one shared solver with different theta: each
+    backward differentiates its own forward's matrix (the node restores it
+    when another forward changed the solver's matrix in between)."""
+    from paper_2311_14206_amd.autograd import sdr_solve
+    A0, theta, xt, b, solver = _setup(24)
+    theta2 = theta * (1.0 + 0.05 * randn(A0.nnz, 31))
+    a0 = torch.from_numpy(A0.values).to(DEV)
+    bb = torch.from_numpy(b).to(DEV)
+    xtd = torch.from_numpy(xt).to(DEV)
+    th1 = torch.from_numpy(theta).to(DEV).requires_grad_(True)
+    th2 = torch.from_numpy(theta2).to(DEV).requires_grad_(True)
+    x1 = sdr_solve(th1 * a0, bb, solver, 1e-12, 1e-12)
+    x2 = sdr_solve(th2 * a0, bb, solver, 1e-12, 1e-12)
+    torch.sum((x1 - xtd) ** 2).backward()
+    torch.sum((x2 - xtd) ** 2).backward()
+    for th, tv in ((th1, theta), (th2, theta2)):
+        _, gref, _ = _dense_reference(A0, tv, xt, b)
+        g = th.grad.detach().cpu().numpy()
+        assert np.linalg.norm(g - gref) <= 1e-7 * np.linalg.norm(gref)

@@ -129,3 +129,35 @@ def test_spmv_and_adjoint_of_a_preconditioned_handle_use_a():
     assert sa["converged"]
     r = g - A.to_scipy().T @ gp._host(lam)
     assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(g)
+
+
+def test_adjoint_after_a_rejected_preconditioner_update_uses_the_new_matrix():
+    """A matrix with a zero diagonal entry is rejected for the preconditioned
+    forward solve, but the adjoint solve (which uses A itself) must then work
+    on that new matrix, with its recycle space's S A^T U recomputed."""
+    from paper_2311_14206_amd.sdr import SDRError
+    K = cd2d_upwind(30)
+    h = gp._solver(K, precond=1, **KW)
+    b = randn(K.n, 24)
+    g = randn(K.n, 25)
+    x, st = h.solve(gp._dev(b), tol=1e-9)
+    lam0, s0 = h.solve_adjoint(gp._dev(g), tol=1e-9)
+    assert st["converged"] and s0["converged"]
+    rows = np.repeat(np.arange(K.n), np.diff(K.row_ptr))
+    zero = K.values.copy()
+    zero[np.nonzero(K.col_idx == rows)[0][7]] = 0.0
+    with pytest.raises(SDRError, match="diagonal"):
+        h.update_matrix(gp._dev(zero))
+    Z = K.with_values(zero)
+    lam, sa = h.solve_adjoint(gp._dev(g), tol=1e-9)
+    assert sa["converged"]
+    r = g - Z.to_scipy().T @ gp._host(lam)
+    assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(g)
+    # the oracle's adjoint sequence: A^T, then the new matrix's transpose
+    # with the recycle space carried and S A^T U recomputed
+    ref0 = sdr_solve(K.to_scipy().T.tocsr(), g, tol=1e-9, **KW)
+    ref = sdr_solve(Z.to_scipy().T.tocsr(), g, recycle=ref0.recycle, new_matrix=True, tol=1e-9, **KW)
+    xg = gp._host(lam)
+    print(f"adjoint after rejected update: {sa['iters']} steps (oracle {ref.iters}), "
+          f"rel. diff {np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x):.1e}", flush=True)
+    assert np.linalg.norm(xg - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
