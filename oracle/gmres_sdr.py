@@ -71,6 +71,8 @@ class Check:
     sres: float
     res: float
     safety: float
+    est: float = float("nan")  # Givens estimate (Givens control only)
+    eps: float = float("nan")  # its eps before the check
 
 
 @dataclass
@@ -100,6 +102,8 @@ class SolveResult:
     res_checks: int = 0
     trace: list = field(default_factory=list)
     recycle: Recycle | None = None
+    eps: float = float("nan")  # fitted eps of the Givens control
+    refits: list = field(default_factory=list)  # its eps refits
 
 
 def _norm(v) -> float:
@@ -231,9 +235,116 @@ class SafetyControl:
             self.safety = res / sres
 
 
+def givens_sine(SAU, SV, H, j: int) -> float:
+    """|s_j|, the sine of the j-th Givens rotation of the QR factorisation of
+    the augmented Hessenberg matrix of Section 5.
+
+    With [SAU, SV(:, 1:j+1)] = W R (economy QR), S A [U, V_j] = W G_j where
+    G_j = R blkdiag(I, H_j): its first k columns are already triangular and
+    the rest, R22 H_j, is upper Hessenberg, so one Givens rotation per
+    Arnoldi step triangularises it.  Built here from scratch at every step.
+    """
+    kh = SAU.shape[1]
+    _, R = np.linalg.qr(np.concatenate([SAU, SV[:, : j + 1]], axis=1))
+    B = np.zeros((kh + j + 1, kh + j), dtype=R.dtype)
+    B[:kh, :kh] = np.eye(kh)
+    B[kh:, kh:] = H[: j + 1, :j]
+    G = R @ B
+    s_last = 0.0
+    for i in range(j):  # rotation i acts on rows kh+i, kh+i+1
+        c0 = kh + i
+        a, b = G[c0, c0], G[c0 + 1, c0]
+        r = np.hypot(abs(a), abs(b))
+        if r == 0.0:
+            s_last = 0.0
+            continue
+        cs = abs(a) / r
+        sn = (a / abs(a) if a != 0 else 1.0) * np.conj(b) / r
+        rows = G[c0 : c0 + 2, c0:].copy()
+        G[c0, c0:] = cs * rows[0] + sn * rows[1]
+        G[c0 + 1, c0:] = -np.conj(sn) * rows[0] + cs * rows[1]
+        s_last = abs(b) / r
+    return float(s_last)
+
+
+def givens_factor(sine: float, eps: float) -> float:
+    """Growth factor of the true-residual estimate over one step (Section 4.5,
+    the corollary to the Givens-sine theorem): ||r_j|| <= sqrt((s_j^2 +
+    2 eps (1 + c_j)) / (1 - eps^2)) ||r_{j-1}||, with c_j = sqrt(1 - s_j^2),
+    evaluated at the sketched sine (the computable one)."""
+    c = np.sqrt(max(0.0, 1.0 - sine * sine))
+    return float(np.sqrt((sine * sine + 2.0 * eps * (1.0 + c)) / (1.0 - eps * eps)))
+
+
+class GivensControl:
+    """Residual control by the Givens-rotation estimate (Sections 4.5 and 5).
+
+    The estimate starts each cycle from ||r0|| (no recycled block) or from
+    the U-only sketched residual divided by sqrt(1 - eps) (the bound eq. (3.5)
+    gives for the sketched minimiser), and is multiplied by givens_factor at
+    every step.  The true residual is evaluated once the estimate falls below
+    the tolerance.  When a true residual exceeds its estimate, eps is raised to
+    the smallest value for which the estimate, restarted from the last anchor
+    (the cycle start or the previous true residual), reaches it; the estimate
+    then restarts from the true residual.  eps persists across cycles.
+    """
+
+    def __init__(self, eps: float):
+        self.eps = float(eps)
+        self.est = np.inf
+        self.sines = []        # sines since the anchor
+        self.anchor = None     # (value, depends_on_eps) of the anchor
+        self.safety = np.nan   # (recorded with the checks)
+        self.refits = []       # (res, eps before, eps after, estimates at the bracket ends)
+
+    def start(self, beta: float, sres0: float, khat: int) -> None:
+        if khat == 0:
+            self.anchor = (beta, False)
+        else:
+            self.anchor = (sres0, True)
+        self.sines = []
+        self.est = self._estimate(self.eps)
+
+    def _estimate(self, eps: float) -> float:
+        v, scaled = self.anchor
+        e = v / np.sqrt(1.0 - eps) if scaled else v
+        for sn in self.sines:
+            e *= givens_factor(sn, eps)
+        return e
+
+    def step(self, sine: float) -> None:
+        self.sines.append(sine)
+        self.est *= givens_factor(sine, self.eps)
+
+    def due(self, sres: float, tol_abs: float) -> bool:
+        return self.est < tol_abs
+
+    def failed(self, sres: float, res: float) -> None:
+        self.checked(res)
+
+    def checked(self, res: float) -> None:
+        """A true residual res at this step: refit eps if the estimate fell
+        short of it, then restart the estimate from res."""
+        if res > self._estimate(self.eps):
+            lo, hi = self.eps, 1.0
+            for _ in range(200):  # bisection: the estimate grows with eps
+                mid = 0.5 * (lo + hi)
+                if mid <= lo or mid >= hi:
+                    break
+                if self._estimate(mid) >= res:
+                    hi = mid
+                else:
+                    lo = mid
+            self.refits.append((res, self.eps, hi, self._estimate(hi), self._estimate(lo)))
+            self.eps = hi
+        self.anchor = (res, False)
+        self.sines = []
+        self.est = res
+
+
 def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
               safety: float, *, breakdown_rtol=1e-14, rank_rtol=1e-12,
-              counters=None, keep=None):
+              counters=None, keep=None, control=None):
     """One restart cycle of GMRES-SDR for the correction equation A x = r0.
 
     The search space is [U, V_j]: the recycle block and the truncated Arnoldi
@@ -244,8 +355,10 @@ def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
     at j = m, at an Arnoldi breakdown or when the sketched basis loses rank.
     Finally the recycle triple is compressed by harmonic_ritz_update.
 
-    Returns (xt, rt, res, new_recycle, record, safety).  If ``keep`` is a
-    dict it receives the cycle's V, H, SV, SAV, y and G for inspection.
+    ``control`` is the residual control (SafetyControl(safety) when None, or
+    a GivensControl carried across cycles).  Returns (xt, rt, res,
+    new_recycle, record, safety).  If ``keep`` is a dict it receives the
+    cycle's V, H, SV, SAV, y and G for inspection.
     """
     N = r0.shape[0]
     s = S.shape[0]
@@ -268,7 +381,13 @@ def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
     SV = np.zeros((s, m + 1), dtype=dt)
     SV[:, 0] = Sr / beta
     SAV = np.zeros((s, m), dtype=dt)
-    control = SafetyControl(safety)
+    if control is None:
+        control = SafetyControl(safety)
+    givens = isinstance(control, GivensControl)
+    if givens:
+        # the sketched residual over span(U) alone, where the estimate starts
+        sres0 = sketched_least_squares(SAU, Sr)[1] if U.shape[1] > 0 else _norm(Sr)
+        control.start(beta, sres0, U.shape[1])
 
     rec_out = CycleRecord(0, np.inf, np.inf, False, False, False, 0, 0)
     xt = None
@@ -283,6 +402,8 @@ def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
         y, sres = sketched_least_squares(SAW, Sr)
         rec_out.sres_hist.append(sres)
         rank_loss = newest_column_dependent(SAW, rank_rtol)
+        if givens:
+            control.step(givens_sine(SAU, SV, H, j))
         if not (control.due(sres, tol_abs) or j == m or breakdown or rank_loss):
             continue
         # true residual of the iterate from the search space
@@ -292,7 +413,9 @@ def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
         res = _norm(rt)
         bump("inner_products")
         bump("res_checks")
-        rec_out.checks.append(Check(j, sres, res, control.safety))
+        rec_out.checks.append(Check(j, sres, res, control.safety,
+                                    control.est if givens else float("nan"),
+                                    control.eps if givens else float("nan")))
         j_stop = j
         if res < tol_abs:
             rec_out.converged = True
@@ -328,11 +451,15 @@ def sdr_solve(A, b, *, x0=None, m: int, k: int, t: int, s: int, zeta: int = 8,
               new_matrix: bool = False, variant: str = "exact",
               persist_safety: bool = False, S=None,
               breakdown_rtol: float = 1e-14, rank_rtol: float = 1e-12,
-              keep_cycles: list | None = None) -> SolveResult:
+              keep_cycles: list | None = None, resid_control: str = "safety",
+              givens_eps0: float = 0.0) -> SolveResult:
     """Restarted GMRES-SDR for A x = b (relative tolerance ``tol``).
 
     ``recycle`` carries U, SU, SAU from a previous solve; ``new_matrix`` says
     that A differs from the matrix SAU was formed with (Section 3.6).
+    ``resid_control`` "safety" (Section 3.4) or "givens" (the Givens-rotation
+    estimate of Sections 4.5 and 5 with eps fitted to the true residuals,
+    starting from ``givens_eps0``; the fitted eps is returned as ``eps``).
     """
     if A.dtype.kind == "c" or np.iscomplexobj(b):
         dt = np.complex128
@@ -365,6 +492,9 @@ def sdr_solve(A, b, *, x0=None, m: int, k: int, t: int, s: int, zeta: int = 8,
         out.recycle = recycle
         return out
     safety = safety0
+    if resid_control not in ("safety", "givens"):
+        raise ValueError("resid_control is 'safety' or 'givens'")
+    gctl = GivensControl(givens_eps0) if resid_control == "givens" else None
     converged = rn <= tol_abs
     cyc = 0
     while not converged and cyc < max_cycles:
@@ -374,7 +504,7 @@ def sdr_solve(A, b, *, x0=None, m: int, k: int, t: int, s: int, zeta: int = 8,
         xt, rt, res, recycle, rec, safety = sdr_cycle(
             A, S, r, recycle, tol_abs, m, t, k, safety,
             breakdown_rtol=breakdown_rtol, rank_rtol=rank_rtol, counters=cnt,
-            keep=keep)
+            keep=keep, control=gctl)
         if keep_cycles is not None:
             keep.update(r0=r, U=recycle.U)
             keep_cycles.append(keep)
@@ -396,6 +526,8 @@ def sdr_solve(A, b, *, x0=None, m: int, k: int, t: int, s: int, zeta: int = 8,
     out.sketches = cnt.get("sketches", 0)
     out.res_checks = cnt.get("res_checks", 0)
     out.recycle = recycle
+    out.eps = gctl.eps if gctl is not None else float("nan")
+    out.refits = gctl.refits if gctl is not None else []
     return out
 
 

@@ -104,3 +104,36 @@ def test_precond_mutant_is_caught(name, monkeypatch):
             caught = True
             break
     assert caught, f"mutant {name} passed every pin"
+
+
+# Planted mistakes in the Givens-rotation residual control, against its pins.
+GIVENS_MUTANTS = {
+    "cosine_for_sine": ("        s_last = abs(b) / r\n", "        s_last = abs(a) / r\n"),
+    "rotation_sign": ("G[c0 + 1, c0:] = -np.conj(sn) * rows[0] + cs * rows[1]",
+                      "G[c0 + 1, c0:] = np.conj(sn) * rows[0] + cs * rows[1]"),
+    "factor_without_sqrt": ("return float(np.sqrt((sine * sine + 2.0 * eps * (1.0 + c)) / (1.0 - eps * eps)))",
+                            "return float((sine * sine + 2.0 * eps * (1.0 + c)) / (1.0 - eps * eps))"),
+    "eps_not_refitted": ("            self.eps = hi\n", "            self.eps = self.eps\n"),
+    "anchor_ignores_recycled_block": ("        if khat == 0:\n            self.anchor = (beta, False)",
+                                      "        if True:\n            self.anchor = (beta, False)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GIVENS_MUTANTS))
+def test_givens_mutant_is_caught(name, monkeypatch):
+    import test_oracle_givens as gpins
+    mod = _mutant_module(*GIVENS_MUTANTS[name])
+    for attr in ("sdr_solve", "givens_sine", "givens_factor", "sketched_least_squares"):
+        monkeypatch.setattr(gpins, attr, getattr(mod, attr))
+    caught = False
+    for pin in (lambda: gpins.test_sketched_residual_is_givens_sine_times_previous(False),
+                gpins.test_identity_sketch_estimate_is_the_true_residual,
+                gpins.test_eps_refit_reaches_the_observed_residual,
+                gpins.test_givens_control_solution_matches_dense_lu,
+                gpins.test_givens_factor_special_values):
+        try:
+            pin()
+        except Exception:
+            caught = True
+            break
+    assert caught, f"mutant {name} passed every pin"
