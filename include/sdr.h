@@ -203,6 +203,31 @@ int sdr_get_recycle(sdr_handle* h, void* U, void* SU, void* SAU, int* k_out);
  * from the handle's seed. */
 int sdr_sketch(sdr_handle* h, const void* X, int ncols, void* Y);
 
+/*
+ * Allocation-free form of sdr_sketch, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Y = S X for ncols device columns X (n x ncols, ld = n) of
+ * dtype SDR_F64 or SDR_C128 (interleaved), Y s_dim x ncols (ld = s_dim): the
+ * sparse-sign operator with zeta nonzeros per column drawn from seed, the
+ * same operator and the same kernels as sdr_sketch on a handle created with
+ * that seed, s_dim and option "zeta".  No handle, no allocation: the partial
+ * sums live in a static device array of SDR_NOALLOC_SCRATCH_BYTES (16 MiB),
+ * one per GPU, held until the process ends; the array's device address is
+ * looked up on the first call on each device.
+ *   Limits: 1 <= n < 2^31, s_dim a multiple of zeta, s_dim <= 2048 (real) or
+ *   1024 (complex), and n * (s_dim + 1) * element size / 2048 within the
+ *   scratch (about n <= 17e6 at s_dim = 240 real, 5.9e6 at 360 complex);
+ *   beyond them SDR_EINVAL with a message.
+ * The work is queued on hip_stream (hipStream_t as void*, NULL = the null
+ * stream) and the call returns without waiting: Y is complete when that
+ * stream's work is.  Every call on one GPU shares that GPU's scratch: calls
+ * whose work overlaps on one GPU (other streams, other threads) race and
+ * must be ordered by the caller.  Returns 0 or a negative error code.
+ */
+#define SDR_NOALLOC_SCRATCH_BYTES (16u << 20)
+int sdr_sketch_noalloc(int64_t n, int s_dim, int zeta, uint64_t seed, sdr_dtype dtype, const void* X,
+                       int ncols, void* Y, void* hip_stream);
+
 /* y = A x with the handle's matrix (FP64 / complex128 device vectors). */
 int sdr_spmv(sdr_handle* h, const void* x, void* y);
 

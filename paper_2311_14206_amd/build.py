@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdr.so")
 
-SOURCES = ["sdr_kernels.hip", "sdr_solver.cpp", "dense.cpp"]
+SOURCES = ["sdr_kernels.hip", "sdr_solver.cpp", "dense.cpp", "sdr_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -32,15 +32,19 @@ def build(verbose: bool = True) -> str:
     objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
+    procs = []
+    for src in SOURCES:  # the sources compile in parallel
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         # host-only code: AVX2/FMA, inline complex products, vectorised dot products
         extra = ["-march=x86-64-v3", "-fcx-limited-range", "-fopenmp-simd"] if src == "dense.cpp" else []
         cmd = [hipcc, *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [cmd for cmd, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     if verbose:

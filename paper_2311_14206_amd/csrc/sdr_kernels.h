@@ -1,9 +1,14 @@
 // Launch wrappers of the GMRES-SDR device kernels (gfx950).
 #pragma once
 
+#include <string>
+
 #include "sdr_common.h"
 
 namespace sdr {
+
+// Set the thread-local message that sdr_last_error() returns.
+void set_last_error(const std::string& msg);
 
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kWaves = kBlock / 64;

@@ -1213,6 +1213,9 @@ class Solver final : public SolverBase {
 
 }  // namespace
 
+// The thread-local message of sdr_last_error, for the other C entry points.
+void sdr::set_last_error(const std::string& msg) { set_err(msg); }
+
 // ============================================================== C handle ===
 struct sdr_handle {
   int n = 0;

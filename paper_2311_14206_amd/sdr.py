@@ -60,6 +60,8 @@ EXPORTS = {
                                   C.POINTER(C.c_int)]),
     "sdr_sketch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "sdr_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sdr_sketch_noalloc": (C.c_int, [C.c_int64, C.c_int, C.c_int, C.c_uint64, C.c_int, C.c_void_p,
+                                     C.c_int, C.c_void_p, C.c_void_p]),
     "sdr_get_basis": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sdr_reset": (C.c_int, [C.c_void_p]),
     "sdr_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
@@ -275,6 +277,29 @@ class SDRSolver:
         _check(lib().sdr_get_basis(self.h, ncols, C.c_void_p(_ptr(V)), C.c_void_p(H.ctypes.data),
                                    C.c_void_p(SV.ctypes.data)), "sdr_get_basis")
         return V.T, H.T, SV.T
+
+
+def sketch_noalloc(X, s, seed=42, zeta=8):
+    """S X through the allocation-free entry point: X of shape (n,) or (n, c)
+    (float64 or complex128 CUDA), no handle.  Queued on torch's current stream;
+    the library allocates nothing (the output tensor is torch's)."""
+    if X.dtype == torch.float64:
+        dt = SDR_F64
+    elif X.dtype == torch.complex128:
+        dt = SDR_C128
+    else:
+        raise TypeError("X must be float64 or complex128")
+    if not X.is_cuda:
+        raise ValueError("X must be a CUDA tensor")
+    one = X.dim() == 1
+    n = X.shape[0]
+    Xc = X.reshape(n, -1).T.contiguous()
+    c = Xc.shape[0]
+    Y = torch.empty((c, s), dtype=X.dtype, device=X.device)
+    st = torch.cuda.current_stream(X.device).cuda_stream
+    _check(lib().sdr_sketch_noalloc(n, s, zeta, C.c_uint64(seed & (2 ** 64 - 1)), dt, C.c_void_p(_ptr(Xc)),
+                                    c, C.c_void_p(_ptr(Y)), C.c_void_p(st)), "sdr_sketch_noalloc")
+    return Y[0] if one else Y.T
 
 
 def host_harmonic_ritz(R, Cm, s, k, is_complex):

@@ -100,3 +100,21 @@ def test_host_harmonic_ritz_truncated_svd_path(cplx):
     assert ell == ello == l0 - 1
     assert keff == keffo
     assert _angle(G, Go) < 1e-7
+
+
+def test_noalloc_sketch_rejects_sizes_beyond_its_scratch():
+    """The allocation-free sketch checks its limits before touching a device."""
+    L = ctypes.CDLL(LIB)
+    f = L.sdr_sketch_noalloc
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
+                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.sdr_last_error.restype = ctypes.c_char_p
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+    assert f(1 << 28, 240, 8, 1, 0, fake, 1, fake, None) == -1
+    assert b"scratch" in L.sdr_last_error()
+    assert f(1000, 100, 8, 1, 0, fake, 1, fake, None) == -1  # s_dim not a multiple of zeta
+    assert f(1000, 4096, 8, 1, 0, fake, 1, fake, None) == -1  # s_dim beyond the LDS bins
+    assert f(1000, 2048, 8, 1, 2, fake, 1, fake, None) == -1  # complex beyond 1024
+    assert f(1000, 240, 8, 1, 1, fake, 1, fake, None) == -1  # FP32 is not a data type here
+    assert f(0, 240, 8, 1, 0, fake, 1, fake, None) == -1
