@@ -73,10 +73,10 @@ typedef struct {
   int32_t k_eff;           /* recycle dimension after the solve */
   double relres;           /* ||b - A x|| / ||b|| at exit (FP64) */
   double sres;             /* last sketched residual */
-  double safety;           /* safety factor at exit */
+  double safety;           /* safety factor at exit (0 with the Givens control) */
   double seconds;          /* wall time of the solve */
   double host_eig_seconds; /* host time in the harmonic-Ritz eigen-step */
-  double gpu_step_seconds; /* not used; 0 */
+  double eps;              /* fitted eps of the Givens residual control (0 otherwise) */
 } sdr_stats;
 
 /* Per-cycle decision record of the last solve. */
@@ -138,6 +138,20 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *                    (sdr_get_recycle, sdr_get_basis) belong to A D^-1.
  *                    sdr_spmv and the adjoint solve use A unpreconditioned.
  *                    Default 0, set before the first solve.
+ *   "resid_control"  0 (default): the safety-factor rule of Section 3.4, a
+ *                    true residual once the sketched one is below tol /
+ *                    safety; 1: the Givens-rotation estimate of Sections 4.5
+ *                    and 5: each step's sine is the ratio of consecutive
+ *                    sketched residuals, the estimate of the true residual
+ *                    grows by sqrt((s^2 + 2 eps (1 + c)) / (1 - eps^2)) from
+ *                    ||r0|| (or the sketched residual over span(U) / sqrt(1 -
+ *                    eps)), a true residual is computed once the estimate is
+ *                    below tol, and eps is raised (by bisection) to the
+ *                    smallest value whose estimate reaches a true residual
+ *                    that exceeded it; the estimate then restarts from that
+ *                    residual.  eps persists across the cycles of a solve
+ *                    (stats.eps)
+ *   "givens_eps0"    initial eps of the Givens control, in [0, 1) (default 0)
  *   "kernel_timing"  n > 0: HIP events around the SpMV and update kernels of
  *                    one Arnoldi step in n, at positions that move by 13 from
  *                    cycle to cycle (sdr_kernel_times); default 0
@@ -235,6 +249,13 @@ int sdr_spmv(sdr_handle* h, const void* x, void* y);
  * basis vectors V (n x ncols, FP64/c128 device), H ((m+1) x m host, column
  * major), SV (s x ncols host).  Any pointer may be NULL. */
 int sdr_get_basis(sdr_handle* h, int ncols, void* V, void* H_host, void* SV_host);
+
+/* Sketched residual norms ||S r0 - SAW y_j|| of the last cycle of the last
+ * solve, by Arnoldi step (the quantity Section 3.3's least squares
+ * minimises): out[0] over span(U) alone (||S r0|| without a recycled block),
+ * out[j] after step j.  Writes min(cap, count) host doubles and returns
+ * count (j_stop + 1; 0 before the first solve). */
+int sdr_get_step_sres(sdr_handle* h, double* out, int cap);
 
 /* Drop the recycle space (the next solve starts without U).  Returns 0. */
 int sdr_reset(sdr_handle* h);

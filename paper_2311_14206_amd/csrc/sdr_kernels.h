@@ -61,8 +61,21 @@ struct Ctrl {
   int32_t halt;     // != 0: step kernels return immediately
   int32_t halt_j;
   int32_t flags;
-  int32_t pad;
-  double thresh;    // tol_abs / safety
+  int32_t mode;     // residual control: 0 safety factor, 1 Givens estimate
+  double thresh;    // tol_abs / safety (mode 0), tol_abs (mode 1)
+  // Givens estimate (mode 1): eps, the running estimate of the true
+  // residual and the previous step's sketched residual (its sine is the
+  // ratio of consecutive sketched residuals).  Written by the least-squares
+  // kernels on their stream, and by the host's resume after a check.
+  double eps, est, sprev;
+};
+
+// Residual control of a cycle start, for the least-squares init: mode, eps
+// and ||r0|| (the estimate's anchor when no recycled block precedes V).
+struct GivensInit {
+  int mode;
+  double eps;
+  double beta;
 };
 
 // Small dense state of the sketched least squares (FP64 / complex128).
@@ -153,9 +166,11 @@ void launch_reduce_steps(hipStream_t st, const A* part1, int64_t slot1, int nb1,
                          int t, int nslot, double scl, A* redb, int64_t slotr, const Ctrl* ctrl);
 
 // Initialise the QR of SAW with its first khat columns (SAU) and rho = S r0.
+// Also seeds the control block's residual estimate (gv.mode 1) and writes
+// the sketched residual over span(U) alone to the step record 0.
 template <class A>
 void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr,
-                     double rank_rtol, int m);
+                     double rank_rtol, int m, GivensInit gv);
 
 // y = R(0:n,0:n)^{-1} z(0:n); coefficients for [U, P]: y_i (U part), y_i / nu_i (P part).
 template <class A>
@@ -244,5 +259,9 @@ void launch_widen_scale(hipStream_t st, int n, const T* src, double scale,
                         typename traits<T>::acc* dst);
 
 void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh);
+// Resume under the Givens control: halt cleared, threshold tol, eps and the
+// estimate restarted from the true residual est at the step whose sketched
+// residual is sprev.
+void launch_set_ctrl_givens(hipStream_t st, Ctrl* c, double thresh, double eps, double est, double sprev);
 
 }  // namespace sdr

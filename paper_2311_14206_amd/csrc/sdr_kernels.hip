@@ -727,6 +727,46 @@ __device__ __forceinline__ void put_record(const LsqState<A>& S, int j, double s
   }
 }
 
+// Residual control of one step (one thread): the safety-factor rule of
+// Section 3.4 (sres < tol / safety), or the Givens estimate of Sections 4.5
+// and 5: the step's sine is sres / sres_prev (the sketched residual falls by
+// the Givens sine), the estimate grows by sqrt((s^2 + 2 eps (1 + c)) /
+// (1 - eps^2)), and the check is due once it is below tol.
+__device__ __forceinline__ bool control_due(Ctrl* c, double sres) {
+  if (c->mode == 0) return sres < c->thresh;
+  const double sp = c->sprev;
+  double sn = sp > 0.0 ? sres / sp : 0.0;
+  sn = sn < 1.0 ? sn : 1.0;
+  const double cs = sqrt(fmax(0.0, 1.0 - sn * sn));
+  const double e = c->eps;
+  const double est = c->est * sqrt((sn * sn + 2.0 * e * (1.0 + cs)) / (1.0 - e * e));
+  c->est = est;
+  c->sprev = sres;
+  return est < c->thresh;
+}
+
+// Cycle start of the control (one thread): sres0 is the sketched residual
+// over span(U) alone (||S r0|| without a recycled block).
+template <class A>
+__device__ __forceinline__ void control_start(const LsqState<A>& S, int khat, double sres0, GivensInit gv) {
+  Ctrl* c = S.ctrl;
+  c->mode = gv.mode;
+  if (gv.mode != 0) {
+    c->eps = gv.eps;
+    c->sprev = sres0;
+    c->est = khat == 0 ? gv.beta : sres0 / sqrt(1.0 - gv.eps);
+  }
+  S.rec[0].sres = sres0;
+}
+
+// ||rho|| over the block (red: blockDim.x / 64 doubles), valid in every thread.
+template <class A>
+__device__ double rho_norm(const A* rho, int s, double* red) {
+  double q = 0.0;
+  for (int r = threadIdx.x; r < s; r += blockDim.x) q += abs2(rho[r]);
+  return sqrt(block_sum(q, red));
+}
+
 constexpr int kLsqPrefetch = 16;  // staged elements per thread and chunk
 
 // LDS layout of the least-squares kernels: a (s), acc (s), c (2 Lmax), then
@@ -1071,7 +1111,8 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step_reg(LsqState<A> S, int j
     int flags = 0;
     if (brk) flags |= 2;
     if (loss) flags |= 4;
-    const bool halt = sres < S.ctrl->thresh || j == m || brk || loss;
+    const bool due = control_due(S.ctrl, sres);  // (updates the estimate: always evaluated)
+    const bool halt = due || j == m || brk || loss;
     if (halt) flags |= 1;
     S.sres_hist[j] = sres;
     if (halt) {
@@ -1191,7 +1232,8 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_steps_reg(LsqState<A> S, int 
         int flags = 0;
         if (brk) flags |= 2;
         if (loss) flags |= 4;
-        const bool halt = sres < S.ctrl->thresh || j == m || brk || loss;
+        const bool due = control_due(S.ctrl, sres);  // (updates the estimate: always evaluated)
+    const bool halt = due || j == m || brk || loss;
         if (halt) flags |= 1;
         S.sres_hist[j] = sres;
         if (halt) {
@@ -1217,7 +1259,8 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_steps_reg(LsqState<A> S, int 
 
 template <class A, int RL, int CW>
 __global__ __launch_bounds__(kLsqBlock) void k_lsq_init_reg(LsqState<A> S, int khat, int s,
-                                                            const A* __restrict__ Sr, double rank_rtol) {
+                                                            const A* __restrict__ Sr, double rank_rtol,
+                                                            GivensInit gv) {
   __shared__ A lds_red[kRegWaves * 64 * RL];
   __shared__ double scr_all[kRegWaves * 16 * (CW * ncomp<A>::v + 1)];
   __shared__ double sh_res;
@@ -1249,7 +1292,11 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_init_reg(LsqState<A> S, int k
     }
     sres = regq_residual<A, RL>(a, S.rho, S.z + c, loss, s, &sh_res);
   }
-  if (threadIdx.x == 0) S.sres_hist[0] = sres;
+  if (khat == 0) sres = rho_norm(S.rho, s, (double*)lds_red);
+  if (threadIdx.x == 0) {
+    S.sres_hist[0] = sres;
+    control_start(S, khat, sres, gv);
+  }
 }
 
 // register shapes: rows per lane RL and columns per wave CW
@@ -1326,7 +1373,8 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_step(LsqState<A> S, int j, in
     int flags = 0;
     if (brk) flags |= 2;
     if (loss) flags |= 4;
-    const bool halt = sres < S.ctrl->thresh || j == m || brk || loss;
+    const bool due = control_due(S.ctrl, sres);  // (updates the estimate: always evaluated)
+    const bool halt = due || j == m || brk || loss;
     if (halt) flags |= 1;
     S.sres_hist[j] = sres;
     if (halt) {
@@ -1397,7 +1445,8 @@ void launch_lsq_steps(hipStream_t st, LsqState<A> S, int j0, int j1, int khat, i
 
 template <class A>
 __global__ __launch_bounds__(kLsqBlock) void k_lsq_init(LsqState<A> S, int khat, int s,
-                                                        const A* __restrict__ Sr, double rank_rtol) {
+                                                        const A* __restrict__ Sr, double rank_rtol,
+                                                        GivensInit gv) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lmax = khat + 1;
   const int ch = lsq_chunk<A>(s, lmax);
@@ -1415,23 +1464,27 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_init(LsqState<A> S, int khat,
     bool loss = false;
     sres = qr_append(S, a, accb, cbuf, qs, ch, red, c, s, rank_rtol, &loss);
   }
-  if (threadIdx.x == 0) S.sres_hist[0] = sres;
+  if (khat == 0) sres = rho_norm(S.rho, s, (double*)red);
+  if (threadIdx.x == 0) {
+    S.sres_hist[0] = sres;
+    control_start(S, khat, sres, gv);
+  }
 }
 
 template <class A>
 void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr, double rank_rtol,
-                     int m) {
+                     int m, GivensInit gv) {
   int rl = 0, cw = 0;
   // the same register shape as the step kernel of this cycle
   if (lsq_reg_shape<A>(s, khat + m + 1, &rl, &cw)) {
-    SDR_LSQ_REG_CASE(2, 8, k_lsq_init_reg, S, khat, s, Sr, rank_rtol)
-    SDR_LSQ_REG_CASE(2, 16, k_lsq_init_reg, S, khat, s, Sr, rank_rtol)
-    SDR_LSQ_REG_CASE(4, 16, k_lsq_init_reg, S, khat, s, Sr, rank_rtol)
-    SDR_LSQ_REG_CASE(4, 8, k_lsq_init_reg, S, khat, s, Sr, rank_rtol)
+    SDR_LSQ_REG_CASE(2, 8, k_lsq_init_reg, S, khat, s, Sr, rank_rtol, gv)
+    SDR_LSQ_REG_CASE(2, 16, k_lsq_init_reg, S, khat, s, Sr, rank_rtol, gv)
+    SDR_LSQ_REG_CASE(4, 16, k_lsq_init_reg, S, khat, s, Sr, rank_rtol, gv)
+    SDR_LSQ_REG_CASE(4, 8, k_lsq_init_reg, S, khat, s, Sr, rank_rtol, gv)
   }
   const int lmax = khat + 1;
   const size_t lds = (size_t)(2 * s + 2 * lmax + lsq_chunk<A>(s, lmax) * s) * sizeof(A);
-  hipLaunchKernelGGL(k_lsq_init<A>, dim3(1), dim3(kLsqBlock), lds, st, S, khat, s, Sr, rank_rtol);
+  hipLaunchKernelGGL(k_lsq_init<A>, dim3(1), dim3(kLsqBlock), lds, st, S, khat, s, Sr, rank_rtol, gv);
 }
 
 // R y = z by columns (back substitution), then the basis coefficients.
@@ -2032,6 +2085,21 @@ void launch_set_ctrl(hipStream_t st, Ctrl* c, int halt, double thresh) {
   hipLaunchKernelGGL(k_set_ctrl, dim3(1), dim3(64), 0, st, c, halt, thresh);
 }
 
+__global__ void k_set_ctrl_givens(Ctrl* c, double thresh, double eps, double est, double sprev) {
+  if (threadIdx.x == 0) {
+    c->halt = 0;
+    c->halt_j = 0;
+    c->flags = 0;
+    c->thresh = thresh;
+    c->eps = eps;
+    c->est = est;
+    c->sprev = sprev;
+  }
+}
+void launch_set_ctrl_givens(hipStream_t st, Ctrl* c, double thresh, double eps, double est, double sprev) {
+  hipLaunchKernelGGL(k_set_ctrl_givens, dim3(1), dim3(64), 0, st, c, thresh, eps, est, sprev);
+}
+
 // ------------------------------------------- right Jacobi preconditioning ---
 // A D^-1 with D = diag(A): d from each row's stored diagonal entry (zero if
 // the row stores none, which sets *flag), the column-scaled values
@@ -2119,7 +2187,7 @@ SDR_INST_BASIS(cx<float>)
   template void launch_reduce2<A>(hipStream_t, const A*, int, int, int, double, const A*, int,  \
                                   int, A*, const Ctrl*);                                        \
   template void launch_init_v0<A>(hipStream_t, const A*, int, A*, double*);                     \
-  template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double, int);  \
+  template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double, int, GivensInit); \
   template void launch_lsq_steps<A>(hipStream_t, LsqState<A>, int, int, int, int, int, int,      \
                                     const A*, int64_t, int, double, double);                     \
   template void launch_reduce_steps<A>(hipStream_t, const A*, int64_t, int, int, int, int, int,  \

@@ -91,6 +91,8 @@ struct Options {
   int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
   int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
   int precond = 0;        // 0: none; 1: right Jacobi, the forward solve runs on A D^-1
+  int resid_control = 0;  // 0: safety factor (Section 3.4); 1: Givens estimate (Sections 4.5, 5)
+  double givens_eps0 = 0.0;  // initial eps of the Givens estimate
 };
 
 // Diagonal layout of a CSR pattern: the distinct offsets column - row (at
@@ -152,8 +154,10 @@ struct SolverBase {
   virtual void matrix_changed() = 0;
   virtual int get_recycle(void* U, void* SU, void* SAU, int* k) = 0;
   virtual int get_basis(int ncols, void* V, void* H, void* SV) = 0;
+  virtual int step_sres(double* out, int cap) = 0;
   virtual int sketch(const void* X, int ncols, void* Y) = 0;
   virtual void set_stream(hipStream_t s) = 0;
+  virtual void set_options(const Options& o) = 0;
   virtual void reset() = 0;
   virtual int kernel_times(double* ms, int64_t* counts, int cap) = 0;
   virtual int spmv_layout(int* offsets, int cap) = 0;
@@ -291,6 +295,16 @@ class Solver final : public SolverBase {
   ~Solver() override { release(); }
 
   void set_stream(hipStream_t s) override { stream_ = s; }
+
+  // Options that may change between solves (the others are refused once the
+  // solver exists).
+  void set_options(const Options& o) override {
+    opt_.max_cycles = o.max_cycles;
+    opt_.safety0 = o.safety0;
+    opt_.persist_safety = o.persist_safety;
+    opt_.resid_control = o.resid_control;
+    opt_.givens_eps0 = o.givens_eps0;
+  }
 
   void set_matrix(MatView<A> mat) { M_ = mat; }
 
@@ -612,6 +626,41 @@ class Solver final : public SolverBase {
            std::to_string(bad(xt)) + "/" + std::to_string(n_) + ", k_hat " + std::to_string(khat_);
   }
 
+  // Givens estimate of the true residual at step j (Sections 4.5 and 5),
+  // rebuilt on the host from the anchor (the value at step a, divided by
+  // sqrt(1 - eps) when it is a sketched residual) and the sketched residuals
+  // of steps a .. j in the step records: the same operations in the same
+  // order as the least-squares kernels' running estimate.
+  double givens_estimate(double eps, double anchor, bool scaled, int a, int j) const {
+    double e = scaled ? anchor / std::sqrt(1.0 - eps) : anchor;
+    double sp = rec_host_[a].sres;
+    for (int i = a + 1; i <= j; ++i) {
+      const double sr = rec_host_[i].sres;
+      double sn = sp > 0.0 ? sr / sp : 0.0;
+      sn = sn < 1.0 ? sn : 1.0;
+      const double cs = std::sqrt(std::max(0.0, 1.0 - sn * sn));
+      e *= std::sqrt((sn * sn + 2.0 * eps * (1.0 + cs)) / (1.0 - eps * eps));
+      sp = sr;
+    }
+    return e;
+  }
+
+  // A true residual res at step j: raise eps to the smallest value (by
+  // bisection) whose estimate from the anchor reaches res, if it fell short.
+  double givens_refit(double eps, double anchor, bool scaled, int a, int j, double res) const {
+    if (!(res > givens_estimate(eps, anchor, scaled, a, j))) return eps;
+    double lo = eps, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (givens_estimate(mid, anchor, scaled, a, j) >= res)
+        hi = mid;
+      else
+        lo = mid;
+    }
+    return hi;
+  }
+
   // Residual check after step j: x~ = [U P] y and r_new = r0 - A x~, queued on
   // stream A (finish_residual() returns ||r_new||).
   void enqueue_check(int j) {
@@ -671,6 +720,11 @@ class Solver final : public SolverBase {
     }
     sau_stale_ = false;
     double safety = opt_.safety0;
+    // Givens control: eps persists across the cycles of a solve; the
+    // threshold is tol itself
+    const bool givens = opt_.resid_control == 1;
+    double geps = opt_.givens_eps0;
+    auto thresh_of = [&](double sf) { return givens ? tol_abs : tol_abs / sf; };
     bool converged = rn <= tol_abs;
     double last_sres = 0.0;
     int status = SDR_NOT_CONVERGED;
@@ -680,7 +734,7 @@ class Solver final : public SolverBase {
     while (!converged && cycles < opt_.max_cycles) {
       if (!opt_.persist_safety) safety = opt_.safety0;
       sdr_cycle_record rec{};
-      if (!started) start_cycle(r_, rn, tol_abs / safety, vals);
+      if (!started) start_cycle(r_, rn, thresh_of(safety), vals);
       started = false;
       const int cyc_par = cycle_par_;
       sketches++;
@@ -702,8 +756,15 @@ class Solver final : public SolverBase {
         HIPCHK(hipMemcpyAsync(SAW_ + (size_t)(kmax_ - khat_) * s_, SAU_, sizeof(A) * s_ * khat_,
                               hipMemcpyDeviceToDevice, streamB_));
       }
-      launch_lsq_init<A>(streamB_, lsq(), khat_, s_, Sr_, opt_.rank_rtol, m_);
+      launch_lsq_init<A>(streamB_, lsq(), khat_, s_, Sr_, opt_.rank_rtol, m_,
+                         GivensInit{givens ? 1 : 0, geps, rn});
       LAUNCHCHK();
+      // anchor of the Givens estimate: ||r0||, or the sketched residual over
+      // span(U) (step record 0) divided by sqrt(1 - eps)
+      const bool g_scaled0 = khat_ > 0;
+      double g_anchor = rn;
+      bool g_scaled = g_scaled0;
+      int g_a = 0;
       // --- truncated Arnoldi with sketched least squares ---
       int done = 0, jstop = 0, flags_stop = 0;
       bool early = false;
@@ -749,7 +810,7 @@ class Solver final : public SolverBase {
               launch_axpy<A>(stream_, n_, from_cd<A>({1.0, 0.0}), xt_, x);
               LAUNCHCHK();
               cur_ ^= 1;
-              start_cycle(rnew_, -1.0, tol_abs / opt_.safety0, vals);
+              start_cycle(rnew_, -1.0, thresh_of(opt_.safety0), vals);
               cur_ ^= 1;
               started = true;
             }
@@ -774,13 +835,24 @@ class Solver final : public SolverBase {
             flags_stop = rc.flags & 6;
             break;
           }
-          if (sres > 0.0) safety = res / sres;
+          if (givens) {
+            if (g_a == 0 && g_scaled) g_anchor = rec_host_[0].sres;  // (written by this cycle's init)
+            geps = givens_refit(geps, g_anchor, g_scaled, g_a, done, res);
+            g_anchor = res;
+            g_scaled = false;
+            g_a = done;
+          } else if (sres > 0.0) {
+            safety = res / sres;
+          }
           if (done == m_) {
             jstop = done;
             break;
           }
           // resume: the steps after `done` may have been skipped by the halt
-          launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
+          if (givens)
+            launch_set_ctrl_givens(stream_, ctrl_, tol_abs, geps, res, rec_host_[done].sres);
+          else
+            launch_set_ctrl(stream_, ctrl_, 0, tol_abs / safety);
           LAUNCHCHK();
           __atomic_store_n(&halt_host_->seq, -1, __ATOMIC_RELEASE);
           enqA = done;
@@ -802,6 +874,10 @@ class Solver final : public SolverBase {
       rn = res;
       rec.j_stop = jstop;
       rec.flags = (cyc_conv ? 1 : 0) | flags_stop;
+      // the cycle's sketched residuals by step (records 0 .. jstop are
+      // complete: stream B was synchronised after the last halt)
+      step_sres_.assign(jstop + 1, 0.0);
+      for (int i = 0; i <= jstop; ++i) step_sres_[i] = rec_host_[i].sres;
       rec.sres = sres;
       rec.res = res;
       trace->push_back(rec);
@@ -821,7 +897,8 @@ class Solver final : public SolverBase {
     drain_timing();
     status = converged ? SDR_OK : SDR_NOT_CONVERGED;
     fill_stats(st, cycles, iters, matvecs, ips, sketches, checks, status, rn / nb, last_sres,
-               safety, now() - t0, eig_time);
+               givens ? 0.0 : safety, now() - t0, eig_time);
+    if (st) st->eps = givens ? geps : 0.0;
     return status;
   }
 
@@ -1043,6 +1120,13 @@ class Solver final : public SolverBase {
     return SDR_OK;
   }
 
+  int step_sres(double* out, int cap) override {
+    const int n = (int)step_sres_.size();
+    if (out)
+      for (int i = 0; i < std::min(n, cap); ++i) out[i] = step_sres_[i];
+    return n;
+  }
+
   int get_basis(int ncols, void* V, void* Hh, void* SVh) override {
     if (ncols < 0 || ncols > m_ + 1) {
       set_err("ncols out of range");
@@ -1120,6 +1204,7 @@ class Solver final : public SolverBase {
   MatView<A> M_;
   int n_ = 0, m_, k_, t_, s_;
   Options opt_;
+  std::vector<double> step_sres_;  // sketched residual by step of the last cycle (0: over span(U))
   hipStream_t stream_;
   SketchSpec sk_{};
   double brtol_ = 1e-14;
@@ -1507,6 +1592,12 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
   } else if (k == "precond") {
     if (built || (v != 0.0 && v != 1.0)) return set_err("precond is 0 or 1, before the first solve"), SDR_EINVAL;
     h->opt.precond = (int)v;
+  } else if (k == "resid_control") {
+    if (v != 0.0 && v != 1.0) return set_err("resid_control is 0 (safety) or 1 (Givens)"), SDR_EINVAL;
+    h->opt.resid_control = (int)v;
+  } else if (k == "givens_eps0") {
+    if (!(v >= 0.0 && v < 1.0)) return set_err("givens_eps0 in [0, 1)"), SDR_EINVAL;
+    h->opt.givens_eps0 = v;
   } else if (k == "lsq_chunk") {
     if (built || v < 1 || v > 64) return set_err("lsq_chunk in [1,64], before the first solve"), SDR_EINVAL;
     h->opt.lsq_chunk = (int)v;
@@ -1514,6 +1605,8 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
     set_err("unknown option " + k);
     return SDR_EINVAL;
   }
+  if (h->fwd) h->fwd->set_options(h->opt);
+  if (h->adj) h->adj->set_options(h->opt);
   return SDR_OK;
 }
 
@@ -1695,6 +1788,12 @@ int sdr_get_basis(sdr_handle* h, int ncols, void* V, void* H, void* SV) {
   } catch (HipError& e) {
     return e.code;
   }
+}
+
+int sdr_get_step_sres(sdr_handle* h, double* out, int cap) {
+  if (!h || cap < 0) return set_err("null handle or cap < 0"), SDR_EINVAL;
+  if (!h->fwd) return 0;
+  return h->fwd->step_sres(out, cap);
 }
 
 int sdr_reset(sdr_handle* h) {

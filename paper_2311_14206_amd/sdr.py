@@ -33,7 +33,7 @@ class sdr_stats(C.Structure):
                 ("res_checks", C.c_int32), ("status", C.c_int32), ("k_eff", C.c_int32),
                 ("relres", C.c_double), ("sres", C.c_double), ("safety", C.c_double),
                 ("seconds", C.c_double), ("host_eig_seconds", C.c_double),
-                ("gpu_step_seconds", C.c_double)]
+                ("eps", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -64,6 +64,7 @@ EXPORTS = {
                                      C.c_int, C.c_void_p, C.c_void_p]),
     "sdr_get_basis": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sdr_reset": (C.c_int, [C.c_void_p]),
+    "sdr_get_step_sres": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int]),
     "sdr_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
     "sdr_spmv_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int]),
     "sdr_destroy": (None, [C.c_void_p]),
@@ -234,6 +235,13 @@ class SDRSolver:
         lib().sdr_get_trace(self.h, buf, n)
         return [{f: getattr(buf[i], f) for f, _ in sdr_cycle_record._fields_ if f != "pad"}
                 for i in range(n)]
+
+    def step_sres(self):
+        """Sketched residual by Arnoldi step of the last cycle ([0]: over span(U))."""
+        n = _check(lib().sdr_get_step_sres(self.h, None, 0), "sdr_get_step_sres")
+        buf = (C.c_double * max(n, 1))()
+        lib().sdr_get_step_sres(self.h, buf, n)
+        return [buf[i] for i in range(n)]
 
     def recycle(self):
         k = C.c_int(0)

@@ -106,6 +106,15 @@ def _compare_solve(A: CSR, b, params, tol, x0=None, max_cycles=10000, extra=None
 def _assert_trace_and_x(xg, st, tr, ref, tol_x=1e-8, strict=True, A=None, b=None, tol=None):
     """Decision traces must match cycle by cycle; then x agrees to tol_x.
 
+    Per cycle the stop index, the number of true-residual checks, k_eff and
+    the breakdown / rank-loss flags must be the oracle's, and the sketched
+    and true residual norms at the stop must agree to 1e-10 relative above a
+    floor of 1e-13 ||b|| (the rounding of a residual recomputed in FP64).
+    Past that, the two runs are several correct results (the rounding of the
+    two paths grows from cycle to cycle): the first such cycle is reported
+    and both solutions must meet the tolerance, while x is still held to
+    tol_x while the decisions agree.
+
     A stop index is a threshold decision: with an ill-conditioned sketched
     least-squares matrix the two implementations may legitimately take a near
     decision differently.  With strict=False such a divergence is reported and
@@ -114,6 +123,7 @@ def _assert_trace_and_x(xg, st, tr, ref, tol_x=1e-8, strict=True, A=None, b=None
     jg = [c["j_stop"] for c in tr]
     print("oracle j_stop", jo, "gpu", jg, flush=True)
     div = None
+    dsres, dres = [], []
     for i, (cg, co) in enumerate(zip(tr, ref.trace)):
         same = (cg["j_stop"] == co.j_stop and cg["n_checks"] == len(co.checks)
                 and cg["k_eff"] == co.k_eff
@@ -121,22 +131,40 @@ def _assert_trace_and_x(xg, st, tr, ref, tol_x=1e-8, strict=True, A=None, b=None
         if not same:
             div = i
             break
-        floor = 1e-13 * (np.linalg.norm(b) if b is not None else 0.0)
-        assert abs(cg["res"] - co.res) <= 1e-6 * co.res + floor, i
+        dsres.append(abs(cg["sres"] - co.sres))
+        dres.append(abs(cg["res"] - co.res))
+    floor = 1e-13 * np.linalg.norm(b)
+    val_div = None
+    for i, (ds, dr, co) in enumerate(zip(dsres, dres, ref.trace)):
+        if ds > 1e-10 * co.sres + floor or dr > 1e-10 * co.res + floor:
+            val_div = i
+            break
+    print("per-cycle rel. diff sres", ["%.1e" % (d / max(c.sres, 1e-300)) for d, c in zip(dsres, ref.trace)],
+          flush=True)
+    print("per-cycle rel. diff res ", ["%.1e" % (d / max(c.res, 1e-300)) for d, c in zip(dres, ref.trace)],
+          flush=True)
     if div is None and len(jg) != len(jo):
         div = min(len(jg), len(jo))
+    As = (A.to_scipy() if A is not None else None)
     if div is not None:
         print(f"decision traces diverge at cycle {div}", flush=True)
         assert not strict, f"traces diverge at cycle {div}: gpu {jg} oracle {jo}"
         assert st["converged"] and ref.converged
         nb = np.linalg.norm(b)
-        As = A.to_scipy()
         assert np.linalg.norm(b - As @ xg) <= tol * nb
         assert np.linalg.norm(b - As @ ref.x) <= tol * nb
         return
+    if val_div is not None:
+        print(f"residual norms differ beyond 1e-10 (+ 1e-13 ||b||) from cycle {val_div}", flush=True)
+        if As is not None:
+            nb = np.linalg.norm(b)
+            assert st["converged"] and ref.converged
+            assert np.linalg.norm(b - As @ xg) <= tol * nb
+            assert np.linalg.norm(b - As @ ref.x) <= tol * nb
     assert st["converged"] == ref.converged
     assert st["iters"] == ref.iters and st["matvecs"] == ref.matvecs
     assert st["inner_products"] == ref.inner_products
+    print(f"x rel. error vs oracle {np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x):.1e}", flush=True)
     assert np.linalg.norm(xg - ref.x) <= tol_x * np.linalg.norm(ref.x)
 
 
@@ -146,7 +174,7 @@ def test_solve_cd2d_64_matches_oracle(dia):
     SpMV on diagonal storage (dia=1) and on CSR (dia=0)."""
     A, b, p = workload("cd2d_64")
     h, xg, st, tr, ref = _compare_solve(A, b, p, p["tol"], extra=dict(dia=dia))
-    _assert_trace_and_x(xg, st, tr, ref)
+    _assert_trace_and_x(xg, st, tr, ref, A=A, b=b, tol=p["tol"])
     r = b - A.to_scipy() @ xg
     assert np.linalg.norm(r) <= p["tol"] * np.linalg.norm(b)
 
@@ -188,7 +216,7 @@ def test_solve_general_sparse_pattern_matches_oracle():
     b = randn(A.n, 5)
     h, xg, st, tr, ref = _compare_solve(A, b, dict(m=30, k=6, t=2, s=80), 1e-9)
     assert len(ref.trace) > 2  # several cycles with a recycle space
-    _assert_trace_and_x(xg, st, tr, ref)
+    _assert_trace_and_x(xg, st, tr, ref, A=A, b=b, tol=1e-9)
     y = _host(h.spmv(_dev(b)))
     ref_y = A.to_scipy() @ b
     assert np.linalg.norm(y - ref_y) <= 1e-14 * np.linalg.norm(ref_y)
@@ -198,7 +226,7 @@ def test_solve_complex_helmholtz_matches_oracle():
     A = helmholtz2d(32, kappa=8.0)
     b = crandn(A.n, 3)
     h, xg, st, tr, ref = _compare_solve(A, b, dict(m=40, k=8, t=3, s=96), 1e-9)
-    _assert_trace_and_x(xg, st, tr, ref)
+    _assert_trace_and_x(xg, st, tr, ref, A=A, b=b, tol=1e-9)
 
 
 def test_nonzero_initial_guess_and_zero_rhs():
@@ -206,7 +234,7 @@ def test_nonzero_initial_guess_and_zero_rhs():
     b = randn(A.n, 2)
     x0 = 0.1 * randn(A.n, 3)
     h, xg, st, tr, ref = _compare_solve(A, b, dict(m=30, k=6, t=2, s=80), 1e-9, x0=x0)
-    _assert_trace_and_x(xg, st, tr, ref)
+    _assert_trace_and_x(xg, st, tr, ref, A=A, b=b, tol=1e-9)
     x, st = h.solve(_dev(np.zeros(A.n)), x=_dev(x0), tol=1e-9)
     assert st["converged"] and float(torch.abs(x).max()) == 0.0
 
@@ -225,7 +253,7 @@ def test_sequence_exact_variant_matches_oracle():
         x, st = h.solve(_dev(bi), tol=1e-9)
         ref = sdr_solve(Ai.to_scipy(), bi, recycle=rec, new_matrix=True, tol=1e-9, **kw)
         rec = ref.recycle
-        _assert_trace_and_x(_host(x), st, h.trace(), ref)
+        _assert_trace_and_x(_host(x), st, h.trace(), ref, A=Ai, b=bi, tol=1e-9)
 
 
 def test_mixed_precision_reaches_fp64_tolerance():
@@ -262,6 +290,18 @@ def test_errors_and_not_converged():
     bn[0] = np.nan
     with pytest.raises(SDRError):
         h.solve(_dev(bn), tol=1e-8)
+    # a non-finite matrix entry: the solve refuses it (non-finite initial
+    # residual, also from x0 = 0 since NaN * 0 is NaN), whether the matrix
+    # came with the handle or with an update
+    h2 = _solver(A.with_values(bad), m=5, k=2, t=2, s=16)
+    with pytest.raises(SDRError, match="non-finite"):
+        h2.solve(_dev(b), tol=1e-8)
+    h.update_matrix(_dev(bad))
+    with pytest.raises(SDRError, match="non-finite"):
+        h.solve(_dev(b), tol=1e-8)
+    h.update_matrix(_dev(A.values))
+    x, st = h.solve(_dev(b), tol=1e-6)
+    assert np.all(np.isfinite(_host(x)))
 
 
 def test_breakdown_on_invariant_krylov_space():
@@ -271,12 +311,12 @@ def test_breakdown_on_invariant_krylov_space():
     b = np.ones(N)
     h, xg, st, tr, ref = _compare_solve(A, b, dict(m=10, k=2, t=3, s=32), 1e-12)
     assert st["converged"]
-    _assert_trace_and_x(xg, st, tr, ref, b=b)
+    _assert_trace_and_x(xg, st, tr, ref, A=A, b=b, tol=1e-12)
 
 
 def test_large_cd2d_1024_first_cycle_and_residual():
-    """Full-size 1024^2 operator: the first cycle's decisions match the oracle
-    and the solve reaches 1e-8 (true residual recomputed on the host)."""
+    """Full-size 1024^2 operator, first cycle only: its decisions, true
+    residual and x match the oracle's first cycle."""
     A, b, p = workload("cd2d_1024")
     h = _solver(A, m=p["m"], k=p["k"], t=p["t"], s=p["s"], max_cycles=1)
     x1, st1 = h.solve(_dev(b), tol=p["tol"])
@@ -284,7 +324,11 @@ def test_large_cd2d_1024_first_cycle_and_residual():
                     max_cycles=1)
     tr = h.trace()
     assert tr[0]["j_stop"] == ref.trace[0].j_stop
-    assert abs(tr[0]["res"] - ref.trace[0].res) <= 1e-8 * ref.trace[0].res
+    assert abs(tr[0]["res"] - ref.trace[0].res) <= 1e-10 * ref.trace[0].res
+    assert abs(tr[0]["sres"] - ref.trace[0].sres) <= 1e-10 * ref.trace[0].sres
+    sg = np.array(h.step_sres()[1:])
+    so = np.array(ref.trace[0].sres_hist)
+    assert np.all(np.abs(sg - so) <= 1e-12 * so[0])
     x1 = _host(x1)
     assert np.linalg.norm(x1 - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
 
@@ -297,4 +341,127 @@ def test_large_sketch_takes_four_wave_spmv_blocks(cplx, s):
     b = crandn(A.n, 23) if cplx else randn(A.n, 23)
     h, xg, st, tr, ref = _compare_solve(A, b, dict(m=20, k=4, t=2, s=s), 1e-9)
     assert len(h.spmv_layout()) == 5
-    _assert_trace_and_x(xg, st, tr, ref, b=b)
+    _assert_trace_and_x(xg, st, tr, ref, A=A, b=b, tol=1e-9)
+
+
+def _golden_c2():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cd2d_1024_trace.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _x_against_golden(xg, gold):
+    """Relative errors of the stored samples of x, of ||x|| and of x . g."""
+    from workloads import randn
+    n = xg.shape[0]
+    idx = np.sort(np.random.default_rng(gold["sample_seed"]).choice(n, len(gold["x_sample"]),
+                                                                   replace=False))
+    xs = np.array(gold["x_sample"])
+    e_samp = np.linalg.norm(xg[idx] - xs) / np.linalg.norm(xs)
+    e_norm = abs(np.linalg.norm(xg) - gold["x_norm"]) / gold["x_norm"]
+    e_dot = abs(xg @ randn(n, gold["g_seed"]) - gold["x_dot_g"]) / abs(gold["x_dot_g"])
+    return e_samp, e_norm, e_dot
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cd2d_1024_full_solve_against_stored_oracle_run(precision):
+    """The complete 1024^2 solve (m=100, k=20, t=2, s=240, tol 1e-8) against
+    the oracle's complete run (tests/golden/make_cd2d_1024_trace.py).
+
+    FP64 (precision=0): the decisions of every cycle (stop index, checks, ell,
+    k_eff) must be the oracle's.  The per-cycle sketched and true residuals
+    are compared and the first cycle where they differ by more than 1e-10
+    (relative) is reported: rounding differences grow from cycle to cycle, so
+    the two runs are then several correct results, and both must meet the
+    tolerance (the oracle's stored relres, the library's recomputed on the
+    host).  The error of x against the oracle's (stored samples, norm and an
+    inner product) is printed and bounded.  FP32 basis (precision=1): its own
+    decisions; the same x comparison, reported and bounded.
+    """
+    gold = _golden_c2()
+    A, b, p = workload("cd2d_1024")
+    h = _solver(A, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"], precision=precision)
+    x, st = h.solve(_dev(b), tol=p["tol"])
+    xg = _host(x)
+    tr = h.trace()
+    relres = float(np.linalg.norm(b - A.to_scipy() @ xg) / np.linalg.norm(b))
+    print(f"precision {precision}: {st['cycles']} cycles, {st['iters']} steps "
+          f"(oracle {gold['cycles']}, {gold['iters']}), relres {relres:.3e} "
+          f"(oracle {gold['relres']:.3e}), {st['seconds']:.4f} s", flush=True)
+    assert st["converged"] and relres <= p["tol"]
+    assert gold["converged"] and gold["relres"] <= p["tol"]
+    e_samp, e_norm, e_dot = _x_against_golden(xg, gold)
+    print(f"x vs oracle: samples {e_samp:.2e}, norm {e_norm:.2e}, x.g {e_dot:.2e}", flush=True)
+    if precision == 0:
+        first_dev = None
+        for i, (cg, co) in enumerate(zip(tr, gold["trace"])):
+            dec = (cg["j_stop"], cg["n_checks"], cg["ell"], cg["k_eff"])
+            assert dec == (co["j_stop"], co["n_checks"], co["ell"], co["k_eff"]), (i, dec, co)
+            ds = abs(cg["sres"] - co["sres"]) / co["sres"]
+            dr = abs(cg["res"] - co["res"]) / co["res"]
+            if first_dev is None and max(ds, dr) > 1e-10:
+                first_dev = i
+            print(f"cycle {i:2d}: j {dec[0]:3d} checks {dec[1]} ell {dec[2]:3d} k {dec[3]:2d}  "
+                  f"rel. diff sres {ds:.1e} res {dr:.1e}", flush=True)
+        assert len(tr) == len(gold["trace"])
+        assert st["iters"] == gold["iters"] and st["matvecs"] == gold["matvecs"]
+        print(f"first cycle beyond 1e-10: {first_dev}", flush=True)
+        if first_dev is None:
+            assert e_samp <= 1e-8
+    # two solutions that both meet tol differ by at most cond(A) * 2 tol
+    # relative; at this operator's conditioning that is far above what either
+    # path shows, so the bound asserted is the measured agreement's order
+    assert e_samp <= (1e-5 if precision == 0 else 1e-4)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_one_cycle_kernel_results_match_oracle(cplx):
+    """One cycle from x0 = 0 (no recycled block), then a second cycle's worth
+    of recycle data, per kernel to 1e-12 against the oracle:
+    * the sketched least squares: the sketched residual after every step
+      (sdr_get_step_sres; step 0 is ||S r0||) against the oracle's lstsq;
+    * the basis product x~ = [U V] y (the cycle's x) and the residual kernel
+      (the cycle's true residual);
+    * the harmonic-Ritz update of U, SU, SAU (sdr_get_recycle): range(U)
+      against the oracle's U by the largest principal-angle sine, and the
+      triple's consistency SU = S U, SAU = S A U with the oracle's S and A.
+    """
+    if cplx:
+        A = helmholtz2d(36, kappa=8.0)
+        b = crandn(A.n, 31)
+        kw = dict(m=30, k=6, t=3, s=96)
+    else:
+        A = cd2d_upwind(45)
+        b = randn(A.n, 31)
+        kw = dict(m=30, k=6, t=2, s=80)
+    h = _solver(A, max_cycles=1, **kw)
+    x, st = h.solve(_dev(b), tol=1e-14)
+    keep = []
+    ref = sdr_solve(A.to_scipy(), b, tol=1e-14, max_cycles=1, keep_cycles=keep, **kw)
+    So = sketch_operator(A.n, kw["s"], 8, 42)
+    nb = np.linalg.norm(b)
+    sg = np.array(h.step_sres())
+    so = np.array([np.linalg.norm(So @ b)] + list(ref.trace[0].sres_hist))
+    assert sg.shape == so.shape
+    print("step sres max rel. diff (to ||S b||)", np.max(np.abs(sg - so)) / so[0], flush=True)
+    assert np.all(np.abs(sg - so) <= 1e-12 * so[0])
+    xg = _host(x)
+    print("x~ rel. diff", np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x), flush=True)
+    assert np.linalg.norm(xg - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+    tr = h.trace()
+    assert abs(tr[0]["res"] - ref.trace[0].res) <= 1e-12 * nb
+    U, SU, SAU = (_host(t) for t in h.recycle())
+    Uo = ref.recycle.U
+    assert U.shape == Uo.shape
+    import scipy.linalg as sla
+    Qa, Qb = sla.orth(U), sla.orth(Uo)
+    sin_max = max(np.linalg.norm(Qb - Qa @ (Qa.conj().T @ Qb), 2),
+                  np.linalg.norm(Qa - Qb @ (Qb.conj().T @ Qa), 2))
+    print("recycle space: largest principal-angle sine", sin_max, flush=True)
+    assert sin_max <= 1e-10
+    SUr = So @ U
+    SAUr = So @ (A.to_scipy() @ U)
+    assert np.linalg.norm(SU - SUr) <= 1e-12 * np.linalg.norm(SUr)
+    assert np.linalg.norm(SAU - SAUr) <= 1e-12 * np.linalg.norm(SAUr)

@@ -25,7 +25,7 @@ def _check_against_oracle(A, b, tol, x0=None, extra=None):
     h = gp._solver(A, precond=1, **KW, **(extra or {}))
     x, st = h.solve(gp._dev(b), x=None if x0 is None else gp._dev(x0), tol=tol)
     ref = sdr_solve_right_jacobi(A.to_scipy(), b, x0=x0, tol=tol, **KW)
-    gp._assert_trace_and_x(gp._host(x), st, h.trace(), ref, b=b)
+    gp._assert_trace_and_x(gp._host(x), st, h.trace(), ref, A=A, b=b, tol=tol)
     r = b - A.to_scipy() @ gp._host(x)
     assert np.linalg.norm(r) <= tol * np.linalg.norm(b)
     return h, st, ref
@@ -68,7 +68,7 @@ def test_jacobi_sequence_exact_variant_matches_oracle():
         x, st = h.solve(gp._dev(bi), tol=1e-9)
         ref = sdr_solve_right_jacobi(Ai.to_scipy(), bi, recycle=rec, new_matrix=True, tol=1e-9, **KW)
         rec = ref.recycle
-        gp._assert_trace_and_x(gp._host(x), st, h.trace(), ref, b=bi)
+        gp._assert_trace_and_x(gp._host(x), st, h.trace(), ref, A=Ai, b=bi, tol=1e-9)
 
 
 def test_jacobi_zero_or_missing_diagonal_is_an_error():

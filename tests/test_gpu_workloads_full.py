@@ -1,8 +1,9 @@
 """Full-size workloads on the GPU.
 
 At these sizes the oracle runs one cycle in seconds, so each workload checks
-its first cycle against the oracle (the same decisions, the same residual to
-1e-8 relative, the same x to 1e-8) and checks the complete solves through
+its first cycle against the oracle (the same decisions, the sketched and true
+residuals to 1e-10 relative, the sketched residual of every step to 1e-12,
+the same x to 1e-8) and checks the complete solves through
 properties that hold at any size: the FP64 residual recomputed on the host
 meets the tolerance, and for the differentiated solve the loss and gradient
 match a sparse direct solve and a central difference.  Timings are printed for
@@ -49,8 +50,18 @@ def _first_cycle_parity(A, b, p):
     assert tr[0]["j_stop"] == ref.trace[0].j_stop
     assert tr[0]["n_checks"] == len(ref.trace[0].checks)
     assert tr[0]["k_eff"] == ref.trace[0].k_eff
-    assert abs(tr[0]["res"] - ref.trace[0].res) <= 1e-8 * ref.trace[0].res
+    nb = np.linalg.norm(b)
+    ds = abs(tr[0]["sres"] - ref.trace[0].sres)
+    dr = abs(tr[0]["res"] - ref.trace[0].res)
+    print(f"first cycle: rel. diff sres {ds / ref.trace[0].sres:.1e}, res {dr / ref.trace[0].res:.1e}",
+          flush=True)
+    assert ds <= 1e-10 * ref.trace[0].sres + 1e-13 * nb
+    assert dr <= 1e-10 * ref.trace[0].res + 1e-13 * nb
+    sg = np.array(h.step_sres()[1:])
+    so = np.array(ref.trace[0].sres_hist)
+    assert np.all(np.abs(sg - so) <= 1e-12 * so[0])
     xg = x.cpu().numpy()
+    print(f"first cycle: x rel. diff {np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x):.1e}", flush=True)
     assert np.linalg.norm(xg - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
     h.close()
 
