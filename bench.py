@@ -20,8 +20,18 @@ in HBM before the timed region.  Prints one JSON line:
   profiles/<kernel>_<workload>_hbm_traffic.md; null when the kernel sources
   differ from the ones the counters were taken on (a digest of the sources is
   stored with the figures);
-* cpu_baseline: the FP64 oracle on the host cores, timed on one 100-step
-  cycle of the same solve and scaled to the solve's Arnoldi steps.
+* cpu_baseline: the FP64 oracle on the host cores, timed on the first
+  cycle (no recycled block) and the second (k recycled vectors, the steady
+  state of every later cycle) of the same solve, extrapolated to the GPU
+  solve's steps (the first cycle's cost once, the second's per step after);
+* sequence: the 20 slowly changing 3D systems (128^3, N = 2,097,152) solved
+  in turn with the recycle space carried (exact variant), in FP64 and with
+  the FP32 basis: solves/s, steps per system, the FP64 residual recomputed on
+  the host, the first cycle's x against the oracle's, and the step kernel's
+  bandwidth (its per-step working set exceeds the 256 MB last-level cache);
+* helmholtz: the complex shifted Helmholtz system (1024^2) to 1e-8 in
+  complex128 and with the complex64 basis: time, steps, host eigen-step time,
+  the host residual and the first cycle's x against the oracle's.
 
     python bench.py --summarize-pmc FETCH.csv WRITE.csv --copy-calib-mb 256
 
@@ -164,7 +174,7 @@ def summarize_pmc(fetch_csv, write_csv, calib_mb, workload_name):
     R = "$R"
     run = (f"timeout -s KILL 240 rocprofv3 --pmc {{c}} --output-format csv -d {{d}} "
            f"-o run -- python3 {R}/bench.py --workload {workload_name} --steps 1 --warmup 0 "
-           f"--no-cpu-baseline --copy-calib-mb {calib_mb}")
+           f"--no-cpu-baseline --no-extras --copy-calib-mb {calib_mb}")
     lines = [f"# HBM traffic per dispatch, {workload_name} solve (rocprofv3 counters)", "",
              "Commands (from /tmp with TMPDIR=/tmp; R is the repository root):", "",
              "    " + run.format(c="FETCH_SIZE", d=_rel_dir(fetch_csv)),
@@ -228,7 +238,7 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name):
              f"recycle space ({sv['iters']} Arnoldi steps, {sv['cycles']} cycles).", "",
              "Commands (from /tmp with TMPDIR=/tmp; R is the repository root):", "",
              f"    timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d "
-             f"{kd} -o run -- python3 {R}/bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+             f"{kd} -o run -- python3 {R}/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras",
              f"    python3 {R}/bench.py --summarize-kstats {kd}/{os.path.basename(stats_csv)} "
              f"{_rel_dir(trace_csv)}/{os.path.basename(trace_csv)} BENCH.json --workload {workload_name}", "",
              "(BENCH.json: the output line of `python3 bench.py` run just before, on the same box.)", "",
@@ -249,30 +259,197 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name):
     return "\n".join(lines) + "\n"
 
 
-def cpu_baseline(A, b, p, gpu_iters):
-    import numpy as np
-    from oracle import sdr_solve
-    from oracle.sketch import sketch_operator
+def _blas_threads():
     try:
         import threadpoolctl
         info = threadpoolctl.threadpool_info()
-        blas_threads = max([i.get("num_threads", 1) for i in info] or [1])
+        return int(max([i.get("num_threads", 1) for i in info] or [1]))
     except Exception:  # pragma: no cover
-        blas_threads = 1
+        return 1
+
+
+def cpu_baseline(A, b, p, gpu_iters):
+    """The oracle's first two cycles of the same solve on the host: the first
+    (no recycled block) once, the second (k recycled vectors, as every later
+    cycle) per step for the remaining steps of the GPU solve."""
+    from oracle import sdr_solve
+    from oracle.sketch import sketch_operator
+    blas_threads = _blas_threads()
     As = A.to_scipy()
     S = sketch_operator(A.n, p["s"], p["zeta"], p["s_seed"])
+    kw = dict(m=p["m"], k=p["k"], t=p["t"], s=p["s"], zeta=p["zeta"], seed=p["s_seed"], tol=p["tol"], S=S)
     t0 = time.perf_counter()
-    ro = sdr_solve(As, b, m=p["m"], k=p["k"], t=p["t"], s=p["s"], zeta=p["zeta"],
-                   seed=p["s_seed"], tol=p["tol"], max_cycles=1, S=S)
+    r1 = sdr_solve(As, b, max_cycles=1, **kw)
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r2 = sdr_solve(As, b, x0=r1.x, recycle=r1.recycle, max_cycles=1, **kw)
+    t2 = time.perf_counter() - t0
+    per_step2 = t2 / max(r2.iters, 1)
+    value = t1 + per_step2 * max(gpu_iters - r1.iters, 0)
+    return {"value": value, "unit": "s", "cores": int(blas_threads), "kind": "oracle",
+            "sample": (f"the oracle's first two cycles of the same solve on the host: cycle 1 "
+                       f"({r1.iters} steps, no recycled block) {t1:.1f} s, cycle 2 ({r2.iters} steps, "
+                       f"k_hat = {r1.recycle.k}, the steady state of the later cycles) {t2:.1f} s = "
+                       f"{per_step2 * 1e3:.1f} ms per step incl. its least squares, checks and "
+                       f"eigen-step; extrapolated: cycle 1 + {gpu_iters - r1.iters} further steps at "
+                       f"the cycle-2 rate (the GPU solve's {gpu_iters} steps); SciPy sparse products "
+                       f"single-threaded, BLAS threads {blas_threads}, nproc {os.cpu_count()}")}
+
+
+def _first_cycle_error(A, b, p, xg1):
+    """Relative 2-norm error of a first-cycle x against the FP64 oracle's first
+    cycle from x0 = 0 (and the oracle's time for it)."""
+    import numpy as np
+    from oracle import sdr_solve
+    t0 = time.perf_counter()
+    r = sdr_solve(A.to_scipy(), b, m=p["m"], k=p["k"], t=p["t"], s=p["s"], zeta=p["zeta"],
+                  seed=p["s_seed"], tol=p["tol"], max_cycles=1)
     dt = time.perf_counter() - t0
-    per_step = dt / max(ro.iters, 1)
-    return {"value": per_step * gpu_iters, "unit": "s", "cores": int(blas_threads),
-            "kind": "oracle",
-            "sample": (f"one {ro.iters}-step cycle of the same solve on the host "
-                       f"({dt:.1f} s, {per_step * 1e3:.1f} ms per Arnoldi step incl. its "
-                       f"least squares and the cycle's checks/eigen-step), scaled to the "
-                       f"GPU solve's {gpu_iters} steps; SciPy sparse products single-threaded, "
-                       f"BLAS threads {blas_threads}, nproc {os.cpu_count()}")}
+    return [float(np.linalg.norm(x - r.x) / np.linalg.norm(r.x)) for x in xg1], dt
+
+
+def _step_kernel_rate(kt, N, ndiag, p, pv):
+    """Average duration and algorithmic bandwidth of the SpMV + sketch kernel
+    from a handle's sampled kernel timings (diagonal storage)."""
+    hist, launches = kt["window_hist"], kt["launches"]
+    if not launches or kt["spmv_sketch_ms"] <= 0:
+        return None
+    byts = sum(hist[tw] * spmv_dia_sketch_bytes(N, ndiag, tw, p=p, pv=pv) for tw in range(len(hist)))
+    sec = kt["spmv_sketch_ms"] * 1e-3
+    return {"avg_us": 1e6 * sec / launches, "gbs": byts / sec / 1e9,
+            "frac": byts / sec / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": byts / launches,
+            "launches": launches}
+
+
+def sequence_bench(dev, with_oracle=True):
+    """The 20-system 3D sequence in FP64 and with the FP32 basis."""
+    import numpy as np
+    import torch
+    from paper_2311_14206_amd.sdr import SDRSolver
+    from workloads import workload, sequence_system, describe
+
+    name = "cd3d_128_seq"
+    A0, _, p = workload(name)
+    systems = [sequence_system(A0, p, i) for i in range(1, p["n_systems"] + 1)]
+    rp = torch.from_numpy(A0.row_ptr).to(dev)
+    ci = torch.from_numpy(A0.col_idx).to(dev)
+    vals = [torch.from_numpy(Ai.values).to(dev) for Ai, _ in systems]
+    bs = [torch.from_numpy(bi).to(dev) for _, bi in systems]
+    out = {"workload": describe(name), "m": p["m"], "k": p["k"], "t": p["t"], "s": p["s"],
+           "tol": p["tol"], "variant": "exact (S A_i U recomputed per system)",
+           "fp64_no_carry_note": "the same systems with the recycle space dropped before each "
+                                 "(deflated restarting within a solve only), for comparison"}
+    first = {}
+    runs = ((0, "fp64", True), (1, "fp32_basis", True), (0, "fp64_no_carry", False))
+    for prec, key, carry in runs:
+        h = SDRSolver(rp, ci, vals[0], m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
+                      zeta=p["zeta"], precision=prec, kernel_timing=64)
+        # warm-up: one solve of system 1, then the recycle space is dropped
+        h.solve(bs[0], tol=p["tol"])
+        h.reset()
+        h.kernel_times()
+        torch.cuda.synchronize()
+        xs, sts = [], []
+        t0 = time.perf_counter()
+        for i in range(len(systems)):
+            if not carry:
+                h.reset()  # deflated restarting within each solve only
+            h.update_matrix(vals[i])
+            x, st = h.solve(bs[i], tol=p["tol"])
+            xs.append(x)
+            sts.append(st)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        kt = h.kernel_times()
+        relres = []
+        for (Ai, bi), x in zip(systems, xs):
+            xh = x.cpu().numpy()
+            relres.append(float(np.linalg.norm(bi - Ai.to_scipy() @ xh) / np.linalg.norm(bi)))
+        iters = [st["iters"] for st in sts]
+        rate = _step_kernel_rate(kt, A0.n, len(h.spmv_layout()), 8 if prec == 0 else 4,
+                                 8 if prec == 0 else 4)
+        out[key] = {"solves_per_s": len(systems) / total, "seconds_total": total,
+                    "steps_per_system": iters, "steps_system1": iters[0],
+                    "steps_mean_later": float(np.mean(iters[1:])),
+                    "matvecs_total": int(sum(st["matvecs"] for st in sts)),
+                    "converged_all": all(st["converged"] for st in sts),
+                    "relres_host_max": max(relres),
+                    "host_eig_seconds_total": float(sum(st["host_eig_seconds"] for st in sts)),
+                    "step_kernel": rate}
+        print(f"[bench] sequence {key}: {len(systems) / total:.2f} solves/s, steps {iters}, "
+              f"max host relres {max(relres):.2e}", file=sys.stderr, flush=True)
+        if not carry:
+            h.close()
+            continue
+        # first cycle of system 1 on a fresh handle, for the error against the oracle
+        h1 = SDRSolver(rp, ci, vals[0], m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
+                       zeta=p["zeta"], precision=prec, max_cycles=1)
+        x1, _ = h1.solve(bs[0], tol=p["tol"])
+        first[key] = x1.cpu().numpy()
+        h.close()
+        h1.close()
+        del xs
+    if with_oracle:
+        errs, dt = _first_cycle_error(systems[0][0], systems[0][1], p, [first["fp64"], first["fp32_basis"]])
+        out["fp64"]["first_cycle_x_err_vs_oracle"] = errs[0]
+        out["fp32_basis"]["first_cycle_x_err_vs_oracle"] = errs[1]
+        out["oracle_first_cycle_seconds"] = dt
+    return out
+
+
+def helmholtz_bench(dev, with_oracle=True, reps=2):
+    """The complex Helmholtz system in complex128 and with the complex64 basis."""
+    import numpy as np
+    import torch
+    from paper_2311_14206_amd.sdr import SDRSolver
+    from workloads import workload, describe
+
+    name = "helmholtz_1024"
+    A, b, p = workload(name)
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_idx).to(dev)
+    vals = torch.from_numpy(A.values).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    out = {"workload": describe(name), "m": p["m"], "k": p["k"], "t": p["t"], "s": p["s"], "tol": p["tol"]}
+    first = {}
+    for prec, key in ((0, "c128"), (1, "c64_basis")):
+        h = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
+                      zeta=p["zeta"], precision=prec, kernel_timing=64)
+        h.solve(bd, tol=p["tol"])  # warm-up
+        h.kernel_times()
+        times, st, x = [], None, None
+        for _ in range(reps):
+            h.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = h.solve(bd, tol=p["tol"])
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        kt = h.kernel_times()
+        xh = x.cpu().numpy()
+        relres = float(np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b))
+        rate = _step_kernel_rate(kt, A.n, len(h.spmv_layout()), 16 if prec == 0 else 8,
+                                 16 if prec == 0 else 8)
+        out[key] = {"time_to_tol_s": statistics.median(times), "times": times, "iters": st["iters"],
+                    "cycles": st["cycles"], "res_checks": st["res_checks"], "converged": st["converged"],
+                    "relres_host": relres, "host_eig_seconds": st["host_eig_seconds"],
+                    "host_eig_seconds_per_cycle": st["host_eig_seconds"] / max(st["cycles"], 1),
+                    "step_kernel": rate}
+        print(f"[bench] helmholtz {key}: {statistics.median(times):.3f} s, {st['iters']} steps, "
+              f"{st['cycles']} cycles, host eig {st['host_eig_seconds']:.3f} s, relres {relres:.2e}",
+              file=sys.stderr, flush=True)
+        h1 = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
+                       zeta=p["zeta"], precision=prec, max_cycles=1)
+        x1, _ = h1.solve(bd, tol=p["tol"])
+        first[key] = x1.cpu().numpy()
+        h.close()
+        h1.close()
+    if with_oracle:
+        errs, dt = _first_cycle_error(A, b, p, [first["c128"], first["c64_basis"]])
+        out["c128"]["first_cycle_x_err_vs_oracle"] = errs[0]
+        out["c64_basis"]["first_cycle_x_err_vs_oracle"] = errs[1]
+        out["oracle_first_cycle_seconds"] = dt
+    return out
 
 
 def main():
@@ -282,6 +459,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cd2d_1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the sequence and Helmholtz measurements (profiling runs)")
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--timing-every", type=int, default=64,
                     help="time the SpMV and update kernels of every n-th Arnoldi step with HIP "
@@ -309,7 +488,7 @@ def main():
     import torch
 
     from paper_2311_14206_amd.sdr import SDRSolver
-    from workloads import workload
+    from workloads import workload, describe
 
     dev = "cuda:0"
     A, b, p = workload(args.workload)
@@ -402,18 +581,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 0 else "f32-basis/f64",
         "data": "synthetic",
-        "config": {"workload": (f"{args.workload}: 2D upwind convection-diffusion "
-                                f"{p['n']}x{p['n']} (N={N}, nnz={nnz}), Peclet 50, "
-                                f"b~N(0,1) seed {p['b_seed']}"),
+        "config": {"workload": describe(args.workload),
                    "m": p["m"], "k": p["k"], "t": p["t"], "s": p["s"], "zeta": p["zeta"],
                    "tol": p["tol"], "precision": "fp64" if args.precision == 0 else "mixed"},
-        "solves_per_s": 1.0 / med,
+        "single_solves_per_s": 1.0 / med,
         "solve": {"cycles": st["cycles"], "iters": st["iters"], "matvecs": st["matvecs"],
                   "inner_products": st["inner_products"], "res_checks": st["res_checks"],
                   "relres": st["relres"], "relres_host_check": relres_host,
                   "host_eig_seconds": st["host_eig_seconds"]},
         "roofline": {"bound": "hbm",
                      "kernel": k1_name,
+                     "note": ("effective bandwidth: algorithmic bytes / kernel time; the counters "
+                              "behind traffic count L2 egress, and this step's ~100 MB working set "
+                              "fits the 256 MB last-level cache, so part of it is served from there "
+                              "(sequence.*.step_kernel measures the 3D sequence, whose per-step "
+                              "working set does not fit)"),
                      "achieved": k1_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (k1_gbs / HBM_PEAK_GBS) if k1_gbs else None,
                      "traffic": read_traffic(traffic_summary_path(k1_key.split("<")[0], args.workload),
@@ -428,6 +610,13 @@ def main():
                          "bytes_per_step": (k1_bytes + k2_bytes) / max(launches, 1),
                          "launches": launches},
     }
+    h.close()
+    del x, bd, vals, ci, rp
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        line["sequence"] = sequence_bench(dev, with_oracle=not args.no_cpu_baseline)
+        torch.cuda.empty_cache()
+        line["helmholtz"] = helmholtz_bench(dev, with_oracle=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(A, b, p, st["iters"])

@@ -19,6 +19,7 @@ from .problems import (  # noqa: F401
     randn,
     crandn,
     workload,
+    describe,
     sequence_system,
     WORKLOADS,
 )

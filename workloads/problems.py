@@ -228,6 +228,28 @@ WORKLOADS = {
 }
 
 
+def describe(name: str) -> str:
+    """One-line description of a named workload (operator, size, inputs)."""
+    p = WORKLOADS[name]
+    n = p["n"]
+    if p["kind"] == "cd2d_upwind":
+        N = n * n
+        what = (f"2D upwind convection-diffusion {n}x{n} (N={N}, nnz={5 * N - 4 * n}), Peclet 50")
+        if "theta_seed" in p:
+            what += f", edge weights theta = 1 + 0.1 N(0,1) seed {p['theta_seed']}"
+        return f"{name}: {what}, b~N(0,1) seed {p['b_seed']}"
+    if p["kind"] == "cd3d_upwind":
+        N = n ** 3
+        return (f"{name}: 3D upwind convection-diffusion {n}^3 (N={N}, nnz={7 * N - 6 * n * n}), "
+                f"Peclet 50; {p['n_systems']} systems A_i = A + diag(d_i), d_i ~ "
+                f"{p['d_scale']:g} U(0,1) seeds {p['d_seed0']}+i, b_i ~ N(0,1) seeds {p['b_seed0']}+i")
+    if p["kind"] == "helmholtz2d":
+        N = n * n
+        return (f"{name}: complex shifted Helmholtz -Laplace - kappa^2 (1 + 0.5i), kappa {p['kappa']:g}, "
+                f"{n}x{n} (N={N}, nnz={5 * N - 4 * n}, complex128), b~CN(0,1) seed {p['b_seed']}")
+    raise ValueError(p["kind"])
+
+
 def workload(name: str, n: int | None = None):
     """Return (A, b, params) for a named workload; ``n`` overrides the grid size."""
     p = dict(WORKLOADS[name])
