@@ -232,16 +232,19 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name):
     R = "$R"
     kd = _rel_dir(stats_csv)
     sv = bj["solve"]
+    prec_flag = " --precision 1" if bj["config"].get("precision") == "mixed" else ""
     lines = [f"# rocprofv3 kernel statistics: GMRES-SDR solve, {workload_name} ({bj['dtype']})", "",
              f"Workload {bj['config']['workload']}; m = {p['m']}, k = {p['k']}, t = {p['t']}, "
              f"s = {p['s']}, zeta = {p['zeta']}, tol {p['tol']:g}; one solve from x0 = 0 with an empty "
              f"recycle space ({sv['iters']} Arnoldi steps, {sv['cycles']} cycles).", "",
              "Commands (from /tmp with TMPDIR=/tmp; R is the repository root):", "",
              f"    timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d "
-             f"{kd} -o run -- python3 {R}/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras",
+             f"{kd} -o run -- python3 {R}/bench.py --workload {workload_name}{prec_flag} --steps 1 "
+             f"--warmup 0 --no-cpu-baseline --no-extras",
              f"    python3 {R}/bench.py --summarize-kstats {kd}/{os.path.basename(stats_csv)} "
              f"{_rel_dir(trace_csv)}/{os.path.basename(trace_csv)} BENCH.json --workload {workload_name}", "",
-             "(BENCH.json: the output line of `python3 bench.py` run just before, on the same box.)", "",
+             f"(BENCH.json: the output line of `python3 bench.py --workload {workload_name}{prec_flag} "
+             "--no-cpu-baseline --no-extras` run just before, on the same box.)", "",
              f"Kernel source digest (bench.py kernel_source_digest, comments ignored): {kernel_source_digest()}.",
              "",
              f"The step kernel {k1n} averages {float(k1['AverageNs']) / 1e3:.2f} us over {len(dur)} launches "
@@ -539,9 +542,11 @@ def main():
 
     hist = kt["window_hist"]
     launches = kt["launches"]
-    pb = 8 if args.precision == 0 else 4
+    pb = (8 if args.precision == 0 else 4) * (2 if A.values.dtype.kind == "c" else 1)
     layout = h.spmv_layout()
-    tname = "double" if args.precision == 0 else "float"
+    cpx = A.values.dtype.kind == "c"
+    tname = ("sdr::cx<double>" if cpx else "double") if args.precision == 0 else \
+        ("sdr::cx<float>" if cpx else "float")
     if layout:
         # instantiation: <type, diagonals (0: any), window bound (2 for t <= 2, else 4),
         # threads (512 while 8 waves of FP64 sketch bins fit 64 KiB of LDS; else the
@@ -579,7 +584,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f32-basis/f64",
+        "dtype": (("c128" if cpx else "f64") if args.precision == 0 else
+                  ("c64-basis/c128" if cpx else "f32-basis/f64")),
         "data": "synthetic",
         "config": {"workload": describe(args.workload),
                    "m": p["m"], "k": p["k"], "t": p["t"], "s": p["s"], "zeta": p["zeta"],

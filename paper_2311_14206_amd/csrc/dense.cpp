@@ -149,6 +149,252 @@ bool schur(Mat& T, Mat& Z) {
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Complex leading invariant subspace without the Schur vectors of the whole
+// matrix.  The Hessenberg reduction keeps its reflectors instead of forming
+// Z, the QR iteration updates only its active window (the eigenvalues do not
+// need the rest of T) and logs its rotations, and the leading kk Schur
+// vectors are formed afterwards from the log and the reflectors alone: Z =
+// Q_h G_1 G_2 ... G_N, so Z(:, 1:kk) = Q_h (G_1 (... (G_N E_kk))), an n x kk
+// product instead of n x n.  Valid when the selected eigenvalues occupy the
+// leading diagonal positions, which the caller checks.
+// ---------------------------------------------------------------------------
+struct Rot {
+  int k;
+  double c, sr, si;  // G = [[c, s], [-conj(s), c]], s = sr + i si
+};
+
+// Split (real, imaginary) column-major n x n matrix: the loops below run on
+// contiguous real arrays, which vectorise where std::complex does not.
+struct SplitMat {
+  int n = 0;
+  std::vector<double> re, im;
+  explicit SplitMat(int nn = 0) : n(nn), re((size_t)nn * nn, 0.0), im((size_t)nn * nn, 0.0) {}
+  double& r(int i, int j) { return re[(size_t)j * n + i]; }
+  double& c(int i, int j) { return im[(size_t)j * n + i]; }
+};
+
+// Householder reduction of T to upper Hessenberg form; reflector k (acting
+// on rows k+1 .. n-1) is I - f_k v_k v_k^H with v_k in column k of (Vr, Vi),
+// rows 0 .. n-k-2.
+static void hessenberg_reflectors(SplitMat& T, std::vector<double>& Vr, std::vector<double>& Vi,
+                                  std::vector<double>& F) {
+  const int n = T.n;
+  Vr.assign((size_t)n * n, 0.0);
+  Vi.assign((size_t)n * n, 0.0);
+  F.assign(n, 0.0);
+  std::vector<double> wr(n), wi(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int len = n - k - 1;
+    double* __restrict__ cr = T.re.data() + (size_t)k * n + k + 1;
+    double* __restrict__ ci = T.im.data() + (size_t)k * n + k + 1;
+    double xn = 0.0;
+    for (int i = 0; i < len; ++i) xn += cr[i] * cr[i] + ci[i] * ci[i];
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const double ax0 = std::hypot(cr[0], ci[0]);
+    const double ar = ax0 > 0.0 ? -cr[0] / ax0 * xn : -xn;
+    const double ai = ax0 > 0.0 ? -ci[0] / ax0 * xn : 0.0;
+    double* __restrict__ vr = Vr.data() + (size_t)k * n;
+    double* __restrict__ vi = Vi.data() + (size_t)k * n;
+    for (int i = 0; i < len; ++i) {
+      vr[i] = cr[i];
+      vi[i] = ci[i];
+    }
+    vr[0] -= ar;
+    vi[0] -= ai;
+    double vn2 = 0.0;
+    for (int i = 0; i < len; ++i) vn2 += vr[i] * vr[i] + vi[i] * vi[i];
+    if (vn2 == 0.0) continue;
+    const double f = 2.0 / vn2;
+    F[k] = f;
+    // left: T(k+1:, j) -= v (f v^H T(k+1:, j)) for j > k
+    for (int j = k + 1; j < n; ++j) {
+      double* __restrict__ tr = T.re.data() + (size_t)j * n + k + 1;
+      double* __restrict__ ti = T.im.data() + (size_t)j * n + k + 1;
+      double sr = 0.0, si = 0.0;
+      for (int i = 0; i < len; ++i) {
+        sr += vr[i] * tr[i] + vi[i] * ti[i];
+        si += vr[i] * ti[i] - vi[i] * tr[i];
+      }
+      sr *= f;
+      si *= f;
+      for (int i = 0; i < len; ++i) {
+        tr[i] -= vr[i] * sr - vi[i] * si;
+        ti[i] -= vr[i] * si + vi[i] * sr;
+      }
+    }
+    // right: T(:, k+1:) -= (f T(:, k+1:) v) v^H
+    std::fill(wr.begin(), wr.end(), 0.0);
+    std::fill(wi.begin(), wi.end(), 0.0);
+    for (int l = 0; l < len; ++l) {
+      const double* __restrict__ tr = T.re.data() + (size_t)(k + 1 + l) * n;
+      const double* __restrict__ ti = T.im.data() + (size_t)(k + 1 + l) * n;
+      const double a = vr[l], b = vi[l];
+      for (int i = 0; i < n; ++i) {
+        wr[i] += tr[i] * a - ti[i] * b;
+        wi[i] += tr[i] * b + ti[i] * a;
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      wr[i] *= f;
+      wi[i] *= f;
+    }
+    for (int l = 0; l < len; ++l) {
+      double* __restrict__ tr = T.re.data() + (size_t)(k + 1 + l) * n;
+      double* __restrict__ ti = T.im.data() + (size_t)(k + 1 + l) * n;
+      const double a = vr[l], b = vi[l];  // conj(v_l) = a - i b
+      for (int i = 0; i < n; ++i) {
+        tr[i] -= wr[i] * a + wi[i] * b;
+        ti[i] -= wi[i] * a - wr[i] * b;
+      }
+    }
+    cr[0] = ar;
+    ci[0] = ai;
+    for (int i = 1; i < len; ++i) cr[i] = ci[i] = 0.0;
+  }
+}
+
+// Single-shift QR on the Hessenberg matrix T, updating only the active
+// window [l, hi]; the diagonal holds the eigenvalues on return, in the
+// positions the full iteration gives them.  Rotations are appended to log in
+// the order applied.
+static bool hessenberg_qr_window(SplitMat& T, std::vector<Rot>& log) {
+  const int n = T.n;
+  auto at = [&](int i, int j) { return cd(T.r(i, j), T.c(i, j)); };
+  auto put = [&](int i, int j, cd v) {
+    T.r(i, j) = v.real();
+    T.c(i, j) = v.imag();
+  };
+  const double eps = std::numeric_limits<double>::epsilon();
+  double anorm = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i <= std::min(j + 1, n - 1); ++i) anorm = std::max(anorm, abs1(at(i, j)));
+  double* __restrict__ Re = T.re.data();
+  double* __restrict__ Im = T.im.data();
+  int hi = n - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    int l = hi;
+    for (; l > 0; --l) {
+      double sc = abs1(at(l - 1, l - 1)) + abs1(at(l, l));
+      if (sc == 0.0) sc = anorm;
+      if (abs1(at(l, l - 1)) <= eps * sc) break;
+    }
+    if (l > 0) put(l, l - 1, 0.0);
+    if (l == hi) {
+      --hi;
+      iter = 0;
+      continue;
+    }
+    cd mu;
+    if (iter > 0 && iter % 10 == 0) {
+      mu = at(hi, hi) + cd(0.75 * abs1(at(hi, hi - 1)), 0.0);  // exceptional shift
+    } else {
+      const cd a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+      const cd tr = 0.5 * (a + d);
+      const cd disc = std::sqrt(0.25 * (a - d) * (a - d) + b * c);
+      const cd m1 = tr + disc, m2 = tr - disc;
+      mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+    }
+    cd x = at(l, l) - mu, y = at(l + 1, l);
+    for (int k = l; k < hi; ++k) {
+      if (k > l) {
+        x = at(k, k - 1);
+        y = at(k + 1, k - 1);
+      }
+      double c;
+      cd s;
+      givens(x, y, c, s);
+      const double sr = s.real(), si = s.imag();
+      // rows k, k+1 over columns max(l, k-1) .. hi (stride n)
+      for (int j = std::max(l, k - 1); j <= hi; ++j) {
+        const size_t o = (size_t)j * n + k;
+        const double ar = Re[o], ai = Im[o], br = Re[o + 1], bi = Im[o + 1];
+        Re[o] = c * ar + (sr * br - si * bi);
+        Im[o] = c * ai + (sr * bi + si * br);
+        Re[o + 1] = -(sr * ar + si * ai) + c * br;  // -conj(s) a + c b
+        Im[o + 1] = -(sr * ai - si * ar) + c * bi;
+      }
+      // columns k, k+1 over rows l .. min(k+2, hi) (contiguous)
+      const int rmax = std::min(k + 2, hi);
+      double* __restrict__ r0 = Re + (size_t)k * n;
+      double* __restrict__ i0 = Im + (size_t)k * n;
+      double* __restrict__ r1 = r0 + n;
+      double* __restrict__ i1 = i0 + n;
+      for (int i = l; i <= rmax; ++i) {
+        const double ar = r0[i], ai = i0[i], br = r1[i], bi = i1[i];
+        r0[i] = c * ar + (sr * br + si * bi);  // c a + conj(s) b
+        i0[i] = c * ai + (sr * bi - si * br);
+        r1[i] = -(sr * ar - si * ai) + c * br;  // -s a + c b
+        i1[i] = -(sr * ai + si * ar) + c * bi;
+      }
+      log.push_back(Rot{k, c, sr, si});
+      if (k > l) put(k + 1, k - 1, 0.0);
+    }
+    ++iter;
+    if (++total > 60 * n) return false;
+  }
+  return true;
+}
+
+// Z(:, 0 .. kk-1) of the Schur form reached by the logged iteration, from the
+// reflectors (Vr, Vi, F) and the rotation log: Y = Q_h G_1 ... G_N E_kk.
+static void leading_schur_vectors(int n, int kk, const std::vector<double>& Vr, const std::vector<double>& Vi,
+                                  const std::vector<double>& F, const std::vector<Rot>& log, Mat& Y) {
+  // M = G_1 ... G_N E_kk, rows contiguous (n x kk, split): G on rows k, k+1
+  std::vector<double> Mr((size_t)n * kk, 0.0), Mi((size_t)n * kk, 0.0);
+  for (int j = 0; j < kk; ++j) Mr[(size_t)j * kk + j] = 1.0;
+  int top = kk - 1;  // rows beyond top are zero
+  for (auto it = log.rbegin(); it != log.rend(); ++it) {
+    const int k = it->k;
+    if (k > top) continue;
+    const double c = it->c, sr = it->sr, si = it->si;
+    double* __restrict__ ar = Mr.data() + (size_t)k * kk;
+    double* __restrict__ ai = Mi.data() + (size_t)k * kk;
+    double* __restrict__ br = ar + kk;
+    double* __restrict__ bi = ai + kk;
+    for (int j = 0; j < kk; ++j) {
+      const double xr = ar[j], xi = ai[j], yr = br[j], yi = bi[j];
+      ar[j] = c * xr - (sr * yr - si * yi);  // c a - s b
+      ai[j] = c * xi - (sr * yi + si * yr);
+      br[j] = (sr * xr + si * xi) + c * yr;  // conj(s) a + c b
+      bi[j] = (sr * xi - si * xr) + c * yi;
+    }
+    if (k + 1 > top) top = k + 1;
+  }
+  // Y = Q_h M with Q_h = P_0 P_1 ... P_{n-3}: columns of Y split, column major
+  std::vector<double> Yr((size_t)n * kk), Yi((size_t)n * kk);
+  for (int j = 0; j < kk; ++j)
+    for (int i = 0; i < n; ++i) {
+      Yr[(size_t)j * n + i] = Mr[(size_t)i * kk + j];
+      Yi[(size_t)j * n + i] = Mi[(size_t)i * kk + j];
+    }
+  for (int k = n - 3; k >= 0; --k) {
+    const double f = F[k];
+    if (f == 0.0) continue;
+    const int len = n - k - 1;
+    const double* __restrict__ vr = Vr.data() + (size_t)k * n;
+    const double* __restrict__ vi = Vi.data() + (size_t)k * n;
+    for (int j = 0; j < kk; ++j) {
+      double* __restrict__ yr = Yr.data() + (size_t)j * n + k + 1;
+      double* __restrict__ yi = Yi.data() + (size_t)j * n + k + 1;
+      double dr = 0.0, di = 0.0;
+      for (int i = 0; i < len; ++i) {
+        dr += vr[i] * yr[i] + vi[i] * yi[i];
+        di += vr[i] * yi[i] - vi[i] * yr[i];
+      }
+      dr *= f;
+      di *= f;
+      for (int i = 0; i < len; ++i) {
+        yr[i] -= vr[i] * dr - vi[i] * di;
+        yi[i] -= vr[i] * di + vi[i] * dr;
+      }
+    }
+  }
+  Y = Mat(n, kk);
+  for (size_t i = 0; i < Y.a.size(); ++i) Y.a[i] = cd(Yr[i], Yi[i]);
+}
+
 // M(r0 : r0+len, c0 : c1] -= f v (v^T M(r0 : r0+len, c0 : c1]), four columns a
 // pass (one sweep of v per four dot products and per four updates).
 static void reflect_left(double* __restrict__ M, int n, int r0, int len, const double* __restrict__ v,
@@ -822,6 +1068,9 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
   std::vector<int> partner(n, -1);
   std::vector<double> Tr, Zr;
   Mat T, Z;
+  SplitMat H;  // complex data: Hessenberg form iterated to triangular (window updates only)
+  std::vector<double> hVr, hVi, hF;
+  std::vector<Rot> hlog;
   if (real) {
     Tr.resize((size_t)n * n);
     for (size_t i = 0; i < Tr.size(); ++i) Tr[i] = Aeig.a[i].real();
@@ -839,9 +1088,15 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
       }
     }
   } else {
-    T = Aeig;
-    if (!schur(T, Z)) return -1;
-    for (int i = 0; i < n; ++i) mod[i] = std::abs(T(i, i));
+    // eigenvalues by the windowed QR; the Schur vectors only if needed below
+    H = SplitMat(n);
+    for (size_t i = 0; i < Aeig.a.size(); ++i) {
+      H.re[i] = Aeig.a[i].real();
+      H.im[i] = Aeig.a[i].imag();
+    }
+    hessenberg_reflectors(H, hVr, hVi, hF);
+    if (!hessenberg_qr_window(H, hlog)) return -1;
+    for (int i = 0; i < n; ++i) mod[i] = std::hypot(H.r(i, i), H.c(i, i));
   }
   std::vector<int> ord(n);
   std::iota(ord.begin(), ord.end(), 0);
@@ -858,7 +1113,10 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
   for (int i = keff; i < n; ++i)
     if (sel[i]) leading = false;
   Mat Y;
-  if (real && leading) {
+  if (!real && leading) {
+    // the leading Schur vectors span the selected invariant subspace
+    leading_schur_vectors(n, keff, hVr, hVi, hF, hlog, Y);
+  } else if (real && leading) {
     // the leading real Schur vectors are an orthonormal real basis of the
     // selected invariant subspace: no reordering, no complex form needed
     Y = Mat(n, keff);
@@ -868,6 +1126,11 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
     if (real) {
       std::vector<int> pc;
       real_to_complex_schur(n, Tr, Zr, T, Z, pc);
+    } else {
+      // the full Schur form (T, Z) for the reordering: the same iteration,
+      // so the same eigenvalue positions
+      T = Aeig;
+      if (!schur(T, Z)) return -1;
     }
     keff = reorder(T, Z, sel);
     Mat Zk(n, keff);

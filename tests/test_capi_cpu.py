@@ -118,3 +118,49 @@ def test_noalloc_sketch_rejects_sizes_beyond_its_scratch():
     assert f(1000, 2048, 8, 1, 2, fake, 1, fake, None) == -1  # complex beyond 1024
     assert f(1000, 240, 8, 1, 1, fake, 1, fake, None) == -1  # FP32 is not a data type here
     assert f(0, 240, 8, 1, 0, fake, 1, fake, None) == -1
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_host_harmonic_ritz_complex_helmholtz_shape(seed):
+    """The size of the complex Helmholtz cycle: ell0 = k + m = 180, s = 360,
+    k = 30 (random data, whose selected eigenvalues need not lead the Schur
+    form)."""
+    from oracle import harmonic_ritz_update
+    from paper_2311_14206_amd.sdr import host_harmonic_ritz
+    s, l0, k = 360, 180, 30
+    SAW, SB = _case(seed, s, l0, True)
+    Q, R = np.linalg.qr(SAW)
+    G, ell, keff = host_harmonic_ritz(R, Q.conj().T @ SB, s, k, True)
+    Go, ello, keffo = harmonic_ritz_update(np.eye(l0), SB, SAW, k, False, s)
+    assert keff == keffo == k and ell == ello
+    assert _angle(G, Go) < 1e-8
+    assert np.linalg.norm(G.conj().T @ G - np.eye(keff)) < 1e-12
+
+
+def test_host_harmonic_ritz_on_helmholtz_cycles():
+    """Two cycles of a complex shifted Helmholtz solve with the full-size
+    m = 150, k = 30, t = 3, s = 360 (the second has ell0 = 180): the library's
+    step spans the oracle's recycle space, to within the first-order
+    perturbation bound of an invariant subspace, eps cond(R) / (relative gap
+    between the k-th and (k+1)-th largest |mu|), with a factor 100."""
+    from oracle import sdr_solve
+    from paper_2311_14206_amd.sdr import host_harmonic_ritz
+    from workloads import helmholtz2d, crandn
+    A = helmholtz2d(96, kappa=40.0).to_scipy()
+    b = crandn(A.shape[0], 3)
+    keep = []
+    sdr_solve(A, b, m=150, k=30, t=3, s=360, tol=1e-14, max_cycles=2, keep_cycles=keep)
+    assert keep[1]["j"] + keep[1]["U_in"].shape[1] == 180
+    for kc in keep:
+        j = kc["j"]
+        SAW = np.concatenate([kc["SAU_in"], kc["SAV"][:, :j]], axis=1)
+        SB = np.concatenate([kc["SU_in"], kc["SV"][:, :j]], axis=1)
+        Q, R = np.linalg.qr(SAW)
+        Cm = Q.conj().T @ SB
+        G, ell, keff = host_harmonic_ritz(R, Cm, 360, 30, True)
+        assert keff == kc["G"].shape[1]
+        mu = np.sort(np.abs(np.linalg.eigvals(np.linalg.solve(R, Cm))))[::-1]
+        bound = 100 * 2.0 ** -52 * np.linalg.cond(R) / ((mu[29] - mu[30]) / mu[29])
+        ang = _angle(G, kc["G"])
+        print(f"ell0 {R.shape[0]}: angle {ang:.1e}, bound {bound:.1e}")
+        assert ang < max(bound, 1e-10)
