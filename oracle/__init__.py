@@ -9,6 +9,8 @@ Contents
 ``sketch``      the sparse-sign sketching operator S (Section 3, eq. (3.1)):
                 an explicit scipy matrix built from a published counter-based
                 generator (SplitMix64 output mixer).
+``srdct``       the subsampled randomised DCT sketch S = sqrt(N/s) P F E of
+                Section 6 (scipy's orthonormal DCT-II).
 ``gmres_sdr``   GMRES-SDR written from Section 3: truncated Arnoldi,
                 sketches, sketched least squares, residual control and the
                 harmonic-Ritz compression as separate parts, composed into a
@@ -18,6 +20,7 @@ Contents
 """
 
 from .sketch import sketch_operator, sketch_pattern, splitmix64_mix  # noqa: F401
+from .srdct import SRDCT, srdct_rows, srdct_signs  # noqa: F401
 from .gmres_sdr import (  # noqa: F401
     Recycle,
     SolveResult,

@@ -50,6 +50,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from .sketch import sketch_operator
+from .srdct import SRDCT
 
 
 @dataclass
@@ -452,7 +453,7 @@ def sdr_solve(A, b, *, x0=None, m: int, k: int, t: int, s: int, zeta: int = 8,
               persist_safety: bool = False, S=None,
               breakdown_rtol: float = 1e-14, rank_rtol: float = 1e-12,
               keep_cycles: list | None = None, resid_control: str = "safety",
-              givens_eps0: float = 0.0) -> SolveResult:
+              givens_eps0: float = 0.0, sketch: str = "sparse_sign") -> SolveResult:
     """Restarted GMRES-SDR for A x = b (relative tolerance ``tol``).
 
     ``recycle`` carries U, SU, SAU from a previous solve; ``new_matrix`` says
@@ -460,6 +461,8 @@ def sdr_solve(A, b, *, x0=None, m: int, k: int, t: int, s: int, zeta: int = 8,
     ``resid_control`` "safety" (Section 3.4) or "givens" (the Givens-rotation
     estimate of Sections 4.5 and 5 with eps fitted to the true residuals,
     starting from ``givens_eps0``; the fitted eps is returned as ``eps``).
+    ``sketch`` "sparse_sign" (zeta nonzeros per column) or "srdct" (the
+    subsampled randomised DCT of Section 6); an explicit ``S`` overrides it.
     """
     if A.dtype.kind == "c" or np.iscomplexobj(b):
         dt = np.complex128
@@ -467,7 +470,12 @@ def sdr_solve(A, b, *, x0=None, m: int, k: int, t: int, s: int, zeta: int = 8,
         dt = np.float64
     N = b.shape[0]
     if S is None:
-        S = sketch_operator(N, s, zeta, seed)
+        if sketch == "srdct":
+            S = SRDCT(N, s, seed)
+        elif sketch == "sparse_sign":
+            S = sketch_operator(N, s, zeta, seed)
+        else:
+            raise ValueError("sketch is 'sparse_sign' or 'srdct'")
     b = np.asarray(b, dtype=dt)
     x = np.zeros(N, dtype=dt) if x0 is None else np.array(x0, dtype=dt)
     cnt: dict = {}

@@ -47,10 +47,11 @@ PINS = [
 ]
 
 
-def _mutant_module(old, new):
-    src = open(SRC).read()
+def _mutant_module(old, new, path=SRC):
+    src = open(path).read()
     assert src.count(old) == 1, old
-    src = src.replace(old, new).replace("from .sketch import", "from oracle.sketch import")
+    src = (src.replace(old, new).replace("from .sketch import", "from oracle.sketch import")
+           .replace("from .srdct import", "from oracle.srdct import"))
     name = "oracle_mutant"
     mod = types.ModuleType(name)
     sys.modules[name] = mod  # dataclasses look their module up here
@@ -131,6 +132,35 @@ def test_givens_mutant_is_caught(name, monkeypatch):
                 gpins.test_eps_refit_reaches_the_observed_residual,
                 gpins.test_givens_control_solution_matches_dense_lu,
                 gpins.test_givens_factor_special_values):
+        try:
+            pin()
+        except Exception:
+            caught = True
+            break
+    assert caught, f"mutant {name} passed every pin"
+
+
+# Planted mistakes in the subsampled randomised DCT sketch, against its pins.
+SRDCT_SRC = os.path.join(os.path.dirname(SRC), "srdct.py")
+SRDCT_MUTANTS = {
+    "scale_dropped": ("self.scale = np.sqrt(N / s)", "self.scale = 1.0"),
+    "signs_not_applied": ("Y = X.reshape(self.N, -1) * self.signs[:, None]", "Y = X.reshape(self.N, -1) * 1.0"),
+    "dct_type_3": ("F = scipy.fft.dct(Y, type=2, norm=\"ortho\", axis=0)",
+                   "F = scipy.fft.dct(Y, type=3, norm=\"ortho\", axis=0)"),
+    "rows_by_largest_key": ("order = np.lexsort((np.arange(N), k))", "order = np.lexsort((np.arange(N), -k))"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SRDCT_MUTANTS))
+def test_srdct_mutant_is_caught(name, monkeypatch):
+    import test_oracle_srdct as spins
+    mod = _mutant_module(*SRDCT_MUTANTS[name], path=SRDCT_SRC)
+    for attr in ("SRDCT", "srdct_rows", "srdct_signs"):
+        monkeypatch.setattr(spins, attr, getattr(mod, attr))
+    caught = False
+    for pin in (spins.test_columns_follow_the_dct_definition,
+                spins.test_signs_and_rows_follow_the_generator,
+                lambda: spins.test_all_rows_kept_is_an_isometry(64)):
         try:
             pin()
         except Exception:
