@@ -138,6 +138,14 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *                    (sdr_get_recycle, sdr_get_basis) belong to A D^-1.
  *                    sdr_spmv and the adjoint solve use A unpreconditioned.
  *                    Default 0, set before the first solve.
+ *   "sketch"         0 (default): the sparse-sign operator (zeta nonzeros
+ *                    per column, drawn from seed); 1: the subsampled
+ *                    randomised DCT S = sqrt(N/s) P F E of Section 6 (F the
+ *                    orthonormal DCT-II, E random signs, P s distinct random
+ *                    rows, all drawn from seed; s_dim <= n, any s_dim).  Set
+ *                    before the first solve.  The DCT sketch costs s
+ *                    multiply-adds per entry (ALU-bound), the sparse sign a
+ *                    few LDS adds.
  *   "resid_control"  0 (default): the safety-factor rule of Section 3.4, a
  *                    true residual once the sketched one is below tol /
  *                    safety; 1: the Givens-rotation estimate of Sections 4.5

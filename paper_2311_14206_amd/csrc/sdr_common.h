@@ -92,6 +92,8 @@ struct SketchSpec {
   int zeta;   // nonzeros per column
   int bsz;    // s / zeta
   int words;  // ceil(zeta / 4)
+  int ext;    // 1: rows 0 .. s-1 are formed by another kernel (the subsampled
+              // DCT); a step kernel keeps the partial layout and fills the rest
 };
 
 }  // namespace sdr

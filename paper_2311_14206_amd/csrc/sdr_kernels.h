@@ -176,6 +176,28 @@ void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr
 template <class A>
 void launch_backsolve(hipStream_t st, LsqState<A> S, int n, int khat, A* ycoef);
 
+// One kept row of the subsampled randomised DCT sketch S = sqrt(N/s) P F E
+// (Section 6): DCT-II frequency p, the cosine and sine of the phase step
+// pi p / N between consecutive entries, and the row's scale sqrt(N/s) c_p.
+struct DctRow {
+  int64_t p;
+  double cb, sb, a;
+};
+struct DctSpec {
+  const DctRow* rows;  // s rows, device
+  int s;
+  int64_t n4;          // 4 N: phases p (2r + 1) are reduced mod 4N exactly
+  double ang;          // pi / (2N)
+  uint64_t sign_seed;  // seed of E's signs (SplitMix64 keys, bit 0)
+};
+
+// S x for the subsampled DCT: per-tile partial sums (tiles of kRowsSpmv rows,
+// those of the step kernels) into rows 0 .. s-1 of part, the rows already
+// scaled; with with_norm also ||x||^2 into row s (nb = ceil(n / kRowsSpmv)).
+template <class X>
+void launch_dct_sketch(hipStream_t st, int n, const X* x, DctSpec d, typename traits<X>::acc* part, int nb,
+                       bool with_norm, const Ctrl* ctrl);
+
 // Batched sketch of cc columns of X (ld) plus column norms: partials
 // [(cc*s + cc) x nb], then reduced by launch_reduce_cols.
 template <class X>

@@ -184,9 +184,10 @@ __device__ __forceinline__ void put_re(cx<double>* p, double v) { *p = cx<double
 // and a fixed-order sum over the waves: the same operations in the same
 // order as one block_sum per value, with one barrier instead of three each.
 template <class A, int NW = kWaves, int NT = kBlock>  // NW waves, NT threads per block
-__device__ __forceinline__ void store_step_partials(A* __restrict__ part, int nb, int tile, int s, int tw,
-                                                    const A* bins_all, double nx, const A (&d)[kMaxWindow],
-                                                    double nw, A (*wsum)[kMaxWindow + 2]) {
+__device__ __forceinline__ void store_step_partials(A* __restrict__ part, int nb, int tile, int s, int sb,
+                                                    int tw, const A* bins_all, double nx,
+                                                    const A (&d)[kMaxWindow], double nw,
+                                                    A (*wsum)[kMaxWindow + 2]) {
   constexpr int NV = kMaxWindow + 2;
   {
     A v[NV];
@@ -201,9 +202,10 @@ __device__ __forceinline__ void store_step_partials(A* __restrict__ part, int nb
       for (int i = 0; i < NV; ++i) wsum[threadIdx.x >> 6][i] = v[i];
   }
   __syncthreads();
-  for (int row = threadIdx.x; row < s; row += NT) {
+  // (sb = 0: the sketch rows are another kernel's)
+  for (int row = threadIdx.x; row < sb; row += NT) {
     A sum = bins_all[row];
-    for (int q = 1; q < NW; ++q) sum += bins_all[q * s + row];
+    for (int q = 1; q < NW; ++q) sum += bins_all[q * sb + row];
     part[(int64_t)row * nb + tile] = sum;
   }
   // thread i < tw + 2 writes value i: ||x||^2 (when sketching) at row s, the
@@ -249,10 +251,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sketch(
   if (ctrl->halt) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = sk.s;  // 0: no sketch
+  const int sb = sk.ext ? 0 : s;  // sketch bins of this kernel
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  A* bins = reinterpret_cast<A*>(smem_raw) + wv * s;                   // this wave's sketch [s]
-  A* prod = reinterpret_cast<A*>(smem_raw) + kWaves * s + wv * wave_cap;  // this wave's staging
-  for (int i = lane; i < s; i += 64) bins[i] = zero<A>();
+  A* bins = reinterpret_cast<A*>(smem_raw) + wv * sb;                   // this wave's sketch [sb]
+  A* prod = reinterpret_cast<A*>(smem_raw) + kWaves * sb + wv * wave_cap;  // this wave's staging
+  for (int i = lane; i < sb; i += 64) bins[i] = zero<A>();
   A d[kMaxWindow];
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) d[q] = zero<A>();
@@ -318,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sketch(
     if (in) {
       if (s > 0) {
         nx += abs2(xa);
-        sketch_scatter(bins, r, xa, sk);
+        if (sb > 0) sketch_scatter(bins, r, xa, sk);
       }
       if (do_spmv) {
         const T wt = narrow<T>(acc);
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sketch(
     }
   }
   __shared__ A wsum[kWaves][kMaxWindow + 2];
-  store_step_partials(part, nb, tile, s, tw, reinterpret_cast<const A*>(smem_raw), nx, d, nw, wsum);
+  store_step_partials(part, nb, tile, s, sb, tw, reinterpret_cast<const A*>(smem_raw), nx, d, nw, wsum);
 }
 
 template <class T>
@@ -349,8 +352,9 @@ void launch_spmv_sketch(hipStream_t st, int n, const int* rp, const int* ci, con
                         typename traits<T>::acc* part, int nb, const Ctrl* ctrl, hipEvent_t e0,
                         hipEvent_t e1) {
   using A = typename traits<T>::acc;
-  const int cap = spmv ? spmv_wave_cap<T>(sk.s) : 0;
-  const size_t lds = ((size_t)kWaves * sk.s + (size_t)kWaves * cap) * sizeof(A);
+  const int sb = sk.ext ? 0 : sk.s;
+  const int cap = spmv ? spmv_wave_cap<T>(sb) : 0;
+  const size_t lds = ((size_t)kWaves * sb + (size_t)kWaves * cap) * sizeof(A);
   const int dsp = spmv ? 1 : 0;
   if (e0)  // events recorded by the dispatch itself: the kernel's own duration
     hipExtLaunchKernelGGL(k_spmv_sketch<T>, dim3(nb), dim3(kBlock), lds, st, e0, e1, 0, n, rp, ci, val,
@@ -382,8 +386,9 @@ __global__ __launch_bounds__(NT) void k_spmv_dia_sketch(
   const int halted = ctrl->halt;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = sk.s;  // 0: no sketch
-  A* bins = reinterpret_cast<A*>(smem_raw) + (threadIdx.x >> 6) * s;
-  for (int i = threadIdx.x & 63; i < s; i += 64) bins[i] = zero<A>();
+  const int sb = sk.ext ? 0 : s;  // sketch bins of this kernel
+  A* bins = reinterpret_cast<A*>(smem_raw) + (threadIdx.x >> 6) * sb;
+  for (int i = threadIdx.x & 63; i < sb; i += 64) bins[i] = zero<A>();
   A d[kMaxWindow];
 #pragma unroll
   for (int q = 0; q < kMaxWindow; ++q) d[q] = zero<A>();
@@ -396,7 +401,7 @@ __global__ __launch_bounds__(NT) void k_spmv_dia_sketch(
       const A xa = widen(x[r]);
       if (halted) return;
       nx += abs2(xa);
-      sketch_scatter(bins, r, xa, sk);
+      if (sb > 0) sketch_scatter(bins, r, xa, sk);
     }
   } else {
     const int nd = ND > 0 ? ND : M.ndiag;
@@ -420,7 +425,7 @@ __global__ __launch_bounds__(NT) void k_spmv_dia_sketch(
       const A xa = widen(xt);
       if (s > 0) {
         nx += abs2(xa);
-        sketch_scatter(bins, r, xa, sk);
+        if (sb > 0) sketch_scatter(bins, r, xa, sk);
       }
       A acc = zero<A>();
 #pragma unroll
@@ -442,7 +447,8 @@ __global__ __launch_bounds__(NT) void k_spmv_dia_sketch(
   }
   if (halted) return;
   __shared__ A wsum[NT / 64][kMaxWindow + 2];
-  store_step_partials<A, NT / 64, NT>(part, nb, tile, s, tw, reinterpret_cast<const A*>(smem_raw), nx, d, nw, wsum);
+  store_step_partials<A, NT / 64, NT>(part, nb, tile, s, sb, tw, reinterpret_cast<const A*>(smem_raw), nx, d,
+                                      nw, wsum);
 }
 
 template <class T>
@@ -452,10 +458,11 @@ void launch_spmv_dia_sketch(hipStream_t st, int n, DiaView<T> M, const T* x, T* 
   using A = typename traits<T>::acc;
   // 8 waves per block when their sketch bins fit the LDS budget, else 4 (the
   // generic instantiation); sdr_create keeps 4 waves' bins within it
+  const int sb = sk.ext ? 0 : sk.s;
   const bool wide =
-      (size_t)(kSpmvThreads / 64) * (sk.s + kMaxWindow + 2) * sizeof(A) <= (size_t)kSpmvLds;  // bins + wsum
+      (size_t)(kSpmvThreads / 64) * (sb + kMaxWindow + 2) * sizeof(A) <= (size_t)kSpmvLds;  // bins + wsum
   const int nt = wide ? kSpmvThreads : kBlock;
-  const size_t lds = (size_t)(nt / 64) * sk.s * sizeof(A);
+  const size_t lds = (size_t)(nt / 64) * sb * sizeof(A);
   const int dsp = spmv ? 1 : 0;
   void (*kern)(int, DiaView<T>, const T*, T*, Window<T>, int, SketchSpec, int, A*, int, const Ctrl*);
   if (!wide) {
@@ -1580,6 +1587,94 @@ void launch_sketch_cols(hipStream_t st, int n, const X* x, int64_t ld, int cc, S
   hipLaunchKernelGGL(k_sketch_cols<X>, dim3(nb), dim3(kBlock), lds, st, n, x, ld, cc, sk, part, nb);
 }
 
+// ----------------------------------- subsampled randomised DCT sketch ---
+// y_i = a_i sum_r e_r x_r cos(pi p_i (2r + 1) / (2N)) over a tile of
+// kRowsSpmv rows per block: the tile's e_r x_r is staged in LDS in sub-tiles
+// of kDctSub rows; thread f owns frequencies f, f + kBlock, ...  At each
+// sub-tile start the phase pi p (2 r0 + 1) / (2N) is reduced exactly in
+// integers (mod 4N) and its cosine and sine taken; inside the sub-tile the
+// cosine advances by a rotation through pi p / N (error O(kDctSub eps)).
+// The work is s multiply-adds and rotations per entry: ALU-bound.
+constexpr int kDctSub = kBlock;     // rows staged per sub-tile
+constexpr int kDctMaxFpt = 8;       // frequencies per thread (s <= 2048)
+
+template <class X>
+__global__ __launch_bounds__(kBlock) void k_dct_sketch(int n, const X* __restrict__ x, DctSpec d,
+                                                       typename traits<X>::acc* __restrict__ part, int nb,
+                                                       int with_norm, const Ctrl* __restrict__ ctrl) {
+  using A = typename traits<X>::acc;
+  if (ctrl && ctrl->halt) return;
+  __shared__ A v[kDctSub];
+  __shared__ double red[kWaves];
+  const int tile = xcd_tile(blockIdx.x, nb);
+  const int r0 = tile * kRowsSpmv;
+  const int r1 = min(n, r0 + kRowsSpmv);
+  const int fpt = (d.s + kBlock - 1) / kBlock;
+  A acc[kDctMaxFpt];
+#pragma unroll
+  for (int k = 0; k < kDctMaxFpt; ++k) acc[k] = zero<A>();
+  double nx = 0.0;
+  for (int q0 = r0; q0 < r1; q0 += kDctSub) {
+    const int r = q0 + (int)threadIdx.x;
+    A e = zero<A>();
+    if (r < r1) {
+      const A xv = widen(x[r]);
+      nx += abs2(xv);
+      const uint64_t h = mix64(d.sign_seed + kGamma * (uint64_t)(r + 1));
+      e = neg_if(xv, (h & 1ull) != 0ull);
+    }
+    __syncthreads();  // (the previous sub-tile's reads are done)
+    v[threadIdx.x] = e;
+    __syncthreads();
+    const int len = min(kDctSub, r1 - q0);
+#pragma unroll
+    for (int k = 0; k < kDctMaxFpt; ++k) {
+      if (k >= fpt) break;
+      const int f = (int)threadIdx.x + k * kBlock;
+      if (f < d.s) {
+        const DctRow w = d.rows[f];
+        const uint64_t ph = ((uint64_t)w.p * (uint64_t)(2 * q0 + 1)) % (uint64_t)d.n4;
+        double sn, cs;
+        sincos((double)ph * d.ang, &sn, &cs);
+        A a = acc[k];
+        int q = 0;
+        for (; q + 4 <= len; q += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a += v[q + u] * cs;
+            const double c2 = cs * w.cb - sn * w.sb;
+            sn = sn * w.cb + cs * w.sb;
+            cs = c2;
+          }
+        }
+        for (; q < len; ++q) {
+          a += v[q] * cs;
+          const double c2 = cs * w.cb - sn * w.sb;
+          sn = sn * w.cb + cs * w.sb;
+          cs = c2;
+        }
+        acc[k] = a;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kDctMaxFpt; ++k) {
+    const int f = (int)threadIdx.x + k * kBlock;
+    if (k < fpt && f < d.s) part[(int64_t)f * nb + tile] = scale(acc[k], d.rows[f].a);
+  }
+  if (with_norm) {
+    const double t = block_sum(nx, red);
+    if (threadIdx.x == 0) put_re(&part[(int64_t)d.s * nb + tile], t);
+  }
+}
+
+template <class X>
+void launch_dct_sketch(hipStream_t st, int n, const X* x, DctSpec d, typename traits<X>::acc* part, int nb,
+                       bool with_norm, const Ctrl* ctrl) {
+  hipLaunchKernelGGL(k_dct_sketch<X>, dim3(nb), dim3(kBlock), 0, st, n, x, d, part, nb, with_norm ? 1 : 0,
+                     ctrl);
+}
+
 // ------------------------------------------------- tall-skinny products ---
 // acc + sum_i X(r, i) y_i over nc columns, in column order, eight loads in
 // flight per round.
@@ -2164,6 +2259,8 @@ void launch_scale_by_diag(hipStream_t st, int n, const A* d, A* x, bool divide) 
                                  int, double*, int, int, const Ctrl*, hipEvent_t, hipEvent_t);    \
   template void launch_sketch_cols<T>(hipStream_t, int, const T*, int64_t, int, SketchSpec,       \
                                       traits<T>::acc*, int);                                      \
+  template void launch_dct_sketch<T>(hipStream_t, int, const T*, DctSpec, traits<T>::acc*, int, bool, \
+                                     const Ctrl*);                                                \
   template void launch_gemv_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
                                      int, const traits<T>::acc*, traits<T>::acc*);                \
   template void launch_gemm_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \

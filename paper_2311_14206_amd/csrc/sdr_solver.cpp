@@ -92,6 +92,7 @@ struct Options {
   int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
   int precond = 0;        // 0: none; 1: right Jacobi, the forward solve runs on A D^-1
   int resid_control = 0;  // 0: safety factor (Section 3.4); 1: Givens estimate (Sections 4.5, 5)
+  int sketch = 0;         // 0: sparse sign; 1: subsampled randomised DCT (Section 6)
   double givens_eps0 = 0.0;  // initial eps of the Givens estimate
 };
 
@@ -178,6 +179,11 @@ class Solver final : public SolverBase {
     sk_.zeta = opt.zeta;
     sk_.bsz = s / opt.zeta;
     sk_.words = (opt.zeta + 3) / 4;
+    dct_on_ = opt.sketch == 1;
+    sk_.ext = dct_on_ ? 1 : 0;
+    // the sparse sign's sums are scaled by 1/sqrt(zeta) when reduced; the DCT
+    // kernel scales its own rows
+    sk_scl_ = dct_on_ ? 1.0 : 1.0 / std::sqrt((double)opt.zeta);
     brtol_ = opt.brtol >= 0.0 ? opt.brtol : (kSame ? 1e-14 : 1e-6);
     nb1_ = (n_ + kRowsSpmv - 1) / kRowsSpmv;
     nb2_ = (n_ + kRowsUpdate - 1) / kRowsUpdate;
@@ -216,6 +222,7 @@ class Solver final : public SolverBase {
       red0_ = dalloc<A>(s + 1);
       psk_ = dalloc<A>((size_t)(8 * s + 8 + 1) * nb2_);
       red2_ = dalloc<A>(8 * s + 8 + 1);
+      if (dct_on_) build_dct(seed);
       HIPCHK(hipStreamCreateWithFlags(&streamB_, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&ev_copy_, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&ev_res_, hipEventDisableTiming));
@@ -335,17 +342,70 @@ class Solver final : public SolverBase {
     return valB_;
   }
 
+  // The subsampled randomised DCT S = sqrt(N/s) P F E (Section 6): the kept
+  // rows P are the s indices with the smallest SplitMix64 keys of seed ^
+  // kDctRowSalt (ties by index), in increasing order; E's sign of row r is
+  // bit 0 of the key of seed ^ kDctSignSalt.  Per kept row the kernel needs
+  // its frequency, the phase step pi p / N and the scale sqrt(N/s) c_p.
+  void build_dct(uint64_t seed) {
+    static constexpr uint64_t kDctSignSalt = 0x5851F42D4C957F2Dull;
+    static constexpr uint64_t kDctRowSalt = 0x14057B7EF767814Full;
+    if (s_ > n_) {
+      set_err("the subsampled DCT sketch needs s_dim <= n");
+      throw HipError{SDR_EINVAL};
+    }
+    std::vector<std::pair<uint64_t, int>> keys(n_);
+    const uint64_t base = seed ^ kDctRowSalt;
+    for (int i = 0; i < n_; ++i) keys[i] = {mix64(base + kGamma * (uint64_t)(i + 1)), i};
+    std::nth_element(keys.begin(), keys.begin() + (s_ - 1), keys.end());
+    std::vector<int> rows(s_);
+    for (int i = 0; i < s_; ++i) rows[i] = keys[i].second;
+    std::sort(rows.begin(), rows.end());
+    std::vector<DctRow> h(s_);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < s_; ++i) {
+      const int p = rows[i];
+      const double step = pi * (double)p / (double)n_;
+      h[i].p = p;
+      h[i].cb = std::cos(step);
+      h[i].sb = std::sin(step);
+      h[i].a = std::sqrt((double)n_ / s_) * (p == 0 ? std::sqrt(1.0 / n_) : std::sqrt(2.0 / n_));
+    }
+    dct_rows_ = dalloc<DctRow>(s_);
+    HIPCHK(hipMemcpy(dct_rows_, h.data(), sizeof(DctRow) * s_, hipMemcpyHostToDevice));
+    dct_.rows = dct_rows_;
+    dct_.s = s_;
+    dct_.n4 = 4 * (int64_t)n_;
+    dct_.ang = pi / (2.0 * n_);
+    dct_.sign_seed = seed ^ kDctSignSalt;
+  }
+
   // out[c] = S X(:, c) for c < nc (X with leading dimension n), norms^2 in nrm2.
   template <class X>
   void sketch_cols(const X* x, int nc, A* out, int ldo, double* nrm2) {
     sr_of_ = nullptr;  // (the partials below replace a residual's sketch)
+    if (dct_on_) {
+      for (int c = 0; c < nc; ++c) {
+        launch_dct_sketch<X>(stream_, n_, x + (size_t)c * n_, dct_, psk_, nb1_, true, nullptr);
+        LAUNCHCHK();
+        launch_reduce_cols<A>(stream_, psk_, nb1_, s_ + 1, s_, 1.0, red2_, nullptr);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(out + (size_t)c * ldo, red2_, sizeof(A) * s_, hipMemcpyDeviceToDevice, stream_));
+        if (nrm2) {
+          HIPCHK(hipMemcpyAsync(hscal_, red2_ + s_, sizeof(A), hipMemcpyDeviceToHost, stream_));
+          HIPCHK(hipStreamSynchronize(stream_));
+          nrm2[c] = to_double_re(hscal_[0]);
+        }
+      }
+      return;
+    }
     const int maxcc = std::max(1, std::min(8, (int)(48 * 1024 / (kWaves * s_ * sizeof(A)))));
     for (int c0 = 0; c0 < nc; c0 += maxcc) {
       const int cc = std::min(maxcc, nc - c0);
       launch_sketch_cols<X>(stream_, n_, x + (size_t)c0 * n_, (int64_t)n_, cc, sk_, psk_, nb2_);
       LAUNCHCHK();
       launch_reduce_cols<A>(stream_, psk_, nb2_, cc * s_ + cc, cc * s_,
-                            1.0 / std::sqrt((double)sk_.zeta), red2_, nullptr);
+                            sk_scl_, red2_, nullptr);
       LAUNCHCHK();
       for (int c = 0; c < cc; ++c)
         HIPCHK(hipMemcpyAsync(out + (size_t)(c0 + c) * ldo, red2_ + (size_t)c * s_, sizeof(A) * s_,
@@ -371,7 +431,7 @@ class Solver final : public SolverBase {
     // The residual kernel also sketches r (when its bins fit), so that a
     // cycle starting from r reduces these partials instead of sketching r
     // in a pass of its own.
-    const bool fuse = (size_t)kWaves * s_ * sizeof(A) <= 48 * 1024;
+    const bool fuse = !dct_on_ && (size_t)kWaves * s_ * sizeof(A) <= 48 * 1024;
     SketchSpec skr = sk_;
     if (!fuse) skr.s = 0;
     if constexpr (std::is_same<T, A>::value) {
@@ -437,6 +497,12 @@ class Solver final : public SolverBase {
       // sketch of p_m only (the diagonal-storage kernel's sketch pass needs far
       // less LDS than the CSR kernel's staging, so more of its blocks run at once)
       Window<T> none{};
+      if (dct_on_) {  // S p_m and ||p_m||^2 by the DCT kernel
+        launch_dct_sketch<T>(stream_, n_, x, dct_, p1, nb1_, true, ctrl_);
+        LAUNCHCHK();
+        HIPCHK(hipEventRecord(evs_[sl], stream_));
+        return;
+      }
       if (dia())
         launch_spmv_dia_sketch<T>(stream_, n_, dia_, x, nullptr, none, 0, sk_, false, p1, nb1_, ctrl_);
       else
@@ -460,6 +526,10 @@ class Solver final : public SolverBase {
       launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
                             tm ? te[0] : nullptr, tm ? te[1] : nullptr);
     LAUNCHCHK();
+    if (dct_on_) {  // S p_{j-1} into the sketch rows the step kernel left alone
+      launch_dct_sketch<T>(stream_, n_, x, dct_, p1, nb1_, false, ctrl_);
+      LAUNCHCHK();
+    }
     if (ev) HIPCHK(hipEventRecord(evs_[sl], stream_));
     launch_update<T>(stream_, n_, w, win, tw, p1, nb1_, s_, nu_, i0, j - 1, ctrl_,
                      tm ? te[2] : nullptr, tm ? te[3] : nullptr);
@@ -509,7 +579,7 @@ class Solver final : public SolverBase {
   void enqueue_chunk(int j0, int j1) {
     HIPCHK(hipStreamWaitEvent(streamB_, evs_[(j1 + 1) % nslot_], 0));
     launch_reduce_steps<A>(streamB_, part1_, (int64_t)slot1_, nb1_, s_, j0, j1, t_, nslot_,
-                           1.0 / std::sqrt((double)sk_.zeta), redb_, (int64_t)slotr_, ctrl_);
+                           sk_scl_, redb_, (int64_t)slotr_, ctrl_);
     launch_lsq_steps<A>(streamB_, lsq(), j0, j1, khat_, m_, t_, s_, redb_, (int64_t)slotr_, nslot_,
                         brtol_, opt_.rank_rtol);
     LAUNCHCHK();
@@ -919,7 +989,7 @@ class Solver final : public SolverBase {
     SB_ = SBbuf_[cur_];
     SAW_ = SAWbuf_[cur_];
     if (sr_of_ == r0) {  // sketched by the residual kernel that formed r0
-      launch_reduce_cols<A>(stream_, psk_, nb2_, s_, s_, 1.0 / std::sqrt((double)sk_.zeta), Sr_, nullptr);
+      launch_reduce_cols<A>(stream_, psk_, nb2_, s_, s_, sk_scl_, Sr_, nullptr);
       LAUNCHCHK();
     } else {
       sketch_cols<A>(r0, 1, Sr_, s_, nullptr);
@@ -935,7 +1005,7 @@ class Solver final : public SolverBase {
     enqueue_step_a(1, vals, true);
     HIPCHK(hipStreamWaitEvent(streamB_, evs_[1 % nslot_], 0));
     launch_reduce_cols<A>(streamB_, part1_ + slot1_ * (1 % nslot_), nb1_, s_ + 1, s_,
-                          1.0 / std::sqrt((double)sk_.zeta), red0_, nullptr);
+                          sk_scl_, red0_, nullptr);
     launch_init_v0<A>(streamB_, red0_, s_, SB_ + (size_t)kmax_ * s_, nu_);
     LAUNCHCHK();
   }
@@ -1169,7 +1239,7 @@ class Solver final : public SolverBase {
                     (void*)nu_, (void*)sres_hist_, (void*)ctrl_, (void*)ctrl_free_, (void*)part1_,
                     (void*)redb_, (void*)psk_, (void*)red2_, (void*)red3_, (void*)Sr_,
                     (void*)ycoef_, (void*)xt_, (void*)r_, (void*)rnew_, (void*)G_, (void*)Gs_,
-                    (void*)C_})
+                    (void*)C_, (void*)dct_rows_})
       dfree(p);
     if (rec_host_) (void)hipHostFree(rec_host_);
     rec_host_ = nullptr;
@@ -1237,6 +1307,10 @@ class Solver final : public SolverBase {
   double *nu_ = nullptr, *sres_hist_ = nullptr;
   Ctrl *ctrl_ = nullptr, *ctrl_free_ = nullptr;
   const A* sr_of_ = nullptr;  // the vector whose sketch partials psk_ holds (rows 0 .. s-1)
+  bool dct_on_ = false;       // subsampled randomised DCT sketch (option "sketch")
+  double sk_scl_ = 1.0;       // scale of the reduced sketch rows
+  DctRow* dct_rows_ = nullptr;
+  DctSpec dct_{};
   A *part1_ = nullptr, *redb_ = nullptr, *psk_ = nullptr, *red2_ = nullptr, *red3_ = nullptr,
     *red0_ = nullptr;
   int nslot_ = 0;
@@ -1404,7 +1478,7 @@ void precond_scale(sdr_handle* h, void* x, bool to_u) {
 }
 
 SolverBase* fwd(sdr_handle* h) {
-  if (h->s % h->opt.zeta != 0) {
+  if (h->opt.sketch == 0 && h->s % h->opt.zeta != 0) {
     set_err("s_dim must be a multiple of zeta");
     throw HipError{SDR_EINVAL};
   }
@@ -1592,6 +1666,10 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
   } else if (k == "precond") {
     if (built || (v != 0.0 && v != 1.0)) return set_err("precond is 0 or 1, before the first solve"), SDR_EINVAL;
     h->opt.precond = (int)v;
+  } else if (k == "sketch") {
+    if (built || (v != 0.0 && v != 1.0))
+      return set_err("sketch is 0 (sparse sign) or 1 (subsampled DCT), before the first solve"), SDR_EINVAL;
+    h->opt.sketch = (int)v;
   } else if (k == "resid_control") {
     if (v != 0.0 && v != 1.0) return set_err("resid_control is 0 (safety) or 1 (Givens)"), SDR_EINVAL;
     h->opt.resid_control = (int)v;
@@ -1691,7 +1769,8 @@ int sdr_solve_adjoint(sdr_handle* h, const void* g, void* lam, double tol, sdr_s
       build_adjoint(h);
       refresh_adjoint_values(h);
     }
-    if (h->s % h->opt.zeta != 0) return set_err("s_dim must be a multiple of zeta"), SDR_EINVAL;
+    if (h->opt.sketch == 0 && h->s % h->opt.zeta != 0)
+      return set_err("s_dim must be a multiple of zeta"), SDR_EINVAL;
     if (!h->adj) h->adj = make_solver(h, true);
     std::vector<sdr_cycle_record> tr;
     order_after_caller(h);
