@@ -31,7 +31,10 @@ in HBM before the timed region.  Prints one JSON line:
   bandwidth (its per-step working set exceeds the 256 MB last-level cache);
 * helmholtz: the complex shifted Helmholtz system (1024^2) to 1e-8 in
   complex128 and with the complex64 basis: time, steps, host eigen-step time,
-  the host residual and the first cycle's x against the oracle's.
+  the host residual and the first cycle's x against the oracle's;
+* srdct: the 1024^2 solve with the subsampled randomised DCT sketch of
+  Section 6: time, steps, host residual, first-cycle x against the oracle's,
+  and the DCT kernel's duration against the FP64 vector issue rate.
 
     python bench.py --summarize-pmc FETCH.csv WRITE.csv --copy-calib-mb 256
 
@@ -400,6 +403,69 @@ def sequence_bench(dev, with_oracle=True):
     return out
 
 
+FP64_VALU_GOPS = 256 * 64 * 2.4  # FP64 vector lane-operations per ns: 78.6 TFLOP/s counts an FMA as 2
+
+
+def srdct_bench(dev, with_oracle=True, reps=2):
+    """The 1024^2 solve with the subsampled randomised DCT sketch (Section 6)."""
+    import numpy as np
+    import torch
+    from paper_2311_14206_amd.sdr import SDRSolver
+    from workloads import workload, describe
+
+    name = "cd2d_1024"
+    A, b, p = workload(name)
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_idx).to(dev)
+    vals = torch.from_numpy(A.values).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    h = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"], sketch=1,
+                  kernel_timing=64)
+    h.solve(bd, tol=p["tol"])  # warm-up
+    h.kernel_times()
+    times, st, x = [], None, None
+    for _ in range(reps):
+        h.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = h.solve(bd, tol=p["tol"])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    kt = h.kernel_times()
+    xh = x.cpu().numpy()
+    relres = float(np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b))
+    n_l = max(kt["launches"], 1)
+    dct_us = 1e3 * kt["dct_sketch_ms"] / n_l
+    # per entry and kept row: one multiply-add and the rotation's two
+    # multiplies and two multiply-adds, FP64 lane operations
+    ops = 5.0 * p["s"] * A.n
+    out = {"workload": describe(name) + ", subsampled randomised DCT sketch",
+           "time_to_tol_s": statistics.median(times), "times": times, "iters": st["iters"],
+           "cycles": st["cycles"], "converged": st["converged"], "relres_host": relres,
+           "dct_kernel": {"avg_us": dct_us, "bound": "alu",
+                          "achieved_gops": ops / (dct_us * 1e3) if dct_us > 0 else None,
+                          "peak_gops": FP64_VALU_GOPS,
+                          "frac": ops / (dct_us * 1e3) / FP64_VALU_GOPS if dct_us > 0 else None,
+                          "ops_per_launch": ops, "launches": kt["launches"]},
+           "spmv_avg_us": 1e3 * kt["spmv_sketch_ms"] / n_l, "step_avg_us": 1e3 * kt["step_ms"] / n_l}
+    print(f"[bench] DCT sketch: {statistics.median(times):.3f} s, {st['iters']} steps, DCT kernel "
+          f"{dct_us:.1f} us, relres {relres:.2e}", file=sys.stderr, flush=True)
+    h1 = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"], sketch=1,
+                   max_cycles=1)
+    x1, _ = h1.solve(bd, tol=p["tol"])
+    x1 = x1.cpu().numpy()
+    h.close()
+    h1.close()
+    if with_oracle:
+        from oracle import sdr_solve
+        t0 = time.perf_counter()
+        r = sdr_solve(A.to_scipy(), b, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
+                      tol=p["tol"], max_cycles=1, sketch="srdct")
+        out["oracle_first_cycle_seconds"] = time.perf_counter() - t0
+        out["first_cycle_x_err_vs_oracle"] = float(np.linalg.norm(x1 - r.x) / np.linalg.norm(r.x))
+    return out
+
+
 def helmholtz_bench(dev, with_oracle=True, reps=2):
     """The complex Helmholtz system in complex128 and with the complex64 basis."""
     import numpy as np
@@ -465,6 +531,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the sequence and Helmholtz measurements (profiling runs)")
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--sketch", type=int, default=0,
+                    help="0: sparse sign; 1: subsampled randomised DCT (profiling runs)")
     ap.add_argument("--timing-every", type=int, default=64,
                     help="time the SpMV and update kernels of every n-th Arnoldi step with HIP "
                          "events (events between kernels cost launch gaps; 1 times all)")
@@ -503,7 +571,8 @@ def main():
     vals = torch.from_numpy(A.values).to(dev)
     bd = torch.from_numpy(b).to(dev)
     h = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
-                  zeta=p["zeta"], kernel_timing=args.timing_every, precision=args.precision)
+                  zeta=p["zeta"], kernel_timing=args.timing_every, precision=args.precision,
+                  sketch=args.sketch)
     if args.copy_calib_mb:
         src = torch.ones(args.copy_calib_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -553,7 +622,7 @@ def main():
         # generic 256-thread one)
         if 8 * (p["s"] + 6) * 8 <= 64 * 1024:
             k1_key = (f"k_spmv_dia_sketch<{tname}, {len(layout) if len(layout) in (3, 5, 7, 9) else 0}, "
-                      f"{2 if p['t'] <= 2 else 4}, 512>")
+                      f"{2 if p['t'] <= 2 else 3 if p['t'] == 3 else 4}, 512>")
         else:
             k1_key = f"k_spmv_dia_sketch<{tname}, 0, 4, 256>"
         k1_bytes = sum(hist[tw] * spmv_dia_sketch_bytes(N, len(layout), tw, p=pb, pv=pb)
@@ -623,6 +692,8 @@ def main():
         line["sequence"] = sequence_bench(dev, with_oracle=not args.no_cpu_baseline)
         torch.cuda.empty_cache()
         line["helmholtz"] = helmholtz_bench(dev, with_oracle=not args.no_cpu_baseline)
+        torch.cuda.empty_cache()
+        line["srdct"] = srdct_bench(dev, with_oracle=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(A, b, p, st["iters"])

@@ -272,9 +272,10 @@ int sdr_reset(sdr_handle* h);
  * Per-step kernel timings gathered with HIP events on the handle's stream
  * when the option "kernel_timing" is n > 0 (one step in n), accumulated since the last call and
  * then cleared.  ms[0]: SpMV + window products + sketch kernel, ms[1]:
- * orthogonalisation update kernel, ms[2]: both kernels of the step, from the
- * start of the first to the end of the second (the least squares runs on a
- * second stream).  counts[0..2]: launches timed; counts[3 + tw]:
+ * orthogonalisation update kernel, ms[2]: the kernels of the step, from the
+ * start of the first to the end of the update (the least squares runs on a
+ * second stream), ms[3]: the subsampled-DCT sketch kernel (option sketch=1,
+ * launched between them; 0 otherwise).  counts[0..2]: launches timed; counts[3 + tw]:
  * steps whose truncation window held tw vectors (tw <= 4).  cap is the
  * length of both arrays (8 covers everything).
  */

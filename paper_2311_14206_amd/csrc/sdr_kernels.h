@@ -177,11 +177,16 @@ template <class A>
 void launch_backsolve(hipStream_t st, LsqState<A> S, int n, int khat, A* ycoef);
 
 // One kept row of the subsampled randomised DCT sketch S = sqrt(N/s) P F E
-// (Section 6): DCT-II frequency p, the cosine and sine of the phase step
-// pi p / N between consecutive entries, and the row's scale sqrt(N/s) c_p.
+// (Section 6), with what its kernel needs to run the cosines cos(phi + q b)
+// along the entries, b = pi p / N, by Reinsch's two-term recurrence (c += d,
+// d -= lam c): for b <= pi/2 directly; for b > pi/2 as (-1)^q cos(phi - q b')
+// with b' = pi - b, so that lam = 4 sin^2(b'/2) stays small.  sh, ch: sin and
+// cos of b'/2; a: the row's scale sqrt(N/s) c_p; out: its output row (rows
+// are processed grouped by mode).
 struct DctRow {
   int64_t p;
-  double cb, sb, a;
+  double lam, sh, ch, a;
+  int32_t out, mode;  // mode 1: the alternating form (b > pi/2)
 };
 struct DctSpec {
   const DctRow* rows;  // s rows, device
@@ -196,7 +201,7 @@ struct DctSpec {
 // scaled; with with_norm also ||x||^2 into row s (nb = ceil(n / kRowsSpmv)).
 template <class X>
 void launch_dct_sketch(hipStream_t st, int n, const X* x, DctSpec d, typename traits<X>::acc* part, int nb,
-                       bool with_norm, const Ctrl* ctrl);
+                       bool with_norm, const Ctrl* ctrl, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Batched sketch of cc columns of X (ld) plus column norms: partials
 // [(cc*s + cc) x nb], then reduced by launch_reduce_cols.

@@ -475,6 +475,14 @@ void launch_spmv_dia_sketch(hipStream_t st, int n, DiaView<T> M, const T* x, T* 
       case 9: kern = k_spmv_dia_sketch<T, 9, 2, kSpmvThreads>; break;
       default: kern = k_spmv_dia_sketch<T, 0, 2, kSpmvThreads>; break;
     }
+  } else if (tw <= 3) {
+    switch (M.ndiag) {
+      case 3: kern = k_spmv_dia_sketch<T, 3, 3, kSpmvThreads>; break;
+      case 5: kern = k_spmv_dia_sketch<T, 5, 3, kSpmvThreads>; break;
+      case 7: kern = k_spmv_dia_sketch<T, 7, 3, kSpmvThreads>; break;
+      case 9: kern = k_spmv_dia_sketch<T, 9, 3, kSpmvThreads>; break;
+      default: kern = k_spmv_dia_sketch<T, 0, 3, kSpmvThreads>; break;
+    }
   } else {
     switch (M.ndiag) {
       case 3: kern = k_spmv_dia_sketch<T, 3, kMaxWindow, kSpmvThreads>; break;
@@ -510,7 +518,7 @@ void launch_pack_dia(hipStream_t st, int64_t nnz, const typename traits<T>::acc*
 // uses.  Then p_j = (w - sum c_q p_q) / nu_{j-1} in place with
 // c_q = <p_q, w> / nu_q^2: a pure stream over w and the window vectors, each
 // thread with kUpdateRows independent rows in flight.
-template <class T, int TWM>  // TWM: bound on the window length tw
+template <class T, int TWM, int UR>  // TWM: bound on the window length tw; UR rows per thread
 __global__ __launch_bounds__(kBlock) void k_update(
     int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ part,
     int nb1, int s, double* __restrict__ nu, int i0, int jprev, const Ctrl* __restrict__ ctrl) {
@@ -530,10 +538,10 @@ __global__ __launch_bounds__(kBlock) void k_update(
 #pragma unroll
     for (int c = 0; c < NC; ++c) pv0[u][c] = pp[(int64_t)min(c, nc - 1) * nb1 + i];
   }
-  const int base = xcd_tile(blockIdx.x, gridDim.x) * (kBlock * kUpdateRows) + (int)threadIdx.x;
-  T wv[kUpdateRows], pv[kUpdateRows][TWM];
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * (kBlock * UR) + (int)threadIdx.x;
+  T wv[UR], pv[UR][TWM];
 #pragma unroll
-  for (int u = 0; u < kUpdateRows; ++u) {
+  for (int u = 0; u < UR; ++u) {
     const int r = min(base + u * kBlock, n - 1);
     wv[u] = w[r];
 #pragma unroll
@@ -600,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
   }
   const double inv = 1.0 / nprev;
 #pragma unroll
-  for (int u = 0; u < kUpdateRows; ++u) {
+  for (int u = 0; u < UR; ++u) {
     const int r = base + u * kBlock;
     if (r < n) {
       A v = widen(wv[u]);
@@ -617,8 +625,13 @@ void launch_update(hipStream_t st, int n, T* w, Window<T> win, int tw,
                    const typename traits<T>::acc* part, int nb1, int s, double* nu, int i0, int jprev,
                    const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
   const int nb = (n + kBlock * kUpdateRows - 1) / (kBlock * kUpdateRows);
+  // the window bound as a template parameter: a short window's rows take no
+  // registers (t = 3, the complex workload's, is the common longer one)
   void (*kern)(int, T*, Window<T>, int, const typename traits<T>::acc*, int, int, double*, int, int,
-               const Ctrl*) = tw <= 1 ? k_update<T, 1> : tw <= 2 ? k_update<T, 2> : k_update<T, kMaxWindow>;
+               const Ctrl*) = tw <= 1   ? k_update<T, 1, kUpdateRows>
+                              : tw <= 2 ? k_update<T, 2, kUpdateRows>
+                              : tw <= 3 ? k_update<T, 3, kUpdateRows>
+                                        : k_update<T, kMaxWindow, kUpdateRows>;
   if (e0)
     hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, e0, e1, 0, n, w, win, tw, part, nb1, s, nu,
                           i0, jprev, ctrl);
@@ -1589,90 +1602,132 @@ void launch_sketch_cols(hipStream_t st, int n, const X* x, int64_t ld, int cc, S
 
 // ----------------------------------- subsampled randomised DCT sketch ---
 // y_i = a_i sum_r e_r x_r cos(pi p_i (2r + 1) / (2N)) over a tile of
-// kRowsSpmv rows per block: the tile's e_r x_r is staged in LDS in sub-tiles
-// of kDctSub rows; thread f owns frequencies f, f + kBlock, ...  At each
-// sub-tile start the phase pi p (2 r0 + 1) / (2N) is reduced exactly in
-// integers (mod 4N) and its cosine and sine taken; inside the sub-tile the
-// cosine advances by a rotation through pi p / N (error O(kDctSub eps)).
-// The work is s multiply-adds and rotations per entry: ALU-bound.
-constexpr int kDctSub = kBlock;     // rows staged per sub-tile
-constexpr int kDctMaxFpt = 8;       // frequencies per thread (s <= 2048)
+// kRowsSpmv rows per block of kDctThreads: the tile's e_r x_r is staged in
+// LDS (and a copy with every other entry negated, for the alternating form).
+// Each half of the block takes half of the tile's rows; thread f of a half
+// owns kept rows f, f + kBlock, ...  Each half runs its rows as two chains of
+// kDctChain entries, each started from its phase pi p (2 r + 1) / (2N)
+// reduced exactly in integers (mod 4N) and advanced by Reinsch's recurrence:
+// per entry and kept row one multiply-add into the sum and two recurrence
+// operations (error O(kDctChain eps)).  The halves' sums are added in a fixed
+// order.  ALU-bound: s multiply-adds per entry.
+constexpr int kDctThreads = 2 * kBlock;
+constexpr int kDctChain = kRowsSpmv / 4;  // 384 (even: chains start on even entries)
+constexpr int kDctMaxFpt = 8;             // kept rows per thread (s <= 2048)
+
+// cos(phi) and the first difference d = c_0 - c_{-1} of the row's recurrence.
+__device__ __forceinline__ void dct_start(const DctRow& w, uint64_t ph, double ang, double* c, double* d) {
+  double sn, cs;
+  sincos((double)ph * ang, &sn, &cs);
+  *c = cs;
+  // mode 0: c_q = cos(phi + q b): d = cos phi - cos(phi - b) = -2 sin(b/2) sin(phi - b/2)
+  // mode 1: c'_q = cos(phi - q b'): d = cos phi - cos(phi + b') = 2 sin(b'/2) sin(phi + b'/2)
+  *d = w.mode ? 2.0 * w.sh * (sn * w.ch + cs * w.sh) : -2.0 * w.sh * (sn * w.ch - cs * w.sh);
+}
 
 template <class X>
-__global__ __launch_bounds__(kBlock) void k_dct_sketch(int n, const X* __restrict__ x, DctSpec d,
-                                                       typename traits<X>::acc* __restrict__ part, int nb,
-                                                       int with_norm, const Ctrl* __restrict__ ctrl) {
+__global__ __launch_bounds__(kDctThreads) void k_dct_sketch(int n, const X* __restrict__ x, DctSpec d,
+                                                            typename traits<X>::acc* __restrict__ part,
+                                                            int nb, int with_norm,
+                                                            const Ctrl* __restrict__ ctrl) {
   using A = typename traits<X>::acc;
   if (ctrl && ctrl->halt) return;
-  __shared__ A v[kDctSub];
-  __shared__ double red[kWaves];
+  __shared__ A vb[2 * kRowsSpmv + 1];  // e x, then (-1)^q e x (one pad entry between: other banks)
+  __shared__ double red[kDctThreads / 64];
+  A* v0 = vb;
+  A* v1 = vb + kRowsSpmv + 1;
   const int tile = xcd_tile(blockIdx.x, nb);
   const int r0 = tile * kRowsSpmv;
-  const int r1 = min(n, r0 + kRowsSpmv);
-  const int fpt = (d.s + kBlock - 1) / kBlock;
-  A acc[kDctMaxFpt];
-#pragma unroll
-  for (int k = 0; k < kDctMaxFpt; ++k) acc[k] = zero<A>();
+  const int len = min(kRowsSpmv, n - r0);
   double nx = 0.0;
-  for (int q0 = r0; q0 < r1; q0 += kDctSub) {
-    const int r = q0 + (int)threadIdx.x;
+  for (int q = (int)threadIdx.x; q < kRowsSpmv; q += kDctThreads) {
     A e = zero<A>();
-    if (r < r1) {
+    if (q < len) {
+      const int r = r0 + q;
       const A xv = widen(x[r]);
       nx += abs2(xv);
       const uint64_t h = mix64(d.sign_seed + kGamma * (uint64_t)(r + 1));
       e = neg_if(xv, (h & 1ull) != 0ull);
     }
-    __syncthreads();  // (the previous sub-tile's reads are done)
-    v[threadIdx.x] = e;
-    __syncthreads();
-    const int len = min(kDctSub, r1 - q0);
-#pragma unroll
-    for (int k = 0; k < kDctMaxFpt; ++k) {
-      if (k >= fpt) break;
-      const int f = (int)threadIdx.x + k * kBlock;
-      if (f < d.s) {
-        const DctRow w = d.rows[f];
-        const uint64_t ph = ((uint64_t)w.p * (uint64_t)(2 * q0 + 1)) % (uint64_t)d.n4;
-        double sn, cs;
-        sincos((double)ph * d.ang, &sn, &cs);
-        A a = acc[k];
-        int q = 0;
-        for (; q + 4 <= len; q += 4) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            a += v[q + u] * cs;
-            const double c2 = cs * w.cb - sn * w.sb;
-            sn = sn * w.cb + cs * w.sb;
-            cs = c2;
-          }
-        }
-        for (; q < len; ++q) {
-          a += v[q] * cs;
-          const double c2 = cs * w.cb - sn * w.sb;
-          sn = sn * w.cb + cs * w.sb;
-          cs = c2;
-        }
-        acc[k] = a;
-      }
-    }
+    v0[q] = e;
+    v1[q] = neg_if(e, (q & 1) != 0);
   }
+  __syncthreads();
+  const int half = (int)threadIdx.x / kBlock, lt = (int)threadIdx.x % kBlock;
+  // this half's chains: [qa, qa + na) and [qb, qb + nbb)
+  const int qa = half * 2 * kDctChain, qb = qa + kDctChain;
+  const int na = max(0, min(kDctChain, len - qa)), nbb = max(0, min(kDctChain, len - qb));
+  const int fpt = (d.s + kBlock - 1) / kBlock;
+  const uint64_t n4 = (uint64_t)d.n4;
+  A acc[kDctMaxFpt];
 #pragma unroll
   for (int k = 0; k < kDctMaxFpt; ++k) {
-    const int f = (int)threadIdx.x + k * kBlock;
-    if (k < fpt && f < d.s) part[(int64_t)f * nb + tile] = scale(acc[k], d.rows[f].a);
+    acc[k] = zero<A>();
+    const int f = lt + k * kBlock;
+    if (k >= fpt || f >= d.s || na == 0) continue;
+    const DctRow w = d.rows[f];
+    const A* vs = w.mode ? v1 : v0;
+    double ca, da, cb, db;
+    dct_start(w, ((uint64_t)w.p * (uint64_t)(2 * (r0 + qa) + 1)) % n4, d.ang, &ca, &da);
+    dct_start(w, ((uint64_t)w.p * (uint64_t)(2 * (r0 + qb) + 1)) % n4, d.ang, &cb, &db);
+    const double lam = w.lam;
+    A sa = zero<A>(), sb = zero<A>();
+    const A* pa = vs + qa;
+    const A* pb = vs + qb;
+    int q = 0;
+    for (; q + 2 <= nbb; q += 2) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        sa += pa[q + u] * ca;
+        da -= lam * ca;
+        ca += da;
+        sb += pb[q + u] * cb;
+        db -= lam * cb;
+        cb += db;
+      }
+    }
+    for (; q < nbb; ++q) {
+      sa += pa[q] * ca;
+      da -= lam * ca;
+      ca += da;
+      sb += pb[q] * cb;
+      db -= lam * cb;
+      cb += db;
+    }
+    for (; q < na; ++q) {
+      sa += pa[q] * ca;
+      da -= lam * ca;
+      ca += da;
+    }
+    acc[k] = sa + sb;
   }
-  if (with_norm) {
-    const double t = block_sum(nx, red);
-    if (threadIdx.x == 0) put_re(&part[(int64_t)d.s * nb + tile], t);
+  // the halves' sums, added in a fixed order (half 0, then half 1)
+  const double tn = with_norm ? block_sum(nx, red) : 0.0;  // (its barriers also end the reads of vb)
+  if (!with_norm) __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kDctMaxFpt; ++k) {
+    if (k >= fpt) break;
+    if (half == 1) vb[lt] = acc[k];
+    __syncthreads();
+    const int f = lt + k * kBlock;
+    if (half == 0 && f < d.s) {
+      const DctRow& w = d.rows[f];
+      part[(int64_t)w.out * nb + tile] = scale(acc[k] + vb[lt], w.a);
+    }
+    __syncthreads();
   }
+  if (with_norm && threadIdx.x == 0) put_re(&part[(int64_t)d.s * nb + tile], tn);
 }
 
 template <class X>
 void launch_dct_sketch(hipStream_t st, int n, const X* x, DctSpec d, typename traits<X>::acc* part, int nb,
-                       bool with_norm, const Ctrl* ctrl) {
-  hipLaunchKernelGGL(k_dct_sketch<X>, dim3(nb), dim3(kBlock), 0, st, n, x, d, part, nb, with_norm ? 1 : 0,
-                     ctrl);
+                       bool with_norm, const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
+  if (e0)
+    hipExtLaunchKernelGGL(k_dct_sketch<X>, dim3(nb), dim3(kDctThreads), 0, st, e0, e1, 0, n, x, d, part, nb,
+                          with_norm ? 1 : 0, ctrl);
+  else
+    hipLaunchKernelGGL(k_dct_sketch<X>, dim3(nb), dim3(kDctThreads), 0, st, n, x, d, part, nb,
+                       with_norm ? 1 : 0, ctrl);
 }
 
 // ------------------------------------------------- tall-skinny products ---
@@ -2260,7 +2315,7 @@ void launch_scale_by_diag(hipStream_t st, int n, const A* d, A* x, bool divide) 
   template void launch_sketch_cols<T>(hipStream_t, int, const T*, int64_t, int, SketchSpec,       \
                                       traits<T>::acc*, int);                                      \
   template void launch_dct_sketch<T>(hipStream_t, int, const T*, DctSpec, traits<T>::acc*, int, bool, \
-                                     const Ctrl*);                                                \
+                                     const Ctrl*, hipEvent_t, hipEvent_t);                        \
   template void launch_gemv_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \
                                      int, const traits<T>::acc*, traits<T>::acc*);                \
   template void launch_gemm_basis<T>(hipStream_t, int, const T*, int64_t, int, const T*, int64_t, \

@@ -243,7 +243,7 @@ class Solver final : public SolverBase {
       C_ = dalloc<A>((size_t)lmax_ * lmax_);
       if (opt.kernel_timing) {
         for (auto& evp : ev_) {
-          evp.assign(m + 2, std::array<hipEvent_t, 4>{});
+          evp.assign(m + 2, std::array<hipEvent_t, 6>{});
           // (timing only: no system-scope fence at each record)
           for (auto& a : evp)
             for (auto& e : a) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
@@ -365,12 +365,19 @@ class Solver final : public SolverBase {
     const double pi = 3.14159265358979323846;
     for (int i = 0; i < s_; ++i) {
       const int p = rows[i];
-      const double step = pi * (double)p / (double)n_;
+      // step b = pi p / N; b > pi/2 (2p > N) runs the alternating form with b' = pi - b
+      const int mode = 2 * (int64_t)p > (int64_t)n_ ? 1 : 0;
+      const double half = pi * (double)(mode ? n_ - p : p) / (2.0 * n_);  // b/2 or b'/2
       h[i].p = p;
-      h[i].cb = std::cos(step);
-      h[i].sb = std::sin(step);
+      h[i].sh = std::sin(half);
+      h[i].ch = std::cos(half);
+      h[i].lam = 4.0 * h[i].sh * h[i].sh;
       h[i].a = std::sqrt((double)n_ / s_) * (p == 0 ? std::sqrt(1.0 / n_) : std::sqrt(2.0 / n_));
+      h[i].out = i;
+      h[i].mode = mode;
     }
+    // processed grouped by mode, so that a wavefront's lanes read one LDS array
+    std::stable_sort(h.begin(), h.end(), [](const DctRow& a, const DctRow& b) { return a.mode < b.mode; });
     dct_rows_ = dalloc<DctRow>(s_);
     HIPCHK(hipMemcpy(dct_rows_, h.data(), sizeof(DctRow) * s_, hipMemcpyHostToDevice));
     dct_.rows = dct_rows_;
@@ -527,7 +534,8 @@ class Solver final : public SolverBase {
                             tm ? te[0] : nullptr, tm ? te[1] : nullptr);
     LAUNCHCHK();
     if (dct_on_) {  // S p_{j-1} into the sketch rows the step kernel left alone
-      launch_dct_sketch<T>(stream_, n_, x, dct_, p1, nb1_, false, ctrl_);
+      launch_dct_sketch<T>(stream_, n_, x, dct_, p1, nb1_, false, ctrl_, tm ? te[4] : nullptr,
+                           tm ? te[5] : nullptr);
       LAUNCHCHK();
     }
     if (ev) HIPCHK(hipEventRecord(evs_[sl], stream_));
@@ -558,6 +566,11 @@ class Solver final : public SolverBase {
       kt_ms_[0] += a;
       kt_ms_[1] += b2;
       kt_ms_[2] += c;
+      if (dct_on_) {
+        float dd = 0.f;
+        HIPCHK(hipEventElapsedTime(&dd, evs[j][4], evs[j][5]));
+        kt_ms_[3] += dd;
+      }
       kt_n_[0]++;
       kt_n_[1]++;
       kt_n_[2]++;
@@ -1333,10 +1346,10 @@ class Solver final : public SolverBase {
   std::condition_variable eig_cv_;
   bool eig_job_ = false, eig_done_ = false, eig_quit_ = false, eig_pending_ = false;
   EigResult eig_res_;
-  std::vector<std::array<hipEvent_t, 4>> ev_[2];  // kernel timing events, by cycle parity
+  std::vector<std::array<hipEvent_t, 6>> ev_[2];  // kernel timing events, by cycle parity
   int evp_ = 0, ev_pend_p_ = 0, ev_pend_j_ = 0, cycle_par_ = 0;
   int ev_ofs_[2] = {0, 0}, ev_ofs_next_ = 0;  // timed-step offsets by cycle parity
-  double kt_ms_[3] = {0, 0, 0};
+  double kt_ms_[4] = {0, 0, 0, 0};  // SpMV, update, step, DCT sketch
   int64_t kt_n_[3] = {0, 0, 0};
   int64_t kt_bytes_tw_[kMaxWindow + 1] = {0, 0, 0, 0, 0};
 
@@ -1352,13 +1365,16 @@ class Solver final : public SolverBase {
     return dia_.ndiag;
   }
 
-  // [0] SpMV + sketch ms, [1] update ms, [2] both kernels of a step (SpMV start to update end);
+  // [0] SpMV + sketch ms, [1] update ms, [2] the kernels of a step (SpMV start to update end),
+  // [3] the DCT sketch kernel (sketch=1; its launches are counts[0]);
   // counts[0..2] launches; counts[3 + tw] = launches with window size tw.
   int kernel_times(double* ms, int64_t* counts, int cap) override {
     for (int i = 0; i < 3 && i < cap; ++i) {
       if (ms) ms[i] = kt_ms_[i];
       if (counts) counts[i] = kt_n_[i];
     }
+    if (ms && cap > 3) ms[3] = kt_ms_[3];
+    kt_ms_[3] = 0;
     for (int tw = 0; tw <= kMaxWindow; ++tw)
       if (counts && 3 + tw < cap) counts[3 + tw] = kt_bytes_tw_[tw];
     for (int i = 0; i < 3; ++i) {

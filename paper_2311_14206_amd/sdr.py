@@ -220,7 +220,7 @@ class SDRSolver:
         ms = (C.c_double * 8)()
         cnt = (C.c_int64 * 8)()
         _check(lib().sdr_kernel_times(self.h, ms, cnt, 8), "sdr_kernel_times")
-        return {"spmv_sketch_ms": ms[0], "update_ms": ms[1], "step_ms": ms[2],
+        return {"spmv_sketch_ms": ms[0], "update_ms": ms[1], "step_ms": ms[2], "dct_sketch_ms": ms[3],
                 "launches": cnt[0], "window_hist": [cnt[3 + i] for i in range(5)]}
 
     def spmv_layout(self):
