@@ -24,7 +24,9 @@ GPU library takes the same ones):
   formed, the true-residual check is forced at this j and the cycle ends.
 * Rank loss of the sketched least-squares matrix, i.e. the new column of
   SAW lies within rank_rtol (relative) of the span of the previous columns:
-  the minimum-norm solution is kept, the check is forced and the cycle ends.
+  that column is taken as dependent and left out of the least squares (its
+  coefficient is zero, the sketched residual is the previous step's), the
+  check is forced and the cycle ends.
 * The recycle space is refreshed after every cycle, converged or not
   (Algorithm 1 reaches the update after ``break``).  Its input "SW" is the
   sketched search basis [SU, SV(:, 1:j)], and V(:, 1:m) there means the j
@@ -400,9 +402,15 @@ def sdr_cycle(A, S, r0, rec: Recycle, tol_abs: float, m: int, t: int, k: int,
         sketch_extend(S, V, H, SV, SAV, j, breakdown, bump)
         bump("iters")
         SAW = np.concatenate([SAU, SAV[:, :j]], axis=1)
-        y, sres = sketched_least_squares(SAW, Sr)
-        rec_out.sres_hist.append(sres)
         rank_loss = newest_column_dependent(SAW, rank_rtol)
+        if rank_loss:
+            # a column declared dependent adds no direction: the least squares
+            # runs over the others and its coefficient is zero
+            y, sres = sketched_least_squares(SAW[:, :-1], Sr)
+            y = np.concatenate([y, np.zeros(1, dtype=y.dtype)])
+        else:
+            y, sres = sketched_least_squares(SAW, Sr)
+        rec_out.sres_hist.append(sres)
         if givens:
             control.step(givens_sine(SAU, SV, H, j))
         if not (control.due(sres, tol_abs) or j == m or breakdown or rank_loss):

@@ -29,6 +29,10 @@ MUTANTS = {
     "m_without_conjugate": ("M = Uh.conj().T @ SB @ Vh", "M = Uh.T @ SB @ Vh"),
     "safety_inverted": ("safety = res / sres", "safety = sres / res"),
     "sketch_not_of_new_vector": ("SV[:, j] = S @ V[:, j]\n", "SV[:, j] = S @ V[:, j - 1]\n"),
+    "rank_loss_keeps_dependent_column": ("        if rank_loss:\n            # a column",
+                                         "        if False:\n            # a column"),
+    "rank_loss_absolute_distance": ("return not (_norm(a - SAW[:, :-1] @ c) / na > rank_rtol)",
+                                    "return not (_norm(a - SAW[:, :-1] @ c) > rank_rtol)"),
 }
 
 PINS = [
@@ -44,6 +48,7 @@ PINS = [
     lambda: pins.test_solution_matches_dense_lu("cd"),
     lambda: pins.test_solution_matches_dense_lu("helmholtz"),
     pins.test_safety_factor_update_rule,
+    pins.test_rank_loss_leaves_the_dependent_column_out,
 ]
 
 

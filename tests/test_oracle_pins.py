@@ -420,3 +420,36 @@ def test_not_converged_and_breakdown_paths():
     bb = np.ones(N)
     r = sdr_solve(Dd, bb, m=10, k=2, t=3, s=32, tol=1e-12)
     assert r.converged and r.trace[0].j_stop <= 4
+
+
+def test_rank_loss_leaves_the_dependent_column_out():
+    """A cycle that stops because SAW loses rank (the paper is silent; the
+    oracle's reading): the stop is the first step whose new SAW column lies
+    within rank_rtol (relative) of the span of the earlier columns, measured
+    here by a Householder QR of those columns; the column adds no direction,
+    so the sketched residual at the stop is the minimum over the earlier
+    columns (projection with the same QR) and the column's coefficient is 0.
+    Window t = 1 makes SAW nearly dependent within 40 steps."""
+    A = cd2d_upwind(23)
+    b = randn(A.n, 23)
+    keep = []
+    r = sdr_solve(A.to_scipy(), b, m=40, k=8, t=1, s=104, tol=1e-9, rank_rtol=1e-4,
+                  max_cycles=1, keep_cycles=keep)
+    c = r.trace[0]
+    assert c.rank_loss and c.j_stop == len(c.sres_hist)
+    kp = keep[0]
+    SAV, j, Sr = kp["SAV"], kp["j"], kp["Sr"]
+    dist = []
+    for jj in range(2, j + 1):
+        Q, _ = np.linalg.qr(SAV[:, : jj - 1])
+        a = SAV[:, jj - 1]
+        dist.append(np.linalg.norm(a - Q @ (Q.T @ a)) / np.linalg.norm(a))
+    assert dist[-1] <= 1e-4 < min(dist[:-1])
+    Q, _ = np.linalg.qr(SAV[:, : j - 1])
+    smin = np.linalg.norm(Sr - Q @ (Q.T @ Sr))
+    # (SAW is ill-conditioned here: lstsq and this QR agree to ~1e-12)
+    assert abs(c.sres - smin) <= 1e-9 * smin
+    assert c.sres_hist[-1] == c.sres_hist[-2]
+    assert kp["y"][-1] == 0.0
+    # and the true residual of the check is that of the returned iterate
+    assert abs(c.res - np.linalg.norm(b - A.to_scipy() @ r.x)) <= 1e-12 * np.linalg.norm(b)
