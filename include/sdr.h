@@ -120,6 +120,12 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *   "breakdown_rtol" Arnoldi breakdown threshold (default 1e-14; 1e-6 FP32)
  *   "rank_rtol"      rank-loss threshold of the sketched LSQ (default 1e-12)
  *   "lsq_chunk"      Arnoldi steps per least-squares launch (default 8)
+ *   "lsq_kernel"     least-squares kernel: 0 (default) keeps the QR factor in
+ *                    registers where the sketch and the basis are small
+ *                    enough, else block Gram-Schmidt (blocks of up to 8
+ *                    steps, Q swept four times per block); 1: block kernel;
+ *                    2: one launch per step (reference form).  The same
+ *                    decisions and, up to rounding, the same factor.
  *   "dia"            1 (default): a pattern whose entries lie on at most 16
  *                    diagonals (padding at most nnz/4) is stored by diagonals
  *                    for the basis SpMV; 0: always CSR

@@ -151,12 +151,16 @@ void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int 
                      const A* red, double brtol, double rank_rtol);
 
 // Steps j0 .. j1 of the least squares, step j reading its reduced inputs at
-// redb + slotr * (j % nslot) (layout of launch_lsq_step's red).  One launch
-// with the QR factor held on chip where the register shape allows, else one
-// launch per step.  Stops after a step that raises the halt flag.
+// redb + slotr * (j % nslot) (layout of launch_lsq_step's red).  kind 0: one
+// launch with the QR factor held in registers where the register shape
+// allows, else the block Gram-Schmidt kernel (one launch, blocks of up to 8
+// steps); kind 1: the block kernel; kind 2: one launch per step.  A shape the
+// chosen kernel cannot take falls back to one launch per step.  Stops after
+// a step that raises the halt flag.
 template <class A>
 void launch_lsq_steps(hipStream_t st, LsqState<A> S, int j0, int j1, int khat, int m, int t, int s,
-                      const A* redb, int64_t slotr, int nslot, double brtol, double rank_rtol);
+                      const A* redb, int64_t slotr, int nslot, double brtol, double rank_rtol,
+                      int kind = 0);
 
 // The reduced inputs of steps j0 .. j1 into their slots of redb (slot
 // j % nslot): [S p_j scaled by scl, ||p_j||^2] from the SpMV partial slot of

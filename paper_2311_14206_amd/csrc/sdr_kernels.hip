@@ -1432,6 +1432,365 @@ void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int 
                      brtol, rank_rtol);
 }
 
+// ---- block variant --------------------------------------------------------
+// For shapes whose factor does not fit the registers (a wide sketch, complex
+// data), the steps of a launch are taken in blocks of up to kBlkCols columns
+// by block classical Gram-Schmidt with reorthogonalisation (BCGS2): the new
+// SAV columns W are projected against the committed factor Q, the remainder
+// is factorised inside the block by CGS2 (W1 = Q1 R1), Q1 is projected once
+// more and factorised again (Q2 R2), so that
+//   W = Q (P1 + P2 R1) + Q2 (R2 R1),
+// which appends Q2 to Q and [P1 + P2 R1; R2 R1] to R.  Q is swept four times
+// per block instead of four times per column, and each sweep is a product
+// with up to eight columns at once.  The steps are then finished one by one
+// in the order of the sequential kernels (projected residual, residual
+// control, records), and only the steps up to the one that halts are
+// committed: the columns of Q and R beyond it are rewritten before they are
+// read if the cycle resumes.
+constexpr int kBlkThreads = 1024;
+constexpr int kBlkWaves = kBlkThreads / 64;
+constexpr int kBlkCols = 8;     // columns per block (the product lanes are 8 row groups x 8 columns)
+constexpr int kBlkMaxS = 4096;  // largest sketch taken by the block kernel
+
+// LDS pitch of the block's columns: >= s and 2 mod 16, so that the rows read
+// by one product instruction (eight consecutive rows of each of the eight
+// columns) fall in different banks.
+__host__ __device__ inline int blk_pitch(int s) { return ((s + 13) / 16) * 16 + 2; }
+
+__device__ __forceinline__ double shfl_xor_v(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ cx<double> shfl_xor_v(cx<double> v, int m) {
+  return {__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)};
+}
+
+// P(i, b) = Q(:, i)^H X(:, b) for i < ncol, b < nb (P row major, stride kBlkCols).
+// A wave takes four columns of Q at a time; lane (g, b) = (lane / 8, lane % 8)
+// sums rows g, g + 8, ... of column b of X, so every load instruction reads
+// eight consecutive rows (one 128-byte line) of each Q column, and the eight
+// row groups are combined by three exchanges in a fixed order.  Waves
+// wv < nb first store ||X(:, wv)|| in n0 when n0 is given.
+template <class A>
+__device__ void blk_project(const A* __restrict__ Q, int ldq, int ncol, int s, const A* X, int ps, int nb,
+                            A* P, double* n0) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (n0 != nullptr && wv < nb) {
+    double q = 0.0;
+    for (int r = lane; r < s; r += 64) q += abs2(X[wv * ps + r]);
+    q = wave_sum(q);
+    if (lane == 0) n0[wv] = sqrt(q);
+  }
+  const int g = lane >> 3, b = lane & 7;
+  const bool bact = b < nb;
+  for (int i0 = 4 * wv; i0 < ncol; i0 += 4 * kBlkWaves) {
+    const A* q0 = Q + (int64_t)i0 * ldq;
+    const A* q1 = Q + (int64_t)min(i0 + 1, ncol - 1) * ldq;
+    const A* q2 = Q + (int64_t)min(i0 + 2, ncol - 1) * ldq;
+    const A* q3 = Q + (int64_t)min(i0 + 3, ncol - 1) * ldq;
+    A a0 = zero<A>(), a1 = zero<A>(), a2 = zero<A>(), a3 = zero<A>();
+#pragma unroll 2
+    for (int r = g; r < s; r += 8) {
+      const A x = bact ? X[b * ps + r] : zero<A>();
+      a0 += conj(q0[r]) * x;
+      a1 += conj(q1[r]) * x;
+      a2 += conj(q2[r]) * x;
+      a3 += conj(q3[r]) * x;
+    }
+#pragma unroll
+    for (int msk = 8; msk < 64; msk <<= 1) {
+      a0 += shfl_xor_v(a0, msk);
+      a1 += shfl_xor_v(a1, msk);
+      a2 += shfl_xor_v(a2, msk);
+      a3 += shfl_xor_v(a3, msk);
+    }
+    if (g == 0 && bact) {
+      P[i0 * kBlkCols + b] = a0;
+      if (i0 + 1 < ncol) P[(i0 + 1) * kBlkCols + b] = a1;
+      if (i0 + 2 < ncol) P[(i0 + 2) * kBlkCols + b] = a2;
+      if (i0 + 3 < ncol) P[(i0 + 3) * kBlkCols + b] = a3;
+    }
+  }
+}
+
+// X(:, b) -= Q(:, 0:ncol) P(0:ncol, b) for b < nb, one thread per row and
+// half block; the row's columns stay in registers over the sweep.
+template <class A, int CB>
+__device__ __forceinline__ void blk_update_rows(const A* __restrict__ Q, int ldq, int ncol, int r, int c0,
+                                                A* X, int ps, int nb, const A* P) {
+  A acc[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) acc[c] = c0 + c < nb ? X[(c0 + c) * ps + r] : zero<A>();
+  constexpr int U = sizeof(A) == 16 ? 2 : 4;  // columns per group (register budget)
+  int i = 0;
+  for (; i + U <= ncol; i += U) {
+    A q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = Q[(int64_t)(i + u) * ldq + r];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[c] -= q[u] * P[(i + u) * kBlkCols + c0 + c];
+  }
+  for (; i < ncol; ++i) {
+    const A q = Q[(int64_t)i * ldq + r];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[c] -= q * P[i * kBlkCols + c0 + c];
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c)
+    if (c0 + c < nb) X[(c0 + c) * ps + r] = acc[c];
+}
+
+template <class A>
+__device__ void blk_update(const A* __restrict__ Q, int ldq, int ncol, int s, A* X, int ps, int nb,
+                           const A* P) {
+  constexpr int CB = kBlkCols / 2;
+  for (int idx = threadIdx.x; idx < 2 * s; idx += kBlkThreads) {
+    const int h = idx / s, r = idx - h * s;
+    blk_update_rows<A, CB>(Q, ldq, ncol, r, h * CB, X, ps, nb, P);
+  }
+}
+
+// CGS2 inside the block: X(:, 0:nb) = Xq Rm, Xq overwriting X, Rm upper
+// triangular (column major, stride kBlkCols, real positive diagonal; zero
+// below it).  A zero remainder gives a zero column and Rm(b, b) = 0.
+template <class A>
+__device__ void blk_qr(A* X, int ps, int s, int nb, A* Rm, A* dcur, A* dsum, double* sh_na) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int b = 0; b < nb; ++b) {
+    A* xb = X + b * ps;
+    for (int pass = 0; pass < 2 && b > 0; ++pass) {
+      if (wv < b) {
+        A d = zero<A>();
+        for (int r = lane; r < s; r += 64) d += conj(X[wv * ps + r]) * xb[r];
+        d = wave_sum(d);
+        if (lane == 0) dcur[wv] = d;
+      }
+      __syncthreads();
+      for (int r = tid; r < s; r += kBlkThreads) {
+        A v = xb[r];
+        for (int c = 0; c < b; ++c) v -= X[c * ps + r] * dcur[c];
+        xb[r] = v;
+      }
+      if (tid == 0)
+        for (int c = 0; c < b; ++c) dsum[c] = pass == 0 ? dcur[c] : dsum[c] + dcur[c];
+      __syncthreads();
+    }
+    if (wv == 0) {
+      double q = 0.0;
+      for (int r = lane; r < s; r += 64) q += abs2(xb[r]);
+      q = sqrt(wave_sum(q));
+      if (lane == 0) *sh_na = q;
+    }
+    __syncthreads();
+    const double na = *sh_na;
+    const double inv = na > 0.0 ? 1.0 / na : 0.0;
+    for (int r = tid; r < s; r += kBlkThreads) xb[r] = scale(xb[r], inv);
+    if (tid < kBlkCols) {
+      A v = zero<A>();
+      if (tid < b) v = dsum[tid];
+      if (tid == b) *(double*)&v = na;
+      Rm[b * kBlkCols + tid] = v;
+    }
+    __syncthreads();
+  }
+}
+
+template <class A>
+__global__ __launch_bounds__(kBlkThreads) void k_lsq_block(LsqState<A> S, int j0, int j1, int khat, int m,
+                                                           int t, int s, const A* __restrict__ redb,
+                                                           int64_t slotr, int nslot, double brtol,
+                                                           double rank_rtol, int bc, int prow) {
+  if (S.ctrl->halt) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ps = blk_pitch(s);
+  A* X = reinterpret_cast<A*>(smem_raw);  // ps x bc
+  A* P = X + ps * bc;                      // prow x kBlkCols
+  A* R1 = P + prow * kBlkCols;             // kBlkCols x kBlkCols, column major
+  A* R2 = R1 + kBlkCols * kBlkCols;
+  A* rhol = R2 + kBlkCols * kBlkCols;      // s: the projected residual (finishing wave)
+  __shared__ A hc[kBlkCols][kMaxWindow + 1];
+  __shared__ A RB[kBlkCols * kBlkCols];
+  __shared__ A dcur[kBlkCols], dsum[kBlkCols];
+  __shared__ double nujs[kBlkCols], n0[kBlkCols], sh_na;
+  __shared__ int brks[kBlkCols], sh_halt, sh_last;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int jb = j0; jb <= j1; jb += bc) {
+    const int nb = min(bc, j1 - jb + 1);
+    const int col0 = khat + jb - 1;  // committed columns of Q
+    // H columns, breakdown tests and norms of the block's steps, in order
+    if (tid == 0) {
+      double nuprev = S.nu[jb - 1];
+      for (int b = 0; b < nb; ++b) {
+        const int j = jb + b;
+        const A* red = redb + slotr * (j % nslot);
+        const int i0 = j - t > 0 ? j - t : 0, tw = j - i0;
+        const A* dots = red + s + 1;
+        const double nuj = sqrt(re(red[s]));
+        const double nw = sqrt(re(dots[tw]));
+        const bool brk = !(nuj > brtol * nw / nuprev);  // H(j,j-1) vs ||A v_{j-1}||
+        for (int q = 0; q < tw; ++q) {
+          const int i = i0 + q;
+          const double nui = i < jb ? S.nu[i] : nujs[i - jb];
+          hc[b][q] = scale(dots[q], 1.0 / (nui * nuprev));
+        }
+        A hs = zero<A>();
+        *(double*)&hs = brk ? 0.0 : nuj;
+        hc[b][tw] = hs;
+        nujs[b] = nuj;
+        brks[b] = brk;
+        nuprev = nuj;
+      }
+    }
+    __syncthreads();
+    // SV and SAV columns (SAV(:, j) = SV(:, window) H(window, j)); the window
+    // columns of earlier steps of this block are read back from SB, written
+    // just before by the same thread.
+    for (int r = tid; r < s; r += kBlkThreads) {
+      for (int b = 0; b < nb; ++b) {
+        const int j = jb + b;
+        const A* red = redb + slotr * (j % nslot);
+        const int i0 = j - t > 0 ? j - t : 0, tw = j - i0;
+        const A v = brks[b] ? zero<A>() : scale(red[r], 1.0 / nujs[b]);
+        A sum = zero<A>();
+        for (int q = 0; q < tw; ++q) sum += S.SB[(int64_t)(khat + i0 + q) * S.ldsb + r] * hc[b][q];
+        sum += v * hc[b][tw];
+        S.SB[(int64_t)(khat + j) * S.ldsb + r] = v;
+        S.SAW[(int64_t)(khat + j - 1) * S.ldsaw + r] = sum;
+        X[b * ps + r] = sum;
+      }
+    }
+    __syncthreads();
+    // first projection: P1 = Q^H W (stored as the R entries above the block), W1 = W - Q P1
+    blk_project(S.Q, S.ldq, col0, s, X, ps, nb, P, n0);
+    __syncthreads();
+    for (int i = tid; i < col0; i += kBlkThreads)
+      for (int b = 0; b < nb; ++b) S.R[(int64_t)(col0 + b) * S.ldr + i] = P[i * kBlkCols + b];
+    blk_update(S.Q, S.ldq, col0, s, X, ps, nb, P);
+    __syncthreads();
+    blk_qr(X, ps, s, nb, R1, dcur, dsum, &sh_na);  // W1 = Q1 R1
+    // second projection: P2 = Q^H Q1, Q1 - Q P2 = Q2 R2; R above the block
+    // becomes P1 + P2 R1 (each thread reads back what it stored)
+    blk_project(S.Q, S.ldq, col0, s, X, ps, nb, P, (double*)nullptr);
+    __syncthreads();
+    for (int i = tid; i < col0; i += kBlkThreads)
+      for (int b = 0; b < nb; ++b) {
+        A u = zero<A>();
+        for (int c = 0; c <= b; ++c) u += P[i * kBlkCols + c] * R1[b * kBlkCols + c];
+        A* rp = S.R + (int64_t)(col0 + b) * S.ldr + i;
+        *rp = *rp + u;
+      }
+    blk_update(S.Q, S.ldq, col0, s, X, ps, nb, P);
+    __syncthreads();
+    blk_qr(X, ps, s, nb, R2, dcur, dsum, &sh_na);
+    // the block's R = R2 R1, then the steps in order (one wave)
+    if (wv == 0) {
+      const int c = lane >> 3, b = lane & 7;
+      A v = zero<A>();
+      if (c <= b && b < nb)
+        for (int e = c; e <= b; ++e) v += R2[e * kBlkCols + c] * R1[b * kBlkCols + e];
+      RB[b * kBlkCols + c] = v;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int r = lane; r < s; r += 64) rhol[r] = S.rho[r];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      int last = nb - 1, halted = 0;
+      for (int bb = 0; bb < nb; ++bb) {
+        const int j = jb + bb, col = col0 + bb;
+        const double na = re(RB[bb * kBlkCols + bb]);
+        const bool loss = !(na > rank_rtol * n0[bb]);
+        A zc = zero<A>();
+        const A* qb = X + bb * ps;
+        if (!loss) {
+          for (int r = lane; r < s; r += 64) zc += conj(qb[r]) * rhol[r];
+          zc = wave_sum(zc);
+        }
+        double rr2 = 0.0;
+        for (int r = lane; r < s; r += 64) {
+          A v = rhol[r];
+          if (!loss) {
+            v -= qb[r] * zc;
+            rhol[r] = v;
+          }
+          rr2 += abs2(v);
+        }
+        const double sres = sqrt(wave_sum(rr2));
+        int hv = 0;
+        if (lane == 0) {
+          const bool brk = brks[bb];
+          const int i0 = j - t > 0 ? j - t : 0, tw = j - i0;
+          S.nu[j] = nujs[bb];
+          for (int q = 0; q <= tw; ++q) S.H[(int64_t)(j - 1) * S.ldh + i0 + q] = hc[bb][q];
+          S.z[col] = zc;
+          int flags = 0;
+          if (brk) flags |= 2;
+          if (loss) flags |= 4;
+          const bool due = control_due(S.ctrl, sres);  // (updates the estimate: always evaluated)
+          const bool halt = due || j == m || brk || loss;
+          if (halt) flags |= 1;
+          S.sres_hist[j] = sres;
+          if (halt) {
+            S.ctrl->halt = 1;
+            S.ctrl->halt_j = j;
+            S.ctrl->flags = flags;
+          }
+          put_record(S, j, sres, nujs[bb], flags, halt);
+          hv = halt;
+        }
+        hv = __shfl(hv, 0, 64);
+        if (hv) {
+          last = bb;
+          halted = 1;
+          break;
+        }
+      }
+      for (int r = lane; r < s; r += 64) S.rho[r] = rhol[r];
+      if (lane == 0) {
+        sh_last = last;
+        sh_halt = halted;
+      }
+    }
+    __syncthreads();
+    // commit Q and the block's R up to the last finished step
+    const int last = sh_last;
+    for (int idx = tid; idx < (last + 1) * s; idx += kBlkThreads) {
+      const int b = idx / s, r = idx - b * s;
+      S.Q[(int64_t)(col0 + b) * S.ldq + r] = X[b * ps + r];
+    }
+    if (tid < kBlkCols * kBlkCols) {
+      const int c = tid >> 3, b = tid & 7;
+      if (c <= b && b <= last) S.R[(int64_t)(col0 + b) * S.ldr + col0 + c] = RB[b * kBlkCols + c];
+    }
+    if (sh_halt) return;
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// Columns per block of the block kernel for this launch (0: it does not fit).
+template <class A>
+static int lsq_block_cols(int s, int prow, size_t* lds) {
+  if (s > kBlkMaxS) return 0;
+  static int limit[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (limit[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+    limit[dev] = std::min(v, 160 * 1024) - 4096;  // room for the kernel's static LDS
+  }
+  for (int bc = kBlkCols; bc >= 1; --bc) {
+    const size_t bytes =
+        ((size_t)blk_pitch(s) * bc + (size_t)prow * kBlkCols + 2 * kBlkCols * kBlkCols + s) * sizeof(A);
+    if (bytes <= (size_t)limit[dev]) {
+      *lds = bytes;
+      return bc;
+    }
+  }
+  return 0;
+}
+
 // LDS of the batched kernel: update partials, reduction scratch, window ring
 template <class A>
 static constexpr size_t lsq_steps_lds(int rl, int cw) {
@@ -1450,13 +1809,23 @@ static constexpr size_t lsq_steps_lds(int rl, int cw) {
 
 template <class A>
 void launch_lsq_steps(hipStream_t st, LsqState<A> S, int j0, int j1, int khat, int m, int t, int s,
-                      const A* redb, int64_t slotr, int nslot, double brtol, double rank_rtol) {
+                      const A* redb, int64_t slotr, int nslot, double brtol, double rank_rtol, int kind) {
   int rl = 0, cw = 0;
-  if (lsq_reg_shape<A>(s, khat + m + 1, &rl, &cw)) {
+  if (kind == 0 && lsq_reg_shape<A>(s, khat + m + 1, &rl, &cw)) {
     SDR_LSQ_STEPS_CASE(2, 8)
     SDR_LSQ_STEPS_CASE(2, 16)
     SDR_LSQ_STEPS_CASE(4, 16)
     SDR_LSQ_STEPS_CASE(4, 8)
+  }
+  if (kind != 2) {
+    size_t lds = 0;
+    const int prow = std::max(1, khat + j1 - 1);
+    const int bc = lsq_block_cols<A>(s, prow, &lds);
+    if (bc > 0) {
+      hipLaunchKernelGGL(k_lsq_block<A>, dim3(1), dim3(kBlkThreads), lds, st, S, j0, j1, khat, m, t, s, redb,
+                         slotr, nslot, brtol, rank_rtol, bc, prow);
+      return;
+    }
   }
   // shapes without a batched kernel: one launch per step
   for (int j = j0; j <= j1; ++j)
@@ -2341,7 +2710,7 @@ SDR_INST_BASIS(cx<float>)
   template void launch_init_v0<A>(hipStream_t, const A*, int, A*, double*);                     \
   template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double, int, GivensInit); \
   template void launch_lsq_steps<A>(hipStream_t, LsqState<A>, int, int, int, int, int, int,      \
-                                    const A*, int64_t, int, double, double);                     \
+                                    const A*, int64_t, int, double, double, int);                \
   template void launch_reduce_steps<A>(hipStream_t, const A*, int64_t, int, int, int, int, int,  \
                                        int, double, A*, int64_t, const Ctrl*);                  \
   template void launch_backsolve<A>(hipStream_t, LsqState<A>, int, int, A*);                    \

@@ -88,6 +88,7 @@ struct Options {
   double brtol = -1.0;  // < 0: default for the basis precision
   double rank_rtol = 1e-12;
   int lsq_chunk = 8;      // steps per least-squares launch
+  int lsq_kernel = 0;     // 0: register kernel where the shape allows, else block; 1: block; 2: per step
   int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
   int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
   int precond = 0;        // 0: none; 1: right Jacobi, the forward solve runs on A D^-1
@@ -311,6 +312,7 @@ class Solver final : public SolverBase {
     opt_.persist_safety = o.persist_safety;
     opt_.resid_control = o.resid_control;
     opt_.givens_eps0 = o.givens_eps0;
+    opt_.lsq_kernel = o.lsq_kernel;
   }
 
   void set_matrix(MatView<A> mat) { M_ = mat; }
@@ -594,7 +596,7 @@ class Solver final : public SolverBase {
     launch_reduce_steps<A>(streamB_, part1_, (int64_t)slot1_, nb1_, s_, j0, j1, t_, nslot_,
                            sk_scl_, redb_, (int64_t)slotr_, ctrl_);
     launch_lsq_steps<A>(streamB_, lsq(), j0, j1, khat_, m_, t_, s_, redb_, (int64_t)slotr_, nslot_,
-                        brtol_, opt_.rank_rtol);
+                        brtol_, opt_.rank_rtol, opt_.lsq_kernel);
     LAUNCHCHK();
   }
 
@@ -1692,6 +1694,10 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
   } else if (k == "givens_eps0") {
     if (!(v >= 0.0 && v < 1.0)) return set_err("givens_eps0 in [0, 1)"), SDR_EINVAL;
     h->opt.givens_eps0 = v;
+  } else if (k == "lsq_kernel") {
+    if (v != 0.0 && v != 1.0 && v != 2.0)
+      return set_err("lsq_kernel is 0 (automatic), 1 (block) or 2 (one launch per step)"), SDR_EINVAL;
+    h->opt.lsq_kernel = (int)v;
   } else if (k == "lsq_chunk") {
     if (built || v < 1 || v > 64) return set_err("lsq_chunk in [1,64], before the first solve"), SDR_EINVAL;
     h->opt.lsq_chunk = (int)v;
