@@ -533,6 +533,8 @@ def main():
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--sketch", type=int, default=0,
                     help="0: sparse sign; 1: subsampled randomised DCT (profiling runs)")
+    ap.add_argument("--lsq-kernel", type=int, default=0,
+                    help="least-squares kernel: 0 automatic, 1 block Gram-Schmidt, 2 one launch per step")
     ap.add_argument("--timing-every", type=int, default=64,
                     help="time the SpMV and update kernels of every n-th Arnoldi step with HIP "
                          "events (events between kernels cost launch gaps; 1 times all)")
@@ -572,7 +574,7 @@ def main():
     bd = torch.from_numpy(b).to(dev)
     h = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
                   zeta=p["zeta"], kernel_timing=args.timing_every, precision=args.precision,
-                  sketch=args.sketch)
+                  sketch=args.sketch, lsq_kernel=args.lsq_kernel)
     if args.copy_calib_mb:
         src = torch.ones(args.copy_calib_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

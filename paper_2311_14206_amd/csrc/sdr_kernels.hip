@@ -1462,12 +1462,14 @@ __device__ __forceinline__ cx<double> shfl_xor_v(cx<double> v, int m) {
   return {__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)};
 }
 
-// P(i, b) = Q(:, i)^H X(:, b) for i < ncol, b < nb (P row major, stride kBlkCols).
-// A wave takes four columns of Q at a time; lane (g, b) = (lane / 8, lane % 8)
-// sums rows g, g + 8, ... of column b of X, so every load instruction reads
-// eight consecutive rows (one 128-byte line) of each Q column, and the eight
-// row groups are combined by three exchanges in a fixed order.  Waves
-// wv < nb first store ||X(:, wv)|| in n0 when n0 is given.
+// P(i, b) = Q(:, i)^H X(:, b) for i < ncol, b < nb (P row major, stride
+// kBlkCols; rows ncol .. up to the next multiple of 8 are set to zero).  A
+// wave takes eight columns of Q at a time; lane (c, g) = (lane / 8, lane % 8)
+// sums rows g, g + 8, ... of column c of the group against all block columns,
+// so one load instruction reads eight consecutive rows (a 128-byte line) of
+// each of eight columns.  The eight row groups are combined by DPP inside
+// each half row (quad swaps, then the half-row mirror), a fixed order.
+// Waves wv < nb first store ||X(:, wv)|| in n0 when n0 is given.
 template <class A>
 __device__ void blk_project(const A* __restrict__ Q, int ldq, int ncol, int s, const A* X, int ps, int nb,
                             A* P, double* n0) {
@@ -1478,61 +1480,66 @@ __device__ void blk_project(const A* __restrict__ Q, int ldq, int ncol, int s, c
     q = wave_sum(q);
     if (lane == 0) n0[wv] = sqrt(q);
   }
-  const int g = lane >> 3, b = lane & 7;
-  const bool bact = b < nb;
-  for (int i0 = 4 * wv; i0 < ncol; i0 += 4 * kBlkWaves) {
-    const A* q0 = Q + (int64_t)i0 * ldq;
-    const A* q1 = Q + (int64_t)min(i0 + 1, ncol - 1) * ldq;
-    const A* q2 = Q + (int64_t)min(i0 + 2, ncol - 1) * ldq;
-    const A* q3 = Q + (int64_t)min(i0 + 3, ncol - 1) * ldq;
-    A a0 = zero<A>(), a1 = zero<A>(), a2 = zero<A>(), a3 = zero<A>();
-#pragma unroll 2
-    for (int r = g; r < s; r += 8) {
-      const A x = bact ? X[b * ps + r] : zero<A>();
-      a0 += conj(q0[r]) * x;
-      a1 += conj(q1[r]) * x;
-      a2 += conj(q2[r]) * x;
-      a3 += conj(q3[r]) * x;
-    }
+  const int c = lane >> 3, g = lane & 7;
+  for (int i0 = 8 * wv; i0 < ncol; i0 += 8 * kBlkWaves) {
+    const int i = i0 + c;
+    const A* __restrict__ qc = Q + (int64_t)min(i, ncol - 1) * ldq;
+    A acc[kBlkCols];
 #pragma unroll
-    for (int msk = 8; msk < 64; msk <<= 1) {
-      a0 += shfl_xor_v(a0, msk);
-      a1 += shfl_xor_v(a1, msk);
-      a2 += shfl_xor_v(a2, msk);
-      a3 += shfl_xor_v(a3, msk);
+    for (int b = 0; b < kBlkCols; ++b) acc[b] = zero<A>();
+#pragma unroll 4
+    for (int r = g; r < s; r += 8) {
+      const A q = conj(qc[r]);
+#pragma unroll
+      for (int b = 0; b < kBlkCols; ++b)
+        if (b < nb) acc[b] += q * X[b * ps + r];
     }
-    if (g == 0 && bact) {
-      P[i0 * kBlkCols + b] = a0;
-      if (i0 + 1 < ncol) P[(i0 + 1) * kBlkCols + b] = a1;
-      if (i0 + 2 < ncol) P[(i0 + 2) * kBlkCols + b] = a2;
-      if (i0 + 3 < ncol) P[(i0 + 3) * kBlkCols + b] = a3;
+    double d[kBlkCols * ncomp<A>::v];
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) split_re(acc[b], d + b * ncomp<A>::v);
+#pragma unroll
+    for (int e = 0; e < kBlkCols * ncomp<A>::v; ++e) {
+      d[e] += dpp_mov<0xB1>(d[e]);
+      d[e] += dpp_mov<0x4E>(d[e]);
+      d[e] += dpp_mov<0x141>(d[e]);
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int b = 0; b < kBlkCols; ++b) {
+        A v;
+        join_re(v, d + b * ncomp<A>::v);
+        if (b < nb) P[i * kBlkCols + b] = i < ncol ? v : zero<A>();
+      }
     }
   }
 }
 
 // X(:, b) -= Q(:, 0:ncol) P(0:ncol, b) for b < nb, one thread per row and
-// half block; the row's columns stay in registers over the sweep.
+// half block; the row's columns stay in registers over the sweep, and the
+// next eight Q entries are loaded while the current eight are applied (P's
+// zero rows past ncol pad the last group, a multiple of U rows).
 template <class A, int CB>
 __device__ __forceinline__ void blk_update_rows(const A* __restrict__ Q, int ldq, int ncol, int r, int c0,
                                                 A* X, int ps, int nb, const A* P) {
+  constexpr int U = sizeof(A) == 16 ? 4 : 8;  // (register budget)
   A acc[CB];
 #pragma unroll
   for (int c = 0; c < CB; ++c) acc[c] = c0 + c < nb ? X[(c0 + c) * ps + r] : zero<A>();
-  constexpr int U = sizeof(A) == 16 ? 2 : 4;  // columns per group (register budget)
-  int i = 0;
-  for (; i + U <= ncol; i += U) {
+  A qn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) qn[u] = ncol > 0 ? Q[(int64_t)min(u, ncol - 1) * ldq + r] : zero<A>();
+  for (int i = 0; i < ncol; i += U) {
     A q[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) q[u] = Q[(int64_t)(i + u) * ldq + r];
+    for (int u = 0; u < U; ++u) q[u] = qn[u];
+    if (i + U < ncol) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) qn[u] = Q[(int64_t)min(i + U + u, ncol - 1) * ldq + r];
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int c = 0; c < CB; ++c) acc[c] -= q[u] * P[(i + u) * kBlkCols + c0 + c];
-  }
-  for (; i < ncol; ++i) {
-    const A q = Q[(int64_t)i * ldq + r];
-#pragma unroll
-    for (int c = 0; c < CB; ++c) acc[c] -= q * P[i * kBlkCols + c0 + c];
   }
 #pragma unroll
   for (int c = 0; c < CB; ++c)
@@ -1612,51 +1619,73 @@ __global__ __launch_bounds__(kBlkThreads) void k_lsq_block(LsqState<A> S, int j0
   __shared__ A dcur[kBlkCols], dsum[kBlkCols];
   __shared__ double nujs[kBlkCols], n0[kBlkCols], sh_na;
   __shared__ int brks[kBlkCols], sh_halt, sh_last;
+  __shared__ Ctrl cl;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int jb = j0; jb <= j1; jb += bc) {
     const int nb = min(bc, j1 - jb + 1);
     const int col0 = khat + jb - 1;  // committed columns of Q
-    // H columns, breakdown tests and norms of the block's steps, in order
-    if (tid == 0) {
-      double nuprev = S.nu[jb - 1];
-      for (int b = 0; b < nb; ++b) {
-        const int j = jb + b;
-        const A* red = redb + slotr * (j % nslot);
-        const int i0 = j - t > 0 ? j - t : 0, tw = j - i0;
-        const A* dots = red + s + 1;
-        const double nuj = sqrt(re(red[s]));
-        const double nw = sqrt(re(dots[tw]));
-        const bool brk = !(nuj > brtol * nw / nuprev);  // H(j,j-1) vs ||A v_{j-1}||
-        for (int q = 0; q < tw; ++q) {
-          const int i = i0 + q;
-          const double nui = i < jb ? S.nu[i] : nujs[i - jb];
-          hc[b][q] = scale(dots[q], 1.0 / (nui * nuprev));
-        }
-        A hs = zero<A>();
-        *(double*)&hs = brk ? 0.0 : nuj;
-        hc[b][tw] = hs;
-        nujs[b] = nuj;
-        brks[b] = brk;
-        nuprev = nuj;
+    // H columns, breakdown tests and norms of the block's steps, one thread
+    // per step (each norm is recomputed from its step's sums: the same bits)
+    if (tid < nb) {
+      const int b = tid, j = jb + b;
+      const A* red = redb + slotr * (j % nslot);
+      const int i0 = j - t > 0 ? j - t : 0, tw = j - i0;
+      const A* dots = red + s + 1;
+      const double nuj = sqrt(re(red[s]));
+      const double nw = sqrt(re(dots[tw]));
+      const double nuprev = b == 0 ? S.nu[jb - 1] : sqrt(re(redb[slotr * ((j - 1) % nslot) + s]));
+      const bool brk = !(nuj > brtol * nw / nuprev);  // H(j,j-1) vs ||A v_{j-1}||
+      for (int q = 0; q < tw; ++q) {
+        const int i = i0 + q;
+        const double nui = i < jb ? S.nu[i] : sqrt(re(redb[slotr * (i % nslot) + s]));
+        hc[b][q] = scale(dots[q], 1.0 / (nui * nuprev));
       }
+      A hs = zero<A>();
+      *(double*)&hs = brk ? 0.0 : nuj;
+      hc[b][tw] = hs;
+      nujs[b] = nuj;
+      brks[b] = brk;
     }
     __syncthreads();
-    // SV and SAV columns (SAV(:, j) = SV(:, window) H(window, j)); the window
-    // columns of earlier steps of this block are read back from SB, written
-    // just before by the same thread.
+    // SV and SAV columns (SAV(:, j) = SV(:, window) H(window, j)), one thread
+    // per row: every load first (the block's sketch sums and the window
+    // columns before the block), the SV values into X, then the SAV columns
+    // in place, last first, so that column b still finds the SV values of
+    // the columns before it.  The same sums in the same order as the
+    // column-by-column kernels.
     for (int r = tid; r < s; r += kBlkThreads) {
-      for (int b = 0; b < nb; ++b) {
-        const int j = jb + b;
-        const A* red = redb + slotr * (j % nslot);
-        const int i0 = j - t > 0 ? j - t : 0, tw = j - i0;
-        const A v = brks[b] ? zero<A>() : scale(red[r], 1.0 / nujs[b]);
-        A sum = zero<A>();
-        for (int q = 0; q < tw; ++q) sum += S.SB[(int64_t)(khat + i0 + q) * S.ldsb + r] * hc[b][q];
-        sum += v * hc[b][tw];
-        S.SB[(int64_t)(khat + j) * S.ldsb + r] = v;
-        S.SAW[(int64_t)(khat + j - 1) * S.ldsaw + r] = sum;
-        X[b * ps + r] = sum;
+      A wpre[kMaxWindow];
+#pragma unroll
+      for (int p = 0; p < kMaxWindow; ++p) {
+        const int i = jb - kMaxWindow + p;
+        wpre[p] = (i >= 0 && i >= jb - t) ? S.SB[(int64_t)(khat + i) * S.ldsb + r] : zero<A>();
       }
+      A raw[kBlkCols];
+#pragma unroll
+      for (int b = 0; b < kBlkCols; ++b) raw[b] = b < nb ? redb[slotr * ((jb + b) % nslot) + r] : zero<A>();
+#pragma unroll
+      for (int b = 0; b < kBlkCols; ++b)
+        if (b < nb) {
+          const A v = brks[b] ? zero<A>() : scale(raw[b], 1.0 / nujs[b]);
+          X[b * ps + r] = v;
+          S.SB[(int64_t)(khat + jb + b) * S.ldsb + r] = v;
+        }
+#pragma unroll 1
+      for (int b = nb - 1; b >= 0; --b) {
+          const int j = jb + b, i0 = j - t > 0 ? j - t : 0, tw = j - i0;
+          A sum = zero<A>();
+          for (int q = 0; q < tw; ++q) {
+            const int e = i0 + q - jb;  // window column relative to the block
+            A w = e >= 0 ? X[max(e, 0) * ps + r] : zero<A>();
+#pragma unroll
+            for (int p = 0; p < kMaxWindow; ++p)
+              if (e == p - kMaxWindow) w = wpre[p];
+            sum += w * hc[b][q];
+          }
+          sum += X[b * ps + r] * hc[b][tw];
+          X[b * ps + r] = sum;
+          S.SAW[(int64_t)(khat + j - 1) * S.ldsaw + r] = sum;
+        }
     }
     __syncthreads();
     // first projection: P1 = Q^H W (stored as the R entries above the block), W1 = W - Q P1
@@ -1692,6 +1721,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_lsq_block(LsqState<A> S, int j0
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int r = lane; r < s; r += 64) rhol[r] = S.rho[r];
+      if (lane == 0) cl = *S.ctrl;  // the control block, kept in LDS and written back
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1726,11 +1756,13 @@ __global__ __launch_bounds__(kBlkThreads) void k_lsq_block(LsqState<A> S, int j0
           int flags = 0;
           if (brk) flags |= 2;
           if (loss) flags |= 4;
-          const bool due = control_due(S.ctrl, sres);  // (updates the estimate: always evaluated)
+          const bool due = control_due(&cl, sres);  // (updates the estimate: always evaluated)
           const bool halt = due || j == m || brk || loss;
           if (halt) flags |= 1;
           S.sres_hist[j] = sres;
           if (halt) {
+            S.ctrl->est = cl.est;
+            S.ctrl->sprev = cl.sprev;
             S.ctrl->halt = 1;
             S.ctrl->halt_j = j;
             S.ctrl->flags = flags;
@@ -1746,6 +1778,10 @@ __global__ __launch_bounds__(kBlkThreads) void k_lsq_block(LsqState<A> S, int j0
         }
       }
       for (int r = lane; r < s; r += 64) S.rho[r] = rhol[r];
+      if (lane == 0 && !halted) {
+        S.ctrl->est = cl.est;
+        S.ctrl->sprev = cl.sprev;
+      }
       if (lane == 0) {
         sh_last = last;
         sh_halt = halted;
@@ -1819,7 +1855,7 @@ void launch_lsq_steps(hipStream_t st, LsqState<A> S, int j0, int j1, int khat, i
   }
   if (kind != 2) {
     size_t lds = 0;
-    const int prow = std::max(1, khat + j1 - 1);
+    const int prow = (std::max(1, khat + j1 - 1) + 7) / 8 * 8;  // P rows padded to whole groups
     const int bc = lsq_block_cols<A>(s, prow, &lds);
     if (bc > 0) {
       hipLaunchKernelGGL(k_lsq_block<A>, dim3(1), dim3(kBlkThreads), lds, st, S, j0, j1, khat, m, t, s, redb,
