@@ -17,6 +17,8 @@ Contents
                 restart cycle, with the restart and sequence logic of
                 Section 3.6, in float64 / complex128, and its right Jacobi
                 preconditioned form.
+``ilu``         ILU(0) in a greedy multicolour ordering and GMRES-SDR right
+                preconditioned with it (Section 6 preconditions by ILU).
 """
 
 from .sketch import sketch_operator, sketch_pattern, splitmix64_mix  # noqa: F401
@@ -29,3 +31,4 @@ from .gmres_sdr import (  # noqa: F401
     sdr_solve_right_jacobi,
     harmonic_ritz_update,
 )
+from .ilu import ILU0, greedy_colours, ilu0, multicolour_order, sdr_solve_right_ilu0  # noqa: F401

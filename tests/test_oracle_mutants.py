@@ -172,3 +172,45 @@ def test_srdct_mutant_is_caught(name, monkeypatch):
             caught = True
             break
     assert caught, f"mutant {name} passed every pin"
+
+
+# Planted mistakes in the multicolour ILU(0) right preconditioning, against its pins.
+ILU_SRC = os.path.join(os.path.dirname(SRC), "ilu.py")
+ILU_MUTANTS = {
+    "left_preconditioning": ("return A @ M.solve(np.asarray(v).reshape(-1))",
+                             "return M.solve(A @ np.asarray(v).reshape(-1))"),
+    "no_pivot_division": ("            row[k] = row[k] / piv\n", "            row[k] = row[k]\n"),
+    "update_only_right_of_diagonal": ("                if j > k and j in row:", "                if j >= i and j in row:"),
+    "colours_from_higher_neighbours": ("used = {int(colours[j]) for j in nb if j < i}",
+                                       "used = {int(colours[j]) for j in nb if j > i}"),
+    "natural_order": ("    return np.lexsort((np.arange(n), colours))", "    return np.arange(n)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ILU_MUTANTS))
+def test_ilu_mutant_is_caught(name, monkeypatch):
+    import test_oracle_ilu as ipins
+    old, new = ILU_MUTANTS[name]
+    src = open(ILU_SRC).read()
+    assert src.count(old) == 1, old
+    src = src.replace(old, new).replace("from .gmres_sdr import", "from oracle.gmres_sdr import")
+    mod = types.ModuleType("oracle_ilu_mutant")
+    sys.modules["oracle_ilu_mutant"] = mod
+    try:
+        exec(compile(src, "oracle_ilu_mutant", "exec"), mod.__dict__)
+    finally:
+        del sys.modules["oracle_ilu_mutant"]
+    for attr in ("ILU0", "greedy_colours", "ilu0", "multicolour_order", "sdr_solve_right_ilu0"):
+        monkeypatch.setattr(ipins, attr, getattr(mod, attr))
+    caught = False
+    for pin in (ipins.test_five_point_colouring_is_the_checkerboard,
+                ipins.test_colouring_is_proper_and_greedy,
+                lambda: ipins.test_ilu0_defining_property_and_column_elimination("general"),
+                ipins.test_apply_and_multiply_are_inverse_and_match_dense_factors,
+                lambda: ipins.test_preconditioned_solution_matches_dense_solve("cd")):
+        try:
+            pin()
+        except Exception:
+            caught = True
+            break
+    assert caught, f"mutant {name} passed every pin"
