@@ -143,6 +143,21 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *                    b - A D^-1 u); the recycle space, basis and sketches
  *                    (sdr_get_recycle, sdr_get_basis) belong to A D^-1.
  *                    sdr_spmv and the adjoint solve use A unpreconditioned.
+ *                    2: right ILU(0) preconditioning (Section 6 solves its
+ *                    Stokes systems with ILU; zero fill, the right side and
+ *                    the elimination order are this library's readings):
+ *                    (A M^-1) u = b, x = M^-1 u, M = L U the ILU(0)
+ *                    factorisation of A with the unknowns taken colour by
+ *                    colour in a greedy colouring of the symmetrised pattern
+ *                    (each row, in increasing index, takes the smallest
+ *                    colour none of its lower-indexed neighbours holds).
+ *                    The factors live on A's entries and are refreshed by
+ *                    sdr_update_matrix; every diagonal entry must be stored
+ *                    and every pivot nonzero, else SDR_EINVAL as for 1.  An
+ *                    Arnoldi step applies M^-1 (2C - 1 launches for C
+ *                    colours, 3 for a 5-point stencil) before its SpMV.
+ *                    Residuals, basis and recycle space as for 1, with
+ *                    A M^-1 in place of A D^-1.
  *                    Default 0, set before the first solve.
  *   "sketch"         0 (default): the sparse-sign operator (zeta nonzeros
  *                    per column, drawn from seed); 1: the subsampled
@@ -258,6 +273,12 @@ int sdr_sketch_noalloc(int64_t n, int s_dim, int zeta, uint64_t seed, sdr_dtype 
 
 /* y = A x with the handle's matrix (FP64 / complex128 device vectors). */
 int sdr_spmv(sdr_handle* h, const void* x, void* y);
+
+/* z = M^-1 v for the handle's preconditioner (option "precond": 0 the
+ * identity, 1 D^-1, 2 the ILU(0) solve; Section 6), FP64 / complex128 device
+ * vectors of length n.  Factors the current matrix first if no solve has.
+ * SDR_EINVAL if that factorisation failed (zero diagonal entry or pivot). */
+int sdr_precond_apply(sdr_handle* h, const void* v, void* z);
 
 /* Basis data of the last cycle for inspection: the first ncols normalised
  * basis vectors V (n x ncols, FP64/c128 device), H ((m+1) x m host, column

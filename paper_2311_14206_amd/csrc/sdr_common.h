@@ -94,6 +94,8 @@ struct SketchSpec {
   int words;  // ceil(zeta / 4)
   int ext;    // 1: rows 0 .. s-1 are formed by another kernel (the subsampled
               // DCT); a step kernel keeps the partial layout and fills the rest
+  const void* src = nullptr;  // a step kernel's sketch and norm input when it is
+                              // not the SpMV input (right preconditioning)
 };
 
 }  // namespace sdr

@@ -265,6 +265,44 @@ void launch_jacobi(hipStream_t st, int n, int64_t nnz, const int* rp, const int*
 // x <- x * d (divide false) or x * (1 / d) (divide true), elementwise.
 template <class A>
 void launch_scale_by_diag(hipStream_t st, int n, const A* d, A* x, bool divide);
+
+// ILU(0) right preconditioning in a multicolour elimination order (Section 6
+// preconditions by ILU; zero fill and the greedy colour order are readings).
+// The factors live on A's own entries: F[e] is l_ik for an entry left of the
+// diagonal in the elimination order (kind 0), u_ii (kind 1) or u_ij (kind 2).
+// Rows of one colour are never neighbours, so the factorisation and both
+// triangular solves advance a colour per launch.
+struct IluView {
+  int n = 0;
+  int ncolours = 0;
+  const int* crow = nullptr;     // the rows, colour by colour (device)
+  const int* coff = nullptr;     // ncolours + 1 offsets into crow (host)
+  const int* rp = nullptr;       // A's pattern (device)
+  const int* ci = nullptr;
+  const uint8_t* kind = nullptr; // per entry: 0 lower, 1 diagonal, 2 upper
+  const int* dpos = nullptr;     // per row: its diagonal entry
+  const void* F = nullptr;       // factor values, A's value type
+};
+
+// The elimination, colour by colour: per row, its entries left of the
+// diagonal in elimination order, lo[l] = (entry (i,k), diagonal entry of k),
+// each followed by its updates up[up_off[l] .. up_off[l+1]) = (target entry
+// (i,j), source entry (k,j)).  F holds A's values on entry and the factors on
+// return; *flag is set if a pivot is zero.
+template <class A>
+void launch_ilu_factor(hipStream_t st, const IluView& v, const int* lo_off, const int2* lo, const int* up_off,
+                       const int2* up, A* F, int* flag);
+
+// out = M^-1 in (forward solve with L into y, backward solve with U), one
+// thread per row of a colour; y holds the forward solution (acc type).  With
+// ctrl, a launch returns at once when its halt flag is set.
+template <class T>
+void launch_ilu_apply(hipStream_t st, const IluView& v, const T* in, typename traits<T>::acc* y, T* out,
+                      const Ctrl* ctrl);
+
+// out = M x = L (U x), t = U x.
+template <class A>
+void launch_ilu_mult(hipStream_t st, const IluView& v, const A* x, A* t, A* out);
 // dst (T) = scale * src (acc type), rounding to T; with ctrl, the control
 // block is also reset for a new cycle (not halted, threshold thresh).
 template <class T>

@@ -320,8 +320,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sketch(
     }
     if (in) {
       if (s > 0) {
-        nx += abs2(xa);
-        if (sb > 0) sketch_scatter(bins, r, xa, sk);
+        const A xs = sk.src ? widen(static_cast<const T*>(sk.src)[r]) : xa;
+        nx += abs2(xs);
+        if (sb > 0) sketch_scatter(bins, r, xs, sk);
       }
       if (do_spmv) {
         const T wt = narrow<T>(acc);
@@ -424,8 +425,9 @@ __global__ __launch_bounds__(NT) void k_spmv_dia_sketch(
       if (halted) return;
       const A xa = widen(xt);
       if (s > 0) {
-        nx += abs2(xa);
-        if (sb > 0) sketch_scatter(bins, r, xa, sk);
+        const A xs = sk.src ? widen(static_cast<const T*>(sk.src)[r]) : xa;
+        nx += abs2(xs);
+        if (sb > 0) sketch_scatter(bins, r, xs, sk);
       }
       A acc = zero<A>();
 #pragma unroll
@@ -2706,6 +2708,130 @@ void launch_scale_by_diag(hipStream_t st, int n, const A* d, A* x, bool divide) 
                      divide ? 1 : 0);
 }
 
+// ------------------------------------------------------------- ILU(0) ---
+// One thread per row of the colour being eliminated: the row's entries left
+// of the diagonal in elimination order, in that order, each divided by its
+// pivot (a row of an earlier colour, already final) and its updates applied
+// to the row's own entries.
+template <class A>
+__global__ void k_ilu_factor(int cnt, const int* __restrict__ rows, const int* __restrict__ lo_off,
+                             const int2* __restrict__ lo, const int* __restrict__ up_off,
+                             const int2* __restrict__ up, const int* __restrict__ dpos, A* __restrict__ F,
+                             int* __restrict__ flag) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    const int i = rows[t];
+    for (int l = lo_off[i]; l < lo_off[i + 1]; ++l) {
+      const int2 pk = lo[l];
+      const A lik = F[pk.x] * recip(F[pk.y]);
+      F[pk.x] = lik;
+      for (int u = up_off[l]; u < up_off[l + 1]; ++u) {
+        const int2 q = up[u];
+        F[q.x] -= lik * F[q.y];
+      }
+    }
+    if (abs2(F[dpos[i]]) == 0.0) flag[0] = 1;
+  }
+}
+
+// Forward solve of one colour: y_i = in_i - sum over the row's lower entries
+// of l_ik y_k (the k of earlier colours); for the last colour also the
+// backward step z_i = y_i / u_ii (it has no entries right of the diagonal).
+template <class T>
+__global__ void k_ilu_fwd(int cnt, const int* __restrict__ rows, const int* __restrict__ rp,
+                          const int* __restrict__ ci, const uint8_t* __restrict__ kind,
+                          const int* __restrict__ dpos, const typename traits<T>::acc* __restrict__ F,
+                          const T* __restrict__ in, typename traits<T>::acc* __restrict__ y, T* __restrict__ z,
+                          int last, const Ctrl* __restrict__ ctrl) {
+  using A = typename traits<T>::acc;
+  if (ctrl && ctrl->halt) return;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    const int i = rows[t];
+    A acc = widen(in[i]);
+    const int e1 = rp[i + 1];
+    for (int e = rp[i]; e < e1; ++e)
+      if (kind[e] == 0) acc -= F[e] * y[ci[e]];
+    y[i] = acc;
+    if (last) z[i] = narrow<T>(acc * recip(F[dpos[i]]));
+  }
+}
+
+// Backward solve of one colour: z_i = (y_i - sum over the row's upper entries
+// of u_ij z_j) / u_ii (the j of later colours, already solved).
+template <class T>
+__global__ void k_ilu_bwd(int cnt, const int* __restrict__ rows, const int* __restrict__ rp,
+                          const int* __restrict__ ci, const uint8_t* __restrict__ kind,
+                          const int* __restrict__ dpos, const typename traits<T>::acc* __restrict__ F,
+                          const typename traits<T>::acc* __restrict__ y, T* __restrict__ z,
+                          const Ctrl* __restrict__ ctrl) {
+  using A = typename traits<T>::acc;
+  if (ctrl && ctrl->halt) return;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    const int i = rows[t];
+    A acc = y[i];
+    const int e1 = rp[i + 1];
+    for (int e = rp[i]; e < e1; ++e)
+      if (kind[e] == 2) acc -= F[e] * widen(z[ci[e]]);
+    z[i] = narrow<T>(acc * recip(F[dpos[i]]));
+  }
+}
+
+// t = U x over all rows (mode 0) or out = t + L t (mode 1).
+template <class A>
+__global__ void k_ilu_mult(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const uint8_t* __restrict__ kind, const A* __restrict__ F, const A* __restrict__ x,
+                           A* __restrict__ out, int mode) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    A acc = mode == 0 ? zero<A>() : x[i];
+    const int e1 = rp[i + 1];
+    for (int e = rp[i]; e < e1; ++e) {
+      const int k = kind[e];
+      if (mode == 0 ? k != 0 : k == 0) acc += F[e] * x[ci[e]];
+    }
+    out[i] = acc;
+  }
+}
+
+static inline int ilu_grid(int cnt) { return std::max(1, std::min((cnt + kBlock - 1) / kBlock, 1 << 16)); }
+
+template <class A>
+void launch_ilu_factor(hipStream_t st, const IluView& v, const int* lo_off, const int2* lo, const int* up_off,
+                       const int2* up, A* F, int* flag) {
+  for (int c = 0; c < v.ncolours; ++c) {
+    const int c0 = v.coff[c], cnt = v.coff[c + 1] - c0;
+    if (cnt <= 0) continue;
+    hipLaunchKernelGGL(k_ilu_factor<A>, dim3(ilu_grid(cnt)), dim3(kBlock), 0, st, cnt, v.crow + c0, lo_off, lo,
+                       up_off, up, v.dpos, F, flag);
+  }
+}
+
+template <class T>
+void launch_ilu_apply(hipStream_t st, const IluView& v, const T* in, typename traits<T>::acc* y, T* out,
+                      const Ctrl* ctrl) {
+  using A = typename traits<T>::acc;
+  const A* F = static_cast<const A*>(v.F);
+  const int C = v.ncolours;
+  for (int c = 0; c < C; ++c) {
+    const int c0 = v.coff[c], cnt = v.coff[c + 1] - c0;
+    if (cnt <= 0) continue;
+    hipLaunchKernelGGL(k_ilu_fwd<T>, dim3(ilu_grid(cnt)), dim3(kBlock), 0, st, cnt, v.crow + c0, v.rp, v.ci,
+                       v.kind, v.dpos, F, in, y, out, c == C - 1 ? 1 : 0, ctrl);
+  }
+  for (int c = C - 2; c >= 0; --c) {
+    const int c0 = v.coff[c], cnt = v.coff[c + 1] - c0;
+    if (cnt <= 0) continue;
+    hipLaunchKernelGGL(k_ilu_bwd<T>, dim3(ilu_grid(cnt)), dim3(kBlock), 0, st, cnt, v.crow + c0, v.rp, v.ci,
+                       v.kind, v.dpos, F, y, out, ctrl);
+  }
+}
+
+template <class A>
+void launch_ilu_mult(hipStream_t st, const IluView& v, const A* x, A* t, A* out) {
+  const A* F = static_cast<const A*>(v.F);
+  hipLaunchKernelGGL(k_ilu_mult<A>, dim3(ilu_grid(v.n)), dim3(kBlock), 0, st, v.n, v.rp, v.ci, v.kind, F, x, t, 0);
+  hipLaunchKernelGGL(k_ilu_mult<A>, dim3(ilu_grid(v.n)), dim3(kBlock), 0, st, v.n, v.rp, v.ci, v.kind, F, t, out,
+                     1);
+}
+
 // ---------------------------------------------------- instantiations ---
 #define SDR_INST_BASIS(T)                                                                        \
   template void launch_spmv_sketch<T>(hipStream_t, int, const int*, const int*, const T*,          \
@@ -2729,7 +2855,9 @@ void launch_scale_by_diag(hipStream_t st, int n, const A* d, A* x, bool divide) 
   template void launch_cast_rscale<T>(hipStream_t, int, const traits<T>::acc*, const traits<T>::acc*, T*, \
                                        Ctrl*, double);                                             \
   template void launch_widen_scale<T>(hipStream_t, int, const T*, double, traits<T>::acc*);       \
-  template void launch_narrow_values<T>(hipStream_t, int64_t, const traits<T>::acc*, T*);
+  template void launch_narrow_values<T>(hipStream_t, int64_t, const traits<T>::acc*, T*);        \
+  template void launch_ilu_apply<T>(hipStream_t, const IluView&, const T*, traits<T>::acc*, T*,    \
+                                    const Ctrl*);
 
 SDR_INST_BASIS(double)
 SDR_INST_BASIS(float)
@@ -2763,7 +2891,10 @@ SDR_INST_BASIS(cx<float>)
   template void launch_scale_by_diag<A>(hipStream_t, int, const A*, A*, bool);                 \
   template void launch_gather_conj<A>(hipStream_t, int64_t, const A*, const int*, A*);          \
   template void launch_grad_values<A>(hipStream_t, int, const int*, const int*, const A*,       \
-                                      const A*, A*);
+                                      const A*, A*);                                            \
+  template void launch_ilu_factor<A>(hipStream_t, const IluView&, const int*, const int2*,      \
+                                     const int*, const int2*, A*, int*);                        \
+  template void launch_ilu_mult<A>(hipStream_t, const IluView&, const A*, A*, A*);
 
 SDR_INST_ACC(double)
 SDR_INST_ACC(cx<double>)

@@ -91,7 +91,7 @@ struct Options {
   int lsq_kernel = 0;     // 0: register kernel where the shape allows, else block; 1: block; 2: per step
   int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
   int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
-  int precond = 0;        // 0: none; 1: right Jacobi, the forward solve runs on A D^-1
+  int precond = 0;        // 0: none; 1: right Jacobi (A D^-1); 2: right ILU(0), multicolour order
   int resid_control = 0;  // 0: safety factor (Section 3.4); 1: Givens estimate (Sections 4.5, 5)
   int sketch = 0;         // 0: sparse sign; 1: subsampled randomised DCT (Section 6)
   double givens_eps0 = 0.0;  // initial eps of the Givens estimate
@@ -160,6 +160,8 @@ struct SolverBase {
   virtual int sketch(const void* X, int ncols, void* Y) = 0;
   virtual void set_stream(hipStream_t s) = 0;
   virtual void set_options(const Options& o) = 0;
+  // Right ILU(0) preconditioning: the solver runs on A M^-1 (null: on A).
+  virtual void set_ilu(const IluView* v) = 0;
   virtual void reset() = 0;
   virtual int kernel_times(double* ms, int64_t* counts, int cap) = 0;
   virtual int spmv_layout(int* offsets, int cap) = 0;
@@ -315,6 +317,16 @@ class Solver final : public SolverBase {
     opt_.lsq_kernel = o.lsq_kernel;
   }
 
+  void set_ilu(const IluView* v) override {
+    ilu_ = v;
+    if (v && !izb_) {
+      izb_ = dalloc<T>(n_);
+      iy_ = dalloc<A>(n_);
+      izA_ = dalloc<A>(n_);
+      iyA_ = dalloc<A>(n_);
+    }
+  }
+
   void set_matrix(MatView<A> mat) { M_ = mat; }
 
   void matrix_changed() override {
@@ -439,7 +451,12 @@ class Solver final : public SolverBase {
   void enqueue_residual(const A* x, const A* b, A* r) {
     // The residual kernel also sketches r (when its bins fit), so that a
     // cycle starting from r reduces these partials instead of sketching r
-    // in a pass of its own.
+    // in a pass of its own.  Right ILU(0): r = b - A (M^-1 x).
+    if (ilu_) {
+      launch_ilu_apply<A>(stream_, *ilu_, x, iyA_, izA_, nullptr);
+      LAUNCHCHK();
+      x = izA_;
+    }
     const bool fuse = !dct_on_ && (size_t)kWaves * s_ * sizeof(A) <= 48 * 1024;
     SketchSpec skr = sk_;
     if (!fuse) skr.s = 0;
@@ -528,11 +545,21 @@ class Solver final : public SolverBase {
     T* w = P_ + (size_t)j * n_;
     const bool tm = timed(j, evp_);
     hipEvent_t* te = tm ? ev_[evp_][j].data() : nullptr;
+    // right ILU(0): the SpMV multiplies z = M^-1 p_{j-1}, the sketch and the
+    // norm stay those of p_{j-1}
+    const T* xin = x;
+    SketchSpec skj = sk_;
+    if (ilu_) {
+      launch_ilu_apply<T>(stream_, *ilu_, x, iy_, izb_, ctrl_);
+      LAUNCHCHK();
+      xin = izb_;
+      skj.src = x;
+    }
     if (dia())
-      launch_spmv_dia_sketch<T>(stream_, n_, dia_, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
+      launch_spmv_dia_sketch<T>(stream_, n_, dia_, xin, w, win, tw, skj, true, p1, nb1_, ctrl_,
                                 tm ? te[0] : nullptr, tm ? te[1] : nullptr);
     else
-      launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, x, w, win, tw, sk_, true, p1, nb1_, ctrl_,
+      launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, xin, w, win, tw, skj, true, p1, nb1_, ctrl_,
                             tm ? te[0] : nullptr, tm ? te[1] : nullptr);
     LAUNCHCHK();
     if (dct_on_) {  // S p_{j-1} into the sketch rows the step kernel left alone
@@ -790,11 +817,17 @@ class Solver final : public SolverBase {
       // exact variant: S A_i U with the new matrix (k products and sketches)
       for (int c = 0; c < khat_; ++c) {
         Window<T> win{};
+        const T* uc = U_ + (size_t)c * n_;
+        if (ilu_) {  // A M^-1 U
+          launch_ilu_apply<T>(stream_, *ilu_, uc, iy_, izb_, nullptr);
+          LAUNCHCHK();
+          uc = izb_;
+        }
         if (dia())
-          launch_spmv_dia_sketch<T>(stream_, n_, dia_, U_ + (size_t)c * n_, Unew_ + (size_t)c * n_, win, 0,
+          launch_spmv_dia_sketch<T>(stream_, n_, dia_, uc, Unew_ + (size_t)c * n_, win, 0,
                                     SketchSpec{}, true, part1_, nb1_, ctrl_free_);
         else
-          launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, U_ + (size_t)c * n_,
+          launch_spmv_sketch<T>(stream_, n_, M_.rp, M_.ci, vals, uc,
                                 Unew_ + (size_t)c * n_, win, 0, SketchSpec{}, true, part1_, nb1_,
                                 ctrl_free_);
         LAUNCHCHK();
@@ -1254,7 +1287,7 @@ class Solver final : public SolverBase {
                     (void*)nu_, (void*)sres_hist_, (void*)ctrl_, (void*)ctrl_free_, (void*)part1_,
                     (void*)redb_, (void*)psk_, (void*)red2_, (void*)red3_, (void*)Sr_,
                     (void*)ycoef_, (void*)xt_, (void*)r_, (void*)rnew_, (void*)G_, (void*)Gs_,
-                    (void*)C_, (void*)dct_rows_})
+                    (void*)C_, (void*)dct_rows_, (void*)izb_, (void*)iy_, (void*)izA_, (void*)iyA_})
       dfree(p);
     if (rec_host_) (void)hipHostFree(rec_host_);
     rec_host_ = nullptr;
@@ -1301,6 +1334,11 @@ class Solver final : public SolverBase {
   int* dia_map_ = nullptr;
   T* diaval_ = nullptr;
   T *P_ = nullptr, *U_ = nullptr, *Unew_ = nullptr;
+  // right ILU(0): z = M^-1 p for the step SpMV (izb_, forward solve in iy_)
+  // and for the residual (izA_, iyA_)
+  const IluView* ilu_ = nullptr;
+  T* izb_ = nullptr;
+  A *iy_ = nullptr, *izA_ = nullptr, *iyA_ = nullptr;
   T* Pbuf_[2] = {nullptr, nullptr};
   A* SBbuf_[2] = {nullptr, nullptr};
   A* SAWbuf_[2] = {nullptr, nullptr};
@@ -1414,7 +1452,17 @@ struct sdr_handle {
   void* d_pc = nullptr;
   void* vals_pc = nullptr;
   int* pc_flag = nullptr;
-  bool pc_bad = false;  // the last matrix had a zero diagonal entry: vals_pc is stale
+  bool pc_bad = false;  // the last matrix had a zero diagonal entry (or ILU pivot): the factors are stale
+  // right ILU(0) (option "precond" 2): the multicolour order and elimination
+  // lists of the pattern (built once) and the factors on A's entries
+  IluView ilu;
+  std::vector<int> ilu_coff;
+  int *ilu_crow = nullptr, *ilu_dpos = nullptr, *ilu_lo_off = nullptr, *ilu_up_off = nullptr;
+  int2 *ilu_lo = nullptr, *ilu_up = nullptr;
+  uint8_t* ilu_kind = nullptr;
+  void* ilu_F = nullptr;
+  void *ilu_t = nullptr, *ilu_u = nullptr;  // n-vectors for the change of variable
+  bool ilu_built = false;
   bool adj_ready = false;
   uint64_t pattern_hash = 0;
   hipStream_t own = nullptr;
@@ -1442,7 +1490,7 @@ uint64_t hash_pattern(const std::vector<int>& rp, const std::vector<int>& ci) {
 std::unique_ptr<SolverBase> make_solver(sdr_handle* h, bool adjoint) {
   const int* rp = adjoint ? h->rpT : h->rp;
   const int* ci = adjoint ? h->ciT : h->ci;
-  const void* v = adjoint ? h->valsT : h->opt.precond ? h->vals_pc : h->vals;
+  const void* v = adjoint ? h->valsT : h->opt.precond == 1 ? h->vals_pc : h->vals;
   if (!h->cpx) {
     MatView<double> mv{h->n, h->nnz, rp, ci, static_cast<const double*>(v)};
     if (h->opt.precision == 1)
@@ -1455,11 +1503,180 @@ std::unique_ptr<SolverBase> make_solver(sdr_handle* h, bool adjoint) {
   return std::unique_ptr<SolverBase>(new Solver<cx<double>>(mv, h->m, h->k, h->t, h->s, h->seed, h->opt, h->stream));
 }
 
+// The multicolour order and elimination lists of right ILU(0) for the
+// handle's pattern (host work, once per pattern): a greedy colouring of the
+// symmetrised pattern (each row, in increasing index, takes the smallest
+// colour none of its lower-indexed neighbours holds), the rows colour by
+// colour, each entry tagged left of / on / right of the diagonal in that
+// order, and per row its left entries in elimination order with the updates
+// each one makes to the row.  Throws SDR_EINVAL if a diagonal entry is not
+// stored.
+void build_ilu(sdr_handle* h) {
+  const int n = (int)h->n;
+  const int64_t nnz = h->nnz;
+  std::vector<int> rp(n + 1), ci(std::max<int64_t>(nnz, 1));
+  HIPCHK(hipMemcpy(rp.data(), h->rp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+  if (nnz > 0) HIPCHK(hipMemcpy(ci.data(), h->ci, sizeof(int) * nnz, hipMemcpyDeviceToHost));
+  // transpose pattern, for the symmetrised neighbours
+  std::vector<int> tp(n + 1, 0), tc(std::max<int64_t>(nnz, 1));
+  for (int64_t e = 0; e < nnz; ++e) tp[ci[e] + 1]++;
+  for (int i = 0; i < n; ++i) tp[i + 1] += tp[i];
+  {
+    std::vector<int> fill(tp.begin(), tp.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int e = rp[i]; e < rp[i + 1]; ++e) tc[fill[ci[e]]++] = i;
+  }
+  std::vector<int> colour(n, -1), mark;
+  int ncol = 0;
+  for (int i = 0; i < n; ++i) {
+    auto note = [&](int j) {
+      if (j < i) {
+        const int c = colour[j];
+        if (c >= (int)mark.size()) mark.resize(c + 1, -1);
+        mark[c] = i;
+      }
+    };
+    for (int e = rp[i]; e < rp[i + 1]; ++e) note(ci[e]);
+    for (int e = tp[i]; e < tp[i + 1]; ++e) note(tc[e]);
+    int c = 0;
+    while (c < (int)mark.size() && mark[c] == i) ++c;
+    colour[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  // rows by colour (increasing index within a colour) and their ranks
+  std::vector<int> coff(ncol + 1, 0), crow(n), rank(n);
+  for (int i = 0; i < n; ++i) coff[colour[i] + 1]++;
+  for (int c = 0; c < ncol; ++c) coff[c + 1] += coff[c];
+  {
+    std::vector<int> fill(coff.begin(), coff.end() - 1);
+    for (int i = 0; i < n; ++i) crow[fill[colour[i]]++] = i;
+  }
+  for (int p = 0; p < n; ++p) rank[crow[p]] = p;
+  std::vector<uint8_t> kind(std::max<int64_t>(nnz, 1));
+  std::vector<int> dpos(n, -1);
+  for (int i = 0; i < n; ++i)
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      const int j = ci[e];
+      kind[e] = j == i ? 1 : (rank[j] < rank[i] ? 0 : 2);
+      if (j == i) dpos[i] = e;
+    }
+  for (int i = 0; i < n; ++i)
+    if (dpos[i] < 0) {
+      h->pc_bad = true;
+      set_err("ILU(0) preconditioning needs every diagonal entry of A stored");
+      throw HipError{SDR_EINVAL};
+    }
+  // per row: left entries in elimination order, each with its updates
+  std::vector<int> lo_off(n + 1, 0), up_off(1, 0);
+  std::vector<int2> lo, up;
+  std::vector<int> left;
+  for (int i = 0; i < n; ++i) {
+    left.clear();
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+      if (kind[e] == 0) left.push_back(e);
+    std::sort(left.begin(), left.end(), [&](int a, int b) { return rank[ci[a]] < rank[ci[b]]; });
+    for (int e : left) {
+      const int k = ci[e];
+      lo.push_back(make_int2(e, dpos[k]));
+      for (int f = rp[k]; f < rp[k + 1]; ++f) {
+        if (kind[f] != 2) continue;  // u_kj, rank(j) > rank(k)
+        const int jc = ci[f];
+        for (int g = rp[i]; g < rp[i + 1]; ++g)
+          if (ci[g] == jc) {
+            up.push_back(make_int2(g, f));
+            break;
+          }
+      }
+      up_off.push_back((int)up.size());
+    }
+    lo_off[i + 1] = (int)lo.size();
+  }
+  const size_t nlo = std::max<size_t>(lo.size(), 1), nup = std::max<size_t>(up.size(), 1);
+  h->ilu_crow = dalloc<int>(n);
+  h->ilu_dpos = dalloc<int>(n);
+  h->ilu_lo_off = dalloc<int>(n + 1);
+  h->ilu_up_off = dalloc<int>(up_off.size());
+  h->ilu_lo = dalloc<int2>(nlo);
+  h->ilu_up = dalloc<int2>(nup);
+  h->ilu_kind = dalloc<uint8_t>(kind.size());
+  h->ilu_F = dalloc<unsigned char>(h->elem() * std::max<int64_t>(nnz, 1));
+  h->ilu_t = dalloc<unsigned char>(h->elem() * n);
+  h->ilu_u = dalloc<unsigned char>(h->elem() * n);
+  HIPCHK(hipMemcpy(h->ilu_crow, crow.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->ilu_dpos, dpos.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->ilu_lo_off, lo_off.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->ilu_up_off, up_off.data(), sizeof(int) * up_off.size(), hipMemcpyHostToDevice));
+  if (!lo.empty()) HIPCHK(hipMemcpy(h->ilu_lo, lo.data(), sizeof(int2) * lo.size(), hipMemcpyHostToDevice));
+  if (!up.empty()) HIPCHK(hipMemcpy(h->ilu_up, up.data(), sizeof(int2) * up.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->ilu_kind, kind.data(), kind.size(), hipMemcpyHostToDevice));
+  h->ilu_coff = coff;
+  IluView& v = h->ilu;
+  v.n = n;
+  v.ncolours = ncol;
+  v.crow = h->ilu_crow;
+  v.coff = h->ilu_coff.data();
+  v.rp = h->rp;
+  v.ci = h->ci;
+  v.kind = h->ilu_kind;
+  v.dpos = h->ilu_dpos;
+  v.F = h->ilu_F;
+  h->ilu_built = true;
+}
+
+// Right ILU(0): the factors of the handle's matrix (on A's entries, in the
+// multicolour order).  Throws SDR_EINVAL on a zero pivot.
+void refresh_ilu(sdr_handle* h) {
+  if (!h->ilu_built) build_ilu(h);
+  if (!h->pc_flag) h->pc_flag = dalloc<int>(1);
+  HIPCHK(hipMemsetAsync(h->pc_flag, 0, sizeof(int), h->stream));
+  HIPCHK(hipMemcpyAsync(h->ilu_F, h->vals, h->elem() * h->nnz, hipMemcpyDeviceToDevice, h->stream));
+  if (h->cpx)
+    launch_ilu_factor<cx<double>>(h->stream, h->ilu, h->ilu_lo_off, h->ilu_lo, h->ilu_up_off, h->ilu_up,
+                                  static_cast<cx<double>*>(h->ilu_F), h->pc_flag);
+  else
+    launch_ilu_factor<double>(h->stream, h->ilu, h->ilu_lo_off, h->ilu_lo, h->ilu_up_off, h->ilu_up,
+                              static_cast<double*>(h->ilu_F), h->pc_flag);
+  HIPCHK(hipGetLastError());
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, h->pc_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->pc_bad = flag != 0;
+  if (flag) {
+    set_err("ILU(0) preconditioning met a zero pivot");
+    throw HipError{SDR_EINVAL};
+  }
+}
+
+// x <- M x (to_u) or M^-1 x: the change of variable of right ILU(0).
+void ilu_transform(sdr_handle* h, void* x, bool to_u) {
+  if (h->cpx) {
+    auto* xv = static_cast<cx<double>*>(x);
+    auto* t = static_cast<cx<double>*>(h->ilu_t);
+    auto* u = static_cast<cx<double>*>(h->ilu_u);
+    if (to_u)
+      launch_ilu_mult<cx<double>>(h->stream, h->ilu, xv, t, u);
+    else
+      launch_ilu_apply<cx<double>>(h->stream, h->ilu, xv, t, u, nullptr);
+  } else {
+    auto* xv = static_cast<double*>(x);
+    auto* t = static_cast<double*>(h->ilu_t);
+    auto* u = static_cast<double*>(h->ilu_u);
+    if (to_u)
+      launch_ilu_mult<double>(h->stream, h->ilu, xv, t, u);
+    else
+      launch_ilu_apply<double>(h->stream, h->ilu, xv, t, u, nullptr);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(x, h->ilu_u, h->elem() * h->n, hipMemcpyDeviceToDevice, h->stream));
+}
+
 // Right Jacobi preconditioning, A x = b as (A D^-1) u = b with x = D^-1 u and
 // D = diag(A): refresh d and the values of A D^-1 from the handle's matrix.
-// Throws SDR_EINVAL if a diagonal entry is zero or not stored.
+// Throws SDR_EINVAL if a diagonal entry is zero or not stored.  (Precond 2:
+// the ILU(0) factors instead.)
 void refresh_precond(sdr_handle* h) {
   if (h->opt.precond == 0) return;
+  if (h->opt.precond == 2) return refresh_ilu(h);
   if (!h->vals_pc) {
     h->d_pc = dalloc<unsigned char>(h->elem() * h->n);
     h->vals_pc = dalloc<unsigned char>(h->elem() * std::max<int64_t>(h->nnz, 1));
@@ -1503,6 +1720,7 @@ SolverBase* fwd(sdr_handle* h) {
   if (!h->fwd) {
     refresh_precond(h);
     h->fwd = make_solver(h, false);
+    if (h->opt.precond == 2) h->fwd->set_ilu(&h->ilu);
   }
   return h->fwd.get();
 }
@@ -1682,7 +1900,8 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
     if (built || (v != 0.0 && v != 1.0)) return set_err("dia is 0 or 1, before the first solve"), SDR_EINVAL;
     h->opt.dia = (int)v;
   } else if (k == "precond") {
-    if (built || (v != 0.0 && v != 1.0)) return set_err("precond is 0 or 1, before the first solve"), SDR_EINVAL;
+    if (built || (v != 0.0 && v != 1.0 && v != 2.0))
+      return set_err("precond is 0, 1 (Jacobi) or 2 (ILU(0)), before the first solve"), SDR_EINVAL;
     h->opt.precond = (int)v;
   } else if (k == "sketch") {
     if (built || (v != 0.0 && v != 1.0))
@@ -1770,8 +1989,16 @@ int sdr_solve(sdr_handle* h, const sdr_csr* A, const void* b, void* x, double to
     SolverBase* f = fwd(h);
     if (h->opt.precond == 0) return f->solve(b, x, tol, st, &h->trace);
     if (h->pc_bad) {
-      set_err("Jacobi preconditioning needs every diagonal entry of A stored and nonzero");
+      set_err(h->opt.precond == 2 ? "ILU(0) preconditioning of the current matrix failed (zero pivot)"
+                                  : "Jacobi preconditioning needs every diagonal entry of A stored and nonzero");
       return SDR_EINVAL;
+    }
+    if (h->opt.precond == 2) {
+      ilu_transform(h, x, true);  // the initial guess u0 = M x0
+      const int rc = f->solve(b, x, tol, st, &h->trace);
+      ilu_transform(h, x, false);  // x = M^-1 u
+      HIPCHK(hipStreamSynchronize(h->stream));
+      return rc;
     }
     precond_scale(h, x, true);  // the initial guess u0 = D x0
     const int rc = f->solve(b, x, tol, st, &h->trace);
@@ -1842,6 +2069,25 @@ int sdr_sketch(sdr_handle* h, const void* X, int ncols, void* Y) {
   try {
     order_after_caller(h);
     return fwd(h)->sketch(X, ncols, Y);
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_precond_apply(sdr_handle* h, const void* v, void* z) {
+  if (!h || !v || !z) return set_err("bad argument"), SDR_EINVAL;
+  g_err.clear();
+  try {
+    order_after_caller(h);
+    (void)fwd(h);  // (builds and factors the preconditioner)
+    if (h->pc_bad) return set_err("the preconditioner of the current matrix failed"), SDR_EINVAL;
+    HIPCHK(hipMemcpyAsync(z, v, h->elem() * h->n, hipMemcpyDeviceToDevice, h->stream));
+    if (h->opt.precond == 2)
+      ilu_transform(h, z, false);
+    else if (h->opt.precond == 1)
+      precond_scale(h, z, false);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SDR_OK;
   } catch (HipError& e) {
     return e.code;
   }
@@ -1928,7 +2174,9 @@ void sdr_destroy(sdr_handle* h) {
   h->fwd.reset();
   h->adj.reset();
   for (void* p : {(void*)h->rp, (void*)h->ci, h->vals, (void*)h->rpT, (void*)h->ciT, (void*)h->perm,
-                  h->valsT, h->d_pc, h->vals_pc, (void*)h->pc_flag})
+                  h->valsT, h->d_pc, h->vals_pc, (void*)h->pc_flag, (void*)h->ilu_crow, (void*)h->ilu_dpos,
+                  (void*)h->ilu_lo_off, (void*)h->ilu_up_off, (void*)h->ilu_lo, (void*)h->ilu_up,
+                  (void*)h->ilu_kind, h->ilu_F, h->ilu_t, h->ilu_u})
     dfree(p);
   if (h->own) (void)hipStreamDestroy(h->own);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);

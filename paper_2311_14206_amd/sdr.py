@@ -60,6 +60,7 @@ EXPORTS = {
                                   C.POINTER(C.c_int)]),
     "sdr_sketch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "sdr_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sdr_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sdr_sketch_noalloc": (C.c_int, [C.c_int64, C.c_int, C.c_int, C.c_uint64, C.c_int, C.c_void_p,
                                      C.c_int, C.c_void_p, C.c_void_p]),
     "sdr_get_basis": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -273,6 +274,14 @@ class SDRSolver:
         self._stream()
         _check(lib().sdr_spmv(self.h, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y))), "sdr_spmv")
         return y
+
+    def precond_apply(self, v):
+        """z = M^-1 v for the solver's preconditioner (the identity without one)."""
+        self._vec(v)
+        z = torch.empty_like(v)
+        self._stream()
+        _check(lib().sdr_precond_apply(self.h, C.c_void_p(_ptr(v)), C.c_void_p(_ptr(z))), "sdr_precond_apply")
+        return z
 
     def basis(self, ncols):
         """Normalised basis V (n x ncols), H ((m+1) x m) and SV (s x ncols) of the last cycle."""
