@@ -521,6 +521,66 @@ def helmholtz_bench(dev, with_oracle=True, reps=2):
     return out
 
 
+def ilu_bench(dev, reps=2):
+    """The 1024^2 convection-diffusion system right-preconditioned by ILU(0)
+    (multicolour order): time to 1e-8 and the cost of one M^-1 apply.  The
+    oracle's ILU(0) is pure Python, too slow at this size: its parity is held
+    by the GPU tests at small sizes."""
+    import numpy as np
+    import torch
+    from paper_2311_14206_amd.sdr import SDRSolver
+    from workloads import workload, describe
+
+    name = "cd2d_1024"
+    A, b, p = workload(name)
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_idx).to(dev)
+    vals = torch.from_numpy(A.values).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    h = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"], zeta=p["zeta"],
+                  precond=2, kernel_timing=64)
+    h.solve(bd, tol=p["tol"])  # warm-up (and the factorisation)
+    times, st, x = [], None, None
+    for _ in range(reps):
+        h.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = h.solve(bd, tol=p["tol"])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    xh = x.cpu().numpy()
+    relres = float(np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b))
+    # one apply z = M^-1 v, timed alone
+    z = h.precond_apply(bd)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nrep = 20
+    e0.record()
+    for _ in range(nrep):
+        z = h.precond_apply(bd)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / nrep
+    # algorithmic bytes of one apply (two colours, packed factors): every
+    # off-diagonal factor entry once (column index and value); per row its
+    # position in the colour order, the input, 1/u_ii and z written; the
+    # neighbours' values once (in for the first colour's rows, z for the
+    # second's)
+    n, nnz, ev = A.n, A.nnz, 8
+    bytes_apply = (nnz - n) * (4 + ev) + n * (4 + ev + ev + ev) + n * ev
+    out = {"workload": describe(name) + ", right ILU(0), multicolour order", "m": p["m"], "k": p["k"],
+           "t": p["t"], "s": p["s"], "tol": p["tol"],
+           "time_to_tol_s": statistics.median(times), "times": times, "iters": st["iters"],
+           "cycles": st["cycles"], "converged": st["converged"], "relres_host": relres,
+           "apply": {"ms": ms, "bytes": bytes_apply, "achieved_gbs": bytes_apply / (ms * 1e-3) / 1e9,
+                     "peak_gbs": 8000.0, "launches": 2,
+                     "note": "20 applies back to back timed with events (launch gaps included)"}}
+    print(f"[bench] ilu(0) cd2d_1024: {statistics.median(times):.3f} s, {st['iters']} steps, "
+          f"{st['cycles']} cycles, relres {relres:.2e}, apply {ms * 1e3:.1f} us", file=sys.stderr, flush=True)
+    h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -696,6 +756,8 @@ def main():
         line["helmholtz"] = helmholtz_bench(dev, with_oracle=not args.no_cpu_baseline)
         torch.cuda.empty_cache()
         line["srdct"] = srdct_bench(dev, with_oracle=not args.no_cpu_baseline)
+        torch.cuda.empty_cache()
+        line["ilu"] = ilu_bench(dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(A, b, p, st["iters"])

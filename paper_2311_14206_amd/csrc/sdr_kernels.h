@@ -282,6 +282,22 @@ struct IluView {
   const uint8_t* kind = nullptr; // per entry: 0 lower, 1 diagonal, 2 upper
   const int* dpos = nullptr;     // per row: its diagonal entry
   const void* F = nullptr;       // factor values, A's value type
+  // The factors packed for the solves, by colour in sliced ELL form (64 rows
+  // of a colour per slice; a slice's entries column-major, so lane l of a
+  // wave reads row l of every entry column): the entries left of the
+  // diagonal for the forward solve of colours 1.., right of it for the
+  // backward solve of colours ..C-2.  Padding has value 0 and column 0.
+  const int* lslice = nullptr;   // per slice: first packed slot (host index by colour: lsl0)
+  const int* lw = nullptr;       // per slice: width
+  const int* lcol = nullptr;
+  const void* lval = nullptr;
+  const int* uslice = nullptr;
+  const int* uw = nullptr;
+  const int* ucol = nullptr;
+  const void* uval = nullptr;
+  const int* lsl0 = nullptr;     // host: ncolours + 1 first slice of each colour (forward)
+  const int* usl0 = nullptr;     // host: ncolours + 1 (backward)
+  const void* dinv = nullptr;    // 1 / u_ii by position in crow
 };
 
 // The elimination, colour by colour: per row, its entries left of the
@@ -292,6 +308,12 @@ struct IluView {
 template <class A>
 void launch_ilu_factor(hipStream_t st, const IluView& v, const int* lo_off, const int2* lo, const int* up_off,
                        const int2* up, A* F, int* flag);
+
+// The packed copies of the factors (lval, uval from F through the slot maps
+// lsrc, usrc, -1 for padding) and dinv.
+template <class A>
+void launch_ilu_pack(hipStream_t st, const IluView& v, int64_t nl, const int* lsrc, int64_t nu,
+                     const int* usrc);
 
 // out = M^-1 in (forward solve with L into y, backward solve with U), one
 // thread per row of a colour; y holds the forward solution (acc type).  With

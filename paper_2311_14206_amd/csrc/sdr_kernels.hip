@@ -2733,46 +2733,75 @@ __global__ void k_ilu_factor(int cnt, const int* __restrict__ rows, const int* _
   }
 }
 
-// Forward solve of one colour: y_i = in_i - sum over the row's lower entries
-// of l_ik y_k (the k of earlier colours); for the last colour also the
-// backward step z_i = y_i / u_ii (it has no entries right of the diagonal).
+// Forward solve of one colour from its packed lower entries: y_i = in_i -
+// sum of l_ik y_k (the k of earlier colours; src is y, or in itself when
+// every earlier row is of colour 0, where y = in).  For the last colour also
+// the backward step z_i = y_i / u_ii (no entries right of its diagonal);
+// y is then not stored unless asked for.
 template <class T>
-__global__ void k_ilu_fwd(int cnt, const int* __restrict__ rows, const int* __restrict__ rp,
-                          const int* __restrict__ ci, const uint8_t* __restrict__ kind,
-                          const int* __restrict__ dpos, const typename traits<T>::acc* __restrict__ F,
-                          const T* __restrict__ in, typename traits<T>::acc* __restrict__ y, T* __restrict__ z,
-                          int last, const Ctrl* __restrict__ ctrl) {
+__global__ void k_ilu_fwd(int cnt, const int* __restrict__ rows, const int* __restrict__ sl_off,
+                          const int* __restrict__ sl_w, const int* __restrict__ col,
+                          const typename traits<T>::acc* __restrict__ val,
+                          const typename traits<T>::acc* __restrict__ dinv, const T* __restrict__ in,
+                          const typename traits<T>::acc* __restrict__ ysrc, int src_in,
+                          typename traits<T>::acc* __restrict__ y, T* __restrict__ z, int last,
+                          const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
   if (ctrl && ctrl->halt) return;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    const int sl = t >> 6, lane = t & 63;
     const int i = rows[t];
     A acc = widen(in[i]);
-    const int e1 = rp[i + 1];
-    for (int e = rp[i]; e < e1; ++e)
-      if (kind[e] == 0) acc -= F[e] * y[ci[e]];
-    y[i] = acc;
-    if (last) z[i] = narrow<T>(acc * recip(F[dpos[i]]));
+    const int o = sl_off[sl], w = sl_w[sl];
+    for (int k = 0; k < w; ++k) {
+      const int c = col[o + k * 64 + lane];
+      const A v = val[o + k * 64 + lane];
+      acc -= v * (src_in ? widen(in[c]) : ysrc[c]);
+    }
+    if (y) y[i] = acc;
+    if (last) z[i] = narrow<T>(acc * dinv[t]);
   }
 }
 
-// Backward solve of one colour: z_i = (y_i - sum over the row's upper entries
-// of u_ij z_j) / u_ii (the j of later colours, already solved).
+// Backward solve of one colour from its packed upper entries: z_i = (y_i -
+// sum of u_ij z_j) / u_ii, the j of later colours (y_i = in_i for colour 0).
 template <class T>
-__global__ void k_ilu_bwd(int cnt, const int* __restrict__ rows, const int* __restrict__ rp,
-                          const int* __restrict__ ci, const uint8_t* __restrict__ kind,
-                          const int* __restrict__ dpos, const typename traits<T>::acc* __restrict__ F,
+__global__ void k_ilu_bwd(int cnt, const int* __restrict__ rows, const int* __restrict__ sl_off,
+                          const int* __restrict__ sl_w, const int* __restrict__ col,
+                          const typename traits<T>::acc* __restrict__ val,
+                          const typename traits<T>::acc* __restrict__ dinv, const T* __restrict__ in,
                           const typename traits<T>::acc* __restrict__ y, T* __restrict__ z,
                           const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
   if (ctrl && ctrl->halt) return;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    const int sl = t >> 6, lane = t & 63;
     const int i = rows[t];
-    A acc = y[i];
-    const int e1 = rp[i + 1];
-    for (int e = rp[i]; e < e1; ++e)
-      if (kind[e] == 2) acc -= F[e] * widen(z[ci[e]]);
-    z[i] = narrow<T>(acc * recip(F[dpos[i]]));
+    A acc = y ? y[i] : widen(in[i]);
+    const int o = sl_off[sl], w = sl_w[sl];
+    for (int k = 0; k < w; ++k) {
+      const int c = col[o + k * 64 + lane];
+      const A v = val[o + k * 64 + lane];
+      acc -= v * widen(z[c]);
+    }
+    z[i] = narrow<T>(acc * dinv[t]);
   }
+}
+
+// Packed factor copies: val[p] = F[src[p]] (0 for padding).
+template <class A>
+__global__ void k_ilu_pack(int64_t np, const int* __restrict__ src, const A* __restrict__ F, A* __restrict__ out) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    const int e = src[p];
+    out[p] = e >= 0 ? F[e] : zero<A>();
+  }
+}
+
+template <class A>
+__global__ void k_ilu_dinv(int n, const int* __restrict__ rows, const int* __restrict__ dpos,
+                           const A* __restrict__ F, A* __restrict__ dinv) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    dinv[t] = recip(F[dpos[rows[t]]]);
 }
 
 // t = U x over all rows (mode 0) or out = t + L t (mode 1).
@@ -2804,24 +2833,50 @@ void launch_ilu_factor(hipStream_t st, const IluView& v, const int* lo_off, cons
   }
 }
 
+// Colour 0 has no entries left of its diagonal (its rows neighbour no row of
+// the same colour), so y = in there; with two colours the forward solve of
+// colour 1 reads in directly and y is never stored: two launches.
 template <class T>
 void launch_ilu_apply(hipStream_t st, const IluView& v, const T* in, typename traits<T>::acc* y, T* out,
                       const Ctrl* ctrl) {
   using A = typename traits<T>::acc;
-  const A* F = static_cast<const A*>(v.F);
+  const A* lval = static_cast<const A*>(v.lval);
+  const A* uval = static_cast<const A*>(v.uval);
+  const A* dinv = static_cast<const A*>(v.dinv);
   const int C = v.ncolours;
+  const bool two = C <= 2;
   for (int c = 0; c < C; ++c) {
     const int c0 = v.coff[c], cnt = v.coff[c + 1] - c0;
     if (cnt <= 0) continue;
-    hipLaunchKernelGGL(k_ilu_fwd<T>, dim3(ilu_grid(cnt)), dim3(kBlock), 0, st, cnt, v.crow + c0, v.rp, v.ci,
-                       v.kind, v.dpos, F, in, y, out, c == C - 1 ? 1 : 0, ctrl);
+    if (c == 0 && C > 1 && two) continue;  // y = in for colour 0, read in place
+    const int s0 = v.lsl0[c];
+    hipLaunchKernelGGL(k_ilu_fwd<T>, dim3(ilu_grid(cnt)), dim3(kBlock), 0, st, cnt, v.crow + c0,
+                       v.lslice + s0, v.lw + s0, v.lcol, lval, dinv + c0, in, (const A*)y, two ? 1 : 0,
+                       two ? (A*)nullptr : y, out, c == C - 1 ? 1 : 0, ctrl);
   }
   for (int c = C - 2; c >= 0; --c) {
     const int c0 = v.coff[c], cnt = v.coff[c + 1] - c0;
     if (cnt <= 0) continue;
-    hipLaunchKernelGGL(k_ilu_bwd<T>, dim3(ilu_grid(cnt)), dim3(kBlock), 0, st, cnt, v.crow + c0, v.rp, v.ci,
-                       v.kind, v.dpos, F, y, out, ctrl);
+    const int s0 = v.usl0[c];
+    hipLaunchKernelGGL(k_ilu_bwd<T>, dim3(ilu_grid(cnt)), dim3(kBlock), 0, st, cnt, v.crow + c0,
+                       v.uslice + s0, v.uw + s0, v.ucol, uval, dinv + c0, in,
+                       (c == 0 && two) ? (const A*)nullptr : (const A*)y, out, ctrl);
   }
+}
+
+template <class A>
+void launch_ilu_pack(hipStream_t st, const IluView& v, int64_t nl, const int* lsrc, int64_t nu,
+                     const int* usrc) {
+  const A* F = static_cast<const A*>(v.F);
+  auto grid = [](int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 1 << 16)); };
+  if (nl > 0)
+    hipLaunchKernelGGL(k_ilu_pack<A>, dim3(grid(nl)), dim3(kBlock), 0, st, nl, lsrc, F,
+                       static_cast<A*>(const_cast<void*>(v.lval)));
+  if (nu > 0)
+    hipLaunchKernelGGL(k_ilu_pack<A>, dim3(grid(nu)), dim3(kBlock), 0, st, nu, usrc, F,
+                       static_cast<A*>(const_cast<void*>(v.uval)));
+  hipLaunchKernelGGL(k_ilu_dinv<A>, dim3(ilu_grid(v.n)), dim3(kBlock), 0, st, v.n, v.crow, v.dpos, F,
+                     static_cast<A*>(const_cast<void*>(v.dinv)));
 }
 
 template <class A>
@@ -2894,7 +2949,8 @@ SDR_INST_BASIS(cx<float>)
                                       const A*, A*);                                            \
   template void launch_ilu_factor<A>(hipStream_t, const IluView&, const int*, const int2*,      \
                                      const int*, const int2*, A*, int*);                        \
-  template void launch_ilu_mult<A>(hipStream_t, const IluView&, const A*, A*, A*);
+  template void launch_ilu_mult<A>(hipStream_t, const IluView&, const A*, A*, A*);               \
+  template void launch_ilu_pack<A>(hipStream_t, const IluView&, int64_t, const int*, int64_t, const int*);
 
 SDR_INST_ACC(double)
 SDR_INST_ACC(cx<double>)

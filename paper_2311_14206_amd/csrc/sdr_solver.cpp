@@ -1462,6 +1462,13 @@ struct sdr_handle {
   uint8_t* ilu_kind = nullptr;
   void* ilu_F = nullptr;
   void *ilu_t = nullptr, *ilu_u = nullptr;  // n-vectors for the change of variable
+  // sliced-ELL copies for the solves: slot maps (entry of F or -1), columns,
+  // values, slice tables (device) and each colour's first slice (host)
+  int *ilu_lsrc = nullptr, *ilu_usrc = nullptr, *ilu_lcol = nullptr, *ilu_ucol = nullptr;
+  int *ilu_lslice = nullptr, *ilu_lw = nullptr, *ilu_uslice = nullptr, *ilu_uw = nullptr;
+  void *ilu_lval = nullptr, *ilu_uval = nullptr, *ilu_dinv = nullptr;
+  std::vector<int> ilu_lsl0, ilu_usl0;
+  int64_t ilu_nl = 0, ilu_nu = 0;
   bool ilu_built = false;
   bool adj_ready = false;
   uint64_t pattern_hash = 0;
@@ -1591,6 +1598,63 @@ void build_ilu(sdr_handle* h) {
     }
     lo_off[i + 1] = (int)lo.size();
   }
+  // sliced-ELL packing by colour: kind 0 entries for the forward solve,
+  // kind 2 for the backward solve
+  auto pack = [&](uint8_t want, std::vector<int>& src, std::vector<int>& col, std::vector<int>& slo,
+                  std::vector<int>& sw, std::vector<int>& sl0) {
+    sl0.assign(ncol + 1, 0);
+    std::vector<int> ent;
+    for (int c = 0; c < ncol; ++c) {
+      sl0[c] = (int)slo.size();
+      const int c0 = coff[c], cnt = coff[c + 1] - c0;
+      for (int b0 = 0; b0 < cnt; b0 += 64) {
+        int w = 0;
+        for (int t = b0; t < std::min(cnt, b0 + 64); ++t) {
+          const int i = crow[c0 + t];
+          int k = 0;
+          for (int e = rp[i]; e < rp[i + 1]; ++e) k += kind[e] == want;
+          w = std::max(w, k);
+        }
+        const int o = (int)src.size();
+        slo.push_back(o);
+        sw.push_back(w);
+        src.resize(o + (size_t)w * 64, -1);
+        col.resize(o + (size_t)w * 64, 0);
+        for (int t = b0; t < std::min(cnt, b0 + 64); ++t) {
+          const int i = crow[c0 + t];
+          int k = 0;
+          for (int e = rp[i]; e < rp[i + 1]; ++e)
+            if (kind[e] == want) {
+              src[o + (size_t)k * 64 + (t - b0)] = e;
+              col[o + (size_t)k * 64 + (t - b0)] = ci[e];
+              ++k;
+            }
+        }
+      }
+    }
+    sl0[ncol] = (int)slo.size();
+  };
+  std::vector<int> lsrc, lcolv, lslo, lsw, usrc, ucolv, uslo, usw;
+  pack(0, lsrc, lcolv, lslo, lsw, h->ilu_lsl0);
+  pack(2, usrc, ucolv, uslo, usw, h->ilu_usl0);
+  auto up_vec = [](const std::vector<int>& v) {
+    int* d = dalloc<int>(std::max<size_t>(v.size(), 1));
+    if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice));
+    return d;
+  };
+  h->ilu_lsrc = up_vec(lsrc);
+  h->ilu_lcol = up_vec(lcolv);
+  h->ilu_lslice = up_vec(lslo);
+  h->ilu_lw = up_vec(lsw);
+  h->ilu_usrc = up_vec(usrc);
+  h->ilu_ucol = up_vec(ucolv);
+  h->ilu_uslice = up_vec(uslo);
+  h->ilu_uw = up_vec(usw);
+  h->ilu_nl = (int64_t)lsrc.size();
+  h->ilu_nu = (int64_t)usrc.size();
+  h->ilu_lval = dalloc<unsigned char>(h->elem() * std::max<size_t>(lsrc.size(), 1));
+  h->ilu_uval = dalloc<unsigned char>(h->elem() * std::max<size_t>(usrc.size(), 1));
+  h->ilu_dinv = dalloc<unsigned char>(h->elem() * n);
   const size_t nlo = std::max<size_t>(lo.size(), 1), nup = std::max<size_t>(up.size(), 1);
   h->ilu_crow = dalloc<int>(n);
   h->ilu_dpos = dalloc<int>(n);
@@ -1620,6 +1684,17 @@ void build_ilu(sdr_handle* h) {
   v.kind = h->ilu_kind;
   v.dpos = h->ilu_dpos;
   v.F = h->ilu_F;
+  v.lslice = h->ilu_lslice;
+  v.lw = h->ilu_lw;
+  v.lcol = h->ilu_lcol;
+  v.lval = h->ilu_lval;
+  v.uslice = h->ilu_uslice;
+  v.uw = h->ilu_uw;
+  v.ucol = h->ilu_ucol;
+  v.uval = h->ilu_uval;
+  v.lsl0 = h->ilu_lsl0.data();
+  v.usl0 = h->ilu_usl0.data();
+  v.dinv = h->ilu_dinv;
   h->ilu_built = true;
 }
 
@@ -1630,12 +1705,15 @@ void refresh_ilu(sdr_handle* h) {
   if (!h->pc_flag) h->pc_flag = dalloc<int>(1);
   HIPCHK(hipMemsetAsync(h->pc_flag, 0, sizeof(int), h->stream));
   HIPCHK(hipMemcpyAsync(h->ilu_F, h->vals, h->elem() * h->nnz, hipMemcpyDeviceToDevice, h->stream));
-  if (h->cpx)
+  if (h->cpx) {
     launch_ilu_factor<cx<double>>(h->stream, h->ilu, h->ilu_lo_off, h->ilu_lo, h->ilu_up_off, h->ilu_up,
                                   static_cast<cx<double>*>(h->ilu_F), h->pc_flag);
-  else
+    launch_ilu_pack<cx<double>>(h->stream, h->ilu, h->ilu_nl, h->ilu_lsrc, h->ilu_nu, h->ilu_usrc);
+  } else {
     launch_ilu_factor<double>(h->stream, h->ilu, h->ilu_lo_off, h->ilu_lo, h->ilu_up_off, h->ilu_up,
                               static_cast<double*>(h->ilu_F), h->pc_flag);
+    launch_ilu_pack<double>(h->stream, h->ilu, h->ilu_nl, h->ilu_lsrc, h->ilu_nu, h->ilu_usrc);
+  }
   HIPCHK(hipGetLastError());
   int flag = 0;
   HIPCHK(hipMemcpyAsync(&flag, h->pc_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -2081,11 +2159,18 @@ int sdr_precond_apply(sdr_handle* h, const void* v, void* z) {
     order_after_caller(h);
     (void)fwd(h);  // (builds and factors the preconditioner)
     if (h->pc_bad) return set_err("the preconditioner of the current matrix failed"), SDR_EINVAL;
-    HIPCHK(hipMemcpyAsync(z, v, h->elem() * h->n, hipMemcpyDeviceToDevice, h->stream));
-    if (h->opt.precond == 2)
-      ilu_transform(h, z, false);
-    else if (h->opt.precond == 1)
-      precond_scale(h, z, false);
+    if (h->opt.precond == 2) {  // straight into z, the forward solution in the handle's scratch
+      if (h->cpx)
+        launch_ilu_apply<cx<double>>(h->stream, h->ilu, static_cast<const cx<double>*>(v),
+                                     static_cast<cx<double>*>(h->ilu_t), static_cast<cx<double>*>(z), nullptr);
+      else
+        launch_ilu_apply<double>(h->stream, h->ilu, static_cast<const double*>(v),
+                                 static_cast<double*>(h->ilu_t), static_cast<double*>(z), nullptr);
+      HIPCHK(hipGetLastError());
+    } else {
+      HIPCHK(hipMemcpyAsync(z, v, h->elem() * h->n, hipMemcpyDeviceToDevice, h->stream));
+      if (h->opt.precond == 1) precond_scale(h, z, false);
+    }
     HIPCHK(hipStreamSynchronize(h->stream));
     return SDR_OK;
   } catch (HipError& e) {
@@ -2176,7 +2261,9 @@ void sdr_destroy(sdr_handle* h) {
   for (void* p : {(void*)h->rp, (void*)h->ci, h->vals, (void*)h->rpT, (void*)h->ciT, (void*)h->perm,
                   h->valsT, h->d_pc, h->vals_pc, (void*)h->pc_flag, (void*)h->ilu_crow, (void*)h->ilu_dpos,
                   (void*)h->ilu_lo_off, (void*)h->ilu_up_off, (void*)h->ilu_lo, (void*)h->ilu_up,
-                  (void*)h->ilu_kind, h->ilu_F, h->ilu_t, h->ilu_u})
+                  (void*)h->ilu_kind, h->ilu_F, h->ilu_t, h->ilu_u, (void*)h->ilu_lsrc, (void*)h->ilu_usrc,
+                  (void*)h->ilu_lcol, (void*)h->ilu_ucol, (void*)h->ilu_lslice, (void*)h->ilu_lw,
+                  (void*)h->ilu_uslice, (void*)h->ilu_uw, h->ilu_lval, h->ilu_uval, h->ilu_dinv})
     dfree(p);
   if (h->own) (void)hipStreamDestroy(h->own);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
