@@ -17,8 +17,11 @@ struct cx {
 template <class R> SDR_HD cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
 template <class R> SDR_HD cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
 template <class R> SDR_HD cx<R> operator-(cx<R> a) { return {-a.x, -a.y}; }
+// Each component is one product and one fused multiply-add in a fixed
+// order, so a complex product rounds the same in every kernel whatever the
+// compiler contracts around it.
 template <class R> SDR_HD cx<R> operator*(cx<R> a, cx<R> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+  return {fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
 }
 template <class R> SDR_HD cx<R> operator*(cx<R> a, R s) { return {a.x * s, a.y * s}; }
 template <class R> SDR_HD cx<R>& operator+=(cx<R>& a, cx<R> b) { a.x += b.x; a.y += b.y; return a; }
@@ -29,7 +32,7 @@ SDR_HD float conj(float a) { return a; }
 template <class R> SDR_HD cx<R> conj(cx<R> a) { return {a.x, -a.y}; }
 SDR_HD double abs2(double a) { return a * a; }
 SDR_HD double abs2(float a) { return (double)a * (double)a; }
-template <class R> SDR_HD double abs2(cx<R> a) { return (double)a.x * a.x + (double)a.y * a.y; }
+template <class R> SDR_HD double abs2(cx<R> a) { return fma((double)a.x, (double)a.x, (double)a.y * a.y); }
 SDR_HD double re(double a) { return a; }
 template <class R> SDR_HD R re(cx<R> a) { return a.x; }
 
