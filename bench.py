@@ -205,7 +205,7 @@ def summarize_pmc(fetch_csv, write_csv, calib_mb, workload_name):
     return "\n".join(lines) + "\n"
 
 
-def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name):
+def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name, flags=""):
     """Markdown summary of a rocprofv3 kernel-trace run: per-kernel calls and
     durations, the step kernel's per-launch distribution, whether any of its
     launches overlapped a kernel of the least-squares stream, and the bench's
@@ -235,7 +235,8 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name):
     R = "$R"
     kd = _rel_dir(stats_csv)
     sv = bj["solve"]
-    prec_flag = " --precision 1" if bj["config"].get("precision") == "mixed" else ""
+    prec_flag = (" --precision 1" if bj["config"].get("precision") == "mixed" else "") + \
+        (" " + flags if flags else "")
     lines = [f"# rocprofv3 kernel statistics: GMRES-SDR solve, {workload_name} ({bj['dtype']})", "",
              f"Workload {bj['config']['workload']}; m = {p['m']}, k = {p['k']}, t = {p['t']}, "
              f"s = {p['s']}, zeta = {p['zeta']}, tol {p['tol']:g}; one solve from x0 = 0 with an empty "
@@ -245,7 +246,8 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name):
              f"{kd} -o run -- python3 {R}/bench.py --workload {workload_name}{prec_flag} --steps 1 "
              f"--warmup 0 --no-cpu-baseline --no-extras",
              f"    python3 {R}/bench.py --summarize-kstats {kd}/{os.path.basename(stats_csv)} "
-             f"{_rel_dir(trace_csv)}/{os.path.basename(trace_csv)} BENCH.json --workload {workload_name}", "",
+             f"{_rel_dir(trace_csv)}/{os.path.basename(trace_csv)} BENCH.json --workload {workload_name}"
+             + (f" --kstats-flags \"{flags}\"" if flags else ""), "",
              f"(BENCH.json: the output line of `python3 bench.py --workload {workload_name}{prec_flag} "
              "--no-cpu-baseline --no-extras` run just before, on the same box.)", "",
              f"Kernel source digest (bench.py kernel_source_digest, comments ignored): {kernel_source_digest()}.",
@@ -593,6 +595,10 @@ def main():
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--sketch", type=int, default=0,
                     help="0: sparse sign; 1: subsampled randomised DCT (profiling runs)")
+    ap.add_argument("--kstats-flags", default="",
+                    help="with --summarize-kstats: the bench options of the profiled run (--sketch 1, ...)")
+    ap.add_argument("--precond", type=int, default=0,
+                    help="right preconditioning of the timed solve: 0 none, 1 Jacobi, 2 ILU(0)")
     ap.add_argument("--lsq-kernel", type=int, default=0,
                     help="least-squares kernel: 0 automatic, 1 block Gram-Schmidt, 2 one launch per step")
     ap.add_argument("--timing-every", type=int, default=64,
@@ -606,7 +612,7 @@ def main():
                     help="write the kernel-statistics summary of a rocprofv3 kernel-trace run and exit")
     args = ap.parse_args()
     if args.summarize_kstats:
-        sys.stdout.write(summarize_kstats(*args.summarize_kstats, args.workload))
+        sys.stdout.write(summarize_kstats(*args.summarize_kstats, args.workload, args.kstats_flags))
         return
     if args.summarize_pmc:
         sys.stdout.write(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
@@ -634,7 +640,7 @@ def main():
     bd = torch.from_numpy(b).to(dev)
     h = SDRSolver(rp, ci, vals, m=p["m"], k=p["k"], t=p["t"], s=p["s"], seed=p["s_seed"],
                   zeta=p["zeta"], kernel_timing=args.timing_every, precision=args.precision,
-                  sketch=args.sketch, lsq_kernel=args.lsq_kernel)
+                  sketch=args.sketch, lsq_kernel=args.lsq_kernel, precond=args.precond)
     if args.copy_calib_mb:
         src = torch.ones(args.copy_calib_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -718,7 +724,8 @@ def main():
         "dtype": (("c128" if cpx else "f64") if args.precision == 0 else
                   ("c64-basis/c128" if cpx else "f32-basis/f64")),
         "data": "synthetic",
-        "config": {"workload": describe(args.workload),
+        "config": {"workload": describe(args.workload) + {0: "", 1: ", right Jacobi preconditioning",
+                                                          2: ", right ILU(0) preconditioning"}[args.precond],
                    "m": p["m"], "k": p["k"], "t": p["t"], "s": p["s"], "zeta": p["zeta"],
                    "tol": p["tol"], "precision": "fp64" if args.precision == 0 else "mixed"},
         "single_solves_per_s": 1.0 / med,

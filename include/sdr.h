@@ -277,7 +277,9 @@ int sdr_spmv(sdr_handle* h, const void* x, void* y);
 /* z = M^-1 v for the handle's preconditioner (option "precond": 0 the
  * identity, 1 D^-1, 2 the ILU(0) solve; Section 6), FP64 / complex128 device
  * vectors of length n.  Factors the current matrix first if no solve has.
- * SDR_EINVAL if that factorisation failed (zero diagonal entry or pivot). */
+ * SDR_EINVAL if that factorisation failed (zero diagonal entry or pivot).
+ * The apply is queued on the handle's stream (sdr_set_stream) and the call
+ * returns without waiting: z is complete when that stream's work is. */
 int sdr_precond_apply(sdr_handle* h, const void* v, void* z);
 
 /* Basis data of the last cycle for inspection: the first ncols normalised

@@ -2171,8 +2171,7 @@ int sdr_precond_apply(sdr_handle* h, const void* v, void* z) {
       HIPCHK(hipMemcpyAsync(z, v, h->elem() * h->n, hipMemcpyDeviceToDevice, h->stream));
       if (h->opt.precond == 1) precond_scale(h, z, false);
     }
-    HIPCHK(hipStreamSynchronize(h->stream));
-    return SDR_OK;
+    return SDR_OK;  // queued on the handle's stream
   } catch (HipError& e) {
     return e.code;
   }
