@@ -123,9 +123,11 @@ sdr_handle* sdr_create(const sdr_csr* A, int m, int k, int t, int s_dim, uint64_
  *   "lsq_kernel"     least-squares kernel: 0 (default) keeps the QR factor in
  *                    registers where the sketch and the basis are small
  *                    enough, else block Gram-Schmidt (blocks of up to 8
- *                    steps, Q swept four times per block); 1: block kernel;
- *                    2: one launch per step (reference form).  The same
- *                    decisions and, up to rounding, the same factor.
+ *                    steps, Q swept four times per block) with the sweeps
+ *                    spread over many workgroups; 1: the block method in
+ *                    one workgroup; 2: one launch per step (reference
+ *                    form); 3: the block method on many workgroups.  The
+ *                    same decisions and, up to rounding, the same factor.
  *   "dia"            1 (default): a pattern whose entries lie on at most 16
  *                    diagonals (padding at most nnz/4) is stored by diagonals
  *                    for the basis SpMV; 0: always CSR

@@ -78,6 +78,22 @@ struct GivensInit {
   double beta;
 };
 
+// Work arrays of the block least squares on several workgroups (device,
+// allocated by the solver): the block W (s x 8, ld s; then Q1, then W2),
+// the projections P (rows x 8, row major), the in-block factors R1 and R2
+// (8 x 8, column major), and the block's step headers (H columns, norms,
+// breakdown flags, column norms of W).
+template <class A> struct BlkWork {
+  A* W = nullptr;
+  A* P = nullptr;
+  A* R1 = nullptr;
+  A* R2 = nullptr;
+  A* hc = nullptr;      // 8 x (kMaxWindow + 1)
+  double* nuj = nullptr;
+  double* n0 = nullptr;
+  int* brk = nullptr;
+};
+
 // Small dense state of the sketched least squares (FP64 / complex128).
 template <class A> struct LsqState {
   A* Q;    int ldq;   // s x Lmax orthonormal factor of SAW
@@ -92,6 +108,7 @@ template <class A> struct LsqState {
   Ctrl* ctrl;
   StepRec* rec;       // host-mapped records, one per step
   HaltRec* halt;      // host-mapped record of the halting step
+  BlkWork<A> bw;      // the block least squares' work arrays
 };
 
 // w = A x (if spmv) with per-block partial sums in part (nb blocks of
@@ -153,10 +170,12 @@ void launch_lsq_step(hipStream_t st, LsqState<A> S, int j, int khat, int m, int 
 // Steps j0 .. j1 of the least squares, step j reading its reduced inputs at
 // redb + slotr * (j % nslot) (layout of launch_lsq_step's red).  kind 0: one
 // launch with the QR factor held in registers where the register shape
-// allows, else the block Gram-Schmidt kernel (one launch, blocks of up to 8
-// steps); kind 1: the block kernel; kind 2: one launch per step.  A shape the
-// chosen kernel cannot take falls back to one launch per step.  Stops after
-// a step that raises the halt flag.
+// allows, else block Gram-Schmidt over several workgroups (blocks of up to 8
+// steps, seven launches per block), else in one workgroup; kind 1: block
+// Gram-Schmidt in one workgroup (one launch); kind 2: one launch per step;
+// kind 3: the several-workgroup block kernels.  A shape the chosen kernel
+// cannot take falls back to one launch per step.  Stops after a step that raises the
+// halt flag.
 template <class A>
 void launch_lsq_steps(hipStream_t st, LsqState<A> S, int j0, int j1, int khat, int m, int t, int s,
                       const A* redb, int64_t slotr, int nslot, double brtol, double rank_rtol,

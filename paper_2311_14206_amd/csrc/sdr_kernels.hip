@@ -1829,6 +1829,550 @@ static int lsq_block_cols(int s, int prow, size_t* lds) {
   return 0;
 }
 
+// ---- block variant on several workgroups ------------------------------------
+// The same block Gram-Schmidt as k_lsq_block, split at its sweeps over Q so
+// that each sweep runs on many workgroups: the step headers and the block W
+// (k_mblk_head), the projection P = Q^H W (k_mblk_proj, a workgroup per eight
+// columns of Q), the update W -= Q P (k_mblk_upd, a workgroup per 64 rows),
+// the CGS2 inside the block (k_mblk_qr), the second projection and update,
+// then the second in-block factorisation with the steps finished in order
+// (k_mblk_fin).  The in-block kernels hold the block in registers: lane l of
+// wave w keeps rows 64 (NW u + w) + l, u < RPL, of the eight columns (NW <= 4
+// waves, s <= 64 NW RPL; rows past s hold zeros), so their sums are DPP
+// steps and, with several waves, one LDS exchange.  Every kernel returns at
+// once when the halt flag is set.  (The least squares of a cycle runs once
+// the Arnoldi chain has drained, so the sweeps have the GPU to themselves.)
+constexpr int kMblkMaxWaves = 4;   // waves of the in-block kernels
+constexpr int kMblkHeadThreads = 1024;
+constexpr int kMblkSweepThreads = 1024;
+constexpr int kMblkSweepWaves = kMblkSweepThreads / 64;
+
+// Workgroup sums of NV per-lane values: every thread gets every sum, the same
+// bits on every call.  Wave sums first; with nw > 1 waves the wave sums are
+// added in wave order through xs (2 halves of kMblkSweepWaves x 32 doubles,
+// used alternately, so one barrier per call keeps a later call from
+// overwriting sums not yet read).  scr: this wave's wave_sums scratch.
+template <int NV>
+__device__ __forceinline__ void grp_sums(double (&d)[NV], double* scr, double* xs, int nw, int& ph) {
+  if constexpr (NV == 8 || NV == 16 || NV == 32) {
+    wave_sums<NV>(d, scr);
+  } else {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) d[c] = wave_sum(d[c]);
+  }
+  if (nw > 1) {
+    double* x = xs + ph * (kMblkSweepWaves * 32);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane < NV) {
+      double v = d[0];
+#pragma unroll
+      for (int c = 1; c < NV; ++c)
+        if (lane == c) v = d[c];
+      x[wv * 32 + lane] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double t = x[c];
+      for (int w = 1; w < nw; ++w) t += x[w * 32 + c];
+      d[c] = t;
+    }
+    ph ^= 1;
+  }
+}
+
+template <class A, int RPL>
+__device__ __forceinline__ int mblk_row(int u, int nw) {
+  return 64 * (nw * u + (int)(threadIdx.x >> 6)) + (int)(threadIdx.x & 63);
+}
+
+// CGS2 of the register block: X(:, 0:nb) = Xq Rm, Xq overwriting X; Rm
+// upper triangular (column major, stride kBlkCols, real non-negative
+// diagonal, zeros below), written by thread 0.  A zero remainder gives a zero
+// column and Rm(b, b) = 0.
+template <class A, int RPL>
+__device__ void mblk_qr(A (&X)[kBlkCols][RPL], int nb, A* Rm, double* scr, double* xs, int nw, int& ph) {
+  constexpr int NC = ncomp<A>::v;
+#pragma unroll
+  for (int b = 0; b < kBlkCols; ++b) {
+    if (b >= nb) continue;
+    A dsum[kBlkCols];
+#pragma unroll
+    for (int c = 0; c < kBlkCols; ++c) dsum[c] = zero<A>();
+    if (b > 0) {
+#pragma unroll 1
+      for (int pass = 0; pass < 2; ++pass) {
+        double d[kBlkCols * NC];
+#pragma unroll
+        for (int c = 0; c < kBlkCols; ++c) {
+          A acc = zero<A>();
+          if (c < b) {
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) acc += conj(X[c][u]) * X[b][u];
+          }
+          split_re(acc, d + c * NC);
+        }
+        grp_sums<kBlkCols * NC>(d, scr, xs, nw, ph);
+        A dc[kBlkCols];
+#pragma unroll
+        for (int c = 0; c < kBlkCols; ++c) join_re(dc[c], d + c * NC);
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          A v = X[b][u];
+#pragma unroll
+          for (int c = 0; c < kBlkCols; ++c)
+            if (c < b) v -= X[c][u] * dc[c];
+          X[b][u] = v;
+        }
+#pragma unroll
+        for (int c = 0; c < kBlkCols; ++c)
+          if (c < b) dsum[c] = pass == 0 ? dc[c] : dsum[c] + dc[c];
+      }
+    }
+    double q[1] = {0.0};
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) q[0] += abs2(X[b][u]);
+    grp_sums<1>(q, scr, xs, nw, ph);
+    const double na = sqrt(q[0]);
+    const double inv = na > 0.0 ? 1.0 / na : 0.0;
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) X[b][u] = scale(X[b][u], inv);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int c = 0; c < kBlkCols; ++c) {
+        A v = c < b ? dsum[c] : zero<A>();
+        if (c == b) *(double*)&v = na;
+        Rm[b * kBlkCols + c] = v;
+      }
+    }
+  }
+}
+
+// Step headers (a thread per step) and the block's SV and SAV columns into
+// S.SB, S.SAW and bw.W (ld s), a thread per row; ||W(:, b)|| into bw.n0.
+// The same sums in the same order as the column-by-column kernels.
+template <class A>
+__global__ __launch_bounds__(kMblkHeadThreads) void k_mblk_head(LsqState<A> S, int jb, int nb, int khat, int t,
+                                                                int s, const A* __restrict__ redb, int64_t slotr,
+                                                                int nslot, double brtol) {
+  if (S.ctrl->halt) return;
+  const BlkWork<A> B = S.bw;
+  __shared__ A hc[kBlkCols][kMaxWindow + 1];
+  __shared__ double nujs[kBlkCols];
+  __shared__ int brks[kBlkCols], tws[kBlkCols];
+  __shared__ double scr_all[(kMblkHeadThreads / 64) * 16 * (kBlkCols + 1)];
+  __shared__ double xs[2 * kMblkSweepWaves * 32];
+  const int tid = threadIdx.x, wv = tid >> 6, nw = blockDim.x >> 6;
+  // the first row's loads are issued before the headers are formed
+  A wpre[kMaxWindow], x[kBlkCols];
+  auto load_row = [&](int r) {
+#pragma unroll
+    for (int p = 0; p < kMaxWindow; ++p) {
+      const int i = jb - kMaxWindow + p;
+      wpre[p] = (i >= 0 && i >= jb - t) ? S.SB[(int64_t)(khat + i) * S.ldsb + r] : zero<A>();
+    }
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) x[b] = b < nb ? redb[slotr * ((jb + b) % nslot) + r] : zero<A>();
+  };
+  if (tid < s) load_row(tid);
+  if (tid < nb) {
+    const int b = tid, j = jb + b;
+    const A* red = redb + slotr * (j % nslot);
+    const int i0 = j - t > 0 ? j - t : 0, tw = j - i0;
+    const A* dots = red + s + 1;
+    const double nuj = sqrt(re(red[s]));
+    const double nw2 = sqrt(re(dots[tw]));
+    const double nuprev = b == 0 ? S.nu[jb - 1] : sqrt(re(redb[slotr * ((j - 1) % nslot) + s]));
+    const bool brk = !(nuj > brtol * nw2 / nuprev);  // H(j,j-1) vs ||A v_{j-1}||
+    for (int q = 0; q < tw; ++q) {
+      const int i = i0 + q;
+      const double nui = i < jb ? S.nu[i] : sqrt(re(redb[slotr * (i % nslot) + s]));
+      hc[b][q] = scale(dots[q], 1.0 / (nui * nuprev));
+    }
+    A hs = zero<A>();
+    *(double*)&hs = brk ? 0.0 : nuj;
+    hc[b][tw] = hs;
+    nujs[b] = nuj;
+    brks[b] = brk;
+    tws[b] = tw;
+    for (int q = 0; q <= kMaxWindow; ++q) B.hc[b * (kMaxWindow + 1) + q] = q <= tw ? hc[b][q] : zero<A>();
+    B.nuj[b] = nuj;
+    B.brk[b] = brk;
+  }
+  __syncthreads();
+  double nn[kBlkCols];
+#pragma unroll
+  for (int b = 0; b < kBlkCols; ++b) nn[b] = 0.0;
+  for (int r = tid; r < s; r += blockDim.x) {
+    if (r != tid) load_row(r);
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b)
+      if (b < nb) {
+        x[b] = brks[b] ? zero<A>() : scale(x[b], 1.0 / nujs[b]);
+        S.SB[(int64_t)(khat + jb + b) * S.ldsb + r] = x[b];
+      }
+    // SAV(:, j) = SV(:, window) H(window, j), last column first so that
+    // column b still finds the SV values before it; window column j - d sits
+    // at block column b - d, or before the block (wpre) when that is < 0
+#pragma unroll
+    for (int b = kBlkCols - 1; b >= 0; --b)
+      if (b < nb) {
+        const int tw = tws[b];
+        A sum = zero<A>();
+#pragma unroll
+        for (int d = kMaxWindow; d >= 1; --d)
+          if (d <= tw) {
+            const A w = b - d >= 0 ? x[b - d >= 0 ? b - d : 0] : wpre[kMaxWindow + b - d >= 0 ? kMaxWindow + b - d : 0];
+            sum += w * hc[b][tw - d];
+          }
+        sum += x[b] * hc[b][tw];
+        x[b] = sum;
+        S.SAW[(int64_t)(khat + jb + b - 1) * S.ldsaw + r] = sum;
+        B.W[b * s + r] = sum;
+        nn[b] += abs2(sum);
+      }
+  }
+  int ph = 0;
+  grp_sums<kBlkCols>(nn, scr_all + wv * 16 * (kBlkCols + 1), xs, nw, ph);
+  if (tid < kBlkCols) {
+    double v = nn[0];
+#pragma unroll
+    for (int b = 1; b < kBlkCols; ++b)
+      if (tid == b) v = nn[b];
+    B.n0[tid] = sqrt(v);
+  }
+}
+
+// P(i, b) = Q(:, i)^H W(:, b) for i < ncol, b < nb (rows ncol .. the next
+// multiple of 8 set to zero); with Rtop also R(i, col0 + b) = P(i, b).  A
+// workgroup per eight columns of Q; its waves take a share of the row groups
+// each (lane (c, g): column c, rows g, g + 8, ...: one load instruction reads
+// eight consecutive rows of each of eight columns), combined by DPP within a
+// wave and through LDS across the waves in wave order.
+template <class A>
+__global__ __launch_bounds__(kMblkSweepThreads) void k_mblk_proj(const A* __restrict__ Q, int ldq, int ncol, int s,
+                                                                 const A* __restrict__ W, int nb, A* __restrict__ P,
+                                                                 A* __restrict__ Rtop, int ldr,
+                                                                 const Ctrl* __restrict__ ctrl) {
+  if (ctrl->halt) return;
+  __shared__ A part[kMblkSweepWaves][kBlkCols][kBlkCols];
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c = lane >> 3, g = lane & 7;
+  const int i0 = blockIdx.x * 8, i = i0 + c;
+  const A* __restrict__ qc = Q + (int64_t)min(i, ncol - 1) * ldq;
+  const int ngrp = (s + 7) / 8;  // rows g + 8 k, k < ngrp
+  const int k0 = wv * ngrp / kMblkSweepWaves, k1 = (wv + 1) * ngrp / kMblkSweepWaves;
+  A acc[kBlkCols];
+#pragma unroll
+  for (int b = 0; b < kBlkCols; ++b) acc[b] = zero<A>();
+  for (int k = k0; k < k1; ++k) {
+    const int r = min(g + 8 * k, s - 1);
+    const A q = g + 8 * k < s ? conj(qc[r]) : zero<A>();
+    A w[kBlkCols];
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) w[b] = b < nb ? W[b * s + r] : zero<A>();
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) acc[b] += q * w[b];
+  }
+  double d[kBlkCols * ncomp<A>::v];
+#pragma unroll
+  for (int b = 0; b < kBlkCols; ++b) split_re(acc[b], d + b * ncomp<A>::v);
+#pragma unroll
+  for (int e = 0; e < kBlkCols * ncomp<A>::v; ++e) {
+    d[e] += dpp_mov<0xB1>(d[e]);
+    d[e] += dpp_mov<0x4E>(d[e]);
+    d[e] += dpp_mov<0x141>(d[e]);
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) join_re(part[wv][c][b], d + b * ncomp<A>::v);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int cc = threadIdx.x >> 3, b = threadIdx.x & 7, ii = i0 + cc;
+    A v = part[0][cc][b];
+#pragma unroll
+    for (int w = 1; w < kMblkSweepWaves; ++w) v += part[w][cc][b];
+    if (b < nb) {
+      P[ii * kBlkCols + b] = ii < ncol ? v : zero<A>();
+      if (Rtop && ii < ncol) Rtop[(int64_t)b * ldr + ii] = v;
+    }
+  }
+}
+
+// W(r, b) -= sum_i Q(r, i) P(i, b): a workgroup per 64 rows, a lane per row;
+// its waves take consecutive shares of the columns of Q (one load
+// instruction reads 64 consecutive rows of a column; P's row is the same for
+// the whole wave: scalar loads), and the partial sums of each entry are added
+// in wave order through LDS (dynamic: kMblkSweepWaves x kBlkCols x 64).
+template <class A>
+__global__ __launch_bounds__(kMblkSweepThreads) void k_mblk_upd(const A* __restrict__ Q, int ldq, int ncol, int s,
+                                                                A* __restrict__ W, int nb, const A* __restrict__ P,
+                                                                const Ctrl* __restrict__ ctrl) {
+  if (ctrl->halt) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  A* part = reinterpret_cast<A*>(smem_raw);
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = blockIdx.x * 64 + lane, rr = min(r, s - 1);
+  const int c0 = wv * ncol / kMblkSweepWaves, c1 = (wv + 1) * ncol / kMblkSweepWaves;
+  A acc[kBlkCols];
+#pragma unroll
+  for (int b = 0; b < kBlkCols; ++b) acc[b] = zero<A>();
+  int i = c0;
+  for (; i + 4 <= c1; i += 4) {
+    A q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = Q[(int64_t)(i + u) * ldq + rr];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int b = 0; b < kBlkCols; ++b) acc[b] += q[u] * P[(i + u) * kBlkCols + b];
+  }
+  for (; i < c1; ++i) {
+    const A q = Q[(int64_t)i * ldq + rr];
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) acc[b] += q * P[i * kBlkCols + b];
+  }
+#pragma unroll
+  for (int b = 0; b < kBlkCols; ++b) part[(wv * kBlkCols + b) * 64 + lane] = acc[b];
+  __syncthreads();
+  // wave w < nb finishes block column w
+  if (r < s && wv < nb) {
+    A v = part[wv * 64 + lane];
+    for (int w = 1; w < kMblkSweepWaves; ++w) v += part[(w * kBlkCols + wv) * 64 + lane];
+    W[wv * s + r] -= v;
+  }
+}
+
+// CGS2 inside the block: bw.W = Q1 R1 in place, R1 into bw.R1.
+template <class A, int RPL>
+__global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_qr(LsqState<A> S, int nb, int s) {
+  if (S.ctrl->halt) return;
+  __shared__ double scr_all[kMblkMaxWaves * 16 * (kBlkCols * ncomp<A>::v + 1)];
+  __shared__ double xs[2 * kMblkSweepWaves * 32];
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
+  double* scr = scr_all + wv * 16 * (kBlkCols * ncomp<A>::v + 1);
+  A X[kBlkCols][RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int r = mblk_row<A, RPL>(u, nw);
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) X[b][u] = (r < s && b < nb) ? S.bw.W[b * s + r] : zero<A>();
+  }
+  int ph = 0;
+  mblk_qr<A, RPL>(X, nb, S.bw.R1, scr, xs, nw, ph);
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int r = mblk_row<A, RPL>(u, nw);
+    if (r < s) {
+#pragma unroll
+      for (int b = 0; b < kBlkCols; ++b)
+        if (b < nb) S.bw.W[b * s + r] = X[b][u];
+    }
+  }
+}
+
+// The second in-block factorisation (bw.W = Q2 R2), R above the block
+// completed (P1 + P2 R1), the block's R = R2 R1, then the steps in order
+// (projected residual, residual control, records) and the commit of Q and R
+// up to the last finished step.
+template <class A, int RPL>
+__global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, int jb, int nb, int m, int t,
+                                                                 int s, int col0, double rank_rtol) {
+  if (S.ctrl->halt) return;
+  constexpr int NC = ncomp<A>::v;
+  const BlkWork<A> B = S.bw;
+  __shared__ double scr_all[kMblkMaxWaves * 16 * (kBlkCols * NC + 1)];
+  __shared__ double xs[2 * kMblkSweepWaves * 32];
+  __shared__ A R1[kBlkCols * kBlkCols], R2[kBlkCols * kBlkCols], RB[kBlkCols * kBlkCols];
+  __shared__ A hcs[kBlkCols * (kMaxWindow + 1)];
+  __shared__ double nujs[kBlkCols], n0s[kBlkCols];
+  __shared__ int brks[kBlkCols];
+  __shared__ int sh_halt;
+  __shared__ Ctrl cl;
+  const int tid = threadIdx.x, nw = blockDim.x >> 6, wv = tid >> 6;
+  double* scr = scr_all + wv * 16 * (kBlkCols * NC + 1);
+  if (tid < kBlkCols * (kMaxWindow + 1)) hcs[tid] = B.hc[tid];
+  if (tid < kBlkCols) {
+    nujs[tid] = B.nuj[tid];
+    n0s[tid] = B.n0[tid];
+    brks[tid] = B.brk[tid];
+  }
+  A X[kBlkCols][RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int r = mblk_row<A, RPL>(u, nw);
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) X[b][u] = (r < s && b < nb) ? B.W[b * s + r] : zero<A>();
+  }
+  A rh[RPL];  // the projected residual
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int r = mblk_row<A, RPL>(u, nw);
+    rh[u] = r < s ? S.rho[r] : zero<A>();
+  }
+  if (tid < kBlkCols * kBlkCols) R1[tid] = B.R1[tid];
+  if (tid == 0) cl = *S.ctrl;  // the control block, kept in LDS and written back
+  int ph = 0;
+  mblk_qr<A, RPL>(X, nb, R2, scr, xs, nw, ph);
+  __syncthreads();
+  // R above the block: P1 (stored by the first projection) + P2 R1
+  for (int i = tid; i < col0; i += blockDim.x)
+    for (int b = 0; b < nb; ++b) {
+      A u = zero<A>();
+      for (int c = 0; c <= b; ++c) u += B.P[i * kBlkCols + c] * R1[b * kBlkCols + c];
+      A* rp = S.R + (int64_t)(col0 + b) * S.ldr + i;
+      *rp = *rp + u;
+    }
+  if (tid < kBlkCols * kBlkCols) {
+    const int c = tid >> 3, b = tid & 7;
+    A v = zero<A>();
+    if (c <= b && b < nb)
+      for (int e = c; e <= b; ++e) v += R2[e * kBlkCols + c] * R1[b * kBlkCols + e];
+    RB[b * kBlkCols + c] = v;
+  }
+  __syncthreads();
+  int last = nb - 1, halted = 0;
+#pragma unroll
+  for (int bb = 0; bb < kBlkCols; ++bb) {
+    if (bb >= nb) break;
+    const int j = jb + bb, col = col0 + bb;
+    const double na = re(RB[bb * kBlkCols + bb]);
+    const bool loss = !(na > rank_rtol * n0s[bb]);
+    A zc = zero<A>();
+    if (!loss) {
+      double d[NC];
+      A acc = zero<A>();
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) acc += conj(X[bb][u]) * rh[u];
+      split_re(acc, d);
+      grp_sums<NC>(d, scr, xs, nw, ph);
+      join_re(zc, d);
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) rh[u] -= X[bb][u] * zc;
+    }
+    double q[1] = {0.0};
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) q[0] += abs2(rh[u]);
+    grp_sums<1>(q, scr, xs, nw, ph);
+    const double sres = sqrt(q[0]);
+    if (tid == 0) {
+      const bool brk = brks[bb];
+      const int i0 = j - t > 0 ? j - t : 0, tw = j - i0;
+      const double nuj = nujs[bb];
+      S.nu[j] = nuj;
+      for (int qq = 0; qq <= tw; ++qq) S.H[(int64_t)(j - 1) * S.ldh + i0 + qq] = hcs[bb * (kMaxWindow + 1) + qq];
+      S.z[col] = zc;
+      int flags = 0;
+      if (brk) flags |= 2;
+      if (loss) flags |= 4;
+      const bool due = control_due(&cl, sres);  // (updates the estimate: always evaluated)
+      const bool halt = due || j == m || brk || loss;
+      if (halt) flags |= 1;
+      S.sres_hist[j] = sres;
+      if (halt) {
+        S.ctrl->est = cl.est;
+        S.ctrl->sprev = cl.sprev;
+        S.ctrl->halt = 1;
+        S.ctrl->halt_j = j;
+        S.ctrl->flags = flags;
+      }
+      put_record(S, j, sres, nuj, flags, halt);
+      sh_halt = halt;
+    }
+    __syncthreads();
+    if (sh_halt) {
+      last = bb;
+      halted = 1;
+      break;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int r = mblk_row<A, RPL>(u, nw);
+    if (r < s) S.rho[r] = rh[u];
+  }
+  if (tid == 0 && !halted) {
+    S.ctrl->est = cl.est;
+    S.ctrl->sprev = cl.sprev;
+  }
+  // commit Q and the block's R up to the last finished step
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int r = mblk_row<A, RPL>(u, nw);
+    if (r < s) {
+#pragma unroll
+      for (int b = 0; b < kBlkCols; ++b)
+        if (b <= last) S.Q[(int64_t)(col0 + b) * S.ldq + r] = X[b][u];
+    }
+  }
+  if (tid < kBlkCols * kBlkCols) {
+    const int c = tid >> 3, b = tid & 7;
+    if (c <= b && b <= last) S.R[(int64_t)(col0 + b) * S.ldr + col0 + c] = RB[b * kBlkCols + c];
+  }
+}
+
+// Rows per lane of the in-block kernels and their waves for a sketch of s
+// rows: the smallest RPL that kMblkMaxWaves waves cover (more waves share
+// the FP64 arithmetic and shorten each lane's chains), then the fewest waves
+// for it; false when s exceeds kMblkMaxWaves waves of the largest RPL (the
+// register budget: eight columns of RPL entries).
+template <class A>
+static bool mblk_shape(int s, int* rpl, int* nw) {
+  constexpr int opts[3] = {2, 4, sizeof(A) == 16 ? 6 : 8};
+  if (s < 1) return false;
+  for (int o : opts)
+    if (s <= 64 * kMblkMaxWaves * o) {
+      *rpl = o;
+      *nw = (s + 64 * o - 1) / (64 * o);
+      return true;
+    }
+  return false;
+}
+
+// The in-block factorisation, the second sweep and the finish of one block.
+template <class A, int RPL>
+static void launch_mblk_tail(hipStream_t st, const LsqState<A>& S, int jb, int nb, int m, int t, int s, int col0,
+                             int nw, double rank_rtol) {
+  const size_t lds_upd = (size_t)kMblkSweepWaves * kBlkCols * 64 * sizeof(A);
+  hipLaunchKernelGGL((k_mblk_qr<A, RPL>), dim3(1), dim3(64 * nw), 0, st, S, nb, s);
+  if (col0 > 0) {
+    hipLaunchKernelGGL(k_mblk_proj<A>, dim3((col0 + 7) / 8), dim3(kMblkSweepThreads), 0, st, S.Q, S.ldq, col0, s,
+                       S.bw.W, nb, S.bw.P, (A*)nullptr, S.ldr, S.ctrl);
+    hipLaunchKernelGGL(k_mblk_upd<A>, dim3((s + 63) / 64), dim3(kMblkSweepThreads), lds_upd, st, S.Q, S.ldq, col0,
+                       s, S.bw.W, nb, S.bw.P, S.ctrl);
+  }
+  hipLaunchKernelGGL((k_mblk_fin<A, RPL>), dim3(1), dim3(64 * nw), 0, st, S, jb, nb, m, t, s, col0, rank_rtol);
+}
+
+// The several-workgroup block path for steps j0 .. j1 (false: the sketch is
+// too long for the in-block kernels' registers).
+template <class A>
+static bool launch_lsq_blocks_multi(hipStream_t st, LsqState<A> S, int j0, int j1, int khat, int m, int t, int s,
+                                    const A* redb, int64_t slotr, int nslot, double brtol, double rank_rtol) {
+  constexpr bool cpx = sizeof(A) == 16;
+  int rpl = 0, nw = 0;
+  if (!mblk_shape<A>(s, &rpl, &nw)) return false;
+  const size_t lds_upd = (size_t)kMblkSweepWaves * kBlkCols * 64 * sizeof(A);
+  for (int jb = j0; jb <= j1; jb += kBlkCols) {
+    const int nb = std::min(kBlkCols, j1 - jb + 1);
+    const int col0 = khat + jb - 1;  // committed columns of Q
+    hipLaunchKernelGGL(k_mblk_head<A>, dim3(1), dim3(kMblkHeadThreads), 0, st, S, jb, nb, khat, t, s, redb, slotr,
+                       nslot, brtol);
+    if (col0 > 0) {
+      hipLaunchKernelGGL(k_mblk_proj<A>, dim3((col0 + 7) / 8), dim3(kMblkSweepThreads), 0, st, S.Q, S.ldq, col0,
+                         s, S.bw.W, nb, S.bw.P, S.R + (int64_t)col0 * S.ldr, S.ldr, S.ctrl);
+      hipLaunchKernelGGL(k_mblk_upd<A>, dim3((s + 63) / 64), dim3(kMblkSweepThreads), lds_upd, st, S.Q, S.ldq,
+                         col0, s, S.bw.W, nb, S.bw.P, S.ctrl);
+    }
+    if (rpl == 2) launch_mblk_tail<A, 2>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
+    else if (rpl == 4) launch_mblk_tail<A, 4>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
+    else if constexpr (cpx) launch_mblk_tail<A, 6>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
+    else launch_mblk_tail<A, 8>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
+  }
+  return true;
+}
+
 // LDS of the batched kernel: update partials, reduction scratch, window ring
 template <class A>
 static constexpr size_t lsq_steps_lds(int rl, int cw) {
@@ -1855,7 +2399,10 @@ void launch_lsq_steps(hipStream_t st, LsqState<A> S, int j0, int j1, int khat, i
     SDR_LSQ_STEPS_CASE(4, 16)
     SDR_LSQ_STEPS_CASE(4, 8)
   }
-  if (kind != 2) {
+  if ((kind == 0 || kind == 3) &&
+      launch_lsq_blocks_multi<A>(st, S, j0, j1, khat, m, t, s, redb, slotr, nslot, brtol, rank_rtol))
+    return;
+  if (kind == 0 || kind == 1) {
     size_t lds = 0;
     const int prow = (std::max(1, khat + j1 - 1) + 7) / 8 * 8;  // P rows padded to whole groups
     const int bc = lsq_block_cols<A>(s, prow, &lds);

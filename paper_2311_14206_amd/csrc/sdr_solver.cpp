@@ -88,7 +88,8 @@ struct Options {
   double brtol = -1.0;  // < 0: default for the basis precision
   double rank_rtol = 1e-12;
   int lsq_chunk = 8;      // steps per least-squares launch
-  int lsq_kernel = 0;     // 0: register kernel where the shape allows, else block; 1: block; 2: per step
+  int lsq_kernel = 0;     // 0: register kernel where the shape allows, else block; 1: block in one
+                          // workgroup; 2: per step; 3: block over several workgroups
   int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
   int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
   int precond = 0;        // 0: none; 1: right Jacobi (A D^-1); 2: right ILU(0), multicolour order
@@ -236,6 +237,10 @@ class Solver final : public SolverBase {
       // the default system-scope fence (an L2 writeback each time) is skipped.
       for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence));
       red3_ = dalloc<A>(4);
+      // block least-squares work: W (s x 8), P ((lmax + 8) x 8), R1, R2, the H columns
+      blkA_ = dalloc<A>((size_t)s * 8 + (size_t)(lmax_ + 8) * 8 + 2 * 64 + 8 * (kMaxWindow + 1));
+      blkD_ = dalloc<double>(16);
+      blkI_ = dalloc<int>(8);
       Sr_ = dalloc<A>(s);
       ycoef_ = dalloc<A>(lmax_);
       xt_ = dalloc<A>(N);
@@ -508,6 +513,14 @@ class Solver final : public SolverBase {
     S.ctrl = ctrl_;
     S.rec = rec_dev_;
     S.halt = halt_dev_;
+    S.bw.W = blkA_;
+    S.bw.P = blkA_ + (size_t)s_ * 8;
+    S.bw.R1 = S.bw.P + (size_t)(lmax_ + 8) * 8;
+    S.bw.R2 = S.bw.R1 + 64;
+    S.bw.hc = S.bw.R2 + 64;
+    S.bw.nuj = blkD_;
+    S.bw.n0 = blkD_ + 8;
+    S.bw.brk = blkI_;
     return S;
   }
 
@@ -1287,7 +1300,7 @@ class Solver final : public SolverBase {
                     (void*)nu_, (void*)sres_hist_, (void*)ctrl_, (void*)ctrl_free_, (void*)part1_,
                     (void*)redb_, (void*)psk_, (void*)red2_, (void*)red3_, (void*)Sr_,
                     (void*)ycoef_, (void*)xt_, (void*)r_, (void*)rnew_, (void*)G_, (void*)Gs_,
-                    (void*)C_, (void*)dct_rows_, (void*)izb_, (void*)iy_, (void*)izA_, (void*)iyA_})
+                    (void*)C_, (void*)dct_rows_, (void*)blkA_, (void*)blkD_, (void*)blkI_, (void*)izb_, (void*)iy_, (void*)izA_, (void*)iyA_})
       dfree(p);
     if (rec_host_) (void)hipHostFree(rec_host_);
     rec_host_ = nullptr;
@@ -1364,6 +1377,9 @@ class Solver final : public SolverBase {
   double sk_scl_ = 1.0;       // scale of the reduced sketch rows
   DctRow* dct_rows_ = nullptr;
   DctSpec dct_{};
+  A *blkA_ = nullptr;
+  double* blkD_ = nullptr;
+  int* blkI_ = nullptr;
   A *part1_ = nullptr, *redb_ = nullptr, *psk_ = nullptr, *red2_ = nullptr, *red3_ = nullptr,
     *red0_ = nullptr;
   int nslot_ = 0;
@@ -1992,8 +2008,10 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
     if (!(v >= 0.0 && v < 1.0)) return set_err("givens_eps0 in [0, 1)"), SDR_EINVAL;
     h->opt.givens_eps0 = v;
   } else if (k == "lsq_kernel") {
-    if (v != 0.0 && v != 1.0 && v != 2.0)
-      return set_err("lsq_kernel is 0 (automatic), 1 (block) or 2 (one launch per step)"), SDR_EINVAL;
+    if (v != 0.0 && v != 1.0 && v != 2.0 && v != 3.0)
+      return set_err("lsq_kernel is 0 (automatic), 1 (block, one workgroup), 2 (one launch per step) or 3 "
+                     "(block, several workgroups)"),
+             SDR_EINVAL;
     h->opt.lsq_kernel = (int)v;
   } else if (k == "lsq_chunk") {
     if (built || v < 1 || v > 64) return set_err("lsq_chunk in [1,64], before the first solve"), SDR_EINVAL;
