@@ -1886,66 +1886,224 @@ __device__ __forceinline__ int mblk_row(int u, int nw) {
   return 64 * (nw * u + (int)(threadIdx.x >> 6)) + (int)(threadIdx.x & 63);
 }
 
-// CGS2 of the register block: X(:, 0:nb) = Xq Rm, Xq overwriting X; Rm
-// upper triangular (column major, stride kBlkCols, real non-negative
-// diagonal, zeros below), written by thread 0.  A zero remainder gives a zero
-// column and Rm(b, b) = 0.
-template <class A, int RPL>
-__device__ void mblk_qr(A (&X)[kBlkCols][RPL], int nb, A* Rm, double* scr, double* xs, int nw, int& ph) {
+// acc + conj(a) b and acc - a b as chains of fused multiply-adds (four for
+// complex data): the in-block kernels' inner products and updates, whose
+// rounding need not match any other kernel's.
+__device__ __forceinline__ double fmac_conj(double acc, double a, double b) { return fma(a, b, acc); }
+__device__ __forceinline__ cx<double> fmac_conj(cx<double> acc, cx<double> a, cx<double> b) {
+  return {fma(a.y, b.y, fma(a.x, b.x, acc.x)), fma(-a.y, b.x, fma(a.x, b.y, acc.y))};
+}
+__device__ __forceinline__ double fmsub(double acc, double a, double b) { return fma(-a, b, acc); }
+__device__ __forceinline__ cx<double> fmsub(cx<double> acc, cx<double> a, cx<double> b) {
+  return {fma(a.y, b.y, fma(-a.x, b.x, acc.x)), fma(-a.y, b.x, fma(-a.x, b.y, acc.y))};
+}
+
+// One projection pass of column B against the columns before it (NV packed
+// sums: the projections first, the squared norm of column B last when
+// with_norm): d = X(:, 0:B)^H X(:, B), X(:, B) -= X(:, 0:B) d.  Returns the
+// squared norm (with_norm) and the projections' squared moduli in corr.
+template <class A, int RPL, int B, int NV>
+__device__ __forceinline__ double mblk_pass(A (&X)[kBlkCols][RPL], bool with_norm, A (&dsum)[kBlkCols], bool first,
+                                            double* corr, double* scr, double* xs, int nw, int& ph) {
   constexpr int NC = ncomp<A>::v;
+  static_assert(B * NC + 1 <= NV, "packing");
+  double d[NV];
 #pragma unroll
-  for (int b = 0; b < kBlkCols; ++b) {
-    if (b >= nb) continue;
-    A dsum[kBlkCols];
+  for (int e = 0; e < NV; ++e) d[e] = 0.0;
 #pragma unroll
-    for (int c = 0; c < kBlkCols; ++c) dsum[c] = zero<A>();
-    if (b > 0) {
-#pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass) {
-        double d[kBlkCols * NC];
+  for (int c = 0; c < B; ++c) {
+    A acc = zero<A>();
 #pragma unroll
-        for (int c = 0; c < kBlkCols; ++c) {
-          A acc = zero<A>();
-          if (c < b) {
+    for (int u = 0; u < RPL; ++u) acc = fmac_conj(acc, X[c][u], X[B][u]);
+    split_re(acc, d + c * NC);
+  }
+  if (with_norm) {
 #pragma unroll
-            for (int u = 0; u < RPL; ++u) acc += conj(X[c][u]) * X[b][u];
-          }
-          split_re(acc, d + c * NC);
-        }
-        grp_sums<kBlkCols * NC>(d, scr, xs, nw, ph);
-        A dc[kBlkCols];
+    for (int u = 0; u < RPL; ++u) d[NV - 1] += abs2(X[B][u]);
+  }
+  grp_sums<NV>(d, scr, xs, nw, ph);
+  A dc[B > 0 ? B : 1];
+  double cr = 0.0;
 #pragma unroll
-        for (int c = 0; c < kBlkCols; ++c) join_re(dc[c], d + c * NC);
+  for (int c = 0; c < B; ++c) {
+    join_re(dc[c], d + c * NC);
+    cr += abs2(dc[c]);
+  }
 #pragma unroll
-        for (int u = 0; u < RPL; ++u) {
-          A v = X[b][u];
+  for (int u = 0; u < RPL; ++u) {
+    A v = X[B][u];
 #pragma unroll
-          for (int c = 0; c < kBlkCols; ++c)
-            if (c < b) v -= X[c][u] * dc[c];
-          X[b][u] = v;
-        }
+    for (int c = 0; c < B; ++c) v = fmsub(v, X[c][u], dc[c]);
+    X[B][u] = v;
+  }
 #pragma unroll
-        for (int c = 0; c < kBlkCols; ++c)
-          if (c < b) dsum[c] = pass == 0 ? dc[c] : dsum[c] + dc[c];
-      }
-    }
+  for (int c = 0; c < B; ++c) dsum[c] = first ? dc[c] : dsum[c] + dc[c];
+  *corr = cr;
+  return d[NV - 1];
+}
+
+// Column B of the in-block CGS2 (see mblk_qr).
+template <class A, int RPL, int B>
+__device__ __forceinline__ void mblk_qr_col(A (&X)[kBlkCols][RPL], int nb, A* Rm, double* scr, double* xs, int nw,
+                                            int& ph) {
+  if (B >= nb) return;
+  constexpr int NC = ncomp<A>::v;
+  constexpr int NV = B * NC + 1 <= 8 ? 8 : 16;  // the projections and the norm, packed
+  A dsum[kBlkCols];
+#pragma unroll
+  for (int c = 0; c < kBlkCols; ++c) dsum[c] = zero<A>();
+  double na2 = 0.0, corr = 0.0;
+  bool explicit_norm = B == 0;
+  if constexpr (B > 0) {
+    mblk_pass<A, RPL, B, NV>(X, false, dsum, true, &corr, scr, xs, nw, ph);
+    const double n2 = mblk_pass<A, RPL, B, NV>(X, true, dsum, false, &corr, scr, xs, nw, ph);
+    na2 = n2 - corr;
+    explicit_norm = !(corr <= 0.25 * n2);
+  }
+  if (explicit_norm) {
     double q[1] = {0.0};
 #pragma unroll
-    for (int u = 0; u < RPL; ++u) q[0] += abs2(X[b][u]);
+    for (int u = 0; u < RPL; ++u) q[0] += abs2(X[B][u]);
     grp_sums<1>(q, scr, xs, nw, ph);
-    const double na = sqrt(q[0]);
-    const double inv = na > 0.0 ? 1.0 / na : 0.0;
+    na2 = q[0];
+  }
+  const double na = sqrt(fmax(na2, 0.0));
+  const double inv = na > 0.0 ? 1.0 / na : 0.0;
 #pragma unroll
-    for (int u = 0; u < RPL; ++u) X[b][u] = scale(X[b][u], inv);
-    if (threadIdx.x == 0) {
+  for (int u = 0; u < RPL; ++u) X[B][u] = scale(X[B][u], inv);
+  if (threadIdx.x == 0) {
 #pragma unroll
-      for (int c = 0; c < kBlkCols; ++c) {
-        A v = c < b ? dsum[c] : zero<A>();
-        if (c == b) *(double*)&v = na;
-        Rm[b * kBlkCols + c] = v;
-      }
+    for (int c = 0; c < kBlkCols; ++c) {
+      A v = c < B ? dsum[c] : zero<A>();
+      if (c == B) *(double*)&v = na;
+      Rm[B * kBlkCols + c] = v;
     }
   }
+}
+
+// CGS2 of the register block: X(:, 0:nb) = Xq Rm, Xq overwriting X; Rm
+// upper triangular (column major, stride kBlkCols, real non-negative
+// diagonal, zeros below), written by thread 0.  Column b takes two workgroup
+// sums: the projections on the columns before it, then the projections of the
+// remainder together with its squared norm; the norm after the second
+// (small) correction is that squared norm less the corrections' squares
+// (Pythagoras), or a third sum when the correction is not small against the
+// remainder (a column nearly in the span of those before it).  A zero
+// remainder gives a zero column and Rm(b, b) = 0.
+template <class A, int RPL>
+__device__ void mblk_qr(A (&X)[kBlkCols][RPL], int nb, A* Rm, double* scr, double* xs, int nw, int& ph) {
+  static_assert(kBlkCols == 8, "columns");
+  static_assert((kBlkCols - 1) * ncomp<A>::v + 1 <= 16, "packing");
+  mblk_qr_col<A, RPL, 0>(X, nb, Rm, scr, xs, nw, ph);
+  mblk_qr_col<A, RPL, 1>(X, nb, Rm, scr, xs, nw, ph);
+  mblk_qr_col<A, RPL, 2>(X, nb, Rm, scr, xs, nw, ph);
+  mblk_qr_col<A, RPL, 3>(X, nb, Rm, scr, xs, nw, ph);
+  mblk_qr_col<A, RPL, 4>(X, nb, Rm, scr, xs, nw, ph);
+  mblk_qr_col<A, RPL, 5>(X, nb, Rm, scr, xs, nw, ph);
+  mblk_qr_col<A, RPL, 6>(X, nb, Rm, scr, xs, nw, ph);
+  mblk_qr_col<A, RPL, 7>(X, nb, Rm, scr, xs, nw, ph);
+}
+
+__device__ __forceinline__ double shfl_v(double v, int l) { return __shfl(v, l, 64); }
+__device__ __forceinline__ cx<double> shfl_v(cx<double> v, int l) { return {__shfl(v.x, l, 64), __shfl(v.y, l, 64)}; }
+__device__ __forceinline__ double read_lane_v(double v, int l) { return read_lane(v, l); }
+__device__ __forceinline__ cx<double> read_lane_v(cx<double> v, int l) { return {read_lane(v.x, l), read_lane(v.y, l)}; }
+
+// Cholesky QR of the register block, the in-block factorisation when the
+// block is well conditioned: G = X^H X (each pair's lane sums added over
+// quads by DPP, then through LDS, gbuf: nw x 36 x 2 x 16 doubles, by lane
+// (a, b) of each wave in a fixed order), G = Rm^H Rm, X <- X Rm^-1 row by
+// row.  Inside block Gram-Schmidt with
+// reorthogonalisation this is as stable as CGS2 while the block's condition
+// number stays far below eps^(-1/2); a pivot below 1e-8 of its diagonal
+// entry (a column within about 1e-4 of the span of those before it, a zero
+// column) returns false with X untouched, and the caller takes CGS2.  The
+// factorisation runs on the lanes of each wave alike: lane (a, b) = (lane /
+// 8, lane % 8) holds G(a, b), row j of Rm is formed at step j and reaches
+// the other lanes by shuffles; columns nb .. 7 get a unit pivot.
+template <class A, int RPL>
+__device__ bool mblk_cholqr(A (&X)[kBlkCols][RPL], int nb, A* Rm, double* gbuf) {
+  static_assert(kBlkCols == 8, "one wave holds the 8 x 8 factor");
+  constexpr int NC = ncomp<A>::v;
+  constexpr int NP = kBlkCols * (kBlkCols + 1) / 2;  // pairs i <= j
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // each pair's lane sums, added over quads (DPP), into gbuf[wave][pair][part][quad]
+  {
+    int p = 0;
+#pragma unroll
+    for (int i = 0; i < kBlkCols; ++i)
+#pragma unroll
+      for (int j = i; j < kBlkCols; ++j, ++p) {
+        A acc = zero<A>();
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) acc = fmac_conj(acc, X[i][u], X[j][u]);
+        double t[NC];
+        split_re(acc, t);
+#pragma unroll
+        for (int h = 0; h < NC; ++h) {
+          t[h] += dpp_mov<0xB1>(t[h]);
+          t[h] += dpp_mov<0x4E>(t[h]);
+          if ((lane & 3) == 0) gbuf[((wv * NP + p) * NC + h) * 16 + (lane >> 2)] = t[h];
+        }
+      }
+  }
+  __syncthreads();
+  const int ra = lane >> 3, cb = lane & 7;
+  A g = zero<A>();
+  if (ra <= cb) {
+    const int p = ra * kBlkCols - ra * (ra - 1) / 2 + (cb - ra);
+    double t[NC];
+#pragma unroll
+    for (int h = 0; h < NC; ++h) t[h] = 0.0;
+    for (int w = 0; w < nw; ++w)
+#pragma unroll
+      for (int h = 0; h < NC; ++h)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t[h] += gbuf[((w * NP + p) * NC + h) * 16 + q];
+    join_re(g, t);
+  }
+  if (ra >= nb || cb >= nb) {
+    g = zero<A>();
+    if (ra == cb) *(double*)&g = 1.0;
+  }
+  const double gdiag = re(g);
+  bool ok = true;
+  double inv[kBlkCols];
+#pragma unroll
+  for (int j = 0; j < kBlkCols; ++j) {
+    const double d = read_lane(re(g), j * 9);  // the pivot, lane (j, j)
+    ok = ok && (j >= nb || d > 1e-8 * read_lane(gdiag, j * 9));
+    const double r = sqrt(fmax(d, 0.0));
+    inv[j] = r > 0.0 ? 1.0 / r : 0.0;
+    if (ra == j) {
+      if (cb == j) {
+        g = zero<A>();
+        *(double*)&g = r;
+      } else if (cb > j) {
+        g = scale(g, inv[j]);
+      }
+    }
+    const A rja = shfl_v(g, j * 8 + ra), rjb = shfl_v(g, j * 8 + cb);
+    if (ra > j && ra <= cb) g = fmsub(g, conj(rja), rjb);
+  }
+  if (!ok) return false;
+  // lane (c, b), c <= b, holds Rm(c, b); column j of Xq = (X(:, j) -
+  // sum_{k<j} Xq(:, k) Rm(k, j)) / Rm(j, j), the earlier columns final first
+#pragma unroll
+  for (int j = 0; j < kBlkCols; ++j) {
+    A rkj[kBlkCols];
+#pragma unroll
+    for (int k = 0; k < j; ++k) rkj[k] = read_lane_v(g, k * 8 + j);
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      A v = X[j][u];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v = fmsub(v, X[k][u], rkj[k]);
+      X[j][u] = scale(v, inv[j]);
+    }
+  }
+  if (threadIdx.x < 64) Rm[cb * kBlkCols + ra] = (ra <= cb && cb < nb) ? g : zero<A>();
+  return true;
 }
 
 // Step headers (a thread per step) and the block's SV and SAV columns into
@@ -2044,18 +2202,22 @@ __global__ __launch_bounds__(kMblkHeadThreads) void k_mblk_head(LsqState<A> S, i
 }
 
 // P(i, b) = Q(:, i)^H W(:, b) for i < ncol, b < nb (rows ncol .. the next
-// multiple of 8 set to zero); with Rtop also R(i, col0 + b) = P(i, b).  A
-// workgroup per eight columns of Q; its waves take a share of the row groups
-// each (lane (c, g): column c, rows g, g + 8, ...: one load instruction reads
-// eight consecutive rows of each of eight columns), combined by DPP within a
-// wave and through LDS across the waves in wave order.
+// multiple of 8 set to zero), and the R entries above the block, Rtop(i, b)
+// = R(i, col0 + b): the first projection stores them (Rtop = P1), the second
+// (with R1) adds P2 R1 to them (Rtop = P1 + P2 R1).  A workgroup per eight
+// columns of Q; its waves take a share of the row groups each (lane (c, g):
+// column c, rows g, g + 8, ...: one load instruction reads eight consecutive
+// rows of each of eight columns), combined by DPP within a wave and through
+// LDS across the waves in wave order.
 template <class A>
 __global__ __launch_bounds__(kMblkSweepThreads) void k_mblk_proj(const A* __restrict__ Q, int ldq, int ncol, int s,
                                                                  const A* __restrict__ W, int nb, A* __restrict__ P,
                                                                  A* __restrict__ Rtop, int ldr,
+                                                                 const A* __restrict__ R1,
                                                                  const Ctrl* __restrict__ ctrl) {
   if (ctrl->halt) return;
   __shared__ A part[kMblkSweepWaves][kBlkCols][kBlkCols];
+  __shared__ A pfin[kBlkCols][kBlkCols];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = lane >> 3, g = lane & 7;
   const int i0 = blockIdx.x * 8, i = i0 + c;
@@ -2088,15 +2250,23 @@ __global__ __launch_bounds__(kMblkSweepThreads) void k_mblk_proj(const A* __rest
     for (int b = 0; b < kBlkCols; ++b) join_re(part[wv][c][b], d + b * ncomp<A>::v);
   }
   __syncthreads();
+  const int cc = threadIdx.x >> 3, b = threadIdx.x & 7, ii = i0 + cc;
+  A v = zero<A>();
   if (threadIdx.x < 64) {
-    const int cc = threadIdx.x >> 3, b = threadIdx.x & 7, ii = i0 + cc;
-    A v = part[0][cc][b];
+    v = part[0][cc][b];
 #pragma unroll
     for (int w = 1; w < kMblkSweepWaves; ++w) v += part[w][cc][b];
-    if (b < nb) {
-      P[ii * kBlkCols + b] = ii < ncol ? v : zero<A>();
-      if (Rtop && ii < ncol) Rtop[(int64_t)b * ldr + ii] = v;
-    }
+    if (b < nb) P[ii * kBlkCols + b] = ii < ncol ? v : zero<A>();
+    if (R1 == nullptr && b < nb && ii < ncol) Rtop[(int64_t)b * ldr + ii] = v;
+    pfin[cc][b] = v;
+  }
+  if (R1 == nullptr) return;
+  __syncthreads();
+  if (threadIdx.x < 64 && b < nb && ii < ncol) {
+    A u = zero<A>();
+    for (int c = 0; c <= b; ++c) u += pfin[cc][c] * R1[b * kBlkCols + c];
+    A* rp = Rtop + (int64_t)b * ldr + ii;
+    *rp = *rp + u;
   }
 }
 
@@ -2148,10 +2318,11 @@ __global__ __launch_bounds__(kMblkSweepThreads) void k_mblk_upd(const A* __restr
 template <class A, int RPL>
 __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_qr(LsqState<A> S, int nb, int s) {
   if (S.ctrl->halt) return;
-  __shared__ double scr_all[kMblkMaxWaves * 16 * (kBlkCols * ncomp<A>::v + 1)];
+  __shared__ double scr_all[kMblkMaxWaves * 16 * 33];
   __shared__ double xs[2 * kMblkSweepWaves * 32];
+  __shared__ double gbuf[kMblkMaxWaves * 36 * 2 * 16];
   const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
-  double* scr = scr_all + wv * 16 * (kBlkCols * ncomp<A>::v + 1);
+  double* scr = scr_all + wv * 16 * 33;
   A X[kBlkCols][RPL];
 #pragma unroll
   for (int u = 0; u < RPL; ++u) {
@@ -2160,7 +2331,7 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_qr(LsqState<A> S, i
     for (int b = 0; b < kBlkCols; ++b) X[b][u] = (r < s && b < nb) ? S.bw.W[b * s + r] : zero<A>();
   }
   int ph = 0;
-  mblk_qr<A, RPL>(X, nb, S.bw.R1, scr, xs, nw, ph);
+  if (!mblk_cholqr<A, RPL>(X, nb, S.bw.R1, gbuf)) mblk_qr<A, RPL>(X, nb, S.bw.R1, scr, xs, nw, ph);
 #pragma unroll
   for (int u = 0; u < RPL; ++u) {
     const int r = mblk_row<A, RPL>(u, nw);
@@ -2172,26 +2343,27 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_qr(LsqState<A> S, i
   }
 }
 
-// The second in-block factorisation (bw.W = Q2 R2), R above the block
-// completed (P1 + P2 R1), the block's R = R2 R1, then the steps in order
-// (projected residual, residual control, records) and the commit of Q and R
-// up to the last finished step.
+// The second in-block factorisation (bw.W = Q2 R2), the block's R = R2 R1
+// (the entries above it were completed by the second projection), then the
+// steps in order (projected residual, residual control, records) and the
+// commit of Q and R up to the last finished step.
 template <class A, int RPL>
 __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, int jb, int nb, int m, int t,
                                                                  int s, int col0, double rank_rtol) {
   if (S.ctrl->halt) return;
   constexpr int NC = ncomp<A>::v;
   const BlkWork<A> B = S.bw;
-  __shared__ double scr_all[kMblkMaxWaves * 16 * (kBlkCols * NC + 1)];
+  __shared__ double scr_all[kMblkMaxWaves * 16 * 33];
   __shared__ double xs[2 * kMblkSweepWaves * 32];
+  __shared__ double gbuf[kMblkMaxWaves * 36 * 2 * 16];
   __shared__ A R1[kBlkCols * kBlkCols], R2[kBlkCols * kBlkCols], RB[kBlkCols * kBlkCols];
   __shared__ A hcs[kBlkCols * (kMaxWindow + 1)];
   __shared__ double nujs[kBlkCols], n0s[kBlkCols];
   __shared__ int brks[kBlkCols];
-  __shared__ int sh_halt;
+  __shared__ int sh_halt;  // the last finished step of the block
   __shared__ Ctrl cl;
   const int tid = threadIdx.x, nw = blockDim.x >> 6, wv = tid >> 6;
-  double* scr = scr_all + wv * 16 * (kBlkCols * NC + 1);
+  double* scr = scr_all + wv * 16 * 33;
   if (tid < kBlkCols * (kMaxWindow + 1)) hcs[tid] = B.hc[tid];
   if (tid < kBlkCols) {
     nujs[tid] = B.nuj[tid];
@@ -2214,16 +2386,8 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, 
   if (tid < kBlkCols * kBlkCols) R1[tid] = B.R1[tid];
   if (tid == 0) cl = *S.ctrl;  // the control block, kept in LDS and written back
   int ph = 0;
-  mblk_qr<A, RPL>(X, nb, R2, scr, xs, nw, ph);
+  if (!mblk_cholqr<A, RPL>(X, nb, R2, gbuf)) mblk_qr<A, RPL>(X, nb, R2, scr, xs, nw, ph);
   __syncthreads();
-  // R above the block: P1 (stored by the first projection) + P2 R1
-  for (int i = tid; i < col0; i += blockDim.x)
-    for (int b = 0; b < nb; ++b) {
-      A u = zero<A>();
-      for (int c = 0; c <= b; ++c) u += B.P[i * kBlkCols + c] * R1[b * kBlkCols + c];
-      A* rp = S.R + (int64_t)(col0 + b) * S.ldr + i;
-      *rp = *rp + u;
-    }
   if (tid < kBlkCols * kBlkCols) {
     const int c = tid >> 3, b = tid & 7;
     A v = zero<A>();
@@ -2232,42 +2396,73 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, 
     RB[b * kBlkCols + c] = v;
   }
   __syncthreads();
-  int last = nb - 1, halted = 0;
+  // The steps.  Every projection of the incoming residual in one sum, then
+  // the residual left after each step in a second: the block's columns are
+  // orthonormal, so projecting the incoming residual on column b equals
+  // projecting what the steps before b left of it, up to rounding.  A step
+  // with rank loss keeps its column out (projection 0).
+  bool loss[kBlkCols];
 #pragma unroll
-  for (int bb = 0; bb < kBlkCols; ++bb) {
-    if (bb >= nb) break;
-    const int j = jb + bb, col = col0 + bb;
-    const double na = re(RB[bb * kBlkCols + bb]);
-    const bool loss = !(na > rank_rtol * n0s[bb]);
-    A zc = zero<A>();
-    if (!loss) {
-      double d[NC];
+  for (int b = 0; b < kBlkCols; ++b) loss[b] = b < nb && !(re(RB[b * kBlkCols + b]) > rank_rtol * n0s[b]);
+  A zb[kBlkCols];
+  {
+    double d[kBlkCols * NC];
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) {
       A acc = zero<A>();
+      if (b < nb && !loss[b]) {
 #pragma unroll
-      for (int u = 0; u < RPL; ++u) acc += conj(X[bb][u]) * rh[u];
-      split_re(acc, d);
-      grp_sums<NC>(d, scr, xs, nw, ph);
-      join_re(zc, d);
-#pragma unroll
-      for (int u = 0; u < RPL; ++u) rh[u] -= X[bb][u] * zc;
+        for (int u = 0; u < RPL; ++u) acc = fmac_conj(acc, X[b][u], rh[u]);
+      }
+      split_re(acc, d + b * NC);
     }
-    double q[1] = {0.0};
+    grp_sums<kBlkCols * NC>(d, scr, xs, nw, ph);
 #pragma unroll
-    for (int u = 0; u < RPL; ++u) q[0] += abs2(rh[u]);
-    grp_sums<1>(q, scr, xs, nw, ph);
-    const double sres = sqrt(q[0]);
-    if (tid == 0) {
+    for (int b = 0; b < kBlkCols; ++b) join_re(zb[b], d + b * NC);
+  }
+  double nn[kBlkCols];
+  {
+    A rr[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) rr[u] = rh[u];
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b) {
+      if (b < nb && !loss[b]) {
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) rr[u] = fmsub(rr[u], X[b][u], zb[b]);
+      }
+      nn[b] = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) nn[b] += abs2(rr[u]);
+    }
+    grp_sums<kBlkCols>(nn, scr, xs, nw, ph);
+  }
+  if (tid == 0) {
+    // the residual control in step order, up to the step that halts
+    A zs[kBlkCols];
+    double ss[kBlkCols];
+    int last = nb - 1, halted = 0;
+#pragma unroll
+    for (int bb = 0; bb < kBlkCols; ++bb) {
+      zs[bb] = zb[bb];
+      ss[bb] = sqrt(nn[bb]);
+    }
+#pragma unroll
+    for (int bb = 0; bb < kBlkCols; ++bb) {
+      if (bb >= nb || halted) continue;
+      const int j = jb + bb, col = col0 + bb;
+      const double sres = ss[bb];
       const bool brk = brks[bb];
       const int i0 = j - t > 0 ? j - t : 0, tw = j - i0;
       const double nuj = nujs[bb];
       S.nu[j] = nuj;
       for (int qq = 0; qq <= tw; ++qq) S.H[(int64_t)(j - 1) * S.ldh + i0 + qq] = hcs[bb * (kMaxWindow + 1) + qq];
-      S.z[col] = zc;
+      S.z[col] = zs[bb];
       int flags = 0;
       if (brk) flags |= 2;
-      if (loss) flags |= 4;
+      if (loss[bb]) flags |= 4;
       const bool due = control_due(&cl, sres);  // (updates the estimate: always evaluated)
-      const bool halt = due || j == m || brk || loss;
+      const bool halt = due || j == m || brk || loss[bb];
       if (halt) flags |= 1;
       S.sres_hist[j] = sres;
       if (halt) {
@@ -2278,23 +2473,30 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, 
         S.ctrl->flags = flags;
       }
       put_record(S, j, sres, nuj, flags, halt);
-      sh_halt = halt;
+      if (halt) {
+        last = bb;
+        halted = 1;
+      }
     }
-    __syncthreads();
-    if (sh_halt) {
-      last = bb;
-      halted = 1;
-      break;
+    if (!halted) {
+      S.ctrl->est = cl.est;
+      S.ctrl->sprev = cl.sprev;
     }
+    sh_halt = last;
   }
+  __syncthreads();
+  const int last = sh_halt;
+  // the residual after the last finished step
+#pragma unroll
+  for (int b = 0; b < kBlkCols; ++b)
+    if (b <= last && b < nb && !loss[b]) {
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) rh[u] = fmsub(rh[u], X[b][u], zb[b]);
+    }
 #pragma unroll
   for (int u = 0; u < RPL; ++u) {
     const int r = mblk_row<A, RPL>(u, nw);
     if (r < s) S.rho[r] = rh[u];
-  }
-  if (tid == 0 && !halted) {
-    S.ctrl->est = cl.est;
-    S.ctrl->sprev = cl.sprev;
   }
   // commit Q and the block's R up to the last finished step
 #pragma unroll
@@ -2313,13 +2515,12 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, 
 }
 
 // Rows per lane of the in-block kernels and their waves for a sketch of s
-// rows: the smallest RPL that kMblkMaxWaves waves cover (more waves share
-// the FP64 arithmetic and shorten each lane's chains), then the fewest waves
-// for it; false when s exceeds kMblkMaxWaves waves of the largest RPL (the
-// register budget: eight columns of RPL entries).
+// rows: the smallest RPL that kMblkMaxWaves waves cover (the block, the
+// Gram products and the fallback's sums stay in registers), then the fewest
+// waves for it; false when s exceeds kMblkMaxWaves waves of the largest RPL.
 template <class A>
 static bool mblk_shape(int s, int* rpl, int* nw) {
-  constexpr int opts[3] = {2, 4, sizeof(A) == 16 ? 6 : 8};
+  constexpr int opts[3] = {2, 4, sizeof(A) == 16 ? 4 : 8};
   if (s < 1) return false;
   for (int o : opts)
     if (s <= 64 * kMblkMaxWaves * o) {
@@ -2338,7 +2539,7 @@ static void launch_mblk_tail(hipStream_t st, const LsqState<A>& S, int jb, int n
   hipLaunchKernelGGL((k_mblk_qr<A, RPL>), dim3(1), dim3(64 * nw), 0, st, S, nb, s);
   if (col0 > 0) {
     hipLaunchKernelGGL(k_mblk_proj<A>, dim3((col0 + 7) / 8), dim3(kMblkSweepThreads), 0, st, S.Q, S.ldq, col0, s,
-                       S.bw.W, nb, S.bw.P, (A*)nullptr, S.ldr, S.ctrl);
+                       S.bw.W, nb, S.bw.P, S.R + (int64_t)col0 * S.ldr, S.ldr, (const A*)S.bw.R1, S.ctrl);
     hipLaunchKernelGGL(k_mblk_upd<A>, dim3((s + 63) / 64), dim3(kMblkSweepThreads), lds_upd, st, S.Q, S.ldq, col0,
                        s, S.bw.W, nb, S.bw.P, S.ctrl);
   }
@@ -2357,18 +2558,17 @@ static bool launch_lsq_blocks_multi(hipStream_t st, LsqState<A> S, int j0, int j
   for (int jb = j0; jb <= j1; jb += kBlkCols) {
     const int nb = std::min(kBlkCols, j1 - jb + 1);
     const int col0 = khat + jb - 1;  // committed columns of Q
-    hipLaunchKernelGGL(k_mblk_head<A>, dim3(1), dim3(kMblkHeadThreads), 0, st, S, jb, nb, khat, t, s, redb, slotr,
-                       nslot, brtol);
+    hipLaunchKernelGGL(k_mblk_head<A>, dim3(1), dim3(std::min(kMblkHeadThreads, (s + 63) / 64 * 64)), 0, st, S, jb,
+                       nb, khat, t, s, redb, slotr, nslot, brtol);
     if (col0 > 0) {
       hipLaunchKernelGGL(k_mblk_proj<A>, dim3((col0 + 7) / 8), dim3(kMblkSweepThreads), 0, st, S.Q, S.ldq, col0,
-                         s, S.bw.W, nb, S.bw.P, S.R + (int64_t)col0 * S.ldr, S.ldr, S.ctrl);
+                         s, S.bw.W, nb, S.bw.P, S.R + (int64_t)col0 * S.ldr, S.ldr, (const A*)nullptr, S.ctrl);
       hipLaunchKernelGGL(k_mblk_upd<A>, dim3((s + 63) / 64), dim3(kMblkSweepThreads), lds_upd, st, S.Q, S.ldq,
                          col0, s, S.bw.W, nb, S.bw.P, S.ctrl);
     }
     if (rpl == 2) launch_mblk_tail<A, 2>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
-    else if (rpl == 4) launch_mblk_tail<A, 4>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
-    else if constexpr (cpx) launch_mblk_tail<A, 6>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
-    else launch_mblk_tail<A, 8>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
+    else if (rpl == 4 || cpx) launch_mblk_tail<A, 4>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
+    else if constexpr (!cpx) launch_mblk_tail<A, 8>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
   }
   return true;
 }
@@ -2897,6 +3097,121 @@ __global__ __launch_bounds__(kBlock) void k_gemm_basis(int n, const T* __restric
   }
 }
 
+// C = [U P] G on the matrix cores (v_mfma_f64_16x16x4f64: a 16 x 4 block of
+// A times a 4 x 16 block of B added to a 16 x 16 block, 64 lanes).  G, l0 x
+// kc (l0 = ku + jp), is staged once per workgroup into LDS, as real and
+// imaginary planes of W = 16 NCT columns (zero padded to a multiple of 4 rows
+// and to W columns); the grid is persistent, each workgroup taking blocks of
+// 512 rows, each wave 64 rows (four 16-row tiles).  Lane (i, q) = (lane % 16,
+// lane / 16) supplies row i, basis column k0 + q of A and row k0 + q, column
+// i of B; its result register v holds row 4 v + q, column i of the 16 x 16
+// block (the layout measured on gfx950).
+// A complex product takes four real ones: re += a.x g.x + a.y (-g.y),
+// im += a.x g.y + a.y g.x.  The next four basis columns are loaded while the
+// current ones are multiplied.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kGemmMfmaThreads = 512;
+constexpr int kGemmMfmaRows = 64 * (kGemmMfmaThreads / 64);  // rows per workgroup block
+
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ double cre(double a) { return a; }
+__device__ __forceinline__ double cim(double) { return 0.0; }
+__device__ __forceinline__ double cre(cx<double> a) { return a.x; }
+__device__ __forceinline__ double cim(cx<double> a) { return a.y; }
+
+template <class T, int NCT>
+__global__ __launch_bounds__(kGemmMfmaThreads) void k_gemm_basis_mfma(
+    int n, const T* __restrict__ U, int64_t ldu, int ku, const T* __restrict__ P, int64_t ldp, int jp,
+    const typename traits<T>::acc* __restrict__ G, int ldg, int kc, T* __restrict__ C, int64_t ldc) {
+  using A = typename traits<T>::acc;
+  constexpr bool CPX = traits<T>::cpx;
+  constexpr int W = 16 * NCT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* gr = reinterpret_cast<double*>(smem_raw);
+  const int l0 = ku + jp, l0p = (l0 + 3) & ~3;
+  double* gi = gr + (size_t)l0p * W;
+  for (int e = threadIdx.x; e < l0p * W; e += blockDim.x) {
+    const int k = e / W, j = e - k * W;
+    const A g = (k < l0 && j < kc) ? G[(int64_t)k * ldg + j] : zero<A>();
+    gr[e] = cre(g);
+    if constexpr (CPX) gi[e] = cim(g);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i16 = lane & 15, q = lane >> 4;
+  for (int rb = blockIdx.x; (int64_t)rb * kGemmMfmaRows < n; rb += gridDim.x) {
+    const int row0 = rb * kGemmMfmaRows + wv * 64;
+    v4d acc[4][NCT][CPX ? 2 : 1];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int h = 0; h < (CPX ? 2 : 1); ++h) acc[t][ct][h] = v4d{0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int k0, A (&a)[4]) {
+      const int c = k0 + q;
+      const T* col = c < ku ? U + (int64_t)c * ldu : P + (int64_t)(c < l0 ? c - ku : 0) * ldp;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = row0 + t * 16 + i16;
+        const A v = widen(col[min(r, n - 1)]);
+        a[t] = (c < l0 && r < n) ? v : zero<A>();
+      }
+    };
+    A an[4];
+    load(0, an);
+    for (int k0 = 0; k0 < l0p; k0 += 4) {
+      A a[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = an[t];
+      if (k0 + 4 < l0p) load(k0 + 4, an);
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const int e = (k0 + q) * W + ct * 16 + i16;
+        const double br = gr[e];
+        if constexpr (CPX) {
+          const double bi = gi[e];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            acc[t][ct][0] = mfma_f64(cre(a[t]), br, acc[t][ct][0]);
+            acc[t][ct][0] = mfma_f64(cim(a[t]), -bi, acc[t][ct][0]);
+            acc[t][ct][1] = mfma_f64(cre(a[t]), bi, acc[t][ct][1]);
+            acc[t][ct][1] = mfma_f64(cim(a[t]), br, acc[t][ct][1]);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[t][ct][0] = mfma_f64(cre(a[t]), br, acc[t][ct][0]);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const int j = ct * 16 + i16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = row0 + t * 16 + 4 * v + q;
+          if (r < n && j < kc) {
+            A out;
+            if constexpr (CPX) out = A{acc[t][ct][0][v], acc[t][ct][1][v]};
+            else out = acc[t][ct][0][v];
+            C[(int64_t)j * ldc + r] = narrow<T>(out);
+          }
+        }
+      }
+  }
+}
+
+// LDS of the matrix-core product for l0 basis columns (0: too many for it).
+template <class T>
+static size_t gemm_mfma_lds(int l0, int nct) {
+  const size_t bytes = (size_t)((l0 + 3) & ~3) * 16 * nct * sizeof(double) * (traits<T>::cpx ? 2 : 1);
+  return bytes <= 144 * 1024 ? bytes : 0;
+}
+
 int gemm_basis_width(int kc) { return kc <= 8 ? 8 : (kc + 7) / 8 * 8; }
 
 template <class T>
@@ -2905,6 +3220,31 @@ void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, c
                        int64_t ldc) {
   const int nb = (n + kBlock - 1) / kBlock;
   const int ldg = gemm_basis_width(kc);
+  // complex data on the matrix cores, output columns in launches of at most 32
+  if (traits<T>::cpx && gemm_mfma_lds<T>(ku + jp, 2) > 0) {
+    static int ncu[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (ncu[dev] == 0 && hipDeviceGetAttribute(&ncu[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu[dev] = 256;
+    // one workgroup per CU (its LDS), 32 CUs left free: the product runs
+    // beside the least squares, whose small launches would otherwise wait for
+    // it to drain
+    const int blocks = (n + kGemmMfmaRows - 1) / kGemmMfmaRows;
+    const int grid = std::max(1, std::min(blocks, ncu[dev] >= 128 ? ncu[dev] - 32 : ncu[dev]));
+    for (int c0 = 0; c0 < kc; c0 += 32) {
+      const int cc = std::min(32, kc - c0);
+      const int nct = cc <= 16 ? 1 : 2;
+      const size_t lds = gemm_mfma_lds<T>(ku + jp, nct);
+      if (nct == 1)
+        hipLaunchKernelGGL((k_gemm_basis_mfma<T, 1>), dim3(grid), dim3(kGemmMfmaThreads), lds, st, n, U, ldu, ku,
+                           P, ldp, jp, G + c0, ldg, cc, C + (int64_t)c0 * ldc, ldc);
+      else
+        hipLaunchKernelGGL((k_gemm_basis_mfma<T, 2>), dim3(grid), dim3(kGemmMfmaThreads), lds, st, n, U, ldu, ku,
+                           P, ldp, jp, G + c0, ldg, cc, C + (int64_t)c0 * ldc, ldc);
+    }
+    return;
+  }
   // output columns in launches of at most 32 (the padded row width covers
   // the last one)
   for (int c0 = 0; c0 < kc; c0 += 32) {
