@@ -205,11 +205,52 @@ def summarize_pmc(fetch_csv, write_csv, calib_mb, workload_name):
     return "\n".join(lines) + "\n"
 
 
-def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name, flags=""):
+def _step_periods(trace, k1n):
+    """Median step period (start of the step kernel to its next start, within
+    a cycle) and median gap before the step kernel (end of the previous
+    first-stream kernel to its start) of a kernel trace."""
+    import numpy as np
+    starts = sorted(s_ for s_, e, n in trace if n == k1n)
+    per = np.diff(np.array(starts, dtype=np.float64)) / 1e3
+    per = per[per < 3 * np.median(per)]  # (cycle boundaries left out)
+    first = sorted((s_, e, n) for s_, e, n in trace
+                   if n == k1n or n.startswith(("k_update<", "k_ilu_", "k_dct_sketch<")))
+    gaps = [(b[0] - a[1]) / 1e3 for a, b in zip(first, first[1:]) if b[2] == k1n and a[2] != k1n]
+    return float(np.median(per)), float(np.median(gaps)) if gaps else 0.0
+
+
+def _mblk_summary(trace):
+    """Median durations of the several-workgroup block least-squares kernels
+    and of a whole block (step headers to finish), or '' without them."""
+    import numpy as np
+    names = ("k_mblk_head", "k_mblk_proj", "k_mblk_upd", "k_mblk_qr", "k_mblk_fin")
+    ev = sorted((s_, e, n) for s_, e, n in trace if n.startswith(names))
+    if not ev:
+        return ""
+    med = {}
+    for nm in names:
+        d = [(e - s_) / 1e3 for s_, e, n in ev if n.startswith(nm)]
+        if d:
+            med[nm] = float(np.median(d))
+    blocks, cur = [], None
+    for s_, e, n in ev:
+        if n.startswith("k_mblk_head"):
+            cur = s_
+        elif n.startswith("k_mblk_fin") and cur is not None:
+            blocks.append((e - cur) / 1e3)
+            cur = None
+    parts = ", ".join(f"{k[7:]} {v:.1f}" for k, v in med.items())
+    return (f"Block least squares on several workgroups ({len(blocks)} blocks of up to 8 steps): median "
+            f"kernel times (us) {parts}; a whole block, step headers to finish, median "
+            f"{np.median(blocks):.1f} us.")
+
+
+def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name, flags="", plain_trace=None):
     """Markdown summary of a rocprofv3 kernel-trace run: per-kernel calls and
     durations, the step kernel's per-launch distribution, whether any of its
     launches overlapped a kernel of the least-squares stream, and the bench's
-    own event timing of the same kernel."""
+    own event timing of the same kernel.  With plain_trace (a kernel trace of
+    the same command without --stats) also the step period of both runs."""
     import numpy as np
 
     def short(n):
@@ -247,7 +288,9 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name, flags=""):
              f"--warmup 0 --no-cpu-baseline --no-extras",
              f"    python3 {R}/bench.py --summarize-kstats {kd}/{os.path.basename(stats_csv)} "
              f"{_rel_dir(trace_csv)}/{os.path.basename(trace_csv)} BENCH.json --workload {workload_name}"
-             + (f" --kstats-flags \"{flags}\"" if flags else ""), "",
+             + (f" --kstats-flags \"{flags}\"" if flags else "")
+             + (f" --plain-trace {_rel_dir(plain_trace)}/{os.path.basename(plain_trace)}" if plain_trace else ""),
+             "",
              f"(BENCH.json: the output line of `python3 bench.py --workload {workload_name}{prec_flag} "
              "--no-cpu-baseline --no-extras` run just before, on the same box.)", "",
              f"Kernel source digest (bench.py kernel_source_digest, comments ignored): {kernel_source_digest()}.",
@@ -258,8 +301,28 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name, flags=""):
              f"{overlap} of its launches overlapped a least-squares kernel of the second stream. "
              f"The bench's own HIP events (recorded by the dispatches themselves on sampled steps, "
              f"created without a system-scope fence) read {bj['roofline']['avg_us']:.2f} us over "
-             f"{bj['arnoldi_step']['launches']} launches in the bench run.", "",
-             "| Calls | Avg (us) | Total (ms) | % | Kernel |", "|---:|---:|---:|---:|---|"]
+             f"{bj['arnoldi_step']['launches']} launches in the bench run.", ""]
+    mb = _mblk_summary(trace)
+    if mb:
+        lines += [mb, ""]
+    if plain_trace:
+        with open(plain_trace) as f:
+            ptrace = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(r["Kernel_Name"]))
+                      for r in csv.DictReader(f)]
+        per_s, gap_s = _step_periods(trace, k1n)
+        per_p, gap_p = _step_periods(ptrace, k1n)
+        pd_ = _rel_dir(plain_trace)
+        lines += [f"Step period (start of {k1n} to its next start within a cycle), median: "
+                  f"{per_p:.2f} us in a kernel trace without --stats (median gap before the step kernel "
+                  f"{gap_p:.2f} us), {per_s:.2f} us in the run above (gap {gap_s:.2f} us: the statistics "
+                  f"mode delays dispatches). The trace without --stats:", "",
+                  f"    timeout -k 10 300 rocprofv3 --kernel-trace --output-format csv -d {pd_} -o run -- "
+                  f"python3 {R}/bench.py --workload {workload_name}{prec_flag} --steps 1 --warmup 0 "
+                  f"--no-cpu-baseline --no-extras", ""]
+        mbp = _mblk_summary(ptrace)
+        if mbp:
+            lines += ["Without --stats: " + mbp, ""]
+    lines += ["| Calls | Avg (us) | Total (ms) | % | Kernel |", "|---:|---:|---:|---:|---|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
         lines.append(f"| {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.2f} | "
@@ -597,6 +660,8 @@ def main():
                     help="0: sparse sign; 1: subsampled randomised DCT (profiling runs)")
     ap.add_argument("--kstats-flags", default="",
                     help="with --summarize-kstats: the bench options of the profiled run (--sketch 1, ...)")
+    ap.add_argument("--plain-trace", default=None,
+                    help="with --summarize-kstats: a kernel trace of the same run without --stats")
     ap.add_argument("--precond", type=int, default=0,
                     help="right preconditioning of the timed solve: 0 none, 1 Jacobi, 2 ILU(0)")
     ap.add_argument("--lsq-kernel", type=int, default=0,
@@ -612,7 +677,8 @@ def main():
                     help="write the kernel-statistics summary of a rocprofv3 kernel-trace run and exit")
     args = ap.parse_args()
     if args.summarize_kstats:
-        sys.stdout.write(summarize_kstats(*args.summarize_kstats, args.workload, args.kstats_flags))
+        sys.stdout.write(summarize_kstats(*args.summarize_kstats, args.workload, args.kstats_flags,
+                                          args.plain_trace))
         return
     if args.summarize_pmc:
         sys.stdout.write(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],

@@ -190,10 +190,12 @@ void launch_reduce_steps(hipStream_t st, const A* part1, int64_t slot1, int nb1,
 
 // Initialise the QR of SAW with its first khat columns (SAU) and rho = S r0.
 // Also seeds the control block's residual estimate (gv.mode 1) and writes
-// the sketched residual over span(U) alone to the step record 0.
+// the sketched residual over span(U) alone to the step record 0.  kind as
+// for launch_lsq_steps: the register kernel or the several-workgroup block
+// kernels where the steps take them, else one workgroup.
 template <class A>
 void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr,
-                     double rank_rtol, int m, GivensInit gv);
+                     double rank_rtol, int m, GivensInit gv, int kind = 0);
 
 // y = R(0:n,0:n)^{-1} z(0:n); coefficients for [U, P]: y_i (U part), y_i / nu_i (P part).
 template <class A>

@@ -2201,6 +2201,39 @@ __global__ __launch_bounds__(kMblkHeadThreads) void k_mblk_head(LsqState<A> S, i
   }
 }
 
+// The cycle's recycled columns, a block of nb from column c0: SAW's columns
+// into bw.W (ld s), their norms into bw.n0; with c0 = 0 also rho = S r0.
+template <class A>
+__global__ __launch_bounds__(kMblkHeadThreads) void k_mblk_init_head(LsqState<A> S, int c0, int nb, int s,
+                                                                     const A* __restrict__ Sr) {
+  const BlkWork<A> B = S.bw;
+  __shared__ double scr_all[(kMblkHeadThreads / 64) * 16 * (kBlkCols + 1)];
+  __shared__ double xs[2 * kMblkSweepWaves * 32];
+  const int tid = threadIdx.x, wv = tid >> 6, nw = blockDim.x >> 6;
+  double nn[kBlkCols];
+#pragma unroll
+  for (int b = 0; b < kBlkCols; ++b) nn[b] = 0.0;
+  for (int r = tid; r < s; r += blockDim.x) {
+    if (c0 == 0) S.rho[r] = Sr[r];
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b)
+      if (b < nb) {
+        const A v = S.SAW[(int64_t)(c0 + b) * S.ldsaw + r];
+        B.W[b * s + r] = v;
+        nn[b] += abs2(v);
+      }
+  }
+  int ph = 0;
+  grp_sums<kBlkCols>(nn, scr_all + wv * 16 * (kBlkCols + 1), xs, nw, ph);
+  if (tid < kBlkCols) {
+    double v = nn[0];
+#pragma unroll
+    for (int b = 1; b < kBlkCols; ++b)
+      if (tid == b) v = nn[b];
+    B.n0[tid] = sqrt(v);
+  }
+}
+
 // P(i, b) = Q(:, i)^H W(:, b) for i < ncol, b < nb (rows ncol .. the next
 // multiple of 8 set to zero), and the R entries above the block, Rtop(i, b)
 // = R(i, col0 + b): the first projection stores them (Rtop = P1), the second
@@ -2349,7 +2382,8 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_qr(LsqState<A> S, i
 // commit of Q and R up to the last finished step.
 template <class A, int RPL>
 __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, int jb, int nb, int m, int t,
-                                                                 int s, int col0, double rank_rtol) {
+                                                                 int s, int col0, double rank_rtol, int mode,
+                                                                 GivensInit gv) {
   if (S.ctrl->halt) return;
   constexpr int NC = ncomp<A>::v;
   const BlkWork<A> B = S.bw;
@@ -2437,7 +2471,36 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, 
     }
     grp_sums<kBlkCols>(nn, scr, xs, nw, ph);
   }
-  if (tid == 0) {
+  if (mode != 0) {
+    // recycled columns (the cycle's start): every column committed, its
+    // projection of the residual recorded; after the last block, the
+    // sketched residual over span(U) starts the residual control
+#pragma unroll
+    for (int b = 0; b < kBlkCols; ++b)
+      if (b < nb && !loss[b]) {
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) rh[u] = fmsub(rh[u], X[b][u], zb[b]);
+      }
+    if (tid < kBlkCols) {
+      A zv = zb[0];
+#pragma unroll
+      for (int b = 1; b < kBlkCols; ++b)
+        if (tid == b) zv = zb[b];
+      if (tid < nb) S.z[col0 + tid] = zv;
+    }
+    if (mode == 2) {
+      double q[1] = {0.0};
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) q[0] += abs2(rh[u]);
+      grp_sums<1>(q, scr, xs, nw, ph);
+      if (tid == 0) {
+        const double sres = sqrt(q[0]);
+        S.sres_hist[0] = sres;
+        control_start(S, col0 + nb, sres, gv);
+      }
+    }
+    if (tid == 0) sh_halt = nb - 1;
+  } else if (tid == 0) {
     // the residual control in step order, up to the step that halts
     A zs[kBlkCols];
     double ss[kBlkCols];
@@ -2489,7 +2552,7 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, 
   // the residual after the last finished step
 #pragma unroll
   for (int b = 0; b < kBlkCols; ++b)
-    if (b <= last && b < nb && !loss[b]) {
+    if (mode == 0 && b <= last && b < nb && !loss[b]) {
 #pragma unroll
       for (int u = 0; u < RPL; ++u) rh[u] = fmsub(rh[u], X[b][u], zb[b]);
     }
@@ -2534,7 +2597,7 @@ static bool mblk_shape(int s, int* rpl, int* nw) {
 // The in-block factorisation, the second sweep and the finish of one block.
 template <class A, int RPL>
 static void launch_mblk_tail(hipStream_t st, const LsqState<A>& S, int jb, int nb, int m, int t, int s, int col0,
-                             int nw, double rank_rtol) {
+                             int nw, double rank_rtol, int mode = 0, GivensInit gv = GivensInit{}) {
   const size_t lds_upd = (size_t)kMblkSweepWaves * kBlkCols * 64 * sizeof(A);
   hipLaunchKernelGGL((k_mblk_qr<A, RPL>), dim3(1), dim3(64 * nw), 0, st, S, nb, s);
   if (col0 > 0) {
@@ -2543,7 +2606,8 @@ static void launch_mblk_tail(hipStream_t st, const LsqState<A>& S, int jb, int n
     hipLaunchKernelGGL(k_mblk_upd<A>, dim3((s + 63) / 64), dim3(kMblkSweepThreads), lds_upd, st, S.Q, S.ldq, col0,
                        s, S.bw.W, nb, S.bw.P, S.ctrl);
   }
-  hipLaunchKernelGGL((k_mblk_fin<A, RPL>), dim3(1), dim3(64 * nw), 0, st, S, jb, nb, m, t, s, col0, rank_rtol);
+  hipLaunchKernelGGL((k_mblk_fin<A, RPL>), dim3(1), dim3(64 * nw), 0, st, S, jb, nb, m, t, s, col0, rank_rtol,
+                     mode, gv);
 }
 
 // The several-workgroup block path for steps j0 .. j1 (false: the sketch is
@@ -2569,6 +2633,36 @@ static bool launch_lsq_blocks_multi(hipStream_t st, LsqState<A> S, int j0, int j
     if (rpl == 2) launch_mblk_tail<A, 2>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
     else if (rpl == 4 || cpx) launch_mblk_tail<A, 4>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
     else if constexpr (!cpx) launch_mblk_tail<A, 8>(st, S, jb, nb, m, t, s, col0, nw, rank_rtol);
+  }
+  return true;
+}
+
+// The cycle start on the several-workgroup block path: the khat recycled
+// columns of SAW appended to the factor in blocks of up to 8 (the same
+// projections, updates and in-block factorisations as the steps), z and the
+// projected residual from S r0, the sketched residual over span(U) and the
+// control's start (false: the sketch is too long for the in-block kernels).
+template <class A>
+static bool launch_lsq_init_multi(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr, double rank_rtol,
+                                  GivensInit gv) {
+  constexpr bool cpx = sizeof(A) == 16;
+  int rpl = 0, nw = 0;
+  if (khat < 1 || !mblk_shape<A>(s, &rpl, &nw)) return false;
+  const size_t lds_upd = (size_t)kMblkSweepWaves * kBlkCols * 64 * sizeof(A);
+  for (int c0 = 0; c0 < khat; c0 += kBlkCols) {
+    const int nb = std::min(kBlkCols, khat - c0);
+    const int mode = c0 + nb == khat ? 2 : 1;
+    hipLaunchKernelGGL(k_mblk_init_head<A>, dim3(1), dim3(std::min(kMblkHeadThreads, (s + 63) / 64 * 64)), 0, st,
+                       S, c0, nb, s, Sr);
+    if (c0 > 0) {
+      hipLaunchKernelGGL(k_mblk_proj<A>, dim3((c0 + 7) / 8), dim3(kMblkSweepThreads), 0, st, S.Q, S.ldq, c0, s,
+                         S.bw.W, nb, S.bw.P, S.R + (int64_t)c0 * S.ldr, S.ldr, (const A*)nullptr, S.ctrl);
+      hipLaunchKernelGGL(k_mblk_upd<A>, dim3((s + 63) / 64), dim3(kMblkSweepThreads), lds_upd, st, S.Q, S.ldq, c0,
+                         s, S.bw.W, nb, S.bw.P, S.ctrl);
+    }
+    if (rpl == 2) launch_mblk_tail<A, 2>(st, S, 0, nb, 0, 0, s, c0, nw, rank_rtol, mode, gv);
+    else if (rpl == 4 || cpx) launch_mblk_tail<A, 4>(st, S, 0, nb, 0, 0, s, c0, nw, rank_rtol, mode, gv);
+    else if constexpr (!cpx) launch_mblk_tail<A, 8>(st, S, 0, nb, 0, 0, s, c0, nw, rank_rtol, mode, gv);
   }
   return true;
 }
@@ -2647,15 +2741,17 @@ __global__ __launch_bounds__(kLsqBlock) void k_lsq_init(LsqState<A> S, int khat,
 
 template <class A>
 void launch_lsq_init(hipStream_t st, LsqState<A> S, int khat, int s, const A* Sr, double rank_rtol,
-                     int m, GivensInit gv) {
+                     int m, GivensInit gv, int kind) {
   int rl = 0, cw = 0;
   // the same register shape as the step kernel of this cycle
-  if (lsq_reg_shape<A>(s, khat + m + 1, &rl, &cw)) {
+  if (kind == 0 && lsq_reg_shape<A>(s, khat + m + 1, &rl, &cw)) {
     SDR_LSQ_REG_CASE(2, 8, k_lsq_init_reg, S, khat, s, Sr, rank_rtol, gv)
     SDR_LSQ_REG_CASE(2, 16, k_lsq_init_reg, S, khat, s, Sr, rank_rtol, gv)
     SDR_LSQ_REG_CASE(4, 16, k_lsq_init_reg, S, khat, s, Sr, rank_rtol, gv)
     SDR_LSQ_REG_CASE(4, 8, k_lsq_init_reg, S, khat, s, Sr, rank_rtol, gv)
   }
+  // the several-workgroup block path, where the steps take it too
+  if ((kind == 0 || kind == 3) && launch_lsq_init_multi<A>(st, S, khat, s, Sr, rank_rtol, gv)) return;
   const int lmax = khat + 1;
   const size_t lds = (size_t)(2 * s + 2 * lmax + lsq_chunk<A>(s, lmax) * s) * sizeof(A);
   hipLaunchKernelGGL(k_lsq_init<A>, dim3(1), dim3(kLsqBlock), lds, st, S, khat, s, Sr, rank_rtol, gv);
@@ -3220,7 +3316,8 @@ void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, c
                        int64_t ldc) {
   const int nb = (n + kBlock - 1) / kBlock;
   const int ldg = gemm_basis_width(kc);
-  // complex data on the matrix cores, output columns in launches of at most 32
+  // complex data on the matrix cores (real data streams faster through the
+  // vector kernel below), output columns in launches of at most 32
   if (traits<T>::cpx && gemm_mfma_lds<T>(ku + jp, 2) > 0) {
     static int ncu[64] = {0};
     int dev = 0;
@@ -3814,7 +3911,7 @@ SDR_INST_BASIS(cx<float>)
   template void launch_reduce2<A>(hipStream_t, const A*, int, int, int, double, const A*, int,  \
                                   int, A*, const Ctrl*);                                        \
   template void launch_init_v0<A>(hipStream_t, const A*, int, A*, double*);                     \
-  template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double, int, GivensInit); \
+  template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double, int, GivensInit, int); \
   template void launch_lsq_steps<A>(hipStream_t, LsqState<A>, int, int, int, int, int, int,      \
                                     const A*, int64_t, int, double, double, int);                \
   template void launch_reduce_steps<A>(hipStream_t, const A*, int64_t, int, int, int, int, int,  \

@@ -888,7 +888,7 @@ class Solver final : public SolverBase {
                               hipMemcpyDeviceToDevice, streamB_));
       }
       launch_lsq_init<A>(streamB_, lsq(), khat_, s_, Sr_, opt_.rank_rtol, m_,
-                         GivensInit{givens ? 1 : 0, geps, rn});
+                         GivensInit{givens ? 1 : 0, geps, rn}, opt_.lsq_kernel);
       LAUNCHCHK();
       // anchor of the Givens estimate: ||r0||, or the sketched residual over
       // span(U) (step record 0) divided by sqrt(1 - eps)
