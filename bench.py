@@ -312,10 +312,11 @@ def summarize_kstats(stats_csv, trace_csv, bench_json, workload_name, flags="", 
         per_s, gap_s = _step_periods(trace, k1n)
         per_p, gap_p = _step_periods(ptrace, k1n)
         pd_ = _rel_dir(plain_trace)
+        why = ": the statistics mode delays dispatches" if gap_s > gap_p + 0.5 else ""
         lines += [f"Step period (start of {k1n} to its next start within a cycle), median: "
                   f"{per_p:.2f} us in a kernel trace without --stats (median gap before the step kernel "
-                  f"{gap_p:.2f} us), {per_s:.2f} us in the run above (gap {gap_s:.2f} us: the statistics "
-                  f"mode delays dispatches). The trace without --stats:", "",
+                  f"{gap_p:.2f} us), {per_s:.2f} us in the run above (gap {gap_s:.2f} us{why}). "
+                  "The trace without --stats:", "",
                   f"    timeout -k 10 300 rocprofv3 --kernel-trace --output-format csv -d {pd_} -o run -- "
                   f"python3 {R}/bench.py --workload {workload_name}{prec_flag} --steps 1 --warmup 0 "
                   f"--no-cpu-baseline --no-extras", ""]
