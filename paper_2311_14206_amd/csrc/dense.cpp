@@ -11,12 +11,98 @@
 #include "dense.h"
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
 #include <limits>
+#include <mutex>
 #include <numeric>
+#include <thread>
+#include <vector>
 
 namespace sdr {
 namespace dense {
+
+// Helper threads for the column-parallel loops of the eigen-step (the
+// triangular inverse and product, the leading Schur vectors): started on first use and kept for the life of
+// the process.  parallel_for(n, fn) calls fn(i) for every i < n, spread over
+// the calling thread and the helpers by an atomic counter, and returns when
+// all calls are done; concurrent callers take turns.  Each fn(i) writes data
+// of its own, so results do not depend on the thread count.  A helper polls
+// for the next job for about 0.2 ms before it sleeps, so the loops of one
+// eigen-step start without a wake-up each.
+class ColumnPool {
+ public:
+  static ColumnPool& instance() {
+    static ColumnPool* p = new ColumnPool();  // (kept: helpers are never joined)
+    return *p;
+  }
+  int helpers() const { return helpers_; }
+  void parallel_for(int n, const std::function<void(int)>& fn) {
+    if (n <= 1 || helpers_ == 0) {
+      for (int i = 0; i < n; ++i) fn(i);
+      return;
+    }
+    std::lock_guard<std::mutex> turn(run_mu_);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      n_ = n;
+      next_.store(0, std::memory_order_relaxed);
+      busy_.store(helpers_, std::memory_order_relaxed);
+      gen_.fetch_add(1, std::memory_order_release);
+    }
+    cv_.notify_all();
+    work();
+    for (int spin = 0; busy_.load(std::memory_order_acquire) != 0; ++spin) {
+      if (spin > 4096) {
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [this] { return busy_.load(std::memory_order_acquire) == 0; });
+        break;
+      }
+      std::this_thread::yield();
+    }
+  }
+
+ private:
+  ColumnPool() {
+    const unsigned hw = std::thread::hardware_concurrency();
+    helpers_ = hw >= 8 ? 3 : hw >= 2 ? (int)hw - 1 : 0;
+    for (int t = 0; t < helpers_; ++t) std::thread([this] { loop(); }).detach();
+  }
+  void work() {
+    const int n = n_;
+    for (int i = next_.fetch_add(1); i < n; i = next_.fetch_add(1)) (*fn_)(i);
+  }
+  void loop() {
+    long seen = 0;
+    for (;;) {
+      const auto t0 = std::chrono::steady_clock::now();
+      while (gen_.load(std::memory_order_acquire) == seen &&
+             std::chrono::steady_clock::now() - t0 < std::chrono::microseconds(200)) {
+      }
+      if (gen_.load(std::memory_order_acquire) == seen) {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != seen; });
+      }
+      seen = gen_.load(std::memory_order_acquire);
+      work();
+      if (busy_.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+        std::lock_guard<std::mutex> lk(mu_);
+        done_cv_.notify_all();
+      }
+    }
+  }
+  int helpers_ = 0;
+  std::mutex run_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int n_ = 0;
+  std::atomic<int> next_{0}, busy_{0};
+  std::atomic<long> gen_{0};
+};
 
 static inline double abs1(cd z) { return std::fabs(z.real()) + std::fabs(z.imag()); }
 
@@ -341,56 +427,65 @@ static bool hessenberg_qr_window(SplitMat& T, std::vector<Rot>& log) {
 // reflectors (Vr, Vi, F) and the rotation log: Y = Q_h G_1 ... G_N E_kk.
 static void leading_schur_vectors(int n, int kk, const std::vector<double>& Vr, const std::vector<double>& Vi,
                                   const std::vector<double>& F, const std::vector<Rot>& log, Mat& Y) {
-  // M = G_1 ... G_N E_kk, rows contiguous (n x kk, split): G on rows k, k+1
-  std::vector<double> Mr((size_t)n * kk, 0.0), Mi((size_t)n * kk, 0.0);
-  for (int j = 0; j < kk; ++j) Mr[(size_t)j * kk + j] = 1.0;
-  int top = kk - 1;  // rows beyond top are zero
-  for (auto it = log.rbegin(); it != log.rend(); ++it) {
-    const int k = it->k;
-    if (k > top) continue;
-    const double c = it->c, sr = it->sr, si = it->si;
-    double* __restrict__ ar = Mr.data() + (size_t)k * kk;
-    double* __restrict__ ai = Mi.data() + (size_t)k * kk;
-    double* __restrict__ br = ar + kk;
-    double* __restrict__ bi = ai + kk;
-    for (int j = 0; j < kk; ++j) {
-      const double xr = ar[j], xi = ai[j], yr = br[j], yi = bi[j];
-      ar[j] = c * xr - (sr * yr - si * yi);  // c a - s b
-      ai[j] = c * xi - (sr * yi + si * yr);
-      br[j] = (sr * xr + si * xi) + c * yr;  // conj(s) a + c b
-      bi[j] = (sr * xi - si * xr) + c * yi;
-    }
-    if (k + 1 > top) top = k + 1;
-  }
-  // Y = Q_h M with Q_h = P_0 P_1 ... P_{n-3}: columns of Y split, column major
+  // M = G_1 ... G_N E_kk, rows contiguous (n x kk, split): G on rows k, k+1.
+  // Columns are independent: parts of up to 8 columns go to the helper
+  // threads, each applying the whole log, then the reflectors, to its own.
+  constexpr int kPart = 8;
   std::vector<double> Yr((size_t)n * kk), Yi((size_t)n * kk);
-  for (int j = 0; j < kk; ++j)
-    for (int i = 0; i < n; ++i) {
-      Yr[(size_t)j * n + i] = Mr[(size_t)i * kk + j];
-      Yi[(size_t)j * n + i] = Mi[(size_t)i * kk + j];
-    }
-  for (int k = n - 3; k >= 0; --k) {
-    const double f = F[k];
-    if (f == 0.0) continue;
-    const int len = n - k - 1;
-    const double* __restrict__ vr = Vr.data() + (size_t)k * n;
-    const double* __restrict__ vi = Vi.data() + (size_t)k * n;
-    for (int j = 0; j < kk; ++j) {
-      double* __restrict__ yr = Yr.data() + (size_t)j * n + k + 1;
-      double* __restrict__ yi = Yi.data() + (size_t)j * n + k + 1;
-      double dr = 0.0, di = 0.0;
-      for (int i = 0; i < len; ++i) {
-        dr += vr[i] * yr[i] + vi[i] * yi[i];
-        di += vr[i] * yi[i] - vi[i] * yr[i];
+  const int parts = (kk + kPart - 1) / kPart;
+  ColumnPool::instance().parallel_for(parts, [&](int part) {
+    const int j0 = part * kPart, w = std::min(kk, j0 + kPart) - j0;
+    // this part's columns of M in a buffer of its own (no cache line shared
+    // with another part), rows contiguous
+    std::vector<double> Mr((size_t)n * w, 0.0), Mi((size_t)n * w, 0.0);
+    for (int j = 0; j < w; ++j) Mr[(size_t)(j0 + j) * w + j] = 1.0;
+    int top = j0 + w - 1;  // rows beyond top are zero in these columns
+    for (auto it = log.rbegin(); it != log.rend(); ++it) {
+      const int k = it->k;
+      if (k > top) continue;
+      const double c = it->c, sr = it->sr, si = it->si;
+      double* __restrict__ ar = Mr.data() + (size_t)k * w;
+      double* __restrict__ ai = Mi.data() + (size_t)k * w;
+      double* __restrict__ br = ar + w;
+      double* __restrict__ bi = ai + w;
+      for (int j = 0; j < w; ++j) {
+        const double xr = ar[j], xi = ai[j], yr = br[j], yi = bi[j];
+        ar[j] = c * xr - (sr * yr - si * yi);  // c a - s b
+        ai[j] = c * xi - (sr * yi + si * yr);
+        br[j] = (sr * xr + si * xi) + c * yr;  // conj(s) a + c b
+        bi[j] = (sr * xi - si * xr) + c * yi;
       }
-      dr *= f;
-      di *= f;
-      for (int i = 0; i < len; ++i) {
-        yr[i] -= vr[i] * dr - vi[i] * di;
-        yi[i] -= vr[i] * di + vi[i] * dr;
+      if (k + 1 > top) top = k + 1;
+    }
+    // Y = Q_h M with Q_h = P_0 P_1 ... P_{n-3}: columns of Y split, column major
+    for (int j = 0; j < w; ++j)
+      for (int i = 0; i < n; ++i) {
+        Yr[(size_t)(j0 + j) * n + i] = Mr[(size_t)i * w + j];
+        Yi[(size_t)(j0 + j) * n + i] = Mi[(size_t)i * w + j];
+      }
+    for (int k = n - 3; k >= 0; --k) {
+      const double f = F[k];
+      if (f == 0.0) continue;
+      const int len = n - k - 1;
+      const double* __restrict__ vr = Vr.data() + (size_t)k * n;
+      const double* __restrict__ vi = Vi.data() + (size_t)k * n;
+      for (int j = j0; j < j0 + w; ++j) {
+        double* __restrict__ yr = Yr.data() + (size_t)j * n + k + 1;
+        double* __restrict__ yi = Yi.data() + (size_t)j * n + k + 1;
+        double dr = 0.0, di = 0.0;
+        for (int i = 0; i < len; ++i) {
+          dr += vr[i] * yr[i] + vi[i] * yi[i];
+          di += vr[i] * yi[i] - vi[i] * yr[i];
+        }
+        dr *= f;
+        di *= f;
+        for (int i = 0; i < len; ++i) {
+          yr[i] -= vr[i] * dr - vi[i] * di;
+          yi[i] -= vr[i] * di + vi[i] * dr;
+        }
       }
     }
-  }
+  });
   Y = Mat(n, kk);
   for (size_t i = 0; i < Y.a.size(); ++i) Y.a[i] = cd(Yr[i], Yi[i]);
 }
@@ -924,7 +1019,8 @@ static double tri_inverse_product(int n, const S* R, S* Ri, const S* C, std::vec
   // Ri zero on entry; column jc = j0 + c is R^{-1} e_jc, its rows above jc
   // found from the bottom: at step p row p is final, rows 0 .. p-1 take its
   // contribution and row p-1 is then divided by its diagonal entry
-  for (int j0 = 0; j0 < n; j0 += 4) {
+  ColumnPool::instance().parallel_for((n + 3) / 4, [&](int g) {
+    const int j0 = 4 * g;
     const int jb = std::min(4, n - j0);
     S* col[4];
     for (int c = 0; c < 4; ++c) col[c] = Ri + (size_t)(j0 + std::min(c, jb - 1)) * n;
@@ -953,7 +1049,7 @@ static double tri_inverse_product(int n, const S* R, S* Ri, const S* C, std::vec
       for (int c = 0; c < jb; ++c)
         if (p <= j0 + c) col[c][p - 1] /= d;
     }
-  }
+  });
   double f = 0.0, fi = 0.0;
   for (int j = 0; j < n; ++j)
     for (int i = 0; i <= j; ++i) {
@@ -961,8 +1057,19 @@ static double tri_inverse_product(int n, const S* R, S* Ri, const S* C, std::vec
       fi += norm_(Ri[(size_t)j * n + i]);
     }
   X.assign((size_t)n * n, S(0.0));
-  int j = 0;
-  for (; j + 4 <= n; j += 4) {
+  const int nq = n / 4;  // groups of four columns, then the rest one by one
+  ColumnPool::instance().parallel_for(nq + (n - 4 * nq), [&](int g) {
+    if (g >= nq) {
+      const int j = 4 * nq + (g - nq);
+      S* xj = X.data() + (size_t)j * n;
+      for (int p = 0; p < n; ++p) {
+        const S cpj = C[(size_t)j * n + p];
+        const S* rip = Ri + (size_t)p * n;
+        for (int i = 0; i <= p; ++i) xj[i] += rip[i] * cpj;
+      }
+      return;
+    }
+    const int j = 4 * g;
     S* __restrict__ x0 = X.data() + (size_t)j * n;
     S* __restrict__ x1 = x0 + n;
     S* __restrict__ x2 = x1 + n;
@@ -979,20 +1086,12 @@ static double tri_inverse_product(int n, const S* R, S* Ri, const S* C, std::vec
         x3[i] += r * a3;
       }
     }
-  }
-  for (; j < n; ++j) {
-    S* xj = X.data() + (size_t)j * n;
-    for (int p = 0; p < n; ++p) {
-      const S cpj = C[(size_t)j * n + p];
-      const S* rip = Ri + (size_t)p * n;
-      for (int i = 0; i <= p; ++i) xj[i] += rip[i] * cpj;
-    }
-  }
+  });
   return std::sqrt(f * fi);
 }
 
 int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std::vector<cd>& G,
-                  int* ell_out) {
+                  int* ell_out, const cd* RiC_in, double ri_fro2) {
   G.clear();
   *ell_out = 0;
   if (l0 <= 0 || k <= 0) return 0;
@@ -1010,7 +1109,14 @@ int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std
     if (std::abs(Rm(i, i)) == 0.0) singular = true;
   double cond = std::numeric_limits<double>::infinity();
   Mat RiC;  // R^{-1} C when R is nonsingular
-  if (!singular) {
+  if (!singular && RiC_in != nullptr && ri_fro2 >= 0.0) {
+    double f = 0.0;
+    for (int j = 0; j < l0; ++j)
+      for (int i = 0; i <= j; ++i) f += std::norm(Rm(i, j));
+    cond = std::sqrt(f * ri_fro2);
+    RiC = Mat(l0, l0);
+    for (size_t i = 0; i < RiC.a.size(); ++i) RiC.a[i] = RiC_in[i];
+  } else if (!singular) {
     if (real) {
       std::vector<double> r((size_t)l0 * l0), ri((size_t)l0 * l0, 0.0), c((size_t)l0 * l0), x;
       for (size_t i = 0; i < r.size(); ++i) {

@@ -33,9 +33,11 @@ void svd_jacobi(const Mat& A, Mat& P, std::vector<double>& sig, Mat& W, bool rea
 
 // Sketched harmonic-Ritz step (Section 3.5): see sdr_host_harmonic_ritz.
 // R: l0 x l0 upper triangular factor of SAW; C = Q^H [SU, SV].  Writes G
-// (l0 x k_eff) and returns k_eff, or -1 on failure.
+// (l0 x k_eff) and returns k_eff, or -1 on failure.  RiC, when given, is
+// R^{-1} C formed elsewhere (l0 x l0, column major) and ri_fro2 the squared
+// Frobenius norm of R^{-1}: the triangular inverse is then not formed here.
 int harmonic_ritz(int l0, const cd* R, const cd* C, int s, int k, bool real, std::vector<cd>& G,
-                  int* ell);
+                  int* ell, const cd* RiC = nullptr, double ri_fro2 = -1.0);
 
 }  // namespace dense
 }  // namespace sdr

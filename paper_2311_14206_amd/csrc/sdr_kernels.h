@@ -272,6 +272,12 @@ template <class A>
 bool launch_back_subst(hipStream_t st, int nls, int khat, const A* R, int ldr, const A* z, const double* nu,
                        A* y);
 
+// Ri = R^{-1} for the upper triangular n x n leading block of R (ld ldr),
+// one wavefront per column, and fro2[j] = ||Ri(:, j)||^2; false (nothing
+// launched) when n exceeds 512.
+template <class A>
+bool launch_tri_inverse(hipStream_t st, int n, const A* R, int ldr, A* Ri, int ldri, double* fro2);
+
 template <class A>
 void launch_small_gemm(hipStream_t st, bool conjtrans, int M, int N, int K, const A* a, int lda,
                        const A* b, int ldb, A* c, int ldc);

@@ -3308,6 +3308,76 @@ static size_t gemm_mfma_lds(int l0, int nct) {
   return bytes <= 144 * 1024 ? bytes : 0;
 }
 
+// Columns of R^{-1} (R: n x n upper triangular, ld ldr), a wave per column
+// j: x = e_j, then for i = j down to 0: x_i /= R(i, i) and x(0:i) -= x_i
+// R(0:i, i), lane l holding rows l + 64 q (q < kTriRows); column i + 1 of R
+// is loaded while column i is applied.  Writes Ri(:, j) (ld ldri, zeros below
+// j) and ||Ri(:, j)||^2 to fro2[j].  n <= 64 kTriRows.
+constexpr int kTriRows = 8;
+template <class A>
+__global__ __launch_bounds__(64) void k_tri_inv_cols(int n, const A* __restrict__ R, int ldr, A* __restrict__ Ri,
+                                                     int ldri, double* __restrict__ fro2) {
+  const int j = blockIdx.x, lane = threadIdx.x;
+  A x[kTriRows];
+#pragma unroll
+  for (int q = 0; q < kTriRows; ++q) {
+    A v = zero<A>();
+    if (lane + 64 * q == j) *(double*)&v = 1.0;
+    x[q] = v;
+  }
+  A col[kTriRows], nxt[kTriRows];
+  auto load = [&](int i, A (&c)[kTriRows]) {
+#pragma unroll
+    for (int q = 0; q < kTriRows; ++q) {
+      const int r = lane + 64 * q;
+      c[q] = r <= i && r < n ? R[(int64_t)i * ldr + r] : zero<A>();
+    }
+  };
+  load(j, nxt);
+  for (int i = j; i >= 0; --i) {
+#pragma unroll
+    for (int q = 0; q < kTriRows; ++q) col[q] = nxt[q];
+    if (i > 0) load(i - 1, nxt);
+    // x_i /= R(i, i): the owner lane's entry, broadcast
+    const int ow = i & 63, oq = i >> 6;
+    A xi = zero<A>(), rii = zero<A>();
+#pragma unroll
+    for (int q = 0; q < kTriRows; ++q)
+      if (q == oq) {
+        xi = x[q];
+        rii = col[q];
+      }
+    xi = shfl_v(xi, ow);
+    rii = shfl_v(rii, ow);
+    const double d = abs2(rii);
+    xi = d > 0.0 ? scale(xi * conj(rii), 1.0 / d) : zero<A>();
+#pragma unroll
+    for (int q = 0; q < kTriRows; ++q) {
+      const int r = lane + 64 * q;
+      if (r == i) x[q] = xi;
+      else if (r < i) x[q] -= col[q] * xi;
+    }
+  }
+  double nr = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTriRows; ++q) {
+    const int r = lane + 64 * q;
+    if (r < n) {
+      Ri[(int64_t)j * ldri + r] = r <= j ? x[q] : zero<A>();
+      if (r <= j) nr += abs2(x[q]);
+    }
+  }
+  nr = wave_sum(nr);
+  if (lane == 0) fro2[j] = nr;
+}
+
+template <class A>
+bool launch_tri_inverse(hipStream_t st, int n, const A* R, int ldr, A* Ri, int ldri, double* fro2) {
+  if (n < 1 || n > 64 * kTriRows) return false;
+  hipLaunchKernelGGL(k_tri_inv_cols<A>, dim3(n), dim3(64), 0, st, n, R, ldr, Ri, ldri, fro2);
+  return true;
+}
+
 int gemm_basis_width(int kc) { return kc <= 8 ? 8 : (kc + 7) / 8 * 8; }
 
 template <class T>
@@ -3912,6 +3982,7 @@ SDR_INST_BASIS(cx<float>)
                                   int, A*, const Ctrl*);                                        \
   template void launch_init_v0<A>(hipStream_t, const A*, int, A*, double*);                     \
   template void launch_lsq_init<A>(hipStream_t, LsqState<A>, int, int, const A*, double, int, GivensInit, int); \
+  template bool launch_tri_inverse<A>(hipStream_t, int, const A*, int, A*, int, double*);                    \
   template void launch_lsq_steps<A>(hipStream_t, LsqState<A>, int, int, int, int, int, int,      \
                                     const A*, int64_t, int, double, double, int);                \
   template void launch_reduce_steps<A>(hipStream_t, const A*, int64_t, int, int, int, int, int,  \

@@ -237,6 +237,14 @@ class Solver final : public SolverBase {
       // the default system-scope fence (an L2 writeback each time) is skipped.
       for (auto& e : evs_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence));
       red3_ = dalloc<A>(4);
+      // the eigen-step's R^{-1} and R^{-1} C, formed on the device for complex data
+      if (traits<T>::cpx) {
+        Ri_ = dalloc<A>((size_t)lmax_ * lmax_);
+        RiC_ = dalloc<A>((size_t)lmax_ * lmax_);
+        fro2_ = dalloc<double>(lmax_);
+        HIPCHK(hipHostMalloc((void**)&hRiC_, sizeof(A) * (size_t)lmax_ * lmax_, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&hfro2_, sizeof(double) * lmax_, hipHostMallocDefault));
+      }
       // block least-squares work: W (s x 8), P ((lmax + 8) x 8), R1, R2, the H columns
       blkA_ = dalloc<A>((size_t)s * 8 + (size_t)(lmax_ + 8) * 8 + 2 * 64 + 8 * (kMaxWindow + 1));
       blkD_ = dalloc<double>(16);
@@ -1097,6 +1105,16 @@ class Solver final : public SolverBase {
     if (k_ == 0 || l0 == 0) return;
     launch_small_gemm<A>(st, true, l0, l0, s_, Q_, s_, pend_.SB, s_, C_, l0);
     LAUNCHCHK();
+    // complex data: R^{-1} (a wavefront per column) and R^{-1} C on the
+    // device, so that the host's step starts from them (its longest serial
+    // part on this data); real data keep the host's own triangular solve
+    pend_.gpu_ric = Ri_ != nullptr && launch_tri_inverse<A>(st, l0, R_, lmax_, Ri_, l0, fro2_);
+    if (pend_.gpu_ric) {
+      launch_small_gemm<A>(st, false, l0, l0, l0, Ri_, l0, C_, l0, RiC_, l0);
+      LAUNCHCHK();
+      HIPCHK(hipMemcpyAsync(hRiC_, RiC_, sizeof(A) * (size_t)l0 * l0, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hfro2_, fro2_, sizeof(double) * l0, hipMemcpyDeviceToHost, st));
+    }
     HIPCHK(hipMemcpyAsync(hR_, R_, sizeof(A) * (size_t)lmax_ * l0, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(hC_, C_, sizeof(A) * (size_t)l0 * l0, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(hnu_, nu_, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
@@ -1168,7 +1186,16 @@ class Solver final : public SolverBase {
         Rc[(size_t)c * l0 + i] = i <= c ? to_cd(hR_[(size_t)c * lmax_ + i]) : std::complex<double>(0.0);
         Cc[(size_t)c * l0 + i] = to_cd(hC_[(size_t)c * l0 + i]);
       }
-    r.keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s_, k_, !traits<T>::cpx, r.G, &r.ell);
+    if (pend_.gpu_ric) {
+      std::vector<std::complex<double>> RiC((size_t)l0 * l0);
+      for (size_t i = 0; i < RiC.size(); ++i) RiC[i] = to_cd(hRiC_[i]);
+      double fro2 = 0.0;
+      for (int c = 0; c < l0; ++c) fro2 += hfro2_[c];
+      r.keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s_, k_, !traits<T>::cpx, r.G, &r.ell, RiC.data(),
+                                    fro2);
+    } else {
+      r.keff = dense::harmonic_ritz(l0, Rc.data(), Cc.data(), s_, k_, !traits<T>::cpx, r.G, &r.ell);
+    }
     if (r.keff < 0) {
       set_err("Schur iteration did not converge");
       throw HipError{SDR_EDEVICE};
@@ -1300,7 +1327,8 @@ class Solver final : public SolverBase {
                     (void*)nu_, (void*)sres_hist_, (void*)ctrl_, (void*)ctrl_free_, (void*)part1_,
                     (void*)redb_, (void*)psk_, (void*)red2_, (void*)red3_, (void*)Sr_,
                     (void*)ycoef_, (void*)xt_, (void*)r_, (void*)rnew_, (void*)G_, (void*)Gs_,
-                    (void*)C_, (void*)dct_rows_, (void*)blkA_, (void*)blkD_, (void*)blkI_, (void*)izb_, (void*)iy_, (void*)izA_, (void*)iyA_})
+                    (void*)C_, (void*)dct_rows_, (void*)blkA_, (void*)blkD_, (void*)blkI_, (void*)Ri_, (void*)RiC_,
+                    (void*)fro2_, (void*)izb_, (void*)iy_, (void*)izA_, (void*)iyA_})
       dfree(p);
     if (rec_host_) (void)hipHostFree(rec_host_);
     rec_host_ = nullptr;
@@ -1308,9 +1336,10 @@ class Solver final : public SolverBase {
     halt_host_ = nullptr;
     for (void* p : {(void*)hR_, (void*)hC_, (void*)hz_, (void*)hy_, (void*)hnu_, (void*)hG_,
                     (void*)hRc_, (void*)hnuc_,
-                    (void*)hscal_, (void*)hres_})
+                    (void*)hscal_, (void*)hres_, (void*)hRiC_, (void*)hfro2_})
       if (p) (void)hipHostFree(p);
-    hR_ = hC_ = hz_ = hy_ = hG_ = hscal_ = hRc_ = hres_ = nullptr;
+    hR_ = hC_ = hz_ = hy_ = hG_ = hscal_ = hRc_ = hres_ = hRiC_ = nullptr;
+    hfro2_ = nullptr;
     hres_dev_ = nullptr;
     hnu_ = hnuc_ = nullptr;
     for (auto& evp : ev_) {
@@ -1363,6 +1392,7 @@ class Solver final : public SolverBase {
     T* P = nullptr;
     A* SB = nullptr;   // shifted so that column 0 is the first recycled column
     A* SAW = nullptr;
+    bool gpu_ric = false;  // R^{-1} C and ||R^{-1}||_F^2 copied to the host by the device
   } pend_;
   hipEvent_t ev_copy_ = nullptr;
   hipEvent_t ev_res_ = nullptr;   // after the residual norm's reduction into host-mapped memory
@@ -1377,6 +1407,8 @@ class Solver final : public SolverBase {
   double sk_scl_ = 1.0;       // scale of the reduced sketch rows
   DctRow* dct_rows_ = nullptr;
   DctSpec dct_{};
+  A *Ri_ = nullptr, *RiC_ = nullptr, *hRiC_ = nullptr;
+  double *fro2_ = nullptr, *hfro2_ = nullptr;
   A *blkA_ = nullptr;
   double* blkD_ = nullptr;
   int* blkI_ = nullptr;
