@@ -281,7 +281,9 @@ int sdr_spmv(sdr_handle* h, const void* x, void* y);
  * vectors of length n.  Factors the current matrix first if no solve has.
  * SDR_EINVAL if that factorisation failed (zero diagonal entry or pivot).
  * The apply is queued on the handle's stream (sdr_set_stream) and the call
- * returns without waiting: z is complete when that stream's work is. */
+ * returns without waiting: z is complete when that stream's work is.  With
+ * the null stream set, the null stream's later work waits for the apply (on
+ * the device). */
 int sdr_precond_apply(sdr_handle* h, const void* v, void* z);
 
 /* Basis data of the last cycle for inspection: the first ncols normalised

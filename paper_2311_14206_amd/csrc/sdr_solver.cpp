@@ -2076,6 +2076,15 @@ void order_after_caller(sdr_handle* h) {
   HIPCHK(hipEventRecord(h->ev_in, nullptr));
   HIPCHK(hipStreamWaitEvent(h->own, h->ev_in, 0));
 }
+
+// For a call that returns without waiting: the caller's later null-stream
+// work is ordered after the call's work on the handle's own stream (a wait
+// on the device, not on the host).
+void order_caller_after(sdr_handle* h) {
+  if (!h->follow_null) return;
+  HIPCHK(hipEventRecord(h->ev_in, h->own));
+  HIPCHK(hipStreamWaitEvent(nullptr, h->ev_in, 0));
+}
 }  // namespace
 
 int sdr_update_matrix(sdr_handle* h, const sdr_csr* A) {
@@ -2221,6 +2230,7 @@ int sdr_precond_apply(sdr_handle* h, const void* v, void* z) {
       HIPCHK(hipMemcpyAsync(z, v, h->elem() * h->n, hipMemcpyDeviceToDevice, h->stream));
       if (h->opt.precond == 1) precond_scale(h, z, false);
     }
+    order_caller_after(h);
     return SDR_OK;  // queued on the handle's stream
   } catch (HipError& e) {
     return e.code;
