@@ -1846,6 +1846,12 @@ constexpr int kMblkMaxWaves = 4;   // waves of the in-block kernels
 constexpr int kMblkHeadThreads = 1024;
 constexpr int kMblkSweepThreads = 1024;
 constexpr int kMblkSweepWaves = kMblkSweepThreads / 64;
+// LDS of the in-block kernels' shared buffer: the Gram staging (waves x 36
+// pairs x 2 parts x 8 groups) or the cross-wave sums (2 x kMblkSweepWaves x
+// 32) with the per-wave wave_sums scratch (16 x 33), whichever is larger
+constexpr int kMblkPool = (kMblkMaxWaves * 36 * 2 * 8 > 2 * kMblkSweepWaves * 32 + kMblkMaxWaves * 16 * 33)
+                              ? kMblkMaxWaves * 36 * 2 * 8
+                              : 2 * kMblkSweepWaves * 32 + kMblkMaxWaves * 16 * 33;
 
 // Workgroup sums of NV per-lane values: every thread gets every sum, the same
 // bits on every call.  Wave sums first; with nw > 1 waves the wave sums are
@@ -2011,8 +2017,8 @@ __device__ __forceinline__ cx<double> read_lane_v(cx<double> v, int l) { return 
 
 // Cholesky QR of the register block, the in-block factorisation when the
 // block is well conditioned: G = X^H X (each pair's lane sums added over
-// quads by DPP, then through LDS, gbuf: nw x 36 x 2 x 16 doubles, by lane
-// (a, b) of each wave in a fixed order), G = Rm^H Rm, X <- X Rm^-1 row by
+// groups of eight lanes by DPP, then through LDS, gbuf: nw x 36 x 2 x 8
+// doubles, by lane (a, b) of each wave in a fixed order), G = Rm^H Rm, X <- X Rm^-1 row by
 // row.  Inside block Gram-Schmidt with
 // reorthogonalisation this is as stable as CGS2 while the block's condition
 // number stays far below eps^(-1/2); a pivot below 1e-8 of its diagonal
@@ -2027,7 +2033,8 @@ __device__ bool mblk_cholqr(A (&X)[kBlkCols][RPL], int nb, A* Rm, double* gbuf) 
   constexpr int NC = ncomp<A>::v;
   constexpr int NP = kBlkCols * (kBlkCols + 1) / 2;  // pairs i <= j
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  // each pair's lane sums, added over quads (DPP), into gbuf[wave][pair][part][quad]
+  // each pair's lane sums, added over groups of eight lanes (DPP), into
+  // gbuf[wave][pair][part][group]
   {
     int p = 0;
 #pragma unroll
@@ -2043,7 +2050,8 @@ __device__ bool mblk_cholqr(A (&X)[kBlkCols][RPL], int nb, A* Rm, double* gbuf) 
         for (int h = 0; h < NC; ++h) {
           t[h] += dpp_mov<0xB1>(t[h]);
           t[h] += dpp_mov<0x4E>(t[h]);
-          if ((lane & 3) == 0) gbuf[((wv * NP + p) * NC + h) * 16 + (lane >> 2)] = t[h];
+          t[h] += dpp_mov<0x141>(t[h]);
+          if ((lane & 7) == 0) gbuf[((wv * NP + p) * NC + h) * 8 + (lane >> 3)] = t[h];
         }
       }
   }
@@ -2059,9 +2067,10 @@ __device__ bool mblk_cholqr(A (&X)[kBlkCols][RPL], int nb, A* Rm, double* gbuf) 
 #pragma unroll
       for (int h = 0; h < NC; ++h)
 #pragma unroll
-        for (int q = 0; q < 16; ++q) t[h] += gbuf[((w * NP + p) * NC + h) * 16 + q];
+        for (int q = 0; q < 8; ++q) t[h] += gbuf[((w * NP + p) * NC + h) * 8 + q];
     join_re(g, t);
   }
+  __syncthreads();  // (gbuf's buffer is the sums' scratch of what follows)
   if (ra >= nb || cb >= nb) {
     g = zero<A>();
     if (ra == cb) *(double*)&g = 1.0;
@@ -2351,11 +2360,13 @@ __global__ __launch_bounds__(kMblkSweepThreads) void k_mblk_upd(const A* __restr
 template <class A, int RPL>
 __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_qr(LsqState<A> S, int nb, int s) {
   if (S.ctrl->halt) return;
-  __shared__ double scr_all[kMblkMaxWaves * 16 * 33];
-  __shared__ double xs[2 * kMblkSweepWaves * 32];
-  __shared__ double gbuf[kMblkMaxWaves * 36 * 2 * 16];
-  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
-  double* scr = scr_all + wv * 16 * 33;
+  // the Gram staging of the Cholesky QR and the sums' scratch of the CGS2
+  // fallback share one buffer: they are never live together
+  __shared__ double pool[kMblkPool];
+  double* gbuf = pool;
+  double* xs = pool;
+  double* scr = pool + 2 * kMblkSweepWaves * 32 + (threadIdx.x >> 6) * 16 * 33;
+  const int nw = blockDim.x >> 6;
   A X[kBlkCols][RPL];
 #pragma unroll
   for (int u = 0; u < RPL; ++u) {
@@ -2387,9 +2398,9 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, 
   if (S.ctrl->halt) return;
   constexpr int NC = ncomp<A>::v;
   const BlkWork<A> B = S.bw;
-  __shared__ double scr_all[kMblkMaxWaves * 16 * 33];
-  __shared__ double xs[2 * kMblkSweepWaves * 32];
-  __shared__ double gbuf[kMblkMaxWaves * 36 * 2 * 16];
+  __shared__ double pool[kMblkPool];  // (the Gram staging, then the sums' scratch)
+  double* gbuf = pool;
+  double* xs = pool;
   __shared__ A R1[kBlkCols * kBlkCols], R2[kBlkCols * kBlkCols], RB[kBlkCols * kBlkCols];
   __shared__ A hcs[kBlkCols * (kMaxWindow + 1)];
   __shared__ double nujs[kBlkCols], n0s[kBlkCols];
@@ -2397,7 +2408,7 @@ __global__ __launch_bounds__(64 * kMblkMaxWaves) void k_mblk_fin(LsqState<A> S, 
   __shared__ int sh_halt;  // the last finished step of the block
   __shared__ Ctrl cl;
   const int tid = threadIdx.x, nw = blockDim.x >> 6, wv = tid >> 6;
-  double* scr = scr_all + wv * 16 * 33;
+  double* scr = pool + 2 * kMblkSweepWaves * 32 + wv * 16 * 33;
   if (tid < kBlkCols * (kMaxWindow + 1)) hcs[tid] = B.hc[tid];
   if (tid < kBlkCols) {
     nujs[tid] = B.nuj[tid];
