@@ -3042,22 +3042,22 @@ void launch_gemv_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, c
 // ||rnew||^2 into row 0.
 template <class A>
 __device__ __forceinline__ void store_residual_partials(A* __restrict__ part, int s, double nrm,
-                                                        const A* bins_all, A* red) {
+                                                        const A* bins_all, A* red, int tile) {
   const double sum = block_sum(nrm, (double*)red);  // (its barriers also complete the bins)
   for (int i = threadIdx.x; i < s; i += kBlock) {
     A t = bins_all[i];
     for (int q = 1; q < kWaves; ++q) t += bins_all[q * s + i];
-    part[(int64_t)i * gridDim.x + blockIdx.x] = t;
+    part[(int64_t)i * gridDim.x + tile] = t;
   }
   if (threadIdx.x == 0) {
     A v = zero<A>();
     *(double*)&v = sum;
-    part[(int64_t)s * gridDim.x + blockIdx.x] = v;
+    part[(int64_t)s * gridDim.x + tile] = v;
   }
 }
 
 // rnew = r0 - A x over CSR (full-precision values), partial ||rnew||^2 per
-// block; with sk.s > 0 also the partial sketch of rnew, so that the next
+// row tile; with sk.s > 0 also the partial sketch of rnew, so that the next
 // cycle's S r0 needs no pass of its own.
 template <class A>
 __global__ __launch_bounds__(kBlock) void k_spmv_residual(int n, const int* __restrict__ rp,
@@ -3074,7 +3074,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_residual(int n, const int* __re
   A* bins = bins_all + (threadIdx.x >> 6) * s;
   for (int i = threadIdx.x & 63; i < s; i += 64) bins[i] = zero<A>();
   double nrm = 0.0;
-  const int b0 = blockIdx.x * kRowsUpdate;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);  // partial sums are stored by tile
+  const int b0 = tile * kRowsUpdate;
   const int b1 = min(n, b0 + kRowsUpdate);
   for (int r = b0 + (int)threadIdx.x; r < b1; r += kBlock) {
     A acc = zero<A>();
@@ -3085,7 +3086,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_residual(int n, const int* __re
     if (s > 0) sketch_scatter(bins, r, v, sk);
     nrm += abs2(v);
   }
-  store_residual_partials(part, s, nrm, bins_all, red);
+  store_residual_partials(part, s, nrm, bins_all, red, tile);
 }
 
 // rnew = r0 - A x over the diagonal storage (values in the accumulation
@@ -3104,7 +3105,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_residual(int n, DiaView<A> 
   for (int i = threadIdx.x & 63; i < s; i += 64) bins[i] = zero<A>();
   const int nd = ND > 0 ? ND : M.ndiag;
   double nrm = 0.0;
-  const int b0 = blockIdx.x * kRowsUpdate;
+  // tiles XCD-aware, so that the +-n halo rows of x are in the L2 of the
+  // XCD that works on the neighbouring tiles
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);  // partial sums are stored by tile
+  const int b0 = tile * kRowsUpdate;
   const int b1 = min(n, b0 + kRowsUpdate);
   for (int r = b0 + (int)threadIdx.x; r < b1; r += kBlock) {
     A vv[KD], xc[KD];
@@ -3130,7 +3134,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_residual(int n, DiaView<A> 
     if (s > 0) sketch_scatter(bins, r, v, sk);
     nrm += abs2(v);
   }
-  store_residual_partials(part, s, nrm, bins_all, red);
+  store_residual_partials(part, s, nrm, bins_all, red, tile);
 }
 
 template <class A>
