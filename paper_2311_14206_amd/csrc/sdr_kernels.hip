@@ -3208,6 +3208,75 @@ __global__ __launch_bounds__(kBlock) void k_gemm_basis(int n, const T* __restric
   }
 }
 
+// Real data: two adjacent rows per thread, one two-wide load per column, so
+// each scalar entry of G feeds two multiply-adds and fewer rows of G are held
+// at once (no scalar-register spills at KM <= 24).  Each row's sum is formed
+// in column order as in k_gemm_basis, with the same bits.  Requires n, the
+// leading dimensions and the base addresses even (two-element aligned).
+template <class T> struct pair2;
+template <> struct pair2<double> { using type = double2; };
+template <> struct pair2<float> { using type = float2; };
+
+template <class T, int KM>
+__global__ __launch_bounds__(kBlock) void k_gemm_basis2(int n, const T* __restrict__ U, int64_t ldu,
+                                                        int ku, const T* __restrict__ P, int64_t ldp,
+                                                        int jp, const double* __restrict__ G, int ldg,
+                                                        int kc, T* __restrict__ C, int64_t ldc) {
+  using T2 = typename pair2<T>::type;
+  const int l0 = ku + jp;
+  // one pass: the grid covers the rows (a loop over the grid kept more
+  // scalar registers live and spilled)
+  const int r = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (r >= n) return;
+  {
+    double a0[KM], a1[KM];
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+      a0[c] = 0.0;
+      a1[c] = 0.0;
+    }
+    int i = 0;
+    for (; i + 2 <= l0; i += 2) {
+      T2 v[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int ii = i + u;
+        const T* src = ii < ku ? U + ii * ldu : P + (int64_t)(ii - ku) * ldp;
+        v[u] = *reinterpret_cast<const T2*>(src + r);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double* g = G + (int64_t)(i + u) * ldg;
+        const double x0 = widen(v[u].x), x1 = widen(v[u].y);
+#pragma unroll
+        for (int c = 0; c < KM; ++c) {
+          a0[c] += x0 * g[c];
+          a1[c] += x1 * g[c];
+        }
+      }
+    }
+    for (; i < l0; ++i) {
+      const T* src = i < ku ? U + i * ldu : P + (int64_t)(i - ku) * ldp;
+      const T2 v = *reinterpret_cast<const T2*>(src + r);
+      const double* g = G + (int64_t)i * ldg;
+      const double x0 = widen(v.x), x1 = widen(v.y);
+#pragma unroll
+      for (int c = 0; c < KM; ++c) {
+        a0[c] += x0 * g[c];
+        a1[c] += x1 * g[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+      if (c < kc) {
+        T2 o;
+        o.x = narrow<T>(a0[c]);
+        o.y = narrow<T>(a1[c]);
+        *reinterpret_cast<T2*>(C + r + c * ldc) = o;
+      }
+  }
+}
+
 // C = [U P] G on the matrix cores (v_mfma_f64_16x16x4f64: a 16 x 4 block of
 // A times a 4 x 16 block of B added to a 16 x 16 block, 64 lanes).  G, l0 x
 // kc (l0 = ku + jp), is staged once per workgroup into LDS, as real and
@@ -3426,6 +3495,33 @@ void launch_gemm_basis(hipStream_t st, int n, const T* U, int64_t ldu, int ku, c
                            P, ldp, jp, G + c0, ldg, cc, C + (int64_t)c0 * ldc, ldc);
     }
     return;
+  }
+  // real data, even sizes and two-element aligned columns: two rows per
+  // thread while the accumulators fit (output columns in launches of at most
+  // 24)
+  if constexpr (!traits<T>::cpx) {
+    auto even2 = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % (2 * sizeof(T)) == 0; };
+    if (n % 2 == 0 && ldu % 2 == 0 && ldp % 2 == 0 && ldc % 2 == 0 && even2(U) && even2(P) && even2(C)) {
+      const int nb2 = (n / 2 + kBlock - 1) / kBlock;
+      for (int c0 = 0; c0 < kc; c0 += 24) {
+        const int cc = std::min(24, kc - c0);
+        const auto* Gc = G + c0;
+        T* Cc = C + (int64_t)c0 * ldc;
+        if (cc <= 8)
+          hipLaunchKernelGGL((k_gemm_basis2<T, 8>), dim3(nb2), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp, jp,
+                             Gc, ldg, cc, Cc, ldc);
+        else if (cc <= 16)
+          hipLaunchKernelGGL((k_gemm_basis2<T, 16>), dim3(nb2), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp,
+                             jp, Gc, ldg, cc, Cc, ldc);
+        else if (cc <= 20)
+          hipLaunchKernelGGL((k_gemm_basis2<T, 20>), dim3(nb2), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp,
+                             jp, Gc, ldg, cc, Cc, ldc);
+        else
+          hipLaunchKernelGGL((k_gemm_basis2<T, 24>), dim3(nb2), dim3(kBlock), 0, st, n, U, ldu, ku, P, ldp,
+                             jp, Gc, ldg, cc, Cc, ldc);
+      }
+      return;
+    }
   }
   // output columns in launches of at most 32 (the padded row width covers
   // the last one)
