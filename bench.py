@@ -647,6 +647,99 @@ def ilu_bench(dev, reps=2):
     return out
 
 
+def differentiated_bench(dev):
+    """The differentiated solve on the theta-weighted 512^2 convection-diffusion
+    operator: gradient-descent steps on ||x(theta) - x_t||^2, each a forward
+    and an adjoint GMRES-SDR solve (the adjoint's recycle space carried from
+    step to step, S A^T U recomputed for each theta) plus the gradient kernel.
+    Reports seconds per gradient step, the Arnoldi steps and matrix-vector
+    products of both solves, and the gradient at the final theta against a
+    sparse direct solve (SuperLU factors of A(theta), solves with A and A^T)."""
+    import numpy as np
+    import scipy.sparse.linalg as spl
+    import torch
+    from paper_2311_14206_amd.autograd import sdr_solve as solve_ad
+    from paper_2311_14206_amd.sdr import SDRSolver
+    from workloads import describe, edge_weighted, randn, workload
+
+    name = "cd2d_512_theta"
+    A, b, p = workload(name)
+    A0, theta0 = p["A0"], p["theta"]
+    xt = randn(A.n, p["xt_seed"])
+
+    def dv(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    h = SDRSolver(dv(A.row_ptr), dv(A.col_idx), dv(A.values), m=p["m"], k=p["k"], t=p["t"], s=p["s"],
+                  seed=p["s_seed"], zeta=p["zeta"])
+    rows = np.repeat(np.arange(A0.n), np.diff(A0.row_ptr))
+    on = rows == A0.col_idx
+    a0, offm = dv(A0.values), dv((~on).astype(np.float64))
+    rows_t, diag_pos = dv(rows.astype(np.int64)), dv(np.nonzero(on)[0].astype(np.int64))
+
+    def values_of(theta):
+        """The edge-weighted entries of the workload as a torch function of theta:
+        theta_e a_e off the diagonal, a_ii + sum_j (1 - theta_ij) a_ij on it."""
+        shift = torch.zeros(A0.n, dtype=a0.dtype, device=a0.device).index_add(
+            0, rows_t, (a0 - theta * a0) * offm)
+        return theta * a0 * offm + a0 * (1 - offm) + torch.zeros_like(a0).index_add(0, diag_pos, shift)
+
+    tol = p["tol"]
+    bb, xtd = dv(b), dv(xt)
+
+    def grad_step(th):
+        x = solve_ad(values_of(th), bb, h, tol)
+        loss = torch.sum((x - xtd) ** 2)
+        loss.backward()
+        return float(loss.detach())
+
+    warm = dv(theta0).requires_grad_(True)
+    grad_step(warm)  # warm-up, then both recycle spaces dropped
+    h.reset()
+    th = dv(theta0).requires_grad_(True)
+    losses, times, fw, ad = [], [], [], []
+    eta = None
+    for _ in range(p["gd_steps"]):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses.append(grad_step(th))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        fw.append(h.last_forward_stats)
+        ad.append(h.last_adjoint_stats)
+        with torch.no_grad():
+            if eta is None:
+                eta = 1e-3 / float(th.grad.abs().max())
+            th -= eta * th.grad
+        th.grad = None
+    # the gradient at the final theta against the sparse direct one
+    th_np = th.detach().cpu().numpy()
+    thr = dv(th_np).requires_grad_(True)
+    loss_f = grad_step(thr)
+    g = thr.grad.detach().cpu().numpy()
+    lu = spl.splu(edge_weighted(A0, th_np).to_scipy().tocsc())
+    xr = lu.solve(b)
+    lam = lu.solve(2.0 * (xr - xt), trans="T")
+    gr = np.where(on, 0.0, A0.values * (-lam[rows] * xr[A0.col_idx] + lam[rows] * xr[rows]))
+    lr = float(np.sum((xr - xt) ** 2))
+    gerr = float(np.linalg.norm(g - gr) / np.linalg.norm(gr))
+    out = {"workload": describe(name) + f", x_t~N(0,1) seed {p['xt_seed']}; loss ||x(theta) - x_t||^2",
+           "m": p["m"], "k": p["k"], "t": p["t"], "s": p["s"], "tol": tol, "gd_steps": p["gd_steps"],
+           "seconds_per_gradient_step": statistics.median(times),
+           "seconds_total": sum(times),
+           "forward_iters": [f["iters"] for f in fw], "adjoint_iters": [a["iters"] for a in ad],
+           "forward_matvecs_total": sum(f["matvecs"] for f in fw),
+           "adjoint_matvecs_total": sum(a["matvecs"] for a in ad),
+           "loss_first": losses[0], "loss_last": losses[-1],
+           "final_theta": {"loss": loss_f, "loss_direct": lr, "gradient_rel_err_vs_direct": gerr,
+                           "reference": "SuperLU factors of A(theta): x and the adjoint from direct solves"}}
+    print(f"[bench] differentiated cd2d_512: {statistics.median(times):.3f} s per gradient step, "
+          f"loss {losses[0]:.4e} -> {losses[-1]:.4e}, adjoint steps {ad[0]['iters']} ... {ad[-1]['iters']}, "
+          f"gradient error vs direct {gerr:.1e}", file=sys.stderr, flush=True)
+    h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -832,6 +925,8 @@ def main():
         line["srdct"] = srdct_bench(dev, with_oracle=not args.no_cpu_baseline)
         torch.cuda.empty_cache()
         line["ilu"] = ilu_bench(dev)
+        torch.cuda.empty_cache()
+        line["differentiated"] = differentiated_bench(dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(A, b, p, st["iters"])

@@ -298,7 +298,8 @@ int sdr_get_basis(sdr_handle* h, int ncols, void* V, void* H_host, void* SV_host
  * count (j_stop + 1; 0 before the first solve). */
 int sdr_get_step_sres(sdr_handle* h, double* out, int cap);
 
-/* Drop the recycle space (the next solve starts without U).  Returns 0. */
+/* Drop the recycle spaces of the forward and the adjoint solver (the next
+ * solve of either starts without U).  Returns 0. */
 int sdr_reset(sdr_handle* h);
 
 /*

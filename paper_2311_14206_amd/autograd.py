@@ -26,6 +26,7 @@ class SDRSolve(torch.autograd.Function):
         x, st = solver.solve(b.detach().contiguous(), tol=tol)
         if not st["converged"]:
             raise RuntimeError(f"forward GMRES-SDR solve did not converge: {st}")
+        solver.last_forward_stats = st
         ctx.solver = solver
         ctx.generation = solver.generation
         ctx.adj_tol = tol if adj_tol is None else adj_tol
