@@ -685,13 +685,33 @@ class Solver final : public SolverBase {
 
   // Queue the rest of the cycle from step j0: the Arnoldi steps (with
   // events at chunk ends) and the least-squares chunks behind them.
+  // Chunks whose steps the chain has already finished (their events are
+  // complete when queued, as after a late eigen-step) share one reduction
+  // launch: the same sums per step, one bandwidth-bound pass instead of a
+  // latency-bound launch per chunk.
   void enqueue_from(int j0, int& enqA, const T* vals) {
     const int base = j0;
     while (enqA < m_ + 1) {
       ++enqA;
       enqueue_step_a(enqA, vals, needs_event(enqA, base));
     }
-    for (int c0 = j0; c0 <= m_; c0 += opt_.lsq_chunk) enqueue_chunk(c0, std::min(c0 + opt_.lsq_chunk - 1, m_));
+    int done_to = j0 - 1;
+    for (int c0 = j0; c0 <= m_; c0 += opt_.lsq_chunk) {
+      const int c1 = std::min(c0 + opt_.lsq_chunk - 1, m_);
+      if (hipEventQuery(evs_[(c1 + 1) % nslot_]) != hipSuccess) break;
+      done_to = c1;
+    }
+    int c0 = j0;
+    if (done_to > j0) {
+      HIPCHK(hipStreamWaitEvent(streamB_, evs_[(done_to + 1) % nslot_], 0));  // (complete: no wait)
+      launch_reduce_steps<A>(streamB_, part1_, (int64_t)slot1_, nb1_, s_, j0, done_to, t_, nslot_, sk_scl_,
+                             redb_, (int64_t)slotr_, ctrl_);
+      for (; c0 <= done_to; c0 += opt_.lsq_chunk)
+        launch_lsq_steps<A>(streamB_, lsq(), c0, std::min(c0 + opt_.lsq_chunk - 1, m_), khat_, m_, t_, s_, redb_,
+                            (int64_t)slotr_, nslot_, brtol_, opt_.rank_rtol, opt_.lsq_kernel);
+      LAUNCHCHK();
+    }
+    for (; c0 <= m_; c0 += opt_.lsq_chunk) enqueue_chunk(c0, std::min(c0 + opt_.lsq_chunk - 1, m_));
   }
 
   // y = R^{-1} z for the leading (khat + j) block; coefficients of the stored
