@@ -685,31 +685,63 @@ void launch_reduce2(hipStream_t st, const A* pa, int nba, int ca, int nscaled, d
                      nbb, out, ctrl);
 }
 
+// col_sum of one column by a single wave: lane l stands in for the threads
+// l, l + 64, l + 128 and l + 192 of a kBlock-thread block, each accumulating
+// its partials in col_sum's order; the four wave sums are then added in wave
+// order, as block_sum adds them.  The same bits as col_sum, with no LDS and
+// no barrier.
+template <class A>
+__device__ __forceinline__ A col_sum_wave(const A* __restrict__ part, int nb, int col) {
+  static_assert(kBlock == 4 * 64, "four waves per block");
+  const int lane = threadIdx.x & 63;
+  const A* p = part + (int64_t)col * nb;
+  A acc[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) acc[w] = zero<A>();
+  for (int i0 = lane; i0 < nb; i0 += 4 * kBlock) {
+    A v[4][4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[w][u] = p[min(i0 + 64 * w + u * kBlock, nb - 1)];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + 64 * w + u * kBlock < nb) acc[w] += v[w][u];
+  }
+  A sum = wave_sum(acc[0]);
+#pragma unroll
+  for (int w = 1; w < 4; ++w) sum += wave_sum(acc[w]);
+  return sum;
+}
+
 // Reduced inputs of the least squares of steps j0 .. j0 + gridDim.y - 1, each
 // into its slot of redb: [S p_j (s, scaled), ||p_j||^2] from the SpMV
 // partials of step j+1, then the window products and ||w||^2 of step j.
-// One block per (column, step), the same fixed order as k_reduce2.
+// One wave per (column, step), four columns per block, each sum in the fixed
+// order of col_sum (the order the update kernel uses for the same values).
 template <class A>
 __global__ __launch_bounds__(kBlock) void k_reduce_steps(const A* __restrict__ part1, int64_t slot1,
                                                          int nb1, int s, int j0, int t, int nslot,
                                                          double scl, A* __restrict__ redb,
                                                          int64_t slotr, const Ctrl* __restrict__ ctrl) {
   if (ctrl->halt) return;
-  __shared__ A red[kWaves];
   const int j = j0 + (int)blockIdx.y;
   const int tw = j - (j - t > 0 ? j - t : 0);
-  const int col = blockIdx.x;
-  if (col >= s + 1 + tw + 1) return;
+  const int col = (int)blockIdx.x * kWaves + ((int)threadIdx.x >> 6);
+  if (col >= s + 1 + tw + 1) return;  // (whole waves)
   const A* pa = part1 + slot1 * ((j + 1) % nslot);
   const A* pb = part1 + slot1 * (j % nslot) + (int64_t)(s + 1) * nb1;
-  const A sum = col < s + 1 ? col_sum(pa, nb1, col, red) : col_sum(pb, nb1, col - (s + 1), red);
-  if (threadIdx.x == 0) redb[slotr * (j % nslot) + col] = col < s ? scale(sum, scl) : sum;
+  const A sum = col < s + 1 ? col_sum_wave(pa, nb1, col) : col_sum_wave(pb, nb1, col - (s + 1));
+  if ((threadIdx.x & 63) == 0) redb[slotr * (j % nslot) + col] = col < s ? scale(sum, scl) : sum;
 }
 
 template <class A>
 void launch_reduce_steps(hipStream_t st, const A* part1, int64_t slot1, int nb1, int s, int j0, int j1,
                          int t, int nslot, double scl, A* redb, int64_t slotr, const Ctrl* ctrl) {
-  hipLaunchKernelGGL(k_reduce_steps<A>, dim3(s + 1 + kMaxWindow + 1, j1 - j0 + 1), dim3(kBlock), 0, st,
+  const int ncol = s + 1 + kMaxWindow + 1;
+  hipLaunchKernelGGL(k_reduce_steps<A>, dim3((ncol + kWaves - 1) / kWaves, j1 - j0 + 1), dim3(kBlock), 0, st,
                      part1, slot1, nb1, s, j0, t, nslot, scl, redb, slotr, ctrl);
 }
 
