@@ -18,7 +18,8 @@ constexpr int kRowsSpmv = 1536;    // rows per tile, SpMV + window products + sk
 constexpr int kSpmvThreads = 512;  // threads of the diagonal-storage SpMV (3 rows each); 256 when
                                    // 8 waves of sketch bins exceed kSpmvLds
 constexpr int kRowsUpdate = 2048;  // rows per block of the other streaming kernels
-constexpr int kUpdateRows = 8;     // rows per thread of the update (a tile of 2048 rows)
+constexpr int kUpdateRows = 8;     // rows per thread of the update
+constexpr int kUpdateThreads = 512;  // threads per update block for complex data (4096 rows)
 constexpr int kPartRounds = 3;     // SpMV partials per thread the update loads up front (768 tiles)
 constexpr int kWaveTileNnz = 512;  // largest staged chunk (entries of 64 rows) per wave of the SpMV
 constexpr int kSpmvLds = 64 * 1024;  // LDS budget of the SpMV kernel: sketch bins + staged chunks

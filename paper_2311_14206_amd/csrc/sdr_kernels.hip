@@ -520,31 +520,38 @@ void launch_pack_dia(hipStream_t st, int64_t nnz, const typename traits<T>::acc*
 // uses.  Then p_j = (w - sum c_q p_q) / nu_{j-1} in place with
 // c_q = <p_q, w> / nu_q^2: a pure stream over w and the window vectors, each
 // thread with kUpdateRows independent rows in flight.
-template <class T, int TWM, int UR>  // TWM: bound on the window length tw; UR rows per thread
-__global__ __launch_bounds__(kBlock) void k_update(
+// NT threads per block (a multiple of kBlock): the first kBlock threads form
+// the sums exactly as a kBlock-thread block would, so the bits do not depend
+// on NT; a larger block repeats that reduction for fewer blocks.
+template <class T, int TWM, int UR, int NT>  // TWM: bound on the window length tw; UR rows per thread
+__global__ __launch_bounds__(NT) void k_update(
     int n, T* __restrict__ w, Window<T> win, int tw, const typename traits<T>::acc* __restrict__ part,
     int nb1, int s, double* __restrict__ nu, int i0, int jprev, const Ctrl* __restrict__ ctrl) {
   using A = typename traits<T>::acc;
+  static_assert(NT % kBlock == 0, "NT");
   constexpr int NC = TWM + 1;
   const int halted = ctrl->halt;  // tested once the loads below are out
   __shared__ A red[NC * kWaves];
+  const bool reducer = threadIdx.x < kBlock;  // (whole waves)
   // This step's partial sums (columns s .. s + tw, L2-resident) are loaded
   // first: their values return ahead of the stream loads issued after them,
   // so the block's reduction runs while the stream is still in flight.
   const A* pp = part + (int64_t)s * nb1;
   const int nc = tw + 1;
   A pv0[kPartRounds][NC];  // columns past nc re-read column nc - 1 and are not added
+  if (reducer) {
 #pragma unroll
-  for (int u = 0; u < kPartRounds; ++u) {
-    const int i = min((int)threadIdx.x + u * kBlock, nb1 - 1);
+    for (int u = 0; u < kPartRounds; ++u) {
+      const int i = min((int)threadIdx.x + u * kBlock, nb1 - 1);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) pv0[u][c] = pp[(int64_t)min(c, nc - 1) * nb1 + i];
+      for (int c = 0; c < NC; ++c) pv0[u][c] = pp[(int64_t)min(c, nc - 1) * nb1 + i];
+    }
   }
-  const int base = xcd_tile(blockIdx.x, gridDim.x) * (kBlock * UR) + (int)threadIdx.x;
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * (NT * UR) + (int)threadIdx.x;
   T wv[UR], pv[UR][TWM];
 #pragma unroll
   for (int u = 0; u < UR; ++u) {
-    const int r = min(base + u * kBlock, n - 1);
+    const int r = min(base + u * NT, n - 1);
     wv[u] = w[r];
 #pragma unroll
     for (int q = 0; q < TWM; ++q)
@@ -554,40 +561,44 @@ __global__ __launch_bounds__(kBlock) void k_update(
 #pragma unroll
   for (int q = 0; q < TWM; ++q) nqv[q] = (q < tw && i0 + q != jprev) ? nu[i0 + q] : 1.0;
   if (halted) return;
-  // column sums in the order of col_sum: each thread adds partials
+  // column sums in the order of col_sum: each reducer thread adds partials
   // threadIdx.x, + kBlock, + 2 kBlock, ... in increasing order, then the
   // waves in order (the grouping of the loads into rounds does not change it)
   A sums[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) sums[c] = zero<A>();
+  if (reducer) {
 #pragma unroll
-  for (int u = 0; u < kPartRounds; ++u)
-    if ((int)threadIdx.x + u * kBlock < nb1)
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (c < nc) sums[c] += pv0[u][c];
-  for (int j0 = (int)threadIdx.x + kPartRounds * kBlock; j0 < nb1; j0 += 4 * kBlock) {
-    A v[4][NC];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = min(j0 + u * kBlock, nb1 - 1);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) v[u][c] = pp[(int64_t)min(c, nc - 1) * nb1 + i];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (j0 + u * kBlock < nb1)
+    for (int u = 0; u < kPartRounds; ++u)
+      if ((int)threadIdx.x + u * kBlock < nb1)
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-          if (c < nc) sums[c] += v[u][c];
+          if (c < nc) sums[c] += pv0[u][c];
+    for (int j0 = (int)threadIdx.x + kPartRounds * kBlock; j0 < nb1; j0 += 4 * kBlock) {
+      A v[4][NC];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = min(j0 + u * kBlock, nb1 - 1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[u][c] = pp[(int64_t)min(c, nc - 1) * nb1 + i];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j0 + u * kBlock < nb1)
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            if (c < nc) sums[c] += v[u][c];
+    }
   }
   {
     const int lane = threadIdx.x & 63, wv_ = threadIdx.x >> 6;
+    if (reducer) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) sums[c] = wave_sum(sums[c]);
-    if (lane == 0)
+      for (int c = 0; c < NC; ++c) sums[c] = wave_sum(sums[c]);
+      if (lane == 0)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) red[c * kWaves + wv_] = sums[c];
+        for (int c = 0; c < NC; ++c) red[c * kWaves + wv_] = sums[c];
+    }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -611,7 +622,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
   const double inv = 1.0 / nprev;
 #pragma unroll
   for (int u = 0; u < UR; ++u) {
-    const int r = base + u * kBlock;
+    const int r = base + u * NT;
     if (r < n) {
       A v = widen(wv[u]);
 #pragma unroll
@@ -626,19 +637,27 @@ template <class T>
 void launch_update(hipStream_t st, int n, T* w, Window<T> win, int tw,
                    const typename traits<T>::acc* part, int nb1, int s, double* nu, int i0, int jprev,
                    const Ctrl* ctrl, hipEvent_t e0, hipEvent_t e1) {
-  const int nb = (n + kBlock * kUpdateRows - 1) / (kBlock * kUpdateRows);
   // the window bound as a template parameter: a short window's rows take no
-  // registers (t = 3, the complex workload's, is the common longer one)
+  // registers (t = 3, the complex workload's, is the common longer one).
+  // Complex data take kUpdateThreads threads per block (half the blocks
+  // repeat the reduction of the step's partials: 14.98-15.16 us against
+  // 15.84 us per complex128 update at 1024^2); real data keep kBlock, where
+  // the larger block was slower (6.7-6.8 against 6.2-6.6 us); the longest
+  // window keeps kBlock too (its complex rows would spill at two waves per
+  // SIMD)
+  constexpr int NT = traits<T>::cpx ? kUpdateThreads : kBlock;
+  const int nt = tw <= 3 ? NT : kBlock;
+  const int nb = (n + nt * kUpdateRows - 1) / (nt * kUpdateRows);
   void (*kern)(int, T*, Window<T>, int, const typename traits<T>::acc*, int, int, double*, int, int,
-               const Ctrl*) = tw <= 1   ? k_update<T, 1, kUpdateRows>
-                              : tw <= 2 ? k_update<T, 2, kUpdateRows>
-                              : tw <= 3 ? k_update<T, 3, kUpdateRows>
-                                        : k_update<T, kMaxWindow, kUpdateRows>;
+               const Ctrl*) = tw <= 1   ? k_update<T, 1, kUpdateRows, NT>
+                              : tw <= 2 ? k_update<T, 2, kUpdateRows, NT>
+                              : tw <= 3 ? k_update<T, 3, kUpdateRows, NT>
+                                        : k_update<T, kMaxWindow, kUpdateRows, kBlock>;
   if (e0)
-    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, e0, e1, 0, n, w, win, tw, part, nb1, s, nu,
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(nt), 0, st, e0, e1, 0, n, w, win, tw, part, nb1, s, nu,
                           i0, jprev, ctrl);
   else
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, n, w, win, tw, part, nb1, s, nu, i0, jprev,
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(nt), 0, st, n, w, win, tw, part, nb1, s, nu, i0, jprev,
                        ctrl);
 }
 
