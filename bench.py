@@ -78,8 +78,16 @@ def spmv_sketch_bytes(N, nnz, tw, p=8, pv=8):
 
 def spmv_dia_sketch_bytes(N, ndiag, tw, p=8, pv=8):
     """The same for a matrix stored by diagonals: ndiag value streams of N
-    entries (zero padding included), no index arrays, then the vectors."""
+    entries (zero padding included), no index arrays, then the vectors.
+    ndiag counts the streams the kernel reads: a diagonal found constant is
+    passed to the kernel as a value and moves no bytes."""
     return ndiag * N * pv + p * N * (1 + max(tw - 1, 0) + 1)
+
+
+def read_diagonals(h):
+    """Value streams the step kernel reads: the stored diagonals less those
+    found constant."""
+    return len(h.spmv_layout()) - bin(h.const_diagonals()).count("1")
 
 
 def update_bytes(N, tw, p=8):
@@ -438,7 +446,7 @@ def sequence_bench(dev, with_oracle=True):
             xh = x.cpu().numpy()
             relres.append(float(np.linalg.norm(bi - Ai.to_scipy() @ xh) / np.linalg.norm(bi)))
         iters = [st["iters"] for st in sts]
-        rate = _step_kernel_rate(kt, A0.n, len(h.spmv_layout()), 8 if prec == 0 else 4,
+        rate = _step_kernel_rate(kt, A0.n, read_diagonals(h), 8 if prec == 0 else 4,
                                  8 if prec == 0 else 4)
         out[key] = {"solves_per_s": len(systems) / total, "seconds_total": total,
                     "steps_per_system": iters, "steps_system1": iters[0],
@@ -563,7 +571,7 @@ def helmholtz_bench(dev, with_oracle=True, reps=2):
         kt = h.kernel_times()
         xh = x.cpu().numpy()
         relres = float(np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b))
-        rate = _step_kernel_rate(kt, A.n, len(h.spmv_layout()), 16 if prec == 0 else 8,
+        rate = _step_kernel_rate(kt, A.n, read_diagonals(h), 16 if prec == 0 else 8,
                                  16 if prec == 0 else 8)
         out[key] = {"time_to_tol_s": statistics.median(times), "times": times, "iters": st["iters"],
                     "cycles": st["cycles"], "res_checks": st["res_checks"], "converged": st["converged"],
@@ -848,15 +856,20 @@ def main():
         # instantiation: <type, diagonals (0: any), window bound (2 for t <= 2, else 4),
         # threads (512 while 8 waves of FP64 sketch bins fit 64 KiB of LDS; else the
         # generic 256-thread one)
+        cm = h.const_diagonals()
         if 8 * (p["s"] + 6) * 8 <= 64 * 1024:
+            # (last parameter: the constant-diagonal instantiation)
+            cmv = "true" if cm and len(layout) in (5, 7) and p["t"] <= 3 else "false"
             k1_key = (f"k_spmv_dia_sketch<{tname}, {len(layout) if len(layout) in (3, 5, 7, 9) else 0}, "
-                      f"{2 if p['t'] <= 2 else 3 if p['t'] == 3 else 4}, 512>")
+                      f"{2 if p['t'] <= 2 else 3 if p['t'] == 3 else 4}, 512, {cmv}>")
         else:
-            k1_key = f"k_spmv_dia_sketch<{tname}, 0, 4, 256>"
-        k1_bytes = sum(hist[tw] * spmv_dia_sketch_bytes(N, len(layout), tw, p=pb, pv=pb)
+            k1_key = f"k_spmv_dia_sketch<{tname}, 0, 4, 256, false>"
+        k1_bytes = sum(hist[tw] * spmv_dia_sketch_bytes(N, read_diagonals(h), tw, p=pb, pv=pb)
                        for tw in range(len(hist)))
+        const_note = (f"; {bin(cm).count('1')} constant diagonals passed as values, their streams "
+                      "not read nor counted") if cm else ""
         k1_name = (f"k_spmv_dia_sketch (stencil SpMV on {len(layout)} diagonals {layout} + "
-                   "truncation-window products + sparse-sign sketch of the input basis vector)")
+                   f"truncation-window products + sparse-sign sketch of the input basis vector{const_note})")
     else:
         k1_key = f"k_spmv_sketch<{tname}>"
         k1_bytes = sum(hist[tw] * spmv_sketch_bytes(N, nnz, tw, p=pb, pv=pb) for tw in range(len(hist)))

@@ -323,6 +323,20 @@ int sdr_kernel_times(sdr_handle* h, double* ms, int64_t* counts, int cap);
  */
 int sdr_spmv_layout(sdr_handle* h, int* offsets, int cap);
 
+/*
+ * Diagonals of that storage found constant when the matrix was last packed
+ * (every entry inside the matrix with the same bits, as in a constant-
+ * coefficient stencil): bit d set for diagonal d of sdr_spmv_layout's order.
+ * The step kernel takes their values from its arguments instead of reading
+ * them; the products are the same.  Option "dia_const": 1 on, 0 off; by
+ * default on for complex data and off for real data (whose step kernel at
+ * the 1024^2 stencil ran no faster without the streams).
+ * Packing happens at the first solve after the matrix is set or updated, so
+ * the mask describes the matrix of the last solve (0 before the first, or
+ * for CSR).  Negative: error code.
+ */
+int sdr_spmv_const_diagonals(sdr_handle* h);
+
 void sdr_destroy(sdr_handle* h);
 
 /* Message of the last error on this thread ("" if none). */

@@ -34,6 +34,11 @@ template <class T> struct DiaView {
   int ndiag;
   int off[kMaxDiag];
   const T* val;
+  // diagonals whose stored entries are one value wherever the diagonal lies
+  // in the matrix (bit d of cmask; the value in cval[d]): the step kernel
+  // takes that value from here instead of reading its stream
+  unsigned cmask;
+  T cval[kMaxDiag];
 };
 
 // Record of one Arnoldi step, written by the least-squares kernels with
@@ -136,6 +141,10 @@ void launch_spmv_dia_sketch(hipStream_t st, int n, DiaView<T> A, const T* x, T* 
 template <class T>
 void launch_pack_dia(hipStream_t st, int64_t nnz, const typename traits<T>::acc* src, const int* map,
                      T* dst);
+// Constant diagonals of a packed matrix: flags[d] = 1 and vals[d] = the value
+// when every entry of diagonal d inside the matrix has the same bits.
+template <class T>
+void launch_dia_const(hipStream_t st, int n, DiaView<T> M, int* flags, T* vals);
 
 // Prologue: nu[jprev] = ||p_jprev|| and d_q from this step's SpMV partials
 // (part, nb1 blocks, sketch length s: columns s, s+1 .. s+tw).  Then

@@ -376,7 +376,7 @@ void launch_spmv_sketch(hipStream_t st, int n, const int* rp, const int* ci, con
 // longer windows), so a short window's accumulators take no registers.  NT
 // threads per block (512: 8 waves, 3 rows each over a 1536-row tile; 256 when
 // 8 waves of sketch bins do not fit the LDS budget).
-template <class T, int ND, int TWM, int NT>
+template <class T, int ND, int TWM, int NT, bool CM = false>
 __global__ __launch_bounds__(NT) void k_spmv_dia_sketch(
     int n, DiaView<T> M, const T* __restrict__ x, T* __restrict__ w, Window<T> win, int tw, SketchSpec sk,
     int do_spmv, typename traits<T>::acc* __restrict__ part, int nb, const Ctrl* __restrict__ ctrl) {
@@ -418,7 +418,12 @@ __global__ __launch_bounds__(NT) void k_spmv_dia_sketch(
 #pragma unroll
       for (int k = 0; k < KD; ++k) {
         if (ND > 0 || k < nd) {
-          vv[k] = M.val[(int64_t)k * n + r];
+          // (CM: a constant diagonal's value from the kernel argument, its
+          // stream not read; the condition is the same for the whole grid)
+          if (CM && ((M.cmask >> k) & 1u))
+            vv[k] = M.cval[k];
+          else
+            vv[k] = M.val[(int64_t)k * n + r];
           xc[k] = x[min(max(r + M.off[k], 0), n - 1)];
         }
       }
@@ -467,7 +472,15 @@ void launch_spmv_dia_sketch(hipStream_t st, int n, DiaView<T> M, const T* x, T* 
   const size_t lds = (size_t)(nt / 64) * sb * sizeof(A);
   const int dsp = spmv ? 1 : 0;
   void (*kern)(int, DiaView<T>, const T*, T*, Window<T>, int, SketchSpec, int, A*, int, const Ctrl*);
-  if (!wide) {
+  if (wide && M.cmask != 0 && tw <= 3 && (M.ndiag == 5 || M.ndiag == 7)) {
+    // constant diagonals (the stencils of constant-coefficient operators)
+    if (tw <= 2)
+      kern = M.ndiag == 5 ? k_spmv_dia_sketch<T, 5, 2, kSpmvThreads, true>
+                          : k_spmv_dia_sketch<T, 7, 2, kSpmvThreads, true>;
+    else
+      kern = M.ndiag == 5 ? k_spmv_dia_sketch<T, 5, 3, kSpmvThreads, true>
+                          : k_spmv_dia_sketch<T, 7, 3, kSpmvThreads, true>;
+  } else if (!wide) {
     kern = k_spmv_dia_sketch<T, 0, kMaxWindow, kBlock>;
   } else if (tw <= 2) {
     switch (M.ndiag) {
@@ -512,6 +525,50 @@ template <class T>
 void launch_pack_dia(hipStream_t st, int64_t nnz, const typename traits<T>::acc* src, const int* map, T* dst) {
   const int nb = (int)std::min<int64_t>((nnz + kBlock - 1) / kBlock, 65536);
   hipLaunchKernelGGL(k_pack_dia<T>, dim3(nb > 0 ? nb : 1), dim3(kBlock), 0, st, nnz, src, map, dst);
+}
+
+// One block per diagonal: every entry inside the matrix (rows with
+// 0 <= r + off < n) compared bitwise with the first; the diagonal is constant
+// when none differs.  A diagonal with no entry inside the matrix is not.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dia_const(int n, DiaView<T> M, int* __restrict__ flags,
+                                                      T* __restrict__ vals) {
+  static_assert(sizeof(T) % sizeof(unsigned) == 0, "T");
+  constexpr int NW = (int)(sizeof(T) / sizeof(unsigned));
+  __shared__ int bad;
+  const int d = blockIdx.x;
+  const int off = M.off[d];
+  const int ra = off < 0 ? -off : 0, rb = off > 0 ? n - off : n;
+  if (threadIdx.x == 0) bad = ra < rb ? 0 : 1;
+  __syncthreads();
+  if (ra < rb) {
+    const T* v = M.val + (int64_t)d * n;
+    const T ref = v[ra];
+    unsigned rw[NW];
+    __builtin_memcpy(rw, &ref, sizeof(T));
+    int mine = 0;
+    for (int r = ra + (int)threadIdx.x; r < rb; r += kBlock) {
+      const T e = v[r];
+      unsigned ew[NW];
+      __builtin_memcpy(ew, &e, sizeof(T));
+#pragma unroll
+      for (int q = 0; q < NW; ++q) mine |= ew[q] != rw[q];
+    }
+    if (mine) bad = 1;  // (every writer stores 1)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      flags[d] = bad ? 0 : 1;
+      vals[d] = ref;
+    }
+  } else if (threadIdx.x == 0) {
+    flags[d] = 0;
+    vals[d] = T{};
+  }
+}
+
+template <class T>
+void launch_dia_const(hipStream_t st, int n, DiaView<T> M, int* flags, T* vals) {
+  hipLaunchKernelGGL(k_dia_const<T>, dim3(M.ndiag), dim3(kBlock), 0, st, n, M, flags, vals);
 }
 
 // ------------------------------------------- truncated orthogonalisation ---
@@ -4112,6 +4169,7 @@ void launch_ilu_mult(hipStream_t st, const IluView& v, const A* x, A* t, A* out)
                                           int, SketchSpec, bool, traits<T>::acc*, int,           \
                                           const Ctrl*, hipEvent_t, hipEvent_t);                  \
   template void launch_pack_dia<T>(hipStream_t, int64_t, const traits<T>::acc*, const int*, T*);   \
+  template void launch_dia_const<T>(hipStream_t, int, DiaView<T>, int*, T*);                       \
   template void launch_update<T>(hipStream_t, int, T*, Window<T>, int, const traits<T>::acc*, int, \
                                  int, double*, int, int, const Ctrl*, hipEvent_t, hipEvent_t);    \
   template void launch_sketch_cols<T>(hipStream_t, int, const T*, int64_t, int, SketchSpec,       \

@@ -92,6 +92,8 @@ struct Options {
                           // workgroup; 2: per step; 3: block over several workgroups
   int kernel_timing = 0;  // 0: off; n: time the SpMV and update kernels of every n-th step
   int dia = 1;            // 1: diagonal storage for stencil patterns; 0: always CSR
+  int dia_const = -1;     // 1: constant diagonals passed to the step kernel as values; 0: read;
+                          // -1: 1 for complex data (their 16-byte streams), 0 for real
   int precond = 0;        // 0: none; 1: right Jacobi (A D^-1); 2: right ILU(0), multicolour order
   int resid_control = 0;  // 0: safety factor (Section 3.4); 1: Givens estimate (Sections 4.5, 5)
   int sketch = 0;         // 0: sparse sign; 1: subsampled randomised DCT (Section 6)
@@ -166,6 +168,7 @@ struct SolverBase {
   virtual void reset() = 0;
   virtual int kernel_times(double* ms, int64_t* counts, int cap) = 0;
   virtual int spmv_layout(int* offsets, int cap) = 0;
+  virtual unsigned const_diagonals() const = 0;
 };
 
 template <class T>
@@ -305,6 +308,8 @@ class Solver final : public SolverBase {
           HIPCHK(hipMemsetAsync(diaval_, 0, sizeof(T) * (size_t)dia_.ndiag * n_, stream_));
           HIPCHK(hipStreamSynchronize(stream_));
           dia_.val = diaval_;
+          dcflag_ = dalloc<int>(kMaxDiag);
+          dcval_ = dalloc<T>(kMaxDiag);
         }
       }
       if (!kSame && !dia()) valB_ = dalloc<T>((size_t)mat.nnz);  // CSR values in the basis precision
@@ -349,6 +354,28 @@ class Solver final : public SolverBase {
 
   bool dia() const { return dia_.ndiag > 0; }
 
+  // After a packing: which diagonals hold one value inside the matrix (the
+  // host waits for the answer, once per matrix change; the step kernel then
+  // takes those values from its arguments).
+  void find_constant_diagonals() {
+    dia_.cmask = 0;
+    if (opt_.dia_const == 0 || (opt_.dia_const < 0 && !traits<T>::cpx)) return;
+    launch_dia_const<T>(stream_, n_, dia_, dcflag_, dcval_);
+    LAUNCHCHK();
+    int fl[kMaxDiag] = {};
+    T cv[kMaxDiag];
+    HIPCHK(hipMemcpyAsync(fl, dcflag_, sizeof(int) * dia_.ndiag, hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipMemcpyAsync(cv, dcval_, sizeof(T) * dia_.ndiag, hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+    for (int d = 0; d < dia_.ndiag; ++d)
+      if (fl[d]) {
+        dia_.cmask |= 1u << d;
+        dia_.cval[d] = cv[d];
+      }
+  }
+
+  unsigned const_diagonals() const override { return dia_.cmask; }
+
   // Matrix values for the basis SpMV: diagonal storage (packed on change) or
   // CSR values in the basis precision.
   const T* basis_values() {
@@ -357,6 +384,7 @@ class Solver final : public SolverBase {
         launch_pack_dia<T>(stream_, M_.nnz, M_.val, dia_map_, diaval_);
         LAUNCHCHK();
         low_dirty_ = false;
+        find_constant_diagonals();
       }
       return diaval_;
     }
@@ -1339,7 +1367,8 @@ class Solver final : public SolverBase {
       eig_cv_.notify_all();
       eig_thr_.join();
     }
-    for (void* p : {(void*)valB_, (void*)dia_map_, (void*)diaval_, (void*)Pbuf_[0], (void*)Pbuf_[1],
+    for (void* p : {(void*)valB_, (void*)dia_map_, (void*)diaval_, (void*)dcflag_, (void*)dcval_,
+                    (void*)Pbuf_[0], (void*)Pbuf_[1],
                     (void*)U_, (void*)Unew_, (void*)SU_,
                     (void*)red0_,
                     (void*)SAU_, (void*)Q_, (void*)R_, (void*)z_, (void*)rho_, (void*)SBbuf_[0],
@@ -1395,6 +1424,8 @@ class Solver final : public SolverBase {
   DiaView<T> dia_{};      // diagonal storage of the basis-precision matrix (ndiag 0: CSR)
   int* dia_map_ = nullptr;
   T* diaval_ = nullptr;
+  int* dcflag_ = nullptr;  // constant-diagonal flags and values (kMaxDiag each)
+  T* dcval_ = nullptr;
   T *P_ = nullptr, *U_ = nullptr, *Unew_ = nullptr;
   // right ILU(0): z = M^-1 p for the step SpMV (izb_, forward solve in iy_)
   // and for the residual (izA_, iyA_)
@@ -2045,6 +2076,10 @@ int sdr_set_option(sdr_handle* h, const char* key, double v) {
   } else if (k == "dia") {
     if (built || (v != 0.0 && v != 1.0)) return set_err("dia is 0 or 1, before the first solve"), SDR_EINVAL;
     h->opt.dia = (int)v;
+  } else if (k == "dia_const") {
+    if (built || (v != 0.0 && v != 1.0))
+      return set_err("dia_const is 0 or 1, before the first solve"), SDR_EINVAL;
+    h->opt.dia_const = (int)v;
   } else if (k == "precond") {
     if (built || (v != 0.0 && v != 1.0 && v != 2.0))
       return set_err("precond is 0, 1 (Jacobi) or 2 (ILU(0)), before the first solve"), SDR_EINVAL;
@@ -2327,6 +2362,15 @@ int sdr_spmv_layout(sdr_handle* h, int* offsets, int cap) {
   if (!h) return set_err("null handle"), SDR_EINVAL;
   try {
     return fwd(h)->spmv_layout(offsets, cap);
+  } catch (HipError& e) {
+    return e.code;
+  }
+}
+
+int sdr_spmv_const_diagonals(sdr_handle* h) {
+  if (!h) return set_err("null handle"), SDR_EINVAL;
+  try {
+    return (int)fwd(h)->const_diagonals();
   } catch (HipError& e) {
     return e.code;
   }

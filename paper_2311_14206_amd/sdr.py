@@ -68,6 +68,7 @@ EXPORTS = {
     "sdr_get_step_sres": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int]),
     "sdr_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
     "sdr_spmv_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int]),
+    "sdr_spmv_const_diagonals": (C.c_int, [C.c_void_p]),
     "sdr_destroy": (None, [C.c_void_p]),
     "sdr_last_error": (C.c_char_p, []),
     "sdr_host_harmonic_ritz": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
@@ -229,6 +230,11 @@ class SDRSolver:
         off = (C.c_int * 16)()
         nd = _check(lib().sdr_spmv_layout(self.h, off, 16), "sdr_spmv_layout")
         return [off[i] for i in range(nd)]
+
+    def const_diagonals(self):
+        """Bit mask of the diagonals (spmv_layout's order) found constant at the
+        last packing; their values are passed to the step kernel, not read."""
+        return _check(lib().sdr_spmv_const_diagonals(self.h), "sdr_spmv_const_diagonals")
 
     def trace(self):
         n = _check(lib().sdr_get_trace(self.h, None, 0), "sdr_get_trace")
